@@ -1,0 +1,208 @@
+"""Seeded synthetic inputs shared by the oracle tests, the GPU tests and the benchmark.
+
+This module holds no arithmetic of the simulation method itself: it only produces
+inputs (lattice sizes, initial density arrays with seeded noise, capsule meshes and
+capsule placements).  Both the CPU oracle and the HIP library receive the same
+arrays from here, so their initial states are bit-identical.
+
+Workloads (lattice units, dx = dt = 1):
+
+* ``c1``   32^3 box, wall at z=0, two-component mixture rho^c = 1*(1 + 0.02*xi),
+           xi uniform in [-1, 1), one capsule R=6 (icosphere level 3, 1280
+           triangles), ks=0.01, C=9, 200 steps.
+* ``pf``   the same box as ``c1`` with a flat film (film layers 1..10, one mixed
+           layer, gas above) and the same capsule centred at z=10, straddling
+           the interface; 1000 steps.  Non-chaotic parity geometry.
+* ``c2``   128x128x64 film-drying geometry: film 12 lu above the wall, repulsive
+           plane 10 lu above the wall, two capsules R=10 (level 4, 5120 triangles)
+           at separation 3R, anchored, ks in {0.005, 0.05, 5.0}.
+* ``c3``   256x256x96 film with 16 capsules R=10 at seeded random non-overlapping
+           positions (periodic centre distance >= 2R + delta0 + 1), ks=0.05.
+
+The film layout follows the paper's setup (Section 3.2): majority density 0.7,
+minority 0.04, and one interface layer where both components have density 0.3.
+"""
+from __future__ import annotations
+
+import copy
+import math
+from typing import Dict, List, Tuple
+
+import numpy as np
+
+SEED = 15405
+
+# --------------------------------------------------------------------------------------
+# Icosphere meshes
+# --------------------------------------------------------------------------------------
+
+
+def _icosahedron() -> Tuple[np.ndarray, List[Tuple[int, int, int]]]:
+    t = (1.0 + math.sqrt(5.0)) / 2.0
+    v = [(-1, t, 0), (1, t, 0), (-1, -t, 0), (1, -t, 0),
+         (0, -1, t), (0, 1, t), (0, -1, -t), (0, 1, -t),
+         (t, 0, -1), (t, 0, 1), (-t, 0, -1), (-t, 0, 1)]
+    f = [(0, 11, 5), (0, 5, 1), (0, 1, 7), (0, 7, 10), (0, 10, 11),
+         (1, 5, 9), (5, 11, 4), (11, 10, 2), (10, 7, 6), (7, 1, 8),
+         (3, 9, 4), (3, 4, 2), (3, 2, 6), (3, 6, 8), (3, 8, 9),
+         (4, 9, 5), (2, 4, 11), (6, 2, 10), (8, 6, 7), (9, 8, 1)]
+    verts = np.array(v, dtype=np.float64)
+    verts /= np.linalg.norm(verts, axis=1, keepdims=True)
+    return verts, f
+
+
+def icosphere(level: int, radius: float = 1.0,
+              center=(0.0, 0.0, 0.0)) -> Tuple[np.ndarray, np.ndarray]:
+    """Geodesic sphere: the icosahedron with every edge split at its midpoint
+    ``level`` times, each new vertex projected back onto the sphere.
+
+    Returns ``(nodes, tris)``: nodes (n, 3) float64, tris (m, 3) int32 with an
+    outward counter-clockwise orientation.  Level L has 10*4^L + 2 nodes and
+    20*4^L triangles (level 3: 642/1280, level 4: 2562/5120).
+    """
+    verts, faces = _icosahedron()
+    vlist = [tuple(p) for p in verts]
+    for _ in range(level):
+        cache: Dict[Tuple[int, int], int] = {}
+        new_faces = []
+
+        def mid(a: int, b: int) -> int:
+            key = (a, b) if a < b else (b, a)
+            if key in cache:
+                return cache[key]
+            p = np.add(vlist[a], vlist[b]) * 0.5
+            p = p / np.linalg.norm(p)
+            vlist.append(tuple(p))
+            cache[key] = len(vlist) - 1
+            return cache[key]
+
+        for (a, b, c) in faces:
+            ab, bc, ca = mid(a, b), mid(b, c), mid(c, a)
+            new_faces += [(a, ab, ca), (b, bc, ab), (c, ca, bc), (ab, bc, ca)]
+        faces = new_faces
+    nodes = np.array(vlist, dtype=np.float64)
+    tris = np.array(faces, dtype=np.int32)
+    # outward orientation: normal . centroid > 0
+    p0, p1, p2 = nodes[tris[:, 0]], nodes[tris[:, 1]], nodes[tris[:, 2]]
+    nrm = np.cross(p1 - p0, p2 - p0)
+    flip = np.einsum("ij,ij->i", nrm, p0 + p1 + p2) < 0
+    tris[flip] = tris[flip][:, [0, 2, 1]]
+    nodes = nodes * float(radius) + np.asarray(center, dtype=np.float64)
+    return np.ascontiguousarray(nodes), np.ascontiguousarray(tris)
+
+
+def level_for_triangles(n_tri: int) -> int:
+    lev = int(round(math.log(n_tri / 20.0, 4)))
+    if 20 * 4 ** lev != n_tri:
+        raise ValueError(f"{n_tri} is not 20*4^L")
+    return lev
+
+
+# --------------------------------------------------------------------------------------
+# Initial density arrays
+# --------------------------------------------------------------------------------------
+
+
+def noise_rho(nx: int, ny: int, nz: int, base=(1.0, 1.0), amp: float = 0.02,
+              seed: int = SEED) -> np.ndarray:
+    """rho^c(x) = base_c * (1 + amp * xi), xi i.i.d. uniform in [-1, 1).
+
+    Layout [2][nz][ny][nx], float64, C-contiguous."""
+    rng = np.random.default_rng(seed)
+    xi = rng.uniform(-1.0, 1.0, size=(2, nz, ny, nx))
+    b = np.asarray(base, dtype=np.float64).reshape(2, 1, 1, 1)
+    return np.ascontiguousarray(b * (1.0 + amp * xi))
+
+
+# --------------------------------------------------------------------------------------
+# Capsule placement
+# --------------------------------------------------------------------------------------
+
+
+def place_capsules(n: int, radius: float, nx: int, ny: int, z: float,
+                   min_dist: float, seed: int = SEED, max_tries: int = 200000):
+    """Seeded rejection sampling of ``n`` capsule centres, x and y uniform in the
+    periodic box, every periodic centre distance >= ``min_dist``."""
+    rng = np.random.default_rng(seed)
+    out: List[Tuple[float, float, float]] = []
+    tries = 0
+    while len(out) < n:
+        tries += 1
+        if tries > max_tries:
+            raise RuntimeError("could not place capsules")
+        x, y = rng.uniform(0.0, nx), rng.uniform(0.0, ny)
+        ok = True
+        for (px, py, _) in out:
+            dx = abs(x - px); dx = min(dx, nx - dx)
+            dy = abs(y - py); dy = min(dy, ny - dy)
+            if dx * dx + dy * dy < min_dist * min_dist:
+                ok = False
+                break
+        if ok:
+            out.append((float(x), float(y), float(z)))
+    return out
+
+
+# --------------------------------------------------------------------------------------
+# Workloads
+# --------------------------------------------------------------------------------------
+
+_BASE = dict(
+    nx=32, ny=32, nz=32, wall_z0=1,
+    tau=[1.0, 1.0], G=3.6, rho0=1.0, sc_norm=1.0,
+    body_force=[0.0, 0.0, 0.0], wall_drho=0.0,
+    init_mode=0, init_rho=[1.0, 1.0],
+    film_height=0.0, rho_maj=0.7, rho_min=0.04, rho_iface=0.3,
+    init_rho_array=None,
+    hertz_xi=1.5, hertz_delta0=1.5, plane_dz=0.0,
+    capsules=[], steps=1,
+)
+
+
+def capsule(center, radius, n_tri, ks, C=9.0, kb=0.0, kv=0.0, wet_drho=0.0,
+            anchor_k=0.0) -> dict:
+    return dict(center=[float(c) for c in center], radius=float(radius),
+                n_tri=int(n_tri), ks=float(ks), C=float(C), kb=float(kb),
+                kv=float(kv), wet_drho=float(wet_drho), anchor_k=float(anchor_k))
+
+
+def workload(name: str, **over) -> dict:
+    """Return a configuration dict; keyword overrides replace top-level keys."""
+    cfg = copy.deepcopy(_BASE)
+    if name == "c1":
+        cfg.update(nx=32, ny=32, nz=32, wall_z0=1, init_mode=2, steps=200,
+                   init_rho_array=noise_rho(32, 32, 32, (1.0, 1.0), 0.02, SEED),
+                   capsules=[capsule((16.0, 16.0, 16.0), 6.0, 1280, 0.01)])
+    elif name == "pf":
+        cfg.update(nx=32, ny=32, nz=32, wall_z0=1, init_mode=1, film_height=10.0,
+                   steps=1000,
+                   capsules=[capsule((16.0, 16.0, 10.0), 6.0, 1280, 0.01)])
+    elif name == "c2":
+        ks = over.pop("ks", 0.05)
+        cfg.update(nx=128, ny=128, nz=64, wall_z0=1, init_mode=1, film_height=12.0,
+                   plane_dz=10.0, steps=20000,
+                   capsules=[capsule((49.0, 64.0, 22.0), 10.0, 5120, ks, anchor_k=1.0),
+                             capsule((79.0, 64.0, 22.0), 10.0, 5120, ks, anchor_k=1.0)])
+    elif name == "c3":
+        R = 10.0
+        cen = place_capsules(16, R, 256, 256, 22.0, 2 * R + 1.5 + 1.0, SEED)
+        cfg.update(nx=256, ny=256, nz=96, wall_z0=1, init_mode=1, film_height=12.0,
+                   plane_dz=10.0, steps=10000,
+                   capsules=[capsule(c, R, 5120, 0.05, anchor_k=1.0) for c in cen])
+    else:
+        raise KeyError(name)
+    for k, v in over.items():
+        if k not in cfg:
+            raise KeyError(k)
+        cfg[k] = v
+    return cfg
+
+
+def capsule_mesh(cap: dict) -> Tuple[np.ndarray, np.ndarray]:
+    """Icosphere mesh for a capsule dict (radius, centre, triangle count)."""
+    return icosphere(level_for_triangles(cap["n_tri"]), cap["radius"], cap["center"])
+
+
+def fluid_sites(cfg: dict) -> int:
+    """Number of fluid sites (the wall layer z=0 is solid when present)."""
+    return cfg["nx"] * cfg["ny"] * (cfg["nz"] - (1 if cfg["wall_z0"] else 0))

@@ -1,0 +1,178 @@
+"""Pins of the oracle's time stepping against invariants, symmetries and closed-form
+flows: mass and momentum conservation, the rest state, Poiseuille flow, Laplace's law,
+component-swap symmetry of the wetting offsets, Newton's third law of the Hertz
+repulsion, and the coupling normalisation that makes the paper's film coexist."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+
+def _film_cfg(**over):
+    return synth.workload("pf", capsules=[], **over)
+
+
+def test_mass_conservation_with_capsule_and_wall():
+    cfg = synth.workload("pf")
+    o = oracle.Oracle(cfg)
+    m0 = o.summary()["mass"]
+    assert o.step(200) == 0
+    s = o.summary()
+    assert np.all(np.abs(s["mass"] - m0) / m0 < 1e-13)
+    assert s["lost_reaction"] == 0
+
+
+def test_uniform_rest_state_is_a_fixed_point():
+    cfg = _film_cfg(init_mode=0, init_rho=[0.7, 0.04], nx=8, ny=8, nz=8)
+    o = oracle.Oracle(cfg)
+    r0 = o.rho()
+    assert o.step(50) == 0
+    # exact up to the rounding of the stencil sums
+    assert np.abs(o.rho() - r0).max() < 1e-14
+    assert np.abs(o.velocity()).max() < 1e-15
+
+
+def test_momentum_invariant_with_capsule_reaction():
+    """Periodic box, no wall, no anchor: Shan-Chen forces cancel in pairs, internal
+    membrane forces sum to zero and the kernel is a partition of unity, so the fluid
+    momentum plus the pending membrane reaction is conserved."""
+    rho = synth.noise_rho(24, 24, 24, (0.7, 0.04), 0.05, seed=11)
+    cfg = synth.workload("pf", wall_z0=0, nx=24, ny=24, nz=24, init_mode=2, init_rho_array=rho,
+                         capsules=[synth.capsule((12.2, 11.7, 12.4), 5.0, 1280, 0.02, kv=0.5,
+                                                 wet_drho=0.05)])
+    o = oracle.Oracle(cfg)
+    s = o.summary()
+    P0 = s["momentum"] + s["pending"]
+    for _ in range(4):
+        assert o.step(25) == 0
+        s = o.summary()
+        assert s["lost_reaction"] == 0
+        assert np.abs(s["momentum"] + s["pending"] - P0).max() < 1e-12 * s["mass"].sum()
+    assert np.abs(s["pending"]).max() > 1e-6      # the reaction path was exercised
+
+
+def test_poiseuille_channel():
+    """Single component (rho2 = 0 so psi2 = 0), body force g along x between the
+    half-way bounce-back walls at z = 1/2 and z = nz - 1/2:
+    u(z) = g / (2 nu) (z - 1/2)(nz - 1/2 - z), nu = c_s^2 (tau - 1/2)."""
+    g, nz = 1e-6, 18
+    for tau in (1.0, 0.8):
+        cfg = _film_cfg(nx=4, ny=4, nz=nz, init_mode=0, init_rho=[1.0, 0.0],
+                        body_force=[g, 0.0, 0.0], tau=[tau, tau])
+        o = oracle.Oracle(cfg)
+        assert o.step(8000) == 0
+        u = o.velocity()[0, 1:, 1, 2]
+        z = np.arange(1, nz)
+        nu = (tau - 0.5) / 3.0
+        ua = g / (2 * nu) * (z - 0.5) * (nz - 0.5 - z)
+        assert np.linalg.norm(u - ua) / np.linalg.norm(ua) < 1e-2
+        assert np.abs(o.velocity()[1:]).max() < 1e-8 * ua.max()
+
+
+def _coexistence(sc_norm, steps=2000):
+    cfg = _film_cfg(nx=4, ny=4, nz=32, sc_norm=sc_norm)
+    o = oracle.Oracle(cfg)
+    r = o.step(steps)
+    return r, o
+
+
+def test_literal_weights_give_the_papers_film():
+    """With the paper's weights omega_i in eq. shanchen and G = 3.6, the film of
+    Section 3.2 settles into two coexisting bulk phases whose densities lie close to the
+    paper's initial majority/minority values 0.7 / 0.04."""
+    r, o = _coexistence(1.0)
+    assert r == 0
+    rho = o.rho()[:, :, 1, 1]
+    maj, mino = rho[0, 3:7].mean(), rho[0, 20:28].mean()
+    assert 0.69 < maj < 0.75 and 0.025 < mino < 0.05
+    # interface still sharp: not a slowly diffusing mixture
+    assert rho[0, 5] - rho[0, 16] > 0.6
+
+
+def test_scaled_weights_diverge_on_the_papers_film():
+    """w_i = omega_i / c_s^2 (three times the paper's weights) drives the minority
+    velocity shift beyond what the second-order equilibrium can hold at tau = 1: the
+    paper's initial film blows up within 100 steps."""
+    r, _ = _coexistence(3.0, steps=100)
+    assert r == -4
+
+
+def test_component_swap_symmetry_of_wetting_offsets():
+    """Exchanging the two components and negating every wetting offset maps one run
+    onto the other exactly (tests the sign convention of the offset)."""
+    base = synth.workload("pf", wall_drho=0.08)
+    cap = dict(base["capsules"][0]); cap["wet_drho"] = 0.12
+    A = synth.workload("pf", wall_drho=0.08, capsules=[cap])
+    capB = dict(cap); capB["wet_drho"] = -0.12
+    B = synth.workload("pf", wall_drho=-0.08, capsules=[capB])
+    oa = oracle.Oracle(A)
+    ra = oa.rho()
+    # B starts from A's densities with the components exchanged
+    B["init_mode"] = 2
+    B["init_rho_array"] = np.ascontiguousarray(ra[::-1])
+    ob = oracle.Oracle(B)
+    assert oa.step(150) == 0 and ob.step(150) == 0
+    assert np.abs(oa.rho() - ob.rho()[::-1]).max() < 1e-13
+    assert np.abs(oa.nodes(0) - ob.nodes(0)).max() < 1e-12
+    # and the offsets matter: compared with a neutral run, fields differ
+    on = oracle.Oracle(synth.workload("pf"))
+    on.step(150)
+    assert np.abs(on.rho() - oa.rho()).max() > 1e-4
+
+
+def test_hertz_pair_forces_are_equal_and_opposite_across_the_periodic_boundary():
+    R = 4.0
+    cfg = synth.workload("pf", wall_z0=0, nx=24, ny=16, nz=16, init_mode=0,
+                         init_rho=[0.7, 0.04],
+                         capsules=[synth.capsule((1.0, 8.0, 8.0), R, 320, 0.01),
+                                   synth.capsule((24.0 - 2 * R - 0.6 + 1.0, 8.0, 8.0), R, 320,
+                                                 0.01)])
+    o = oracle.Oracle(cfg)
+    assert o.step(1) == 0
+    a, b = o.capsule(0)["f_hertz"], o.capsule(1)["f_hertz"]
+    assert np.linalg.norm(a) > 0.1
+    assert np.abs(a + b).max() < 1e-12
+    # capsule 0 sits to the right of capsule 1 through the boundary: pushed to +x
+    assert a[0] > 0
+
+
+@pytest.mark.slow
+def test_laplace_law_quasi_2d():
+    """Cylindrical drops in a thin periodic box: Delta p = gamma / R with the
+    pressure p = c_s^2 (rho1 + rho2) + G w c_s^2 psi1 psi2 of the Shan-Chen mixture."""
+    n, G = 48, 3.6
+    inv_r, dp = [], []
+    for R in (7.0, 9.0, 11.0, 14.0):
+        Y, X = np.mgrid[0:n, 0:n]
+        inside = (X - 23.5) ** 2 + (Y - 23.5) ** 2 < R * R
+        rho = np.zeros((2, 3, n, n))
+        rho[0] = np.where(inside, 0.72, 0.036)
+        rho[1] = np.where(inside, 0.036, 0.72)
+        cfg = synth.workload("pf", capsules=[], wall_z0=0, nx=n, ny=n, nz=3, init_mode=2,
+                             init_rho_array=rho)
+        o = oracle.Oracle(cfg)
+        assert o.step(3000) == 0
+        r = o.rho()[:, 1]
+        psi = 1 - np.exp(-r)
+        p = (r[0] + r[1]) / 3.0 + G / 3.0 * psi[0] * psi[1]
+        dp.append(p[22:26, 22:26].mean() - p[:4, :4].mean())
+        # equivalent radius from the excess mass of the drop component
+        out0, in0 = r[0][:4, :4].mean(), r[0][22:26, 22:26].mean()
+        inv_r.append(1.0 / math.sqrt((r[0] - out0).sum() / (in0 - out0) / math.pi))
+    A = np.vstack([inv_r, np.ones(4)]).T
+    (gamma, c0), res, *_ = np.linalg.lstsq(A, np.array(dp), rcond=None)
+    r2 = 1 - res[0] / np.sum((np.array(dp) - np.mean(dp)) ** 2)
+    assert gamma > 0 and r2 > 0.9999
+    assert abs(c0) < 0.05 * max(dp)
+
+
+def test_fp32_build_tracks_fp64():
+    cfg = synth.workload("pf")
+    a = oracle.Oracle(cfg, "f64")
+    b = oracle.Oracle(cfg, "f32")
+    a.step(100); b.step(100)
+    ra, rb = a.rho(), b.rho()
+    assert np.linalg.norm(ra - rb) / np.linalg.norm(ra) < 1e-5
