@@ -1,0 +1,198 @@
+/*
+ * lbm.h -- C ABI of the MI355X library for the coupled lattice Boltzmann / capsule
+ * time step of Wouters, Aouane, Sega and Harting, "Capillary interactions between soft
+ * capsules protruding through thin fluid films" (arXiv:2007.15405).
+ *
+ * One time step (all on the GPU, on the handle's stream):
+ *   - side labels of every lattice site from the capsule meshes (interior/exterior
+ *     decoupling of the Shan-Chen force, Section 3.1);
+ *   - membrane node forces: Skalak strain energy by virtual work (eq. strain), volume
+ *     penalty (eq. vol_cons), Hertz particle-substrate / particle-particle repulsion
+ *     (Section 3.2, eq. interactions), a centroid anchor, and the pending reaction of
+ *     the cross-membrane Shan-Chen links;
+ *   - immersed-boundary spreading of the node forces (Peskin 4-point kernel);
+ *   - the fused fluid step: pull streaming with half-way bounce-back at the wall,
+ *     densities, pseudopotential psi = 1 - exp(-rho/rho0) (Section 3.1), Shan-Chen
+ *     force (eq. shanchen) with the label substitution, BGK collision (eq.
+ *     method:boltzmann) towards the second-order equilibrium (eq. lbm:equilibrium) at
+ *     the Shan-Chen shifted velocity;
+ *   - interpolation of the physical velocity to the nodes, node advection and
+ *     gathering of the reaction onto the nodes.
+ *
+ * Conventions
+ *   Lattice units (dx = dt = 1).  Site (i, j, k) sits at position (i, j, k); arrays over
+ *   sites are [nz][ny][nx] with x fastest.  The lattice is periodic in x, y and z; with
+ *   wall_z0 the layer k = 0 is a resting solid wall, so the fluid occupies k = 1..nz-1
+ *   between half-way bounce-back planes at z = 0.5 and z = nz - 0.5.
+ *   Component 0 is the film liquid, component 1 the covering fluid.
+ *
+ * Ownership and threading
+ *   The library owns all device memory of a handle.  Caller buffers passed to the
+ *   entry points are host memory owned by the caller, unless the name says "device".
+ *   A handle is used by one host thread at a time.  lbm_step only enqueues work on
+ *   the handle's stream and returns; the observation calls synchronise the stream.
+ *
+ * Errors
+ *   Every entry point returns an lbm_status; on failure lbm_last_error(h) holds a
+ *   message (lbm_last_error(NULL) holds the message of a failed lbm_init).  No C++
+ *   exception crosses this interface.  LBM_E_UNSTABLE reports a non-finite or
+ *   negative density, or a capsule that outgrew its immersed-boundary window; the
+ *   state is then undefined but the handle can still be destroyed.
+ */
+#ifndef LBM_H
+#define LBM_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_handle lbm_handle;
+
+typedef enum {
+    LBM_OK = 0,
+    LBM_E_INVAL = -1,     /* invalid argument or parameter                     */
+    LBM_E_NOMEM = -2,     /* device or host allocation failed                  */
+    LBM_E_DEVICE = -3,    /* a HIP runtime call failed                         */
+    LBM_E_UNSTABLE = -4,  /* non-finite / negative density or capsule overflow */
+    LBM_E_STATE = -5      /* call not allowed in the current state             */
+} lbm_status;
+
+/* Population storage in HBM.  The collision arithmetic is FP32 in every mode.
+ * The 16-bit modes store g_i = f_i - w_i * rho_shift[c] (w_i the lattice weights),
+ * rounded to nearest even, and decode f_i = g_i + w_i * rho_shift[c]. */
+typedef enum {
+    LBM_STORE_F32 = 0,
+    LBM_STORE_F16_SHIFT = 1,
+    LBM_STORE_BF16_SHIFT = 2
+} lbm_storage;
+
+typedef struct {
+    int32_t nx, ny, nz;        /* lattice size, each >= 3                                   */
+    int32_t wall_z0;           /* 1: solid wall layer at k = 0                               */
+    double tau[2];             /* BGK relaxation time per component, > 1/2 (Section 3.1)    */
+    double G;                  /* Shan-Chen coupling G^{12} = G^{21}; G^{cc} = 0 (eq. shanchen) */
+    double rho0;               /* reference density in psi = 1 - exp(-rho / rho0)          */
+    double sc_norm;            /* stencil weights sc_norm * omega_i (1: eq. shanchen as printed) */
+    double body_force[3];      /* acceleration g: force density rho^c g                    */
+    double wall_drho;          /* wetting offset of the wall in the substitution (0 neutral) */
+    int32_t init_mode;         /* 0 uniform init_rho, 1 film (Section 3.2), 2 init_rho_array */
+    int32_t storage;           /* lbm_storage                                              */
+    double init_rho[2];        /* mode 0 densities                                         */
+    double film_height;        /* mode 1: number of film layers above the wall             */
+    double rho_maj, rho_min, rho_iface; /* mode 1 densities (0.7, 0.04, 0.3 in the paper) */
+    const double *init_rho_array; /* mode 2: host [2][nz][ny][nx], copied during lbm_init */
+    double hertz_xi, hertz_delta0; /* Hertz strength and cut-off (1.5, 1.5 in the paper)    */
+    double plane_dz;           /* repulsive plane at z = 0.5 + plane_dz (wall only)        */
+    double rho_shift[2];       /* 16-bit storage shift per component (paper: rho0)        */
+    void *stream;              /* hipStream_t to enqueue on (see stream_given)             */
+    int32_t device;            /* HIP device ordinal                                       */
+    int32_t stream_given;      /* 1: use `stream` as given, NULL meaning the null stream;
+                                  0: NULL makes a private stream of the library             */
+} lbm_params;
+
+typedef struct {
+    double ks;        /* Skalak shear modulus kappa_S (eq. strain)                       */
+    double C;         /* Skalak area constant C > -1/2; kappa_A = kappa_S (1 + 2C)        */
+    double kb;        /* bending modulus: must be 0 (bending is not part of this build) */
+    double kv;        /* volume penalty kappa_V (eq. vol_cons)                           */
+    double wet_drho;  /* wetting offset of the membrane (0 neutral)                      */
+    double anchor_k;  /* centroid anchor spring; 0 leaves the capsule free               */
+} lbm_capsule_params;
+
+typedef struct {
+    double centroid[3];     /* node mean at the current positions                         */
+    double volume;          /* enclosed volume at the current positions                   */
+    double f_anchor[3];     /* force of the fluid on an anchored capsule (last step)      */
+    double f_capillary[3];  /* sum of the pending cross-membrane reaction                 */
+    double f_hertz[3];      /* sum of Hertz forces of the last step                       */
+} lbm_capsule_obs;
+
+typedef struct {
+    double mass[2];         /* sum over fluid sites of rho^c (double accumulation)        */
+    double momentum[3];     /* fluid momentum sum_x sum_c sum_i f*_i e_i                  */
+    double pending[3];      /* sum over all nodes of the pending reaction                 */
+    int64_t step;           /* completed time steps                                       */
+    int64_t lost_reaction;  /* site-steps whose reaction found no kernel coverage         */
+    int32_t n_capsules;
+    int32_t unstable;       /* 1: non-finite / negative density or capsule overflow seen  */
+} lbm_summary;
+
+typedef struct {
+    float *rho;                 /* host [2][nz][ny][nx] densities rho^c, or NULL          */
+    float *meniscus;            /* host [ny][nx] meniscus height (NaN: none), or NULL     */
+    lbm_capsule_obs *capsules;  /* host [n_capsules], or NULL                            */
+    lbm_summary summary;        /* always filled                                          */
+} lbm_obs;
+
+/* Per-kernel timing, collected when profiling is on (lbm_set_profiling). */
+typedef struct {
+    char name[32];
+    int64_t launches;
+    double total_ms;
+} lbm_kernel_stat;
+
+/* Create a simulation: validates the parameters, allocates the device state and sets
+ * f*_i = f^eq_i(rho^c, 0) (eq. lbm:equilibrium at rest) from the initial densities.
+ * init_rho_array is read during the call only.  On failure *out is NULL. */
+lbm_status lbm_init(const lbm_params *params, lbm_handle **out);
+
+/* Add a capsule: a closed triangle mesh, outward counter-clockwise, n_nodes >= 4,
+ * xyz host [n_nodes][3] (unwrapped lattice coordinates), tri host [n_tri][3].  The mesh
+ * at this moment is the stress-free reference (Section 3.1).  Copied during the call.
+ * Only before the first lbm_step (LBM_E_STATE afterwards).  *id_out gets the index. */
+lbm_status lbm_add_capsule(lbm_handle *h, const lbm_capsule_params *cp, int32_t n_nodes,
+                           const double *xyz, int32_t n_tri, const int32_t *tri,
+                           int32_t *id_out);
+
+/* Enqueue n >= 0 time steps on the handle's stream; returns without waiting. */
+lbm_status lbm_step(lbm_handle *h, int64_t n);
+
+/* Wait for all enqueued work; reports LBM_E_UNSTABLE if an instability was flagged. */
+lbm_status lbm_sync(lbm_handle *h);
+
+/* Observables of the current state (synchronises); fills the non-NULL caller buffers. */
+lbm_status lbm_observables(lbm_handle *h, lbm_obs *out);
+
+/* Densities rho^c written to a caller-owned DEVICE buffer [2][nz][ny][nx] float, on the
+ * handle's stream (no synchronisation).  Solid sites get 0. */
+lbm_status lbm_rho_device(lbm_handle *h, float *rho_device);
+
+/* Current node positions of capsule k: host [n_nodes][3] (synchronises). */
+lbm_status lbm_capsule_nodes(lbm_handle *h, int32_t k, double *xyz);
+
+/* Site labels used by the last step: host [nz][ny][nx]; 0 exterior, k+1 inside
+ * capsule k, 255 wall (synchronises). */
+lbm_status lbm_labels(lbm_handle *h, uint8_t *out);
+
+/* Checkpoint: populations, node positions, pending reaction and step counter, in a
+ * binary file; lbm_load restores them into a handle made with the same parameters and
+ * capsules.  Resuming gives the same result as an uninterrupted run, bit for bit. */
+lbm_status lbm_save(lbm_handle *h, const char *path);
+lbm_status lbm_load(lbm_handle *h, const char *path);
+
+/* Per-kernel event timing of later steps (on: 1).  lbm_kernel_stats copies up to max
+ * entries and returns their number in *n (synchronises). */
+lbm_status lbm_set_profiling(lbm_handle *h, int32_t on);
+lbm_status lbm_kernel_stats(lbm_handle *h, lbm_kernel_stat *out, int32_t max, int32_t *n);
+
+/* Launch shape of the fluid step.  tile 1..5 selects the fused single-read kernel with
+ * column tiles of 32x8, 64x4, 32x16, 64x8 or 16x16 sites; tile 0 the two-kernel variant
+ * (densities, then forces and collision).  zchunk is the number of z planes one
+ * workgroup marches through (0: chosen from the lattice size).  Every variant performs
+ * the same arithmetic per site in the same order, so results are identical. */
+lbm_status lbm_set_launch(lbm_handle *h, int32_t tile, int32_t zchunk);
+
+/* Algorithmic HBM bytes per fluid-site update of the fused fluid kernel for the
+ * handle's storage: 2 components x 19 populations x (load + store). */
+double lbm_bytes_per_site(const lbm_handle *h);
+int64_t lbm_fluid_sites(const lbm_handle *h);
+
+const char *lbm_last_error(const lbm_handle *h);
+void lbm_destroy(lbm_handle *h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

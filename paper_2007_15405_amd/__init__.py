@@ -1,0 +1,7 @@
+"""MI355X library for the coupled two-component Shan-Chen D3Q19 lattice Boltzmann /
+Skalak capsule time step (Wouters, Aouane, Sega, Harting; arXiv:2007.15405).
+
+The compute path is ``liblbm.so`` (HIP kernels for gfx950 behind the C ABI in
+``include/lbm.h``); :class:`Sim` is its ctypes binding.
+"""
+from .lbm import Sim, LbmError, load_library, SIGNATURES, LIB_PATH, STORAGE  # noqa: F401

@@ -1,0 +1,808 @@
+// api.hip -- the C ABI of liblbm (include/lbm.h): handle, parameter validation, device
+// state, the per-step launch chain, observables, checkpoints and kernel timing.
+#include "lbm.h"
+#include "lbm_internal.h"
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+using namespace lbmx;
+
+namespace {
+
+thread_local std::string g_init_error;
+
+struct HostCap {
+    lbm_capsule_params p;
+    std::vector<double> x0;    // [nn][3]
+    std::vector<int32_t> tri;  // [nt][3]
+};
+
+struct Timer {
+    const char *name;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+    int64_t launches = 0;
+    double ms = 0.0;
+};
+
+constexpr int MOM_BLOCKS = 512;
+
+}  // namespace
+
+struct lbm_handle {
+    lbm_params p{};
+    std::string err;
+    hipStream_t st = nullptr;
+    bool own_stream = false;
+    int nx = 0, ny = 0, nz = 0, wall = 0, N = 0, storage = 0;
+    size_t esize = 4;
+    void *f[2] = {nullptr, nullptr};
+    int cur = 0;
+    uint8_t *flag = nullptr;
+    float4 *ibm = nullptr, *uo = nullptr, *ro = nullptr;
+    float *psi = nullptr, *cap_drho = nullptr, *rho_tmp = nullptr, *men_tmp = nullptr;
+    int *status = nullptr;
+    double *partial = nullptr;
+    std::vector<HostCap> caps;
+    bool finalized = false;
+    int64_t step = 0;
+    int ntot = 0, ttot = 0;
+    CapDev *d_caps = nullptr;
+    CapState *d_cst = nullptr;
+    double4 *d_X = nullptr;
+    int *d_node_cap = nullptr;
+    float4 *d_F = nullptr, *d_Fh = nullptr, *d_R = nullptr;
+    int4 *d_tri = nullptr;
+    float4 *d_minv = nullptr;
+    float *d_a0 = nullptr;
+    int *d_off = nullptr, *d_list = nullptr, *d_marks = nullptr, *d_rowstart = nullptr,
+        *d_rowids = nullptr;
+    std::vector<CapDev> h_caps;
+    int tile = 1, zchunk = 0;
+    bool profiling = false;
+    std::vector<Timer> timers;
+    std::vector<hipEvent_t> event_pool;
+};
+
+#define HIPCHK(h, expr)                                                               \
+    do {                                                                              \
+        hipError_t e_ = (expr);                                                       \
+        if (e_ != hipSuccess) {                                                       \
+            (h)->err = std::string(#expr) + ": " + hipGetErrorString(e_);             \
+            return LBM_E_DEVICE;                                                      \
+        }                                                                             \
+    } while (0)
+
+static lbm_status fail(lbm_handle *h, lbm_status s, const std::string &m) {
+    h->err = m;
+    return s;
+}
+
+template <typename T> static hipError_t dalloc(T **p, size_t count) {
+    return hipMalloc((void **)p, sizeof(T) * (count ? count : 1));
+}
+
+static void free_all(lbm_handle *h) {
+    void *ptrs[] = {h->f[0], h->f[1], h->flag, h->ibm, h->uo, h->ro, h->psi, h->cap_drho,
+                    h->rho_tmp, h->men_tmp, h->status, h->partial, h->d_caps, h->d_cst, h->d_X,
+                    h->d_node_cap, h->d_F, h->d_Fh, h->d_R, h->d_tri, h->d_minv, h->d_a0,
+                    h->d_off, h->d_list, h->d_marks, h->d_rowstart, h->d_rowids};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    for (hipEvent_t e : h->event_pool) (void)hipEventDestroy(e);
+    for (auto &t : h->timers)
+        for (auto &pr : t.pending) {
+            (void)hipEventDestroy(pr.first);
+            (void)hipEventDestroy(pr.second);
+        }
+    if (h->own_stream && h->st) (void)hipStreamDestroy(h->st);
+}
+
+// ------------------------------------------------------------------------------------
+// Timing
+// ------------------------------------------------------------------------------------
+static hipEvent_t take_event(lbm_handle *h) {
+    if (!h->event_pool.empty()) {
+        hipEvent_t e = h->event_pool.back();
+        h->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+static Timer &timer(lbm_handle *h, const char *name) {
+    for (auto &t : h->timers)
+        if (t.name == name) return t;
+    h->timers.push_back(Timer{name, {}, 0, 0.0});
+    return h->timers.back();
+}
+
+template <typename F> static void timed(lbm_handle *h, const char *name, F &&launch) {
+    if (!h->profiling) {
+        launch();
+        return;
+    }
+    hipEvent_t a = take_event(h), b = take_event(h);
+    if (a) (void)hipEventRecord(a, h->st);
+    launch();
+    if (b) (void)hipEventRecord(b, h->st);
+    if (a && b) timer(h, name).pending.push_back({a, b});
+}
+
+static void collect_timers(lbm_handle *h) {
+    for (auto &t : h->timers) {
+        for (auto &pr : t.pending) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, pr.first, pr.second) == hipSuccess) {
+                t.ms += ms;
+                t.launches++;
+            }
+            h->event_pool.push_back(pr.first);
+            h->event_pool.push_back(pr.second);
+        }
+        t.pending.clear();
+    }
+}
+
+// ------------------------------------------------------------------------------------
+// Initial densities (Section 3.2 film, uniform, or caller array)
+// ------------------------------------------------------------------------------------
+static void initial_density(const lbm_params &p, std::vector<double> &rho) {
+    const long N = (long)p.nx * p.ny * p.nz;
+    rho.assign(2 * N, 0.0);
+    const int kw = p.wall_z0 ? 1 : 0;
+    const long H = std::lround(p.film_height);
+    for (int k = 0; k < p.nz; ++k)
+        for (int j = 0; j < p.ny; ++j)
+            for (int i = 0; i < p.nx; ++i) {
+                const long s = ((long)k * p.ny + j) * p.nx + i;
+                if (p.wall_z0 && k == 0) continue;
+                double a, b;
+                if (p.init_mode == 0) {
+                    a = p.init_rho[0];
+                    b = p.init_rho[1];
+                } else if (p.init_mode == 1) {
+                    const long layer = k - kw;
+                    if (layer < H) { a = p.rho_maj; b = p.rho_min; }
+                    else if (layer == H) { a = p.rho_iface; b = p.rho_iface; }
+                    else { a = p.rho_min; b = p.rho_maj; }
+                } else {
+                    a = p.init_rho_array[s];
+                    b = p.init_rho_array[N + s];
+                }
+                rho[s] = a;
+                rho[N + s] = b;
+            }
+}
+
+static float shift_of(const lbm_handle *h, int c) {
+    return h->storage == LBM_STORE_F32 ? 0.0f : (float)h->p.rho_shift[c];
+}
+
+// ------------------------------------------------------------------------------------
+// lbm_init
+// ------------------------------------------------------------------------------------
+extern "C" lbm_status lbm_init(const lbm_params *p, lbm_handle **out) {
+    if (!out) return LBM_E_INVAL;
+    *out = nullptr;
+    auto bad = [&](const char *m) {
+        g_init_error = m;
+        return LBM_E_INVAL;
+    };
+    if (!p) return bad("params is NULL");
+    if (p->nx < 3 || p->ny < 3 || p->nz < 3) return bad("nx, ny, nz must be >= 3");
+    if ((double)p->nx * p->ny * p->nz > (double)(1 << 30)) return bad("lattice too large");
+    if (!(p->tau[0] > 0.5) || !(p->tau[1] > 0.5)) return bad("tau must exceed 1/2");
+    if (!(p->rho0 > 0.0)) return bad("rho0 must be positive");
+    if (!(p->sc_norm >= 0.0) || !std::isfinite(p->G)) return bad("invalid Shan-Chen coupling");
+    if (p->init_mode < 0 || p->init_mode > 2) return bad("init_mode must be 0, 1 or 2");
+    if (p->init_mode == 2 && !p->init_rho_array) return bad("init_rho_array is NULL");
+    if (p->init_mode == 1 && !(p->film_height >= 0.0)) return bad("film_height must be >= 0");
+    if (p->storage < 0 || p->storage > 2) return bad("storage must be 0, 1 or 2");
+    if (!(p->hertz_xi >= 0.0) || !(p->hertz_delta0 >= 0.0)) return bad("invalid Hertz parameters");
+    if (p->wall_z0 != 0 && p->wall_z0 != 1) return bad("wall_z0 must be 0 or 1");
+
+    lbm_handle *h = new (std::nothrow) lbm_handle();
+    if (!h) return LBM_E_NOMEM;
+    h->p = *p;
+    h->p.init_rho_array = nullptr;
+    h->nx = p->nx; h->ny = p->ny; h->nz = p->nz; h->wall = p->wall_z0;
+    h->N = p->nx * p->ny * p->nz;
+    h->storage = p->storage;
+    h->esize = p->storage == LBM_STORE_F32 ? 4 : 2;
+    auto die = [&](lbm_status s, const std::string &m) {
+        g_init_error = m;
+        free_all(h);
+        delete h;
+        return s;
+    };
+    hipError_t e = hipSetDevice(p->device);
+    if (e != hipSuccess) return die(LBM_E_DEVICE, std::string("hipSetDevice: ") + hipGetErrorString(e));
+    if (p->stream || p->stream_given) {
+        h->st = (hipStream_t)p->stream;
+    } else {
+        e = hipStreamCreateWithFlags(&h->st, hipStreamNonBlocking);
+        if (e != hipSuccess) return die(LBM_E_DEVICE, "hipStreamCreate failed");
+        h->own_stream = true;
+    }
+    const size_t N = (size_t)h->N;
+    const size_t fbytes = 2 * (size_t)Q * N * h->esize;
+    if (hipMalloc(&h->f[0], fbytes) != hipSuccess || hipMalloc(&h->f[1], fbytes) != hipSuccess ||
+        dalloc(&h->flag, N) != hipSuccess || dalloc(&h->ibm, N) != hipSuccess ||
+        dalloc(&h->uo, N) != hipSuccess || dalloc(&h->ro, N) != hipSuccess ||
+        dalloc(&h->psi, 2 * N) != hipSuccess || dalloc(&h->cap_drho, (size_t)MAX_CAPS) != hipSuccess ||
+        dalloc(&h->rho_tmp, 2 * N) != hipSuccess ||
+        dalloc(&h->men_tmp, (size_t)h->nx * h->ny) != hipSuccess ||
+        dalloc(&h->status, (size_t)ST_WORDS) != hipSuccess ||
+        dalloc(&h->partial, (size_t)MOM_BLOCKS * 5) != hipSuccess)
+        return die(LBM_E_NOMEM, "device allocation failed");
+    if (hipMemsetAsync(h->f[0], 0, fbytes, h->st) != hipSuccess ||
+        hipMemsetAsync(h->f[1], 0, fbytes, h->st) != hipSuccess ||
+        hipMemsetAsync(h->flag, 0, N, h->st) != hipSuccess ||
+        hipMemsetAsync(h->ibm, 0, N * sizeof(float4), h->st) != hipSuccess ||
+        hipMemsetAsync(h->uo, 0, N * sizeof(float4), h->st) != hipSuccess ||
+        hipMemsetAsync(h->ro, 0, N * sizeof(float4), h->st) != hipSuccess ||
+        hipMemsetAsync(h->psi, 0, 2 * N * sizeof(float), h->st) != hipSuccess ||
+        hipMemsetAsync(h->cap_drho, 0, MAX_CAPS * sizeof(float), h->st) != hipSuccess ||
+        hipMemsetAsync(h->status, 0, ST_WORDS * sizeof(int), h->st) != hipSuccess)
+        return die(LBM_E_DEVICE, "device memset failed");
+
+    std::vector<double> rho;
+    initial_density(*p, rho);
+    for (double v : rho)
+        if (!std::isfinite(v) || v < 0.0) return die(LBM_E_INVAL, "initial densities must be finite and >= 0");
+    double *d_rho = nullptr;
+    if (dalloc(&d_rho, 2 * N) != hipSuccess) return die(LBM_E_NOMEM, "device allocation failed");
+    e = hipMemcpyAsync(d_rho, rho.data(), 2 * N * sizeof(double), hipMemcpyHostToDevice, h->st);
+    if (e == hipSuccess) {
+        const float s0 = shift_of(h, 0), s1 = shift_of(h, 1);
+        switch (h->storage) {
+            case 0: launch_init_eq<0>(d_rho, h->f[0], h->nx, h->ny, h->nz, h->wall, s0, s1, h->st); break;
+            case 1: launch_init_eq<1>(d_rho, h->f[0], h->nx, h->ny, h->nz, h->wall, s0, s1, h->st); break;
+            default: launch_init_eq<2>(d_rho, h->f[0], h->nx, h->ny, h->nz, h->wall, s0, s1, h->st); break;
+        }
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(h->st);
+    (void)hipFree(d_rho);
+    if (e != hipSuccess) return die(LBM_E_DEVICE, std::string("initialisation: ") + hipGetErrorString(e));
+    *out = h;
+    return LBM_OK;
+}
+
+// ------------------------------------------------------------------------------------
+// Capsules
+// ------------------------------------------------------------------------------------
+extern "C" lbm_status lbm_add_capsule(lbm_handle *h, const lbm_capsule_params *cp,
+                                      int32_t n_nodes, const double *xyz, int32_t n_tri,
+                                      const int32_t *tri, int32_t *id_out) {
+    if (!h) return LBM_E_INVAL;
+    if (h->finalized) return fail(h, LBM_E_STATE, "capsules must be added before the first step");
+    if (!cp || !xyz || !tri || n_nodes < 4 || n_tri < 4)
+        return fail(h, LBM_E_INVAL, "invalid capsule mesh");
+    if ((int)h->caps.size() >= MAX_CAPS) return fail(h, LBM_E_INVAL, "too many capsules");
+    if (cp->kb != 0.0) return fail(h, LBM_E_INVAL, "bending (kb != 0) is not supported");
+    if (!(cp->ks >= 0.0) || !(cp->C > -0.5) || !(cp->kv >= 0.0) || !(cp->anchor_k >= 0.0) ||
+        !std::isfinite(cp->wet_drho))
+        return fail(h, LBM_E_INVAL, "invalid capsule parameters");
+    for (int i = 0; i < 3 * n_tri; ++i)
+        if (tri[i] < 0 || tri[i] >= n_nodes) return fail(h, LBM_E_INVAL, "triangle index out of range");
+    for (int i = 0; i < 3 * n_nodes; ++i)
+        if (!std::isfinite(xyz[i])) return fail(h, LBM_E_INVAL, "non-finite node position");
+    HostCap c;
+    c.p = *cp;
+    c.x0.assign(xyz, xyz + 3 * (size_t)n_nodes);
+    c.tri.assign(tri, tri + 3 * (size_t)n_tri);
+    h->caps.push_back(std::move(c));
+    if (id_out) *id_out = (int32_t)h->caps.size() - 1;
+    return LBM_OK;
+}
+
+// Reference geometry of a triangle (FP64): the vertices in an orthonormal in-plane
+// frame, P1 = (0, 0), P2 = (a, 0), P3 = (b, c); returns the inverse of [P2-P1, P3-P1]
+// (row-major) and the area.
+static void tri_reference(const double *p1, const double *p2, const double *p3, double minv[4],
+                          double *area) {
+    double u[3], v[3];
+    for (int d = 0; d < 3; ++d) { u[d] = p2[d] - p1[d]; v[d] = p3[d] - p1[d]; }
+    const double a = std::sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    const double b = (v[0] * u[0] + v[1] * u[1] + v[2] * u[2]) / a;
+    double w2 = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        const double wd = v[d] - b * u[d] / a;
+        w2 += wd * wd;
+    }
+    const double c = std::sqrt(w2);
+    minv[0] = 1.0 / a;
+    minv[1] = -b / (a * c);
+    minv[2] = 0.0;
+    minv[3] = 1.0 / c;
+    *area = 0.5 * a * c;
+}
+
+static lbm_status finalize(lbm_handle *h) {
+    const int ncap = (int)h->caps.size();
+    h->finalized = true;
+    if (ncap == 0) return LBM_OK;
+    std::vector<double4> X;
+    std::vector<int> node_cap, off, list;
+    std::vector<int4> tri;
+    std::vector<float4> minv;
+    std::vector<float> a0;
+    std::vector<float> drho(MAX_CAPS, 0.0f);
+    h->h_caps.clear();
+    for (int k = 0; k < ncap; ++k) {
+        const HostCap &c = h->caps[k];
+        const int nn = (int)c.x0.size() / 3, nt = (int)c.tri.size() / 3;
+        CapDev cd{};
+        cd.node0 = (int)X.size();
+        cd.nn = nn;
+        cd.tri0 = (int)tri.size();
+        cd.nt = nt;
+        cd.ks = (float)c.p.ks;
+        cd.C = (float)c.p.C;
+        cd.kv = (float)c.p.kv;
+        cd.anchor_k = (float)c.p.anchor_k;
+        double cen[3] = {0, 0, 0};
+        for (int i = 0; i < nn; ++i) {
+            X.push_back(make_double4(c.x0[3 * i], c.x0[3 * i + 1], c.x0[3 * i + 2], 0.0));
+            node_cap.push_back(k);
+            for (int d = 0; d < 3; ++d) cen[d] += c.x0[3 * i + d];
+        }
+        for (int d = 0; d < 3; ++d) cd.c0[d] = cen[d] / nn;
+        double vol = 0.0;
+        for (int t = 0; t < nt; ++t) {
+            const double *p1 = &c.x0[3 * c.tri[3 * t]], *p2 = &c.x0[3 * c.tri[3 * t + 1]],
+                         *p3 = &c.x0[3 * c.tri[3 * t + 2]];
+            double m[4], area;
+            tri_reference(p1, p2, p3, m, &area);
+            if (!(area > 0.0) || !std::isfinite(m[0] + m[1] + m[3]))
+                return fail(h, LBM_E_INVAL, "degenerate reference triangle");
+            tri.push_back(make_int4(cd.node0 + c.tri[3 * t], cd.node0 + c.tri[3 * t + 1],
+                                    cd.node0 + c.tri[3 * t + 2], k));
+            minv.push_back(make_float4((float)m[0], (float)m[1], (float)m[2], (float)m[3]));
+            a0.push_back((float)area);
+            double a[3], b[3], e[3];
+            for (int d = 0; d < 3; ++d) {
+                a[d] = p1[d] - cd.c0[d];
+                b[d] = p2[d] - cd.c0[d];
+                e[d] = p3[d] - cd.c0[d];
+            }
+            vol += (a[0] * (b[1] * e[2] - b[2] * e[1]) + a[1] * (b[2] * e[0] - b[0] * e[2]) +
+                    a[2] * (b[0] * e[1] - b[1] * e[0])) / 6.0;
+        }
+        if (!(vol > 0.0)) return fail(h, LBM_E_INVAL, "capsule mesh must be closed and outward oriented");
+        cd.v0 = vol;
+        drho[k] = (float)c.p.wet_drho;
+        h->h_caps.push_back(cd);
+    }
+    h->ntot = (int)X.size();
+    h->ttot = (int)tri.size();
+    // node -> incident triangle CSR (entries 3 * triangle + corner, triangle order)
+    off.assign(h->ntot + 1, 0);
+    for (const int4 &t : tri) { off[t.x + 1]++; off[t.y + 1]++; off[t.z + 1]++; }
+    for (int i = 0; i < h->ntot; ++i) off[i + 1] += off[i];
+    list.assign(off[h->ntot], 0);
+    std::vector<int> cur(off.begin(), off.end() - 1);
+    for (int t = 0; t < h->ttot; ++t) {
+        list[cur[tri[t].x]++] = 3 * t;
+        list[cur[tri[t].y]++] = 3 * t + 1;
+        list[cur[tri[t].z]++] = 3 * t + 2;
+    }
+    const size_t nt = h->ntot, tt = h->ttot;
+    if (dalloc(&h->d_caps, ncap) != hipSuccess || dalloc(&h->d_cst, ncap) != hipSuccess ||
+        dalloc(&h->d_X, nt) != hipSuccess || dalloc(&h->d_node_cap, nt) != hipSuccess ||
+        dalloc(&h->d_F, nt) != hipSuccess || dalloc(&h->d_Fh, nt) != hipSuccess ||
+        dalloc(&h->d_R, nt) != hipSuccess || dalloc(&h->d_tri, tt) != hipSuccess ||
+        dalloc(&h->d_minv, tt) != hipSuccess || dalloc(&h->d_a0, tt) != hipSuccess ||
+        dalloc(&h->d_off, nt + 1) != hipSuccess || dalloc(&h->d_list, list.size()) != hipSuccess ||
+        dalloc(&h->d_marks, (size_t)ncap * GMAX3) != hipSuccess ||
+        dalloc(&h->d_rowstart, (size_t)ncap * (ROWS_MAX + 1)) != hipSuccess ||
+        dalloc(&h->d_rowids, nt) != hipSuccess)
+        return fail(h, LBM_E_NOMEM, "device allocation failed (capsules)");
+    HIPCHK(h, hipMemcpyAsync(h->d_caps, h->h_caps.data(), ncap * sizeof(CapDev), hipMemcpyHostToDevice, h->st));
+    HIPCHK(h, hipMemsetAsync(h->d_cst, 0, ncap * sizeof(CapState), h->st));
+    HIPCHK(h, hipMemcpyAsync(h->d_X, X.data(), nt * sizeof(double4), hipMemcpyHostToDevice, h->st));
+    HIPCHK(h, hipMemcpyAsync(h->d_node_cap, node_cap.data(), nt * sizeof(int), hipMemcpyHostToDevice, h->st));
+    HIPCHK(h, hipMemsetAsync(h->d_F, 0, nt * sizeof(float4), h->st));
+    HIPCHK(h, hipMemsetAsync(h->d_Fh, 0, nt * sizeof(float4), h->st));
+    HIPCHK(h, hipMemsetAsync(h->d_R, 0, nt * sizeof(float4), h->st));
+    HIPCHK(h, hipMemcpyAsync(h->d_tri, tri.data(), tt * sizeof(int4), hipMemcpyHostToDevice, h->st));
+    HIPCHK(h, hipMemcpyAsync(h->d_minv, minv.data(), tt * sizeof(float4), hipMemcpyHostToDevice, h->st));
+    HIPCHK(h, hipMemcpyAsync(h->d_a0, a0.data(), tt * sizeof(float), hipMemcpyHostToDevice, h->st));
+    HIPCHK(h, hipMemcpyAsync(h->d_off, off.data(), (nt + 1) * sizeof(int), hipMemcpyHostToDevice, h->st));
+    HIPCHK(h, hipMemcpyAsync(h->d_list, list.data(), list.size() * sizeof(int), hipMemcpyHostToDevice, h->st));
+    HIPCHK(h, hipMemsetAsync(h->d_marks, 0, (size_t)ncap * GMAX3 * sizeof(int), h->st));
+    HIPCHK(h, hipMemsetAsync(h->d_rowstart, 0, (size_t)ncap * (ROWS_MAX + 1) * sizeof(int), h->st));
+    HIPCHK(h, hipMemsetAsync(h->d_rowids, 0, nt * sizeof(int), h->st));
+    HIPCHK(h, hipMemcpyAsync(h->cap_drho, drho.data(), MAX_CAPS * sizeof(float), hipMemcpyHostToDevice, h->st));
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    return LBM_OK;
+}
+
+// ------------------------------------------------------------------------------------
+// Stepping
+// ------------------------------------------------------------------------------------
+static MembraneArgs membrane_args(lbm_handle *h) {
+    MembraneArgs m{};
+    m.caps = h->d_caps; m.cst = h->d_cst; m.ncap = (int)h->caps.size();
+    m.X = h->d_X; m.node_cap = h->d_node_cap; m.F = h->d_F; m.Fh = h->d_Fh; m.R = h->d_R;
+    m.tri = h->d_tri; m.minv = h->d_minv; m.a0 = h->d_a0;
+    m.ntri_off = h->d_off; m.ntri = h->d_list;
+    m.marks = h->d_marks; m.rowstart = h->d_rowstart; m.rowids = h->d_rowids;
+    m.flag = h->flag; m.ibm = h->ibm; m.uo = h->uo; m.ro = h->ro; m.status = h->status;
+    m.nx = h->nx; m.ny = h->ny; m.nz = h->nz; m.wall = h->wall;
+    m.hertz_xi = (float)h->p.hertz_xi;
+    m.hertz_d0 = (float)h->p.hertz_delta0;
+    m.plane_z = (float)(0.5 + h->p.plane_dz);
+    return m;
+}
+
+static FluidArgs fluid_args(lbm_handle *h) {
+    FluidArgs a{};
+    a.fin = h->f[h->cur];
+    a.fout = h->f[1 - h->cur];
+    a.flag = h->flag; a.ibm = h->ibm; a.uo = h->uo; a.ro = h->ro; a.psi = h->psi;
+    a.status = h->status; a.cap_drho = h->cap_drho;
+    a.nx = h->nx; a.ny = h->ny; a.nz = h->nz; a.wall = h->wall; a.N = h->N;
+    for (int c = 0; c < 2; ++c) {
+        a.tau[c] = (float)h->p.tau[c];
+        a.inv_tau[c] = (float)(1.0 / h->p.tau[c]);
+        a.shift[c] = shift_of(h, c);
+    }
+    a.G = (float)h->p.G;
+    a.ws_axis = (float)(h->p.sc_norm / 18.0);
+    a.ws_diag = (float)(h->p.sc_norm / 36.0);
+    a.inv_rho0 = (float)(1.0 / h->p.rho0);
+    for (int d = 0; d < 3; ++d) a.g[d] = (float)h->p.body_force[d];
+    a.wall_drho = (float)h->p.wall_drho;
+    a.keepf = !(h->p.tau[0] == 1.0 && h->p.tau[1] == 1.0);
+    return a;
+}
+
+static const int TILE_X[11] = {0, 32, 64, 32, 64, 16, 32, 64, 16, 32, 64},
+                 TILE_Y[11] = {0, 8, 4, 16, 8, 16, 8, 4, 16, 16, 8};
+
+// z planes per workgroup: enough workgroups to fill the chip (about 1024), at least 4
+// planes so the two extra halo planes stay a small share
+static int zchunk_of(const lbm_handle *h) {
+    if (h->zchunk > 0) return h->zchunk;
+    if (h->tile <= 0) return h->nz;
+    const int tiles = ((h->nx + TILE_X[h->tile] - 1) / TILE_X[h->tile]) *
+                      ((h->ny + TILE_Y[h->tile] - 1) / TILE_Y[h->tile]);
+    const int chunks = (1024 + tiles - 1) / tiles;
+    const int zc = (h->nz + chunks - 1) / chunks;
+    return zc < 4 ? 4 : zc;
+}
+
+extern "C" lbm_status lbm_set_launch(lbm_handle *h, int32_t tile, int32_t zchunk) {
+    if (!h) return LBM_E_INVAL;
+    if (tile < 0 || tile > 10 || zchunk < 0) return fail(h, LBM_E_INVAL, "invalid launch shape");
+    h->tile = tile;
+    h->zchunk = zchunk;
+    return LBM_OK;
+}
+
+extern "C" lbm_status lbm_step(lbm_handle *h, int64_t n) {
+    if (!h) return LBM_E_INVAL;
+    if (n < 0) return fail(h, LBM_E_INVAL, "negative step count");
+    if (!h->finalized) {
+        lbm_status s = finalize(h);
+        if (s != LBM_OK) return s;
+    }
+    const bool caps = !h->caps.empty();
+    const MembraneArgs m = caps ? membrane_args(h) : MembraneArgs{};
+    for (int64_t i = 0; i < n; ++i) {
+        if (caps) {
+            timed(h, "capsule_reduce", [&] { launch_capsule_reduce(m, h->st); });
+            timed(h, "window_clear", [&] { launch_window_clear(m, h->st); });
+            timed(h, "node_bin", [&] { launch_node_bin(m, h->st); });
+            timed(h, "membrane_forces", [&] { launch_membrane_forces(m, h->ntot, h->st); });
+            timed(h, "label_marks", [&] { launch_label_marks(m, h->ttot, h->st); });
+            timed(h, "window_fill", [&] { launch_window_fill(m, h->st); });
+        }
+        const FluidArgs a = fluid_args(h);
+        const int zc = zchunk_of(h);
+        timed(h, "fluid", [&] {
+            switch (h->storage) {
+                case 0: launch_fluid_tiled<0>(a, h->tile, zc, h->st); break;
+                case 1: launch_fluid_tiled<1>(a, h->tile, zc, h->st); break;
+                default: launch_fluid_tiled<2>(a, h->tile, zc, h->st); break;
+            }
+        });
+        if (caps) timed(h, "node_update", [&] { launch_node_update(m, h->ntot, h->st); });
+        h->cur = 1 - h->cur;
+        h->step++;
+    }
+    HIPCHK(h, hipGetLastError());
+    return LBM_OK;
+}
+
+static lbm_status check_status(lbm_handle *h, int st[ST_WORDS]) {
+    HIPCHK(h, hipMemcpyAsync(st, h->status, ST_WORDS * sizeof(int), hipMemcpyDeviceToHost, h->st));
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    return LBM_OK;
+}
+
+extern "C" lbm_status lbm_sync(lbm_handle *h) {
+    if (!h) return LBM_E_INVAL;
+    int st[ST_WORDS];
+    lbm_status s = check_status(h, st);
+    if (s != LBM_OK) return s;
+    if (st[ST_UNSTABLE] || st[ST_OVERFLOW])
+        return fail(h, LBM_E_UNSTABLE, st[ST_OVERFLOW] ? "capsule outgrew its window" : "non-finite or negative density");
+    return LBM_OK;
+}
+
+// ------------------------------------------------------------------------------------
+// Observables
+// ------------------------------------------------------------------------------------
+static void launch_rho_any(lbm_handle *h, float *dst) {
+    const float s0 = shift_of(h, 0), s1 = shift_of(h, 1);
+    switch (h->storage) {
+        case 0: launch_rho<0>(h->f[h->cur], dst, h->nx, h->ny, h->nz, h->wall, s0, s1, h->st); break;
+        case 1: launch_rho<1>(h->f[h->cur], dst, h->nx, h->ny, h->nz, h->wall, s0, s1, h->st); break;
+        default: launch_rho<2>(h->f[h->cur], dst, h->nx, h->ny, h->nz, h->wall, s0, s1, h->st); break;
+    }
+}
+
+extern "C" lbm_status lbm_observables(lbm_handle *h, lbm_obs *out) {
+    if (!h || !out) return LBM_E_INVAL;
+    const float s0 = shift_of(h, 0), s1 = shift_of(h, 1);
+    switch (h->storage) {
+        case 0: launch_moments<0>(h->f[h->cur], h->partial, MOM_BLOCKS, h->nx, h->ny, h->nz, h->wall, s0, s1, h->st); break;
+        case 1: launch_moments<1>(h->f[h->cur], h->partial, MOM_BLOCKS, h->nx, h->ny, h->nz, h->wall, s0, s1, h->st); break;
+        default: launch_moments<2>(h->f[h->cur], h->partial, MOM_BLOCKS, h->nx, h->ny, h->nz, h->wall, s0, s1, h->st); break;
+    }
+    HIPCHK(h, hipGetLastError());
+    std::vector<double> part((size_t)MOM_BLOCKS * 5);
+    HIPCHK(h, hipMemcpyAsync(part.data(), h->partial, part.size() * sizeof(double), hipMemcpyDeviceToHost, h->st));
+    if (out->rho || out->meniscus) {
+        launch_rho_any(h, h->rho_tmp);
+        HIPCHK(h, hipGetLastError());
+        if (out->rho)
+            HIPCHK(h, hipMemcpyAsync(out->rho, h->rho_tmp, 2 * (size_t)h->N * sizeof(float), hipMemcpyDeviceToHost, h->st));
+        if (out->meniscus) {
+            launch_meniscus(h->rho_tmp, h->flag, h->men_tmp, h->nx, h->ny, h->nz, h->wall, h->st);
+            HIPCHK(h, hipGetLastError());
+            HIPCHK(h, hipMemcpyAsync(out->meniscus, h->men_tmp, (size_t)h->nx * h->ny * sizeof(float), hipMemcpyDeviceToHost, h->st));
+        }
+    }
+    int st[ST_WORDS];
+    lbm_status s = check_status(h, st);
+    if (s != LBM_OK) return s;
+    lbm_summary &sm = out->summary;
+    std::memset(&sm, 0, sizeof sm);
+    for (int b = 0; b < MOM_BLOCKS; ++b) {
+        sm.mass[0] += part[5 * b];
+        sm.mass[1] += part[5 * b + 1];
+        for (int d = 0; d < 3; ++d) sm.momentum[d] += part[5 * b + 2 + d];
+    }
+    sm.step = h->step;
+    sm.lost_reaction = st[ST_LOST];
+    sm.n_capsules = (int)h->caps.size();
+    sm.unstable = (st[ST_UNSTABLE] || st[ST_OVERFLOW]) ? 1 : 0;
+    if (h->finalized && !h->caps.empty()) {
+        std::vector<double4> X(h->ntot);
+        std::vector<float4> Fh(h->ntot), R(h->ntot);
+        std::vector<CapState> cs(h->caps.size());
+        HIPCHK(h, hipMemcpy(X.data(), h->d_X, X.size() * sizeof(double4), hipMemcpyDeviceToHost));
+        HIPCHK(h, hipMemcpy(Fh.data(), h->d_Fh, Fh.size() * sizeof(float4), hipMemcpyDeviceToHost));
+        HIPCHK(h, hipMemcpy(R.data(), h->d_R, R.size() * sizeof(float4), hipMemcpyDeviceToHost));
+        HIPCHK(h, hipMemcpy(cs.data(), h->d_cst, cs.size() * sizeof(CapState), hipMemcpyDeviceToHost));
+        for (size_t k = 0; k < h->caps.size(); ++k) {
+            const CapDev &cd = h->h_caps[k];
+            double cen[3] = {0, 0, 0}, fr[3] = {0, 0, 0}, fh[3] = {0, 0, 0};
+            for (int i = 0; i < cd.nn; ++i) {
+                const double4 x = X[cd.node0 + i];
+                cen[0] += x.x; cen[1] += x.y; cen[2] += x.z;
+                fr[0] += R[cd.node0 + i].x; fr[1] += R[cd.node0 + i].y; fr[2] += R[cd.node0 + i].z;
+                fh[0] += Fh[cd.node0 + i].x; fh[1] += Fh[cd.node0 + i].y; fh[2] += Fh[cd.node0 + i].z;
+            }
+            for (int d = 0; d < 3; ++d) {
+                cen[d] /= cd.nn;
+                sm.pending[d] += fr[d];
+            }
+            if (out->capsules) {
+                lbm_capsule_obs &o = out->capsules[k];
+                const HostCap &hc = h->caps[k];
+                double vol = 0.0;
+                for (int t = 0; t < cd.nt; ++t) {
+                    const double4 A = X[cd.node0 + hc.tri[3 * t]], B = X[cd.node0 + hc.tri[3 * t + 1]],
+                                  C = X[cd.node0 + hc.tri[3 * t + 2]];
+                    const double a[3] = {A.x - cen[0], A.y - cen[1], A.z - cen[2]};
+                    const double b[3] = {B.x - cen[0], B.y - cen[1], B.z - cen[2]};
+                    const double c[3] = {C.x - cen[0], C.y - cen[1], C.z - cen[2]};
+                    vol += (a[0] * (b[1] * c[2] - b[2] * c[1]) + a[1] * (b[2] * c[0] - b[0] * c[2]) +
+                            a[2] * (b[0] * c[1] - b[1] * c[0])) / 6.0;
+                }
+                o.volume = vol;
+                for (int d = 0; d < 3; ++d) {
+                    o.centroid[d] = cen[d];
+                    o.f_capillary[d] = fr[d];
+                    o.f_hertz[d] = fh[d];
+                    // the anchor of the last step acted at its centroid cs.cen
+                    o.f_anchor[d] = (h->step > 0 && hc.p.anchor_k != 0.0)
+                                        ? hc.p.anchor_k * (cs[k].cen[d] - cd.c0[d]) : 0.0;
+                }
+            }
+        }
+    } else if (out->capsules) {
+        for (size_t k = 0; k < h->caps.size(); ++k) std::memset(&out->capsules[k], 0, sizeof(lbm_capsule_obs));
+    }
+    if (sm.unstable)
+        return fail(h, LBM_E_UNSTABLE, st[ST_OVERFLOW] ? "capsule outgrew its window" : "non-finite or negative density");
+    return LBM_OK;
+}
+
+extern "C" lbm_status lbm_rho_device(lbm_handle *h, float *rho_device) {
+    if (!h || !rho_device) return LBM_E_INVAL;
+    launch_rho_any(h, rho_device);
+    HIPCHK(h, hipGetLastError());
+    return LBM_OK;
+}
+
+extern "C" lbm_status lbm_capsule_nodes(lbm_handle *h, int32_t k, double *xyz) {
+    if (!h || !xyz || k < 0 || k >= (int)h->caps.size()) return LBM_E_INVAL;
+    const HostCap &c = h->caps[k];
+    const int nn = (int)c.x0.size() / 3;
+    if (!h->finalized) {
+        std::memcpy(xyz, c.x0.data(), 3 * nn * sizeof(double));
+        return LBM_OK;
+    }
+    std::vector<double4> X(nn);
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    HIPCHK(h, hipMemcpy(X.data(), h->d_X + h->h_caps[k].node0, nn * sizeof(double4), hipMemcpyDeviceToHost));
+    for (int i = 0; i < nn; ++i) {
+        xyz[3 * i] = X[i].x;
+        xyz[3 * i + 1] = X[i].y;
+        xyz[3 * i + 2] = X[i].z;
+    }
+    return LBM_OK;
+}
+
+extern "C" lbm_status lbm_labels(lbm_handle *h, uint8_t *out) {
+    if (!h || !out) return LBM_E_INVAL;
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    HIPCHK(h, hipMemcpy(out, h->flag, (size_t)h->N, hipMemcpyDeviceToHost));
+    const int plane = h->nx * h->ny;
+    for (int s = 0; s < h->N; ++s) out[s] &= LABEL_MASK;
+    if (h->wall)
+        for (int s = 0; s < plane; ++s) out[s] = 255;
+    return LBM_OK;
+}
+
+// ------------------------------------------------------------------------------------
+// Checkpoints
+// ------------------------------------------------------------------------------------
+namespace {
+struct CkptHeader {
+    char magic[8];
+    int32_t version, nx, ny, nz, storage, ncap, ntot, pad;
+    int64_t step;
+};
+}  // namespace
+
+extern "C" lbm_status lbm_save(lbm_handle *h, const char *path) {
+    if (!h || !path) return LBM_E_INVAL;
+    if (!h->finalized) {
+        lbm_status s = finalize(h);
+        if (s != LBM_OK) return s;
+    }
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    const size_t fbytes = 2 * (size_t)Q * h->N * h->esize;
+    std::vector<char> f(fbytes);
+    HIPCHK(h, hipMemcpy(f.data(), h->f[h->cur], fbytes, hipMemcpyDeviceToHost));
+    std::vector<double4> X(h->ntot);
+    std::vector<float4> R(h->ntot);
+    std::vector<CapState> cs(h->caps.size());
+    if (h->ntot) {
+        HIPCHK(h, hipMemcpy(X.data(), h->d_X, X.size() * sizeof(double4), hipMemcpyDeviceToHost));
+        HIPCHK(h, hipMemcpy(R.data(), h->d_R, R.size() * sizeof(float4), hipMemcpyDeviceToHost));
+        HIPCHK(h, hipMemcpy(cs.data(), h->d_cst, cs.size() * sizeof(CapState), hipMemcpyDeviceToHost));
+    }
+    FILE *fp = std::fopen(path, "wb");
+    if (!fp) return fail(h, LBM_E_INVAL, std::string("cannot open ") + path);
+    CkptHeader hd{};
+    std::memcpy(hd.magic, "LBMXCKP", 8);
+    hd.version = 1; hd.nx = h->nx; hd.ny = h->ny; hd.nz = h->nz; hd.storage = h->storage;
+    hd.ncap = (int)h->caps.size(); hd.ntot = h->ntot; hd.step = h->step;
+    bool ok = std::fwrite(&hd, sizeof hd, 1, fp) == 1 && std::fwrite(f.data(), 1, fbytes, fp) == fbytes;
+    if (h->ntot)
+        ok = ok && std::fwrite(X.data(), sizeof(double4), X.size(), fp) == X.size() &&
+             std::fwrite(R.data(), sizeof(float4), R.size(), fp) == R.size() &&
+             std::fwrite(cs.data(), sizeof(CapState), cs.size(), fp) == cs.size();
+    ok = (std::fclose(fp) == 0) && ok;
+    return ok ? LBM_OK : fail(h, LBM_E_INVAL, "checkpoint write failed");
+}
+
+extern "C" lbm_status lbm_load(lbm_handle *h, const char *path) {
+    if (!h || !path) return LBM_E_INVAL;
+    if (!h->finalized) {
+        lbm_status s = finalize(h);
+        if (s != LBM_OK) return s;
+    }
+    FILE *fp = std::fopen(path, "rb");
+    if (!fp) return fail(h, LBM_E_INVAL, std::string("cannot open ") + path);
+    CkptHeader hd{};
+    const size_t fbytes = 2 * (size_t)Q * h->N * h->esize;
+    std::vector<char> f(fbytes);
+    std::vector<double4> X(h->ntot);
+    std::vector<float4> R(h->ntot);
+    std::vector<CapState> cs(h->caps.size());
+    bool ok = std::fread(&hd, sizeof hd, 1, fp) == 1 && std::memcmp(hd.magic, "LBMXCKP", 8) == 0 &&
+              hd.version == 1 && hd.nx == h->nx && hd.ny == h->ny && hd.nz == h->nz &&
+              hd.storage == h->storage && hd.ncap == (int)h->caps.size() && hd.ntot == h->ntot &&
+              std::fread(f.data(), 1, fbytes, fp) == fbytes;
+    if (ok && h->ntot)
+        ok = std::fread(X.data(), sizeof(double4), X.size(), fp) == X.size() &&
+             std::fread(R.data(), sizeof(float4), R.size(), fp) == R.size() &&
+             std::fread(cs.data(), sizeof(CapState), cs.size(), fp) == cs.size();
+    std::fclose(fp);
+    if (!ok) return fail(h, LBM_E_INVAL, "checkpoint does not match this simulation");
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    HIPCHK(h, hipMemcpy(h->f[h->cur], f.data(), fbytes, hipMemcpyHostToDevice));
+    // every site flag is rebuilt by the next step; windows recorded in cs are cleared
+    HIPCHK(h, hipMemset(h->flag, 0, (size_t)h->N));
+    if (h->ntot) {
+        HIPCHK(h, hipMemcpy(h->d_X, X.data(), X.size() * sizeof(double4), hipMemcpyHostToDevice));
+        HIPCHK(h, hipMemcpy(h->d_R, R.data(), R.size() * sizeof(float4), hipMemcpyHostToDevice));
+        HIPCHK(h, hipMemcpy(h->d_cst, cs.data(), cs.size() * sizeof(CapState), hipMemcpyHostToDevice));
+    }
+    HIPCHK(h, hipMemset(h->status, 0, ST_WORDS * sizeof(int)));
+    h->step = hd.step;
+    return LBM_OK;
+}
+
+// ------------------------------------------------------------------------------------
+// Profiling and misc
+// ------------------------------------------------------------------------------------
+extern "C" lbm_status lbm_set_profiling(lbm_handle *h, int32_t on) {
+    if (!h) return LBM_E_INVAL;
+    h->profiling = on != 0;
+    return LBM_OK;
+}
+
+extern "C" lbm_status lbm_kernel_stats(lbm_handle *h, lbm_kernel_stat *out, int32_t max,
+                                       int32_t *n) {
+    if (!h || !n || (max > 0 && !out)) return LBM_E_INVAL;
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    collect_timers(h);
+    int k = 0;
+    for (auto &t : h->timers) {
+        if (k >= max) break;
+        std::memset(&out[k], 0, sizeof(lbm_kernel_stat));
+        std::snprintf(out[k].name, sizeof out[k].name, "%s", t.name);
+        out[k].launches = t.launches;
+        out[k].total_ms = t.ms;
+        ++k;
+    }
+    *n = k;
+    for (auto &t : h->timers) { t.launches = 0; t.ms = 0.0; }
+    return LBM_OK;
+}
+
+extern "C" double lbm_bytes_per_site(const lbm_handle *h) {
+    return h ? 2.0 * Q * 2.0 * (double)h->esize : 0.0;
+}
+
+extern "C" int64_t lbm_fluid_sites(const lbm_handle *h) {
+    return h ? (int64_t)h->nx * h->ny * (h->nz - h->wall) : 0;
+}
+
+extern "C" const char *lbm_last_error(const lbm_handle *h) {
+    return h ? h->err.c_str() : g_init_error.c_str();
+}
+
+extern "C" void lbm_destroy(lbm_handle *h) {
+    if (!h) return;
+    if (h->st) (void)hipStreamSynchronize(h->st);
+    free_all(h);
+    delete h;
+}

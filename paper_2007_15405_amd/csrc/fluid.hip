@@ -1,0 +1,883 @@
+// fluid.hip -- lattice Boltzmann kernels of liblbm (gfx950).
+//
+// Populations are stored structure-of-arrays, population-major: f[c][i][z][y][x], so a
+// wavefront touching 64 consecutive x reads 64 consecutive values of one population.
+// Streaming is "pull": the step at site x gathers f*_i(x - e_i) from the previous state;
+// where x - e_i is the wall layer, half-way bounce-back returns f*_{opp(i)}(x).
+//
+// Every population is read through its own buffer resource (base in scalar registers,
+// 32-bit byte offset per lane), which keeps 64-bit address arithmetic off the vector
+// ALU; out-of-range offsets read 0 and drop stores instead of faulting.
+#include "lbm_internal.h"
+
+namespace lbmx {
+
+__device__ __forceinline__ int wrap1(int a, int n) {
+    a += (a < 0) ? n : 0;
+    a -= (a >= n) ? n : 0;
+    return a;
+}
+
+__device__ __forceinline__ int wrapn(int a, int n) {
+    a %= n;
+    return a < 0 ? a + n : a;
+}
+
+// psi = 1 - exp(-rho / rho0) (Section 3.1), hardware exp2-based exponential
+__device__ __forceinline__ float psi_of(float rho, float inv_rho0) {
+    return 1.0f - __expf(-rho * inv_rho0);
+}
+
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// ------------------------------------------------------------------------------------
+// Population access
+// ------------------------------------------------------------------------------------
+template <int S> struct Pop {
+    using T = typename Codec<S>::T;
+    __device__ static inline __amdgpu_buffer_rsrc_t res(const void *f, int qg, int N) {
+        return __builtin_amdgcn_make_buffer_rsrc(
+            (void *)((const T *)f + (size_t)qg * N), (short)0, (int)((uint32_t)N * sizeof(T)),
+            0x00020000);
+    }
+    __device__ static inline float load(const void *f, int qg, int N, uint32_t site, float sh) {
+        const __amdgpu_buffer_rsrc_t r = res(f, qg, N);
+        if constexpr (sizeof(T) == 4) {
+            return Codec<S>::dec(__builtin_bit_cast(
+                                     float, __builtin_amdgcn_raw_buffer_load_b32(r, site * 4u, 0, 0)),
+                                 sh);
+        } else {
+            const uint16_t v = __builtin_amdgcn_raw_buffer_load_b16(r, site * 2u, 0, 0);
+            return Codec<S>::dec(__builtin_bit_cast(T, v), sh);
+        }
+    }
+    __device__ static inline void store(void *f, int qg, int N, uint32_t site, float v, float sh) {
+        const __amdgpu_buffer_rsrc_t r = res(f, qg, N);
+        const T e = Codec<S>::enc(v, sh);
+        if constexpr (sizeof(T) == 4)
+            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, e), r, site * 4u, 0, 0);
+        else
+            __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, e), r, site * 2u, 0, 0);
+    }
+};
+
+// Pull the 19 post-streaming populations of both components at site (x, y, z):
+// f_i(x) = f*_i(x - e_i), or f*_{opp(i)}(x) where x - e_i is the wall (half-way bounce-back).
+// wall_lo: the site below is the wall; wall_hi: the site above is the wall.
+template <int S, bool SUM_ONLY>
+__device__ __forceinline__ void pull(const void *f, int N, int x, int y, int z, int nx, int ny,
+                                     int nz, bool wall_lo, bool wall_hi, float sh0, float sh1,
+                                     float (&fl)[2][Q], float &r0, float &r1) {
+    const int xm = wrap1(x - 1, nx), xp = wrap1(x + 1, nx);
+    const int ym = wrap1(y - 1, ny), yp = wrap1(y + 1, ny);
+    const int zm = wrap1(z - 1, nz), zp = wrap1(z + 1, nz);
+    const int self = (z * ny + y) * nx + x;
+    float a0 = 0.f, a1 = 0.f;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int xs = CX[q] == 0 ? x : (CX[q] > 0 ? xm : xp);
+        const int ys = CY[q] == 0 ? y : (CY[q] > 0 ? ym : yp);
+        const int zs = CZ[q] == 0 ? z : (CZ[q] > 0 ? zm : zp);
+        const bool bb = (CZ[q] > 0 && wall_lo) || (CZ[q] < 0 && wall_hi);
+        const uint32_t src = bb ? self : (uint32_t)((zs * ny + ys) * nx + xs);
+        const int qq = bb ? OPP[q] : q;
+        const float v0 = Pop<S>::load(f, qq, N, src, wq(q) * sh0);
+        const float v1 = Pop<S>::load(f, Q + qq, N, src, wq(q) * sh1);
+        if (!SUM_ONLY) {
+            fl[0][q] = v0;
+            fl[1][q] = v1;
+        }
+        a0 += v0;
+        a1 += v1;
+    }
+    r0 = a0;
+    r1 = a1;
+}
+
+// Issue the 38 pulls of site (x, y, z) into registers without consuming them, so the
+// loads stay in flight while other work runs.  Links that cross the wall first read the
+// (unused) wall site; a wave-uniform fix-up then replaces them by the bounced
+// population f*_{opp(i)}(x), keeping the load stream free of per-link branches.
+template <int S>
+__device__ __forceinline__ void pull_issue(const void *f, int N, int x, int y, int z, int nx,
+                                           int ny, int nz, bool wall_lo, bool wall_hi, float sh0,
+                                           float sh1, float (&fl)[2][Q]) {
+    const int xm = wrap1(x - 1, nx), xp = wrap1(x + 1, nx);
+    const int ym = wrap1(y - 1, ny), yp = wrap1(y + 1, ny);
+    const int zm = wrap1(z - 1, nz), zp = wrap1(z + 1, nz);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int xs = CX[q] == 0 ? x : (CX[q] > 0 ? xm : xp);
+        const int ys = CY[q] == 0 ? y : (CY[q] > 0 ? ym : yp);
+        const int zs = CZ[q] == 0 ? z : (CZ[q] > 0 ? zm : zp);
+        const uint32_t src = (uint32_t)((zs * ny + ys) * nx + xs);
+        fl[0][q] = Pop<S>::load(f, q, N, src, wq(q) * sh0);
+        fl[1][q] = Pop<S>::load(f, Q + q, N, src, wq(q) * sh1);
+    }
+    if (wall_lo || wall_hi) {
+        const uint32_t self = (uint32_t)((z * ny + y) * nx + x);
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            if ((CZ[q] > 0 && wall_lo) || (CZ[q] < 0 && wall_hi)) {
+                fl[0][q] = Pop<S>::load(f, OPP[q], N, self, wq(q) * sh0);
+                fl[1][q] = Pop<S>::load(f, Q + OPP[q], N, self, wq(q) * sh1);
+            }
+        }
+    }
+}
+
+// Momentum sum_i f_i e_i; pairs (q, q+1) are opposite links for odd q.
+__device__ __forceinline__ void moments(const float (&f)[Q], float &jx, float &jy, float &jz) {
+    jx = ((f[1] - f[2]) + (f[5] - f[6])) + ((f[7] - f[8]) + (f[11] - f[12])) + (f[13] - f[14]);
+    jy = ((f[3] - f[4]) + (f[5] - f[6])) + ((f[8] - f[7]) + (f[15] - f[16])) + (f[17] - f[18]);
+    jz = ((f[9] - f[10]) + (f[11] - f[12])) + ((f[14] - f[13]) + (f[15] - f[16])) + (f[18] - f[17]);
+}
+
+// Stencil sum sum_i w_i psi_i e_i of eq. shanchen from the 18 neighbour values
+// pn[q - 1] (q = 1..18), evaluated as differences of opposite links.
+__device__ __forceinline__ void stencil(const float (&pn)[Q - 1], float wa, float wd, float &sx,
+                                        float &sy, float &sz) {
+    const float d1 = pn[0] - pn[1], d3 = pn[2] - pn[3], d5 = pn[4] - pn[5], d7 = pn[6] - pn[7];
+    const float d9 = pn[8] - pn[9], d11 = pn[10] - pn[11], d13 = pn[12] - pn[13];
+    const float d15 = pn[14] - pn[15], d17 = pn[16] - pn[17];
+    sx = wa * d1 + wd * ((d5 + d7) + (d11 + d13));
+    sy = wa * d3 + wd * ((d5 - d7) + (d15 + d17));
+    sz = wa * d9 + wd * ((d11 - d13) + (d15 - d17));
+}
+
+// Density and momentum of both components (the same summation order everywhere).
+__device__ __forceinline__ void site_moments(const float (&fl)[2][Q], float (&m)[8]) {
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        float r = 0.f;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) r += fl[c][q];
+        m[4 * c] = r;
+        moments(fl[c], m[4 * c + 1], m[4 * c + 2], m[4 * c + 3]);
+    }
+}
+
+// Forces, BGK collision (eq. method:boltzmann) towards eq. lbm:equilibrium at the
+// Shan-Chen shifted velocity, store; writes the physical velocity and the reaction
+// on window sites.  m: rho, j of both components; S0/S1: stencil sums over the partner
+// component of 0 and 1.  KEEPF: relax the pulled populations fl towards f^eq with
+// 1/tau; otherwise tau = 1 for both components and f* = f^eq needs only the moments.
+template <int S, bool KEEPF>
+__device__ __forceinline__ void collide_store(const FluidArgs &a, const float (&fl)[2][Q],
+                                              const float (&m)[8], uint32_t s, uint8_t fg,
+                                              float psi0, float psi1, const float (&S0)[3],
+                                              const float (&S1)[3], const float (&rx)[3]) {
+    const float rho[2] = {m[0], m[4]};
+    const float jx[2] = {m[1], m[5]}, jy[2] = {m[2], m[6]}, jz[2] = {m[3], m[7]};
+    if (!(rho[0] >= 0.f) || !(rho[1] >= 0.f) || !(rho[0] + rho[1] < 3.0e38f))
+        atomicOr(&a.status[ST_UNSTABLE], 1);
+    const float rt = rho[0] + rho[1];
+    const float irt = rt > 0.f ? rcp(rt) : 0.f;
+    const bool aux = (fg & AUX_BIT) != 0;
+    float fb[4] = {0.f, 0.f, 0.f, 0.f};
+    if (aux) {
+        const float4 v = a.ibm[s];
+        fb[0] = v.x; fb[1] = v.y; fb[2] = v.z; fb[3] = v.w;
+    }
+    const float m0 = rho[0] * irt, m1 = rho[1] * irt;
+    float F0[3], F1[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        F0[d] = -a.G * psi0 * S0[d] + m0 * fb[d] + rho[0] * a.g[d];
+        F1[d] = -a.G * psi1 * S1[d] + m1 * fb[d] + rho[1] * a.g[d];
+    }
+    // Shan-Chen common velocity u' = sum_c j^c/tau^c / sum_c rho^c/tau^c
+    const float den = rho[0] * a.inv_tau[0] + rho[1] * a.inv_tau[1];
+    const float id = den > 0.f ? rcp(den) : 0.f;
+    const float up0 = (jx[0] * a.inv_tau[0] + jx[1] * a.inv_tau[1]) * id;
+    const float up1 = (jy[0] * a.inv_tau[0] + jy[1] * a.inv_tau[1]) * id;
+    const float up2 = (jz[0] * a.inv_tau[0] + jz[1] * a.inv_tau[1]) * id;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const float *Fc = c == 0 ? F0 : F1;
+        const float k = rho[c] > 0.f ? a.tau[c] * rcp(rho[c]) : 0.f;
+        const float u0 = up0 + k * Fc[0], u1 = up1 + k * Fc[1], u2 = up2 + k * Fc[2];
+        const float uu = 1.5f * (u0 * u0 + u1 * u1 + u2 * u2);
+        const float om = a.inv_tau[c];
+        const float sh = a.shift[c];
+        // f^eq of opposite links: symmetric part A, antisymmetric part B; the rest
+        // population takes rho - sum so the rounded weights add no mass
+        float feq[Q], sum = 0.f;
+#pragma unroll
+        for (int q = 1; q < Q; q += 2) {
+            const float w = wq(q) * rho[c];
+            const float eu = CX[q] * u0 + CY[q] * u1 + CZ[q] * u2;
+            const float A = w * (1.0f + 4.5f * eu * eu - uu);
+            const float B = 3.0f * w * eu;
+            feq[q] = A + B;
+            feq[q + 1] = A - B;
+            sum += feq[q] + feq[q + 1];
+        }
+        feq[0] = rho[c] - sum;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const float fs = KEEPF ? fl[c][q] + om * (feq[q] - fl[c][q]) : feq[q];
+            Pop<S>::store(a.fout, c * Q + q, a.N, s, fs, wq(q) * sh);
+        }
+    }
+    if (aux) {
+        a.uo[s] = make_float4((jx[0] + jx[1] + 0.5f * (F0[0] + F1[0])) * irt,
+                              (jy[0] + jy[1] + 0.5f * (F0[1] + F1[1])) * irt,
+                              (jz[0] + jz[1] + 0.5f * (F0[2] + F1[2])) * irt, 0.f);
+        a.ro[s] = make_float4(rx[0], rx[1], rx[2], 0.f);
+    }
+    if ((rx[0] != 0.f || rx[1] != 0.f || rx[2] != 0.f) && !(aux && fb[3] > 0.f))
+        atomicAdd(&a.status[ST_LOST], 1);
+}
+
+// Neighbour psi across labels (eq. shanchen with the decoupling of Section 3.1): the
+// neighbour's own psi on the same side; across the wall or a membrane the partner's
+// density at x itself plus the wetting offset (+ for component 0, - for component 1).
+// Returns the stencil sums and the reaction G sum_c psi^c (cross-membrane part).
+__device__ __forceinline__ void sc_general(const FluidArgs &a, const float *cap_drho,
+                                           const float (&p0n)[Q - 1], const float (&p1n)[Q - 1],
+                                           const int (&nlab)[Q - 1], int lab, float rho0,
+                                           float rho1, float psi0, float psi1, float (&S0)[3],
+                                           float (&S1)[3], float (&rx)[3]) {
+    float e0[Q - 1], e1[Q - 1];
+    bool anycross = false;
+#pragma unroll
+    for (int q = 1; q < Q; ++q) {
+        e0[q - 1] = p0n[q - 1];
+        e1[q - 1] = p1n[q - 1];
+        if (nlab[q - 1] != lab) {
+            const int nl = nlab[q - 1];
+            const float dr = nl == LABEL_WALL ? a.wall_drho : cap_drho[(nl != 0 ? nl : lab) - 1];
+            e0[q - 1] = psi_of(fmaxf(rho0 + dr, 0.f), a.inv_rho0);
+            e1[q - 1] = psi_of(fmaxf(rho1 - dr, 0.f), a.inv_rho0);
+            anycross = anycross || nl != LABEL_WALL;
+        }
+    }
+    stencil(e1, a.ws_axis, a.ws_diag, S0[0], S0[1], S0[2]);
+    stencil(e0, a.ws_axis, a.ws_diag, S1[0], S1[1], S1[2]);
+    rx[0] = rx[1] = rx[2] = 0.f;
+    if (anycross) {
+        float c1[Q - 1], c0[Q - 1];
+#pragma unroll
+        for (int q = 1; q < Q; ++q) {
+            const bool cr = nlab[q - 1] != lab && nlab[q - 1] != LABEL_WALL;
+            c1[q - 1] = cr ? e1[q - 1] : 0.f;
+            c0[q - 1] = cr ? e0[q - 1] : 0.f;
+        }
+        float C0[3], C1[3];
+        stencil(c1, a.ws_axis, a.ws_diag, C0[0], C0[1], C0[2]);
+        stencil(c0, a.ws_axis, a.ws_diag, C1[0], C1[1], C1[2]);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) rx[d] = a.G * (psi0 * C0[d] + psi1 * C1[d]);
+    }
+}
+
+// ------------------------------------------------------------------------------------
+// f* = f^eq(rho, 0) = w_i rho at every fluid site (eq. lbm:equilibrium at rest).
+// ------------------------------------------------------------------------------------
+template <int S>
+__global__ void k_init_eq(const double *__restrict__ rho, void *f, int nx, int ny, int nz,
+                          int wall, float sh0, float sh1) {
+    const int N = nx * ny * nz;
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= N) return;
+    const int z = s / (nx * ny);
+    const bool solid = wall && z == 0;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const double w = (double)wq(q);
+        Pop<S>::store(f, q, N, s, solid ? 0.0f : (float)(w * rho[s]), wq(q) * sh0);
+        Pop<S>::store(f, Q + q, N, s, solid ? 0.0f : (float)(w * rho[N + s]), wq(q) * sh1);
+    }
+}
+
+template <int S>
+void launch_init_eq(const double *rho_dev, void *f, int nx, int ny, int nz, int wall, float s0,
+                    float s1, hipStream_t st) {
+    const int N = nx * ny * nz;
+    hipLaunchKernelGGL(k_init_eq<S>, dim3((N + 255) / 256), dim3(256), 0, st, rho_dev, f, nx, ny,
+                       nz, wall, s0, s1);
+}
+
+// ------------------------------------------------------------------------------------
+// Two-kernel variant: pass 1 writes psi of every site, pass 2 gathers the neighbour psi
+// from memory.  Same per-site arithmetic as the fused kernel.
+// ------------------------------------------------------------------------------------
+template <int S>
+__global__ void __launch_bounds__(256) k_density(FluidArgs a) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= a.N) return;
+    const int x = s % a.nx, t = s / a.nx, y = t % a.ny, z = t / a.ny;
+    if (a.wall && z == 0) return;
+    float fl[2][Q], r0, r1;
+    pull<S, true>(a.fin, a.N, x, y, z, a.nx, a.ny, a.nz, a.wall && z == 1,
+                  a.wall && z == a.nz - 1, a.shift[0], a.shift[1], fl, r0, r1);
+    a.psi[s] = psi_of(r0, a.inv_rho0);
+    a.psi[a.N + s] = psi_of(r1, a.inv_rho0);
+}
+
+template <int S, bool KEEPF>
+__global__ void __launch_bounds__(256) k_collide(FluidArgs a) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= a.N) return;
+    const int nx = a.nx, ny = a.ny, nz = a.nz, N = a.N;
+    const int x = s % nx, t = s / nx, y = t % ny, z = t / ny;
+    if (a.wall && z == 0) return;
+    float fl[2][Q], r0, r1, m[8];
+    pull<S, false>(a.fin, N, x, y, z, nx, ny, nz, a.wall && z == 1, a.wall && z == nz - 1,
+                   a.shift[0], a.shift[1], fl, r0, r1);
+    site_moments(fl, m);
+    const uint8_t fg = a.flag[s];
+    const int lab = fg & LABEL_MASK;
+    float p0n[Q - 1], p1n[Q - 1];
+    int nlab[Q - 1];
+#pragma unroll
+    for (int q = 1; q < Q; ++q) {
+        const int xn = wrap1(x + CX[q], nx), yn = wrap1(y + CY[q], ny), zn = wrap1(z + CZ[q], nz);
+        const int sn = (zn * ny + yn) * nx + xn;
+        const bool solid_n = a.wall && zn == 0;
+        nlab[q - 1] = solid_n ? LABEL_WALL : (a.flag[sn] & LABEL_MASK);
+        p0n[q - 1] = solid_n ? 0.f : a.psi[sn];
+        p1n[q - 1] = solid_n ? 0.f : a.psi[N + sn];
+    }
+    float S0[3], S1[3], rx[3];
+    sc_general(a, a.cap_drho, p0n, p1n, nlab, lab, m[0], m[4], a.psi[s], a.psi[N + s], S0, S1, rx);
+    collide_store<S, KEEPF>(a, fl, m, (uint32_t)s, fg, a.psi[s], a.psi[N + s], S0, S1, rx);
+}
+
+template <int S>
+void launch_fluid(const FluidArgs &a, hipStream_t st) {
+    const dim3 grid((a.N + 255) / 256), blk(256);
+    hipLaunchKernelGGL(k_density<S>, grid, blk, 0, st, a);
+    if (a.keepf)
+        hipLaunchKernelGGL((k_collide<S, true>), grid, blk, 0, st, a);
+    else
+        hipLaunchKernelGGL((k_collide<S, false>), grid, blk, 0, st, a);
+}
+
+// ------------------------------------------------------------------------------------
+// Fused single-read fluid step.  A workgroup owns a TX x TY tile of lattice columns and
+// marches up a chunk of z planes.  At plane p every thread pulls the 38 populations of
+// its site once (kept in registers), computes psi^c and publishes psi and the site flag
+// into a three-plane LDS ring that also holds a one-site halo ring around the tile (halo
+// sites only sum their pulled populations).  After a barrier the previous plane p-1 is
+// collided from registers and the LDS ring, and stored.  A tile-plane whose three LDS
+// planes carry no label, window or wall takes the plain path (no label tests).  Each LDS
+// position holds the periodically wrapped site, so ragged tiles and boxes smaller than
+// a tile need no special case.  Blocks are renumbered so that consecutive tiles run on
+// one XCD and share its L2 for the halo re-reads.
+// ------------------------------------------------------------------------------------
+constexpr uint8_t WALL_FLAG = (uint8_t)LABEL_WALL;
+
+template <int S, int TX, int TY, bool KEEPF>
+__global__ void __launch_bounds__(TX * TY) k_fused(FluidArgs a, int zc, int tiles_x, int tiles_y,
+                                                   int nblocks) {
+    constexpr int KQ = KEEPF ? Q : 1;   // populations held between pull and collision
+    constexpr int NT = TX * TY, LX = TX + 2, LY = TY + 2, NL = LX * LY, NH = NL - NT;
+    static_assert(NH <= NT, "halo ring larger than the tile");
+    __shared__ float s_psi[3][2][NL];
+    __shared__ uint8_t s_flag[3][NL];
+
+    // XCD-aware renumbering: hardware block b runs on XCD b % 8; give each XCD a
+    // contiguous run of logical tiles
+    const int per = (int)gridDim.x / 8;
+    const int L = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+    if (L >= nblocks) return;
+    const int bx = L % tiles_x, t2 = L / tiles_x, by = t2 % tiles_y, bz = t2 / tiles_y;
+    const int nx = a.nx, ny = a.ny, nz = a.nz, N = a.N;
+    const int x0 = bx * TX, y0 = by * TY, z0 = bz * zc, z1 = min(z0 + zc, nz);
+    const float sh0 = a.shift[0], sh1 = a.shift[1];
+
+    const int tid = threadIdx.x, lx = tid % TX, ly = tid / TX;
+    const int li = (ly + 1) * LX + (lx + 1);
+    const int ix = wrapn(x0 + lx, nx), iy = wrapn(y0 + ly, ny);
+    const bool valid = (x0 + lx < nx) && (y0 + ly < ny);
+    // halo ring position of this thread (if any): rows -1 and TY, then columns -1 and TX
+    int hi = -1, hx = 0, hy = 0;
+    if (tid < NH) {
+        int h = tid;
+        if (h < LX) { hx = h - 1; hy = -1; }
+        else if (h < 2 * LX) { hx = h - LX - 1; hy = TY; }
+        else { h -= 2 * LX; hy = h >> 1; hx = (h & 1) ? TX : -1; }
+        hi = (hy + 1) * LX + (hx + 1);
+        hx = wrapn(x0 + hx, nx);
+        hy = wrapn(y0 + hy, ny);
+    }
+
+    // per site state carried from the pull of plane p to its collision: the moments and,
+    // with KEEPF, the populations
+    float fa[2][KQ], fb[2][KQ], ma[8], mb[8];
+#pragma unroll
+    for (int q = 0; q < KQ; ++q) { fa[0][q] = fa[1][q] = fb[0][q] = fb[1][q] = 0.f; }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) { ma[i] = mb[i] = 0.f; }
+    int busy1 = 1, busy2 = 1;   // LDS planes p-1, p-2 carry labels, windows or walls
+
+    // one plane: pull plane p into (nxt, mn), collide plane p - 1 from (cur, mc)
+    auto plane = [&](int p, float (&cur)[2][KQ], float (&mc)[8], float (&nxt)[2][KQ],
+                     float (&mn)[8]) {
+        const int slot = (p - z0 + 1) % 3;
+        const int pz = wrapn(p, nz);
+        const bool solid = a.wall && pz == 0;
+        const bool wlo = a.wall && pz == 1, whi = a.wall && pz == nz - 1;
+        uint8_t fg_me;
+        {
+            float fl[2][Q], r0 = 0.f, r1 = 0.f;
+            if (!solid) {
+                pull<S, false>(a.fin, N, ix, iy, pz, nx, ny, nz, wlo, whi, sh0, sh1, fl, r0, r1);
+                site_moments(fl, mn);
+                if (KEEPF) {
+#pragma unroll
+                    for (int q = 0; q < KQ; ++q) { nxt[0][q] = fl[0][q]; nxt[1][q] = fl[1][q]; }
+                }
+            }
+            s_psi[slot][0][li] = psi_of(r0, a.inv_rho0);
+            s_psi[slot][1][li] = psi_of(r1, a.inv_rho0);
+            fg_me = solid ? WALL_FLAG : a.flag[(pz * ny + iy) * nx + ix];
+            s_flag[slot][li] = fg_me;
+        }
+        uint8_t fg_h = 0;
+        if (hi >= 0) {
+            float r0 = 0.f, r1 = 0.f, dummy[2][Q];
+            if (!solid)
+                pull<S, true>(a.fin, N, hx, hy, pz, nx, ny, nz, wlo, whi, sh0, sh1, dummy, r0, r1);
+            s_psi[slot][0][hi] = psi_of(r0, a.inv_rho0);
+            s_psi[slot][1][hi] = psi_of(r1, a.inv_rho0);
+            fg_h = solid ? WALL_FLAG : a.flag[(pz * ny + hy) * nx + hx];
+            s_flag[slot][hi] = fg_h;
+        }
+        const int busy0 = __syncthreads_or((fg_me | fg_h) != 0);
+        const int pc = p - 1;
+        const int cz = wrapn(pc, nz);
+        if (pc >= z0 && valid && !(a.wall && cz == 0)) {
+            const int sc = (p - z0) % 3, sd = (p - z0 + 2) % 3;   // planes p - 1 and p - 2
+            const uint32_t s = (uint32_t)((cz * ny + iy) * nx + ix);
+            const float psi0 = s_psi[sc][0][li], psi1 = s_psi[sc][1][li];
+            float p0n[Q - 1], p1n[Q - 1];
+#pragma unroll
+            for (int q = 1; q < Q; ++q) {
+                const int ns = CZ[q] == 0 ? sc : (CZ[q] > 0 ? slot : sd);
+                const int nl = li + CX[q] + CY[q] * LX;
+                p0n[q - 1] = s_psi[ns][0][nl];
+                p1n[q - 1] = s_psi[ns][1][nl];
+            }
+            float S0[3], S1[3], rx[3] = {0.f, 0.f, 0.f};
+            uint8_t fg = 0;
+            if (!(busy0 | busy1 | busy2)) {
+                stencil(p1n, a.ws_axis, a.ws_diag, S0[0], S0[1], S0[2]);
+                stencil(p0n, a.ws_axis, a.ws_diag, S1[0], S1[1], S1[2]);
+            } else {
+                fg = s_flag[sc][li];
+                int nlab[Q - 1];
+#pragma unroll
+                for (int q = 1; q < Q; ++q) {
+                    const int ns = CZ[q] == 0 ? sc : (CZ[q] > 0 ? slot : sd);
+                    nlab[q - 1] = s_flag[ns][li + CX[q] + CY[q] * LX] & LABEL_MASK;
+                }
+                sc_general(a, a.cap_drho, p0n, p1n, nlab, fg & LABEL_MASK, mc[0], mc[4], psi0, psi1,
+                           S0, S1, rx);
+            }
+            float fl[2][Q];
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                fl[0][q] = KEEPF ? cur[0][q % KQ] : 0.f;
+                fl[1][q] = KEEPF ? cur[1][q % KQ] : 0.f;
+            }
+            collide_store<S, KEEPF>(a, fl, mc, s, fg, psi0, psi1, S0, S1, rx);
+        }
+        busy2 = busy1;
+        busy1 = busy0;
+        __syncthreads();
+    };
+
+    int p = z0 - 1;
+    for (; p + 1 <= z1; p += 2) {
+        plane(p, fb, mb, fa, ma);
+        plane(p + 1, fa, ma, fb, mb);
+    }
+    if (p <= z1) plane(p, fb, mb, fa, ma);
+}
+
+// ------------------------------------------------------------------------------------
+// Software-pipelined fused step for tau = 1 (f* = f^eq needs only the moments).  Each
+// wave issues the pulls of plane p+2 (its tile site and, for the first NH threads, a
+// halo site), collides plane p from the LDS ring while those loads are in flight, then
+// folds them into moments and psi of plane p+2.  A four-plane LDS ring (p-1 .. p+2)
+// needs one barrier per plane; whether a plane holds any label, window or wall is
+// reduced per wave with a ballot and published next to the ring.
+// ------------------------------------------------------------------------------------
+template <int S>
+__device__ __forceinline__ void collide_store_eq(const FluidArgs &a, const float (&m)[8],
+                                                 uint32_t s, uint8_t fg, float psi0, float psi1,
+                                                 const float (&S0)[3], const float (&S1)[3],
+                                                 const float (&rx)[3]) {
+    const float rho[2] = {m[0], m[4]};
+    const float jx[2] = {m[1], m[5]}, jy[2] = {m[2], m[6]}, jz[2] = {m[3], m[7]};
+    if (!(rho[0] >= 0.f) || !(rho[1] >= 0.f) || !(rho[0] + rho[1] < 3.0e38f))
+        atomicOr(&a.status[ST_UNSTABLE], 1);
+    const float rt = rho[0] + rho[1];
+    const float irt = rt > 0.f ? rcp(rt) : 0.f;
+    const bool aux = (fg & AUX_BIT) != 0;
+    float fb[4] = {0.f, 0.f, 0.f, 0.f};
+    if (aux) {
+        const float4 v = a.ibm[s];
+        fb[0] = v.x; fb[1] = v.y; fb[2] = v.z; fb[3] = v.w;
+    }
+    const float m0 = rho[0] * irt, m1 = rho[1] * irt;
+    float F0[3], F1[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        F0[d] = -a.G * psi0 * S0[d] + m0 * fb[d] + rho[0] * a.g[d];
+        F1[d] = -a.G * psi1 * S1[d] + m1 * fb[d] + rho[1] * a.g[d];
+    }
+    const float den = rho[0] * a.inv_tau[0] + rho[1] * a.inv_tau[1];
+    const float id = den > 0.f ? rcp(den) : 0.f;
+    const float up0 = (jx[0] * a.inv_tau[0] + jx[1] * a.inv_tau[1]) * id;
+    const float up1 = (jy[0] * a.inv_tau[0] + jy[1] * a.inv_tau[1]) * id;
+    const float up2 = (jz[0] * a.inv_tau[0] + jz[1] * a.inv_tau[1]) * id;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const float *Fc = c == 0 ? F0 : F1;
+        const float k = rho[c] > 0.f ? a.tau[c] * rcp(rho[c]) : 0.f;
+        const float u0 = up0 + k * Fc[0], u1 = up1 + k * Fc[1], u2 = up2 + k * Fc[2];
+        const float uu = 1.5f * (u0 * u0 + u1 * u1 + u2 * u2);
+        const float sh = a.shift[c];
+        float sum = 0.f;
+#pragma unroll
+        for (int q = 1; q < Q; q += 2) {
+            const float w = wq(q) * rho[c];
+            const float eu = CX[q] * u0 + CY[q] * u1 + CZ[q] * u2;
+            const float A = w * (1.0f + 4.5f * eu * eu - uu);
+            const float B = 3.0f * w * eu;
+            const float fq = A + B, fo = A - B;
+            sum += fq + fo;
+            Pop<S>::store(a.fout, c * Q + q, a.N, s, fq, wq(q) * sh);
+            Pop<S>::store(a.fout, c * Q + q + 1, a.N, s, fo, wq(q) * sh);
+        }
+        Pop<S>::store(a.fout, c * Q, a.N, s, rho[c] - sum, wq(0) * sh);
+    }
+    if (aux) {
+        a.uo[s] = make_float4((jx[0] + jx[1] + 0.5f * (F0[0] + F1[0])) * irt,
+                              (jy[0] + jy[1] + 0.5f * (F0[1] + F1[1])) * irt,
+                              (jz[0] + jz[1] + 0.5f * (F0[2] + F1[2])) * irt, 0.f);
+        a.ro[s] = make_float4(rx[0], rx[1], rx[2], 0.f);
+    }
+    if ((rx[0] != 0.f || rx[1] != 0.f || rx[2] != 0.f) && !(aux && fb[3] > 0.f))
+        atomicAdd(&a.status[ST_LOST], 1);
+}
+
+template <int S, int TX, int TY>
+__global__ void __launch_bounds__(TX * TY) k_fused_pipe(FluidArgs a, int zc, int tiles_x,
+                                                        int tiles_y, int nblocks) {
+    constexpr int NT = TX * TY, LX = TX + 2, LY = TY + 2, NL = LX * LY, NH = NL - NT;
+    constexpr int NW = NT / 64;
+    static_assert(NH <= NT && NT % 64 == 0, "tile shape");
+    __shared__ float s_psi[4][2][NL];
+    __shared__ uint8_t s_flag[4][NL];
+    __shared__ int s_busy[4][NW];
+    __shared__ float s_drho[MAX_CAPS];
+
+    const int per = (int)gridDim.x / 8;
+    const int L = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+    if (L >= nblocks) return;
+    const int bx = L % tiles_x, t2 = L / tiles_x, by = t2 % tiles_y, bz = t2 / tiles_y;
+    const int nx = a.nx, ny = a.ny, nz = a.nz, N = a.N;
+    const int x0 = bx * TX, y0 = by * TY, z0 = bz * zc, z1 = min(z0 + zc, nz);
+    const float sh0 = a.shift[0], sh1 = a.shift[1];
+
+    const int tid = threadIdx.x, lx = tid % TX, ly = tid / TX;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int li = (ly + 1) * LX + (lx + 1);
+    const int ix = wrapn(x0 + lx, nx), iy = wrapn(y0 + ly, ny);
+    const bool valid = (x0 + lx < nx) && (y0 + ly < ny);
+    int hi = -1, hx = 0, hy = 0;
+    if (tid < NH) {
+        int h = tid;
+        if (h < LX) { hx = h - 1; hy = -1; }
+        else if (h < 2 * LX) { hx = h - LX - 1; hy = TY; }
+        else { h -= 2 * LX; hy = h >> 1; hx = (h & 1) ? TX : -1; }
+        hi = (hy + 1) * LX + (hx + 1);
+        hx = wrapn(x0 + hx, nx);
+        hy = wrapn(y0 + hy, ny);
+    }
+
+    for (int i = tid; i < MAX_CAPS; i += NT) s_drho[i] = a.cap_drho[i];
+
+    // publish psi, flags and the busy bit of plane p from the pulled populations
+    auto publish = [&](int p, bool solid, int pz, const float (&fl)[2][Q],
+                       const float (&hf)[2][Q], uint8_t fl_me, uint8_t fl_h, float (&m)[8]) {
+        const int slot = (p - z0 + 4) & 3;
+        float r0 = 0.f, r1 = 0.f, h0 = 0.f, h1 = 0.f;
+        if (!solid) {
+#pragma unroll
+            for (int q = 0; q < Q; ++q) { r0 += fl[0][q]; r1 += fl[1][q]; }
+            site_moments(fl, m);
+            if (hi >= 0) {
+#pragma unroll
+                for (int q = 0; q < Q; ++q) { h0 += hf[0][q]; h1 += hf[1][q]; }
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) m[i] = 0.f;
+        }
+        const uint8_t fg_me = solid ? WALL_FLAG : fl_me;
+        s_psi[slot][0][li] = psi_of(r0, a.inv_rho0);
+        s_psi[slot][1][li] = psi_of(r1, a.inv_rho0);
+        s_flag[slot][li] = fg_me;
+        uint8_t fg_h = 0;
+        if (hi >= 0) {
+            fg_h = solid ? WALL_FLAG : fl_h;
+            s_psi[slot][0][hi] = psi_of(h0, a.inv_rho0);
+            s_psi[slot][1][hi] = psi_of(h1, a.inv_rho0);
+            s_flag[slot][hi] = fg_h;
+        }
+        const bool any = __builtin_amdgcn_ballot_w64((fg_me | fg_h) != 0) != 0;
+        if (lane == 0) s_busy[slot][wave] = any ? 1 : 0;
+    };
+    // issue the pulls and flag reads of plane p (tile site, and the halo site of the
+    // first NH threads)
+    auto issue = [&](int p, float (&fl)[2][Q], float (&hf)[2][Q], uint8_t &g_me, uint8_t &g_h) {
+        const int pz = wrapn(p, nz);
+        const bool wlo = a.wall && pz == 1, whi = a.wall && pz == nz - 1;
+        g_me = g_h = 0;
+        if (!(a.wall && pz == 0)) {
+            g_me = a.flag[(pz * ny + iy) * nx + ix];
+            pull_issue<S>(a.fin, N, ix, iy, pz, nx, ny, nz, wlo, whi, sh0, sh1, fl);
+            if (hi >= 0) {
+                g_h = a.flag[(pz * ny + hy) * nx + hx];
+                pull_issue<S>(a.fin, N, hx, hy, pz, nx, ny, nz, wlo, whi, sh0, sh1, hf);
+            }
+        }
+    };
+    auto load_plane = [&](int p, float (&m)[8]) {
+        float fl[2][Q], hf[2][Q];
+        uint8_t g_me, g_h;
+        issue(p, fl, hf, g_me, g_h);
+        const int pz = wrapn(p, nz);
+        publish(p, a.wall && pz == 0, pz, fl, hf, g_me, g_h, m);
+    };
+
+    float m0[8], m1[8], m2[8];   // moments of planes p, p+1, p+2
+    load_plane(z0 - 1, m2);
+    load_plane(z0, m0);
+    load_plane(z0 + 1, m1);
+    __syncthreads();
+    for (int p = z0; p < z1; ++p) {
+        // issue the pulls of plane p+2 first; they complete while plane p is collided
+        const bool more = p + 2 <= z1;
+        float fl[2][Q], hf[2][Q];
+        uint8_t g_me = 0, g_h = 0;
+        const int pn = wrapn(p + 2, nz);
+        const bool nsolid = a.wall && pn == 0;
+        if (more) issue(p + 2, fl, hf, g_me, g_h);
+        // ---- collide plane p ----
+        const int cz = wrapn(p, nz);
+        if (valid && !(a.wall && cz == 0)) {
+            const int sc = (p - z0 + 4) & 3, su = (p - z0 + 5) & 3, sd = (p - z0 + 3) & 3;
+            int busy = 0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) busy |= s_busy[sc][w] | s_busy[su][w] | s_busy[sd][w];
+            const uint32_t s = (uint32_t)((cz * ny + iy) * nx + ix);
+            const float psi0 = s_psi[sc][0][li], psi1 = s_psi[sc][1][li];
+            float p0n[Q - 1], p1n[Q - 1];
+#pragma unroll
+            for (int q = 1; q < Q; ++q) {
+                const int ns = CZ[q] == 0 ? sc : (CZ[q] > 0 ? su : sd);
+                const int nl = li + CX[q] + CY[q] * LX;
+                p0n[q - 1] = s_psi[ns][0][nl];
+                p1n[q - 1] = s_psi[ns][1][nl];
+            }
+            float S0[3], S1[3], rx[3] = {0.f, 0.f, 0.f};
+            uint8_t fg = 0;
+            if (!busy) {
+                stencil(p1n, a.ws_axis, a.ws_diag, S0[0], S0[1], S0[2]);
+                stencil(p0n, a.ws_axis, a.ws_diag, S1[0], S1[1], S1[2]);
+            } else {
+                fg = s_flag[sc][li];
+                int nlab[Q - 1];
+#pragma unroll
+                for (int q = 1; q < Q; ++q) {
+                    const int ns = CZ[q] == 0 ? sc : (CZ[q] > 0 ? su : sd);
+                    nlab[q - 1] = s_flag[ns][li + CX[q] + CY[q] * LX] & LABEL_MASK;
+                }
+                sc_general(a, s_drho, p0n, p1n, nlab, fg & LABEL_MASK, m0[0], m0[4], psi0, psi1, S0,
+                           S1, rx);
+            }
+            collide_store_eq<S>(a, m0, s, fg, psi0, psi1, S0, S1, rx);
+        }
+        // ---- fold plane p+2 into the ring ----
+        if (more) {
+            float mn[8];
+            publish(p + 2, nsolid, pn, fl, hf, g_me, g_h, mn);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) { m0[i] = m1[i]; m1[i] = mn[i]; }
+        } else {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) m0[i] = m1[i];
+        }
+        __syncthreads();
+    }
+    (void)m2;
+}
+
+template <int S, int TX, int TY>
+static void launch_pipe_t(const FluidArgs &a, int zc, hipStream_t st) {
+    const int tx = (a.nx + TX - 1) / TX, ty = (a.ny + TY - 1) / TY, tz = (a.nz + zc - 1) / zc;
+    const int nb = tx * ty * tz;
+    const int grid = (nb + 7) / 8 * 8;
+    hipLaunchKernelGGL((k_fused_pipe<S, TX, TY>), dim3(grid), dim3(TX * TY), 0, st, a, zc, tx, ty,
+                       nb);
+}
+
+template <int S, int TX, int TY>
+static void launch_fused_t(const FluidArgs &a, int zc, hipStream_t st) {
+    const int tx = (a.nx + TX - 1) / TX, ty = (a.ny + TY - 1) / TY, tz = (a.nz + zc - 1) / zc;
+    const int nb = tx * ty * tz;
+    const int grid = (nb + 7) / 8 * 8;
+    if (a.keepf)
+        hipLaunchKernelGGL((k_fused<S, TX, TY, true>), dim3(grid), dim3(TX * TY), 0, st, a, zc, tx,
+                           ty, nb);
+    else
+        hipLaunchKernelGGL((k_fused<S, TX, TY, false>), dim3(grid), dim3(TX * TY), 0, st, a, zc,
+                           tx, ty, nb);
+}
+
+// tile: 0 two-kernel variant; 1: 32x8; 2: 64x4; 3: 32x16; 4: 64x8; 5: 16x16
+template <int S>
+void launch_fluid_tiled(const FluidArgs &a, int tile, int zc, hipStream_t st) {
+    switch (tile) {
+        case 1: launch_fused_t<S, 32, 8>(a, zc, st); break;
+        case 2: launch_fused_t<S, 64, 4>(a, zc, st); break;
+        case 3: launch_fused_t<S, 32, 16>(a, zc, st); break;
+        case 4: launch_fused_t<S, 64, 8>(a, zc, st); break;
+        case 5: launch_fused_t<S, 16, 16>(a, zc, st); break;
+        case 6: if (a.keepf) launch_fused_t<S, 32, 8>(a, zc, st); else launch_pipe_t<S, 32, 8>(a, zc, st); break;
+        case 7: if (a.keepf) launch_fused_t<S, 64, 4>(a, zc, st); else launch_pipe_t<S, 64, 4>(a, zc, st); break;
+        case 8: if (a.keepf) launch_fused_t<S, 16, 16>(a, zc, st); else launch_pipe_t<S, 16, 16>(a, zc, st); break;
+        case 9: if (a.keepf) launch_fused_t<S, 32, 16>(a, zc, st); else launch_pipe_t<S, 32, 16>(a, zc, st); break;
+        case 10: if (a.keepf) launch_fused_t<S, 64, 8>(a, zc, st); else launch_pipe_t<S, 64, 8>(a, zc, st); break;
+        default: launch_fluid<S>(a, st); break;
+    }
+}
+
+// ------------------------------------------------------------------------------------
+// Observables
+// ------------------------------------------------------------------------------------
+template <int S>
+__global__ void k_rho(const void *f, float *__restrict__ rho, int nx, int ny, int nz, int wall,
+                      float sh0, float sh1) {
+    const int N = nx * ny * nz;
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= N) return;
+    const int z = s / (nx * ny);
+    float r0 = 0.f, r1 = 0.f;
+    if (!(wall && z == 0)) {
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            r0 += Pop<S>::load(f, q, N, s, wq(q) * sh0);
+            r1 += Pop<S>::load(f, Q + q, N, s, wq(q) * sh1);
+        }
+    }
+    rho[s] = r0;
+    rho[N + s] = r1;
+}
+
+template <int S>
+void launch_rho(const void *f, float *rho, int nx, int ny, int nz, int wall, float s0, float s1,
+                hipStream_t st) {
+    const int N = nx * ny * nz;
+    hipLaunchKernelGGL(k_rho<S>, dim3((N + 255) / 256), dim3(256), 0, st, f, rho, nx, ny, nz, wall,
+                       s0, s1);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    return v;
+}
+
+// mass^c and fluid momentum, double accumulation; one partial row of 5 per block.
+template <int S>
+__global__ void __launch_bounds__(256) k_moments(const void *f, double *__restrict__ partial,
+                                                 int nx, int ny, int nz, int wall, float sh0,
+                                                 float sh1) {
+    const int N = nx * ny * nz;
+    double acc[5] = {0, 0, 0, 0, 0};
+    for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < N; s += gridDim.x * blockDim.x) {
+        const int z = s / (nx * ny);
+        if (wall && z == 0) continue;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const double v0 = Pop<S>::load(f, q, N, s, wq(q) * sh0);
+            const double v1 = Pop<S>::load(f, Q + q, N, s, wq(q) * sh1);
+            acc[0] += v0;
+            acc[1] += v1;
+            if (CX[q]) acc[2] += CX[q] * (v0 + v1);
+            if (CY[q]) acc[3] += CY[q] * (v0 + v1);
+            if (CZ[q]) acc[4] += CZ[q] * (v0 + v1);
+        }
+    }
+    __shared__ double red[4][5];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        const double v = wave_sum(acc[i]);
+        if (lane == 0) red[wid][i] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 5) {
+        double v = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) v += red[w][threadIdx.x];
+        partial[blockIdx.x * 5 + threadIdx.x] = v;
+    }
+}
+
+template <int S>
+void launch_moments(const void *f, double *partial, int nblocks, int nx, int ny, int nz, int wall,
+                    float s0, float s1, hipStream_t st) {
+    hipLaunchKernelGGL(k_moments<S>, dim3(nblocks), dim3(256), 0, st, f, partial, nx, ny, nz, wall,
+                       s0, s1);
+}
+
+// Meniscus height per column: the first upward crossing of
+// phi = (rho0 - rho1) / (rho0 + rho1) from >= 0 to < 0, linearly interpolated; NaN if
+// none or if either site of the crossing lies inside a capsule.
+__global__ void k_meniscus(const float *__restrict__ rho, const uint8_t *__restrict__ flag,
+                           float *__restrict__ out, int nx, int ny, int nz, int wall) {
+    const int col = blockIdx.x * blockDim.x + threadIdx.x;
+    if (col >= nx * ny) return;
+    const int N = nx * ny * nz, plane = nx * ny;
+    float res = __builtin_nanf("");
+    for (int k = wall ? 1 : 0; k + 1 < nz; ++k) {
+        const int s0 = k * plane + col, s1 = s0 + plane;
+        const double a0 = rho[s0], b0 = rho[N + s0], a1 = rho[s1], b1 = rho[N + s1];
+        const double p0 = (a0 - b0) / (a0 + b0), p1 = (a1 - b1) / (a1 + b1);
+        if (p0 >= 0.0 && p1 < 0.0) {
+            if ((flag[s0] & LABEL_MASK) == 0 && (flag[s1] & LABEL_MASK) == 0)
+                res = (float)(k + p0 / (p0 - p1));
+            break;
+        }
+    }
+    out[col] = res;
+}
+
+void launch_meniscus(const float *rho, const uint8_t *flag, float *out, int nx, int ny, int nz,
+                     int wall, hipStream_t st) {
+    hipLaunchKernelGGL(k_meniscus, dim3((nx * ny + 255) / 256), dim3(256), 0, st, rho, flag, out,
+                       nx, ny, nz, wall);
+}
+
+#define LBMX_INST(S)                                                                        \
+    template void launch_init_eq<S>(const double *, void *, int, int, int, int, float, float, \
+                                    hipStream_t);                                           \
+    template void launch_fluid<S>(const FluidArgs &, hipStream_t);                          \
+    template void launch_fluid_tiled<S>(const FluidArgs &, int, int, hipStream_t);          \
+    template void launch_rho<S>(const void *, float *, int, int, int, int, float, float,     \
+                                hipStream_t);                                               \
+    template void launch_moments<S>(const void *, double *, int, int, int, int, int, float,  \
+                                    float, hipStream_t);
+LBMX_INST(0)
+LBMX_INST(1)
+LBMX_INST(2)
+
+}  // namespace lbmx

@@ -1,0 +1,161 @@
+// lbm_internal.h -- device-side definitions shared by the HIP sources of liblbm.
+//
+// D3Q19 lattice (Section 3.1): rest weight 1/3, axis links 1/18, diagonal links 1/36,
+// c_s^2 = 1/3.  The population order here is a storage layout: grouped by the z
+// component of e_i (in-plane first, then +z and -z), opposite pairs adjacent.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbmx {
+
+constexpr int Q = 19;
+//                     0  1  2  3  4  5  6  7  8  9 10 11 12 13 14 15 16 17 18
+constexpr int CX[Q] = {0, 1, -1, 0, 0, 1, -1, 1, -1, 0, 0, 1, -1, 1, -1, 0, 0, 0, 0};
+constexpr int CY[Q] = {0, 0, 0, 1, -1, 1, -1, -1, 1, 0, 0, 0, 0, 0, 0, 1, -1, 1, -1};
+constexpr int CZ[Q] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 1, -1, 1, -1, -1, 1, 1, -1, -1, 1};
+constexpr int OPP[Q] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17};
+
+__host__ __device__ constexpr float wq(int q) {
+    return q == 0 ? 1.0f / 3.0f
+                  : ((CX[q] * CX[q] + CY[q] * CY[q] + CZ[q] * CZ[q]) == 1 ? 1.0f / 18.0f
+                                                                          : 1.0f / 36.0f);
+}
+__host__ __device__ constexpr bool is_axis(int q) {
+    return (CX[q] * CX[q] + CY[q] * CY[q] + CZ[q] * CZ[q]) == 1;
+}
+
+// Per-site flag byte: bits 0..6 side label (0 exterior, k+1 inside capsule k), bit 7
+// set where the site lies inside some capsule's immersed-boundary window, i.e. where
+// the spread force is read and the velocity / reaction are written.
+constexpr uint8_t LABEL_MASK = 0x7f;
+constexpr uint8_t AUX_BIT = 0x80;
+constexpr int LABEL_WALL = 127;   // label value used for wall neighbours inside kernels
+constexpr int MAX_CAPS = 125;
+constexpr int GMAX = 64;          // maximum edge of a capsule window (sites)
+constexpr int GMAX3 = GMAX * GMAX * GMAX;
+constexpr int ROWS_MAX = GMAX * GMAX;
+
+// status words (device): [0] unstable flag, [1] lost reaction count, [2] window overflow
+constexpr int ST_UNSTABLE = 0, ST_LOST = 1, ST_OVERFLOW = 2, ST_WORDS = 4;
+
+// ------------------------------------------------------------------------------------
+// Population storage codec.  S = 0: FP32 as is.  S = 1: FP16 of f - w_i rho_s.
+// S = 2: BF16 (round to nearest even) of f - w_i rho_s.  Arithmetic is FP32.
+// ------------------------------------------------------------------------------------
+template <int S> struct Codec;
+
+template <> struct Codec<0> {
+    using T = float;
+    __device__ static inline float dec(T v, float) { return v; }
+    __device__ static inline T enc(float f, float) { return f; }
+};
+
+template <> struct Codec<1> {
+    using T = _Float16;
+    __device__ static inline float dec(T v, float s) { return (float)v + s; }
+    __device__ static inline T enc(float f, float s) { return (_Float16)(f - s); }
+};
+
+template <> struct Codec<2> {
+    using T = uint16_t;
+    __device__ static inline float dec(T v, float s) {
+        return __uint_as_float((uint32_t)v << 16) + s;
+    }
+    __device__ static inline T enc(float f, float s) {
+        uint32_t u = __float_as_uint(f - s);
+        if ((u & 0x7fffffffu) > 0x7f800000u) return (T)((u >> 16) | 0x40u);  // quiet NaN
+        u += 0x7fffu + ((u >> 16) & 1u);
+        return (T)(u >> 16);
+    }
+};
+
+// ------------------------------------------------------------------------------------
+// Kernel arguments
+// ------------------------------------------------------------------------------------
+struct FluidArgs {
+    const void *fin;        // populations of the last step, [2][19][N] of Codec<S>::T
+    void *fout;             // populations written by this step
+    const uint8_t *flag;    // [N] label | AUX_BIT
+    const float4 *ibm;      // [N] spread force (x, y, z) and kernel coverage (w), aux sites
+    float4 *uo;             // [N] physical velocity, aux sites
+    float4 *ro;             // [N] cross-membrane reaction, aux sites
+    float *psi;             // [2][N] pseudopotential (two-pass kernel)
+    int *status;            // status words
+    const float *cap_drho;  // [MAX_CAPS] wetting offset per capsule
+    int nx, ny, nz, wall;
+    int N;                  // nx * ny * nz
+    float tau[2], inv_tau[2];
+    float G;                // coupling
+    float ws_axis, ws_diag; // stencil weights sc_norm * omega_i
+    float inv_rho0;
+    float g[3];             // body acceleration
+    float wall_drho;
+    float shift[2];         // storage shift rho_s per component (16-bit modes)
+    int keepf;              // 0: tau = 1 for both components, so f* = f^eq (moments suffice)
+};
+
+// Device description of one capsule.
+struct CapDev {
+    int node0, nn;          // first node, node count
+    int tri0, nt;           // first triangle, triangle count
+    float ks, C, kv, anchor_k;
+    double v0;              // reference volume
+    double c0[3];           // reference centroid
+};
+
+// Per-step capsule state written by the reduction kernel.
+struct CapState {
+    double cen[3];          // node mean at X^n
+    double vol;             // enclosed volume at X^n
+    float bmin[3], bmax[3]; // node bounding box (FP32 positions)
+    int lo[3], dim[3];      // window: sites lo .. lo + dim - 1 (unwrapped)
+    int plo[3], pdim[3];    // window of the previous step (to clear)
+};
+
+struct MembraneArgs {
+    const CapDev *caps;
+    CapState *cst;
+    int ncap;
+    double4 *X;             // [Ntot] node positions (unwrapped, FP64 state), w unused
+    const int *node_cap;    // [Ntot] capsule index of each node
+    float4 *F;              // [Ntot] total node force
+    float4 *Fh;             // [Ntot] Hertz part
+    float4 *R;              // [Ntot] pending reaction
+    const int4 *tri;        // [Ttot] global node indices a, b, c and capsule index
+    const float4 *minv;     // [Ttot] reference inverse (row-major 2x2)
+    const float *a0;        // [Ttot] reference area
+    const int *ntri_off;    // [Ntot+1] node -> incident triangle CSR offsets
+    const int *ntri;        // incident entries: 3 * triangle + corner
+    int *marks;             // [ncap][GMAX3] crossing parity marks
+    int *rowstart;          // [ncap][ROWS_MAX + 1] node rows of each window
+    int *rowids;            // [Ntot] node ids sorted by row then id (global ids)
+    uint8_t *flag;
+    float4 *ibm;
+    const float4 *uo, *ro;
+    int *status;
+    int nx, ny, nz, wall;
+    float hertz_xi, hertz_d0, plane_z;
+};
+
+// Launchers (host functions, defined in the .hip files).
+template <int S> void launch_init_eq(const double *rho_dev, void *f, int nx, int ny, int nz,
+                                     int wall, float s0, float s1, hipStream_t st);
+template <int S> void launch_fluid(const FluidArgs &a, hipStream_t st);
+template <int S> void launch_fluid_tiled(const FluidArgs &a, int tile, int zc, hipStream_t st);
+template <int S> void launch_rho(const void *f, float *rho, int nx, int ny, int nz, int wall,
+                                 float s0, float s1, hipStream_t st);
+template <int S> void launch_moments(const void *f, double *partial, int nblocks, int nx, int ny,
+                                     int nz, int wall, float s0, float s1, hipStream_t st);
+void launch_meniscus(const float *rho, const uint8_t *flag, float *out, int nx, int ny, int nz,
+                     int wall, hipStream_t st);
+
+void launch_capsule_reduce(const MembraneArgs &m, hipStream_t st);
+void launch_window_clear(const MembraneArgs &m, hipStream_t st);
+void launch_membrane_forces(const MembraneArgs &m, int ntot, hipStream_t st);
+void launch_label_marks(const MembraneArgs &m, int ttot, hipStream_t st);
+void launch_node_bin(const MembraneArgs &m, hipStream_t st);
+void launch_window_fill(const MembraneArgs &m, hipStream_t st);
+void launch_node_update(const MembraneArgs &m, int ntot, hipStream_t st);
+
+}  // namespace lbmx

@@ -1,0 +1,309 @@
+"""ctypes binding of ``liblbm.so`` (the C ABI declared in ``include/lbm.h``).
+
+Argument marshalling only: every step of the simulation runs in the library's HIP
+kernels.  PyTorch is used, when present, for the stream the library enqueues on and for
+device buffers (``Sim.rho_device``).  The library must have been built
+(``python -m paper_2007_15405_amd.build``); there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblbm.so")
+
+STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
+
+LBM_OK, LBM_E_INVAL, LBM_E_NOMEM, LBM_E_DEVICE, LBM_E_UNSTABLE, LBM_E_STATE = 0, -1, -2, -3, -4, -5
+
+
+class LbmError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"lbm status {status}: {msg}")
+        self.status = status
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("wall_z0", C.c_int32),
+        ("tau", C.c_double * 2), ("G", C.c_double), ("rho0", C.c_double),
+        ("sc_norm", C.c_double), ("body_force", C.c_double * 3), ("wall_drho", C.c_double),
+        ("init_mode", C.c_int32), ("storage", C.c_int32), ("init_rho", C.c_double * 2),
+        ("film_height", C.c_double), ("rho_maj", C.c_double), ("rho_min", C.c_double),
+        ("rho_iface", C.c_double), ("init_rho_array", C.POINTER(C.c_double)),
+        ("hertz_xi", C.c_double), ("hertz_delta0", C.c_double), ("plane_dz", C.c_double),
+        ("rho_shift", C.c_double * 2), ("stream", C.c_void_p), ("device", C.c_int32),
+        ("stream_given", C.c_int32),
+    ]
+
+
+class CapsuleParams(C.Structure):
+    _fields_ = [("ks", C.c_double), ("C", C.c_double), ("kb", C.c_double), ("kv", C.c_double),
+                ("wet_drho", C.c_double), ("anchor_k", C.c_double)]
+
+
+class CapsuleObs(C.Structure):
+    _fields_ = [("centroid", C.c_double * 3), ("volume", C.c_double),
+                ("f_anchor", C.c_double * 3), ("f_capillary", C.c_double * 3),
+                ("f_hertz", C.c_double * 3)]
+
+
+class Summary(C.Structure):
+    _fields_ = [("mass", C.c_double * 2), ("momentum", C.c_double * 3),
+                ("pending", C.c_double * 3), ("step", C.c_int64),
+                ("lost_reaction", C.c_int64), ("n_capsules", C.c_int32),
+                ("unstable", C.c_int32)]
+
+
+class Obs(C.Structure):
+    _fields_ = [("rho", C.POINTER(C.c_float)), ("meniscus", C.POINTER(C.c_float)),
+                ("capsules", C.POINTER(CapsuleObs)), ("summary", Summary)]
+
+
+class KernelStat(C.Structure):
+    _fields_ = [("name", C.c_char * 32), ("launches", C.c_int64), ("total_ms", C.c_double)]
+
+
+# entry point -> (restype, argtypes); every function declared in include/lbm.h
+H = C.c_void_p
+SIGNATURES = {
+    "lbm_init": (C.c_int, [C.POINTER(Params), C.POINTER(C.c_void_p)]),
+    "lbm_add_capsule": (C.c_int, [H, C.POINTER(CapsuleParams), C.c_int32, C.POINTER(C.c_double),
+                                  C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "lbm_step": (C.c_int, [H, C.c_int64]),
+    "lbm_sync": (C.c_int, [H]),
+    "lbm_observables": (C.c_int, [H, C.POINTER(Obs)]),
+    "lbm_rho_device": (C.c_int, [H, C.c_void_p]),
+    "lbm_capsule_nodes": (C.c_int, [H, C.c_int32, C.POINTER(C.c_double)]),
+    "lbm_labels": (C.c_int, [H, C.POINTER(C.c_uint8)]),
+    "lbm_save": (C.c_int, [H, C.c_char_p]),
+    "lbm_load": (C.c_int, [H, C.c_char_p]),
+    "lbm_set_profiling": (C.c_int, [H, C.c_int32]),
+    "lbm_kernel_stats": (C.c_int, [H, C.POINTER(KernelStat), C.c_int32, C.POINTER(C.c_int32)]),
+    "lbm_set_launch": (C.c_int, [H, C.c_int32, C.c_int32]),
+    "lbm_bytes_per_site": (C.c_double, [H]),
+    "lbm_fluid_sites": (C.c_int64, [H]),
+    "lbm_last_error": (C.c_char_p, [H]),
+    "lbm_destroy": (None, [H]),
+}
+
+_LIB = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load liblbm.so; raises if it has not been built.
+
+    PyTorch-ROCm ships its own HIP runtime; importing torch first makes liblbm bind to
+    that already-loaded runtime, so one process never holds two HSA runtimes."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    try:
+        import torch  # noqa: F401
+    except Exception:
+        pass
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with "
+                           f"'python -m paper_2007_15405_amd.build' (no fallback exists)")
+    L = C.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _LIB = L
+    return L
+
+
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _torch_stream():
+    """Handle of torch's current stream (0 for the null stream), or None."""
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return int(torch.cuda.current_stream().cuda_stream)
+    except Exception:
+        pass
+    return None
+
+
+class Sim:
+    """One simulation on the GPU, configured by a dict as made by ``synth.workload``.
+
+    ``storage`` is ``"f32"``, ``"f16"`` or ``"bf16"`` (16-bit modes store f - w rho_shift).
+    ``stream``: ``"torch"`` (default: torch's current stream if a GPU is visible), ``None``
+    (a stream of the library's own) or a raw hipStream_t integer."""
+
+    def __init__(self, cfg: dict, storage: str = "f32", rho_shift=(1.0, 1.0),
+                 stream="torch", device: int = 0, meshes: Optional[list] = None):
+        import synth
+        self.L = load_library()
+        self.cfg = cfg
+        self.nx, self.ny, self.nz = cfg["nx"], cfg["ny"], cfg["nz"]
+        p = Params()
+        p.nx, p.ny, p.nz, p.wall_z0 = self.nx, self.ny, self.nz, int(cfg["wall_z0"])
+        p.tau[0], p.tau[1] = cfg["tau"]
+        p.G, p.rho0, p.sc_norm = cfg["G"], cfg["rho0"], cfg["sc_norm"]
+        for d in range(3):
+            p.body_force[d] = cfg["body_force"][d]
+        p.wall_drho = cfg["wall_drho"]
+        p.init_mode = int(cfg["init_mode"])
+        p.storage = STORAGE[storage]
+        p.init_rho[0], p.init_rho[1] = cfg["init_rho"]
+        p.film_height, p.rho_maj = cfg["film_height"], cfg["rho_maj"]
+        p.rho_min, p.rho_iface = cfg["rho_min"], cfg["rho_iface"]
+        keep = None
+        if cfg.get("init_rho_array") is not None:
+            keep = np.ascontiguousarray(cfg["init_rho_array"], dtype=np.float64)
+            if keep.shape != (2, self.nz, self.ny, self.nx):
+                raise ValueError("init_rho_array must be [2][nz][ny][nx]")
+            p.init_rho_array = _dp(keep)
+        p.hertz_xi, p.hertz_delta0 = cfg["hertz_xi"], cfg["hertz_delta0"]
+        p.plane_dz = cfg["plane_dz"]
+        p.rho_shift[0], p.rho_shift[1] = rho_shift
+        if stream == "torch":
+            s = _torch_stream()
+            if s is not None:
+                p.stream, p.stream_given = (s or None), 1
+        elif stream is not None:
+            p.stream, p.stream_given = (int(stream) or None), 1
+        p.device = device
+        h = C.c_void_p()
+        st = self.L.lbm_init(C.byref(p), C.byref(h))
+        if st != LBM_OK:
+            raise LbmError(st, self.L.lbm_last_error(None).decode())
+        self.h = h
+        self.storage = storage
+        self.n_nodes = []
+        for i, cp in enumerate(cfg["capsules"]):
+            nodes, tris = meshes[i] if meshes is not None else synth.capsule_mesh(cp)
+            self.add_capsule(cp, nodes, tris)
+
+    # -- plumbing --------------------------------------------------------------------------
+    def _check(self, st: int):
+        if st != LBM_OK:
+            raise LbmError(st, self.L.lbm_last_error(self.h).decode())
+
+    def add_capsule(self, cp: dict, nodes, tris) -> int:
+        q = CapsuleParams(cp["ks"], cp["C"], cp["kb"], cp["kv"], cp["wet_drho"], cp["anchor_k"])
+        x = np.ascontiguousarray(nodes, dtype=np.float64)
+        t = np.ascontiguousarray(tris, dtype=np.int32)
+        out = C.c_int32()
+        self._check(self.L.lbm_add_capsule(self.h, C.byref(q), len(x), _dp(x), len(t),
+                                           t.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(out)))
+        self.n_nodes.append(len(x))
+        return out.value
+
+    def step(self, n: int = 1):
+        self._check(self.L.lbm_step(self.h, int(n)))
+
+    def sync(self):
+        self._check(self.L.lbm_sync(self.h))
+
+    # -- observables -------------------------------------------------------------------------
+    def observables(self, rho: bool = False, meniscus: bool = False, capsules: bool = True,
+                    check: bool = True) -> dict:
+        o = Obs()
+        r = m = caps = None
+        if rho:
+            r = np.zeros((2, self.nz, self.ny, self.nx), np.float32)
+            o.rho = r.ctypes.data_as(C.POINTER(C.c_float))
+        if meniscus:
+            m = np.zeros((self.ny, self.nx), np.float32)
+            o.meniscus = m.ctypes.data_as(C.POINTER(C.c_float))
+        nc = len(self.n_nodes)
+        if capsules and nc:
+            caps = (CapsuleObs * nc)()
+            o.capsules = caps
+        st = self.L.lbm_observables(self.h, C.byref(o))
+        if check:
+            self._check(st)
+        s = o.summary
+        out = dict(status=st, summary=dict(
+            mass=np.array(s.mass), momentum=np.array(s.momentum), pending=np.array(s.pending),
+            step=s.step, lost_reaction=s.lost_reaction, n_capsules=s.n_capsules,
+            unstable=s.unstable))
+        if rho:
+            out["rho"] = r
+        if meniscus:
+            out["meniscus"] = m
+        if caps is not None:
+            out["capsules"] = [dict(centroid=np.array(c.centroid), volume=c.volume,
+                                    f_anchor=np.array(c.f_anchor),
+                                    f_capillary=np.array(c.f_capillary),
+                                    f_hertz=np.array(c.f_hertz)) for c in caps]
+        return out
+
+    def rho(self) -> np.ndarray:
+        return self.observables(rho=True, capsules=False)["rho"]
+
+    def meniscus(self) -> np.ndarray:
+        return self.observables(meniscus=True, capsules=False)["meniscus"]
+
+    def summary(self) -> dict:
+        return self.observables(capsules=False)["summary"]
+
+    def capsule(self, k: int) -> dict:
+        return self.observables()["capsules"][k]
+
+    def rho_device(self):
+        """Densities into a new torch CUDA tensor [2][nz][ny][nx] (library stream)."""
+        import torch
+        out = torch.empty((2, self.nz, self.ny, self.nx), dtype=torch.float32, device="cuda")
+        self._check(self.L.lbm_rho_device(self.h, C.c_void_p(out.data_ptr())))
+        return out
+
+    def nodes(self, k: int) -> np.ndarray:
+        out = np.zeros((self.n_nodes[k], 3))
+        self._check(self.L.lbm_capsule_nodes(self.h, k, _dp(out)))
+        return out
+
+    def labels(self) -> np.ndarray:
+        out = np.zeros((self.nz, self.ny, self.nx), np.uint8)
+        self._check(self.L.lbm_labels(self.h, out.ctypes.data_as(C.POINTER(C.c_uint8))))
+        return out
+
+    # -- checkpoints, profiling ------------------------------------------------------------
+    def save(self, path: str):
+        self._check(self.L.lbm_save(self.h, path.encode()))
+
+    def load(self, path: str):
+        self._check(self.L.lbm_load(self.h, path.encode()))
+
+    def set_profiling(self, on: bool = True):
+        self._check(self.L.lbm_set_profiling(self.h, int(on)))
+
+    def kernel_stats(self) -> dict:
+        arr = (KernelStat * 32)()
+        n = C.c_int32()
+        self._check(self.L.lbm_kernel_stats(self.h, arr, 32, C.byref(n)))
+        return {arr[i].name.decode(): (arr[i].launches, arr[i].total_ms) for i in range(n.value)}
+
+    def set_launch(self, tile: int = 1, zchunk: int = 0):
+        """Fluid-step launch shape (tile 0: two-kernel variant; 1..5: fused kernel)."""
+        self._check(self.L.lbm_set_launch(self.h, int(tile), int(zchunk)))
+
+    @property
+    def bytes_per_site(self) -> float:
+        return self.L.lbm_bytes_per_site(self.h)
+
+    @property
+    def fluid_sites(self) -> int:
+        return self.L.lbm_fluid_sites(self.h)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.lbm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
