@@ -20,6 +20,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+
+# HBM bytes per launch of the fused fluid kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE,
+# scaled by the same counters on a plain 1 GiB copy (profiles/fluid_c3_f32_hbm_traffic.md),
+# keyed by (storage, tile, zchunk).  Reported only for the launch shape it was taken on.
+MEASURED_TRAFFIC_BYTES = {("f32", 10, 48): 2.1185e9}
 WORKLOAD = "film 256x256x96, wall, 16 capsules R=10 (5120 tri), ks=0.05"
 
 
@@ -120,6 +125,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--tile", type=int, default=None, help="fixed launch shape (skips tuning)")
+    ap.add_argument("--copy-calib", type=int, default=0, metavar="MB",
+                    help="only run a plain device copy of MB megabytes (counter calibration)")
     ap.add_argument("--zchunk", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -127,6 +134,19 @@ def main():
               f"the multi-GPU halo exchange is a design, not part of this build",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.copy_calib:
+        # plain copy kernel of known size: rocprofv3's FETCH_SIZE / WRITE_SIZE of this run
+        # give the counter scale (bytes counted per byte moved) used for the traffic figure
+        import torch
+        n = args.copy_calib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps(dict(copy_bytes_each_way=n * 4, launches=5)), flush=True)
+        return
 
     import synth
     cfg = synth.workload("c3")
@@ -155,7 +175,12 @@ def main():
         config=dict(workload=WORKLOAD, nx=256, ny=256, nz=96, capsules=16,
                     storage=head_st, fluid_sites=head["fluid_sites"]),
         roofline=dict(bound="hbm", achieved=round(head["achieved_gbs"], 1), peak=PEAK_HBM_GBS,
-                      unit="GB/s", frac=round(head["frac"], 4), traffic=None,
+                      unit="GB/s", frac=round(head["frac"], 4),
+                      traffic=MEASURED_TRAFFIC_BYTES.get(
+                          (head_st, head["launch"]["tile_id"], head["launch"]["zchunk"])
+                          if head.get("launch") else None),
+                      traffic_unit="bytes per launch",
+                      algorithmic_bytes=head["bytes_per_site"] * head["fluid_sites"],
                       bytes_per_site=head["bytes_per_site"], kernel="fluid",
                       kernel_ms=round(head["fluid_ms"], 5), launch=head["launch"]),
         kernels_ms=head["kernels"],

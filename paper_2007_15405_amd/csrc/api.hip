@@ -61,6 +61,8 @@ struct lbm_handle {
     float *d_a0 = nullptr;
     int *d_off = nullptr, *d_list = nullptr, *d_marks = nullptr, *d_rowstart = nullptr,
         *d_rowids = nullptr;
+    float4 *d_wbuf = nullptr;
+    uint8_t *d_wpar = nullptr;
     std::vector<CapDev> h_caps;
     int tile = 1, zchunk = 0;
     bool profiling = false;
@@ -90,7 +92,8 @@ static void free_all(lbm_handle *h) {
     void *ptrs[] = {h->f[0], h->f[1], h->flag, h->ibm, h->uo, h->ro, h->psi, h->cap_drho,
                     h->rho_tmp, h->men_tmp, h->status, h->partial, h->d_caps, h->d_cst, h->d_X,
                     h->d_node_cap, h->d_F, h->d_Fh, h->d_R, h->d_tri, h->d_minv, h->d_a0,
-                    h->d_off, h->d_list, h->d_marks, h->d_rowstart, h->d_rowids};
+                    h->d_off, h->d_list, h->d_marks, h->d_rowstart, h->d_rowids, h->d_wbuf,
+                    h->d_wpar};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (hipEvent_t e : h->event_pool) (void)hipEventDestroy(e);
@@ -404,7 +407,9 @@ static lbm_status finalize(lbm_handle *h) {
         dalloc(&h->d_off, nt + 1) != hipSuccess || dalloc(&h->d_list, list.size()) != hipSuccess ||
         dalloc(&h->d_marks, (size_t)ncap * GMAX3) != hipSuccess ||
         dalloc(&h->d_rowstart, (size_t)ncap * (ROWS_MAX + 1)) != hipSuccess ||
-        dalloc(&h->d_rowids, nt) != hipSuccess)
+        dalloc(&h->d_rowids, nt) != hipSuccess ||
+        dalloc(&h->d_wbuf, (size_t)ncap * GMAX3) != hipSuccess ||
+        dalloc(&h->d_wpar, (size_t)ncap * GMAX3) != hipSuccess)
         return fail(h, LBM_E_NOMEM, "device allocation failed (capsules)");
     HIPCHK(h, hipMemcpyAsync(h->d_caps, h->h_caps.data(), ncap * sizeof(CapDev), hipMemcpyHostToDevice, h->st));
     HIPCHK(h, hipMemsetAsync(h->d_cst, 0, ncap * sizeof(CapState), h->st));
@@ -436,6 +441,7 @@ static MembraneArgs membrane_args(lbm_handle *h) {
     m.tri = h->d_tri; m.minv = h->d_minv; m.a0 = h->d_a0;
     m.ntri_off = h->d_off; m.ntri = h->d_list;
     m.marks = h->d_marks; m.rowstart = h->d_rowstart; m.rowids = h->d_rowids;
+    m.wbuf = h->d_wbuf; m.wpar = h->d_wpar;
     m.flag = h->flag; m.ibm = h->ibm; m.uo = h->uo; m.ro = h->ro; m.status = h->status;
     m.nx = h->nx; m.ny = h->ny; m.nz = h->nz; m.wall = h->wall;
     m.hertz_xi = (float)h->p.hertz_xi;
@@ -500,9 +506,8 @@ extern "C" lbm_status lbm_step(lbm_handle *h, int64_t n) {
     const MembraneArgs m = caps ? membrane_args(h) : MembraneArgs{};
     for (int64_t i = 0; i < n; ++i) {
         if (caps) {
-            timed(h, "capsule_reduce", [&] { launch_capsule_reduce(m, h->st); });
+            timed(h, "capsule_prep", [&] { launch_capsule_prep(m, h->st); });
             timed(h, "window_clear", [&] { launch_window_clear(m, h->st); });
-            timed(h, "node_bin", [&] { launch_node_bin(m, h->st); });
             timed(h, "membrane_forces", [&] { launch_membrane_forces(m, h->ntot, h->st); });
             timed(h, "label_marks", [&] { launch_label_marks(m, h->ttot, h->st); });
             timed(h, "window_fill", [&] { launch_window_fill(m, h->st); });
@@ -530,13 +535,19 @@ static lbm_status check_status(lbm_handle *h, int st[ST_WORDS]) {
     return LBM_OK;
 }
 
+static const char *unstable_message(const int *st) {
+    if (st[ST_WIDE]) return "capsule window wider than 2048 lattice columns (x * y)";
+    if (st[ST_OVERFLOW]) return "capsule outgrew its window";
+    return "non-finite or negative density";
+}
+
 extern "C" lbm_status lbm_sync(lbm_handle *h) {
     if (!h) return LBM_E_INVAL;
     int st[ST_WORDS];
     lbm_status s = check_status(h, st);
     if (s != LBM_OK) return s;
-    if (st[ST_UNSTABLE] || st[ST_OVERFLOW])
-        return fail(h, LBM_E_UNSTABLE, st[ST_OVERFLOW] ? "capsule outgrew its window" : "non-finite or negative density");
+    if (st[ST_UNSTABLE] || st[ST_OVERFLOW] || st[ST_WIDE])
+        return fail(h, LBM_E_UNSTABLE, unstable_message(st));
     return LBM_OK;
 }
 
@@ -587,7 +598,7 @@ extern "C" lbm_status lbm_observables(lbm_handle *h, lbm_obs *out) {
     sm.step = h->step;
     sm.lost_reaction = st[ST_LOST];
     sm.n_capsules = (int)h->caps.size();
-    sm.unstable = (st[ST_UNSTABLE] || st[ST_OVERFLOW]) ? 1 : 0;
+    sm.unstable = (st[ST_UNSTABLE] || st[ST_OVERFLOW] || st[ST_WIDE]) ? 1 : 0;
     if (h->finalized && !h->caps.empty()) {
         std::vector<double4> X(h->ntot);
         std::vector<float4> Fh(h->ntot), R(h->ntot);
@@ -636,8 +647,7 @@ extern "C" lbm_status lbm_observables(lbm_handle *h, lbm_obs *out) {
     } else if (out->capsules) {
         for (size_t k = 0; k < h->caps.size(); ++k) std::memset(&out->capsules[k], 0, sizeof(lbm_capsule_obs));
     }
-    if (sm.unstable)
-        return fail(h, LBM_E_UNSTABLE, st[ST_OVERFLOW] ? "capsule outgrew its window" : "non-finite or negative density");
+    if (sm.unstable) return fail(h, LBM_E_UNSTABLE, unstable_message(st));
     return LBM_OK;
 }
 

@@ -221,10 +221,13 @@ __device__ __forceinline__ void collide_store(const FluidArgs &a, const float (&
         }
     }
     if (aux) {
+        // window sites: physical velocity with the kernel coverage c(x) in .w, and the
+        // reaction already divided by c(x) (0 where c = 0)
         a.uo[s] = make_float4((jx[0] + jx[1] + 0.5f * (F0[0] + F1[0])) * irt,
                               (jy[0] + jy[1] + 0.5f * (F0[1] + F1[1])) * irt,
-                              (jz[0] + jz[1] + 0.5f * (F0[2] + F1[2])) * irt, 0.f);
-        a.ro[s] = make_float4(rx[0], rx[1], rx[2], 0.f);
+                              (jz[0] + jz[1] + 0.5f * (F0[2] + F1[2])) * irt, fb[3]);
+        const float ic = fb[3] > 0.f ? 1.0f / fb[3] : 0.f;
+        a.ro[s] = make_float4(rx[0] * ic, rx[1] * ic, rx[2] * ic, 0.f);
     }
     if ((rx[0] != 0.f || rx[1] != 0.f || rx[2] != 0.f) && !(aux && fb[3] > 0.f))
         atomicAdd(&a.status[ST_LOST], 1);
@@ -557,10 +560,13 @@ __device__ __forceinline__ void collide_store_eq(const FluidArgs &a, const float
         Pop<S>::store(a.fout, c * Q, a.N, s, rho[c] - sum, wq(0) * sh);
     }
     if (aux) {
+        // window sites: physical velocity with the kernel coverage c(x) in .w, and the
+        // reaction already divided by c(x) (0 where c = 0)
         a.uo[s] = make_float4((jx[0] + jx[1] + 0.5f * (F0[0] + F1[0])) * irt,
                               (jy[0] + jy[1] + 0.5f * (F0[1] + F1[1])) * irt,
-                              (jz[0] + jz[1] + 0.5f * (F0[2] + F1[2])) * irt, 0.f);
-        a.ro[s] = make_float4(rx[0], rx[1], rx[2], 0.f);
+                              (jz[0] + jz[1] + 0.5f * (F0[2] + F1[2])) * irt, fb[3]);
+        const float ic = fb[3] > 0.f ? 1.0f / fb[3] : 0.f;
+        a.ro[s] = make_float4(rx[0] * ic, rx[1] * ic, rx[2] * ic, 0.f);
     }
     if ((rx[0] != 0.f || rx[1] != 0.f || rx[2] != 0.f) && !(aux && fb[3] > 0.f))
         atomicAdd(&a.status[ST_LOST], 1);

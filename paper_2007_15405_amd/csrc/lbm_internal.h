@@ -36,8 +36,9 @@ constexpr int GMAX = 64;          // maximum edge of a capsule window (sites)
 constexpr int GMAX3 = GMAX * GMAX * GMAX;
 constexpr int ROWS_MAX = GMAX * GMAX;
 
-// status words (device): [0] unstable flag, [1] lost reaction count, [2] window overflow
-constexpr int ST_UNSTABLE = 0, ST_LOST = 1, ST_OVERFLOW = 2, ST_WORDS = 4;
+// status words (device): [0] unstable flag, [1] lost reaction count, [2] window overflow,
+// [3] window wider than the spreading plane buffer
+constexpr int ST_UNSTABLE = 0, ST_LOST = 1, ST_OVERFLOW = 2, ST_WIDE = 3, ST_WORDS = 4;
 
 // ------------------------------------------------------------------------------------
 // Population storage codec.  S = 0: FP32 as is.  S = 1: FP16 of f - w_i rho_s.
@@ -130,6 +131,8 @@ struct MembraneArgs {
     int *marks;             // [ncap][GMAX3] crossing parity marks
     int *rowstart;          // [ncap][ROWS_MAX + 1] node rows of each window
     int *rowids;            // [Ntot] node ids sorted by row then id (global ids)
+    float4 *wbuf;           // [ncap][GMAX3] own spread force and coverage per window site
+    uint8_t *wpar;          // [ncap][GMAX3] own crossing parity per window site
     uint8_t *flag;
     float4 *ibm;
     const float4 *uo, *ro;
@@ -150,11 +153,10 @@ template <int S> void launch_moments(const void *f, double *partial, int nblocks
 void launch_meniscus(const float *rho, const uint8_t *flag, float *out, int nx, int ny, int nz,
                      int wall, hipStream_t st);
 
-void launch_capsule_reduce(const MembraneArgs &m, hipStream_t st);
+void launch_capsule_prep(const MembraneArgs &m, hipStream_t st);
 void launch_window_clear(const MembraneArgs &m, hipStream_t st);
 void launch_membrane_forces(const MembraneArgs &m, int ntot, hipStream_t st);
 void launch_label_marks(const MembraneArgs &m, int ttot, hipStream_t st);
-void launch_node_bin(const MembraneArgs &m, hipStream_t st);
 void launch_window_fill(const MembraneArgs &m, hipStream_t st);
 void launch_node_update(const MembraneArgs &m, int ntot, hipStream_t st);
 

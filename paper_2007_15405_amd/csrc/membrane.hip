@@ -8,8 +8,6 @@
 
 namespace lbmx {
 
-constexpr int RBLK = 256;   // threads of the per-capsule reduction
-constexpr int BIN_BLK = 1024;
 
 // Peskin's 4-point kernel in one dimension.
 __device__ __forceinline__ float phi4(float r) {
@@ -45,23 +43,30 @@ __device__ __forceinline__ float wave_max(float v) {
 }
 
 // ------------------------------------------------------------------------------------
-// Per capsule: node mean, enclosed volume (FP64), bounding box and the site window.
-// One block per capsule; fixed reduction order.
+// Per capsule (one block of PREP_BLK threads): node mean, enclosed volume (FP64),
+// bounding box and the site window; then the node rows of the window: nodes grouped by
+// the (y, z) lattice row of floor(X), ordered by node id inside a row.  Fixed reduction
+// order throughout.
 // ------------------------------------------------------------------------------------
-__global__ void __launch_bounds__(RBLK) k_capsule_reduce(MembraneArgs m) {
+constexpr int PREP_BLK = 1024, PREP_W = PREP_BLK / 64;
+
+__global__ void __launch_bounds__(PREP_BLK) k_capsule_prep(MembraneArgs m) {
     const int k = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const CapDev cd = m.caps[k];
-    __shared__ double sd[RBLK / 64][4];
-    __shared__ float smin[RBLK / 64][3], smax[RBLK / 64][3];
+    __shared__ double sd[PREP_W][4];
+    __shared__ float smin[PREP_W][3], smax[PREP_W][3];
     __shared__ double cen[3];
-    double s[3] = {0, 0, 0};
+    __shared__ int s_lo[3], s_dim[3];
+    __shared__ int cnt[ROWS_MAX];
+    __shared__ int wsum[PREP_W];
+    double sacc[3] = {0, 0, 0};
     float mn[3] = {3e38f, 3e38f, 3e38f}, mx[3] = {-3e38f, -3e38f, -3e38f};
-    for (int n = tid; n < cd.nn; n += RBLK) {
+    for (int n = tid; n < cd.nn; n += PREP_BLK) {
         const double4 X = m.X[cd.node0 + n];
         const double p[3] = {X.x, X.y, X.z};
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-            s[d] += p[d];
+            sacc[d] += p[d];
             const float pf = (float)p[d];
             mn[d] = fminf(mn[d], pf);
             mx[d] = fmaxf(mx[d], pf);
@@ -69,19 +74,19 @@ __global__ void __launch_bounds__(RBLK) k_capsule_reduce(MembraneArgs m) {
     }
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        const double v = wave_sum(s[d]);
+        const double v = wave_sum(sacc[d]);
         const float a = wave_min(mn[d]), b = wave_max(mx[d]);
         if (lane == 0) { sd[wid][d] = v; smin[wid][d] = a; smax[wid][d] = b; }
     }
     __syncthreads();
     if (tid < 3) {
         double v = 0;
-        for (int w = 0; w < RBLK / 64; ++w) v += sd[w][tid];
+        for (int w = 0; w < PREP_W; ++w) v += sd[w][tid];
         cen[tid] = v / cd.nn;
     }
     __syncthreads();
     double vol = 0;
-    for (int t = tid; t < cd.nt; t += RBLK) {
+    for (int t = tid; t < cd.nt; t += PREP_BLK) {
         const int4 tr = m.tri[cd.tri0 + t];
         const double4 A = m.X[tr.x], B = m.X[tr.y], C = m.X[tr.z];
         const double a[3] = {A.x - cen[0], A.y - cen[1], A.z - cen[2]};
@@ -91,18 +96,17 @@ __global__ void __launch_bounds__(RBLK) k_capsule_reduce(MembraneArgs m) {
                 a[2] * (b[0] * c[1] - b[1] * c[0])) / 6.0;
     }
     vol = wave_sum(vol);
-    __syncthreads();
     if (lane == 0) sd[wid][3] = vol;
     __syncthreads();
     if (tid == 0) {
         CapState &cs = m.cst[k];
         double v = 0;
-        for (int w = 0; w < RBLK / 64; ++w) v += sd[w][3];
+        for (int w = 0; w < PREP_W; ++w) v += sd[w][3];
         cs.vol = v;
         const int nd[3] = {m.nx, m.ny, m.nz};
         for (int d = 0; d < 3; ++d) {
             float a = smin[0][d], b = smax[0][d];
-            for (int w = 1; w < RBLK / 64; ++w) { a = fminf(a, smin[w][d]); b = fmaxf(b, smax[w][d]); }
+            for (int w = 1; w < PREP_W; ++w) { a = fminf(a, smin[w][d]); b = fmaxf(b, smax[w][d]); }
             cs.cen[d] = cen[d];
             cs.bmin[d] = a;
             cs.bmax[d] = b;
@@ -121,12 +125,71 @@ __global__ void __launch_bounds__(RBLK) k_capsule_reduce(MembraneArgs m) {
             }
             cs.lo[d] = fa - 1;
             cs.dim[d] = dim;
+            s_lo[d] = fa - 1;
+            s_dim[d] = dim;
+        }
+    }
+    __syncthreads();
+    // ---- node rows ----
+    const int lo1 = s_lo[1], lo2 = s_lo[2], dim1 = s_dim[1], dim2 = s_dim[2];
+    const int rows = dim1 * dim2;
+    for (int r = tid; r < rows; r += PREP_BLK) cnt[r] = 0;
+    __syncthreads();
+    for (int n = tid; n < cd.nn; n += PREP_BLK) {
+        const double4 X = m.X[cd.node0 + n];
+        const int ry = min(max((int)floor(X.y) - lo1, 0), dim1 - 1);
+        const int rz = min(max((int)floor(X.z) - lo2, 0), dim2 - 1);
+        atomicAdd(&cnt[rz * dim1 + ry], 1);
+    }
+    __syncthreads();
+    // exclusive scan: each thread owns a contiguous chunk of rows
+    const int per = (rows + PREP_BLK - 1) / PREP_BLK;
+    const int q0 = min(tid * per, rows), q1 = min(q0 + per, rows);
+    int local = 0;
+    for (int r = q0; r < q1; ++r) local += cnt[r];
+    int incl = local;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int v = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += v;
+    }
+    if (lane == 63) wsum[wid] = incl;
+    __syncthreads();
+    int base = 0;
+    for (int w = 0; w < wid; ++w) base += wsum[w];
+    int run = base + incl - local;
+    __syncthreads();
+    int *rs = m.rowstart + (size_t)k * (ROWS_MAX + 1);
+    for (int r = q0; r < q1; ++r) {
+        const int c = cnt[r];
+        rs[r] = run;
+        cnt[r] = run;   // becomes the scatter cursor
+        run += c;
+    }
+    if (tid == 0) rs[rows] = cd.nn;
+    __syncthreads();
+    int *ids = m.rowids + cd.node0;
+    for (int n = tid; n < cd.nn; n += PREP_BLK) {
+        const double4 X = m.X[cd.node0 + n];
+        const int ry = min(max((int)floor(X.y) - lo1, 0), dim1 - 1);
+        const int rz = min(max((int)floor(X.z) - lo2, 0), dim2 - 1);
+        ids[atomicAdd(&cnt[rz * dim1 + ry], 1)] = cd.node0 + n;
+    }
+    __syncthreads();
+    // order each row by node id (rows hold a handful of nodes)
+    for (int r = tid; r < rows; r += PREP_BLK) {
+        const int a = rs[r], b = rs[r + 1];
+        for (int i = a + 1; i < b; ++i) {
+            const int v = ids[i];
+            int j = i - 1;
+            while (j >= a && ids[j] > v) { ids[j + 1] = ids[j]; --j; }
+            ids[j + 1] = v;
         }
     }
 }
 
-void launch_capsule_reduce(const MembraneArgs &m, hipStream_t st) {
-    hipLaunchKernelGGL(k_capsule_reduce, dim3(m.ncap), dim3(RBLK), 0, st, m);
+void launch_capsule_prep(const MembraneArgs &m, hipStream_t st) {
+    hipLaunchKernelGGL(k_capsule_prep, dim3(m.ncap), dim3(PREP_BLK), 0, st, m);
 }
 
 // ------------------------------------------------------------------------------------
@@ -182,14 +245,19 @@ __device__ __forceinline__ void skalak_corner(const float3 u, const float3 v, co
     }
 }
 
-__global__ void __launch_bounds__(256) k_membrane_forces(MembraneArgs m, int ntot) {
+constexpr int MEM_BLK = 128;
+
+__global__ void __launch_bounds__(MEM_BLK) k_membrane_forces(MembraneArgs m, int ntot) {
+    __shared__ CapState s_cst[MAX_CAPS];
+    for (int j = threadIdx.x; j < m.ncap; j += MEM_BLK) s_cst[j] = m.cst[j];
+    __syncthreads();
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= ntot) return;
     const int k = m.node_cap[n];
     const CapDev cd = m.caps[k];
     const double4 X = m.X[n];
     float f[3] = {0.f, 0.f, 0.f}, fh[3] = {0.f, 0.f, 0.f};
-    const double vcoef = cd.kv != 0.0f ? -(double)cd.kv * (m.cst[k].vol - cd.v0) / cd.v0 : 0.0;
+    const double vcoef = cd.kv != 0.0f ? -(double)cd.kv * (s_cst[k].vol - cd.v0) / cd.v0 : 0.0;
     for (int e = m.ntri_off[n]; e < m.ntri_off[n + 1]; ++e) {
         const int t = m.ntri[e] / 3, corner = m.ntri[e] - 3 * (m.ntri[e] / 3);
         const int4 tr = m.tri[t];
@@ -222,7 +290,7 @@ __global__ void __launch_bounds__(256) k_membrane_forces(MembraneArgs m, int nto
         const double p[3] = {X.x, X.y, X.z};
         for (int j = 0; j < m.ncap; ++j) {
             if (j == k) continue;
-            const CapState cj = m.cst[j];
+            const CapState &cj = s_cst[j];
             double pl[3];   // this node in the periodic image closest to window j
             bool far = false;
             for (int d = 0; d < 3; ++d) {
@@ -263,7 +331,7 @@ __global__ void __launch_bounds__(256) k_membrane_forces(MembraneArgs m, int nto
         }
     }
     if (cd.anchor_k != 0.0f) {
-        const CapState cs = m.cst[k];
+        const CapState &cs = s_cst[k];
         const double ka = (double)cd.anchor_k / cd.nn;
         for (int d = 0; d < 3; ++d) f[d] += (float)(-ka * (cs.cen[d] - cd.c0[d]));
     }
@@ -273,7 +341,8 @@ __global__ void __launch_bounds__(256) k_membrane_forces(MembraneArgs m, int nto
 }
 
 void launch_membrane_forces(const MembraneArgs &m, int ntot, hipStream_t st) {
-    hipLaunchKernelGGL(k_membrane_forces, dim3((ntot + 255) / 256), dim3(256), 0, st, m, ntot);
+    hipLaunchKernelGGL(k_membrane_forces, dim3((ntot + MEM_BLK - 1) / MEM_BLK), dim3(MEM_BLK), 0, st,
+                       m, ntot);
 }
 
 // ------------------------------------------------------------------------------------
@@ -340,97 +409,123 @@ void launch_label_marks(const MembraneArgs &m, int ttot, hipStream_t st) {
 }
 
 // ------------------------------------------------------------------------------------
-// Node rows: nodes of each capsule grouped by the (y, z) lattice row of floor(X) in the
-// window, ordered by node id inside a row.  One block per capsule.
+// Window fill, in two kernels.
+//
+// k_window_own: one block per (capsule k, plane of its window).  Every node whose kernel
+// support reaches the plane (a contiguous run of the row-sorted ids) adds its 4 x 4 sites
+// of the plane, F_n phi(x - X_n) and phi(x - X_n), into an LDS plane buffer.  The sums
+// are 64-bit fixed point (2^-40 units), so the atomic adds are exact and the result does
+// not depend on their order.  Then one thread per column carries the crossing parity up
+// the column.  Results go to capsule k's window buffers.
+//
+// k_window_combine: per window site, the sum over every window holding the site, in
+// capsule order, of those buffers; the side label is the highest capsule whose parity is
+// odd.  Wall sites receive nothing.  Sites in several windows are written with the same
+// values by each of them.
 // ------------------------------------------------------------------------------------
-__global__ void __launch_bounds__(BIN_BLK) k_node_bin(MembraneArgs m) {
-    const int k = blockIdx.x, tid = threadIdx.x;
-    const CapDev cd = m.caps[k];
-    const CapState cs = m.cst[k];
-    const int rows = cs.dim[1] * cs.dim[2];
-    __shared__ int cnt[ROWS_MAX];
-    __shared__ int wsum[BIN_BLK / 64];
-    for (int r = tid; r < rows; r += BIN_BLK) cnt[r] = 0;
-    __syncthreads();
-    for (int n = tid; n < cd.nn; n += BIN_BLK) {
-        const double4 X = m.X[cd.node0 + n];
-        const int ry = min(max((int)floor(X.y) - cs.lo[1], 0), cs.dim[1] - 1);
-        const int rz = min(max((int)floor(X.z) - cs.lo[2], 0), cs.dim[2] - 1);
-        atomicAdd(&cnt[rz * cs.dim[1] + ry], 1);
+constexpr int FILL_COLS = 2048;     // LDS plane capacity: windows up to 2048 columns (x * y)
+constexpr float FIX_SCALE = 1099511627776.0f;   // 2^40
+
+__device__ __forceinline__ long long to_fix(float v) { return __float2ll_rn(v * FIX_SCALE); }
+__device__ __forceinline__ float from_fix(long long v) {
+    return (float)((double)v * (1.0 / 1099511627776.0));
+}
+
+__global__ void __launch_bounds__(256) k_window_own(MembraneArgs m) {
+    const int k = blockIdx.y, lz = blockIdx.x, tid = threadIdx.x;
+    const CapState ck = m.cst[k];
+    if (lz >= ck.dim[2]) return;
+    const int dx = ck.dim[0], dy = ck.dim[1], ncol = dx * dy;
+    __shared__ unsigned long long s_acc[4][FILL_COLS];
+    if (ncol > FILL_COLS) {   // uniform over the block
+        if (tid == 0) atomicOr(&m.status[ST_WIDE], 1);
+        return;
     }
+    float4 *wb = m.wbuf + (size_t)k * GMAX3 + (size_t)lz * ncol;
+    uint8_t *wp = m.wpar + (size_t)k * GMAX3 + (size_t)lz * ncol;
+    unsigned long long *acc = &s_acc[0][0];
+    constexpr int stride = FILL_COLS;
+    for (int i = tid; i < ncol; i += blockDim.x)
+        for (int d = 0; d < 4; ++d) acc[d * stride + i] = 0ull;
     __syncthreads();
-    // exclusive scan: each thread owns a contiguous chunk of rows
-    const int per = (rows + BIN_BLK - 1) / BIN_BLK;
-    const int r0 = min(tid * per, rows), r1 = min(r0 + per, rows);
-    int local = 0;
-    for (int r = r0; r < r1; ++r) local += cnt[r];
-    const int lane = tid & 63, wid = tid >> 6;
-    int incl = local;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const int v = __shfl_up(incl, o, 64);
-        if (lane >= o) incl += v;
-    }
-    if (lane == 63) wsum[wid] = incl;
-    __syncthreads();
-    int base = 0;
-    for (int w = 0; w < wid; ++w) base += wsum[w];
-    int run = base + incl - local;
-    __syncthreads();
-    int *rs = m.rowstart + (size_t)k * (ROWS_MAX + 1);
-    for (int r = r0; r < r1; ++r) {
-        const int c = cnt[r];
-        rs[r] = run;
-        cnt[r] = run;   // becomes the scatter cursor
-        run += c;
-    }
-    if (tid == 0) rs[rows] = cd.nn;
-    __syncthreads();
-    int *ids = m.rowids + cd.node0;
-    for (int n = tid; n < cd.nn; n += BIN_BLK) {
-        const double4 X = m.X[cd.node0 + n];
-        const int ry = min(max((int)floor(X.y) - cs.lo[1], 0), cs.dim[1] - 1);
-        const int rz = min(max((int)floor(X.z) - cs.lo[2], 0), cs.dim[2] - 1);
-        ids[atomicAdd(&cnt[rz * cs.dim[1] + ry], 1)] = cd.node0 + n;
-    }
-    __syncthreads();
-    // order each row by node id (rows hold a handful of nodes)
-    for (int r = tid; r < rows; r += BIN_BLK) {
-        const int a = rs[r], b = rs[r + 1];
-        for (int i = a + 1; i < b; ++i) {
-            const int v = ids[i];
-            int j = i - 1;
-            while (j >= a && ids[j] > v) { ids[j + 1] = ids[j]; --j; }
-            ids[j + 1] = v;
+    // nodes with floor(Z) - lo_z in [lz - 2, lz + 1] reach this plane
+    const int r0 = max(lz - 2, 0), r1 = min(lz + 1, ck.dim[2] - 1);
+    const int *rs = m.rowstart + (size_t)k * (ROWS_MAX + 1);
+    const int e0 = rs[r0 * dy], e1 = rs[(r1 + 1) * dy];
+    const int node0 = m.caps[k].node0;
+    const double zs = (double)(ck.lo[2] + lz);
+    for (int w = tid; w < (e1 - e0) * 4; w += blockDim.x) {
+        const int e = e0 + (w >> 2), oy = w & 3;
+        const int n = m.rowids[node0 + e];
+        const double4 X = m.X[n];
+        const float4 F = m.F[n];
+        const double fx = floor(X.x), fy = floor(X.y);
+        const float wz = phi4((float)(X.z - zs));
+        const int bx = (int)fx - 1 - ck.lo[0], by = (int)fy - 1 - ck.lo[1];
+        const int ly = by + oy;
+        const float wy = phi4((float)(X.y - fy) + (float)(1 - oy));
+        if (ly < 0 || ly >= dy) continue;
+        for (int ox = 0; ox < 4; ++ox) {
+            const int lx = bx + ox;
+            if (lx < 0 || lx >= dx) continue;
+            const float wgt = phi4((float)(X.x - fx) + (float)(1 - ox)) * wy * wz;
+            const int col = ly * dx + lx;
+            atomicAdd(&acc[col], (unsigned long long)to_fix(wgt * F.x));
+            atomicAdd(&acc[stride + col], (unsigned long long)to_fix(wgt * F.y));
+            atomicAdd(&acc[2 * stride + col], (unsigned long long)to_fix(wgt * F.z));
+            atomicAdd(&acc[3 * stride + col], (unsigned long long)to_fix(wgt));
         }
     }
+    __syncthreads();
+    const int *mk = m.marks + (size_t)k * GMAX3;
+    for (int col = tid; col < ncol; col += blockDim.x) {
+        int par = 0;
+        for (int q = 0; q <= lz; ++q) par ^= mk[q * ncol + col];
+        wb[col] = make_float4(from_fix((long long)acc[col]), from_fix((long long)acc[stride + col]),
+                              from_fix((long long)acc[2 * stride + col]),
+                              from_fix((long long)acc[3 * stride + col]));
+        wp[col] = (uint8_t)(par & 1);
+    }
 }
 
-void launch_node_bin(const MembraneArgs &m, hipStream_t st) {
-    hipLaunchKernelGGL(k_node_bin, dim3(m.ncap), dim3(BIN_BLK), 0, st, m);
-}
-
-// ------------------------------------------------------------------------------------
-// Window fill: per window site, the side label (prefix XOR of the marks of every window
-// holding the site) and the spread force f(x) = sum_n F_n phi(x - X_n) with the kernel
-// coverage c(x) = sum_n phi(x - X_n), gathered over the node rows of every window
-// holding the site, in a fixed order.  Wall sites receive nothing.
-// ------------------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_window_fill(MembraneArgs m) {
-    const int k = blockIdx.y;
+__global__ void __launch_bounds__(256) k_window_combine(MembraneArgs m) {
+    const int k = blockIdx.y, lz = blockIdx.x, tid = threadIdx.x;
     const CapState ck = m.cst[k];
-    const int nv = ck.dim[0] * ck.dim[1] * ck.dim[2];
+    if (lz >= ck.dim[2]) return;
+    const int dx = ck.dim[0], dy = ck.dim[1];
+    __shared__ int s_win[MAX_CAPS + 1];
+    __shared__ CapState s_cs[MAX_CAPS];
+    __shared__ int s_n;
+    // windows meeting this plane of window k, in capsule order (k included)
+    if (tid == 0) {
+        const int nd[3] = {m.nx, m.ny, m.nz};
+        const int blo[3] = {ck.lo[0], ck.lo[1], ck.lo[2] + lz};
+        const int bdim[3] = {dx, dy, 1};
+        int n = 0;
+        for (int j = 0; j < m.ncap; ++j) {
+            const CapState cj = m.cst[j];
+            bool meet = true;
+            for (int d = 0; d < 3; ++d) {
+                const int off = wrapm(cj.lo[d] - blo[d], nd[d]);
+                meet = meet && (off < bdim[d] || off + cj.dim[d] > nd[d]);
+            }
+            if (meet) { s_cs[n] = cj; s_win[n++] = j; }
+        }
+        s_n = n;
+    }
+    __syncthreads();
+    const int nwin = s_n;
     const int nd[3] = {m.nx, m.ny, m.nz};
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += gridDim.x * blockDim.x) {
-        const int lx = i % ck.dim[0], t = i / ck.dim[0], ly = t % ck.dim[1], lz = t / ck.dim[1];
+    for (int col = tid; col < dx * dy; col += blockDim.x) {
+        const int lx = col % dx, ly = col / dx;
         const int u[3] = {ck.lo[0] + lx, ck.lo[1] + ly, ck.lo[2] + lz};
         const int z = wrapm(u[2], m.nz);
         if (m.wall && z == 0) continue;
-        const int x = wrapm(u[0], m.nx), y = wrapm(u[1], m.ny);
         int lab = 0;
         float f[3] = {0.f, 0.f, 0.f}, c = 0.f;
-        for (int j = 0; j < m.ncap; ++j) {
-            const CapState cj = j == k ? ck : m.cst[j];
+        for (int i = 0; i < nwin; ++i) {
+            const int j = s_win[i];
+            const CapState &cj = s_cs[i];
             int l[3];
             bool in = true;
             for (int d = 0; d < 3; ++d) {
@@ -438,32 +533,15 @@ __global__ void __launch_bounds__(256) k_window_fill(MembraneArgs m) {
                 in = in && l[d] < cj.dim[d];
             }
             if (!in) continue;
-            const int *mk = m.marks + (size_t)j * GMAX3;
-            int par = 0;
-            for (int q = 0; q <= l[2]; ++q) par ^= mk[(q * cj.dim[1] + l[1]) * cj.dim[0] + l[0]];
-            if (par & 1) lab = j + 1;
-            const double uj[3] = {(double)(cj.lo[0] + l[0]), (double)(cj.lo[1] + l[1]),
-                                  (double)(cj.lo[2] + l[2])};
-            const int *rs = m.rowstart + (size_t)j * (ROWS_MAX + 1);
-            const int node0 = m.caps[j].node0;
-            for (int rz = max(l[2] - 2, 0); rz <= min(l[2] + 1, cj.dim[2] - 1); ++rz)
-                for (int ry = max(l[1] - 2, 0); ry <= min(l[1] + 1, cj.dim[1] - 1); ++ry) {
-                    const int row = rz * cj.dim[1] + ry;
-                    for (int e = rs[row]; e < rs[row + 1]; ++e) {
-                        const int n = m.rowids[node0 + e];
-                        const double4 X = m.X[n];
-                        const float dx = (float)(X.x - uj[0]);
-                        if (!(dx > -2.0f && dx < 2.0f)) continue;
-                        const float w = phi4(dx) * phi4((float)(X.y - uj[1])) *
-                                        phi4((float)(X.z - uj[2]));
-                        const float4 Fn = m.F[n];
-                        f[0] += w * Fn.x;
-                        f[1] += w * Fn.y;
-                        f[2] += w * Fn.z;
-                        c += w;
-                    }
-                }
+            const int li = (l[2] * cj.dim[1] + l[1]) * cj.dim[0] + l[0];
+            const float4 v = m.wbuf[(size_t)j * GMAX3 + li];
+            f[0] += v.x;
+            f[1] += v.y;
+            f[2] += v.z;
+            c += v.w;
+            if (m.wpar[(size_t)j * GMAX3 + li]) lab = j + 1;
         }
+        const int x = wrapm(u[0], m.nx), y = wrapm(u[1], m.ny);
         const int s = (z * m.ny + y) * m.nx + x;
         m.flag[s] = (uint8_t)(lab | AUX_BIT);
         m.ibm[s] = make_float4(f[0], f[1], f[2], c);
@@ -471,12 +549,14 @@ __global__ void __launch_bounds__(256) k_window_fill(MembraneArgs m) {
 }
 
 void launch_window_fill(const MembraneArgs &m, hipStream_t st) {
-    hipLaunchKernelGGL(k_window_fill, dim3(64, m.ncap), dim3(256), 0, st, m);
+    hipLaunchKernelGGL(k_window_own, dim3(GMAX, m.ncap), dim3(256), 0, st, m);
+    hipLaunchKernelGGL(k_window_combine, dim3(GMAX, m.ncap), dim3(256), 0, st, m);
 }
 
 // ------------------------------------------------------------------------------------
 // Node update: U_n = sum_x u(x) phi(x - X_n) (wall sites contribute nothing),
-// R_n = sum_x r(x) phi(x - X_n) / c(x) over covered sites, X_n += U_n.
+// R_n = sum_x r(x) phi(x - X_n) / c(x) over covered sites (the fluid step stores r / c),
+// X_n += U_n.
 // ------------------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_node_update(MembraneArgs m, int ntot) {
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
@@ -501,13 +581,9 @@ __global__ void __launch_bounds__(256) k_node_update(MembraneArgs m, int ntot) {
                 const int s = (z * m.ny + y) * m.nx + x;
                 const float w = wx[ox] * wy[oy] * wz[oz];
                 const float4 u = m.uo[s];
+                const float4 r = m.ro[s];   // reaction / coverage, 0 where uncovered
                 U[0] += w * u.x; U[1] += w * u.y; U[2] += w * u.z;
-                const float cov = m.ibm[s].w;
-                if (cov > 0.f) {
-                    const float4 r = m.ro[s];
-                    const float wc = w / cov;
-                    Rr[0] += wc * r.x; Rr[1] += wc * r.y; Rr[2] += wc * r.z;
-                }
+                Rr[0] += w * r.x; Rr[1] += w * r.y; Rr[2] += w * r.z;
             }
         }
     }
