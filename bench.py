@@ -100,7 +100,7 @@ def run_gpu(cfg, storage, steps, warmup, do_tune=True, launch=None):
     return out
 
 
-def cpu_baseline(cfg, steps=3):
+def cpu_baseline(cfg, steps=10):
     import oracle
     cores = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
     o = oracle.Oracle(cfg, "f64", n_threads=cores)
