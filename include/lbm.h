@@ -50,6 +50,10 @@ extern "C" {
 
 typedef struct lbm_handle lbm_handle;
 
+/* Limits: capsules per simulation, nodes per capsule mesh. */
+#define LBM_MAX_CAPSULES 125
+#define LBM_MAX_CAPSULE_NODES 8192
+
 typedef enum {
     LBM_OK = 0,
     LBM_E_INVAL = -1,     /* invalid argument or parameter                     */
@@ -138,7 +142,8 @@ typedef struct {
  * init_rho_array is read during the call only.  On failure *out is NULL. */
 lbm_status lbm_init(const lbm_params *params, lbm_handle **out);
 
-/* Add a capsule: a closed triangle mesh, outward counter-clockwise, n_nodes >= 4,
+/* Add a capsule: a closed triangle mesh, outward counter-clockwise,
+ * 4 <= n_nodes <= LBM_MAX_CAPSULE_NODES, at most LBM_MAX_CAPSULES per simulation,
  * xyz host [n_nodes][3] (unwrapped lattice coordinates), tri host [n_tri][3].  The mesh
  * at this moment is the stress-free reference (Section 3.1).  Copied during the call.
  * Only before the first lbm_step (LBM_E_STATE afterwards).  *id_out gets the index. */

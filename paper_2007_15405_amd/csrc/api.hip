@@ -3,6 +3,7 @@
 #include "lbm.h"
 #include "lbm_internal.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -59,8 +60,12 @@ struct lbm_handle {
     int4 *d_tri = nullptr;
     float4 *d_minv = nullptr;
     float *d_a0 = nullptr;
-    int *d_off = nullptr, *d_list = nullptr, *d_marks = nullptr, *d_rowstart = nullptr,
-        *d_rowids = nullptr;
+    int *d_off = nullptr, *d_list = nullptr, *d_rowstart = nullptr, *d_slot = nullptr,
+        *d_counter = nullptr;
+    double4 *d_xrow = nullptr;
+    unsigned long long *d_marks = nullptr;
+    CapPartial *d_part = nullptr;
+    int nch = 1;
     float4 *d_wbuf = nullptr;
     uint8_t *d_wpar = nullptr;
     std::vector<CapDev> h_caps;
@@ -92,8 +97,8 @@ static void free_all(lbm_handle *h) {
     void *ptrs[] = {h->f[0], h->f[1], h->flag, h->ibm, h->uo, h->ro, h->psi, h->cap_drho,
                     h->rho_tmp, h->men_tmp, h->status, h->partial, h->d_caps, h->d_cst, h->d_X,
                     h->d_node_cap, h->d_F, h->d_Fh, h->d_R, h->d_tri, h->d_minv, h->d_a0,
-                    h->d_off, h->d_list, h->d_marks, h->d_rowstart, h->d_rowids, h->d_wbuf,
-                    h->d_wpar};
+                    h->d_off, h->d_list, h->d_marks, h->d_rowstart, h->d_slot, h->d_wbuf,
+                    h->d_wpar, h->d_part, h->d_counter, h->d_xrow};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (hipEvent_t e : h->event_pool) (void)hipEventDestroy(e);
@@ -287,7 +292,9 @@ extern "C" lbm_status lbm_add_capsule(lbm_handle *h, const lbm_capsule_params *c
                                       const int32_t *tri, int32_t *id_out) {
     if (!h) return LBM_E_INVAL;
     if (h->finalized) return fail(h, LBM_E_STATE, "capsules must be added before the first step");
-    if (!cp || !xyz || !tri || n_nodes < 4 || n_tri < 4)
+    static_assert(MAX_CAPS == LBM_MAX_CAPSULES && MAX_CAP_NODES == LBM_MAX_CAPSULE_NODES,
+                  "limits in lbm.h and the kernels agree");
+    if (!cp || !xyz || !tri || n_nodes < 4 || n_tri < 4 || n_nodes > MAX_CAP_NODES)
         return fail(h, LBM_E_INVAL, "invalid capsule mesh");
     if ((int)h->caps.size() >= MAX_CAPS) return fail(h, LBM_E_INVAL, "too many capsules");
     if (cp->kb != 0.0) return fail(h, LBM_E_INVAL, "bending (kb != 0) is not supported");
@@ -386,6 +393,11 @@ static lbm_status finalize(lbm_handle *h) {
         h->h_caps.push_back(cd);
     }
     h->ntot = (int)X.size();
+    {
+        int mw = 1;
+        for (const CapDev &c : h->h_caps) mw = std::max(mw, std::max(c.nn, c.nt));
+        h->nch = reduce_chunks(mw);
+    }
     h->ttot = (int)tri.size();
     // node -> incident triangle CSR (entries 3 * triangle + corner, triangle order)
     off.assign(h->ntot + 1, 0);
@@ -405,9 +417,11 @@ static lbm_status finalize(lbm_handle *h) {
         dalloc(&h->d_R, nt) != hipSuccess || dalloc(&h->d_tri, tt) != hipSuccess ||
         dalloc(&h->d_minv, tt) != hipSuccess || dalloc(&h->d_a0, tt) != hipSuccess ||
         dalloc(&h->d_off, nt + 1) != hipSuccess || dalloc(&h->d_list, list.size()) != hipSuccess ||
-        dalloc(&h->d_marks, (size_t)ncap * GMAX3) != hipSuccess ||
+        dalloc(&h->d_marks, (size_t)ncap * ROWS_MAX) != hipSuccess ||
+        dalloc(&h->d_part, (size_t)ncap * h->nch) != hipSuccess ||
+        dalloc(&h->d_counter, ncap) != hipSuccess ||
         dalloc(&h->d_rowstart, (size_t)ncap * (ROWS_MAX + 1)) != hipSuccess ||
-        dalloc(&h->d_rowids, nt) != hipSuccess ||
+        dalloc(&h->d_slot, nt) != hipSuccess || dalloc(&h->d_xrow, nt) != hipSuccess ||
         dalloc(&h->d_wbuf, (size_t)ncap * GMAX3) != hipSuccess ||
         dalloc(&h->d_wpar, (size_t)ncap * GMAX3) != hipSuccess)
         return fail(h, LBM_E_NOMEM, "device allocation failed (capsules)");
@@ -423,9 +437,11 @@ static lbm_status finalize(lbm_handle *h) {
     HIPCHK(h, hipMemcpyAsync(h->d_a0, a0.data(), tt * sizeof(float), hipMemcpyHostToDevice, h->st));
     HIPCHK(h, hipMemcpyAsync(h->d_off, off.data(), (nt + 1) * sizeof(int), hipMemcpyHostToDevice, h->st));
     HIPCHK(h, hipMemcpyAsync(h->d_list, list.data(), list.size() * sizeof(int), hipMemcpyHostToDevice, h->st));
-    HIPCHK(h, hipMemsetAsync(h->d_marks, 0, (size_t)ncap * GMAX3 * sizeof(int), h->st));
+    HIPCHK(h, hipMemsetAsync(h->d_marks, 0, (size_t)ncap * ROWS_MAX * sizeof(unsigned long long), h->st));
+    HIPCHK(h, hipMemsetAsync(h->d_counter, 0, ncap * sizeof(int), h->st));
     HIPCHK(h, hipMemsetAsync(h->d_rowstart, 0, (size_t)ncap * (ROWS_MAX + 1) * sizeof(int), h->st));
-    HIPCHK(h, hipMemsetAsync(h->d_rowids, 0, nt * sizeof(int), h->st));
+    HIPCHK(h, hipMemsetAsync(h->d_slot, 0, nt * sizeof(int), h->st));
+    HIPCHK(h, hipMemsetAsync(h->d_xrow, 0, nt * sizeof(double4), h->st));
     HIPCHK(h, hipMemcpyAsync(h->cap_drho, drho.data(), MAX_CAPS * sizeof(float), hipMemcpyHostToDevice, h->st));
     HIPCHK(h, hipStreamSynchronize(h->st));
     return LBM_OK;
@@ -440,7 +456,8 @@ static MembraneArgs membrane_args(lbm_handle *h) {
     m.X = h->d_X; m.node_cap = h->d_node_cap; m.F = h->d_F; m.Fh = h->d_Fh; m.R = h->d_R;
     m.tri = h->d_tri; m.minv = h->d_minv; m.a0 = h->d_a0;
     m.ntri_off = h->d_off; m.ntri = h->d_list;
-    m.marks = h->d_marks; m.rowstart = h->d_rowstart; m.rowids = h->d_rowids;
+    m.marks = h->d_marks; m.rowstart = h->d_rowstart; m.xrow = h->d_xrow; m.slot = h->d_slot;
+    m.part = h->d_part; m.counter = h->d_counter; m.nch = h->nch;
     m.wbuf = h->d_wbuf; m.wpar = h->d_wpar;
     m.flag = h->flag; m.ibm = h->ibm; m.uo = h->uo; m.ro = h->ro; m.status = h->status;
     m.nx = h->nx; m.ny = h->ny; m.nz = h->nz; m.wall = h->wall;
@@ -503,13 +520,12 @@ extern "C" lbm_status lbm_step(lbm_handle *h, int64_t n) {
         if (s != LBM_OK) return s;
     }
     const bool caps = !h->caps.empty();
-    const MembraneArgs m = caps ? membrane_args(h) : MembraneArgs{};
+    MembraneArgs m = caps ? membrane_args(h) : MembraneArgs{};
     for (int64_t i = 0; i < n; ++i) {
         if (caps) {
-            timed(h, "capsule_prep", [&] { launch_capsule_prep(m, h->st); });
-            timed(h, "window_clear", [&] { launch_window_clear(m, h->st); });
-            timed(h, "membrane_forces", [&] { launch_membrane_forces(m, h->ntot, h->st); });
-            timed(h, "label_marks", [&] { launch_label_marks(m, h->ttot, h->st); });
+            m.epoch = (int)(h->step & 0x7fffffff);
+            timed(h, "capsule_reduce", [&] { launch_capsule_reduce(m, h->st); });
+            timed(h, "membrane", [&] { launch_membrane(m, h->ntot, h->ttot, h->st); });
             timed(h, "window_fill", [&] { launch_window_fill(m, h->st); });
         }
         const FluidArgs a = fluid_args(h);
@@ -536,6 +552,7 @@ static lbm_status check_status(lbm_handle *h, int st[ST_WORDS]) {
 }
 
 static const char *unstable_message(const int *st) {
+    if (st[ST_SYNC]) return "capsule reduction read partial sums of another step";
     if (st[ST_WIDE]) return "capsule window wider than 2048 lattice columns (x * y)";
     if (st[ST_OVERFLOW]) return "capsule outgrew its window";
     return "non-finite or negative density";
@@ -546,7 +563,7 @@ extern "C" lbm_status lbm_sync(lbm_handle *h) {
     int st[ST_WORDS];
     lbm_status s = check_status(h, st);
     if (s != LBM_OK) return s;
-    if (st[ST_UNSTABLE] || st[ST_OVERFLOW] || st[ST_WIDE])
+    if (st[ST_UNSTABLE] || st[ST_OVERFLOW] || st[ST_WIDE] || st[ST_SYNC])
         return fail(h, LBM_E_UNSTABLE, unstable_message(st));
     return LBM_OK;
 }
@@ -598,7 +615,7 @@ extern "C" lbm_status lbm_observables(lbm_handle *h, lbm_obs *out) {
     sm.step = h->step;
     sm.lost_reaction = st[ST_LOST];
     sm.n_capsules = (int)h->caps.size();
-    sm.unstable = (st[ST_UNSTABLE] || st[ST_OVERFLOW] || st[ST_WIDE]) ? 1 : 0;
+    sm.unstable = (st[ST_UNSTABLE] || st[ST_OVERFLOW] || st[ST_WIDE] || st[ST_SYNC]) ? 1 : 0;
     if (h->finalized && !h->caps.empty()) {
         std::vector<double4> X(h->ntot);
         std::vector<float4> Fh(h->ntot), R(h->ntot);
@@ -692,6 +709,8 @@ extern "C" lbm_status lbm_labels(lbm_handle *h, uint8_t *out) {
 // Checkpoints
 // ------------------------------------------------------------------------------------
 namespace {
+// version 2: capsule state without the previous-window fields
+constexpr int32_t CKPT_VERSION = 2;
 struct CkptHeader {
     char magic[8];
     int32_t version, nx, ny, nz, storage, ncap, ntot, pad;
@@ -721,7 +740,7 @@ extern "C" lbm_status lbm_save(lbm_handle *h, const char *path) {
     if (!fp) return fail(h, LBM_E_INVAL, std::string("cannot open ") + path);
     CkptHeader hd{};
     std::memcpy(hd.magic, "LBMXCKP", 8);
-    hd.version = 1; hd.nx = h->nx; hd.ny = h->ny; hd.nz = h->nz; hd.storage = h->storage;
+    hd.version = CKPT_VERSION; hd.nx = h->nx; hd.ny = h->ny; hd.nz = h->nz; hd.storage = h->storage;
     hd.ncap = (int)h->caps.size(); hd.ntot = h->ntot; hd.step = h->step;
     bool ok = std::fwrite(&hd, sizeof hd, 1, fp) == 1 && std::fwrite(f.data(), 1, fbytes, fp) == fbytes;
     if (h->ntot)
@@ -747,7 +766,7 @@ extern "C" lbm_status lbm_load(lbm_handle *h, const char *path) {
     std::vector<float4> R(h->ntot);
     std::vector<CapState> cs(h->caps.size());
     bool ok = std::fread(&hd, sizeof hd, 1, fp) == 1 && std::memcmp(hd.magic, "LBMXCKP", 8) == 0 &&
-              hd.version == 1 && hd.nx == h->nx && hd.ny == h->ny && hd.nz == h->nz &&
+              hd.version == CKPT_VERSION && hd.nx == h->nx && hd.ny == h->ny && hd.nz == h->nz &&
               hd.storage == h->storage && hd.ncap == (int)h->caps.size() && hd.ntot == h->ntot &&
               std::fread(f.data(), 1, fbytes, fp) == fbytes;
     if (ok && h->ntot)
@@ -765,6 +784,8 @@ extern "C" lbm_status lbm_load(lbm_handle *h, const char *path) {
         HIPCHK(h, hipMemcpy(h->d_R, R.data(), R.size() * sizeof(float4), hipMemcpyHostToDevice));
         HIPCHK(h, hipMemcpy(h->d_cst, cs.data(), cs.size() * sizeof(CapState), hipMemcpyHostToDevice));
     }
+    if (h->ntot)   // crossing masks of windows this handle used before the load
+        HIPCHK(h, hipMemset(h->d_marks, 0, h->caps.size() * ROWS_MAX * sizeof(unsigned long long)));
     HIPCHK(h, hipMemset(h->status, 0, ST_WORDS * sizeof(int)));
     h->step = hd.step;
     return LBM_OK;

@@ -31,14 +31,17 @@ __host__ __device__ constexpr bool is_axis(int q) {
 constexpr uint8_t LABEL_MASK = 0x7f;
 constexpr uint8_t AUX_BIT = 0x80;
 constexpr int LABEL_WALL = 127;   // label value used for wall neighbours inside kernels
-constexpr int MAX_CAPS = 125;
+constexpr int MAX_CAPS = 125;        // LBM_MAX_CAPSULES
+constexpr int MAX_CAP_NODES = 8192;  // LBM_MAX_CAPSULE_NODES
 constexpr int GMAX = 64;          // maximum edge of a capsule window (sites)
 constexpr int GMAX3 = GMAX * GMAX * GMAX;
 constexpr int ROWS_MAX = GMAX * GMAX;
 
 // status words (device): [0] unstable flag, [1] lost reaction count, [2] window overflow,
-// [3] window wider than the spreading plane buffer
-constexpr int ST_UNSTABLE = 0, ST_LOST = 1, ST_OVERFLOW = 2, ST_WIDE = 3, ST_WORDS = 4;
+// [3] window wider than the spreading plane buffer, [4] a cross-block capsule reduction
+// read partial sums of another step (memory ordering failure; never expected)
+constexpr int ST_UNSTABLE = 0, ST_LOST = 1, ST_OVERFLOW = 2, ST_WIDE = 3, ST_SYNC = 4,
+              ST_WORDS = 5;
 
 // ------------------------------------------------------------------------------------
 // Population storage codec.  S = 0: FP32 as is.  S = 1: FP16 of f - w_i rho_s.
@@ -111,7 +114,15 @@ struct CapState {
     double vol;             // enclosed volume at X^n
     float bmin[3], bmax[3]; // node bounding box (FP32 positions)
     int lo[3], dim[3];      // window: sites lo .. lo + dim - 1 (unwrapped)
-    int plo[3], pdim[3];    // window of the previous step (to clear)
+};
+
+// Partial sums of one block of the capsule reduction.
+struct CapPartial {
+    double s[3];            // sum of X - X_ref over the block's nodes (X_ref: first node)
+    double vol;             // sum of signed tetrahedron volumes, apex X_ref
+    float mn[3], mx[3];     // bounding box of the FP32-rounded positions
+    int epoch;              // step that wrote it
+    int pad;
 };
 
 struct MembraneArgs {
@@ -120,7 +131,7 @@ struct MembraneArgs {
     int ncap;
     double4 *X;             // [Ntot] node positions (unwrapped, FP64 state), w unused
     const int *node_cap;    // [Ntot] capsule index of each node
-    float4 *F;              // [Ntot] total node force
+    float4 *F;              // [Ntot] total node force, in row order (index slot[n])
     float4 *Fh;             // [Ntot] Hertz part
     float4 *R;              // [Ntot] pending reaction
     const int4 *tri;        // [Ttot] global node indices a, b, c and capsule index
@@ -128,9 +139,14 @@ struct MembraneArgs {
     const float *a0;        // [Ttot] reference area
     const int *ntri_off;    // [Ntot+1] node -> incident triangle CSR offsets
     const int *ntri;        // incident entries: 3 * triangle + corner
-    int *marks;             // [ncap][GMAX3] crossing parity marks
+    unsigned long long *marks;  // [ncap][ROWS_MAX] crossings per window column, bit = plane
     int *rowstart;          // [ncap][ROWS_MAX + 1] node rows of each window
-    int *rowids;            // [Ntot] node ids sorted by row then id (global ids)
+    double4 *xrow;          // [Ntot] node positions grouped by row (any order in a row)
+    int *slot;              // [Ntot] place of node n in the row order (global index)
+    CapPartial *part;       // [ncap][nch] partial sums of the capsule reduction
+    int *counter;           // [ncap] blocks of the reduction done (reset by the last one)
+    int nch;                // reduction blocks per capsule
+    int epoch;              // step index (low 32 bits)
     float4 *wbuf;           // [ncap][GMAX3] own spread force and coverage per window site
     uint8_t *wpar;          // [ncap][GMAX3] own crossing parity per window site
     uint8_t *flag;
@@ -153,10 +169,9 @@ template <int S> void launch_moments(const void *f, double *partial, int nblocks
 void launch_meniscus(const float *rho, const uint8_t *flag, float *out, int nx, int ny, int nz,
                      int wall, hipStream_t st);
 
-void launch_capsule_prep(const MembraneArgs &m, hipStream_t st);
-void launch_window_clear(const MembraneArgs &m, hipStream_t st);
-void launch_membrane_forces(const MembraneArgs &m, int ntot, hipStream_t st);
-void launch_label_marks(const MembraneArgs &m, int ttot, hipStream_t st);
+int reduce_chunks(int max_work);
+void launch_capsule_reduce(const MembraneArgs &m, hipStream_t st);
+void launch_membrane(const MembraneArgs &m, int ntot, int ttot, hipStream_t st);
 void launch_window_fill(const MembraneArgs &m, hipStream_t st);
 void launch_node_update(const MembraneArgs &m, int ntot, hipStream_t st);
 

@@ -22,8 +22,9 @@ __device__ __forceinline__ int wrapm(int a, int n) {
     return a < 0 ? a + n : a;
 }
 
-__device__ __forceinline__ double min_image(double d, int n, bool periodic) {
-    return periodic ? d - n * floor(d / n + 0.5) : d;
+// nearest periodic image of a separation d along an axis of n sites (inv = 1 / n)
+__device__ __forceinline__ double min_image(double d, int n, double inv, bool periodic) {
+    return periodic ? d - n * floor(d * inv + 0.5) : d;
 }
 
 template <typename T> __device__ __forceinline__ T wave_sum(T v) {
@@ -42,76 +43,187 @@ __device__ __forceinline__ float wave_max(float v) {
     return v;
 }
 
-// ------------------------------------------------------------------------------------
-// Per capsule (one block of PREP_BLK threads): node mean, enclosed volume (FP64),
-// bounding box and the site window; then the node rows of the window: nodes grouped by
-// the (y, z) lattice row of floor(X), ordered by node id inside a row.  Fixed reduction
-// order throughout.
-// ------------------------------------------------------------------------------------
-constexpr int PREP_BLK = 1024, PREP_W = PREP_BLK / 64;
+// Sums over aligned groups of 8 or 16 lanes with DPP moves inside a 16-lane row: pairs
+// (quad_perm 1,0,3,2), quads (quad_perm 2,3,0,1), half-row mirror, row mirror.  Every
+// lane of the group ends with the same, bitwise identical total.
+template <int CTRL> __device__ __forceinline__ float dpp_mov(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float group_sum8(float v) {
+    v += dpp_mov<0xb1>(v);
+    v += dpp_mov<0x4e>(v);
+    v += dpp_mov<0x141>(v);
+    return v;
+}
+__device__ __forceinline__ float group_sum16(float v) {
+    v = group_sum8(v);
+    v += dpp_mov<0x140>(v);
+    return v;
+}
 
-__global__ void __launch_bounds__(PREP_BLK) k_capsule_prep(MembraneArgs m) {
-    const int k = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+// Fixed-point accumulation (2^-40 units) for sums whose terms arrive in no fixed order.
+__device__ __forceinline__ long long to_fix(float v) {
+    return __float2ll_rn(v * 1099511627776.0f);
+}
+__device__ __forceinline__ long long to_fix_d(double v) {
+    return __double2ll_rn(v * 1099511627776.0);
+}
+__device__ __forceinline__ float from_fix(long long v) {
+    return (float)((double)v * (1.0 / 1099511627776.0));
+}
+
+// Wave sum of a double in a fixed order: DPP sums inside each 16-lane row, then the four
+// row totals in row order.  Lane 0 holds the result.
+template <int CTRL> __device__ __forceinline__ double dpp_mov_d(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double wave_sum_d(double v) {
+    v += dpp_mov_d<0xb1>(v);
+    v += dpp_mov_d<0x4e>(v);
+    v += dpp_mov_d<0x141>(v);
+    v += dpp_mov_d<0x140>(v);
+    const double r1 = __shfl(v, 16, 64), r2 = __shfl(v, 32, 64), r3 = __shfl(v, 48, 64);
+    return ((v + r1) + r2) + r3;
+}
+
+// a + o wrapped into [0, n) for |o| small; positions rarely leave [-n, 2n)
+__device__ __forceinline__ int wrap_near(int a, int n) {
+    if (a >= n) a -= n;
+    else if (a < 0) a += n;
+    return (a >= 0 && a < n) ? a : wrapm(a, n);
+}
+
+// ------------------------------------------------------------------------------------
+// Capsule reduction, grid (nch, ncap).  Each block first clears its share of the flags
+// and crossing masks of capsule k's previous window, then reduces its share of the nodes
+// (sum of X - X_ref, FP32 bounding box) and triangles (signed tetrahedron volumes with
+// apex X_ref, the first node; the volume of a closed mesh does not depend on the apex)
+// into a partial record.  The last block of capsule k to finish (device-scope counter,
+// release / acquire fences) sums the records in block order, so the result does not
+// depend on scheduling, then derives the centroid, volume, bounding box and site
+// window, and bins the nodes by the (y, z) lattice row of floor(X) inside the window:
+// positions in row order (any order inside a row), and each node's place in that order.
+// ------------------------------------------------------------------------------------
+constexpr int RED_BLK = 256, RED_W = RED_BLK / 64;
+
+int reduce_chunks(int max_work) {
+    const int c = (max_work + RED_BLK - 1) / RED_BLK;
+    return c < 1 ? 1 : (c > RED_BLK ? RED_BLK : c);
+}
+
+__global__ void __launch_bounds__(RED_BLK) k_capsule_reduce(MembraneArgs m) {
+    const int k = blockIdx.y, c = blockIdx.x, nch = m.nch;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int gstride = nch * RED_BLK, g0 = c * RED_BLK + tid;
     const CapDev cd = m.caps[k];
-    __shared__ double sd[PREP_W][4];
-    __shared__ float smin[PREP_W][3], smax[PREP_W][3];
-    __shared__ double cen[3];
-    __shared__ int s_lo[3], s_dim[3];
-    __shared__ int cnt[ROWS_MAX];
-    __shared__ int wsum[PREP_W];
-    double sacc[3] = {0, 0, 0};
+    {
+        // flags and crossing masks of the previous window (read before this block's
+        // arrival is counted, so before the last block rewrites the window)
+        const CapState old = m.cst[k];
+        const int dx = old.dim[0], dy = old.dim[1], pv = dx * dy * old.dim[2];
+        for (int i = g0; i < pv; i += gstride) {
+            const int lx = i % dx, t = i / dx, ly = t % dy, lz = t / dy;
+            const int x = wrapm(old.lo[0] + lx, m.nx), y = wrapm(old.lo[1] + ly, m.ny),
+                      z = wrapm(old.lo[2] + lz, m.nz);
+            m.flag[(z * m.ny + y) * m.nx + x] = 0;
+        }
+        for (int i = g0; i < dx * dy; i += gstride) m.marks[(size_t)k * ROWS_MAX + i] = 0ull;
+    }
+    const double4 Xr = m.X[cd.node0];
+    double s[3] = {0.0, 0.0, 0.0}, vol = 0.0;
     float mn[3] = {3e38f, 3e38f, 3e38f}, mx[3] = {-3e38f, -3e38f, -3e38f};
-    for (int n = tid; n < cd.nn; n += PREP_BLK) {
+    for (int n = g0; n < cd.nn; n += gstride) {
         const double4 X = m.X[cd.node0 + n];
-        const double p[3] = {X.x, X.y, X.z};
+        const double p[3] = {X.x, X.y, X.z}, r[3] = {Xr.x, Xr.y, Xr.z};
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-            sacc[d] += p[d];
-            const float pf = (float)p[d];
-            mn[d] = fminf(mn[d], pf);
-            mx[d] = fmaxf(mx[d], pf);
+            s[d] += p[d] - r[d];
+            mn[d] = fminf(mn[d], (float)p[d]);
+            mx[d] = fmaxf(mx[d], (float)p[d]);
         }
     }
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        const double v = wave_sum(sacc[d]);
-        const float a = wave_min(mn[d]), b = wave_max(mx[d]);
-        if (lane == 0) { sd[wid][d] = v; smin[wid][d] = a; smax[wid][d] = b; }
-    }
-    __syncthreads();
-    if (tid < 3) {
-        double v = 0;
-        for (int w = 0; w < PREP_W; ++w) v += sd[w][tid];
-        cen[tid] = v / cd.nn;
-    }
-    __syncthreads();
-    double vol = 0;
-    for (int t = tid; t < cd.nt; t += PREP_BLK) {
+    for (int t = g0; t < cd.nt; t += gstride) {
         const int4 tr = m.tri[cd.tri0 + t];
         const double4 A = m.X[tr.x], B = m.X[tr.y], C = m.X[tr.z];
-        const double a[3] = {A.x - cen[0], A.y - cen[1], A.z - cen[2]};
-        const double b[3] = {B.x - cen[0], B.y - cen[1], B.z - cen[2]};
-        const double c[3] = {C.x - cen[0], C.y - cen[1], C.z - cen[2]};
-        vol += (a[0] * (b[1] * c[2] - b[2] * c[1]) + a[1] * (b[2] * c[0] - b[0] * c[2]) +
-                a[2] * (b[0] * c[1] - b[1] * c[0])) / 6.0;
+        const double a[3] = {A.x - Xr.x, A.y - Xr.y, A.z - Xr.z};
+        const double b[3] = {B.x - Xr.x, B.y - Xr.y, B.z - Xr.z};
+        const double e[3] = {C.x - Xr.x, C.y - Xr.y, C.z - Xr.z};
+        vol += (a[0] * (b[1] * e[2] - b[2] * e[1]) + a[1] * (b[2] * e[0] - b[0] * e[2]) +
+                a[2] * (b[0] * e[1] - b[1] * e[0])) / 6.0;
     }
-    vol = wave_sum(vol);
+    __shared__ double sd[RED_W][4];
+    __shared__ float smn[RED_W][3], smx[RED_W][3];
+    __shared__ int s_last;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const double v = wave_sum_d(s[d]);
+        const float a = wave_min(mn[d]), b = wave_max(mx[d]);
+        if (lane == 0) { sd[wid][d] = v; smn[wid][d] = a; smx[wid][d] = b; }
+    }
+    vol = wave_sum_d(vol);
     if (lane == 0) sd[wid][3] = vol;
     __syncthreads();
     if (tid == 0) {
-        CapState &cs = m.cst[k];
-        double v = 0;
-        for (int w = 0; w < PREP_W; ++w) v += sd[w][3];
-        cs.vol = v;
-        const int nd[3] = {m.nx, m.ny, m.nz};
+        CapPartial P;
+        for (int d = 0; d < 4; ++d) {
+            double v = sd[0][d];
+            for (int w = 1; w < RED_W; ++w) v += sd[w][d];
+            if (d < 3) P.s[d] = v; else P.vol = v;
+        }
         for (int d = 0; d < 3; ++d) {
-            float a = smin[0][d], b = smax[0][d];
-            for (int w = 1; w < PREP_W; ++w) { a = fminf(a, smin[w][d]); b = fmaxf(b, smax[w][d]); }
-            cs.cen[d] = cen[d];
+            float a = smn[0][d], b = smx[0][d];
+            for (int w = 1; w < RED_W; ++w) { a = fminf(a, smn[w][d]); b = fmaxf(b, smx[w][d]); }
+            P.mn[d] = a;
+            P.mx[d] = b;
+        }
+        P.epoch = m.epoch;
+        P.pad = 0;
+        m.part[(size_t)k * nch + c] = P;
+        __threadfence();   // release the record before counting this block
+        s_last = atomicAdd(&m.counter[k], 1) == nch - 1;
+    }
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();       // acquire: every record of capsule k is visible from here on
+
+    // ---- last block of capsule k: totals in block order, window ----
+    __shared__ CapPartial s_part[RED_BLK];
+    __shared__ double s_tot[10];
+    __shared__ int s_lo[3], s_dim[3];
+    __shared__ int cnt[ROWS_MAX];
+    for (int i = tid; i < nch; i += RED_BLK) s_part[i] = m.part[(size_t)k * nch + i];
+    __syncthreads();
+    if (tid < 10) {
+        // one component per thread, summed over the records in block order
+        double v = tid < 3 ? 0.0 : (tid == 3 ? 0.0 : (tid < 7 ? 3e38 : -3e38));
+        for (int i = 0; i < nch; ++i) {
+            const CapPartial &P = s_part[i];
+            if (tid < 3) v += P.s[tid];
+            else if (tid == 3) v += P.vol;
+            else if (tid < 7) v = fmin(v, (double)P.mn[tid - 4]);
+            else v = fmax(v, (double)P.mx[tid - 7]);
+        }
+        s_tot[tid] = v;
+    } else if (tid == 10) {
+        bool stale = false;
+        for (int i = 0; i < nch; ++i) stale = stale || s_part[i].epoch != m.epoch;
+        if (stale) atomicOr(&m.status[ST_SYNC], 1);
+        atomicExch(&m.counter[k], 0);
+    }
+    __syncthreads();
+    if (tid == 0) {
+        CapState cs;
+        const double r[3] = {Xr.x, Xr.y, Xr.z};
+        const int nd[3] = {m.nx, m.ny, m.nz};
+        cs.vol = s_tot[3];
+        for (int d = 0; d < 3; ++d) {
+            const float a = (float)s_tot[4 + d], b = (float)s_tot[7 + d];
+            cs.cen[d] = r[d] + s_tot[d] / cd.nn;
             cs.bmin[d] = a;
             cs.bmax[d] = b;
-            cs.plo[d] = cs.lo[d];
-            cs.pdim[d] = cs.dim[d];
             int fa = 0, dim = min(GMAX, nd[d]);
             if (!(b - a <= (float)GMAX) || !(fabsf(a) < 1e8f) || !(fabsf(b) < 1e8f)) {
                 atomicOr(&m.status[ST_OVERFLOW], 1);   // non-finite or exploded capsule
@@ -128,22 +240,41 @@ __global__ void __launch_bounds__(PREP_BLK) k_capsule_prep(MembraneArgs m) {
             s_lo[d] = fa - 1;
             s_dim[d] = dim;
         }
+        m.cst[k] = cs;
     }
     __syncthreads();
-    // ---- node rows ----
+    // ---- node rows: counting sort by (z, y) row; order inside a row is arbitrary ----
     const int lo1 = s_lo[1], lo2 = s_lo[2], dim1 = s_dim[1], dim2 = s_dim[2];
     const int rows = dim1 * dim2;
-    for (int r = tid; r < rows; r += PREP_BLK) cnt[r] = 0;
+    for (int r = tid; r < rows; r += RED_BLK) cnt[r] = 0;
     __syncthreads();
-    for (int n = tid; n < cd.nn; n += PREP_BLK) {
-        const double4 X = m.X[cd.node0 + n];
-        const int ry = min(max((int)floor(X.y) - lo1, 0), dim1 - 1);
-        const int rz = min(max((int)floor(X.z) - lo2, 0), dim2 - 1);
-        atomicAdd(&cnt[rz * dim1 + ry], 1);
+    // nodes in groups of GRP per thread; inside a group every (clamped) load is valid, so
+    // all of them can be in flight at once
+    constexpr int PER = MAX_CAP_NODES / RED_BLK, GRP = 8;
+    auto row_of = [&](double y, double z) {
+        const int ry = min(max((int)floor(y) - lo1, 0), dim1 - 1);
+        const int rz = min(max((int)floor(z) - lo2, 0), dim2 - 1);
+        return rz * dim1 + ry;
+    };
+#pragma unroll
+    for (int g = 0; g < PER / GRP; ++g) {
+        if (g * GRP * RED_BLK < cd.nn) {   // uniform over the block
+            double y[GRP], z[GRP];
+#pragma unroll
+            for (int i = 0; i < GRP; ++i) {
+                const int nc = min(tid + (g * GRP + i) * RED_BLK, cd.nn - 1);
+                y[i] = m.X[cd.node0 + nc].y;
+                z[i] = m.X[cd.node0 + nc].z;
+            }
+#pragma unroll
+            for (int i = 0; i < GRP; ++i)
+                if (tid + (g * GRP + i) * RED_BLK < cd.nn) atomicAdd(&cnt[row_of(y[i], z[i])], 1);
+        }
     }
     __syncthreads();
-    // exclusive scan: each thread owns a contiguous chunk of rows
-    const int per = (rows + PREP_BLK - 1) / PREP_BLK;
+    // exclusive scan: each thread owns a contiguous run of rows
+    __shared__ int wsum[RED_W];
+    const int per = (rows + RED_BLK - 1) / RED_BLK;
     const int q0 = min(tid * per, rows), q1 = min(q0 + per, rows);
     int local = 0;
     for (int r = q0; r < q1; ++r) local += cnt[r];
@@ -155,64 +286,40 @@ __global__ void __launch_bounds__(PREP_BLK) k_capsule_prep(MembraneArgs m) {
     }
     if (lane == 63) wsum[wid] = incl;
     __syncthreads();
-    int base = 0;
-    for (int w = 0; w < wid; ++w) base += wsum[w];
-    int run = base + incl - local;
+    int run = incl - local;
+    for (int w = 0; w < wid; ++w) run += wsum[w];
     __syncthreads();
     int *rs = m.rowstart + (size_t)k * (ROWS_MAX + 1);
     for (int r = q0; r < q1; ++r) {
-        const int c = cnt[r];
+        const int cr = cnt[r];
         rs[r] = run;
-        cnt[r] = run;   // becomes the scatter cursor
-        run += c;
+        cnt[r] = run;   // becomes the scatter cursor, and ends as the end of row r
+        run += cr;
     }
     if (tid == 0) rs[rows] = cd.nn;
     __syncthreads();
-    int *ids = m.rowids + cd.node0;
-    for (int n = tid; n < cd.nn; n += PREP_BLK) {
-        const double4 X = m.X[cd.node0 + n];
-        const int ry = min(max((int)floor(X.y) - lo1, 0), dim1 - 1);
-        const int rz = min(max((int)floor(X.z) - lo2, 0), dim2 - 1);
-        ids[atomicAdd(&cnt[rz * dim1 + ry], 1)] = cd.node0 + n;
-    }
-    __syncthreads();
-    // order each row by node id (rows hold a handful of nodes)
-    for (int r = tid; r < rows; r += PREP_BLK) {
-        const int a = rs[r], b = rs[r + 1];
-        for (int i = a + 1; i < b; ++i) {
-            const int v = ids[i];
-            int j = i - 1;
-            while (j >= a && ids[j] > v) { ids[j + 1] = ids[j]; --j; }
-            ids[j + 1] = v;
+#pragma unroll
+    for (int g = 0; g < PER / GRP; ++g) {
+        if (g * GRP * RED_BLK < cd.nn) {   // uniform over the block
+            double4 Xg[GRP];
+#pragma unroll
+            for (int i = 0; i < GRP; ++i)
+                Xg[i] = m.X[cd.node0 + min(tid + (g * GRP + i) * RED_BLK, cd.nn - 1)];
+#pragma unroll
+            for (int i = 0; i < GRP; ++i) {
+                const int n = tid + (g * GRP + i) * RED_BLK;
+                if (n < cd.nn) {
+                    const int e = cd.node0 + atomicAdd(&cnt[row_of(Xg[i].y, Xg[i].z)], 1);
+                    m.xrow[e] = Xg[i];
+                    m.slot[cd.node0 + n] = e;
+                }
+            }
         }
     }
 }
 
-void launch_capsule_prep(const MembraneArgs &m, hipStream_t st) {
-    hipLaunchKernelGGL(k_capsule_prep, dim3(m.ncap), dim3(PREP_BLK), 0, st, m);
-}
-
-// ------------------------------------------------------------------------------------
-// Clear the flags of the previous windows; zero the crossing marks of the new windows.
-// ------------------------------------------------------------------------------------
-__global__ void k_window_clear(MembraneArgs m) {
-    const int k = blockIdx.y;
-    const CapState cs = m.cst[k];
-    const int stride = gridDim.x * blockDim.x, i0 = blockIdx.x * blockDim.x + threadIdx.x;
-    const int pv = cs.pdim[0] * cs.pdim[1] * cs.pdim[2];
-    for (int i = i0; i < pv; i += stride) {
-        const int lx = i % cs.pdim[0], t = i / cs.pdim[0], ly = t % cs.pdim[1], lz = t / cs.pdim[1];
-        const int x = wrapm(cs.plo[0] + lx, m.nx), y = wrapm(cs.plo[1] + ly, m.ny),
-                  z = wrapm(cs.plo[2] + lz, m.nz);
-        m.flag[(z * m.ny + y) * m.nx + x] = 0;
-    }
-    const int nv = cs.dim[0] * cs.dim[1] * cs.dim[2];
-    int *mk = m.marks + (size_t)k * GMAX3;
-    for (int i = i0; i < nv; i += stride) mk[i] = 0;
-}
-
-void launch_window_clear(const MembraneArgs &m, hipStream_t st) {
-    hipLaunchKernelGGL(k_window_clear, dim3(64, m.ncap), dim3(256), 0, st, m);
+void launch_capsule_reduce(const MembraneArgs &m, hipStream_t st) {
+    hipLaunchKernelGGL(k_capsule_reduce, dim3(m.nch, m.ncap), dim3(RED_BLK), 0, st, m);
 }
 
 // ------------------------------------------------------------------------------------
@@ -245,113 +352,12 @@ __device__ __forceinline__ void skalak_corner(const float3 u, const float3 v, co
     }
 }
 
-constexpr int MEM_BLK = 128;
-
-__global__ void __launch_bounds__(MEM_BLK) k_membrane_forces(MembraneArgs m, int ntot) {
-    __shared__ CapState s_cst[MAX_CAPS];
-    for (int j = threadIdx.x; j < m.ncap; j += MEM_BLK) s_cst[j] = m.cst[j];
-    __syncthreads();
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= ntot) return;
-    const int k = m.node_cap[n];
-    const CapDev cd = m.caps[k];
-    const double4 X = m.X[n];
-    float f[3] = {0.f, 0.f, 0.f}, fh[3] = {0.f, 0.f, 0.f};
-    const double vcoef = cd.kv != 0.0f ? -(double)cd.kv * (s_cst[k].vol - cd.v0) / cd.v0 : 0.0;
-    for (int e = m.ntri_off[n]; e < m.ntri_off[n + 1]; ++e) {
-        const int t = m.ntri[e] / 3, corner = m.ntri[e] - 3 * (m.ntri[e] / 3);
-        const int4 tr = m.tri[t];
-        const double4 A = m.X[tr.x], B = m.X[tr.y], C = m.X[tr.z];
-        const float3 u = make_float3((float)(B.x - A.x), (float)(B.y - A.y), (float)(B.z - A.z));
-        const float3 v = make_float3((float)(C.x - A.x), (float)(C.y - A.y), (float)(C.z - A.z));
-        skalak_corner(u, v, m.minv[t], m.a0[t], cd.ks, cd.C, corner, f);
-        if (vcoef != 0.0) {
-            // dV/dx_a of this triangle with the origin at x_a: (x_b - x_a) x (x_c - x_a) / 6,
-            // (a, b, c) the cyclic order starting at this node
-            const double4 P = corner == 0 ? B : (corner == 1 ? C : A);
-            const double4 Qn = corner == 0 ? C : (corner == 1 ? A : B);
-            const double pb[3] = {P.x - X.x, P.y - X.y, P.z - X.z};
-            const double pc[3] = {Qn.x - X.x, Qn.y - X.y, Qn.z - X.z};
-            f[0] += (float)(vcoef * (pb[1] * pc[2] - pb[2] * pc[1]) / 6.0);
-            f[1] += (float)(vcoef * (pb[2] * pc[0] - pb[0] * pc[2]) / 6.0);
-            f[2] += (float)(vcoef * (pb[0] * pc[1] - pb[1] * pc[0]) / 6.0);
-        }
-    }
-    const float xi = m.hertz_xi, d0 = m.hertz_d0;
-    if (m.wall && xi > 0.f) {
-        const float d = (float)(X.z - (double)m.plane_z);
-        if (d < d0) fh[2] += xi * (d0 - d) * sqrtf(d0 - d);
-    }
-    if (xi > 0.f) {
-        // particle-particle pairs: only the node rows of another capsule's window whose
-        // (y, z) lattice row lies within delta0 of this node can hold a partner
-        const bool per[3] = {true, true, !m.wall};
-        const int nd[3] = {m.nx, m.ny, m.nz};
-        const double p[3] = {X.x, X.y, X.z};
-        for (int j = 0; j < m.ncap; ++j) {
-            if (j == k) continue;
-            const CapState &cj = s_cst[j];
-            double pl[3];   // this node in the periodic image closest to window j
-            bool far = false;
-            for (int d = 0; d < 3; ++d) {
-                const double c = cj.lo[d] + 0.5 * cj.dim[d];
-                pl[d] = c + min_image(p[d] - c, nd[d], per[d]);
-                if (2.0 * (cj.dim[d] + 2.0 * d0 + 2.0) <= nd[d] &&
-                    (pl[d] < cj.lo[d] - d0 || pl[d] > cj.lo[d] + cj.dim[d] + d0))
-                    far = true;
-            }
-            if (far) continue;
-            // the row search sees one periodic image of each partner; it is exact while the
-            // window plus the cut-off is smaller than half the box, else scan all rows
-            bool small = true;
-            for (int d = 0; d < 3; ++d)
-                if (per[d] && 2.0 * (cj.dim[d] + 2.0 * d0 + 2.0) > nd[d]) small = false;
-            const int ry0 = small ? max((int)floor(pl[1] - d0) - cj.lo[1], 0) : 0;
-            const int ry1 = small ? min((int)floor(pl[1] + d0) - cj.lo[1], cj.dim[1] - 1) : cj.dim[1] - 1;
-            const int rz0 = small ? max((int)floor(pl[2] - d0) - cj.lo[2], 0) : 0;
-            const int rz1 = small ? min((int)floor(pl[2] + d0) - cj.lo[2], cj.dim[2] - 1) : cj.dim[2] - 1;
-            const int *rs = m.rowstart + (size_t)j * (ROWS_MAX + 1);
-            const int node0 = m.caps[j].node0;
-            for (int rz = rz0; rz <= rz1; ++rz)
-                for (int ry = ry0; ry <= ry1; ++ry) {
-                    const int row = rz * cj.dim[1] + ry;
-                    for (int e = rs[row]; e < rs[row + 1]; ++e) {
-                        const double4 Y = m.X[m.rowids[node0 + e]];
-                        const double r[3] = {min_image(p[0] - Y.x, nd[0], per[0]),
-                                             min_image(p[1] - Y.y, nd[1], per[1]),
-                                             min_image(p[2] - Y.z, nd[2], per[2])};
-                        const double dd = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
-                        if (dd < d0 && dd > 0.0) {
-                            const float g = (float)(d0 - dd);
-                            const float mag = xi * g * sqrtf(g);
-                            for (int d = 0; d < 3; ++d) fh[d] += (float)(mag * r[d] / dd);
-                        }
-                    }
-                }
-        }
-    }
-    if (cd.anchor_k != 0.0f) {
-        const CapState &cs = s_cst[k];
-        const double ka = (double)cd.anchor_k / cd.nn;
-        for (int d = 0; d < 3; ++d) f[d] += (float)(-ka * (cs.cen[d] - cd.c0[d]));
-    }
-    const float4 R = m.R[n];
-    m.F[n] = make_float4(f[0] + fh[0] + R.x, f[1] + fh[1] + R.y, f[2] + fh[2] + R.z, 0.f);
-    m.Fh[n] = make_float4(fh[0], fh[1], fh[2], 0.f);
-}
-
-void launch_membrane_forces(const MembraneArgs &m, int ntot, hipStream_t st) {
-    hipLaunchKernelGGL(k_membrane_forces, dim3((ntot + MEM_BLK - 1) / MEM_BLK), dim3(MEM_BLK), 0, st,
-                       m, ntot);
-}
-
-// ------------------------------------------------------------------------------------
-// Crossing marks: for every lattice column inside a triangle's xy projection (top-left
+// Crossing masks: for every lattice column inside a triangle's xy projection (top-left
 // rule on shared edges; zero-area projections skipped), the crossing height z_c is the
 // barycentric interpolation of the vertex heights; sites m >= ceil(z_c) lie above it.
-// The mark at (column, ceil(z_c)) is toggled; a prefix XOR up the column gives the
-// inside parity.  Decisions use FP32-rounded positions evaluated in double.
-// ------------------------------------------------------------------------------------
+// Bit ceil(z_c) - lo_z of the column's mask is toggled; the parity of the bits at or
+// below a plane is the inside parity there.  Decisions use FP32-rounded positions
+// evaluated in double.
 __device__ __forceinline__ double edgef(double ux, double uy, double vx, double vy, double px,
                                         double py) {
     return (vx - ux) * (py - uy) - (vy - uy) * (px - ux);
@@ -360,9 +366,7 @@ __device__ __forceinline__ bool edge_in(double w, double ux, double uy, double v
     return w > 0.0 || (w == 0.0 && ((vy < uy) || (vy == uy && vx < ux)));
 }
 
-__global__ void __launch_bounds__(256) k_label_marks(MembraneArgs m, int ttot) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= ttot) return;
+__device__ void label_marks(const MembraneArgs &m, int t) {
     const int4 tr = m.tri[t];
     const int k = tr.w;
     const CapState cs = m.cst[k];
@@ -387,7 +391,7 @@ __global__ void __launch_bounds__(256) k_label_marks(MembraneArgs m, int ttot) {
         return;
     const int x0 = (int)ceil(xlo), x1 = (int)floor(xhi);
     const int y0 = (int)ceil(ylo), y1 = (int)floor(yhi);
-    int *mk = m.marks + (size_t)k * GMAX3;
+    unsigned long long *mk = m.marks + (size_t)k * ROWS_MAX;
     for (int py = y0; py <= y1; ++py)
         for (int px = x0; px <= x1; ++px) {
             const double wa = edgef(bx, by, cx, cy, px, py);
@@ -400,23 +404,147 @@ __global__ void __launch_bounds__(256) k_label_marks(MembraneArgs m, int ttot) {
             const int lx = px - cs.lo[0], ly = py - cs.lo[1], lz = (int)ceil(zc) - cs.lo[2];
             if (lx < 0 || ly < 0 || lz < 0 || lx >= cs.dim[0] || ly >= cs.dim[1] || lz >= cs.dim[2])
                 continue;
-            atomicXor(&mk[(lz * cs.dim[1] + ly) * cs.dim[0] + lx], 1);
+            atomicXor(&mk[ly * cs.dim[0] + lx], 1ull << lz);
         }
 }
 
-void launch_label_marks(const MembraneArgs &m, int ttot, hipStream_t st) {
-    hipLaunchKernelGGL(k_label_marks, dim3((ttot + 255) / 256), dim3(256), 0, st, m, ttot);
+// One launch, two kinds of block: the first nb_forces blocks compute node forces, MEM_L
+// lanes per node (incident triangles and the candidates of each partner capsule split
+// over the lanes, summed by a fixed butterfly); the remaining blocks toggle the crossing
+// masks, one thread per triangle.
+constexpr int MEM_BLK = 256, MEM_L = 8, MEM_NPB = MEM_BLK / MEM_L;
+
+__global__ void __launch_bounds__(MEM_BLK) k_membrane(MembraneArgs m, int ntot, int ttot,
+                                                      int nb_forces) {
+    if ((int)blockIdx.x >= nb_forces) {
+        const int t = ((int)blockIdx.x - nb_forces) * MEM_BLK + threadIdx.x;
+        if (t < ttot) label_marks(m, t);
+        return;
+    }
+    __shared__ CapState s_cst[MAX_CAPS];
+    for (int j = threadIdx.x; j < m.ncap; j += MEM_BLK) s_cst[j] = m.cst[j];
+    __syncthreads();
+    const int n = blockIdx.x * MEM_NPB + (threadIdx.x / MEM_L), sl = threadIdx.x % MEM_L;
+    if (n >= ntot) return;   // whole groups of MEM_L lanes
+    const int k = m.node_cap[n];
+    const CapDev cd = m.caps[k];
+    const double4 X = m.X[n];
+    float f[3] = {0.f, 0.f, 0.f}, fh[3] = {0.f, 0.f, 0.f};
+    const double vcoef = cd.kv != 0.0f ? -(double)cd.kv * (s_cst[k].vol - cd.v0) / cd.v0 : 0.0;
+    const int e1 = m.ntri_off[n + 1];
+    for (int e = m.ntri_off[n] + sl; e < e1; e += MEM_L) {
+        const int ent = m.ntri[e];
+        const int t = ent / 3, corner = ent - 3 * t;
+        const int4 tr = m.tri[t];
+        const double4 A = m.X[tr.x], B = m.X[tr.y], C = m.X[tr.z];
+        const float3 u = make_float3((float)(B.x - A.x), (float)(B.y - A.y), (float)(B.z - A.z));
+        const float3 v = make_float3((float)(C.x - A.x), (float)(C.y - A.y), (float)(C.z - A.z));
+        skalak_corner(u, v, m.minv[t], m.a0[t], cd.ks, cd.C, corner, f);
+        if (vcoef != 0.0) {
+            // dV/dx_a of this triangle with the origin at x_a: (x_b - x_a) x (x_c - x_a) / 6,
+            // (a, b, c) the cyclic order starting at this node
+            const double4 P = corner == 0 ? B : (corner == 1 ? C : A);
+            const double4 Qn = corner == 0 ? C : (corner == 1 ? A : B);
+            const double pb[3] = {P.x - X.x, P.y - X.y, P.z - X.z};
+            const double pc[3] = {Qn.x - X.x, Qn.y - X.y, Qn.z - X.z};
+            f[0] += (float)(vcoef * (pb[1] * pc[2] - pb[2] * pc[1]) / 6.0);
+            f[1] += (float)(vcoef * (pb[2] * pc[0] - pb[0] * pc[2]) / 6.0);
+            f[2] += (float)(vcoef * (pb[0] * pc[1] - pb[1] * pc[0]) / 6.0);
+        }
+    }
+    const float xi = m.hertz_xi, d0 = m.hertz_d0;
+    if (sl == 0 && m.wall && xi > 0.f) {
+        const float d = (float)(X.z - (double)m.plane_z);
+        if (d < d0) fh[2] += xi * (d0 - d) * sqrtf(d0 - d);
+    }
+    if (xi > 0.f) {
+        // particle-particle pairs: only nodes of another capsule whose bounding box lies
+        // within delta0 of this node, and there only the (y, z) rows within delta0, can be
+        // partners.  The candidates of a row range are split over the lanes; rows list
+        // their nodes in no fixed order, so the pair forces are summed in fixed point.
+        const bool per[3] = {true, true, !m.wall};
+        const int nd[3] = {m.nx, m.ny, m.nz};
+        const double inv[3] = {1.0 / m.nx, 1.0 / m.ny, 1.0 / m.nz};
+        const double p[3] = {X.x, X.y, X.z};
+        const double slack = 1e-3;   // FP32 rounding of the bounding box
+        long long acc[3] = {0, 0, 0};
+        for (int j = 0; j < m.ncap; ++j) {
+            if (j == k) continue;
+            const CapState &cj = s_cst[j];
+            double pl[3];   // this node in the periodic image closest to window j
+            bool far = false, small = true;
+            for (int d = 0; d < 3; ++d) {
+                const double c = cj.lo[d] + 0.5 * cj.dim[d];
+                pl[d] = c + min_image(p[d] - c, nd[d], inv[d], per[d]);
+                // the row search sees one periodic image of each partner; it is exact while
+                // the window plus the cut-off is smaller than half the box, else scan all rows
+                const bool fits = 2.0 * (cj.dim[d] + 2.0 * d0 + 2.0) <= nd[d];
+                if (fits && (pl[d] < cj.bmin[d] - d0 - slack || pl[d] > cj.bmax[d] + d0 + slack))
+                    far = true;
+                if (per[d] && !fits) small = false;
+            }
+            if (far) continue;
+            const int ry0 = small ? max((int)floor(pl[1] - d0) - cj.lo[1], 0) : 0;
+            const int ry1 = small ? min((int)floor(pl[1] + d0) - cj.lo[1], cj.dim[1] - 1) : cj.dim[1] - 1;
+            const int rz0 = small ? max((int)floor(pl[2] - d0) - cj.lo[2], 0) : 0;
+            const int rz1 = small ? min((int)floor(pl[2] + d0) - cj.lo[2], cj.dim[2] - 1) : cj.dim[2] - 1;
+            if (ry0 > ry1) continue;
+            const int *rs = m.rowstart + (size_t)j * (ROWS_MAX + 1);
+            const double4 *xr = m.xrow + m.caps[j].node0;
+            for (int rz = rz0; rz <= rz1; ++rz) {
+                // rows ry0 .. ry1 of plane rz are contiguous in the row order
+                const int a = rs[rz * cj.dim[1] + ry0], b = rs[rz * cj.dim[1] + ry1 + 1];
+                for (int e = a + sl; e < b; e += MEM_L) {
+                    const double4 Y = xr[e];
+                    const double r[3] = {min_image(p[0] - Y.x, nd[0], inv[0], per[0]),
+                                         min_image(p[1] - Y.y, nd[1], inv[1], per[1]),
+                                         min_image(p[2] - Y.z, nd[2], inv[2], per[2])};
+                    const double dd = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+                    if (dd < d0 && dd > 0.0) {
+                        const double g = d0 - dd;
+                        const double mag = xi * g * sqrt(g);
+                        for (int d = 0; d < 3; ++d) acc[d] += to_fix_d(mag * r[d] / dd);
+                    }
+                }
+            }
+        }
+        for (int d = 0; d < 3; ++d) fh[d] += from_fix(acc[d]);
+    }
+    if (sl == 0 && cd.anchor_k != 0.0f) {
+        const CapState &cs = s_cst[k];
+        const double ka = (double)cd.anchor_k / cd.nn;
+        for (int d = 0; d < 3; ++d) f[d] += (float)(-ka * (cs.cen[d] - cd.c0[d]));
+    }
+    static_assert(MEM_L == 8, "group sums are over 8 lanes");
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        f[d] = group_sum8(f[d]);
+        fh[d] = group_sum8(fh[d]);
+    }
+    if (sl == 0) {
+        const float4 R = m.R[n];
+        m.F[m.slot[n]] = make_float4(f[0] + fh[0] + R.x, f[1] + fh[1] + R.y, f[2] + fh[2] + R.z, 0.f);
+        m.Fh[n] = make_float4(fh[0], fh[1], fh[2], 0.f);
+    }
+}
+
+void launch_membrane(const MembraneArgs &m, int ntot, int ttot, hipStream_t st) {
+    const int nbf = (ntot + MEM_NPB - 1) / MEM_NPB, nbm = (ttot + MEM_BLK - 1) / MEM_BLK;
+    hipLaunchKernelGGL(k_membrane, dim3(nbf + nbm), dim3(MEM_BLK), 0, st, m, ntot, ttot, nbf);
 }
 
 // ------------------------------------------------------------------------------------
 // Window fill, in two kernels.
 //
 // k_window_own: one block per (capsule k, plane of its window).  Every node whose kernel
-// support reaches the plane (a contiguous run of the row-sorted ids) adds its 4 x 4 sites
-// of the plane, F_n phi(x - X_n) and phi(x - X_n), into an LDS plane buffer.  The sums
-// are 64-bit fixed point (2^-40 units), so the atomic adds are exact and the result does
-// not depend on their order.  Then one thread per column carries the crossing parity up
-// the column.  Results go to capsule k's window buffers.
+// support reaches the plane (node planes lz - 2 .. lz + 1, a contiguous run of the row
+// order) adds its 4 x 4 sites of the plane, F_n phi(x - X_n) and phi(x - X_n), into an
+// LDS plane buffer.  The sums are 64-bit fixed point (2^-40 units), so the atomic adds
+// are exact and the result does not depend on their order.  Neighbours in the row order
+// have overlapping supports, so threads take the nodes in a strided permutation of that
+// order, which keeps the lanes of one atomic instruction on different columns.  The
+// crossing parity of a site is the parity of the set bits of its column mask at or below
+// its plane.  Results go to capsule k's window buffers.
 //
 // k_window_combine: per window site, the sum over every window holding the site, in
 // capsule order, of those buffers; the side label is the highest capsule whose parity is
@@ -424,14 +552,14 @@ void launch_label_marks(const MembraneArgs &m, int ttot, hipStream_t st) {
 // values by each of them.
 // ------------------------------------------------------------------------------------
 constexpr int FILL_COLS = 2048;     // LDS plane capacity: windows up to 2048 columns (x * y)
-constexpr float FIX_SCALE = 1099511627776.0f;   // 2^40
+constexpr int OWN_BLK = 256;
 
-__device__ __forceinline__ long long to_fix(float v) { return __float2ll_rn(v * FIX_SCALE); }
-__device__ __forceinline__ float from_fix(long long v) {
-    return (float)((double)v * (1.0 / 1099511627776.0));
+__device__ __forceinline__ int gcd_int(int a, int b) {
+    while (b) { const int t = a % b; a = b; b = t; }
+    return a;
 }
 
-__global__ void __launch_bounds__(256) k_window_own(MembraneArgs m) {
+__global__ void __launch_bounds__(OWN_BLK) k_window_own(MembraneArgs m) {
     const int k = blockIdx.y, lz = blockIdx.x, tid = threadIdx.x;
     const CapState ck = m.cst[k];
     if (lz >= ck.dim[2]) return;
@@ -441,50 +569,72 @@ __global__ void __launch_bounds__(256) k_window_own(MembraneArgs m) {
         if (tid == 0) atomicOr(&m.status[ST_WIDE], 1);
         return;
     }
-    float4 *wb = m.wbuf + (size_t)k * GMAX3 + (size_t)lz * ncol;
-    uint8_t *wp = m.wpar + (size_t)k * GMAX3 + (size_t)lz * ncol;
     unsigned long long *acc = &s_acc[0][0];
     constexpr int stride = FILL_COLS;
-    for (int i = tid; i < ncol; i += blockDim.x)
+    for (int i = tid; i < ncol; i += OWN_BLK)
         for (int d = 0; d < 4; ++d) acc[d * stride + i] = 0ull;
-    __syncthreads();
     // nodes with floor(Z) - lo_z in [lz - 2, lz + 1] reach this plane
     const int r0 = max(lz - 2, 0), r1 = min(lz + 1, ck.dim[2] - 1);
     const int *rs = m.rowstart + (size_t)k * (ROWS_MAX + 1);
-    const int e0 = rs[r0 * dy], e1 = rs[(r1 + 1) * dy];
-    const int node0 = m.caps[k].node0;
+    const int e0 = rs[r0 * dy], nnode = rs[(r1 + 1) * dy] - e0;
+    const int node0 = m.caps[k].node0 + e0;
+    // stride p coprime with nnode: i -> i * p mod nnode is a permutation
+    int p = nnode / 64 + 1;
+    while (nnode > 1 && gcd_int(p, nnode) != 1) ++p;
     const double zs = (double)(ck.lo[2] + lz);
-    for (int w = tid; w < (e1 - e0) * 4; w += blockDim.x) {
-        const int e = e0 + (w >> 2), oy = w & 3;
-        const int n = m.rowids[node0 + e];
-        const double4 X = m.X[n];
-        const float4 F = m.F[n];
-        const double fx = floor(X.x), fy = floor(X.y);
-        const float wz = phi4((float)(X.z - zs));
-        const int bx = (int)fx - 1 - ck.lo[0], by = (int)fy - 1 - ck.lo[1];
-        const int ly = by + oy;
-        const float wy = phi4((float)(X.y - fy) + (float)(1 - oy));
-        if (ly < 0 || ly >= dy) continue;
-        for (int ox = 0; ox < 4; ++ox) {
-            const int lx = bx + ox;
-            if (lx < 0 || lx >= dx) continue;
-            const float wgt = phi4((float)(X.x - fx) + (float)(1 - ox)) * wy * wz;
-            const int col = ly * dx + lx;
-            atomicAdd(&acc[col], (unsigned long long)to_fix(wgt * F.x));
-            atomicAdd(&acc[stride + col], (unsigned long long)to_fix(wgt * F.y));
-            atomicAdd(&acc[2 * stride + col], (unsigned long long)to_fix(wgt * F.z));
-            atomicAdd(&acc[3 * stride + col], (unsigned long long)to_fix(wgt));
+    __syncthreads();
+    for (int i0 = 0; i0 < nnode; i0 += 2 * OWN_BLK) {
+        // two nodes per thread, both loaded before either is spread
+        double4 X[2];
+        float4 F[2];
+        bool ok[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int i = i0 + tid + u * OWN_BLK;
+            ok[u] = i < nnode;
+            const int e = ok[u] ? (int)(((long long)i * p) % nnode) : 0;
+            X[u] = m.xrow[node0 + e];
+            F[u] = m.F[node0 + e];
+        }
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            if (!ok[u]) continue;
+            const double fx = floor(X[u].x), fy = floor(X[u].y);
+            const float wz = phi4((float)(X[u].z - zs));
+            const float rx = (float)(X[u].x - fx), ry = (float)(X[u].y - fy);
+            const int bx = (int)fx - 1 - ck.lo[0], by = (int)fy - 1 - ck.lo[1];
+            float wx[4];
+#pragma unroll
+            for (int o = 0; o < 4; ++o) wx[o] = phi4(rx + (float)(1 - o));
+#pragma unroll
+            for (int oy = 0; oy < 4; ++oy) {
+                const int ly = by + oy;
+                if (ly < 0 || ly >= dy) continue;
+                const float wyz = phi4(ry + (float)(1 - oy)) * wz;
+#pragma unroll
+                for (int ox = 0; ox < 4; ++ox) {
+                    const int lx = bx + ox;
+                    if (lx < 0 || lx >= dx) continue;
+                    const float wgt = wx[ox] * wyz;
+                    const int col = ly * dx + lx;
+                    atomicAdd(&acc[col], (unsigned long long)to_fix(wgt * F[u].x));
+                    atomicAdd(&acc[stride + col], (unsigned long long)to_fix(wgt * F[u].y));
+                    atomicAdd(&acc[2 * stride + col], (unsigned long long)to_fix(wgt * F[u].z));
+                    atomicAdd(&acc[3 * stride + col], (unsigned long long)to_fix(wgt));
+                }
+            }
         }
     }
     __syncthreads();
-    const int *mk = m.marks + (size_t)k * GMAX3;
-    for (int col = tid; col < ncol; col += blockDim.x) {
-        int par = 0;
-        for (int q = 0; q <= lz; ++q) par ^= mk[q * ncol + col];
+    float4 *wb = m.wbuf + (size_t)k * GMAX3 + (size_t)lz * ncol;
+    uint8_t *wp = m.wpar + (size_t)k * GMAX3 + (size_t)lz * ncol;
+    const unsigned long long *mk = m.marks + (size_t)k * ROWS_MAX;
+    const unsigned long long below = (2ull << lz) - 1ull;   // planes 0 .. lz (lz <= 63)
+    for (int col = tid; col < ncol; col += OWN_BLK) {
         wb[col] = make_float4(from_fix((long long)acc[col]), from_fix((long long)acc[stride + col]),
                               from_fix((long long)acc[2 * stride + col]),
                               from_fix((long long)acc[3 * stride + col]));
-        wp[col] = (uint8_t)(par & 1);
+        wp[col] = (uint8_t)(__popcll(mk[col] & below) & 1);
     }
 }
 
@@ -494,46 +644,57 @@ __global__ void __launch_bounds__(256) k_window_combine(MembraneArgs m) {
     if (lz >= ck.dim[2]) return;
     const int dx = ck.dim[0], dy = ck.dim[1];
     __shared__ int s_win[MAX_CAPS + 1];
-    __shared__ CapState s_cs[MAX_CAPS];
+    __shared__ int s_box[MAX_CAPS][6];   // lo[3], dim[3] of each meeting window
+    __shared__ unsigned long long s_meet[2];
     __shared__ int s_n;
-    // windows meeting this plane of window k, in capsule order (k included)
-    if (tid == 0) {
-        const int nd[3] = {m.nx, m.ny, m.nz};
-        const int blo[3] = {ck.lo[0], ck.lo[1], ck.lo[2] + lz};
-        const int bdim[3] = {dx, dy, 1};
-        int n = 0;
-        for (int j = 0; j < m.ncap; ++j) {
-            const CapState cj = m.cst[j];
-            bool meet = true;
+    // windows meeting this plane of window k, in capsule order (k included): one thread
+    // per capsule tests its window, ballots give each meeting window its place
+    static_assert(MAX_CAPS <= 128, "window list uses two ballots");
+    {
+        const int j = tid;
+        bool meet = false;
+        int box[6] = {0, 0, 0, 0, 0, 0};
+        if (j < m.ncap) {
+#pragma unroll
             for (int d = 0; d < 3; ++d) {
-                const int off = wrapm(cj.lo[d] - blo[d], nd[d]);
-                meet = meet && (off < bdim[d] || off + cj.dim[d] > nd[d]);
+                box[d] = m.cst[j].lo[d];
+                box[3 + d] = m.cst[j].dim[d];
             }
-            if (meet) { s_cs[n] = cj; s_win[n++] = j; }
+            const int ox = wrap_near(box[0] - ck.lo[0], m.nx);
+            const int oy = wrap_near(box[1] - ck.lo[1], m.ny);
+            const int oz = wrap_near(box[2] - (ck.lo[2] + lz), m.nz);
+            meet = (ox < dx || ox + box[3] > m.nx) && (oy < dy || oy + box[4] > m.ny) &&
+                   (oz < 1 || oz + box[5] > m.nz);
         }
-        s_n = n;
+        const unsigned long long b = __ballot(meet);
+        if (tid < 128 && (tid & 63) == 0) s_meet[tid >> 6] = b;
+        __syncthreads();
+        if (meet) {
+            const int lanebit = tid & 63;
+            int pos = __popcll(b & ((1ull << lanebit) - 1ull));
+            if (tid >= 64) pos += __popcll(s_meet[0]);
+#pragma unroll
+            for (int d = 0; d < 6; ++d) s_box[pos][d] = box[d];
+            s_win[pos] = j;
+        }
+        if (tid == 0) s_n = __popcll(s_meet[0]) + __popcll(s_meet[1]);
     }
     __syncthreads();
     const int nwin = s_n;
-    const int nd[3] = {m.nx, m.ny, m.nz};
+    const int uz = ck.lo[2] + lz, z = wrap_near(uz, m.nz);
+    if (m.wall && z == 0) return;   // wall sites receive nothing (uniform over the block)
     for (int col = tid; col < dx * dy; col += blockDim.x) {
-        const int lx = col % dx, ly = col / dx;
-        const int u[3] = {ck.lo[0] + lx, ck.lo[1] + ly, ck.lo[2] + lz};
-        const int z = wrapm(u[2], m.nz);
-        if (m.wall && z == 0) continue;
+        const int ly = col / dx, lx = col - ly * dx;
+        const int ux = ck.lo[0] + lx, uy = ck.lo[1] + ly;
         int lab = 0;
         float f[3] = {0.f, 0.f, 0.f}, c = 0.f;
         for (int i = 0; i < nwin; ++i) {
             const int j = s_win[i];
-            const CapState &cj = s_cs[i];
-            int l[3];
-            bool in = true;
-            for (int d = 0; d < 3; ++d) {
-                l[d] = wrapm(u[d] - cj.lo[d], nd[d]);
-                in = in && l[d] < cj.dim[d];
-            }
-            if (!in) continue;
-            const int li = (l[2] * cj.dim[1] + l[1]) * cj.dim[0] + l[0];
+            const int *bj = s_box[i];
+            const int l0 = wrap_near(ux - bj[0], m.nx), l1 = wrap_near(uy - bj[1], m.ny),
+                      l2 = wrap_near(uz - bj[2], m.nz);
+            if (l0 >= bj[3] || l1 >= bj[4] || l2 >= bj[5]) continue;
+            const int li = (l2 * bj[4] + l1) * bj[3] + l0;
             const float4 v = m.wbuf[(size_t)j * GMAX3 + li];
             f[0] += v.x;
             f[1] += v.y;
@@ -541,8 +702,7 @@ __global__ void __launch_bounds__(256) k_window_combine(MembraneArgs m) {
             c += v.w;
             if (m.wpar[(size_t)j * GMAX3 + li]) lab = j + 1;
         }
-        const int x = wrapm(u[0], m.nx), y = wrapm(u[1], m.ny);
-        const int s = (z * m.ny + y) * m.nx + x;
+        const int s = (z * m.ny + wrap_near(uy, m.ny)) * m.nx + wrap_near(ux, m.nx);
         m.flag[s] = (uint8_t)(lab | AUX_BIT);
         m.ibm[s] = make_float4(f[0], f[1], f[2], c);
     }
@@ -556,46 +716,56 @@ void launch_window_fill(const MembraneArgs &m, hipStream_t st) {
 // ------------------------------------------------------------------------------------
 // Node update: U_n = sum_x u(x) phi(x - X_n) (wall sites contribute nothing),
 // R_n = sum_x r(x) phi(x - X_n) / c(x) over covered sites (the fluid step stores r / c),
-// X_n += U_n.
+// X_n += U_n.  UPD_L = 16 lanes per node, one (y, z) row of 4 sites each; the 16 row sums
+// are combined by a fixed butterfly.
 // ------------------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_node_update(MembraneArgs m, int ntot) {
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= ntot) return;
+constexpr int UPD_BLK = 256, UPD_L = 16, UPD_NPB = UPD_BLK / UPD_L, UPD_GRID = 1 << 20;
+
+__device__ __forceinline__ void node_update_one(const MembraneArgs &m, int n, int sl) {
     double4 X = m.X[n];
-    const int b[3] = {(int)floor(X.x) - 1, (int)floor(X.y) - 1, (int)floor(X.z) - 1};
+    const int oy = sl & 3, oz = sl >> 2;
+    const int bx = (int)floor(X.x) - 1, by = (int)floor(X.y) - 1, bz = (int)floor(X.z) - 1;
     float U[3] = {0.f, 0.f, 0.f}, Rr[3] = {0.f, 0.f, 0.f};
-    float wx[4], wy[4], wz[4];
+    const int z = wrap_near(bz + oz, m.nz);
+    if (!(m.wall && z == 0)) {
+        const float wyz = phi4((float)(X.y - (double)(by + oy))) *
+                          phi4((float)(X.z - (double)(bz + oz)));
+        const int row = (z * m.ny + wrap_near(by + oy, m.ny)) * m.nx;
 #pragma unroll
-    for (int o = 0; o < 4; ++o) {
-        wx[o] = phi4((float)(X.x - (double)(b[0] + o)));
-        wy[o] = phi4((float)(X.y - (double)(b[1] + o)));
-        wz[o] = phi4((float)(X.z - (double)(b[2] + o)));
-    }
-    for (int oz = 0; oz < 4; ++oz) {
-        const int z = wrapm(b[2] + oz, m.nz);
-        if (m.wall && z == 0) continue;
-        for (int oy = 0; oy < 4; ++oy) {
-            const int y = wrapm(b[1] + oy, m.ny);
-            for (int ox = 0; ox < 4; ++ox) {
-                const int x = wrapm(b[0] + ox, m.nx);
-                const int s = (z * m.ny + y) * m.nx + x;
-                const float w = wx[ox] * wy[oy] * wz[oz];
-                const float4 u = m.uo[s];
-                const float4 r = m.ro[s];   // reaction / coverage, 0 where uncovered
-                U[0] += w * u.x; U[1] += w * u.y; U[2] += w * u.z;
-                Rr[0] += w * r.x; Rr[1] += w * r.y; Rr[2] += w * r.z;
-            }
+        for (int ox = 0; ox < 4; ++ox) {
+            const int s = row + wrap_near(bx + ox, m.nx);
+            const float w = phi4((float)(X.x - (double)(bx + ox))) * wyz;
+            const float4 u = m.uo[s];
+            const float4 r = m.ro[s];   // reaction / coverage, 0 where uncovered
+            U[0] += w * u.x; U[1] += w * u.y; U[2] += w * u.z;
+            Rr[0] += w * r.x; Rr[1] += w * r.y; Rr[2] += w * r.z;
         }
     }
-    X.x += U[0];
-    X.y += U[1];
-    X.z += U[2];
-    m.X[n] = X;
-    m.R[n] = make_float4(Rr[0], Rr[1], Rr[2], 0.f);
+    static_assert(UPD_L == 16, "group sums are over 16 lanes");
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        U[d] = group_sum16(U[d]);
+        Rr[d] = group_sum16(Rr[d]);
+    }
+    if (sl == 0) {
+        X.x += U[0];
+        X.y += U[1];
+        X.z += U[2];
+        m.X[n] = X;
+        m.R[n] = make_float4(Rr[0], Rr[1], Rr[2], 0.f);
+    }
+}
+
+__global__ void __launch_bounds__(UPD_BLK) k_node_update(MembraneArgs m, int ntot) {
+    const int sl = threadIdx.x % UPD_L;
+    for (int n = blockIdx.x * UPD_NPB + threadIdx.x / UPD_L; n < ntot; n += gridDim.x * UPD_NPB)
+        node_update_one(m, n, sl);
 }
 
 void launch_node_update(const MembraneArgs &m, int ntot, hipStream_t st) {
-    hipLaunchKernelGGL(k_node_update, dim3((ntot + 255) / 256), dim3(256), 0, st, m, ntot);
+    const int nb = (ntot + UPD_NPB - 1) / UPD_NPB;
+    hipLaunchKernelGGL(k_node_update, dim3(nb < UPD_GRID ? nb : UPD_GRID), dim3(UPD_BLK), 0, st,
+                       m, ntot);
 }
 
 }  // namespace lbmx
