@@ -24,19 +24,25 @@ PEAK_HBM_GBS = 8000.0
 # HBM bytes per launch of the fused fluid kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE,
 # scaled by the same counters on a plain 1 GiB copy (profiles/fluid_c3_f32_hbm_traffic.md),
 # keyed by (storage, tile, zchunk).  Reported only for the launch shape it was taken on.
-MEASURED_TRAFFIC_BYTES = {("f32", 10, 48): 2.1185e9}
+MEASURED_TRAFFIC_BYTES = {("f32", 10, 48): 2.0565e9}
 WORKLOAD = "film 256x256x96, wall, 16 capsules R=10 (5120 tri), ks=0.05"
 
 
 TILES = {1: "32x8", 2: "64x4", 3: "32x16", 4: "64x8", 5: "16x16", 6: "pipe32x8",
-         7: "pipe64x4", 8: "pipe16x16", 9: "pipe32x16", 10: "pipe64x8"}
+         7: "pipe64x4", 8: "pipe16x16", 9: "pipe32x16", 10: "pipe64x8", 11: "rows256x2",
+         12: "rows128x4"}
 
 
-def tune(sim, steps=10):
-    """Launch-shape autotuner: time the fused fluid kernel for every tile shape and a
-    few z-chunk depths with HIP events, keep the fastest."""
+def applicable(tile, nx):
+    """Whole-row tiles need nx equal to their width (the library falls back to 64x8)."""
+    return {11: nx == 256, 12: nx == 128}.get(tile, True)
+
+
+def tune(sim, nx, steps=10):
+    """Launch-shape autotuner: time the fused fluid kernel for every tile shape that
+    applies to this box and a few z-chunk depths with HIP events, keep the fastest."""
     best = None
-    for tile in TILES:
+    for tile in (t for t in TILES if applicable(t, nx)):
         for zc in (0, 8, 12, 16, 24, 32, 48):
             sim.set_launch(tile, zc)
             sim.step(2)
@@ -61,7 +67,7 @@ def run_gpu(cfg, storage, steps, warmup, do_tune=True, launch=None):
 
     sim = Sim(cfg, storage=storage, stream="torch")
     stream = torch.cuda.current_stream()
-    tuned = tune(sim) if do_tune else None
+    tuned = tune(sim, cfg["nx"]) if do_tune else None
     if launch is not None:
         sim.set_launch(*launch)
         tuned = dict(tile=TILES.get(launch[0], "two-kernel"), tile_id=launch[0], zchunk=launch[1])

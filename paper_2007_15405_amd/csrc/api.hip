@@ -489,8 +489,8 @@ static FluidArgs fluid_args(lbm_handle *h) {
     return a;
 }
 
-static const int TILE_X[11] = {0, 32, 64, 32, 64, 16, 32, 64, 16, 32, 64},
-                 TILE_Y[11] = {0, 8, 4, 16, 8, 16, 8, 4, 16, 16, 8};
+static const int TILE_X[13] = {0, 32, 64, 32, 64, 16, 32, 64, 16, 32, 64, 256, 128},
+                 TILE_Y[13] = {0, 8, 4, 16, 8, 16, 8, 4, 16, 16, 8, 2, 4};
 
 // z planes per workgroup: enough workgroups to fill the chip (about 1024), at least 4
 // planes so the two extra halo planes stay a small share
@@ -506,7 +506,7 @@ static int zchunk_of(const lbm_handle *h) {
 
 extern "C" lbm_status lbm_set_launch(lbm_handle *h, int32_t tile, int32_t zchunk) {
     if (!h) return LBM_E_INVAL;
-    if (tile < 0 || tile > 10 || zchunk < 0) return fail(h, LBM_E_INVAL, "invalid launch shape");
+    if (tile < 0 || tile > 12 || zchunk < 0) return fail(h, LBM_E_INVAL, "invalid launch shape");
     h->tile = tile;
     h->zchunk = zchunk;
     return LBM_OK;

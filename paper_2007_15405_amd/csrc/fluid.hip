@@ -51,13 +51,18 @@ template <int S> struct Pop {
             return Codec<S>::dec(__builtin_bit_cast(T, v), sh);
         }
     }
+    // stores are non-temporal: the new state is not read again in this step, and keeping
+    // it out of L2 leaves room for the source rows that neighbouring tiles pull again
+    static constexpr int STORE_NT = 2;
     __device__ static inline void store(void *f, int qg, int N, uint32_t site, float v, float sh) {
         const __amdgpu_buffer_rsrc_t r = res(f, qg, N);
         const T e = Codec<S>::enc(v, sh);
         if constexpr (sizeof(T) == 4)
-            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, e), r, site * 4u, 0, 0);
+            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, e), r, site * 4u, 0,
+                                                  STORE_NT);
         else
-            __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, e), r, site * 2u, 0, 0);
+            __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, e), r, site * 2u, 0,
+                                                  STORE_NT);
     }
 };
 
@@ -508,6 +513,12 @@ __global__ void __launch_bounds__(TX * TY) k_fused(FluidArgs a, int zc, int tile
 // folds them into moments and psi of plane p+2.  A four-plane LDS ring (p-1 .. p+2)
 // needs one barrier per plane; whether a plane holds any label, window or wall is
 // reduced per wave with a ballot and published next to the ring.
+//
+// WX: the tile spans whole rows (TX == nx).  The x wrap then stays inside the tile: the
+// halo is the two neighbouring rows only (one site per thread), and the ring columns -1
+// and TX are copies of columns TX - 1 and 0.  Whole rows also make every store of a
+// plane a run of TX * 4 contiguous bytes per population, which the memory system
+// serves better than shorter runs.
 // ------------------------------------------------------------------------------------
 template <int S>
 __device__ __forceinline__ void collide_store_eq(const FluidArgs &a, const float (&m)[8],
@@ -572,10 +583,11 @@ __device__ __forceinline__ void collide_store_eq(const FluidArgs &a, const float
         atomicAdd(&a.status[ST_LOST], 1);
 }
 
-template <int S, int TX, int TY>
+template <int S, int TX, int TY, bool WX>
 __global__ void __launch_bounds__(TX * TY) k_fused_pipe(FluidArgs a, int zc, int tiles_x,
                                                         int tiles_y, int nblocks) {
-    constexpr int NT = TX * TY, LX = TX + 2, LY = TY + 2, NL = LX * LY, NH = NL - NT;
+    constexpr int NT = TX * TY, LX = TX + 2, LY = TY + 2, NL = LX * LY;
+    constexpr int NH = WX ? 2 * TX : NL - NT;
     constexpr int NW = NT / 64;
     static_assert(NH <= NT && NT % 64 == 0, "tile shape");
     __shared__ float s_psi[4][2][NL];
@@ -599,13 +611,18 @@ __global__ void __launch_bounds__(TX * TY) k_fused_pipe(FluidArgs a, int zc, int
     int hi = -1, hx = 0, hy = 0;
     if (tid < NH) {
         int h = tid;
-        if (h < LX) { hx = h - 1; hy = -1; }
+        if (WX) { hx = h % TX; hy = h < TX ? -1 : TY; }
+        else if (h < LX) { hx = h - 1; hy = -1; }
         else if (h < 2 * LX) { hx = h - LX - 1; hy = TY; }
         else { h -= 2 * LX; hy = h >> 1; hx = (h & 1) ? TX : -1; }
         hi = (hy + 1) * LX + (hx + 1);
         hx = wrapn(x0 + hx, nx);
         hy = wrapn(y0 + hy, ny);
     }
+    // WX: ring positions that also hold this thread's value (the wrapped columns)
+    const int li_w = !WX ? -1 : (lx == TX - 1 ? li - TX : (lx == 0 ? li + TX : -1));
+    const int hi_w = !WX || hi < 0 ? -1
+                                   : ((hi % LX) == TX ? hi - TX : ((hi % LX) == 1 ? hi + TX : -1));
 
     for (int i = tid; i < MAX_CAPS; i += NT) s_drho[i] = a.cap_drho[i];
 
@@ -627,15 +644,27 @@ __global__ void __launch_bounds__(TX * TY) k_fused_pipe(FluidArgs a, int zc, int
             for (int i = 0; i < 8; ++i) m[i] = 0.f;
         }
         const uint8_t fg_me = solid ? WALL_FLAG : fl_me;
-        s_psi[slot][0][li] = psi_of(r0, a.inv_rho0);
-        s_psi[slot][1][li] = psi_of(r1, a.inv_rho0);
+        const float ps0 = psi_of(r0, a.inv_rho0), ps1 = psi_of(r1, a.inv_rho0);
+        s_psi[slot][0][li] = ps0;
+        s_psi[slot][1][li] = ps1;
         s_flag[slot][li] = fg_me;
+        if (WX && li_w >= 0) {
+            s_psi[slot][0][li_w] = ps0;
+            s_psi[slot][1][li_w] = ps1;
+            s_flag[slot][li_w] = fg_me;
+        }
         uint8_t fg_h = 0;
         if (hi >= 0) {
             fg_h = solid ? WALL_FLAG : fl_h;
-            s_psi[slot][0][hi] = psi_of(h0, a.inv_rho0);
-            s_psi[slot][1][hi] = psi_of(h1, a.inv_rho0);
+            const float hp0 = psi_of(h0, a.inv_rho0), hp1 = psi_of(h1, a.inv_rho0);
+            s_psi[slot][0][hi] = hp0;
+            s_psi[slot][1][hi] = hp1;
             s_flag[slot][hi] = fg_h;
+            if (WX && hi_w >= 0) {
+                s_psi[slot][0][hi_w] = hp0;
+                s_psi[slot][1][hi_w] = hp1;
+                s_flag[slot][hi_w] = fg_h;
+            }
         }
         const bool any = __builtin_amdgcn_ballot_w64((fg_me | fg_h) != 0) != 0;
         if (lane == 0) s_busy[slot][wave] = any ? 1 : 0;
@@ -680,6 +709,8 @@ __global__ void __launch_bounds__(TX * TY) k_fused_pipe(FluidArgs a, int zc, int
         const int cz = wrapn(p, nz);
         if (valid && !(a.wall && cz == 0)) {
             const int sc = (p - z0 + 4) & 3, su = (p - z0 + 5) & 3, sd = (p - z0 + 3) & 3;
+            // the tile-plane takes the general path if any label, window or wall flag lies
+            // in its ring planes p - 1 .. p + 1 (all waves meet at the same barrier anyway)
             int busy = 0;
 #pragma unroll
             for (int w = 0; w < NW; ++w) busy |= s_busy[sc][w] | s_busy[su][w] | s_busy[sd][w];
@@ -726,13 +757,13 @@ __global__ void __launch_bounds__(TX * TY) k_fused_pipe(FluidArgs a, int zc, int
     (void)m2;
 }
 
-template <int S, int TX, int TY>
+template <int S, int TX, int TY, bool WX = false>
 static void launch_pipe_t(const FluidArgs &a, int zc, hipStream_t st) {
     const int tx = (a.nx + TX - 1) / TX, ty = (a.ny + TY - 1) / TY, tz = (a.nz + zc - 1) / zc;
     const int nb = tx * ty * tz;
     const int grid = (nb + 7) / 8 * 8;
-    hipLaunchKernelGGL((k_fused_pipe<S, TX, TY>), dim3(grid), dim3(TX * TY), 0, st, a, zc, tx, ty,
-                       nb);
+    hipLaunchKernelGGL((k_fused_pipe<S, TX, TY, WX>), dim3(grid), dim3(TX * TY), 0, st, a, zc, tx,
+                       ty, nb);
 }
 
 template <int S, int TX, int TY>
@@ -748,7 +779,9 @@ static void launch_fused_t(const FluidArgs &a, int zc, hipStream_t st) {
                            tx, ty, nb);
 }
 
-// tile: 0 two-kernel variant; 1: 32x8; 2: 64x4; 3: 32x16; 4: 64x8; 5: 16x16
+// tile: 0 two-kernel variant; 1: 32x8; 2: 64x4; 3: 32x16; 4: 64x8; 5: 16x16; 6-10: the
+// pipelined kernel with 32x8, 64x4, 16x16, 32x16, 64x8; 11: whole rows 256x2; 12: whole
+// rows 128x4
 template <int S>
 void launch_fluid_tiled(const FluidArgs &a, int tile, int zc, hipStream_t st) {
     switch (tile) {
@@ -762,6 +795,17 @@ void launch_fluid_tiled(const FluidArgs &a, int tile, int zc, hipStream_t st) {
         case 8: if (a.keepf) launch_fused_t<S, 16, 16>(a, zc, st); else launch_pipe_t<S, 16, 16>(a, zc, st); break;
         case 9: if (a.keepf) launch_fused_t<S, 32, 16>(a, zc, st); else launch_pipe_t<S, 32, 16>(a, zc, st); break;
         case 10: if (a.keepf) launch_fused_t<S, 64, 8>(a, zc, st); else launch_pipe_t<S, 64, 8>(a, zc, st); break;
+        // whole-row tiles: need nx equal to the tile width, else the 64 x 8 tile is used
+        case 11:
+            if (a.keepf) launch_fused_t<S, 64, 8>(a, zc, st);
+            else if (a.nx == 256) launch_pipe_t<S, 256, 2, true>(a, zc, st);
+            else launch_pipe_t<S, 64, 8>(a, zc, st);
+            break;
+        case 12:
+            if (a.keepf) launch_fused_t<S, 64, 8>(a, zc, st);
+            else if (a.nx == 128) launch_pipe_t<S, 128, 4, true>(a, zc, st);
+            else launch_pipe_t<S, 64, 8>(a, zc, st);
+            break;
         default: launch_fluid<S>(a, st); break;
     }
 }

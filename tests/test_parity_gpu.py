@@ -211,16 +211,24 @@ def test_film_drying_box_two_capsules():
         assert np.linalg.norm(fa_g - fa_o) <= 1e-3 * max(np.linalg.norm(fa_o), 1e-4)
 
 
-@pytest.mark.parametrize("name", ["pf", "ragged", "c3"])
+@pytest.mark.parametrize("name", ["pf", "ragged", "rows128", "rows256", "c3"])
 def test_fused_kernel_matches_two_kernel_variant(name):
     """Every launch shape of the fused fluid kernel computes the same per-site arithmetic
-    as the two-kernel variant: results agree to rounding (bit-exact in practice)."""
+    as the two-kernel variant: results agree to rounding (bit-exact in practice).  The
+    rows cases have nx equal to a whole-row tile width and a y extent that is not a
+    multiple of the tile height, with a capsule across the periodic x boundary."""
     if name == "ragged":
         rho = synth.noise_rho(19, 13, 11, (0.7, 0.04), 0.01, seed=3)
         cfg = synth.workload("pf", nx=19, ny=13, nz=11, wall_z0=0, init_mode=2,
                              init_rho_array=rho,
                              capsules=[synth.capsule((0.6, 12.4, 5.3), 3.0, 320, 0.02)])
         steps = 60
+    elif name in ("rows128", "rows256"):
+        nx, ny = (128, 18) if name == "rows128" else (256, 11)
+        cfg = synth.workload("pf", nx=nx, ny=ny, nz=14, film_height=5,
+                             capsules=[synth.capsule((1.3, 4.2, 6.1), 3.0, 320, 0.02,
+                                                     wet_drho=0.05)])
+        steps = 40
     else:
         cfg = synth.workload(name)
         steps = 60 if name == "pf" else 3
@@ -229,7 +237,7 @@ def test_fused_kernel_matches_two_kernel_variant(name):
     ref.set_launch(0)
     ref.step(steps)
     r0 = ref.rho()
-    for tile in range(1, 11):
+    for tile in range(1, 13):
         for zc in (0, 5):
             g = _sim(cfg)
             g.set_launch(tile, zc)
