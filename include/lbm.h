@@ -177,8 +177,10 @@ lbm_status lbm_labels(lbm_handle *h, uint8_t *out);
 lbm_status lbm_save(lbm_handle *h, const char *path);
 lbm_status lbm_load(lbm_handle *h, const char *path);
 
-/* Per-kernel event timing of later steps (on: 1).  lbm_kernel_stats copies up to max
- * entries and returns their number in *n (synchronises). */
+/* Event timing of later steps on the handle's stream: on = 1 brackets every kernel,
+ * on = 2 only the fluid kernel (two events per step, for timing a run with the least
+ * disturbance), 0 stops.  LBM_E_INVAL for other values.  lbm_kernel_stats copies up to
+ * max entries and returns their number in *n (synchronises). */
 lbm_status lbm_set_profiling(lbm_handle *h, int32_t on);
 lbm_status lbm_kernel_stats(lbm_handle *h, lbm_kernel_stat *out, int32_t max, int32_t *n);
 

@@ -70,7 +70,7 @@ struct lbm_handle {
     uint8_t *d_wpar = nullptr;
     std::vector<CapDev> h_caps;
     int tile = 1, zchunk = 0;
-    bool profiling = false;
+    int profiling = 0;          // 0 off, 1 every kernel, 2 the fluid kernel only
     std::vector<Timer> timers;
     std::vector<hipEvent_t> event_pool;
 };
@@ -132,7 +132,7 @@ static Timer &timer(lbm_handle *h, const char *name) {
 }
 
 template <typename F> static void timed(lbm_handle *h, const char *name, F &&launch) {
-    if (!h->profiling) {
+    if (!h->profiling || (h->profiling == 2 && std::strcmp(name, "fluid") != 0)) {
         launch();
         return;
     }
@@ -796,7 +796,8 @@ extern "C" lbm_status lbm_load(lbm_handle *h, const char *path) {
 // ------------------------------------------------------------------------------------
 extern "C" lbm_status lbm_set_profiling(lbm_handle *h, int32_t on) {
     if (!h) return LBM_E_INVAL;
-    h->profiling = on != 0;
+    if (on < 0 || on > 2) return fail(h, LBM_E_INVAL, "profiling mode must be 0, 1 or 2");
+    h->profiling = on;
     return LBM_OK;
 }
 

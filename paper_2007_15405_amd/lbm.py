@@ -276,7 +276,8 @@ class Sim:
     def load(self, path: str):
         self._check(self.L.lbm_load(self.h, path.encode()))
 
-    def set_profiling(self, on: bool = True):
+    def set_profiling(self, on=True):
+        """on: True/1 times every kernel, 2 only the fluid kernel, False/0 stops."""
         self._check(self.L.lbm_set_profiling(self.h, int(on)))
 
     def kernel_stats(self) -> dict:

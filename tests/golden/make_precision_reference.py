@@ -1,0 +1,59 @@
+"""FP64 oracle reference for the storage-precision study.
+
+Workload: the film-drying box of two anchored capsules (128 x 128 x 64 lattice, wall at
+z = 0, film 12 layers high, repulsive plane 10 lattice units above the wall, capsules
+R = 10 of 5120 triangles at separation 3R, ks = 0.05, anchor spring 1).  The oracle is
+stepped to each checkpoint and its meniscus height field, capsule observables and
+component masses are written to ``c2_precision_reference.npz`` next to this script.
+
+Only the oracle and the seeded input generators are used.  Run from the repository root:
+
+    python tests/golden/make_precision_reference.py [--threads N]
+"""
+import argparse
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+import oracle  # noqa: E402
+import synth  # noqa: E402
+
+CHECKPOINTS = (1000, 5000)
+OUT = os.path.join(HERE, "c2_precision_reference.npz")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--threads", type=int, default=0)
+    args = ap.parse_args()
+    cfg = synth.workload("c2", ks=0.05)
+    o = oracle.Oracle(cfg, "f64", n_threads=args.threads)
+    ncap = len(cfg["capsules"])
+    mass0 = o.summary()["mass"].copy()
+    rec = dict(checkpoints=np.array(CHECKPOINTS), mass0=mass0)
+    done = 0
+    t0 = time.time()
+    for cp in CHECKPOINTS:
+        st = o.step(cp - done)
+        if st != 0:
+            raise SystemExit(f"oracle step failed with status {st}")
+        done = cp
+        caps = [o.capsule(k) for k in range(ncap)]
+        rec[f"meniscus_{cp}"] = o.meniscus().astype(np.float32)
+        rec[f"mass_{cp}"] = o.summary()["mass"].copy()
+        for key in ("centroid", "f_capillary", "f_anchor", "f_hertz"):
+            rec[f"{key}_{cp}"] = np.array([c[key] for c in caps])
+        rec[f"volume_{cp}"] = np.array([c["volume"] for c in caps])
+        print(f"step {cp}: {time.time() - t0:.0f} s", flush=True)
+    o.close()
+    np.savez_compressed(OUT, **rec)
+    print("wrote", OUT)
+
+
+if __name__ == "__main__":
+    main()
