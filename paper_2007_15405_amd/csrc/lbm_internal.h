@@ -111,7 +111,7 @@ struct CapDev {
 // Per-step capsule state written by the reduction kernel.
 struct CapState {
     double cen[3];          // node mean at X^n
-    double vol;             // enclosed volume at X^n
+    double vol;             // enclosed volume at X^n (capsules with kv != 0; else 0)
     float bmin[3], bmax[3]; // node bounding box (FP32 positions)
     int lo[3], dim[3];      // window: sites lo .. lo + dim - 1 (unwrapped)
 };

@@ -103,9 +103,10 @@ __device__ __forceinline__ int wrap_near(int a, int n) {
 // apex X_ref, the first node; the volume of a closed mesh does not depend on the apex)
 // into a partial record.  The last block of capsule k to finish (device-scope counter,
 // release / acquire fences) sums the records in block order, so the result does not
-// depend on scheduling, then derives the centroid, volume, bounding box and site
-// window, and bins the nodes by the (y, z) lattice row of floor(X) inside the window:
-// positions in row order (any order inside a row), and each node's place in that order.
+// depend on scheduling, then derives the centroid, volume (only for capsules with a
+// volume penalty; else 0), bounding box and site window, and bins the nodes by the
+// (y, z) lattice row of floor(X) inside the window: positions in row order (any order
+// inside a row), and each node's place in that order.
 // ------------------------------------------------------------------------------------
 constexpr int RED_BLK = 256, RED_W = RED_BLK / 64;
 
@@ -145,7 +146,8 @@ __global__ void __launch_bounds__(RED_BLK) k_capsule_reduce(MembraneArgs m) {
             mx[d] = fmaxf(mx[d], (float)p[d]);
         }
     }
-    for (int t = g0; t < cd.nt; t += gstride) {
+    // the enclosed volume is needed on the device only for the volume penalty
+    for (int t = g0; cd.kv != 0.0f && t < cd.nt; t += gstride) {
         const int4 tr = m.tri[cd.tri0 + t];
         const double4 A = m.X[tr.x], B = m.X[tr.y], C = m.X[tr.z];
         const double a[3] = {A.x - Xr.x, A.y - Xr.y, A.z - Xr.z};
