@@ -486,6 +486,8 @@ static FluidArgs fluid_args(lbm_handle *h) {
     for (int d = 0; d < 3; ++d) a.g[d] = (float)h->p.body_force[d];
     a.wall_drho = (float)h->p.wall_drho;
     a.keepf = !(h->p.tau[0] == 1.0 && h->p.tau[1] == 1.0);
+    a.zero_drho = h->p.wall_drho == 0.0;
+    for (const HostCap &c : h->caps) a.zero_drho = a.zero_drho && c.p.wet_drho == 0.0;
     return a;
 }
 

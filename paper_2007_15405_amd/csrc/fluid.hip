@@ -241,6 +241,8 @@ __device__ __forceinline__ void collide_store(const FluidArgs &a, const float (&
 // Neighbour psi across labels (eq. shanchen with the decoupling of Section 3.1): the
 // neighbour's own psi on the same side; across the wall or a membrane the partner's
 // density at x itself plus the wetting offset (+ for component 0, - for component 1).
+// With zero offsets that value is psi at x itself (psi0, psi1), so no exponential is
+// evaluated; the result is the same to the bit.
 // Returns the stencil sums and the reaction G sum_c psi^c (cross-membrane part).
 __device__ __forceinline__ void sc_general(const FluidArgs &a, const float *cap_drho,
                                            const float (&p0n)[Q - 1], const float (&p1n)[Q - 1],
@@ -249,16 +251,27 @@ __device__ __forceinline__ void sc_general(const FluidArgs &a, const float *cap_
                                            float (&S1)[3], float (&rx)[3]) {
     float e0[Q - 1], e1[Q - 1];
     bool anycross = false;
+    if (a.zero_drho) {
+        // zero offsets everywhere: the substituted value is the site's own psi
 #pragma unroll
-    for (int q = 1; q < Q; ++q) {
-        e0[q - 1] = p0n[q - 1];
-        e1[q - 1] = p1n[q - 1];
-        if (nlab[q - 1] != lab) {
-            const int nl = nlab[q - 1];
-            const float dr = nl == LABEL_WALL ? a.wall_drho : cap_drho[(nl != 0 ? nl : lab) - 1];
-            e0[q - 1] = psi_of(fmaxf(rho0 + dr, 0.f), a.inv_rho0);
-            e1[q - 1] = psi_of(fmaxf(rho1 - dr, 0.f), a.inv_rho0);
-            anycross = anycross || nl != LABEL_WALL;
+        for (int q = 1; q < Q; ++q) {
+            const bool cr = nlab[q - 1] != lab;
+            e0[q - 1] = cr ? psi0 : p0n[q - 1];
+            e1[q - 1] = cr ? psi1 : p1n[q - 1];
+            anycross = anycross || (cr && nlab[q - 1] != LABEL_WALL);
+        }
+    } else {
+#pragma unroll
+        for (int q = 1; q < Q; ++q) {
+            e0[q - 1] = p0n[q - 1];
+            e1[q - 1] = p1n[q - 1];
+            if (nlab[q - 1] != lab) {
+                const int nl = nlab[q - 1];
+                const float dr = nl == LABEL_WALL ? a.wall_drho : cap_drho[(nl != 0 ? nl : lab) - 1];
+                e0[q - 1] = psi_of(fmaxf(rho0 + dr, 0.f), a.inv_rho0);
+                e1[q - 1] = psi_of(fmaxf(rho1 - dr, 0.f), a.inv_rho0);
+                anycross = anycross || nl != LABEL_WALL;
+            }
         }
     }
     stencil(e1, a.ws_axis, a.ws_diag, S0[0], S0[1], S0[2]);
@@ -522,9 +535,9 @@ __global__ void __launch_bounds__(TX * TY) k_fused(FluidArgs a, int zc, int tile
 // ------------------------------------------------------------------------------------
 template <int S>
 __device__ __forceinline__ void collide_store_eq(const FluidArgs &a, const float (&m)[8],
-                                                 uint32_t s, uint8_t fg, float psi0, float psi1,
-                                                 const float (&S0)[3], const float (&S1)[3],
-                                                 const float (&rx)[3]) {
+                                                 uint32_t s, uint8_t fg, const float4 &ibv,
+                                                 float psi0, float psi1, const float (&S0)[3],
+                                                 const float (&S1)[3], const float (&rx)[3]) {
     const float rho[2] = {m[0], m[4]};
     const float jx[2] = {m[1], m[5]}, jy[2] = {m[2], m[6]}, jz[2] = {m[3], m[7]};
     if (!(rho[0] >= 0.f) || !(rho[1] >= 0.f) || !(rho[0] + rho[1] < 3.0e38f))
@@ -534,8 +547,7 @@ __device__ __forceinline__ void collide_store_eq(const FluidArgs &a, const float
     const bool aux = (fg & AUX_BIT) != 0;
     float fb[4] = {0.f, 0.f, 0.f, 0.f};
     if (aux) {
-        const float4 v = a.ibm[s];
-        fb[0] = v.x; fb[1] = v.y; fb[2] = v.z; fb[3] = v.w;
+        fb[0] = ibv.x; fb[1] = ibv.y; fb[2] = ibv.z; fb[3] = ibv.w;
     }
     const float m0 = rho[0] * irt, m1 = rho[1] * irt;
     float F0[3], F1[3];
@@ -628,8 +640,12 @@ __global__ void __launch_bounds__(TX * TY) k_fused_pipe(FluidArgs a, int zc, int
 
     // publish psi, flags and the busy bit of plane p from the pulled populations
     auto publish = [&](int p, bool solid, int pz, const float (&fl)[2][Q],
-                       const float (&hf)[2][Q], uint8_t fl_me, uint8_t fl_h, float (&m)[8]) {
+                       const float (&hf)[2][Q], uint8_t fl_me, uint8_t fl_h, float (&m)[8],
+                       float4 &ibv) {
         const int slot = (p - z0 + 4) & 3;
+        // window sites: fetch the spread force now, two planes before it is used
+        ibv = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (!solid && (fl_me & AUX_BIT)) ibv = a.ibm[(pz * ny + iy) * nx + ix];
         float r0 = 0.f, r1 = 0.f, h0 = 0.f, h1 = 0.f;
         if (!solid) {
 #pragma unroll
@@ -684,18 +700,19 @@ __global__ void __launch_bounds__(TX * TY) k_fused_pipe(FluidArgs a, int zc, int
             }
         }
     };
-    auto load_plane = [&](int p, float (&m)[8]) {
+    auto load_plane = [&](int p, float (&m)[8], float4 &ibv) {
         float fl[2][Q], hf[2][Q];
         uint8_t g_me, g_h;
         issue(p, fl, hf, g_me, g_h);
         const int pz = wrapn(p, nz);
-        publish(p, a.wall && pz == 0, pz, fl, hf, g_me, g_h, m);
+        publish(p, a.wall && pz == 0, pz, fl, hf, g_me, g_h, m, ibv);
     };
 
     float m0[8], m1[8], m2[8];   // moments of planes p, p+1, p+2
-    load_plane(z0 - 1, m2);
-    load_plane(z0, m0);
-    load_plane(z0 + 1, m1);
+    float4 ib0, ib1, ib2;        // spread force of this thread's site in planes p, p+1
+    load_plane(z0 - 1, m2, ib2);
+    load_plane(z0, m0, ib0);
+    load_plane(z0 + 1, m1, ib1);
     __syncthreads();
     for (int p = z0; p < z1; ++p) {
         // issue the pulls of plane p+2 first; they complete while plane p is collided
@@ -740,21 +757,26 @@ __global__ void __launch_bounds__(TX * TY) k_fused_pipe(FluidArgs a, int zc, int
                 sc_general(a, s_drho, p0n, p1n, nlab, fg & LABEL_MASK, m0[0], m0[4], psi0, psi1, S0,
                            S1, rx);
             }
-            collide_store_eq<S>(a, m0, s, fg, psi0, psi1, S0, S1, rx);
+            collide_store_eq<S>(a, m0, s, fg, ib0, psi0, psi1, S0, S1, rx);
         }
         // ---- fold plane p+2 into the ring ----
         if (more) {
             float mn[8];
-            publish(p + 2, nsolid, pn, fl, hf, g_me, g_h, mn);
+            float4 ibn;
+            publish(p + 2, nsolid, pn, fl, hf, g_me, g_h, mn, ibn);
 #pragma unroll
             for (int i = 0; i < 8; ++i) { m0[i] = m1[i]; m1[i] = mn[i]; }
+            ib0 = ib1;
+            ib1 = ibn;
         } else {
 #pragma unroll
             for (int i = 0; i < 8; ++i) m0[i] = m1[i];
+            ib0 = ib1;
         }
         __syncthreads();
     }
     (void)m2;
+    (void)ib2;
 }
 
 template <int S, int TX, int TY, bool WX = false>

@@ -97,6 +97,7 @@ struct FluidArgs {
     float wall_drho;
     float shift[2];         // storage shift rho_s per component (16-bit modes)
     int keepf;              // 0: tau = 1 for both components, so f* = f^eq (moments suffice)
+    int zero_drho;          // 1: the wall and every capsule have a zero wetting offset
 };
 
 // Device description of one capsule.
