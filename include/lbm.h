@@ -145,7 +145,11 @@ lbm_status lbm_init(const lbm_params *params, lbm_handle **out);
 /* Add a capsule: a closed triangle mesh, outward counter-clockwise,
  * 4 <= n_nodes <= LBM_MAX_CAPSULE_NODES, at most LBM_MAX_CAPSULES per simulation,
  * xyz host [n_nodes][3] (unwrapped lattice coordinates), tri host [n_tri][3].  The mesh
- * at this moment is the stress-free reference (Section 3.1).  Copied during the call.
+ * at this moment is the stress-free reference (Section 3.1).  Its site window (bounding
+ * box widened by the kernel support: floor(max) - floor(min) + 4 sites per axis) must be at
+ * most 64 sites and the lattice size per axis, and at most 2048 columns in x * y;
+ * LBM_E_INVAL otherwise (a capsule that outgrows it later is reported by lbm_sync as
+ * LBM_E_UNSTABLE).  Copied during the call.
  * Only before the first lbm_step (LBM_E_STATE afterwards).  *id_out gets the index. */
 lbm_status lbm_add_capsule(lbm_handle *h, const lbm_capsule_params *cp, int32_t n_nodes,
                            const double *xyz, int32_t n_tri, const int32_t *tri,

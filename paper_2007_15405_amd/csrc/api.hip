@@ -305,6 +305,27 @@ extern "C" lbm_status lbm_add_capsule(lbm_handle *h, const lbm_capsule_params *c
         if (tri[i] < 0 || tri[i] >= n_nodes) return fail(h, LBM_E_INVAL, "triangle index out of range");
     for (int i = 0; i < 3 * n_nodes; ++i)
         if (!std::isfinite(xyz[i])) return fail(h, LBM_E_INVAL, "non-finite node position");
+    {
+        // the site window the kernels derive from the FP32-rounded bounding box must fit
+        // the window limits and the lattice (the device reports a capsule that later
+        // outgrows them)
+        const int nd[3] = {h->nx, h->ny, h->nz};
+        int dim[3];
+        for (int d = 0; d < 3; ++d) {
+            float lo = 3e38f, hi = -3e38f;
+            for (int i = 0; i < n_nodes; ++i) {
+                const float v = (float)xyz[3 * i + d];
+                lo = std::min(lo, v);
+                hi = std::max(hi, v);
+            }
+            dim[d] = (int)std::floor(hi) - (int)std::floor(lo) + 4;
+            if (dim[d] > GMAX || dim[d] > nd[d])
+                return fail(h, LBM_E_INVAL, "capsule too large for its site window (at most 64 "
+                                            "sites and the lattice size per axis)");
+        }
+        if (dim[0] * dim[1] > FILL_COLS)
+            return fail(h, LBM_E_INVAL, "capsule window wider than 2048 lattice columns (x * y)");
+    }
     HostCap c;
     c.p = *cp;
     c.x0.assign(xyz, xyz + 3 * (size_t)n_nodes);

@@ -36,6 +36,7 @@ constexpr int MAX_CAP_NODES = 8192;  // LBM_MAX_CAPSULE_NODES
 constexpr int GMAX = 64;          // maximum edge of a capsule window (sites)
 constexpr int GMAX3 = GMAX * GMAX * GMAX;
 constexpr int ROWS_MAX = GMAX * GMAX;
+constexpr int FILL_COLS = 2048;   // window columns (x * y) the spreading kernel holds in LDS
 
 // status words (device): [0] unstable flag, [1] lost reaction count, [2] window overflow,
 // [3] window wider than the spreading plane buffer, [4] a cross-block capsule reduction

@@ -424,8 +424,44 @@ __global__ void __launch_bounds__(MEM_BLK) k_membrane(MembraneArgs m, int ntot, 
         return;
     }
     __shared__ CapState s_cst[MAX_CAPS];
+    __shared__ uint8_t s_nearf[2][MAX_CAPS];
+    __shared__ int s_near[2][MAX_CAPS], s_nnear[2];
     for (int j = threadIdx.x; j < m.ncap; j += MEM_BLK) s_cst[j] = m.cst[j];
+    // the capsules of this block's first and last node (node ranges are contiguous)
+    const int nb0 = blockIdx.x * MEM_NPB, nb1 = min(nb0 + MEM_NPB, ntot) - 1;
+    const int kb[2] = {m.node_cap[nb0], m.node_cap[nb1]};
     __syncthreads();
+    if (m.hertz_xi > 0.f) {
+        // Hertz partner capsules: those whose node bounding box comes within delta0 of the
+        // bounding box of the block's capsule (periodic images; every pair closer than
+        // delta0 passes, so the per-node search below loses nothing)
+        const bool per[3] = {true, true, !m.wall};
+        const int nd[3] = {m.nx, m.ny, m.nz};
+        const float d0 = m.hertz_d0, slack = 1e-3f;
+        for (int i = threadIdx.x; i < 2 * m.ncap; i += MEM_BLK) {
+            const int w = i / m.ncap, j = i - w * m.ncap;
+            const CapState &A = s_cst[kb[w]], &B = s_cst[j];
+            bool near = j != kb[w];
+            for (int d = 0; d < 3 && near; ++d) {
+                const float ha = 0.5f * (A.bmax[d] - A.bmin[d]), hb = 0.5f * (B.bmax[d] - B.bmin[d]);
+                float dc = 0.5f * (A.bmin[d] + A.bmax[d]) - 0.5f * (B.bmin[d] + B.bmax[d]);
+                if (per[d]) {
+                    if (2.f * (ha + hb + d0 + 1.f) >= (float)nd[d]) continue;   // box-sized: keep
+                    dc -= nd[d] * floorf(dc / nd[d] + 0.5f);
+                }
+                near = fabsf(dc) - ha - hb <= d0 + slack;
+            }
+            s_nearf[w][j] = near ? 1 : 0;
+        }
+        __syncthreads();
+        if (threadIdx.x < 2) {
+            int c = 0;
+            for (int j = 0; j < m.ncap; ++j)
+                if (s_nearf[threadIdx.x][j]) s_near[threadIdx.x][c++] = j;
+            s_nnear[threadIdx.x] = c;
+        }
+        __syncthreads();
+    }
     const int n = blockIdx.x * MEM_NPB + (threadIdx.x / MEM_L), sl = threadIdx.x % MEM_L;
     if (n >= ntot) return;   // whole groups of MEM_L lanes
     const int k = m.node_cap[n];
@@ -470,7 +506,12 @@ __global__ void __launch_bounds__(MEM_BLK) k_membrane(MembraneArgs m, int ntot, 
         const double p[3] = {X.x, X.y, X.z};
         const double slack = 1e-3;   // FP32 rounding of the bounding box
         long long acc[3] = {0, 0, 0};
-        for (int j = 0; j < m.ncap; ++j) {
+        // the partner lists cover the block's first and last capsule; a block of small
+        // meshes holding more capsules scans them all
+        const bool listed = kb[1] - kb[0] <= 1;
+        const int w = k == kb[0] ? 0 : 1, nj = listed ? s_nnear[w] : m.ncap;
+        for (int jj = 0; jj < nj; ++jj) {
+            const int j = listed ? s_near[w][jj] : jj;
             if (j == k) continue;
             const CapState &cj = s_cst[j];
             double pl[3];   // this node in the periodic image closest to window j
@@ -553,7 +594,6 @@ void launch_membrane(const MembraneArgs &m, int ntot, int ttot, hipStream_t st) 
 // odd.  Wall sites receive nothing.  Sites in several windows are written with the same
 // values by each of them.
 // ------------------------------------------------------------------------------------
-constexpr int FILL_COLS = 2048;     // LDS plane capacity: windows up to 2048 columns (x * y)
 constexpr int OWN_BLK = 256;
 
 __device__ __forceinline__ int gcd_int(int a, int b) {

@@ -284,3 +284,47 @@ def test_body_force_channel_carries_a_capsule():
     assert err <= 1e-4 * max(shift, 1.0)
     e = rel_l2(g.rho(), o.rho())
     assert e[0] <= 1e-5
+
+
+@pytest.mark.parametrize("box,radius", [((32, 32, 32), 15.0), ((96, 96, 96), 31.0),
+                                        ((64, 64, 64), 21.0)])
+def test_capsule_too_large_for_its_window_is_rejected(box, radius):
+    """The site window of a new capsule must fit the lattice and the window limits (64
+    sites per axis, 2048 columns in x * y): a mesh that does not is refused before any
+    kernel sees it."""
+    from paper_2007_15405_amd import LbmError
+    nx, ny, nz = box
+    g = _sim(synth.workload("pf", nx=nx, ny=ny, nz=nz, capsules=[]))
+    cap = synth.capsule((nx / 2, ny / 2, nz / 2), radius, 1280, 0.01)
+    nodes, tris = synth.capsule_mesh(cap)
+    with pytest.raises(LbmError) as ei:
+        g.add_capsule(cap, nodes, tris)
+    assert ei.value.status == -1
+    g.close()
+
+
+@pytest.mark.parametrize("case", ["pair", "tiny"])
+def test_hertz_contact_between_capsules(case):
+    """Capsules closer than delta0 repel (eq. interactions, particle-particle): two R = 4
+    capsules 1 lattice unit apart, and three icosahedra of 12 nodes each (a 32-node block
+    of the force kernel then spans three capsules).  Hertz force, nodes and densities
+    against the oracle."""
+    if case == "pair":
+        caps = [synth.capsule((7.5, 12.0, 12.0), 4.0, 320, 0.05),
+                synth.capsule((16.5, 12.3, 12.2), 4.0, 320, 0.05)]
+        box, steps = (24, 24, 24), 60
+    else:
+        caps = [synth.capsule((8.0 + 3.6 * i, 12.0 + 0.2 * i, 10.0), 1.6, 20, 0.05)
+                for i in range(3)]
+        box, steps = (24, 24, 20), 60
+    cfg = synth.workload("pf", nx=box[0], ny=box[1], nz=box[2], film_height=8, capsules=caps)
+    g, o = run_pair(cfg, steps)
+    fh_o = [o.capsule(k)["f_hertz"] for k in range(len(caps))]
+    fh_g = [g.capsule(k)["f_hertz"] for k in range(len(caps))]
+    say("f_hertz oracle", [f.round(5).tolist() for f in fh_o])
+    assert max(np.abs(f[0]) for f in fh_o) > 1e-3       # the contact is active
+    for a, b in zip(fh_g, fh_o):
+        assert np.linalg.norm(a - b) <= 1e-3 * max(np.linalg.norm(b), 1e-3)
+    for k in range(len(caps)):
+        assert np.abs(g.nodes(k) - o.nodes(k)).max() <= 1e-4
+    assert max(rel_l2(g.rho(), o.rho())) <= 1e-5
