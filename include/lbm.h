@@ -26,6 +26,16 @@
  *   between half-way bounce-back planes at z = 0.5 and z = nz - 0.5.
  *   Component 0 is the film liquid, component 1 the covering fluid.
  *
+ * Slabs (independent runs in one lattice)
+ *   With slab_nz < nz the lattice holds nz / slab_nz independent boxes of
+ *   nx x ny x slab_nz sites stacked along z; slab s occupies k = s * slab_nz ..
+ *   (s + 1) * slab_nz - 1 and its own solid layer is k = s * slab_nz.  The wall layer of
+ *   the slab above bounds slab s exactly as the periodic wrap bounds a single walled box,
+ *   so every slab evolves as the box nx x ny x slab_nz with wall_z0 would on its own.
+ *   A capsule belongs to the slab holding its initial centroid; its repulsive plane is
+ *   at s * slab_nz + 0.5 + plane_dz, it meets the capsules of its own slab only, and its
+ *   site window must stay between the wall layers s * slab_nz and (s + 1) * slab_nz.
+ *
  * Ownership and threading
  *   The library owns all device memory of a handle.  Caller buffers passed to the
  *   entry points are host memory owned by the caller, unless the name says "device".
@@ -36,8 +46,9 @@
  *   Every entry point returns an lbm_status; on failure lbm_last_error(h) holds a
  *   message (lbm_last_error(NULL) holds the message of a failed lbm_init).  No C++
  *   exception crosses this interface.  LBM_E_UNSTABLE reports a non-finite or
- *   negative density, or a capsule that outgrew its immersed-boundary window; the
- *   state is then undefined but the handle can still be destroyed.
+ *   negative density, a capsule that outgrew its immersed-boundary window or whose
+ *   window left its slab; the state is then undefined but the handle can still be
+ *   destroyed.
  */
 #ifndef LBM_H
 #define LBM_H
@@ -73,7 +84,8 @@ typedef enum {
 } lbm_storage;
 
 typedef struct {
-    int32_t nx, ny, nz;        /* lattice size, each >= 3                                   */
+    int32_t nx, ny, nz;        /* lattice size, each >= 3; 19 * nx * ny * nz * (4 bytes for
+                                  FP32 storage, 2 for 16-bit) below 2^32                    */
     int32_t wall_z0;           /* 1: solid wall layer at k = 0                               */
     double tau[2];             /* BGK relaxation time per component, > 1/2 (Section 3.1)    */
     double G;                  /* Shan-Chen coupling G^{12} = G^{21}; G^{cc} = 0 (eq. shanchen) */
@@ -94,6 +106,11 @@ typedef struct {
     int32_t device;            /* HIP device ordinal                                       */
     int32_t stream_given;      /* 1: use `stream` as given, NULL meaning the null stream;
                                   0: NULL makes a private stream of the library             */
+    int32_t slab_nz;           /* 0 or nz: one box.  Otherwise the height of each stacked
+                                  slab (>= 3, dividing nz; needs wall_z0), see above        */
+    const double *slab_film_height; /* mode 1 with slabs: host [nz / slab_nz] film layers per
+                                  slab, or NULL for film_height in every slab; read during
+                                  lbm_init                                                  */
 } lbm_params;
 
 typedef struct {
@@ -125,8 +142,10 @@ typedef struct {
 
 typedef struct {
     float *rho;                 /* host [2][nz][ny][nx] densities rho^c, or NULL          */
-    float *meniscus;            /* host [ny][nx] meniscus height (NaN: none), or NULL     */
+    float *meniscus;            /* host [n_slabs][ny][nx] meniscus height above the slab's
+                                   own wall layer (NaN: none), or NULL                    */
     lbm_capsule_obs *capsules;  /* host [n_capsules], or NULL                            */
+    double *slab_mass;          /* host [n_slabs][2] mass per slab and component, or NULL */
     lbm_summary summary;        /* always filled                                          */
 } lbm_obs;
 
@@ -147,8 +166,8 @@ lbm_status lbm_init(const lbm_params *params, lbm_handle **out);
  * xyz host [n_nodes][3] (unwrapped lattice coordinates), tri host [n_tri][3].  The mesh
  * at this moment is the stress-free reference (Section 3.1).  Its site window (bounding
  * box widened by the kernel support: floor(max) - floor(min) + 4 sites per axis) must be at
- * most 64 sites and the lattice size per axis, and at most 2048 columns in x * y;
- * LBM_E_INVAL otherwise (a capsule that outgrows it later is reported by lbm_sync as
+ * most 64 sites and the lattice size per axis, and at most 2048 columns in x * y, and
+ * with slabs lie between the wall layers of the capsule's slab; LBM_E_INVAL otherwise (a capsule that outgrows it later is reported by lbm_sync as
  * LBM_E_UNSTABLE).  Copied during the call.
  * Only before the first lbm_step (LBM_E_STATE afterwards).  *id_out gets the index. */
 lbm_status lbm_add_capsule(lbm_handle *h, const lbm_capsule_params *cp, int32_t n_nodes,
@@ -172,7 +191,7 @@ lbm_status lbm_rho_device(lbm_handle *h, float *rho_device);
 lbm_status lbm_capsule_nodes(lbm_handle *h, int32_t k, double *xyz);
 
 /* Site labels used by the last step: host [nz][ny][nx]; 0 exterior, k+1 inside
- * capsule k, 255 wall (synchronises). */
+ * capsule k, 255 wall layer (synchronises). */
 lbm_status lbm_labels(lbm_handle *h, uint8_t *out);
 
 /* Checkpoint: populations, node positions, pending reaction and step counter, in a
@@ -189,10 +208,13 @@ lbm_status lbm_set_profiling(lbm_handle *h, int32_t on);
 lbm_status lbm_kernel_stats(lbm_handle *h, lbm_kernel_stat *out, int32_t max, int32_t *n);
 
 /* Launch shape of the fluid step.  tile 1..5 selects the fused single-read kernel with
- * column tiles of 32x8, 64x4, 32x16, 64x8 or 16x16 sites; tile 0 the two-kernel variant
- * (densities, then forces and collision).  zchunk is the number of z planes one
- * workgroup marches through (0: chosen from the lattice size).  Every variant performs
- * the same arithmetic per site in the same order, so results are identical. */
+ * column tiles of 32x8, 64x4, 32x16, 64x8 or 16x16 sites; 6..10 its software-pipelined
+ * form (tau = 1 in both components; otherwise the fused kernel of the same tile) with
+ * 32x8, 64x4, 16x16, 32x16 or 64x8; 11 and 12 whole-row tiles 256x2 and 128x4 (nx = 256
+ * resp. 128, otherwise 64x8); tile 0 the two-kernel variant (densities, then forces and
+ * collision).  zchunk is the number of z planes one workgroup marches through (0: chosen
+ * from the lattice size).  Every variant performs the same arithmetic per site in the
+ * same order, so results are identical.  LBM_E_INVAL for other values. */
 lbm_status lbm_set_launch(lbm_handle *h, int32_t tile, int32_t zchunk);
 
 /* Algorithmic HBM bytes per fluid-site update of the fused fluid kernel for the
@@ -202,6 +224,33 @@ int64_t lbm_fluid_sites(const lbm_handle *h);
 
 const char *lbm_last_error(const lbm_handle *h);
 void lbm_destroy(lbm_handle *h);
+
+/* ---- Batches -------------------------------------------------------------------------
+ * A batch advances several simulations together: per step, the capsule kernels of each
+ * handle, then ONE launch of the software-pipelined fluid kernel over the lattices of all
+ * handles (different sizes allowed; each handle may itself hold stacked slabs), then the
+ * node updates.  Each handle ends in exactly the state lbm_step would give it: the
+ * per-site arithmetic is the same.  The handles must share device, stream and storage
+ * mode and have tau = 1 in both components; they stay owned by the caller, who destroys
+ * the batch before them.  Observation calls (lbm_sync, lbm_observables, ...) go to the
+ * handles.  lbm_batch_create fails with LBM_E_INVAL (message in lbm_batch_last_error(NULL))
+ * for handles that do not qualify. */
+typedef struct lbm_batch lbm_batch;
+lbm_status lbm_batch_create(lbm_handle *const *handles, int32_t n, lbm_batch **out);
+
+/* Tile of the batched fluid launch: 6..10 as in lbm_set_launch (default 10, 64x8);
+ * zchunk 0 picks 48 planes, halved while the launch has fewer than 1024 workgroups. */
+lbm_status lbm_batch_set_launch(lbm_batch *b, int32_t tile, int32_t zchunk);
+
+/* Enqueue n >= 0 steps of every handle on the shared stream; returns without waiting. */
+lbm_status lbm_batch_step(lbm_batch *b, int64_t n);
+
+/* Event timing of the batch's kernels, as lbm_set_profiling / lbm_kernel_stats. */
+lbm_status lbm_batch_set_profiling(lbm_batch *b, int32_t on);
+lbm_status lbm_batch_kernel_stats(lbm_batch *b, lbm_kernel_stat *out, int32_t max, int32_t *n);
+
+const char *lbm_batch_last_error(const lbm_batch *b);
+void lbm_batch_destroy(lbm_batch *b);
 
 #ifdef __cplusplus
 }

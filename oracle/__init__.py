@@ -185,6 +185,8 @@ def column_labels(nodes, tris, origin, dims):
 
 
 def make_params(cfg: dict, n_threads: int = 0):
+    if cfg.get("slab_nz", 0) not in (0, cfg["nz"]):
+        raise ValueError("the oracle simulates one box; run each stacked slab as a box of its own")
     p = Params()
     p.nx, p.ny, p.nz, p.wall_z0 = cfg["nx"], cfg["ny"], cfg["nz"], int(cfg["wall_z0"])
     p.tau[0], p.tau[1] = cfg["tau"]

@@ -19,6 +19,7 @@ thread_local std::string g_init_error;
 
 struct HostCap {
     lbm_capsule_params p;
+    int zbase;                 // wall layer of the capsule's slab
     std::vector<double> x0;    // [nn][3]
     std::vector<int32_t> tri;  // [nt][3]
 };
@@ -28,6 +29,13 @@ struct Timer {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
     int64_t launches = 0;
     double ms = 0.0;
+};
+
+// Event timing of kernels on one stream: mode 0 off, 1 every kernel, 2 the fluid kernel
+struct Prof {
+    int mode = 0;
+    std::vector<Timer> timers;
+    std::vector<hipEvent_t> pool;
 };
 
 constexpr int MOM_BLOCKS = 512;
@@ -40,6 +48,8 @@ struct lbm_handle {
     hipStream_t st = nullptr;
     bool own_stream = false;
     int nx = 0, ny = 0, nz = 0, wall = 0, N = 0, storage = 0;
+    int lz = 0, nslab = 1;      // slab height and count (one box: lz = nz)
+    int mom_blocks = 0;         // moment-reduction blocks per slab
     size_t esize = 4;
     void *f[2] = {nullptr, nullptr};
     int cur = 0;
@@ -70,9 +80,7 @@ struct lbm_handle {
     uint8_t *d_wpar = nullptr;
     std::vector<CapDev> h_caps;
     int tile = 1, zchunk = 0;
-    int profiling = 0;          // 0 off, 1 every kernel, 2 the fluid kernel only
-    std::vector<Timer> timers;
-    std::vector<hipEvent_t> event_pool;
+    Prof prof;
 };
 
 #define HIPCHK(h, expr)                                                               \
@@ -93,6 +101,17 @@ template <typename T> static hipError_t dalloc(T **p, size_t count) {
     return hipMalloc((void **)p, sizeof(T) * (count ? count : 1));
 }
 
+static void free_prof(Prof &pf) {
+    for (hipEvent_t e : pf.pool) (void)hipEventDestroy(e);
+    for (auto &t : pf.timers)
+        for (auto &pr : t.pending) {
+            (void)hipEventDestroy(pr.first);
+            (void)hipEventDestroy(pr.second);
+        }
+    pf.pool.clear();
+    pf.timers.clear();
+}
+
 static void free_all(lbm_handle *h) {
     void *ptrs[] = {h->f[0], h->f[1], h->flag, h->ibm, h->uo, h->ro, h->psi, h->cap_drho,
                     h->rho_tmp, h->men_tmp, h->status, h->partial, h->d_caps, h->d_cst, h->d_X,
@@ -101,22 +120,17 @@ static void free_all(lbm_handle *h) {
                     h->d_wpar, h->d_part, h->d_counter, h->d_xrow};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
-    for (hipEvent_t e : h->event_pool) (void)hipEventDestroy(e);
-    for (auto &t : h->timers)
-        for (auto &pr : t.pending) {
-            (void)hipEventDestroy(pr.first);
-            (void)hipEventDestroy(pr.second);
-        }
+    free_prof(h->prof);
     if (h->own_stream && h->st) (void)hipStreamDestroy(h->st);
 }
 
 // ------------------------------------------------------------------------------------
 // Timing
 // ------------------------------------------------------------------------------------
-static hipEvent_t take_event(lbm_handle *h) {
-    if (!h->event_pool.empty()) {
-        hipEvent_t e = h->event_pool.back();
-        h->event_pool.pop_back();
+static hipEvent_t take_event(Prof &pf) {
+    if (!pf.pool.empty()) {
+        hipEvent_t e = pf.pool.back();
+        pf.pool.pop_back();
         return e;
     }
     hipEvent_t e = nullptr;
@@ -124,59 +138,78 @@ static hipEvent_t take_event(lbm_handle *h) {
     return e;
 }
 
-static Timer &timer(lbm_handle *h, const char *name) {
-    for (auto &t : h->timers)
+static Timer &timer(Prof &pf, const char *name) {
+    for (auto &t : pf.timers)
         if (t.name == name) return t;
-    h->timers.push_back(Timer{name, {}, 0, 0.0});
-    return h->timers.back();
+    pf.timers.push_back(Timer{name, {}, 0, 0.0});
+    return pf.timers.back();
 }
 
-template <typename F> static void timed(lbm_handle *h, const char *name, F &&launch) {
-    if (!h->profiling || (h->profiling == 2 && std::strcmp(name, "fluid") != 0)) {
+template <typename F>
+static void timed(Prof &pf, hipStream_t st, const char *name, F &&launch) {
+    if (!pf.mode || (pf.mode == 2 && std::strcmp(name, "fluid") != 0)) {
         launch();
         return;
     }
-    hipEvent_t a = take_event(h), b = take_event(h);
-    if (a) (void)hipEventRecord(a, h->st);
+    hipEvent_t a = take_event(pf), b = take_event(pf);
+    if (a) (void)hipEventRecord(a, st);
     launch();
-    if (b) (void)hipEventRecord(b, h->st);
-    if (a && b) timer(h, name).pending.push_back({a, b});
+    if (b) (void)hipEventRecord(b, st);
+    if (a && b) timer(pf, name).pending.push_back({a, b});
 }
 
-static void collect_timers(lbm_handle *h) {
-    for (auto &t : h->timers) {
+static void collect_timers(Prof &pf) {
+    for (auto &t : pf.timers) {
         for (auto &pr : t.pending) {
             float ms = 0.f;
             if (hipEventElapsedTime(&ms, pr.first, pr.second) == hipSuccess) {
                 t.ms += ms;
                 t.launches++;
             }
-            h->event_pool.push_back(pr.first);
-            h->event_pool.push_back(pr.second);
+            pf.pool.push_back(pr.first);
+            pf.pool.push_back(pr.second);
         }
         t.pending.clear();
     }
 }
 
+// copies up to max timer entries (and resets them); the caller has synchronised
+static int export_timers(Prof &pf, lbm_kernel_stat *out, int max) {
+    collect_timers(pf);
+    int k = 0;
+    for (auto &t : pf.timers) {
+        if (k >= max) break;
+        std::memset(&out[k], 0, sizeof(lbm_kernel_stat));
+        std::snprintf(out[k].name, sizeof out[k].name, "%s", t.name);
+        out[k].launches = t.launches;
+        out[k].total_ms = t.ms;
+        ++k;
+    }
+    for (auto &t : pf.timers) { t.launches = 0; t.ms = 0.0; }
+    return k;
+}
+
 // ------------------------------------------------------------------------------------
 // Initial densities (Section 3.2 film, uniform, or caller array)
 // ------------------------------------------------------------------------------------
-static void initial_density(const lbm_params &p, std::vector<double> &rho) {
+static void initial_density(const lbm_params &p, int lz, std::vector<double> &rho) {
     const long N = (long)p.nx * p.ny * p.nz;
     rho.assign(2 * N, 0.0);
     const int kw = p.wall_z0 ? 1 : 0;
-    const long H = std::lround(p.film_height);
     for (int k = 0; k < p.nz; ++k)
         for (int j = 0; j < p.ny; ++j)
             for (int i = 0; i < p.nx; ++i) {
                 const long s = ((long)k * p.ny + j) * p.nx + i;
-                if (p.wall_z0 && k == 0) continue;
+                const int kr = slab_pos(k, lz);   // plane inside its slab
+                if (p.wall_z0 && kr == 0) continue;
                 double a, b;
                 if (p.init_mode == 0) {
                     a = p.init_rho[0];
                     b = p.init_rho[1];
                 } else if (p.init_mode == 1) {
-                    const long layer = k - kw;
+                    const double hf = p.slab_film_height ? p.slab_film_height[k / lz] : p.film_height;
+                    const long H = std::lround(hf);
+                    const long layer = kr - kw;
                     if (layer < H) { a = p.rho_maj; b = p.rho_min; }
                     else if (layer == H) { a = p.rho_iface; b = p.rho_iface; }
                     else { a = p.rho_min; b = p.rho_maj; }
@@ -205,13 +238,24 @@ extern "C" lbm_status lbm_init(const lbm_params *p, lbm_handle **out) {
     };
     if (!p) return bad("params is NULL");
     if (p->nx < 3 || p->ny < 3 || p->nz < 3) return bad("nx, ny, nz must be >= 3");
-    if ((double)p->nx * p->ny * p->nz > (double)(1 << 30)) return bad("lattice too large");
+    // the kernels address one component's populations with 32-bit byte offsets
+    const double pop_bytes = (double)Q * p->nx * p->ny * p->nz * (p->storage == LBM_STORE_F32 ? 4 : 2);
+    if (pop_bytes >= 4294967296.0)
+        return bad("lattice too large: 19 populations of one component must fit in 4 GiB "
+                   "(56 million sites with FP32 storage, 113 million with 16-bit)");
     if (!(p->tau[0] > 0.5) || !(p->tau[1] > 0.5)) return bad("tau must exceed 1/2");
     if (!(p->rho0 > 0.0)) return bad("rho0 must be positive");
     if (!(p->sc_norm >= 0.0) || !std::isfinite(p->G)) return bad("invalid Shan-Chen coupling");
     if (p->init_mode < 0 || p->init_mode > 2) return bad("init_mode must be 0, 1 or 2");
     if (p->init_mode == 2 && !p->init_rho_array) return bad("init_rho_array is NULL");
     if (p->init_mode == 1 && !(p->film_height >= 0.0)) return bad("film_height must be >= 0");
+    const int lz = p->slab_nz == 0 ? p->nz : p->slab_nz;
+    if (lz < 3 || lz > p->nz || p->nz % lz != 0)
+        return bad("slab_nz must be 0 or a divisor of nz of at least 3");
+    if (lz < p->nz && p->wall_z0 != 1) return bad("stacked slabs need wall_z0 = 1");
+    if (p->init_mode == 1 && p->slab_film_height)
+        for (int sl = 0; sl < p->nz / lz; ++sl)
+            if (!(p->slab_film_height[sl] >= 0.0)) return bad("slab_film_height must be >= 0");
     if (p->storage < 0 || p->storage > 2) return bad("storage must be 0, 1 or 2");
     if (!(p->hertz_xi >= 0.0) || !(p->hertz_delta0 >= 0.0)) return bad("invalid Hertz parameters");
     if (p->wall_z0 != 0 && p->wall_z0 != 1) return bad("wall_z0 must be 0 or 1");
@@ -220,7 +264,11 @@ extern "C" lbm_status lbm_init(const lbm_params *p, lbm_handle **out) {
     if (!h) return LBM_E_NOMEM;
     h->p = *p;
     h->p.init_rho_array = nullptr;
+    h->p.slab_film_height = nullptr;
     h->nx = p->nx; h->ny = p->ny; h->nz = p->nz; h->wall = p->wall_z0;
+    h->lz = lz;
+    h->nslab = p->nz / lz;
+    h->mom_blocks = std::max(8, MOM_BLOCKS / h->nslab);
     h->N = p->nx * p->ny * p->nz;
     h->storage = p->storage;
     h->esize = p->storage == LBM_STORE_F32 ? 4 : 2;
@@ -246,9 +294,9 @@ extern "C" lbm_status lbm_init(const lbm_params *p, lbm_handle **out) {
         dalloc(&h->uo, N) != hipSuccess || dalloc(&h->ro, N) != hipSuccess ||
         dalloc(&h->psi, 2 * N) != hipSuccess || dalloc(&h->cap_drho, (size_t)MAX_CAPS) != hipSuccess ||
         dalloc(&h->rho_tmp, 2 * N) != hipSuccess ||
-        dalloc(&h->men_tmp, (size_t)h->nx * h->ny) != hipSuccess ||
+        dalloc(&h->men_tmp, (size_t)h->nx * h->ny * h->nslab) != hipSuccess ||
         dalloc(&h->status, (size_t)ST_WORDS) != hipSuccess ||
-        dalloc(&h->partial, (size_t)MOM_BLOCKS * 5) != hipSuccess)
+        dalloc(&h->partial, (size_t)h->nslab * h->mom_blocks * 5) != hipSuccess)
         return die(LBM_E_NOMEM, "device allocation failed");
     if (hipMemsetAsync(h->f[0], 0, fbytes, h->st) != hipSuccess ||
         hipMemsetAsync(h->f[1], 0, fbytes, h->st) != hipSuccess ||
@@ -262,7 +310,7 @@ extern "C" lbm_status lbm_init(const lbm_params *p, lbm_handle **out) {
         return die(LBM_E_DEVICE, "device memset failed");
 
     std::vector<double> rho;
-    initial_density(*p, rho);
+    initial_density(*p, lz, rho);
     for (double v : rho)
         if (!std::isfinite(v) || v < 0.0) return die(LBM_E_INVAL, "initial densities must be finite and >= 0");
     double *d_rho = nullptr;
@@ -271,9 +319,9 @@ extern "C" lbm_status lbm_init(const lbm_params *p, lbm_handle **out) {
     if (e == hipSuccess) {
         const float s0 = shift_of(h, 0), s1 = shift_of(h, 1);
         switch (h->storage) {
-            case 0: launch_init_eq<0>(d_rho, h->f[0], h->nx, h->ny, h->nz, h->wall, s0, s1, h->st); break;
-            case 1: launch_init_eq<1>(d_rho, h->f[0], h->nx, h->ny, h->nz, h->wall, s0, s1, h->st); break;
-            default: launch_init_eq<2>(d_rho, h->f[0], h->nx, h->ny, h->nz, h->wall, s0, s1, h->st); break;
+            case 0: launch_init_eq<0>(d_rho, h->f[0], h->nx, h->ny, h->nz, h->wall, h->lz, s0, s1, h->st); break;
+            case 1: launch_init_eq<1>(d_rho, h->f[0], h->nx, h->ny, h->nz, h->wall, h->lz, s0, s1, h->st); break;
+            default: launch_init_eq<2>(d_rho, h->f[0], h->nx, h->ny, h->nz, h->wall, h->lz, s0, s1, h->st); break;
         }
         e = hipGetLastError();
     }
@@ -326,8 +374,27 @@ extern "C" lbm_status lbm_add_capsule(lbm_handle *h, const lbm_capsule_params *c
         if (dim[0] * dim[1] > FILL_COLS)
             return fail(h, LBM_E_INVAL, "capsule window wider than 2048 lattice columns (x * y)");
     }
+    // slab of the capsule: the one holding its node mean
+    double cz = 0.0;
+    for (int i = 0; i < n_nodes; ++i) cz += xyz[3 * i + 2];
+    cz /= n_nodes;
+    int zbase = 0;
+    if (h->nslab > 1) {
+        const int sl = (int)std::floor(cz / h->lz);
+        if (sl < 0 || sl >= h->nslab) return fail(h, LBM_E_INVAL, "capsule centroid outside the lattice");
+        zbase = sl * h->lz;
+        float lo = 3e38f, hi = -3e38f;
+        for (int i = 0; i < n_nodes; ++i) {
+            lo = std::min(lo, (float)xyz[3 * i + 2]);
+            hi = std::max(hi, (float)xyz[3 * i + 2]);
+        }
+        const int wlo = (int)std::floor(lo) - 1, whi = (int)std::floor(hi) + 2;
+        if (wlo < zbase || whi > zbase + h->lz)
+            return fail(h, LBM_E_INVAL, "capsule window crosses a wall layer of its slab");
+    }
     HostCap c;
     c.p = *cp;
+    c.zbase = zbase;
     c.x0.assign(xyz, xyz + 3 * (size_t)n_nodes);
     c.tri.assign(tri, tri + 3 * (size_t)n_tri);
     h->caps.push_back(std::move(c));
@@ -380,6 +447,8 @@ static lbm_status finalize(lbm_handle *h) {
         cd.C = (float)c.p.C;
         cd.kv = (float)c.p.kv;
         cd.anchor_k = (float)c.p.anchor_k;
+        cd.zbase = c.zbase;
+        cd.plane_z = (float)(c.zbase + 0.5 + h->p.plane_dz);
         double cen[3] = {0, 0, 0};
         for (int i = 0; i < nn; ++i) {
             X.push_back(make_double4(c.x0[3 * i], c.x0[3 * i + 1], c.x0[3 * i + 2], 0.0));
@@ -481,20 +550,20 @@ static MembraneArgs membrane_args(lbm_handle *h) {
     m.part = h->d_part; m.counter = h->d_counter; m.nch = h->nch;
     m.wbuf = h->d_wbuf; m.wpar = h->d_wpar;
     m.flag = h->flag; m.ibm = h->ibm; m.uo = h->uo; m.ro = h->ro; m.status = h->status;
-    m.nx = h->nx; m.ny = h->ny; m.nz = h->nz; m.wall = h->wall;
+    m.nx = h->nx; m.ny = h->ny; m.nz = h->nz; m.wall = h->wall; m.lz = h->lz;
     m.hertz_xi = (float)h->p.hertz_xi;
     m.hertz_d0 = (float)h->p.hertz_delta0;
-    m.plane_z = (float)(0.5 + h->p.plane_dz);
     return m;
 }
 
-static FluidArgs fluid_args(lbm_handle *h) {
+// arguments of the fluid kernel reading population buffer cur
+static FluidArgs fluid_args(lbm_handle *h, int cur) {
     FluidArgs a{};
-    a.fin = h->f[h->cur];
-    a.fout = h->f[1 - h->cur];
+    a.fin = h->f[cur];
+    a.fout = h->f[1 - cur];
     a.flag = h->flag; a.ibm = h->ibm; a.uo = h->uo; a.ro = h->ro; a.psi = h->psi;
     a.status = h->status; a.cap_drho = h->cap_drho;
-    a.nx = h->nx; a.ny = h->ny; a.nz = h->nz; a.wall = h->wall; a.N = h->N;
+    a.nx = h->nx; a.ny = h->ny; a.nz = h->nz; a.wall = h->wall; a.N = h->N; a.lz = h->lz;
     for (int c = 0; c < 2; ++c) {
         a.tau[c] = (float)h->p.tau[c];
         a.inv_tau[c] = (float)(1.0 / h->p.tau[c]);
@@ -535,6 +604,13 @@ extern "C" lbm_status lbm_set_launch(lbm_handle *h, int32_t tile, int32_t zchunk
     return LBM_OK;
 }
 
+// labels, membrane forces and spreading: the kernels of a step before the fluid kernel
+static void capsule_kernels_before(lbm_handle *h, const MembraneArgs &m, Prof &pf) {
+    timed(pf, h->st, "capsule_reduce", [&] { launch_capsule_reduce(m, h->st); });
+    timed(pf, h->st, "membrane", [&] { launch_membrane(m, h->ntot, h->ttot, h->st); });
+    timed(pf, h->st, "window_fill", [&] { launch_window_fill(m, h->st); });
+}
+
 extern "C" lbm_status lbm_step(lbm_handle *h, int64_t n) {
     if (!h) return LBM_E_INVAL;
     if (n < 0) return fail(h, LBM_E_INVAL, "negative step count");
@@ -547,25 +623,207 @@ extern "C" lbm_status lbm_step(lbm_handle *h, int64_t n) {
     for (int64_t i = 0; i < n; ++i) {
         if (caps) {
             m.epoch = (int)(h->step & 0x7fffffff);
-            timed(h, "capsule_reduce", [&] { launch_capsule_reduce(m, h->st); });
-            timed(h, "membrane", [&] { launch_membrane(m, h->ntot, h->ttot, h->st); });
-            timed(h, "window_fill", [&] { launch_window_fill(m, h->st); });
+            capsule_kernels_before(h, m, h->prof);
         }
-        const FluidArgs a = fluid_args(h);
+        const FluidArgs a = fluid_args(h, h->cur);
         const int zc = zchunk_of(h);
-        timed(h, "fluid", [&] {
+        timed(h->prof, h->st, "fluid", [&] {
             switch (h->storage) {
                 case 0: launch_fluid_tiled<0>(a, h->tile, zc, h->st); break;
                 case 1: launch_fluid_tiled<1>(a, h->tile, zc, h->st); break;
                 default: launch_fluid_tiled<2>(a, h->tile, zc, h->st); break;
             }
         });
-        if (caps) timed(h, "node_update", [&] { launch_node_update(m, h->ntot, h->st); });
+        if (caps) timed(h->prof, h->st, "node_update", [&] { launch_node_update(m, h->ntot, h->st); });
         h->cur = 1 - h->cur;
         h->step++;
     }
     HIPCHK(h, hipGetLastError());
     return LBM_OK;
+}
+
+// ------------------------------------------------------------------------------------
+// Batches: several handles advanced together, with one launch of the fluid kernel over
+// all their lattices per step
+// ------------------------------------------------------------------------------------
+struct lbm_batch {
+    std::vector<lbm_handle *> hs;
+    std::string err;
+    hipStream_t st = nullptr;
+    int storage = 0;
+    int tile = 10, zchunk = 0;
+    FluidArgs *d_tab = nullptr;    // [2][n]: arguments for parity 0 and 1 of the buffers
+    int4 *d_desc = nullptr;        // [n + 1] first logical block, tiles x, tiles y, zchunk
+    std::vector<int> cur0;         // buffer index of each handle at parity 0
+    bool dirty = true;
+    int par = 0, nblocks = 0;
+    Prof prof;
+};
+
+static lbm_status bfail(lbm_batch *b, lbm_status s, const std::string &m) {
+    b->err = m;
+    return s;
+}
+
+// z planes per workgroup of a batch launch: 48, halved while the launch has fewer than
+// 1024 workgroups (four per compute unit), at least 8
+static int batch_zchunk(const lbm_batch *b, int zc) {
+    if (b->zchunk > 0) return b->zchunk;
+    long total = 0;
+    for (const lbm_handle *h : b->hs)
+        total += (long)((h->nx + TILE_X[b->tile] - 1) / TILE_X[b->tile]) *
+                 ((h->ny + TILE_Y[b->tile] - 1) / TILE_Y[b->tile]) * ((h->nz + zc - 1) / zc);
+    return (total >= 1024 || zc <= 8) ? zc : batch_zchunk(b, std::max(8, zc / 2));
+}
+
+static lbm_status batch_tables(lbm_batch *b) {
+    const int n = (int)b->hs.size();
+    const int zc = batch_zchunk(b, 48);
+    std::vector<FluidArgs> tab(2 * (size_t)n);
+    std::vector<int4> desc(n + 1);
+    int start = 0;
+    for (int g = 0; g < n; ++g) {
+        lbm_handle *h = b->hs[g];
+        b->cur0[g] = h->cur;
+        tab[g] = fluid_args(h, h->cur);
+        tab[n + g] = fluid_args(h, 1 - h->cur);
+        const int tx = (h->nx + TILE_X[b->tile] - 1) / TILE_X[b->tile];
+        const int ty = (h->ny + TILE_Y[b->tile] - 1) / TILE_Y[b->tile];
+        desc[g] = make_int4(start, tx, ty, zc);
+        start += tx * ty * ((h->nz + zc - 1) / zc);
+    }
+    desc[n] = make_int4(start, 0, 0, 0);
+    b->nblocks = start;
+    b->par = 0;
+    // the previous tables may still be read by enqueued launches
+    if (hipStreamSynchronize(b->st) != hipSuccess ||
+        hipMemcpy(b->d_tab, tab.data(), tab.size() * sizeof(FluidArgs), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(b->d_desc, desc.data(), desc.size() * sizeof(int4), hipMemcpyHostToDevice) != hipSuccess)
+        return bfail(b, LBM_E_DEVICE, "batch table upload failed");
+    b->dirty = false;
+    return LBM_OK;
+}
+
+extern "C" lbm_status lbm_batch_create(lbm_handle *const *handles, int32_t n, lbm_batch **out) {
+    if (!out) return LBM_E_INVAL;
+    *out = nullptr;
+    auto bad = [&](const char *m) {
+        g_init_error = m;
+        return LBM_E_INVAL;
+    };
+    if (!handles || n < 1) return bad("a batch needs at least one handle");
+    for (int g = 0; g < n; ++g) {
+        const lbm_handle *h = handles[g];
+        if (!h) return bad("NULL handle in batch");
+        for (int j = 0; j < g; ++j)
+            if (handles[j] == h) return bad("a handle appears twice in the batch");
+        if (h->st != handles[0]->st || h->storage != handles[0]->storage ||
+            h->p.device != handles[0]->p.device)
+            return bad("batched handles must share device, stream and storage mode");
+        if (!(h->p.tau[0] == 1.0 && h->p.tau[1] == 1.0))
+            return bad("batched handles need tau = 1 in both components");
+    }
+    lbm_batch *b = new (std::nothrow) lbm_batch();
+    if (!b) return LBM_E_NOMEM;
+    b->hs.assign(handles, handles + n);
+    b->st = handles[0]->st;
+    b->storage = handles[0]->storage;
+    b->cur0.assign(n, 0);
+    if (dalloc(&b->d_tab, 2 * (size_t)n) != hipSuccess || dalloc(&b->d_desc, (size_t)n + 1) != hipSuccess) {
+        if (b->d_tab) (void)hipFree(b->d_tab);
+        delete b;
+        g_init_error = "device allocation failed (batch)";
+        return LBM_E_NOMEM;
+    }
+    *out = b;
+    return LBM_OK;
+}
+
+extern "C" lbm_status lbm_batch_set_launch(lbm_batch *b, int32_t tile, int32_t zchunk) {
+    if (!b) return LBM_E_INVAL;
+    if (tile < 6 || tile > 10 || zchunk < 0) return bfail(b, LBM_E_INVAL, "batch tile must be 6..10");
+    b->tile = tile;
+    b->zchunk = zchunk;
+    b->dirty = true;
+    return LBM_OK;
+}
+
+extern "C" lbm_status lbm_batch_step(lbm_batch *b, int64_t n) {
+    if (!b) return LBM_E_INVAL;
+    if (n < 0) return bfail(b, LBM_E_INVAL, "negative step count");
+    const int ng = (int)b->hs.size();
+    for (lbm_handle *h : b->hs)
+        if (!h->finalized) {
+            lbm_status s = finalize(h);
+            if (s != LBM_OK) return bfail(b, s, h->err);
+        }
+    // the tables hold both buffer parities; a handle stepped on its own since they were
+    // written needs new ones
+    for (int g = 0; g < ng && !b->dirty; ++g)
+        if ((b->hs[g]->cur ^ b->cur0[g]) != (b->hs[0]->cur ^ b->cur0[0])) b->dirty = true;
+    if (b->dirty) {
+        lbm_status s = batch_tables(b);
+        if (s != LBM_OK) return s;
+    }
+    b->par = b->hs[0]->cur ^ b->cur0[0];
+    std::vector<MembraneArgs> ms(ng);
+    for (int g = 0; g < ng; ++g)
+        if (!b->hs[g]->caps.empty()) ms[g] = membrane_args(b->hs[g]);
+    for (int64_t i = 0; i < n; ++i) {
+        for (int g = 0; g < ng; ++g) {
+            lbm_handle *h = b->hs[g];
+            if (h->caps.empty()) continue;
+            ms[g].epoch = (int)(h->step & 0x7fffffff);
+            capsule_kernels_before(h, ms[g], b->prof);
+        }
+        const FluidArgs *tab = b->d_tab + (size_t)b->par * ng;
+        timed(b->prof, b->st, "fluid", [&] {
+            switch (b->storage) {
+                case 0: launch_fluid_multi<0>(tab, b->d_desc, ng, b->nblocks, b->tile, b->st); break;
+                case 1: launch_fluid_multi<1>(tab, b->d_desc, ng, b->nblocks, b->tile, b->st); break;
+                default: launch_fluid_multi<2>(tab, b->d_desc, ng, b->nblocks, b->tile, b->st); break;
+            }
+        });
+        for (int g = 0; g < ng; ++g) {
+            lbm_handle *h = b->hs[g];
+            if (!h->caps.empty())
+                timed(b->prof, b->st, "node_update", [&] { launch_node_update(ms[g], h->ntot, h->st); });
+            h->cur = 1 - h->cur;
+            h->step++;
+        }
+        b->par ^= 1;
+    }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return bfail(b, LBM_E_DEVICE, std::string("batch step: ") + hipGetErrorString(e));
+    return LBM_OK;
+}
+
+extern "C" lbm_status lbm_batch_set_profiling(lbm_batch *b, int32_t on) {
+    if (!b) return LBM_E_INVAL;
+    if (on < 0 || on > 2) return bfail(b, LBM_E_INVAL, "profiling mode must be 0, 1 or 2");
+    b->prof.mode = on;
+    return LBM_OK;
+}
+
+extern "C" lbm_status lbm_batch_kernel_stats(lbm_batch *b, lbm_kernel_stat *out, int32_t max,
+                                             int32_t *n) {
+    if (!b || !n || (max > 0 && !out)) return LBM_E_INVAL;
+    if (hipStreamSynchronize(b->st) != hipSuccess) return bfail(b, LBM_E_DEVICE, "stream synchronisation failed");
+    *n = export_timers(b->prof, out, max);
+    return LBM_OK;
+}
+
+extern "C" const char *lbm_batch_last_error(const lbm_batch *b) {
+    return b ? b->err.c_str() : g_init_error.c_str();
+}
+
+extern "C" void lbm_batch_destroy(lbm_batch *b) {
+    if (!b) return;
+    if (b->st) (void)hipStreamSynchronize(b->st);
+    if (b->d_tab) (void)hipFree(b->d_tab);
+    if (b->d_desc) (void)hipFree(b->d_desc);
+    free_prof(b->prof);
+    delete b;
 }
 
 static lbm_status check_status(lbm_handle *h, int st[ST_WORDS]) {
@@ -574,8 +832,13 @@ static lbm_status check_status(lbm_handle *h, int st[ST_WORDS]) {
     return LBM_OK;
 }
 
+static bool unstable_flagged(const int *st) {
+    return st[ST_UNSTABLE] || st[ST_OVERFLOW] || st[ST_WIDE] || st[ST_SYNC] || st[ST_SLAB];
+}
+
 static const char *unstable_message(const int *st) {
     if (st[ST_SYNC]) return "capsule reduction read partial sums of another step";
+    if (st[ST_SLAB]) return "capsule window crossed a wall layer of its slab";
     if (st[ST_WIDE]) return "capsule window wider than 2048 lattice columns (x * y)";
     if (st[ST_OVERFLOW]) return "capsule outgrew its window";
     return "non-finite or negative density";
@@ -586,8 +849,7 @@ extern "C" lbm_status lbm_sync(lbm_handle *h) {
     int st[ST_WORDS];
     lbm_status s = check_status(h, st);
     if (s != LBM_OK) return s;
-    if (st[ST_UNSTABLE] || st[ST_OVERFLOW] || st[ST_WIDE] || st[ST_SYNC])
-        return fail(h, LBM_E_UNSTABLE, unstable_message(st));
+    if (unstable_flagged(st)) return fail(h, LBM_E_UNSTABLE, unstable_message(st));
     return LBM_OK;
 }
 
@@ -597,9 +859,9 @@ extern "C" lbm_status lbm_sync(lbm_handle *h) {
 static void launch_rho_any(lbm_handle *h, float *dst) {
     const float s0 = shift_of(h, 0), s1 = shift_of(h, 1);
     switch (h->storage) {
-        case 0: launch_rho<0>(h->f[h->cur], dst, h->nx, h->ny, h->nz, h->wall, s0, s1, h->st); break;
-        case 1: launch_rho<1>(h->f[h->cur], dst, h->nx, h->ny, h->nz, h->wall, s0, s1, h->st); break;
-        default: launch_rho<2>(h->f[h->cur], dst, h->nx, h->ny, h->nz, h->wall, s0, s1, h->st); break;
+        case 0: launch_rho<0>(h->f[h->cur], dst, h->nx, h->ny, h->nz, h->wall, h->lz, s0, s1, h->st); break;
+        case 1: launch_rho<1>(h->f[h->cur], dst, h->nx, h->ny, h->nz, h->wall, h->lz, s0, s1, h->st); break;
+        default: launch_rho<2>(h->f[h->cur], dst, h->nx, h->ny, h->nz, h->wall, h->lz, s0, s1, h->st); break;
     }
 }
 
@@ -607,12 +869,12 @@ extern "C" lbm_status lbm_observables(lbm_handle *h, lbm_obs *out) {
     if (!h || !out) return LBM_E_INVAL;
     const float s0 = shift_of(h, 0), s1 = shift_of(h, 1);
     switch (h->storage) {
-        case 0: launch_moments<0>(h->f[h->cur], h->partial, MOM_BLOCKS, h->nx, h->ny, h->nz, h->wall, s0, s1, h->st); break;
-        case 1: launch_moments<1>(h->f[h->cur], h->partial, MOM_BLOCKS, h->nx, h->ny, h->nz, h->wall, s0, s1, h->st); break;
-        default: launch_moments<2>(h->f[h->cur], h->partial, MOM_BLOCKS, h->nx, h->ny, h->nz, h->wall, s0, s1, h->st); break;
+        case 0: launch_moments<0>(h->f[h->cur], h->partial, h->mom_blocks, h->nx, h->ny, h->nz, h->wall, h->lz, s0, s1, h->st); break;
+        case 1: launch_moments<1>(h->f[h->cur], h->partial, h->mom_blocks, h->nx, h->ny, h->nz, h->wall, h->lz, s0, s1, h->st); break;
+        default: launch_moments<2>(h->f[h->cur], h->partial, h->mom_blocks, h->nx, h->ny, h->nz, h->wall, h->lz, s0, s1, h->st); break;
     }
     HIPCHK(h, hipGetLastError());
-    std::vector<double> part((size_t)MOM_BLOCKS * 5);
+    std::vector<double> part((size_t)h->nslab * h->mom_blocks * 5);
     HIPCHK(h, hipMemcpyAsync(part.data(), h->partial, part.size() * sizeof(double), hipMemcpyDeviceToHost, h->st));
     if (out->rho || out->meniscus) {
         launch_rho_any(h, h->rho_tmp);
@@ -620,9 +882,9 @@ extern "C" lbm_status lbm_observables(lbm_handle *h, lbm_obs *out) {
         if (out->rho)
             HIPCHK(h, hipMemcpyAsync(out->rho, h->rho_tmp, 2 * (size_t)h->N * sizeof(float), hipMemcpyDeviceToHost, h->st));
         if (out->meniscus) {
-            launch_meniscus(h->rho_tmp, h->flag, h->men_tmp, h->nx, h->ny, h->nz, h->wall, h->st);
+            launch_meniscus(h->rho_tmp, h->flag, h->men_tmp, h->nx, h->ny, h->nz, h->wall, h->lz, h->st);
             HIPCHK(h, hipGetLastError());
-            HIPCHK(h, hipMemcpyAsync(out->meniscus, h->men_tmp, (size_t)h->nx * h->ny * sizeof(float), hipMemcpyDeviceToHost, h->st));
+            HIPCHK(h, hipMemcpyAsync(out->meniscus, h->men_tmp, (size_t)h->nx * h->ny * h->nslab * sizeof(float), hipMemcpyDeviceToHost, h->st));
         }
     }
     int st[ST_WORDS];
@@ -630,15 +892,24 @@ extern "C" lbm_status lbm_observables(lbm_handle *h, lbm_obs *out) {
     if (s != LBM_OK) return s;
     lbm_summary &sm = out->summary;
     std::memset(&sm, 0, sizeof sm);
-    for (int b = 0; b < MOM_BLOCKS; ++b) {
-        sm.mass[0] += part[5 * b];
-        sm.mass[1] += part[5 * b + 1];
-        for (int d = 0; d < 3; ++d) sm.momentum[d] += part[5 * b + 2 + d];
+    for (int sl = 0; sl < h->nslab; ++sl) {
+        double ms[2] = {0.0, 0.0};
+        for (int b = sl * h->mom_blocks; b < (sl + 1) * h->mom_blocks; ++b) {
+            ms[0] += part[5 * b];
+            ms[1] += part[5 * b + 1];
+            for (int d = 0; d < 3; ++d) sm.momentum[d] += part[5 * b + 2 + d];
+        }
+        sm.mass[0] += ms[0];
+        sm.mass[1] += ms[1];
+        if (out->slab_mass) {
+            out->slab_mass[2 * sl] = ms[0];
+            out->slab_mass[2 * sl + 1] = ms[1];
+        }
     }
     sm.step = h->step;
     sm.lost_reaction = st[ST_LOST];
     sm.n_capsules = (int)h->caps.size();
-    sm.unstable = (st[ST_UNSTABLE] || st[ST_OVERFLOW] || st[ST_WIDE] || st[ST_SYNC]) ? 1 : 0;
+    sm.unstable = unstable_flagged(st) ? 1 : 0;
     if (h->finalized && !h->caps.empty()) {
         std::vector<double4> X(h->ntot);
         std::vector<float4> Fh(h->ntot), R(h->ntot);
@@ -724,7 +995,8 @@ extern "C" lbm_status lbm_labels(lbm_handle *h, uint8_t *out) {
     const int plane = h->nx * h->ny;
     for (int s = 0; s < h->N; ++s) out[s] &= LABEL_MASK;
     if (h->wall)
-        for (int s = 0; s < plane; ++s) out[s] = 255;
+        for (int sl = 0; sl < h->nslab; ++sl)
+            std::memset(out + (size_t)sl * h->lz * plane, 255, (size_t)plane);
     return LBM_OK;
 }
 
@@ -732,11 +1004,11 @@ extern "C" lbm_status lbm_labels(lbm_handle *h, uint8_t *out) {
 // Checkpoints
 // ------------------------------------------------------------------------------------
 namespace {
-// version 2: capsule state without the previous-window fields
-constexpr int32_t CKPT_VERSION = 2;
+// version 3: slab height in the header
+constexpr int32_t CKPT_VERSION = 3;
 struct CkptHeader {
     char magic[8];
-    int32_t version, nx, ny, nz, storage, ncap, ntot, pad;
+    int32_t version, nx, ny, nz, storage, ncap, ntot, lz;
     int64_t step;
 };
 }  // namespace
@@ -764,7 +1036,7 @@ extern "C" lbm_status lbm_save(lbm_handle *h, const char *path) {
     CkptHeader hd{};
     std::memcpy(hd.magic, "LBMXCKP", 8);
     hd.version = CKPT_VERSION; hd.nx = h->nx; hd.ny = h->ny; hd.nz = h->nz; hd.storage = h->storage;
-    hd.ncap = (int)h->caps.size(); hd.ntot = h->ntot; hd.step = h->step;
+    hd.ncap = (int)h->caps.size(); hd.ntot = h->ntot; hd.lz = h->lz; hd.step = h->step;
     bool ok = std::fwrite(&hd, sizeof hd, 1, fp) == 1 && std::fwrite(f.data(), 1, fbytes, fp) == fbytes;
     if (h->ntot)
         ok = ok && std::fwrite(X.data(), sizeof(double4), X.size(), fp) == X.size() &&
@@ -791,6 +1063,7 @@ extern "C" lbm_status lbm_load(lbm_handle *h, const char *path) {
     bool ok = std::fread(&hd, sizeof hd, 1, fp) == 1 && std::memcmp(hd.magic, "LBMXCKP", 8) == 0 &&
               hd.version == CKPT_VERSION && hd.nx == h->nx && hd.ny == h->ny && hd.nz == h->nz &&
               hd.storage == h->storage && hd.ncap == (int)h->caps.size() && hd.ntot == h->ntot &&
+              hd.lz == h->lz &&
               std::fread(f.data(), 1, fbytes, fp) == fbytes;
     if (ok && h->ntot)
         ok = std::fread(X.data(), sizeof(double4), X.size(), fp) == X.size() &&
@@ -820,7 +1093,7 @@ extern "C" lbm_status lbm_load(lbm_handle *h, const char *path) {
 extern "C" lbm_status lbm_set_profiling(lbm_handle *h, int32_t on) {
     if (!h) return LBM_E_INVAL;
     if (on < 0 || on > 2) return fail(h, LBM_E_INVAL, "profiling mode must be 0, 1 or 2");
-    h->profiling = on;
+    h->prof.mode = on;
     return LBM_OK;
 }
 
@@ -828,18 +1101,7 @@ extern "C" lbm_status lbm_kernel_stats(lbm_handle *h, lbm_kernel_stat *out, int3
                                        int32_t *n) {
     if (!h || !n || (max > 0 && !out)) return LBM_E_INVAL;
     HIPCHK(h, hipStreamSynchronize(h->st));
-    collect_timers(h);
-    int k = 0;
-    for (auto &t : h->timers) {
-        if (k >= max) break;
-        std::memset(&out[k], 0, sizeof(lbm_kernel_stat));
-        std::snprintf(out[k].name, sizeof out[k].name, "%s", t.name);
-        out[k].launches = t.launches;
-        out[k].total_ms = t.ms;
-        ++k;
-    }
-    *n = k;
-    for (auto &t : h->timers) { t.launches = 0; t.ms = 0.0; }
+    *n = export_timers(h->prof, out, max);
     return LBM_OK;
 }
 
@@ -848,7 +1110,7 @@ extern "C" double lbm_bytes_per_site(const lbm_handle *h) {
 }
 
 extern "C" int64_t lbm_fluid_sites(const lbm_handle *h) {
-    return h ? (int64_t)h->nx * h->ny * (h->nz - h->wall) : 0;
+    return h ? (int64_t)h->nx * h->ny * (h->nz - h->wall * h->nslab) : 0;
 }
 
 extern "C" const char *lbm_last_error(const lbm_handle *h) {

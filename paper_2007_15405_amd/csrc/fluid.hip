@@ -5,9 +5,12 @@
 // Streaming is "pull": the step at site x gathers f*_i(x - e_i) from the previous state;
 // where x - e_i is the wall layer, half-way bounce-back returns f*_{opp(i)}(x).
 //
-// Every population is read through its own buffer resource (base in scalar registers,
-// 32-bit byte offset per lane), which keeps 64-bit address arithmetic off the vector
-// ALU; out-of-range offsets read 0 and drop stores instead of faulting.
+// Each component's 19 populations are read through one buffer resource (base in scalar
+// registers) with the population's start as the scalar offset and a 32-bit byte offset
+// per lane: no 64-bit address arithmetic on the vector ALU, and few scalar registers
+// (one resource per component instead of one per population, which the compiler would
+// otherwise keep live across the z march).  Out-of-range offsets read 0 and drop stores
+// instead of faulting.  The byte size of one component's populations must fit 32 bits.
 #include "lbm_internal.h"
 
 namespace lbmx {
@@ -35,19 +38,24 @@ __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x);
 // ------------------------------------------------------------------------------------
 template <int S> struct Pop {
     using T = typename Codec<S>::T;
+    // resource of component qg / Q: populations [Q][N] of T
     __device__ static inline __amdgpu_buffer_rsrc_t res(const void *f, int qg, int N) {
         return __builtin_amdgcn_make_buffer_rsrc(
-            (void *)((const T *)f + (size_t)qg * N), (short)0, (int)((uint32_t)N * sizeof(T)),
-            0x00020000);
+            (void *)((const T *)f + (size_t)(qg / Q) * Q * N), (short)0,
+            (int)((uint32_t)Q * (uint32_t)N * sizeof(T)), 0x00020000);
+    }
+    // byte offset of population qg % Q inside its component
+    __device__ static inline uint32_t qoff(int qg, int N) {
+        return (uint32_t)(qg % Q) * (uint32_t)N * (uint32_t)sizeof(T);
     }
     __device__ static inline float load(const void *f, int qg, int N, uint32_t site, float sh) {
         const __amdgpu_buffer_rsrc_t r = res(f, qg, N);
         if constexpr (sizeof(T) == 4) {
-            return Codec<S>::dec(__builtin_bit_cast(
-                                     float, __builtin_amdgcn_raw_buffer_load_b32(r, site * 4u, 0, 0)),
+            return Codec<S>::dec(__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
+                                                               r, site * 4u, qoff(qg, N), 0)),
                                  sh);
         } else {
-            const uint16_t v = __builtin_amdgcn_raw_buffer_load_b16(r, site * 2u, 0, 0);
+            const uint16_t v = __builtin_amdgcn_raw_buffer_load_b16(r, site * 2u, qoff(qg, N), 0);
             return Codec<S>::dec(__builtin_bit_cast(T, v), sh);
         }
     }
@@ -58,11 +66,11 @@ template <int S> struct Pop {
         const __amdgpu_buffer_rsrc_t r = res(f, qg, N);
         const T e = Codec<S>::enc(v, sh);
         if constexpr (sizeof(T) == 4)
-            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, e), r, site * 4u, 0,
-                                                  STORE_NT);
+            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, e), r, site * 4u,
+                                                  qoff(qg, N), STORE_NT);
         else
-            __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, e), r, site * 2u, 0,
-                                                  STORE_NT);
+            __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, e), r, site * 2u,
+                                                  qoff(qg, N), STORE_NT);
     }
 };
 
@@ -298,12 +306,12 @@ __device__ __forceinline__ void sc_general(const FluidArgs &a, const float *cap_
 // ------------------------------------------------------------------------------------
 template <int S>
 __global__ void k_init_eq(const double *__restrict__ rho, void *f, int nx, int ny, int nz,
-                          int wall, float sh0, float sh1) {
+                          int wall, int lz, float sh0, float sh1) {
     const int N = nx * ny * nz;
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= N) return;
     const int z = s / (nx * ny);
-    const bool solid = wall && z == 0;
+    const bool solid = wall && slab_pos(z, lz) == 0;
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         const double w = (double)wq(q);
@@ -313,11 +321,11 @@ __global__ void k_init_eq(const double *__restrict__ rho, void *f, int nx, int n
 }
 
 template <int S>
-void launch_init_eq(const double *rho_dev, void *f, int nx, int ny, int nz, int wall, float s0,
-                    float s1, hipStream_t st) {
+void launch_init_eq(const double *rho_dev, void *f, int nx, int ny, int nz, int wall, int lz,
+                    float s0, float s1, hipStream_t st) {
     const int N = nx * ny * nz;
     hipLaunchKernelGGL(k_init_eq<S>, dim3((N + 255) / 256), dim3(256), 0, st, rho_dev, f, nx, ny,
-                       nz, wall, s0, s1);
+                       nz, wall, lz, s0, s1);
 }
 
 // ------------------------------------------------------------------------------------
@@ -329,10 +337,11 @@ __global__ void __launch_bounds__(256) k_density(FluidArgs a) {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= a.N) return;
     const int x = s % a.nx, t = s / a.nx, y = t % a.ny, z = t / a.ny;
-    if (a.wall && z == 0) return;
+    const int zr = slab_pos(z, a.lz);
+    if (a.wall && zr == 0) return;
     float fl[2][Q], r0, r1;
-    pull<S, true>(a.fin, a.N, x, y, z, a.nx, a.ny, a.nz, a.wall && z == 1,
-                  a.wall && z == a.nz - 1, a.shift[0], a.shift[1], fl, r0, r1);
+    pull<S, true>(a.fin, a.N, x, y, z, a.nx, a.ny, a.nz, a.wall && zr == 1,
+                  a.wall && zr == a.lz - 1, a.shift[0], a.shift[1], fl, r0, r1);
     a.psi[s] = psi_of(r0, a.inv_rho0);
     a.psi[a.N + s] = psi_of(r1, a.inv_rho0);
 }
@@ -343,9 +352,10 @@ __global__ void __launch_bounds__(256) k_collide(FluidArgs a) {
     if (s >= a.N) return;
     const int nx = a.nx, ny = a.ny, nz = a.nz, N = a.N;
     const int x = s % nx, t = s / nx, y = t % ny, z = t / ny;
-    if (a.wall && z == 0) return;
+    const int zr = slab_pos(z, a.lz);
+    if (a.wall && zr == 0) return;
     float fl[2][Q], r0, r1, m[8];
-    pull<S, false>(a.fin, N, x, y, z, nx, ny, nz, a.wall && z == 1, a.wall && z == nz - 1,
+    pull<S, false>(a.fin, N, x, y, z, nx, ny, nz, a.wall && zr == 1, a.wall && zr == a.lz - 1,
                    a.shift[0], a.shift[1], fl, r0, r1);
     site_moments(fl, m);
     const uint8_t fg = a.flag[s];
@@ -356,7 +366,7 @@ __global__ void __launch_bounds__(256) k_collide(FluidArgs a) {
     for (int q = 1; q < Q; ++q) {
         const int xn = wrap1(x + CX[q], nx), yn = wrap1(y + CY[q], ny), zn = wrap1(z + CZ[q], nz);
         const int sn = (zn * ny + yn) * nx + xn;
-        const bool solid_n = a.wall && zn == 0;
+        const bool solid_n = a.wall && slab_pos(zn, a.lz) == 0;
         nlab[q - 1] = solid_n ? LABEL_WALL : (a.flag[sn] & LABEL_MASK);
         p0n[q - 1] = solid_n ? 0.f : a.psi[sn];
         p1n[q - 1] = solid_n ? 0.f : a.psi[N + sn];
@@ -438,9 +448,9 @@ __global__ void __launch_bounds__(TX * TY) k_fused(FluidArgs a, int zc, int tile
     auto plane = [&](int p, float (&cur)[2][KQ], float (&mc)[8], float (&nxt)[2][KQ],
                      float (&mn)[8]) {
         const int slot = (p - z0 + 1) % 3;
-        const int pz = wrapn(p, nz);
-        const bool solid = a.wall && pz == 0;
-        const bool wlo = a.wall && pz == 1, whi = a.wall && pz == nz - 1;
+        const int pz = wrapn(p, nz), pr = slab_pos(pz, a.lz);
+        const bool solid = a.wall && pr == 0;
+        const bool wlo = a.wall && pr == 1, whi = a.wall && pr == a.lz - 1;
         uint8_t fg_me;
         {
             float fl[2][Q], r0 = 0.f, r1 = 0.f;
@@ -470,7 +480,7 @@ __global__ void __launch_bounds__(TX * TY) k_fused(FluidArgs a, int zc, int tile
         const int busy0 = __syncthreads_or((fg_me | fg_h) != 0);
         const int pc = p - 1;
         const int cz = wrapn(pc, nz);
-        if (pc >= z0 && valid && !(a.wall && cz == 0)) {
+        if (pc >= z0 && valid && !(a.wall && slab_pos(cz, a.lz) == 0)) {
             const int sc = (p - z0) % 3, sd = (p - z0 + 2) % 3;   // planes p - 1 and p - 2
             const uint32_t s = (uint32_t)((cz * ny + iy) * nx + ix);
             const float psi0 = s_psi[sc][0][li], psi1 = s_psi[sc][1][li];
@@ -595,9 +605,11 @@ __device__ __forceinline__ void collide_store_eq(const FluidArgs &a, const float
         atomicAdd(&a.status[ST_LOST], 1);
 }
 
+// One workgroup's tile: logical block L of a lattice tiled tiles_x x tiles_y x (z chunks
+// of zc planes).
 template <int S, int TX, int TY, bool WX>
-__global__ void __launch_bounds__(TX * TY) k_fused_pipe(FluidArgs a, int zc, int tiles_x,
-                                                        int tiles_y, int nblocks) {
+__device__ __forceinline__ void pipe_tile(const FluidArgs &a, int L, int zc, int tiles_x,
+                                          int tiles_y) {
     constexpr int NT = TX * TY, LX = TX + 2, LY = TY + 2, NL = LX * LY;
     constexpr int NH = WX ? 2 * TX : NL - NT;
     constexpr int NW = NT / 64;
@@ -607,9 +619,6 @@ __global__ void __launch_bounds__(TX * TY) k_fused_pipe(FluidArgs a, int zc, int
     __shared__ int s_busy[4][NW];
     __shared__ float s_drho[MAX_CAPS];
 
-    const int per = (int)gridDim.x / 8;
-    const int L = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
-    if (L >= nblocks) return;
     const int bx = L % tiles_x, t2 = L / tiles_x, by = t2 % tiles_y, bz = t2 / tiles_y;
     const int nx = a.nx, ny = a.ny, nz = a.nz, N = a.N;
     const int x0 = bx * TX, y0 = by * TY, z0 = bz * zc, z1 = min(z0 + zc, nz);
@@ -685,13 +694,17 @@ __global__ void __launch_bounds__(TX * TY) k_fused_pipe(FluidArgs a, int zc, int
         const bool any = __builtin_amdgcn_ballot_w64((fg_me | fg_h) != 0) != 0;
         if (lane == 0) s_busy[slot][wave] = any ? 1 : 0;
     };
-    // issue the pulls and flag reads of plane p (tile site, and the halo site of the
-    // first NH threads)
-    auto issue = [&](int p, float (&fl)[2][Q], float (&hf)[2][Q], uint8_t &g_me, uint8_t &g_h) {
+    // slab position of a plane (uniform), stepped along with the planes instead of divided
+    const int lz = a.lz;
+    auto fwd = [&](int r, int k) { r += k; return r >= lz ? r - lz : r; };
+    // issue the pulls and flag reads of plane p at slab position pr (tile site, and the
+    // halo site of the first NH threads)
+    auto issue = [&](int p, int pr, float (&fl)[2][Q], float (&hf)[2][Q], uint8_t &g_me,
+                     uint8_t &g_h) {
         const int pz = wrapn(p, nz);
-        const bool wlo = a.wall && pz == 1, whi = a.wall && pz == nz - 1;
+        const bool wlo = a.wall && pr == 1, whi = a.wall && pr == lz - 1;
         g_me = g_h = 0;
-        if (!(a.wall && pz == 0)) {
+        if (!(a.wall && pr == 0)) {
             g_me = a.flag[(pz * ny + iy) * nx + ix];
             pull_issue<S>(a.fin, N, ix, iy, pz, nx, ny, nz, wlo, whi, sh0, sh1, fl);
             if (hi >= 0) {
@@ -700,31 +713,31 @@ __global__ void __launch_bounds__(TX * TY) k_fused_pipe(FluidArgs a, int zc, int
             }
         }
     };
-    auto load_plane = [&](int p, float (&m)[8], float4 &ibv) {
+    auto load_plane = [&](int p, int pr, float (&m)[8], float4 &ibv) {
         float fl[2][Q], hf[2][Q];
         uint8_t g_me, g_h;
-        issue(p, fl, hf, g_me, g_h);
-        const int pz = wrapn(p, nz);
-        publish(p, a.wall && pz == 0, pz, fl, hf, g_me, g_h, m, ibv);
+        issue(p, pr, fl, hf, g_me, g_h);
+        publish(p, a.wall && pr == 0, wrapn(p, nz), fl, hf, g_me, g_h, m, ibv);
     };
 
     float m0[8], m1[8], m2[8];   // moments of planes p, p+1, p+2
     float4 ib0, ib1, ib2;        // spread force of this thread's site in planes p, p+1
-    load_plane(z0 - 1, m2, ib2);
-    load_plane(z0, m0, ib0);
-    load_plane(z0 + 1, m1, ib1);
+    int rz = slab_pos(z0, lz);   // slab position of plane p
+    load_plane(z0 - 1, fwd(rz, lz - 1), m2, ib2);
+    load_plane(z0, rz, m0, ib0);
+    load_plane(z0 + 1, fwd(rz, 1), m1, ib1);
     __syncthreads();
-    for (int p = z0; p < z1; ++p) {
+    for (int p = z0; p < z1; ++p, rz = fwd(rz, 1)) {
         // issue the pulls of plane p+2 first; they complete while plane p is collided
         const bool more = p + 2 <= z1;
         float fl[2][Q], hf[2][Q];
         uint8_t g_me = 0, g_h = 0;
-        const int pn = wrapn(p + 2, nz);
-        const bool nsolid = a.wall && pn == 0;
-        if (more) issue(p + 2, fl, hf, g_me, g_h);
+        const int pn = wrapn(p + 2, nz), rn = fwd(rz, 2);
+        const bool nsolid = a.wall && rn == 0;
+        if (more) issue(p + 2, rn, fl, hf, g_me, g_h);
         // ---- collide plane p ----
         const int cz = wrapn(p, nz);
-        if (valid && !(a.wall && cz == 0)) {
+        if (valid && !(a.wall && rz == 0)) {
             const int sc = (p - z0 + 4) & 3, su = (p - z0 + 5) & 3, sd = (p - z0 + 3) & 3;
             // the tile-plane takes the general path if any label, window or wall flag lies
             // in its ring planes p - 1 .. p + 1 (all waves meet at the same barrier anyway)
@@ -777,6 +790,58 @@ __global__ void __launch_bounds__(TX * TY) k_fused_pipe(FluidArgs a, int zc, int
     }
     (void)m2;
     (void)ib2;
+}
+
+// XCD-aware renumbering: hardware block b runs on XCD b % 8; each XCD gets a contiguous
+// run of logical tiles, which share its L2 for the halo re-reads
+__device__ __forceinline__ int logical_block() {
+    const int per = (int)gridDim.x / 8;
+    return (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+}
+
+template <int S, int TX, int TY, bool WX>
+__global__ void __launch_bounds__(TX * TY) k_fused_pipe(FluidArgs a, int zc, int tiles_x,
+                                                        int tiles_y, int nblocks) {
+    const int L = logical_block();
+    if (L >= nblocks) return;
+    pipe_tile<S, TX, TY, WX>(a, L, zc, tiles_x, tiles_y);
+}
+
+// Several lattices in one launch: group g owns the logical blocks desc[g].x ..
+// desc[g + 1].x - 1, tiled desc[g].y x desc[g].z columns with z chunks of desc[g].w planes.
+// The tables are read-only for the kernel's lifetime, so they are read through the
+// constant address space (scalar loads).
+typedef __attribute__((address_space(4))) const int ConstInt;
+
+template <int S, int TX, int TY>
+__global__ void __launch_bounds__(TX * TY) k_fused_pipe_multi(const FluidArgs *tab,
+                                                              const int4 *desc, int ngroups,
+                                                              int nblocks) {
+    static_assert(sizeof(FluidArgs) % 4 == 0, "word copy");
+    const int L = logical_block();
+    if (L >= nblocks) return;
+    ConstInt *cd = (ConstInt *)desc;   // int4 rows
+    int g = 0;
+    while (g + 1 < ngroups && L >= cd[4 * (g + 1)]) ++g;
+    FluidArgs a;
+    ConstInt *src = (ConstInt *)(tab + g);
+    int *dst = reinterpret_cast<int *>(&a);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(FluidArgs) / 4); ++i) dst[i] = src[i];
+    pipe_tile<S, TX, TY, false>(a, L - cd[4 * g], cd[4 * g + 3], cd[4 * g + 1], cd[4 * g + 2]);
+}
+
+template <int S>
+void launch_fluid_multi(const FluidArgs *tab, const int4 *desc, int ngroups, int nblocks,
+                        int tile, hipStream_t st) {
+    const dim3 grid((nblocks + 7) / 8 * 8);
+    switch (tile) {
+        case 6: hipLaunchKernelGGL((k_fused_pipe_multi<S, 32, 8>), grid, dim3(256), 0, st, tab, desc, ngroups, nblocks); break;
+        case 7: hipLaunchKernelGGL((k_fused_pipe_multi<S, 64, 4>), grid, dim3(256), 0, st, tab, desc, ngroups, nblocks); break;
+        case 8: hipLaunchKernelGGL((k_fused_pipe_multi<S, 16, 16>), grid, dim3(256), 0, st, tab, desc, ngroups, nblocks); break;
+        case 9: hipLaunchKernelGGL((k_fused_pipe_multi<S, 32, 16>), grid, dim3(512), 0, st, tab, desc, ngroups, nblocks); break;
+        default: hipLaunchKernelGGL((k_fused_pipe_multi<S, 64, 8>), grid, dim3(512), 0, st, tab, desc, ngroups, nblocks); break;
+    }
 }
 
 template <int S, int TX, int TY, bool WX = false>
@@ -837,13 +902,13 @@ void launch_fluid_tiled(const FluidArgs &a, int tile, int zc, hipStream_t st) {
 // ------------------------------------------------------------------------------------
 template <int S>
 __global__ void k_rho(const void *f, float *__restrict__ rho, int nx, int ny, int nz, int wall,
-                      float sh0, float sh1) {
+                      int lz, float sh0, float sh1) {
     const int N = nx * ny * nz;
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= N) return;
     const int z = s / (nx * ny);
     float r0 = 0.f, r1 = 0.f;
-    if (!(wall && z == 0)) {
+    if (!(wall && slab_pos(z, lz) == 0)) {
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             r0 += Pop<S>::load(f, q, N, s, wq(q) * sh0);
@@ -855,11 +920,11 @@ __global__ void k_rho(const void *f, float *__restrict__ rho, int nx, int ny, in
 }
 
 template <int S>
-void launch_rho(const void *f, float *rho, int nx, int ny, int nz, int wall, float s0, float s1,
-                hipStream_t st) {
+void launch_rho(const void *f, float *rho, int nx, int ny, int nz, int wall, int lz, float s0,
+                float s1, hipStream_t st) {
     const int N = nx * ny * nz;
     hipLaunchKernelGGL(k_rho<S>, dim3((N + 255) / 256), dim3(256), 0, st, f, rho, nx, ny, nz, wall,
-                       s0, s1);
+                       lz, s0, s1);
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -869,15 +934,18 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // mass^c and fluid momentum, double accumulation; one partial row of 5 per block.
+// Block (b, sl) sums sites of slab sl only.
 template <int S>
 __global__ void __launch_bounds__(256) k_moments(const void *f, double *__restrict__ partial,
-                                                 int nx, int ny, int nz, int wall, float sh0,
-                                                 float sh1) {
-    const int N = nx * ny * nz;
+                                                 int nx, int ny, int nz, int wall, int lz,
+                                                 float sh0, float sh1) {
+    const int N = nx * ny * nz, plane = nx * ny;
+    const int s_end = (blockIdx.y + 1) * lz * plane;
     double acc[5] = {0, 0, 0, 0, 0};
-    for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < N; s += gridDim.x * blockDim.x) {
-        const int z = s / (nx * ny);
-        if (wall && z == 0) continue;
+    for (int s = blockIdx.y * lz * plane + blockIdx.x * blockDim.x + threadIdx.x; s < s_end;
+         s += gridDim.x * blockDim.x) {
+        const int z = s / plane;
+        if (wall && slab_pos(z, lz) == 0) continue;
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             const double v0 = Pop<S>::load(f, q, N, s, wq(q) * sh0);
@@ -900,28 +968,30 @@ __global__ void __launch_bounds__(256) k_moments(const void *f, double *__restri
     if (threadIdx.x < 5) {
         double v = 0;
         for (int w = 0; w < (int)(blockDim.x >> 6); ++w) v += red[w][threadIdx.x];
-        partial[blockIdx.x * 5 + threadIdx.x] = v;
+        partial[(blockIdx.y * gridDim.x + blockIdx.x) * 5 + threadIdx.x] = v;
     }
 }
 
 template <int S>
 void launch_moments(const void *f, double *partial, int nblocks, int nx, int ny, int nz, int wall,
-                    float s0, float s1, hipStream_t st) {
-    hipLaunchKernelGGL(k_moments<S>, dim3(nblocks), dim3(256), 0, st, f, partial, nx, ny, nz, wall,
-                       s0, s1);
+                    int lz, float s0, float s1, hipStream_t st) {
+    hipLaunchKernelGGL(k_moments<S>, dim3(nblocks, nz / lz), dim3(256), 0, st, f, partial, nx, ny,
+                       nz, wall, lz, s0, s1);
 }
 
-// Meniscus height per column: the first upward crossing of
-// phi = (rho0 - rho1) / (rho0 + rho1) from >= 0 to < 0, linearly interpolated; NaN if
-// none or if either site of the crossing lies inside a capsule.
+// Meniscus height per column of each slab: the first upward crossing of
+// phi = (rho0 - rho1) / (rho0 + rho1) from >= 0 to < 0 above the slab's wall layer,
+// linearly interpolated; NaN if none or if either site of the crossing lies inside a
+// capsule.
 __global__ void k_meniscus(const float *__restrict__ rho, const uint8_t *__restrict__ flag,
-                           float *__restrict__ out, int nx, int ny, int nz, int wall) {
-    const int col = blockIdx.x * blockDim.x + threadIdx.x;
-    if (col >= nx * ny) return;
-    const int N = nx * ny * nz, plane = nx * ny;
+                           float *__restrict__ out, int nx, int ny, int nz, int wall, int lz) {
+    const int plane = nx * ny, N = plane * nz;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= plane * (nz / lz)) return;
+    const int col = idx % plane, base = (idx / plane) * lz * plane;
     float res = __builtin_nanf("");
-    for (int k = wall ? 1 : 0; k + 1 < nz; ++k) {
-        const int s0 = k * plane + col, s1 = s0 + plane;
+    for (int k = wall ? 1 : 0; k + 1 < lz; ++k) {
+        const int s0 = base + k * plane + col, s1 = s0 + plane;
         const double a0 = rho[s0], b0 = rho[N + s0], a1 = rho[s1], b1 = rho[N + s1];
         const double p0 = (a0 - b0) / (a0 + b0), p1 = (a1 - b1) / (a1 + b1);
         if (p0 >= 0.0 && p1 < 0.0) {
@@ -930,24 +1000,27 @@ __global__ void k_meniscus(const float *__restrict__ rho, const uint8_t *__restr
             break;
         }
     }
-    out[col] = res;
+    out[idx] = res;
 }
 
 void launch_meniscus(const float *rho, const uint8_t *flag, float *out, int nx, int ny, int nz,
-                     int wall, hipStream_t st) {
-    hipLaunchKernelGGL(k_meniscus, dim3((nx * ny + 255) / 256), dim3(256), 0, st, rho, flag, out,
-                       nx, ny, nz, wall);
+                     int wall, int lz, hipStream_t st) {
+    const int cols = nx * ny * (nz / lz);
+    hipLaunchKernelGGL(k_meniscus, dim3((cols + 255) / 256), dim3(256), 0, st, rho, flag, out,
+                       nx, ny, nz, wall, lz);
 }
 
 #define LBMX_INST(S)                                                                        \
-    template void launch_init_eq<S>(const double *, void *, int, int, int, int, float, float, \
-                                    hipStream_t);                                           \
+    template void launch_init_eq<S>(const double *, void *, int, int, int, int, int, float,  \
+                                    float, hipStream_t);                                    \
     template void launch_fluid<S>(const FluidArgs &, hipStream_t);                          \
     template void launch_fluid_tiled<S>(const FluidArgs &, int, int, hipStream_t);          \
-    template void launch_rho<S>(const void *, float *, int, int, int, int, float, float,     \
+    template void launch_fluid_multi<S>(const FluidArgs *, const int4 *, int, int, int,       \
+                                        hipStream_t);                                         \
+    template void launch_rho<S>(const void *, float *, int, int, int, int, int, float, float, \
                                 hipStream_t);                                               \
-    template void launch_moments<S>(const void *, double *, int, int, int, int, int, float,  \
-                                    float, hipStream_t);
+    template void launch_moments<S>(const void *, double *, int, int, int, int, int, int,    \
+                                    float, float, hipStream_t);
 LBMX_INST(0)
 LBMX_INST(1)
 LBMX_INST(2)

@@ -40,9 +40,14 @@ constexpr int FILL_COLS = 2048;   // window columns (x * y) the spreading kernel
 
 // status words (device): [0] unstable flag, [1] lost reaction count, [2] window overflow,
 // [3] window wider than the spreading plane buffer, [4] a cross-block capsule reduction
-// read partial sums of another step (memory ordering failure; never expected)
+// read partial sums of another step (memory ordering failure; never expected), [5] a
+// capsule window left the slab of its capsule
 constexpr int ST_UNSTABLE = 0, ST_LOST = 1, ST_OVERFLOW = 2, ST_WIDE = 3, ST_SYNC = 4,
-              ST_WORDS = 5;
+              ST_SLAB = 5, ST_WORDS = 6;
+
+// Slabs: with a wall, the lattice is a stack of boxes of lz planes, each starting with a
+// solid layer (lz = nz: one box).  Position of plane z inside its slab.
+__host__ __device__ inline int slab_pos(int z, int lz) { return z % lz; }
 
 // ------------------------------------------------------------------------------------
 // Population storage codec.  S = 0: FP32 as is.  S = 1: FP16 of f - w_i rho_s.
@@ -90,6 +95,7 @@ struct FluidArgs {
     const float *cap_drho;  // [MAX_CAPS] wetting offset per capsule
     int nx, ny, nz, wall;
     int N;                  // nx * ny * nz
+    int lz;                 // slab height (nz: one box)
     float tau[2], inv_tau[2];
     float G;                // coupling
     float ws_axis, ws_diag; // stencil weights sc_norm * omega_i
@@ -106,6 +112,8 @@ struct CapDev {
     int node0, nn;          // first node, node count
     int tri0, nt;           // first triangle, triangle count
     float ks, C, kv, anchor_k;
+    float plane_z;          // repulsive plane of the capsule's slab
+    int zbase;              // wall layer of the capsule's slab
     double v0;              // reference volume
     double c0[3];           // reference centroid
 };
@@ -156,20 +164,29 @@ struct MembraneArgs {
     const float4 *uo, *ro;
     int *status;
     int nx, ny, nz, wall;
-    float hertz_xi, hertz_d0, plane_z;
+    int lz;                 // slab height (nz: one box)
+    float hertz_xi, hertz_d0;
 };
 
 // Launchers (host functions, defined in the .hip files).
 template <int S> void launch_init_eq(const double *rho_dev, void *f, int nx, int ny, int nz,
-                                     int wall, float s0, float s1, hipStream_t st);
+                                     int wall, int lz, float s0, float s1, hipStream_t st);
 template <int S> void launch_fluid(const FluidArgs &a, hipStream_t st);
 template <int S> void launch_fluid_tiled(const FluidArgs &a, int tile, int zc, hipStream_t st);
+// One launch of the pipelined fluid kernel over several lattices (device tables: the
+// arguments of each lattice, and per lattice {first logical block, tiles in x, tiles in
+// y, z planes per chunk}); tile 6..10 as launch_fluid_tiled.
+template <int S> void launch_fluid_multi(const FluidArgs *tab, const int4 *desc, int ngroups,
+                                         int nblocks, int tile, hipStream_t st);
 template <int S> void launch_rho(const void *f, float *rho, int nx, int ny, int nz, int wall,
-                                 float s0, float s1, hipStream_t st);
+                                 int lz, float s0, float s1, hipStream_t st);
+// partial sums [nz / lz][nblocks][5] (mass of both components, momentum) per slab
 template <int S> void launch_moments(const void *f, double *partial, int nblocks, int nx, int ny,
-                                     int nz, int wall, float s0, float s1, hipStream_t st);
+                                     int nz, int wall, int lz, float s0, float s1,
+                                     hipStream_t st);
+// meniscus heights [nz / lz][ny][nx], measured from each slab's wall layer
 void launch_meniscus(const float *rho, const uint8_t *flag, float *out, int nx, int ny, int nz,
-                     int wall, hipStream_t st);
+                     int wall, int lz, hipStream_t st);
 
 int reduce_chunks(int max_work);
 void launch_capsule_reduce(const MembraneArgs &m, hipStream_t st);

@@ -242,6 +242,10 @@ __global__ void __launch_bounds__(RED_BLK) k_capsule_reduce(MembraneArgs m) {
             s_lo[d] = fa - 1;
             s_dim[d] = dim;
         }
+        // stacked slabs: the window must stay between the wall layers of its slab, or it
+        // would reach the fluid of the neighbouring slab
+        if (m.lz < m.nz && (cs.lo[2] < cd.zbase || cs.lo[2] + cs.dim[2] - 1 > cd.zbase + m.lz))
+            atomicOr(&m.status[ST_SLAB], 1);
         m.cst[k] = cs;
     }
     __syncthreads();
@@ -432,16 +436,16 @@ __global__ void __launch_bounds__(MEM_BLK) k_membrane(MembraneArgs m, int ntot, 
     const int kb[2] = {m.node_cap[nb0], m.node_cap[nb1]};
     __syncthreads();
     if (m.hertz_xi > 0.f) {
-        // Hertz partner capsules: those whose node bounding box comes within delta0 of the
-        // bounding box of the block's capsule (periodic images; every pair closer than
-        // delta0 passes, so the per-node search below loses nothing)
+        // Hertz partner capsules: those of the same slab whose node bounding box comes
+        // within delta0 of the bounding box of the block's capsule (periodic images; every
+        // pair closer than delta0 passes, so the per-node search below loses nothing)
         const bool per[3] = {true, true, !m.wall};
         const int nd[3] = {m.nx, m.ny, m.nz};
         const float d0 = m.hertz_d0, slack = 1e-3f;
         for (int i = threadIdx.x; i < 2 * m.ncap; i += MEM_BLK) {
             const int w = i / m.ncap, j = i - w * m.ncap;
             const CapState &A = s_cst[kb[w]], &B = s_cst[j];
-            bool near = j != kb[w];
+            bool near = j != kb[w] && m.caps[j].zbase == m.caps[kb[w]].zbase;
             for (int d = 0; d < 3 && near; ++d) {
                 const float ha = 0.5f * (A.bmax[d] - A.bmin[d]), hb = 0.5f * (B.bmax[d] - B.bmin[d]);
                 float dc = 0.5f * (A.bmin[d] + A.bmax[d]) - 0.5f * (B.bmin[d] + B.bmax[d]);
@@ -492,7 +496,7 @@ __global__ void __launch_bounds__(MEM_BLK) k_membrane(MembraneArgs m, int ntot, 
     }
     const float xi = m.hertz_xi, d0 = m.hertz_d0;
     if (sl == 0 && m.wall && xi > 0.f) {
-        const float d = (float)(X.z - (double)m.plane_z);
+        const float d = (float)(X.z - (double)cd.plane_z);
         if (d < d0) fh[2] += xi * (d0 - d) * sqrtf(d0 - d);
     }
     if (xi > 0.f) {
@@ -512,7 +516,7 @@ __global__ void __launch_bounds__(MEM_BLK) k_membrane(MembraneArgs m, int ntot, 
         const int w = k == kb[0] ? 0 : 1, nj = listed ? s_nnear[w] : m.ncap;
         for (int jj = 0; jj < nj; ++jj) {
             const int j = listed ? s_near[w][jj] : jj;
-            if (j == k) continue;
+            if (j == k || (!listed && m.caps[j].zbase != cd.zbase)) continue;
             const CapState &cj = s_cst[j];
             double pl[3];   // this node in the periodic image closest to window j
             bool far = false, small = true;
@@ -724,7 +728,7 @@ __global__ void __launch_bounds__(256) k_window_combine(MembraneArgs m) {
     __syncthreads();
     const int nwin = s_n;
     const int uz = ck.lo[2] + lz, z = wrap_near(uz, m.nz);
-    if (m.wall && z == 0) return;   // wall sites receive nothing (uniform over the block)
+    if (m.wall && slab_pos(z, m.lz) == 0) return;   // wall sites receive nothing (uniform)
     for (int col = tid; col < dx * dy; col += blockDim.x) {
         const int ly = col / dx, lx = col - ly * dx;
         const int ux = ck.lo[0] + lx, uy = ck.lo[1] + ly;
@@ -769,7 +773,7 @@ __device__ __forceinline__ void node_update_one(const MembraneArgs &m, int n, in
     const int bx = (int)floor(X.x) - 1, by = (int)floor(X.y) - 1, bz = (int)floor(X.z) - 1;
     float U[3] = {0.f, 0.f, 0.f}, Rr[3] = {0.f, 0.f, 0.f};
     const int z = wrap_near(bz + oz, m.nz);
-    if (!(m.wall && z == 0)) {
+    if (!(m.wall && slab_pos(z, m.lz) == 0)) {
         const float wyz = phi4((float)(X.y - (double)(by + oy))) *
                           phi4((float)(X.z - (double)(bz + oz)));
         const int row = (z * m.ny + wrap_near(by + oy, m.ny)) * m.nx;

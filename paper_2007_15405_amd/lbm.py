@@ -37,7 +37,8 @@ class Params(C.Structure):
         ("rho_iface", C.c_double), ("init_rho_array", C.POINTER(C.c_double)),
         ("hertz_xi", C.c_double), ("hertz_delta0", C.c_double), ("plane_dz", C.c_double),
         ("rho_shift", C.c_double * 2), ("stream", C.c_void_p), ("device", C.c_int32),
-        ("stream_given", C.c_int32),
+        ("stream_given", C.c_int32), ("slab_nz", C.c_int32),
+        ("slab_film_height", C.POINTER(C.c_double)),
     ]
 
 
@@ -61,7 +62,8 @@ class Summary(C.Structure):
 
 class Obs(C.Structure):
     _fields_ = [("rho", C.POINTER(C.c_float)), ("meniscus", C.POINTER(C.c_float)),
-                ("capsules", C.POINTER(CapsuleObs)), ("summary", Summary)]
+                ("capsules", C.POINTER(CapsuleObs)), ("slab_mass", C.POINTER(C.c_double)),
+                ("summary", Summary)]
 
 
 class KernelStat(C.Structure):
@@ -89,6 +91,13 @@ SIGNATURES = {
     "lbm_fluid_sites": (C.c_int64, [H]),
     "lbm_last_error": (C.c_char_p, [H]),
     "lbm_destroy": (None, [H]),
+    "lbm_batch_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(C.c_void_p)]),
+    "lbm_batch_set_launch": (C.c_int, [H, C.c_int32, C.c_int32]),
+    "lbm_batch_step": (C.c_int, [H, C.c_int64]),
+    "lbm_batch_set_profiling": (C.c_int, [H, C.c_int32]),
+    "lbm_batch_kernel_stats": (C.c_int, [H, C.POINTER(KernelStat), C.c_int32, C.POINTER(C.c_int32)]),
+    "lbm_batch_last_error": (C.c_char_p, [H]),
+    "lbm_batch_destroy": (None, [H]),
 }
 
 _LIB = None
@@ -137,6 +146,8 @@ class Sim:
     """One simulation on the GPU, configured by a dict as made by ``synth.workload``.
 
     ``storage`` is ``"f32"``, ``"f16"`` or ``"bf16"`` (16-bit modes store f - w rho_shift).
+    ``cfg["slab_nz"]`` (0: one box) stacks independent boxes of that height along z, with
+    ``cfg["slab_film_height"]`` (or None) their film heights.
     ``stream``: ``"torch"`` (default: torch's current stream if a GPU is visible), ``None``
     (a stream of the library's own) or a raw hipStream_t integer."""
 
@@ -146,6 +157,8 @@ class Sim:
         self.L = load_library()
         self.cfg = cfg
         self.nx, self.ny, self.nz = cfg["nx"], cfg["ny"], cfg["nz"]
+        self.lz = cfg.get("slab_nz", 0) or self.nz
+        self.n_slabs = self.nz // self.lz
         p = Params()
         p.nx, p.ny, p.nz, p.wall_z0 = self.nx, self.ny, self.nz, int(cfg["wall_z0"])
         p.tau[0], p.tau[1] = cfg["tau"]
@@ -164,6 +177,13 @@ class Sim:
             if keep.shape != (2, self.nz, self.ny, self.nx):
                 raise ValueError("init_rho_array must be [2][nz][ny][nx]")
             p.init_rho_array = _dp(keep)
+        p.slab_nz = int(cfg.get("slab_nz", 0))
+        films = None
+        if cfg.get("slab_film_height") is not None:
+            films = np.ascontiguousarray(cfg["slab_film_height"], dtype=np.float64)
+            if films.shape != (self.n_slabs,):
+                raise ValueError("slab_film_height needs one value per slab")
+            p.slab_film_height = _dp(films)
         p.hertz_xi, p.hertz_delta0 = cfg["hertz_xi"], cfg["hertz_delta0"]
         p.plane_dz = cfg["plane_dz"]
         p.rho_shift[0], p.rho_shift[1] = rho_shift
@@ -215,8 +235,10 @@ class Sim:
             r = np.zeros((2, self.nz, self.ny, self.nx), np.float32)
             o.rho = r.ctypes.data_as(C.POINTER(C.c_float))
         if meniscus:
-            m = np.zeros((self.ny, self.nx), np.float32)
+            m = np.zeros((self.n_slabs, self.ny, self.nx), np.float32)
             o.meniscus = m.ctypes.data_as(C.POINTER(C.c_float))
+        sm = np.zeros((self.n_slabs, 2))
+        o.slab_mass = _dp(sm)
         nc = len(self.n_nodes)
         if capsules and nc:
             caps = (CapsuleObs * nc)()
@@ -229,10 +251,12 @@ class Sim:
             mass=np.array(s.mass), momentum=np.array(s.momentum), pending=np.array(s.pending),
             step=s.step, lost_reaction=s.lost_reaction, n_capsules=s.n_capsules,
             unstable=s.unstable))
+        out["slab_mass"] = sm
         if rho:
             out["rho"] = r
         if meniscus:
-            out["meniscus"] = m
+            # one box: [ny][nx]; stacked slabs: [n_slabs][ny][nx], heights above each wall
+            out["meniscus"] = m[0] if self.n_slabs == 1 else m
         if caps is not None:
             out["capsules"] = [dict(centroid=np.array(c.centroid), volume=c.volume,
                                     f_anchor=np.array(c.f_anchor),
@@ -302,6 +326,65 @@ class Sim:
         if getattr(self, "h", None):
             self.L.lbm_destroy(self.h)
             self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Several ``Sim`` objects stepped together, one fluid launch per step over all their
+    lattices (``lbm_batch_*``).  The sims must share stream and storage and have tau = 1;
+    close the batch before them."""
+
+    def __init__(self, sims: list, tile: int = 10, zchunk: int = 0):
+        self.L = load_library()
+        self.sims = list(sims)
+        arr = (C.c_void_p * len(self.sims))(*[s.h.value for s in self.sims])
+        b = C.c_void_p()
+        st = self.L.lbm_batch_create(arr, len(self.sims), C.byref(b))
+        if st != LBM_OK:
+            raise LbmError(st, self.L.lbm_batch_last_error(None).decode())
+        self.b = b
+        self.set_launch(tile, zchunk)
+
+    def _check(self, st: int):
+        if st != LBM_OK:
+            raise LbmError(st, self.L.lbm_batch_last_error(self.b).decode())
+
+    def set_launch(self, tile: int = 10, zchunk: int = 0):
+        self._check(self.L.lbm_batch_set_launch(self.b, int(tile), int(zchunk)))
+
+    def step(self, n: int = 1):
+        self._check(self.L.lbm_batch_step(self.b, int(n)))
+
+    def sync(self):
+        for s in self.sims:
+            s.sync()
+
+    def set_profiling(self, on=True):
+        self._check(self.L.lbm_batch_set_profiling(self.b, int(on)))
+
+    def kernel_stats(self) -> dict:
+        arr = (KernelStat * 32)()
+        n = C.c_int32()
+        self._check(self.L.lbm_batch_kernel_stats(self.b, arr, 32, C.byref(n)))
+        return {arr[i].name.decode(): (arr[i].launches, arr[i].total_ms) for i in range(n.value)}
+
+    @property
+    def fluid_sites(self) -> int:
+        return sum(s.fluid_sites for s in self.sims)
+
+    @property
+    def bytes_per_site(self) -> float:
+        return self.sims[0].bytes_per_site
+
+    def close(self):
+        if getattr(self, "b", None):
+            self.L.lbm_batch_destroy(self.b)
+            self.b = None
 
     def __del__(self):
         try:

@@ -155,6 +155,7 @@ _BASE = dict(
     film_height=0.0, rho_maj=0.7, rho_min=0.04, rho_iface=0.3,
     init_rho_array=None,
     hertz_xi=1.5, hertz_delta0=1.5, plane_dz=0.0,
+    slab_nz=0, slab_film_height=None,
     capsules=[], steps=1,
 )
 

@@ -1,0 +1,185 @@
+"""GPU parity of the batched form: independent runs stacked as slabs of one lattice, and
+several lattices advanced by one fluid launch (lbm_batch_*).
+
+* Stacked slabs: each slab of a stacked lattice is compared with the oracle running that
+  slab as a box of its own (same film, capsule shifted to the box's frame), to the
+  tolerances of the plain parity tests (densities relative L2 <= 1e-5 after 200 steps,
+  nodes 1e-4, meniscus 1e-3, mass 1e-5).  It is also compared with the library running
+  the same box alone: the per-site arithmetic is the same, so results agree bit for bit.
+* Batches: a batch of three lattices of different sizes (one with stacked slabs) ends in
+  the state each handle reaches when stepped alone, also across a handle stepped outside
+  the batch in between; one member is checked against the oracle.  The batched kernel is
+  a separately compiled copy of the same per-site arithmetic, and the backend may fuse a
+  few multiply-adds differently in it (about one ulp): densities agree to 1e-6 relative,
+  as between the launch shapes of the fluid kernel, and nodes to 1e-5.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel_l2(a, b):
+    return [float(np.linalg.norm(a[c] - b[c]) / np.linalg.norm(b[c])) for c in range(2)]
+
+
+def _sim(cfg, **kw):
+    from paper_2007_15405_amd import Sim
+    return Sim(cfg, **kw)
+
+
+def shifted(cap, dz):
+    c = dict(cap)
+    c["center"] = [cap["center"][0], cap["center"][1], cap["center"][2] + dz]
+    return c
+
+
+# three slabs of 32 x 28 x 20 (28 is not a multiple of the tile height): films of 6, 9
+# and 12 layers; a wetting capsule straddling the film in slab 0, none in slab 1, and a
+# capsule pressed against its repulsive plane (Hertz active) in slab 2
+NX, NY, LZ = 32, 28, 20
+FILMS = [6.0, 9.0, 12.0]
+SLAB_CAPS = {0: [synth.capsule((10.3, 14.2, 7.6), 4.0, 320, 0.02, wet_drho=0.05)],
+             1: [],
+             2: [synth.capsule((20.6, 9.1, 7.4), 4.0, 320, 0.05, anchor_k=0.5)]}
+
+
+def box_cfg(s):
+    """Slab s as a box of its own."""
+    return synth.workload("pf", nx=NX, ny=NY, nz=LZ, film_height=FILMS[s], plane_dz=2.0,
+                          capsules=SLAB_CAPS[s])
+
+
+def stacked_cfg():
+    caps = [shifted(c, s * LZ) for s in range(3) for c in SLAB_CAPS[s]]
+    return synth.workload("pf", nx=NX, ny=NY, nz=3 * LZ, slab_nz=LZ, slab_film_height=FILMS,
+                          plane_dz=2.0, capsules=caps)
+
+
+@pytest.mark.parametrize("tile", [10, 1])
+def test_stacked_slabs_match_the_oracle_box_by_box(tile):
+    steps = 200
+    say("stacked 3 x", (NX, NY, LZ), "tile", tile, "steps", steps)
+    g = _sim(stacked_cfg())
+    g.set_launch(tile, 4)     # z chunks of 4 planes: slab boundaries are chunk boundaries
+    g.step(steps)
+    ob = g.observables(rho=True, meniscus=True)
+    assert ob["summary"]["unstable"] == 0 and ob["summary"]["lost_reaction"] == 0
+    rho = ob["rho"].reshape(2, 3, LZ, NY, NX)
+    k = 0
+    for s in range(3):
+        cfg = box_cfg(s)
+        o = oracle.Oracle(cfg)
+        o.step(steps)
+        e = rel_l2(rho[:, s], o.rho())
+        say("slab", s, "rel-L2 vs oracle", e)
+        assert max(e) <= 1e-5
+        so = o.summary()
+        assert np.all(np.abs(ob["slab_mass"][s] - so["mass"]) / so["mass"] < 1e-5)
+        mo, mg = o.meniscus(), ob["meniscus"][s]
+        assert np.array_equal(np.isnan(mg), np.isnan(mo))
+        ok = ~np.isnan(mo)
+        assert ok.sum() > 100 and np.abs(mg[ok] - mo[ok]).max() <= 1e-3
+        for j in range(len(SLAB_CAPS[s])):
+            cg, co = ob["capsules"][k], o.capsule(j)
+            dz = np.array([0.0, 0.0, s * LZ])
+            assert np.abs(cg["centroid"] - dz - co["centroid"]).max() <= 1e-4
+            assert np.abs(g.nodes(k) - dz - o.nodes(j)).max() <= 1e-4
+            for f in ("f_capillary", "f_hertz", "f_anchor"):
+                assert np.linalg.norm(cg[f] - co[f]) <= 1e-3 * max(np.linalg.norm(co[f]), 1e-3)
+            if s == 2:
+                assert abs(co["f_hertz"][2]) > 1e-3       # the plane contact is active
+            k += 1
+        # the same box run alone by the library: identical arithmetic, identical result
+        a = _sim(cfg)
+        a.set_launch(tile, 4)
+        a.step(steps)
+        assert np.array_equal(rho[:, s], a.rho())
+        a.close()
+    lab = g.labels().reshape(3, LZ, NY, NX)
+    assert np.all(lab[:, 0] == 255)
+    g.close()
+
+
+def test_capsule_window_must_stay_inside_its_slab():
+    from paper_2007_15405_amd import LbmError
+    g = _sim(synth.workload("pf", nx=NX, ny=NY, nz=2 * LZ, slab_nz=LZ, capsules=[]))
+    for cz in (LZ - 3.0, LZ + 2.5):     # window through the wall layer above / below
+        cap = synth.capsule((16.0, 14.0, cz), 3.0, 320, 0.02)
+        nodes, tris = synth.capsule_mesh(cap)
+        with pytest.raises(LbmError) as ei:
+            g.add_capsule(cap, nodes, tris)
+        assert ei.value.status == -1
+    cap = synth.capsule((16.0, 14.0, LZ + 8.0), 3.0, 320, 0.02)
+    g.add_capsule(cap, *synth.capsule_mesh(cap))
+    g.close()
+
+
+def batch_members():
+    a = stacked_cfg()                                      # 32 x 28 x 60, three slabs
+    b = synth.workload("pf", nx=48, ny=40, nz=24, film_height=8.0, plane_dz=2.0,
+                       capsules=[synth.capsule((30.5, 12.2, 8.3), 4.0, 320, 0.05,
+                                               anchor_k=0.5),
+                                 synth.capsule((20.1, 20.7, 9.1), 4.0, 320, 0.02)])
+    c = synth.workload("pf", nx=40, ny=16, nz=36, slab_nz=12, film_height=5.0, capsules=[])
+    return [a, b, c]
+
+
+def test_batch_equals_handles_stepped_alone():
+    from paper_2007_15405_amd import Batch
+    cfgs = batch_members()
+    sims = [_sim(c) for c in cfgs]
+    refs = [_sim(c) for c in cfgs]
+    for x in sims + refs:
+        x.set_launch(10, 4)   # for the step taken outside the batch, and the references
+    bt = Batch(sims, tile=10, zchunk=4)
+    say("batch of", [(c["nx"], c["ny"], c["nz"], c["slab_nz"]) for c in cfgs])
+    bt.step(31)
+    sims[1].step(1)           # a member stepped on its own: the batch rebuilds its tables
+    bt.step(30)
+    for i, r in enumerate(refs):
+        r.step(62 if i == 1 else 61)
+    for i, (s, r) in enumerate(zip(sims, refs)):
+        a, b = s.rho(), r.rho()
+        d = float(np.abs(a - b).max())
+        say("member", i, "max |diff| vs alone", d)
+        assert d <= 1e-6 * float(np.abs(b).max())
+        for k in range(len(cfgs[i]["capsules"])):
+            assert np.abs(s.nodes(k) - r.nodes(k)).max() <= 1e-5
+        assert s.summary()["step"] == r.summary()["step"]
+    o = oracle.Oracle(cfgs[1])
+    o.step(62)
+    e = rel_l2(sims[1].rho(), o.rho())
+    say("member 1 vs oracle", e)
+    assert max(e) <= 1e-5
+    for k in range(2):
+        assert np.abs(sims[1].nodes(k) - o.nodes(k)).max() <= 1e-4
+    bt.set_launch(6, 8)       # another tile and z chunk: the same result up to rounding
+    bt.step(5)
+    for i, r in enumerate(refs):
+        r.step(5)
+        a, b = sims[i].rho(), r.rho()
+        d = float(np.abs(a - b).max())
+        say("member", i, "tile 6 zchunk 8: max |diff|", d)
+        assert d <= 1e-6 * float(np.abs(b).max())
+    bt.close()
+
+
+def test_batch_rejects_unequal_relaxation_times():
+    from paper_2007_15405_amd import Batch, LbmError
+    a = _sim(synth.workload("pf", nx=8, ny=8, nz=8, capsules=[]))
+    b = _sim(synth.workload("pf", nx=8, ny=8, nz=8, capsules=[], tau=[0.8, 1.0]))
+    with pytest.raises(LbmError):
+        Batch([a, b])
+    with pytest.raises(LbmError):
+        Batch([a, a])

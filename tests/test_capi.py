@@ -99,3 +99,42 @@ def test_null_handles_are_rejected():
     assert L.lbm_observables(None, None) == lbm.LBM_E_INVAL
     assert L.lbm_bytes_per_site(None) == 0.0
     L.lbm_destroy(None)
+
+
+@pytest.mark.parametrize("nz,slab,wall,msg", [
+    (30, 7, 1, "slab_nz"),       # does not divide nz
+    (30, 2, 1, "slab_nz"),       # too thin
+    (30, 10, 0, "wall_z0"),      # stacked slabs need their wall layers
+])
+def test_invalid_slabs_are_rejected_on_the_host(nz, slab, wall, msg):
+    L = pkg.load_library()
+    p = lbm.Params()
+    p.nx = p.ny = 8
+    p.nz, p.slab_nz, p.wall_z0 = nz, slab, wall
+    p.tau[0] = p.tau[1] = 1.0
+    p.rho0 = 1.0
+    h = C.c_void_p()
+    assert L.lbm_init(C.byref(p), C.byref(h)) == lbm.LBM_E_INVAL and not h.value
+    assert msg in L.lbm_last_error(None).decode()
+
+
+def test_lattice_beyond_32_bit_population_offsets_is_rejected():
+    L = pkg.load_library()
+    p = lbm.Params()
+    p.nx, p.ny, p.nz = 512, 512, 216      # 56.6 M sites: 19 x 4 B x N > 4 GiB
+    p.tau[0] = p.tau[1] = 1.0
+    p.rho0 = 1.0
+    h = C.c_void_p()
+    assert L.lbm_init(C.byref(p), C.byref(h)) == lbm.LBM_E_INVAL
+    assert "too large" in L.lbm_last_error(None).decode()
+
+
+def test_batch_without_handles_is_rejected():
+    L = pkg.load_library()
+    b = C.c_void_p()
+    assert L.lbm_batch_create(None, 0, C.byref(b)) == lbm.LBM_E_INVAL and not b.value
+    arr = (C.c_void_p * 2)(None, None)
+    assert L.lbm_batch_create(arr, 2, C.byref(b)) == lbm.LBM_E_INVAL
+    assert "NULL" in L.lbm_batch_last_error(None).decode()
+    assert L.lbm_batch_step(None, 1) == lbm.LBM_E_INVAL
+    L.lbm_batch_destroy(None)
