@@ -8,7 +8,9 @@ membrane forces, spreading, fused fluid step, interpolation/advection).
 Prints one JSON line: MLUPS (fluid-site updates per microsecond, both components count
 as one update) for FP32 population storage, the HBM roofline of the dominant kernel
 (the fluid step) measured with HIP events on the library's stream, the same figures for
-the shifted FP16 / BF16 storage, and the CPU oracle timed on a bounded sample.
+the shifted FP16 / BF16 storage, the batched form (64 independent capsule-pair boxes of
+sizes 80x60x40 .. 128x96x48, stacked by size into slabs, one fluid launch per step over
+all of them; FP32 and FP16 storage), and the CPU oracle timed on a bounded sample.
 """
 import argparse
 import json
@@ -24,7 +26,7 @@ PEAK_HBM_GBS = 8000.0
 # HBM bytes per launch of the fused fluid kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE,
 # scaled by the same counters on a plain 1 GiB copy (profiles/fluid_c3_f32_hbm_traffic.md),
 # keyed by (storage, tile, zchunk).  Reported only for the launch shape it was taken on.
-MEASURED_TRAFFIC_BYTES = {("f32", 10, 48): 2.0421e9}
+MEASURED_TRAFFIC_BYTES = {("f32", 11, 48): 2.0270e9}
 WORKLOAD = "film 256x256x96, wall, 16 capsules R=10 (5120 tri), ks=0.05"
 
 
@@ -112,6 +114,75 @@ def run_gpu(cfg, storage, steps, warmup, do_tune=True, launch=None):
     return out
 
 
+def run_batch(storage, steps, warmup, do_tune=True):
+    """The batched form: every group of equal box size is one handle of stacked slabs,
+    and one Batch advances all groups with one fluid launch per step."""
+    import torch
+
+    import synth
+    from paper_2007_15405_amd import Batch, Sim
+
+    inst = synth.batch_instances()
+    groups = synth.batch_groups(inst)
+    sims = [Sim(g, storage=storage, stream="torch", meshes=synth.capsule_meshes(g["capsules"]))
+            for g in groups]
+    bt = Batch(sims)
+    stream = torch.cuda.current_stream()
+    best = None
+    for tile in ((6, 7, 8, 9, 10) if do_tune else (10,)):
+        for zc in ((0, 16, 24, 32, 48) if do_tune else (0,)):
+            bt.set_launch(tile, zc)
+            bt.step(2)
+            bt.set_profiling(2)
+            bt.step(10)
+            n, ms = bt.kernel_stats()["fluid"]
+            bt.set_profiling(0)
+            t = ms / n
+            print(f"#   batch {storage} tune tile {TILES[tile]:>10s} zchunk {zc:2d}: fluid "
+                  f"{t * 1e3:8.1f} us", file=sys.stderr, flush=True)
+            if best is None or t < best[0]:
+                best = (t, tile, zc)
+    bt.set_launch(best[1], best[2])
+    bt.step(warmup)
+    bt.sync()
+    bt.kernel_stats()
+    bt.set_profiling(2)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    bt.step(steps)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    bt.sync()
+    ms = t0.elapsed_time(t1)
+    n, fms = bt.kernel_stats()["fluid"]
+    bt.set_profiling(1)
+    bt.step(min(steps, 20))
+    breakdown = bt.kernel_stats()
+    bt.set_profiling(0)
+    sites, bps = bt.fluid_sites, bt.bytes_per_site
+    fl_avg = fms / n
+    achieved = bps * sites / (fl_avg * 1e-3) / 1e9
+    out = dict(
+        workload=f"{len(inst)} capsule-pair boxes {min(g['nx'] for g in groups)}x"
+                 f"{min(g['ny'] for g in groups)}x40 .. 128x96x48, R=10 (5120 tri), ks "
+                 f"log-uniform 0.002..0.2, stacked into {len(groups)} groups of equal size",
+        instances=len(inst), groups=len(groups), capsules=sum(len(g["capsules"]) for g in groups),
+        fluid_sites=sites, storage=storage,
+        mlups=round(sites * steps / (ms * 1e-3) / 1e6, 2), ms_per_step=round(ms / steps, 5),
+        fluid_ms=round(fl_avg, 5), bytes_per_site=bps, achieved_gbs=round(achieved, 1),
+        frac=round(achieved / PEAK_HBM_GBS, 4),
+        launch=dict(tile=TILES[best[1]], tile_id=best[1], zchunk=best[2]),
+        kernels_ms={k: round(v[1] / max(v[0], 1) * (1 if k == "fluid" else len(groups)), 5)
+                    for k, v in breakdown.items()},
+    )
+    bt.close()
+    for x in sims:
+        x.close()
+    return out
+
+
 def cpu_baseline(cfg, steps=10):
     import oracle
     cores = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
@@ -136,6 +207,8 @@ def main():
     ap.add_argument("--storage", default="all", choices=["all", "f32", "f16", "bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched form")
+    ap.add_argument("--batch-only", action="store_true", help="only the batched form")
     ap.add_argument("--tile", type=int, default=None, help="fixed launch shape (skips tuning)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MB",
                     help="only run a plain device copy of MB megabytes (counter calibration)")
@@ -163,6 +236,18 @@ def main():
     import synth
     cfg = synth.workload("c3")
     res = {}
+    batched = {}
+    if not args.no_batch:
+        for st in (["f32", "f16"] if args.storage == "all" else [args.storage]):
+            batched[st] = run_batch(st, min(args.steps, 100), min(args.warmup, 10),
+                                    not args.no_tune)
+            b = batched[st]
+            print(f"# batch {st}: {b['mlups']:.1f} MLUPS, {b['ms_per_step']:.4f} ms/step, fluid "
+                  f"{b['fluid_ms']:.4f} ms = {b['achieved_gbs']:.0f} GB/s", file=sys.stderr,
+                  flush=True)
+    if args.batch_only:
+        print(json.dumps(dict(batched=batched)), flush=True)
+        return
     for st in (["f32", "f16", "bf16"] if args.storage == "all" else [args.storage]):
         fixed = (args.tile, args.zchunk) if args.tile is not None else None
         res[st] = run_gpu(cfg, st, args.steps, args.warmup, not args.no_tune and fixed is None, fixed)
@@ -202,6 +287,7 @@ def main():
                                   frac=round(v["frac"], 4), bytes_per_site=v["bytes_per_site"],
                                   launch=v["launch"])
                           for k, v in res.items()},
+        batched=batched or None,
     )
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(cfg)

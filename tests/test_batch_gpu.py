@@ -183,3 +183,42 @@ def test_batch_rejects_unequal_relaxation_times():
         Batch([a, b])
     with pytest.raises(LbmError):
         Batch([a, a])
+
+
+def test_full_batch_workload_sampled_instances():
+    """The batched workload the benchmark times (64 capsule-pair boxes in 8 groups of
+    stacked slabs, one batch), a few steps, in its default launch shape; the first and the
+    last instance against the oracle running them as boxes of their own."""
+    from paper_2007_15405_amd import Batch
+    inst = synth.batch_instances()
+    groups = synth.batch_groups(inst)
+    say("batch workload:", len(inst), "instances in", len(groups), "groups")
+    sims = [_sim(g, meshes=synth.capsule_meshes(g["capsules"])) for g in groups]
+    bt = Batch(sims)
+    steps = 3
+    bt.step(steps)
+    bt.sync()
+    for k in (0, len(inst) - 1):
+        gi = next(j for j, g in enumerate(groups) if k in g["instances"])
+        g, sim = groups[gi], sims[gi]
+        s = g["instances"].index(k)
+        lz = g["slab_nz"]
+        ob = sim.observables(rho=True)
+        rho = ob["rho"].reshape(2, -1, lz, g["ny"], g["nx"])[:, s]
+        i = inst[k]
+        cfg = synth.workload("c2", nx=i["nx"], ny=i["ny"], nz=i["nz"],
+                             film_height=i["film_height"], capsules=i["capsules"])
+        o = oracle.Oracle(cfg)
+        o.step(steps)
+        e = rel_l2(rho, o.rho())
+        say("instance", k, "box", (i["nx"], i["ny"], i["nz"]), "slab", s, "of group", gi,
+            "rel-L2", e)
+        assert max(e) <= 1e-6
+        for j in range(2):
+            cg = ob["capsules"][2 * s + j]
+            co = o.capsule(j)
+            assert np.abs(cg["centroid"] - np.array([0, 0, s * lz]) - co["centroid"]).max() <= 1e-5
+            assert np.linalg.norm(cg["f_capillary"] - co["f_capillary"]) <= \
+                1e-3 * max(np.linalg.norm(co["f_capillary"]), 1e-3)
+        assert ob["summary"]["lost_reaction"] == 0
+    bt.close()
