@@ -174,8 +174,7 @@ def run_batch(storage, steps, warmup, do_tune=True):
         fluid_ms=round(fl_avg, 5), bytes_per_site=bps, achieved_gbs=round(achieved, 1),
         frac=round(achieved / PEAK_HBM_GBS, 4),
         launch=dict(tile=TILES[best[1]], tile_id=best[1], zchunk=best[2]),
-        kernels_ms={k: round(v[1] / max(v[0], 1) * (1 if k == "fluid" else len(groups)), 5)
-                    for k, v in breakdown.items()},
+        kernels_ms={k: round(v[1] / max(v[0], 1), 5) for k, v in breakdown.items()},
     )
     bt.close()
     for x in sims:

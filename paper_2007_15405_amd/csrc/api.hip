@@ -70,8 +70,7 @@ struct lbm_handle {
     int4 *d_tri = nullptr;
     float4 *d_minv = nullptr;
     float *d_a0 = nullptr;
-    int *d_off = nullptr, *d_list = nullptr, *d_rowstart = nullptr, *d_slot = nullptr,
-        *d_counter = nullptr;
+    int *d_off = nullptr, *d_list = nullptr, *d_rowstart = nullptr, *d_slot = nullptr;
     double4 *d_xrow = nullptr;
     unsigned long long *d_marks = nullptr;
     CapPartial *d_part = nullptr;
@@ -117,7 +116,7 @@ static void free_all(lbm_handle *h) {
                     h->rho_tmp, h->men_tmp, h->status, h->partial, h->d_caps, h->d_cst, h->d_X,
                     h->d_node_cap, h->d_F, h->d_Fh, h->d_R, h->d_tri, h->d_minv, h->d_a0,
                     h->d_off, h->d_list, h->d_marks, h->d_rowstart, h->d_slot, h->d_wbuf,
-                    h->d_wpar, h->d_part, h->d_counter, h->d_xrow};
+                    h->d_wpar, h->d_part, h->d_xrow};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     free_prof(h->prof);
@@ -509,7 +508,6 @@ static lbm_status finalize(lbm_handle *h) {
         dalloc(&h->d_off, nt + 1) != hipSuccess || dalloc(&h->d_list, list.size()) != hipSuccess ||
         dalloc(&h->d_marks, (size_t)ncap * ROWS_MAX) != hipSuccess ||
         dalloc(&h->d_part, (size_t)ncap * h->nch) != hipSuccess ||
-        dalloc(&h->d_counter, ncap) != hipSuccess ||
         dalloc(&h->d_rowstart, (size_t)ncap * (ROWS_MAX + 1)) != hipSuccess ||
         dalloc(&h->d_slot, nt) != hipSuccess || dalloc(&h->d_xrow, nt) != hipSuccess ||
         dalloc(&h->d_wbuf, (size_t)ncap * GMAX3) != hipSuccess ||
@@ -528,7 +526,6 @@ static lbm_status finalize(lbm_handle *h) {
     HIPCHK(h, hipMemcpyAsync(h->d_off, off.data(), (nt + 1) * sizeof(int), hipMemcpyHostToDevice, h->st));
     HIPCHK(h, hipMemcpyAsync(h->d_list, list.data(), list.size() * sizeof(int), hipMemcpyHostToDevice, h->st));
     HIPCHK(h, hipMemsetAsync(h->d_marks, 0, (size_t)ncap * ROWS_MAX * sizeof(unsigned long long), h->st));
-    HIPCHK(h, hipMemsetAsync(h->d_counter, 0, ncap * sizeof(int), h->st));
     HIPCHK(h, hipMemsetAsync(h->d_rowstart, 0, (size_t)ncap * (ROWS_MAX + 1) * sizeof(int), h->st));
     HIPCHK(h, hipMemsetAsync(h->d_slot, 0, nt * sizeof(int), h->st));
     HIPCHK(h, hipMemsetAsync(h->d_xrow, 0, nt * sizeof(double4), h->st));
@@ -547,7 +544,7 @@ static MembraneArgs membrane_args(lbm_handle *h) {
     m.tri = h->d_tri; m.minv = h->d_minv; m.a0 = h->d_a0;
     m.ntri_off = h->d_off; m.ntri = h->d_list;
     m.marks = h->d_marks; m.rowstart = h->d_rowstart; m.xrow = h->d_xrow; m.slot = h->d_slot;
-    m.part = h->d_part; m.counter = h->d_counter; m.nch = h->nch;
+    m.part = h->d_part; m.nch = h->nch;
     m.wbuf = h->d_wbuf; m.wpar = h->d_wpar;
     m.flag = h->flag; m.ibm = h->ibm; m.uo = h->uo; m.ro = h->ro; m.status = h->status;
     m.nx = h->nx; m.ny = h->ny; m.nz = h->nz; m.wall = h->wall; m.lz = h->lz;
@@ -643,8 +640,8 @@ extern "C" lbm_status lbm_step(lbm_handle *h, int64_t n) {
 }
 
 // ------------------------------------------------------------------------------------
-// Batches: several handles advanced together, with one launch of the fluid kernel over
-// all their lattices per step
+// Batches: several handles advanced together, with one launch of each kernel over all
+// their lattices and capsules per step
 // ------------------------------------------------------------------------------------
 struct lbm_batch {
     std::vector<lbm_handle *> hs;
@@ -654,11 +651,18 @@ struct lbm_batch {
     int tile = 10, zchunk = 0;
     FluidArgs *d_tab = nullptr;    // [2][n]: arguments for parity 0 and 1 of the buffers
     int4 *d_desc = nullptr;        // [n + 1] first logical block, tiles x, tiles y, zchunk
-    std::vector<int> cur0;         // buffer index of each handle at parity 0
+    MembraneArgs *d_mtab = nullptr;  // [groups] capsule-kernel arguments of the handles
+    MGroup *d_mgrp = nullptr;        // with capsules, and their places in the launches
+    MGroupTotals mtot{};
+    int nmg = 0;                   // handles with capsules
+    std::vector<int64_t> step0;    // step count of each handle when the tables were written
+    int64_t since = 0;             // batch steps since then
     bool dirty = true;
-    int par = 0, nblocks = 0;
+    int nblocks = 0;
     Prof prof;
 };
+
+extern "C" void lbm_batch_destroy(lbm_batch *b);
 
 static lbm_status bfail(lbm_batch *b, lbm_status s, const std::string &m) {
     b->err = m;
@@ -681,10 +685,29 @@ static lbm_status batch_tables(lbm_batch *b) {
     const int zc = batch_zchunk(b, 48);
     std::vector<FluidArgs> tab(2 * (size_t)n);
     std::vector<int4> desc(n + 1);
+    std::vector<MembraneArgs> mtab;
+    std::vector<MGroup> mgrp;
+    MGroupTotals t{};
     int start = 0;
     for (int g = 0; g < n; ++g) {
         lbm_handle *h = b->hs[g];
-        b->cur0[g] = h->cur;
+        b->step0[g] = h->step;
+        if (!h->caps.empty()) {
+            MGroup mg{};
+            mg.cap0 = t.ncap;
+            mg.mem0 = t.mem_blocks;
+            mg.upd0 = t.upd_blocks;
+            mg.ntot = h->ntot;
+            mg.ttot = h->ttot;
+            mg.nbu = node_update_blocks(h->ntot);
+            mg.epoch0 = (int)(h->step & 0x7fffffff);
+            t.ncap += (int)h->caps.size();
+            t.mem_blocks += membrane_blocks(h->ntot, h->ttot, &mg.nbf);
+            t.upd_blocks += mg.nbu;
+            t.nch_max = std::max(t.nch_max, h->nch);
+            mtab.push_back(membrane_args(h));
+            mgrp.push_back(mg);
+        }
         tab[g] = fluid_args(h, h->cur);
         tab[n + g] = fluid_args(h, 1 - h->cur);
         const int tx = (h->nx + TILE_X[b->tile] - 1) / TILE_X[b->tile];
@@ -694,11 +717,15 @@ static lbm_status batch_tables(lbm_batch *b) {
     }
     desc[n] = make_int4(start, 0, 0, 0);
     b->nblocks = start;
-    b->par = 0;
+    b->since = 0;
+    b->nmg = (int)mgrp.size();
+    b->mtot = t;
     // the previous tables may still be read by enqueued launches
     if (hipStreamSynchronize(b->st) != hipSuccess ||
         hipMemcpy(b->d_tab, tab.data(), tab.size() * sizeof(FluidArgs), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(b->d_desc, desc.data(), desc.size() * sizeof(int4), hipMemcpyHostToDevice) != hipSuccess)
+        hipMemcpy(b->d_desc, desc.data(), desc.size() * sizeof(int4), hipMemcpyHostToDevice) != hipSuccess ||
+        (b->nmg && (hipMemcpy(b->d_mtab, mtab.data(), mtab.size() * sizeof(MembraneArgs), hipMemcpyHostToDevice) != hipSuccess ||
+                    hipMemcpy(b->d_mgrp, mgrp.data(), mgrp.size() * sizeof(MGroup), hipMemcpyHostToDevice) != hipSuccess)))
         return bfail(b, LBM_E_DEVICE, "batch table upload failed");
     b->dirty = false;
     return LBM_OK;
@@ -728,10 +755,14 @@ extern "C" lbm_status lbm_batch_create(lbm_handle *const *handles, int32_t n, lb
     b->hs.assign(handles, handles + n);
     b->st = handles[0]->st;
     b->storage = handles[0]->storage;
-    b->cur0.assign(n, 0);
-    if (dalloc(&b->d_tab, 2 * (size_t)n) != hipSuccess || dalloc(&b->d_desc, (size_t)n + 1) != hipSuccess) {
-        if (b->d_tab) (void)hipFree(b->d_tab);
-        delete b;
+    b->step0.assign(n, 0);
+    const bool ok = hipSetDevice(handles[0]->p.device) == hipSuccess &&
+                    dalloc(&b->d_tab, 2 * (size_t)n) == hipSuccess &&
+                    dalloc(&b->d_desc, (size_t)n + 1) == hipSuccess &&
+                    dalloc(&b->d_mtab, (size_t)n) == hipSuccess &&
+                    dalloc(&b->d_mgrp, (size_t)n) == hipSuccess;
+    if (!ok) {
+        lbm_batch_destroy(b);
         g_init_error = "device allocation failed (batch)";
         return LBM_E_NOMEM;
     }
@@ -757,26 +788,29 @@ extern "C" lbm_status lbm_batch_step(lbm_batch *b, int64_t n) {
             lbm_status s = finalize(h);
             if (s != LBM_OK) return bfail(b, s, h->err);
         }
-    // the tables hold both buffer parities; a handle stepped on its own since they were
-    // written needs new ones
+    // the tables hold both buffer parities and the step stamps; a handle stepped on its
+    // own since they were written needs new ones
     for (int g = 0; g < ng && !b->dirty; ++g)
-        if ((b->hs[g]->cur ^ b->cur0[g]) != (b->hs[0]->cur ^ b->cur0[0])) b->dirty = true;
+        if (b->hs[g]->step != b->step0[g] + b->since) b->dirty = true;
     if (b->dirty) {
         lbm_status s = batch_tables(b);
         if (s != LBM_OK) return s;
     }
-    b->par = b->hs[0]->cur ^ b->cur0[0];
-    std::vector<MembraneArgs> ms(ng);
-    for (int g = 0; g < ng; ++g)
-        if (!b->hs[g]->caps.empty()) ms[g] = membrane_args(b->hs[g]);
+    const MGroupTotals &mt = b->mtot;
     for (int64_t i = 0; i < n; ++i) {
-        for (int g = 0; g < ng; ++g) {
-            lbm_handle *h = b->hs[g];
-            if (h->caps.empty()) continue;
-            ms[g].epoch = (int)(h->step & 0x7fffffff);
-            capsule_kernels_before(h, ms[g], b->prof);
+        const int de = (int)(b->since & 0x7fffffff);
+        if (b->nmg) {
+            timed(b->prof, b->st, "capsule_reduce", [&] {
+                launch_capsule_reduce_multi(b->d_mtab, b->d_mgrp, b->nmg, mt, de, b->st);
+            });
+            timed(b->prof, b->st, "membrane", [&] {
+                launch_membrane_multi(b->d_mtab, b->d_mgrp, b->nmg, mt, b->st);
+            });
+            timed(b->prof, b->st, "window_fill", [&] {
+                launch_window_fill_multi(b->d_mtab, b->d_mgrp, b->nmg, mt, b->st);
+            });
         }
-        const FluidArgs *tab = b->d_tab + (size_t)b->par * ng;
+        const FluidArgs *tab = b->d_tab + (size_t)(b->since & 1) * ng;
         timed(b->prof, b->st, "fluid", [&] {
             switch (b->storage) {
                 case 0: launch_fluid_multi<0>(tab, b->d_desc, ng, b->nblocks, b->tile, b->st); break;
@@ -784,14 +818,15 @@ extern "C" lbm_status lbm_batch_step(lbm_batch *b, int64_t n) {
                 default: launch_fluid_multi<2>(tab, b->d_desc, ng, b->nblocks, b->tile, b->st); break;
             }
         });
-        for (int g = 0; g < ng; ++g) {
-            lbm_handle *h = b->hs[g];
-            if (!h->caps.empty())
-                timed(b->prof, b->st, "node_update", [&] { launch_node_update(ms[g], h->ntot, h->st); });
+        if (b->nmg)
+            timed(b->prof, b->st, "node_update", [&] {
+                launch_node_update_multi(b->d_mtab, b->d_mgrp, b->nmg, mt, b->st);
+            });
+        for (lbm_handle *h : b->hs) {
             h->cur = 1 - h->cur;
             h->step++;
         }
-        b->par ^= 1;
+        b->since++;
     }
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return bfail(b, LBM_E_DEVICE, std::string("batch step: ") + hipGetErrorString(e));
@@ -820,8 +855,9 @@ extern "C" const char *lbm_batch_last_error(const lbm_batch *b) {
 extern "C" void lbm_batch_destroy(lbm_batch *b) {
     if (!b) return;
     if (b->st) (void)hipStreamSynchronize(b->st);
-    if (b->d_tab) (void)hipFree(b->d_tab);
-    if (b->d_desc) (void)hipFree(b->d_desc);
+    void *ptrs[] = {b->d_tab, b->d_desc, b->d_mtab, b->d_mgrp};
+    for (void *q : ptrs)
+        if (q) (void)hipFree(q);
     free_prof(b->prof);
     delete b;
 }

@@ -39,9 +39,9 @@ constexpr int ROWS_MAX = GMAX * GMAX;
 constexpr int FILL_COLS = 2048;   // window columns (x * y) the spreading kernel holds in LDS
 
 // status words (device): [0] unstable flag, [1] lost reaction count, [2] window overflow,
-// [3] window wider than the spreading plane buffer, [4] a cross-block capsule reduction
-// read partial sums of another step (memory ordering failure; never expected), [5] a
-// capsule window left the slab of its capsule
+// [3] window wider than the spreading plane buffer, [4] the capsule reduction read
+// partial sums of another step (never expected), [5] a capsule window left the slab of
+// its capsule
 constexpr int ST_UNSTABLE = 0, ST_LOST = 1, ST_OVERFLOW = 2, ST_WIDE = 3, ST_SYNC = 4,
               ST_SLAB = 5, ST_WORDS = 6;
 
@@ -154,7 +154,6 @@ struct MembraneArgs {
     double4 *xrow;          // [Ntot] node positions grouped by row (any order in a row)
     int *slot;              // [Ntot] place of node n in the row order (global index)
     CapPartial *part;       // [ncap][nch] partial sums of the capsule reduction
-    int *counter;           // [ncap] blocks of the reduction done (reset by the last one)
     int nch;                // reduction blocks per capsule
     int epoch;              // step index (low 32 bits)
     float4 *wbuf;           // [ncap][GMAX3] own spread force and coverage per window site
@@ -187,6 +186,28 @@ template <int S> void launch_moments(const void *f, double *partial, int nblocks
 // meniscus heights [nz / lz][ny][nx], measured from each slab's wall layer
 void launch_meniscus(const float *rho, const uint8_t *flag, float *out, int nx, int ny, int nz,
                      int wall, int lz, hipStream_t st);
+
+// Capsule kernels of several simulations in one launch each (see membrane.hip): per
+// group (simulation with capsules) its first capsule, membrane block and node-update
+// block in the launches, node and triangle counts, force-block count, node-update block
+// count and the step stamp of its reductions when the tables were written.
+struct MGroup {
+    int cap0, mem0, upd0, ntot, ttot, nbf, nbu, epoch0;
+};
+struct MGroupTotals {
+    int ncap, nch_max, mem_blocks, upd_blocks;
+};
+int membrane_blocks(int ntot, int ttot, int *nb_forces);
+int node_update_blocks(int ntot);
+// de: steps since the tables were written (added to each group's epoch0)
+void launch_capsule_reduce_multi(const MembraneArgs *tab, const MGroup *grp, int ng,
+                                 const MGroupTotals &t, int de, hipStream_t st);
+void launch_membrane_multi(const MembraneArgs *tab, const MGroup *grp, int ng,
+                           const MGroupTotals &t, hipStream_t st);
+void launch_window_fill_multi(const MembraneArgs *tab, const MGroup *grp, int ng,
+                              const MGroupTotals &t, hipStream_t st);
+void launch_node_update_multi(const MembraneArgs *tab, const MGroup *grp, int ng,
+                              const MGroupTotals &t, hipStream_t st);
 
 int reduce_chunks(int max_work);
 void launch_capsule_reduce(const MembraneArgs &m, hipStream_t st);

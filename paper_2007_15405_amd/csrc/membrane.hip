@@ -97,16 +97,18 @@ __device__ __forceinline__ int wrap_near(int a, int n) {
 }
 
 // ------------------------------------------------------------------------------------
-// Capsule reduction, grid (nch, ncap).  Each block first clears its share of the flags
-// and crossing masks of capsule k's previous window, then reduces its share of the nodes
-// (sum of X - X_ref, FP32 bounding box) and triangles (signed tetrahedron volumes with
-// apex X_ref, the first node; the volume of a closed mesh does not depend on the apex)
-// into a partial record.  The last block of capsule k to finish (device-scope counter,
-// release / acquire fences) sums the records in block order, so the result does not
-// depend on scheduling, then derives the centroid, volume (only for capsules with a
-// volume penalty; else 0), bounding box and site window, and bins the nodes by the
-// (y, z) lattice row of floor(X) inside the window: positions in row order (any order
-// inside a row), and each node's place in that order.
+// Capsule reduction, in two kernels.  Partials, grid (nch, ncap): each block first clears
+// its share of the flags and crossing masks of capsule k's previous window, then reduces
+// its share of the nodes (sum of X - X_ref, FP32 bounding box) and triangles (signed
+// tetrahedron volumes with apex X_ref, the first node; the volume of a closed mesh does
+// not depend on the apex) into a partial record.  Window, one block per capsule: sums the
+// records in block order, so the result does not depend on scheduling, then derives the
+// centroid, volume (only for capsules with a volume penalty; else 0), bounding box and
+// site window, and bins the nodes by the (y, z) lattice row of floor(X) inside the
+// window: positions in row order (any order inside a row), and each node's place in that
+// order.  (Counting finished blocks instead, and letting the last one go on, needs a
+// device-scope release fence in every block, which writes back the L2 of its XCD: for
+// many capsules that cost more than the second launch.)
 // ------------------------------------------------------------------------------------
 constexpr int RED_BLK = 256, RED_W = RED_BLK / 64;
 
@@ -115,14 +117,15 @@ int reduce_chunks(int max_work) {
     return c < 1 ? 1 : (c > RED_BLK ? RED_BLK : c);
 }
 
-__global__ void __launch_bounds__(RED_BLK) k_capsule_reduce(MembraneArgs m) {
-    const int k = blockIdx.y, c = blockIdx.x, nch = m.nch;
+// block c of capsule k
+__device__ __forceinline__ void capsule_partial_body(const MembraneArgs &m, int k, int c) {
+    const int nch = m.nch;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int gstride = nch * RED_BLK, g0 = c * RED_BLK + tid;
     const CapDev cd = m.caps[k];
     {
-        // flags and crossing masks of the previous window (read before this block's
-        // arrival is counted, so before the last block rewrites the window)
+        // flags and crossing masks of the previous window (rewritten by the window kernel,
+        // which runs after this one)
         const CapState old = m.cst[k];
         const int dx = old.dim[0], dy = old.dim[1], pv = dx * dy * old.dim[2];
         for (int i = g0; i < pv; i += gstride) {
@@ -158,7 +161,6 @@ __global__ void __launch_bounds__(RED_BLK) k_capsule_reduce(MembraneArgs m) {
     }
     __shared__ double sd[RED_W][4];
     __shared__ float smn[RED_W][3], smx[RED_W][3];
-    __shared__ int s_last;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         const double v = wave_sum_d(s[d]);
@@ -184,14 +186,15 @@ __global__ void __launch_bounds__(RED_BLK) k_capsule_reduce(MembraneArgs m) {
         P.epoch = m.epoch;
         P.pad = 0;
         m.part[(size_t)k * nch + c] = P;
-        __threadfence();   // release the record before counting this block
-        s_last = atomicAdd(&m.counter[k], 1) == nch - 1;
     }
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();       // acquire: every record of capsule k is visible from here on
+}
 
-    // ---- last block of capsule k: totals in block order, window ----
+// capsule k: totals in block order, window, node rows
+__device__ __forceinline__ void capsule_window_body(const MembraneArgs &m, int k) {
+    const int nch = m.nch;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const CapDev cd = m.caps[k];
+    const double4 Xr = m.X[cd.node0];
     __shared__ CapPartial s_part[RED_BLK];
     __shared__ double s_tot[10];
     __shared__ int s_lo[3], s_dim[3];
@@ -213,7 +216,6 @@ __global__ void __launch_bounds__(RED_BLK) k_capsule_reduce(MembraneArgs m) {
         bool stale = false;
         for (int i = 0; i < nch; ++i) stale = stale || s_part[i].epoch != m.epoch;
         if (stale) atomicOr(&m.status[ST_SYNC], 1);
-        atomicExch(&m.counter[k], 0);
     }
     __syncthreads();
     if (tid == 0) {
@@ -324,8 +326,17 @@ __global__ void __launch_bounds__(RED_BLK) k_capsule_reduce(MembraneArgs m) {
     }
 }
 
+__global__ void __launch_bounds__(RED_BLK) k_capsule_partial(MembraneArgs m) {
+    capsule_partial_body(m, blockIdx.y, blockIdx.x);
+}
+
+__global__ void __launch_bounds__(RED_BLK) k_capsule_window(MembraneArgs m) {
+    capsule_window_body(m, blockIdx.x);
+}
+
 void launch_capsule_reduce(const MembraneArgs &m, hipStream_t st) {
-    hipLaunchKernelGGL(k_capsule_reduce, dim3(m.nch, m.ncap), dim3(RED_BLK), 0, st, m);
+    hipLaunchKernelGGL(k_capsule_partial, dim3(m.nch, m.ncap), dim3(RED_BLK), 0, st, m);
+    hipLaunchKernelGGL(k_capsule_window, dim3(m.ncap), dim3(RED_BLK), 0, st, m);
 }
 
 // ------------------------------------------------------------------------------------
@@ -420,10 +431,10 @@ __device__ void label_marks(const MembraneArgs &m, int t) {
 // masks, one thread per triangle.
 constexpr int MEM_BLK = 256, MEM_L = 8, MEM_NPB = MEM_BLK / MEM_L;
 
-__global__ void __launch_bounds__(MEM_BLK) k_membrane(MembraneArgs m, int ntot, int ttot,
-                                                      int nb_forces) {
-    if ((int)blockIdx.x >= nb_forces) {
-        const int t = ((int)blockIdx.x - nb_forces) * MEM_BLK + threadIdx.x;
+__device__ __forceinline__ void membrane_body(const MembraneArgs &m, int blk, int ntot, int ttot,
+                                              int nb_forces) {
+    if (blk >= nb_forces) {
+        const int t = (blk - nb_forces) * MEM_BLK + threadIdx.x;
         if (t < ttot) label_marks(m, t);
         return;
     }
@@ -432,7 +443,7 @@ __global__ void __launch_bounds__(MEM_BLK) k_membrane(MembraneArgs m, int ntot, 
     __shared__ int s_near[2][MAX_CAPS], s_nnear[2];
     for (int j = threadIdx.x; j < m.ncap; j += MEM_BLK) s_cst[j] = m.cst[j];
     // the capsules of this block's first and last node (node ranges are contiguous)
-    const int nb0 = blockIdx.x * MEM_NPB, nb1 = min(nb0 + MEM_NPB, ntot) - 1;
+    const int nb0 = blk * MEM_NPB, nb1 = min(nb0 + MEM_NPB, ntot) - 1;
     const int kb[2] = {m.node_cap[nb0], m.node_cap[nb1]};
     __syncthreads();
     if (m.hertz_xi > 0.f) {
@@ -466,7 +477,7 @@ __global__ void __launch_bounds__(MEM_BLK) k_membrane(MembraneArgs m, int ntot, 
         }
         __syncthreads();
     }
-    const int n = blockIdx.x * MEM_NPB + (threadIdx.x / MEM_L), sl = threadIdx.x % MEM_L;
+    const int n = blk * MEM_NPB + (threadIdx.x / MEM_L), sl = threadIdx.x % MEM_L;
     if (n >= ntot) return;   // whole groups of MEM_L lanes
     const int k = m.node_cap[n];
     const CapDev cd = m.caps[k];
@@ -575,6 +586,11 @@ __global__ void __launch_bounds__(MEM_BLK) k_membrane(MembraneArgs m, int ntot, 
     }
 }
 
+__global__ void __launch_bounds__(MEM_BLK) k_membrane(MembraneArgs m, int ntot, int ttot,
+                                                      int nb_forces) {
+    membrane_body(m, blockIdx.x, ntot, ttot, nb_forces);
+}
+
 void launch_membrane(const MembraneArgs &m, int ntot, int ttot, hipStream_t st) {
     const int nbf = (ntot + MEM_NPB - 1) / MEM_NPB, nbm = (ttot + MEM_BLK - 1) / MEM_BLK;
     hipLaunchKernelGGL(k_membrane, dim3(nbf + nbm), dim3(MEM_BLK), 0, st, m, ntot, ttot, nbf);
@@ -605,8 +621,9 @@ __device__ __forceinline__ int gcd_int(int a, int b) {
     return a;
 }
 
-__global__ void __launch_bounds__(OWN_BLK) k_window_own(MembraneArgs m) {
-    const int k = blockIdx.y, lz = blockIdx.x, tid = threadIdx.x;
+// plane lz of capsule k's window
+__device__ __forceinline__ void window_own_body(const MembraneArgs &m, int k, int lz) {
+    const int tid = threadIdx.x;
     const CapState ck = m.cst[k];
     if (lz >= ck.dim[2]) return;
     const int dx = ck.dim[0], dy = ck.dim[1], ncol = dx * dy;
@@ -684,8 +701,8 @@ __global__ void __launch_bounds__(OWN_BLK) k_window_own(MembraneArgs m) {
     }
 }
 
-__global__ void __launch_bounds__(256) k_window_combine(MembraneArgs m) {
-    const int k = blockIdx.y, lz = blockIdx.x, tid = threadIdx.x;
+__device__ __forceinline__ void window_combine_body(const MembraneArgs &m, int k, int lz) {
+    const int tid = threadIdx.x;
     const CapState ck = m.cst[k];
     if (lz >= ck.dim[2]) return;
     const int dx = ck.dim[0], dy = ck.dim[1];
@@ -754,6 +771,14 @@ __global__ void __launch_bounds__(256) k_window_combine(MembraneArgs m) {
     }
 }
 
+__global__ void __launch_bounds__(OWN_BLK) k_window_own(MembraneArgs m) {
+    window_own_body(m, blockIdx.y, blockIdx.x);
+}
+
+__global__ void __launch_bounds__(256) k_window_combine(MembraneArgs m) {
+    window_combine_body(m, blockIdx.y, blockIdx.x);
+}
+
 void launch_window_fill(const MembraneArgs &m, hipStream_t st) {
     hipLaunchKernelGGL(k_window_own, dim3(GMAX, m.ncap), dim3(256), 0, st, m);
     hipLaunchKernelGGL(k_window_combine, dim3(GMAX, m.ncap), dim3(256), 0, st, m);
@@ -802,16 +827,142 @@ __device__ __forceinline__ void node_update_one(const MembraneArgs &m, int n, in
     }
 }
 
-__global__ void __launch_bounds__(UPD_BLK) k_node_update(MembraneArgs m, int ntot) {
+// block blk of nblk, grid-stride over the nodes
+__device__ __forceinline__ void node_update_body(const MembraneArgs &m, int blk, int nblk,
+                                                 int ntot) {
     const int sl = threadIdx.x % UPD_L;
-    for (int n = blockIdx.x * UPD_NPB + threadIdx.x / UPD_L; n < ntot; n += gridDim.x * UPD_NPB)
+    for (int n = blk * UPD_NPB + threadIdx.x / UPD_L; n < ntot; n += nblk * UPD_NPB)
         node_update_one(m, n, sl);
 }
 
-void launch_node_update(const MembraneArgs &m, int ntot, hipStream_t st) {
+__global__ void __launch_bounds__(UPD_BLK) k_node_update(MembraneArgs m, int ntot) {
+    node_update_body(m, blockIdx.x, gridDim.x, ntot);
+}
+
+int node_update_blocks(int ntot) {
     const int nb = (ntot + UPD_NPB - 1) / UPD_NPB;
-    hipLaunchKernelGGL(k_node_update, dim3(nb < UPD_GRID ? nb : UPD_GRID), dim3(UPD_BLK), 0, st,
-                       m, ntot);
+    return nb < UPD_GRID ? nb : UPD_GRID;
+}
+
+int membrane_blocks(int ntot, int ttot, int *nb_forces) {
+    *nb_forces = (ntot + MEM_NPB - 1) / MEM_NPB;
+    return *nb_forces + (ttot + MEM_BLK - 1) / MEM_BLK;
+}
+
+void launch_node_update(const MembraneArgs &m, int ntot, hipStream_t st) {
+    hipLaunchKernelGGL(k_node_update, dim3(node_update_blocks(ntot)), dim3(UPD_BLK), 0, st, m,
+                       ntot);
+}
+
+// ------------------------------------------------------------------------------------
+// The capsule kernels of several simulations in one launch each.  Group g (a simulation
+// with capsules) owns capsules grp[g].cap0 .., membrane blocks grp[g].mem0 .. and node
+// update blocks grp[g].upd0 .. of the launch; its arguments are tab[g].  The tables are
+// read-only for the kernels' lifetime and read through the constant address space.
+// ------------------------------------------------------------------------------------
+typedef __attribute__((address_space(4))) const int ConstIntM;
+
+__device__ __forceinline__ void load_margs(const MembraneArgs *tab, int g, MembraneArgs &m) {
+    static_assert(sizeof(MembraneArgs) % 4 == 0 && sizeof(MGroup) == 32, "word copies");
+    ConstIntM *src = (ConstIntM *)(tab + g);
+    int *dst = reinterpret_cast<int *>(&m);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(MembraneArgs) / 4); ++i) dst[i] = src[i];
+}
+
+// field f of group g (MGroup as 8 ints)
+__device__ __forceinline__ int grp_field(const MGroup *grp, int g, int f) {
+    return ((ConstIntM *)grp)[8 * g + f];
+}
+
+// the last group whose field f (a start index, increasing with g) is <= v
+__device__ __forceinline__ int find_group(const MGroup *grp, int ng, int f, int v) {
+    int g = 0;
+    while (g + 1 < ng && v >= grp_field(grp, g + 1, f)) ++g;
+    return g;
+}
+
+enum { MG_CAP0 = 0, MG_MEM0 = 1, MG_UPD0 = 2, MG_NTOT = 3, MG_TTOT = 4, MG_NBF = 5, MG_NBU = 6,
+       MG_EPOCH0 = 7 };
+
+__global__ void __launch_bounds__(RED_BLK) k_capsule_partial_multi(const MembraneArgs *tab,
+                                                                   const MGroup *grp, int ng,
+                                                                   int de) {
+    const int K = blockIdx.y, g = find_group(grp, ng, MG_CAP0, K);
+    MembraneArgs m;
+    load_margs(tab, g, m);
+    if ((int)blockIdx.x >= m.nch) return;
+    m.epoch = (grp_field(grp, g, MG_EPOCH0) + de) & 0x7fffffff;
+    capsule_partial_body(m, K - grp_field(grp, g, MG_CAP0), blockIdx.x);
+}
+
+__global__ void __launch_bounds__(RED_BLK) k_capsule_window_multi(const MembraneArgs *tab,
+                                                                  const MGroup *grp, int ng,
+                                                                  int de) {
+    const int K = blockIdx.x, g = find_group(grp, ng, MG_CAP0, K);
+    MembraneArgs m;
+    load_margs(tab, g, m);
+    m.epoch = (grp_field(grp, g, MG_EPOCH0) + de) & 0x7fffffff;
+    capsule_window_body(m, K - grp_field(grp, g, MG_CAP0));
+}
+
+__global__ void __launch_bounds__(MEM_BLK) k_membrane_multi(const MembraneArgs *tab,
+                                                            const MGroup *grp, int ng) {
+    const int B = blockIdx.x, g = find_group(grp, ng, MG_MEM0, B);
+    MembraneArgs m;
+    load_margs(tab, g, m);
+    membrane_body(m, B - grp_field(grp, g, MG_MEM0), grp_field(grp, g, MG_NTOT),
+                  grp_field(grp, g, MG_TTOT), grp_field(grp, g, MG_NBF));
+}
+
+__global__ void __launch_bounds__(OWN_BLK) k_window_own_multi(const MembraneArgs *tab,
+                                                              const MGroup *grp, int ng) {
+    const int K = blockIdx.y, g = find_group(grp, ng, MG_CAP0, K);
+    MembraneArgs m;
+    load_margs(tab, g, m);
+    window_own_body(m, K - grp_field(grp, g, MG_CAP0), blockIdx.x);
+}
+
+__global__ void __launch_bounds__(256) k_window_combine_multi(const MembraneArgs *tab,
+                                                              const MGroup *grp, int ng) {
+    const int K = blockIdx.y, g = find_group(grp, ng, MG_CAP0, K);
+    MembraneArgs m;
+    load_margs(tab, g, m);
+    window_combine_body(m, K - grp_field(grp, g, MG_CAP0), blockIdx.x);
+}
+
+__global__ void __launch_bounds__(UPD_BLK) k_node_update_multi(const MembraneArgs *tab,
+                                                               const MGroup *grp, int ng) {
+    const int B = blockIdx.x, g = find_group(grp, ng, MG_UPD0, B);
+    MembraneArgs m;
+    load_margs(tab, g, m);
+    node_update_body(m, B - grp_field(grp, g, MG_UPD0), grp_field(grp, g, MG_NBU),
+                     grp_field(grp, g, MG_NTOT));
+}
+
+void launch_capsule_reduce_multi(const MembraneArgs *tab, const MGroup *grp, int ng,
+                                 const MGroupTotals &t, int de, hipStream_t st) {
+    hipLaunchKernelGGL(k_capsule_partial_multi, dim3(t.nch_max, t.ncap), dim3(RED_BLK), 0, st,
+                       tab, grp, ng, de);
+    hipLaunchKernelGGL(k_capsule_window_multi, dim3(t.ncap), dim3(RED_BLK), 0, st, tab, grp, ng,
+                       de);
+}
+
+void launch_membrane_multi(const MembraneArgs *tab, const MGroup *grp, int ng,
+                           const MGroupTotals &t, hipStream_t st) {
+    hipLaunchKernelGGL(k_membrane_multi, dim3(t.mem_blocks), dim3(MEM_BLK), 0, st, tab, grp, ng);
+}
+
+void launch_window_fill_multi(const MembraneArgs *tab, const MGroup *grp, int ng,
+                              const MGroupTotals &t, hipStream_t st) {
+    hipLaunchKernelGGL(k_window_own_multi, dim3(GMAX, t.ncap), dim3(OWN_BLK), 0, st, tab, grp, ng);
+    hipLaunchKernelGGL(k_window_combine_multi, dim3(GMAX, t.ncap), dim3(256), 0, st, tab, grp, ng);
+}
+
+void launch_node_update_multi(const MembraneArgs *tab, const MGroup *grp, int ng,
+                              const MGroupTotals &t, hipStream_t st) {
+    hipLaunchKernelGGL(k_node_update_multi, dim3(t.upd_blocks), dim3(UPD_BLK), 0, st, tab, grp,
+                       ng);
 }
 
 }  // namespace lbmx
