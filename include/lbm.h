@@ -84,7 +84,7 @@ typedef enum {
 } lbm_storage;
 
 typedef struct {
-    int32_t nx, ny, nz;        /* lattice size, each >= 3; 19 * nx * ny * nz * (4 bytes for
+    int32_t nx, ny, nz;        /* lattice size, each >= 3; 10 * nx * ny * nz * (4 bytes for
                                   FP32 storage, 2 for 16-bit) below 2^32                    */
     int32_t wall_z0;           /* 1: solid wall layer at k = 0                               */
     double tau[2];             /* BGK relaxation time per component, > 1/2 (Section 3.1)    */

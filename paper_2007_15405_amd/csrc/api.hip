@@ -237,11 +237,11 @@ extern "C" lbm_status lbm_init(const lbm_params *p, lbm_handle **out) {
     };
     if (!p) return bad("params is NULL");
     if (p->nx < 3 || p->ny < 3 || p->nz < 3) return bad("nx, ny, nz must be >= 3");
-    // the kernels address one component's populations with 32-bit byte offsets
-    const double pop_bytes = (double)Q * p->nx * p->ny * p->nz * (p->storage == LBM_STORE_F32 ? 4 : 2);
+    // the kernels address 10 populations of one component with 32-bit byte offsets
+    const double pop_bytes = 10.0 * p->nx * p->ny * p->nz * (p->storage == LBM_STORE_F32 ? 4 : 2);
     if (pop_bytes >= 4294967296.0)
-        return bad("lattice too large: 19 populations of one component must fit in 4 GiB "
-                   "(56 million sites with FP32 storage, 113 million with 16-bit)");
+        return bad("lattice too large: 10 populations of one component must fit in 4 GiB "
+                   "(107 million sites with FP32 storage, 214 million with 16-bit)");
     if (!(p->tau[0] > 0.5) || !(p->tau[1] > 0.5)) return bad("tau must exceed 1/2");
     if (!(p->rho0 > 0.0)) return bad("rho0 must be positive");
     if (!(p->sc_norm >= 0.0) || !std::isfinite(p->G)) return bad("invalid Shan-Chen coupling");

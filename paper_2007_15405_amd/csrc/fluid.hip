@@ -5,12 +5,13 @@
 // Streaming is "pull": the step at site x gathers f*_i(x - e_i) from the previous state;
 // where x - e_i is the wall layer, half-way bounce-back returns f*_{opp(i)}(x).
 //
-// Each component's 19 populations are read through one buffer resource (base in scalar
-// registers) with the population's start as the scalar offset and a 32-bit byte offset
-// per lane: no 64-bit address arithmetic on the vector ALU, and few scalar registers
-// (one resource per component instead of one per population, which the compiler would
-// otherwise keep live across the z march).  Out-of-range offsets read 0 and drop stores
-// instead of faulting.  The byte size of one component's populations must fit 32 bits.
+// The populations of a component are read through two buffer resources (populations
+// 0..9 and 10..18; base in scalar registers) with the population's start inside its part
+// as the scalar offset and a 32-bit byte offset per lane: no 64-bit address arithmetic
+// on the vector ALU, and few scalar registers (four resources per population array
+// instead of one per population, which the compiler would otherwise keep live across
+// the z march).  Out-of-range offsets read 0 and drop stores instead of faulting.  The
+// byte size of 10 populations of one component must fit 32 bits.
 #include "lbm_internal.h"
 
 namespace lbmx {
@@ -38,15 +39,18 @@ __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x);
 // ------------------------------------------------------------------------------------
 template <int S> struct Pop {
     using T = typename Codec<S>::T;
-    // resource of component qg / Q: populations [Q][N] of T
+    static constexpr int QH = 10;   // populations in the first part of a component
+    // resource of the part holding population qg (component qg / Q): [QH or Q - QH][N] of T
     __device__ static inline __amdgpu_buffer_rsrc_t res(const void *f, int qg, int N) {
+        const int hi = qg % Q >= QH;
         return __builtin_amdgcn_make_buffer_rsrc(
-            (void *)((const T *)f + (size_t)(qg / Q) * Q * N), (short)0,
-            (int)((uint32_t)Q * (uint32_t)N * sizeof(T)), 0x00020000);
+            (void *)((const T *)f + (size_t)((qg / Q) * Q + hi * QH) * N), (short)0,
+            (int)((uint32_t)(hi ? Q - QH : QH) * (uint32_t)N * sizeof(T)), 0x00020000);
     }
-    // byte offset of population qg % Q inside its component
+    // byte offset of population qg inside its part
     __device__ static inline uint32_t qoff(int qg, int N) {
-        return (uint32_t)(qg % Q) * (uint32_t)N * (uint32_t)sizeof(T);
+        const int q = qg % Q;
+        return (uint32_t)(q >= QH ? q - QH : q) * (uint32_t)N * (uint32_t)sizeof(T);
     }
     __device__ static inline float load(const void *f, int qg, int N, uint32_t site, float sh) {
         const __amdgpu_buffer_rsrc_t r = res(f, qg, N);

@@ -121,7 +121,7 @@ def test_invalid_slabs_are_rejected_on_the_host(nz, slab, wall, msg):
 def test_lattice_beyond_32_bit_population_offsets_is_rejected():
     L = pkg.load_library()
     p = lbm.Params()
-    p.nx, p.ny, p.nz = 512, 512, 216      # 56.6 M sites: 19 x 4 B x N > 4 GiB
+    p.nx, p.ny, p.nz = 1024, 512, 216     # 113 M sites: 10 x 4 B x N > 4 GiB
     p.tau[0] = p.tau[1] = 1.0
     p.rho0 = 1.0
     h = C.c_void_p()
