@@ -114,7 +114,7 @@ def run_gpu(cfg, storage, steps, warmup, do_tune=True, launch=None):
     return out
 
 
-def run_batch(storage, steps, warmup, do_tune=True):
+def run_batch(storage, steps, warmup, do_tune=True, launch=None, parts=None):
     """The batched form: every group of equal box size is one handle of stacked slabs,
     and one Batch advances all groups with one fluid launch per step."""
     import torch
@@ -129,8 +129,11 @@ def run_batch(storage, steps, warmup, do_tune=True):
     bt = Batch(sims)
     stream = torch.cuda.current_stream()
     best = None
-    for tile in ((6, 7, 8, 9, 10) if do_tune else (10,)):
-        for zc in ((0, 16, 24, 32, 48) if do_tune else (0,)):
+    fixed = launch is not None or not do_tune
+    tiles = (launch[0],) if launch is not None else ((6, 7, 8, 9, 10) if do_tune else (10,))
+    zcs = (launch[1],) if launch is not None else ((0, 16, 24, 32, 48) if do_tune else (0,))
+    for tile in tiles:
+        for zc in zcs:
             bt.set_launch(tile, zc)
             bt.step(2)
             bt.set_profiling(2)
@@ -138,29 +141,44 @@ def run_batch(storage, steps, warmup, do_tune=True):
             n, ms = bt.kernel_stats()["fluid"]
             bt.set_profiling(0)
             t = ms / n
-            print(f"#   batch {storage} tune tile {TILES[tile]:>10s} zchunk {zc:2d}: fluid "
-                  f"{t * 1e3:8.1f} us", file=sys.stderr, flush=True)
+            if not fixed:
+                print(f"#   batch {storage} tune tile {TILES[tile]:>10s} zchunk {zc:2d}: fluid "
+                      f"{t * 1e3:8.1f} us", file=sys.stderr, flush=True)
             if best is None or t < best[0]:
                 best = (t, tile, zc)
     bt.set_launch(best[1], best[2])
+
+    def timed_steps():
+        torch.cuda.synchronize()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record(stream)
+        bt.step(steps)
+        t1.record(stream)
+        torch.cuda.synchronize()
+        bt.sync()
+        return t0.elapsed_time(t1)
+
+    # one part: the fluid kernel's duration (HIP events around it) for the roofline
     bt.step(warmup)
     bt.sync()
     bt.kernel_stats()
     bt.set_profiling(2)
-    torch.cuda.synchronize()
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
-    t0.record(stream)
-    bt.step(steps)
-    t1.record(stream)
-    torch.cuda.synchronize()
-    bt.sync()
-    ms = t0.elapsed_time(t1)
+    ms1 = timed_steps()
     n, fms = bt.kernel_stats()["fluid"]
     bt.set_profiling(1)
     bt.step(min(steps, 20))
     breakdown = bt.kernel_stats()
     bt.set_profiling(0)
+    # more parts overlap one part's capsule kernels with another's fluid kernel: the
+    # throughput is taken from the fastest split (no events inside the timed steps)
+    per_parts = {1: ms1}
+    for p in ((2, 3, 4) if parts is None else (parts,) if parts > 1 else ()):
+        bt.set_parts(p)
+        bt.step(warmup)
+        per_parts[p] = timed_steps()
+    best_parts = min(per_parts, key=per_parts.get)
+    ms = per_parts[best_parts]
     sites, bps = bt.fluid_sites, bt.bytes_per_site
     fl_avg = fms / n
     achieved = bps * sites / (fl_avg * 1e-3) / 1e9
@@ -171,6 +189,8 @@ def run_batch(storage, steps, warmup, do_tune=True):
         instances=len(inst), groups=len(groups), capsules=sum(len(g["capsules"]) for g in groups),
         fluid_sites=sites, storage=storage,
         mlups=round(sites * steps / (ms * 1e-3) / 1e6, 2), ms_per_step=round(ms / steps, 5),
+        parts=best_parts,
+        ms_per_step_by_parts={k: round(v / steps, 5) for k, v in per_parts.items()},
         fluid_ms=round(fl_avg, 5), bytes_per_site=bps, achieved_gbs=round(achieved, 1),
         frac=round(achieved / PEAK_HBM_GBS, 4),
         launch=dict(tile=TILES[best[1]], tile_id=best[1], zchunk=best[2]),
@@ -208,6 +228,8 @@ def main():
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched form")
     ap.add_argument("--batch-only", action="store_true", help="only the batched form")
+    ap.add_argument("--parts", type=int, default=None,
+                    help="batched form: only this split over streams (default: try 1..4)")
     ap.add_argument("--tile", type=int, default=None, help="fixed launch shape (skips tuning)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MB",
                     help="only run a plain device copy of MB megabytes (counter calibration)")
@@ -239,7 +261,9 @@ def main():
     if not args.no_batch:
         for st in (["f32", "f16"] if args.storage == "all" else [args.storage]):
             batched[st] = run_batch(st, min(args.steps, 100), min(args.warmup, 10),
-                                    not args.no_tune)
+                                    not args.no_tune,
+                                    (args.tile, args.zchunk) if args.tile is not None else None,
+                                    args.parts)
             b = batched[st]
             print(f"# batch {st}: {b['mlups']:.1f} MLUPS, {b['ms_per_step']:.4f} ms/step, fluid "
                   f"{b['fluid_ms']:.4f} ms = {b['achieved_gbs']:.0f} GB/s", file=sys.stderr,

@@ -242,7 +242,16 @@ lbm_status lbm_batch_create(lbm_handle *const *handles, int32_t n, lbm_batch **o
  * zchunk 0 picks 48 planes, halved while the launch has fewer than 1024 workgroups. */
 lbm_status lbm_batch_set_launch(lbm_batch *b, int32_t tile, int32_t zchunk);
 
-/* Enqueue n >= 0 steps of every handle on the shared stream; returns without waiting. */
+/* Split the handles into `parts` sets of about equal fluid sites (1..4, default 1), each
+ * advanced by its own chain of launches on a stream of the batch's own (default priority),
+ * so that the latency-bound capsule kernels of one set overlap the fluid kernel of
+ * another; lbm_batch_step makes the handles' stream wait for all of them before it
+ * returns.  With more than one part the kernel timings of lbm_batch_kernel_stats overlap.
+ * LBM_E_INVAL for other values. */
+lbm_status lbm_batch_set_parts(lbm_batch *b, int32_t parts);
+
+/* Enqueue n >= 0 steps of every handle; the handles' stream holds them all when the call
+ * returns, which is without waiting. */
 lbm_status lbm_batch_step(lbm_batch *b, int64_t n);
 
 /* Event timing of the batch's kernels, as lbm_set_profiling / lbm_kernel_stats. */

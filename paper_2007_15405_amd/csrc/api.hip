@@ -643,22 +643,34 @@ extern "C" lbm_status lbm_step(lbm_handle *h, int64_t n) {
 // Batches: several handles advanced together, with one launch of each kernel over all
 // their lattices and capsules per step
 // ------------------------------------------------------------------------------------
-struct lbm_batch {
-    std::vector<lbm_handle *> hs;
-    std::string err;
-    hipStream_t st = nullptr;
-    int storage = 0;
-    int tile = 10, zchunk = 0;
-    FluidArgs *d_tab = nullptr;    // [2][n]: arguments for parity 0 and 1 of the buffers
-    int4 *d_desc = nullptr;        // [n + 1] first logical block, tiles x, tiles y, zchunk
+// A part: handles advanced by one chain of launches on one stream.  With several parts the
+// latency-bound capsule kernels of one part overlap the bandwidth-bound fluid kernel of
+// another.
+struct BatchPart {
+    std::vector<int> idx;          // handles of the part (indices into lbm_batch::hs)
+    hipStream_t st = nullptr;      // the batch's stream (one part) or a stream of its own
+    bool own_stream = false;
+    hipEvent_t done = nullptr;     // recorded on st after the part's last enqueued step
+    FluidArgs *d_tab = nullptr;    // [2][handles]: arguments for parity 0 and 1 of the buffers
+    int4 *d_desc = nullptr;        // [handles + 1] first logical block, tiles x, tiles y, zchunk
     MembraneArgs *d_mtab = nullptr;  // [groups] capsule-kernel arguments of the handles
     MGroup *d_mgrp = nullptr;        // with capsules, and their places in the launches
     MGroupTotals mtot{};
     int nmg = 0;                   // handles with capsules
+    int nblocks = 0;
+};
+
+struct lbm_batch {
+    std::vector<lbm_handle *> hs;
+    std::string err;
+    hipStream_t st = nullptr;      // the handles' stream
+    int storage = 0, device = 0;
+    int tile = 10, zchunk = 0, nparts = 1;
+    std::vector<BatchPart> parts;
+    hipEvent_t start = nullptr;    // on st: work enqueued before a batch step
     std::vector<int64_t> step0;    // step count of each handle when the tables were written
     int64_t since = 0;             // batch steps since then
     bool dirty = true;
-    int nblocks = 0;
     Prof prof;
 };
 
@@ -669,64 +681,113 @@ static lbm_status bfail(lbm_batch *b, lbm_status s, const std::string &m) {
     return s;
 }
 
-// z planes per workgroup of a batch launch: 48, halved while the launch has fewer than
-// 1024 workgroups (four per compute unit), at least 8
-static int batch_zchunk(const lbm_batch *b, int zc) {
-    if (b->zchunk > 0) return b->zchunk;
-    long total = 0;
-    for (const lbm_handle *h : b->hs)
-        total += (long)((h->nx + TILE_X[b->tile] - 1) / TILE_X[b->tile]) *
-                 ((h->ny + TILE_Y[b->tile] - 1) / TILE_Y[b->tile]) * ((h->nz + zc - 1) / zc);
-    return (total >= 1024 || zc <= 8) ? zc : batch_zchunk(b, std::max(8, zc / 2));
+static void free_parts(lbm_batch *b) {
+    for (BatchPart &pt : b->parts) {
+        if (pt.st && pt.own_stream) {
+            (void)hipStreamSynchronize(pt.st);
+            (void)hipStreamDestroy(pt.st);
+        }
+        if (pt.done) (void)hipEventDestroy(pt.done);
+        void *ptrs[] = {pt.d_tab, pt.d_desc, pt.d_mtab, pt.d_mgrp};
+        for (void *q : ptrs)
+            if (q) (void)hipFree(q);
+    }
+    b->parts.clear();
 }
 
+// z planes per workgroup of a part's fluid launch: 48, halved while the launch has fewer
+// than 1024 workgroups (four per compute unit), at least 8
+static int batch_zchunk(const lbm_batch *b, const BatchPart &pt, int zc) {
+    if (b->zchunk > 0) return b->zchunk;
+    long total = 0;
+    for (int g : pt.idx) {
+        const lbm_handle *h = b->hs[g];
+        total += (long)((h->nx + TILE_X[b->tile] - 1) / TILE_X[b->tile]) *
+                 ((h->ny + TILE_Y[b->tile] - 1) / TILE_Y[b->tile]) * ((h->nz + zc - 1) / zc);
+    }
+    return (total >= 1024 || zc <= 8) ? zc : batch_zchunk(b, pt, std::max(8, zc / 2));
+}
+
+// split the handles into parts of about equal fluid sites, write every part's tables
 static lbm_status batch_tables(lbm_batch *b) {
     const int n = (int)b->hs.size();
-    const int zc = batch_zchunk(b, 48);
-    std::vector<FluidArgs> tab(2 * (size_t)n);
-    std::vector<int4> desc(n + 1);
-    std::vector<MembraneArgs> mtab;
-    std::vector<MGroup> mgrp;
-    MGroupTotals t{};
-    int start = 0;
-    for (int g = 0; g < n; ++g) {
-        lbm_handle *h = b->hs[g];
-        b->step0[g] = h->step;
-        if (!h->caps.empty()) {
-            MGroup mg{};
-            mg.cap0 = t.ncap;
-            mg.mem0 = t.mem_blocks;
-            mg.upd0 = t.upd_blocks;
-            mg.ntot = h->ntot;
-            mg.ttot = h->ttot;
-            mg.nbu = node_update_blocks(h->ntot);
-            mg.epoch0 = (int)(h->step & 0x7fffffff);
-            t.ncap += (int)h->caps.size();
-            t.mem_blocks += membrane_blocks(h->ntot, h->ttot, &mg.nbf);
-            t.upd_blocks += mg.nbu;
-            t.nch_max = std::max(t.nch_max, h->nch);
-            mtab.push_back(membrane_args(h));
-            mgrp.push_back(mg);
+    if (hipStreamSynchronize(b->st) != hipSuccess) return bfail(b, LBM_E_DEVICE, "stream synchronisation failed");
+    free_parts(b);
+    const int np = std::min(b->nparts, n);
+    b->parts.resize(np);
+    {
+        std::vector<int> order(n);
+        for (int g = 0; g < n; ++g) order[g] = g;
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+            return lbm_fluid_sites(b->hs[x]) > lbm_fluid_sites(b->hs[y]);
+        });
+        std::vector<int64_t> load(np, 0);
+        for (int g : order) {
+            const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+            b->parts[k].idx.push_back(g);
+            load[k] += lbm_fluid_sites(b->hs[g]);
         }
-        tab[g] = fluid_args(h, h->cur);
-        tab[n + g] = fluid_args(h, 1 - h->cur);
-        const int tx = (h->nx + TILE_X[b->tile] - 1) / TILE_X[b->tile];
-        const int ty = (h->ny + TILE_Y[b->tile] - 1) / TILE_Y[b->tile];
-        desc[g] = make_int4(start, tx, ty, zc);
-        start += tx * ty * ((h->nz + zc - 1) / zc);
+        for (BatchPart &pt : b->parts) std::sort(pt.idx.begin(), pt.idx.end());
     }
-    desc[n] = make_int4(start, 0, 0, 0);
-    b->nblocks = start;
+    for (int g = 0; g < n; ++g) b->step0[g] = b->hs[g]->step;
     b->since = 0;
-    b->nmg = (int)mgrp.size();
-    b->mtot = t;
-    // the previous tables may still be read by enqueued launches
-    if (hipStreamSynchronize(b->st) != hipSuccess ||
-        hipMemcpy(b->d_tab, tab.data(), tab.size() * sizeof(FluidArgs), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(b->d_desc, desc.data(), desc.size() * sizeof(int4), hipMemcpyHostToDevice) != hipSuccess ||
-        (b->nmg && (hipMemcpy(b->d_mtab, mtab.data(), mtab.size() * sizeof(MembraneArgs), hipMemcpyHostToDevice) != hipSuccess ||
-                    hipMemcpy(b->d_mgrp, mgrp.data(), mgrp.size() * sizeof(MGroup), hipMemcpyHostToDevice) != hipSuccess)))
-        return bfail(b, LBM_E_DEVICE, "batch table upload failed");
+    for (int k = 0; k < np; ++k) {
+        BatchPart &pt = b->parts[k];
+        const int m = (int)pt.idx.size();
+        const int zc = batch_zchunk(b, pt, 48);
+        std::vector<FluidArgs> tab(2 * (size_t)m);
+        std::vector<int4> desc(m + 1);
+        std::vector<MembraneArgs> mtab;
+        std::vector<MGroup> mgrp;
+        MGroupTotals t{};
+        int start = 0;
+        for (int j = 0; j < m; ++j) {
+            lbm_handle *h = b->hs[pt.idx[j]];
+            if (!h->caps.empty()) {
+                MGroup mg{};
+                mg.cap0 = t.ncap;
+                mg.mem0 = t.mem_blocks;
+                mg.upd0 = t.upd_blocks;
+                mg.ntot = h->ntot;
+                mg.ttot = h->ttot;
+                mg.nbu = node_update_blocks(h->ntot);
+                mg.epoch0 = (int)(h->step & 0x7fffffff);
+                t.ncap += (int)h->caps.size();
+                t.mem_blocks += membrane_blocks(h->ntot, h->ttot, &mg.nbf);
+                t.upd_blocks += mg.nbu;
+                t.nch_max = std::max(t.nch_max, h->nch);
+                mtab.push_back(membrane_args(h));
+                mgrp.push_back(mg);
+            }
+            tab[j] = fluid_args(h, h->cur);
+            tab[m + j] = fluid_args(h, 1 - h->cur);
+            const int tx = (h->nx + TILE_X[b->tile] - 1) / TILE_X[b->tile];
+            const int ty = (h->ny + TILE_Y[b->tile] - 1) / TILE_Y[b->tile];
+            desc[j] = make_int4(start, tx, ty, zc);
+            start += tx * ty * ((h->nz + zc - 1) / zc);
+        }
+        desc[m] = make_int4(start, 0, 0, 0);
+        pt.nblocks = start;
+        pt.nmg = (int)mgrp.size();
+        pt.mtot = t;
+        bool ok = dalloc(&pt.d_tab, tab.size()) == hipSuccess &&
+                  dalloc(&pt.d_desc, desc.size()) == hipSuccess &&
+                  dalloc(&pt.d_mtab, mtab.size()) == hipSuccess &&
+                  dalloc(&pt.d_mgrp, mgrp.size()) == hipSuccess &&
+                  hipEventCreateWithFlags(&pt.done, hipEventDisableTiming) == hipSuccess;
+        if (ok && np > 1) {
+            ok = hipStreamCreateWithFlags(&pt.st, hipStreamNonBlocking) == hipSuccess;
+            pt.own_stream = ok;
+        } else {
+            pt.st = b->st;
+        }
+        if (!ok) return bfail(b, LBM_E_NOMEM, "device allocation failed (batch)");
+        if (hipMemcpy(pt.d_tab, tab.data(), tab.size() * sizeof(FluidArgs), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(pt.d_desc, desc.data(), desc.size() * sizeof(int4), hipMemcpyHostToDevice) != hipSuccess ||
+            (pt.nmg && (hipMemcpy(pt.d_mtab, mtab.data(), mtab.size() * sizeof(MembraneArgs), hipMemcpyHostToDevice) != hipSuccess ||
+                        hipMemcpy(pt.d_mgrp, mgrp.data(), mgrp.size() * sizeof(MGroup), hipMemcpyHostToDevice) != hipSuccess)))
+            return bfail(b, LBM_E_DEVICE, "batch table upload failed");
+    }
     b->dirty = false;
     return LBM_OK;
 }
@@ -755,16 +816,13 @@ extern "C" lbm_status lbm_batch_create(lbm_handle *const *handles, int32_t n, lb
     b->hs.assign(handles, handles + n);
     b->st = handles[0]->st;
     b->storage = handles[0]->storage;
+    b->device = handles[0]->p.device;
     b->step0.assign(n, 0);
-    const bool ok = hipSetDevice(handles[0]->p.device) == hipSuccess &&
-                    dalloc(&b->d_tab, 2 * (size_t)n) == hipSuccess &&
-                    dalloc(&b->d_desc, (size_t)n + 1) == hipSuccess &&
-                    dalloc(&b->d_mtab, (size_t)n) == hipSuccess &&
-                    dalloc(&b->d_mgrp, (size_t)n) == hipSuccess;
-    if (!ok) {
+    if (hipSetDevice(b->device) != hipSuccess ||
+        hipEventCreateWithFlags(&b->start, hipEventDisableTiming) != hipSuccess) {
         lbm_batch_destroy(b);
-        g_init_error = "device allocation failed (batch)";
-        return LBM_E_NOMEM;
+        g_init_error = "device call failed (batch)";
+        return LBM_E_DEVICE;
     }
     *out = b;
     return LBM_OK;
@@ -777,6 +835,41 @@ extern "C" lbm_status lbm_batch_set_launch(lbm_batch *b, int32_t tile, int32_t z
     b->zchunk = zchunk;
     b->dirty = true;
     return LBM_OK;
+}
+
+extern "C" lbm_status lbm_batch_set_parts(lbm_batch *b, int32_t parts) {
+    if (!b) return LBM_E_INVAL;
+    if (parts < 1 || parts > 4) return bfail(b, LBM_E_INVAL, "parts must be 1..4");
+    b->nparts = parts;
+    b->dirty = true;
+    return LBM_OK;
+}
+
+// one step of a part on its stream: labels / forces / spreading, fluid, node update
+static void part_step(lbm_batch *b, BatchPart &pt) {
+    const hipStream_t st = pt.st;
+    const MGroupTotals &mt = pt.mtot;
+    const int de = (int)(b->since & 0x7fffffff);
+    if (pt.nmg) {
+        timed(b->prof, st, "capsule_reduce", [&] {
+            launch_capsule_reduce_multi(pt.d_mtab, pt.d_mgrp, pt.nmg, mt, de, st);
+        });
+        timed(b->prof, st, "membrane", [&] { launch_membrane_multi(pt.d_mtab, pt.d_mgrp, pt.nmg, mt, st); });
+        timed(b->prof, st, "window_fill", [&] {
+            launch_window_fill_multi(pt.d_mtab, pt.d_mgrp, pt.nmg, mt, st);
+        });
+    }
+    const int m = (int)pt.idx.size();
+    const FluidArgs *tab = pt.d_tab + (size_t)(b->since & 1) * m;
+    timed(b->prof, st, "fluid", [&] {
+        switch (b->storage) {
+            case 0: launch_fluid_multi<0>(tab, pt.d_desc, m, pt.nblocks, b->tile, st); break;
+            case 1: launch_fluid_multi<1>(tab, pt.d_desc, m, pt.nblocks, b->tile, st); break;
+            default: launch_fluid_multi<2>(tab, pt.d_desc, m, pt.nblocks, b->tile, st); break;
+        }
+    });
+    if (pt.nmg)
+        timed(b->prof, st, "node_update", [&] { launch_node_update_multi(pt.d_mtab, pt.d_mgrp, pt.nmg, mt, st); });
 }
 
 extern "C" lbm_status lbm_batch_step(lbm_batch *b, int64_t n) {
@@ -796,39 +889,27 @@ extern "C" lbm_status lbm_batch_step(lbm_batch *b, int64_t n) {
         lbm_status s = batch_tables(b);
         if (s != LBM_OK) return s;
     }
-    const MGroupTotals &mt = b->mtot;
-    for (int64_t i = 0; i < n; ++i) {
-        const int de = (int)(b->since & 0x7fffffff);
-        if (b->nmg) {
-            timed(b->prof, b->st, "capsule_reduce", [&] {
-                launch_capsule_reduce_multi(b->d_mtab, b->d_mgrp, b->nmg, mt, de, b->st);
-            });
-            timed(b->prof, b->st, "membrane", [&] {
-                launch_membrane_multi(b->d_mtab, b->d_mgrp, b->nmg, mt, b->st);
-            });
-            timed(b->prof, b->st, "window_fill", [&] {
-                launch_window_fill_multi(b->d_mtab, b->d_mgrp, b->nmg, mt, b->st);
-            });
-        }
-        const FluidArgs *tab = b->d_tab + (size_t)(b->since & 1) * ng;
-        timed(b->prof, b->st, "fluid", [&] {
-            switch (b->storage) {
-                case 0: launch_fluid_multi<0>(tab, b->d_desc, ng, b->nblocks, b->tile, b->st); break;
-                case 1: launch_fluid_multi<1>(tab, b->d_desc, ng, b->nblocks, b->tile, b->st); break;
-                default: launch_fluid_multi<2>(tab, b->d_desc, ng, b->nblocks, b->tile, b->st); break;
-            }
-        });
-        if (b->nmg)
-            timed(b->prof, b->st, "node_update", [&] {
-                launch_node_update_multi(b->d_mtab, b->d_mgrp, b->nmg, mt, b->st);
-            });
+    hipError_t e = hipSuccess;
+    const bool forked = b->parts.size() > 1;
+    if (forked) {   // the parts' streams start after the work already on the handles' stream
+        e = hipEventRecord(b->start, b->st);
+        for (BatchPart &pt : b->parts)
+            if (e == hipSuccess) e = hipStreamWaitEvent(pt.st, b->start, 0);
+    }
+    for (int64_t i = 0; i < n && e == hipSuccess; ++i) {
+        for (BatchPart &pt : b->parts) part_step(b, pt);
         for (lbm_handle *h : b->hs) {
             h->cur = 1 - h->cur;
             h->step++;
         }
         b->since++;
     }
-    const hipError_t e = hipGetLastError();
+    if (forked)     // and the handles' stream continues after all of them
+        for (BatchPart &pt : b->parts) {
+            if (e == hipSuccess) e = hipEventRecord(pt.done, pt.st);
+            if (e == hipSuccess) e = hipStreamWaitEvent(b->st, pt.done, 0);
+        }
+    if (e == hipSuccess) e = hipGetLastError();
     if (e != hipSuccess) return bfail(b, LBM_E_DEVICE, std::string("batch step: ") + hipGetErrorString(e));
     return LBM_OK;
 }
@@ -843,7 +924,9 @@ extern "C" lbm_status lbm_batch_set_profiling(lbm_batch *b, int32_t on) {
 extern "C" lbm_status lbm_batch_kernel_stats(lbm_batch *b, lbm_kernel_stat *out, int32_t max,
                                              int32_t *n) {
     if (!b || !n || (max > 0 && !out)) return LBM_E_INVAL;
-    if (hipStreamSynchronize(b->st) != hipSuccess) return bfail(b, LBM_E_DEVICE, "stream synchronisation failed");
+    bool ok = hipStreamSynchronize(b->st) == hipSuccess;
+    for (BatchPart &pt : b->parts) ok = ok && hipStreamSynchronize(pt.st) == hipSuccess;
+    if (!ok) return bfail(b, LBM_E_DEVICE, "stream synchronisation failed");
     *n = export_timers(b->prof, out, max);
     return LBM_OK;
 }
@@ -855,9 +938,8 @@ extern "C" const char *lbm_batch_last_error(const lbm_batch *b) {
 extern "C" void lbm_batch_destroy(lbm_batch *b) {
     if (!b) return;
     if (b->st) (void)hipStreamSynchronize(b->st);
-    void *ptrs[] = {b->d_tab, b->d_desc, b->d_mtab, b->d_mgrp};
-    for (void *q : ptrs)
-        if (q) (void)hipFree(q);
+    free_parts(b);
+    if (b->start) (void)hipEventDestroy(b->start);
     free_prof(b->prof);
     delete b;
 }

@@ -93,6 +93,7 @@ SIGNATURES = {
     "lbm_destroy": (None, [H]),
     "lbm_batch_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(C.c_void_p)]),
     "lbm_batch_set_launch": (C.c_int, [H, C.c_int32, C.c_int32]),
+    "lbm_batch_set_parts": (C.c_int, [H, C.c_int32]),
     "lbm_batch_step": (C.c_int, [H, C.c_int64]),
     "lbm_batch_set_profiling": (C.c_int, [H, C.c_int32]),
     "lbm_batch_kernel_stats": (C.c_int, [H, C.POINTER(KernelStat), C.c_int32, C.POINTER(C.c_int32)]),
@@ -339,7 +340,7 @@ class Batch:
     lattices (``lbm_batch_*``).  The sims must share stream and storage and have tau = 1;
     close the batch before them."""
 
-    def __init__(self, sims: list, tile: int = 10, zchunk: int = 0):
+    def __init__(self, sims: list, tile: int = 10, zchunk: int = 0, parts: int = 1):
         self.L = load_library()
         self.sims = list(sims)
         arr = (C.c_void_p * len(self.sims))(*[s.h.value for s in self.sims])
@@ -349,6 +350,7 @@ class Batch:
             raise LbmError(st, self.L.lbm_batch_last_error(None).decode())
         self.b = b
         self.set_launch(tile, zchunk)
+        self.set_parts(parts)
 
     def _check(self, st: int):
         if st != LBM_OK:
@@ -356,6 +358,10 @@ class Batch:
 
     def set_launch(self, tile: int = 10, zchunk: int = 0):
         self._check(self.L.lbm_batch_set_launch(self.b, int(tile), int(zchunk)))
+
+    def set_parts(self, parts: int = 1):
+        """Advance the sims in ``parts`` sets on streams of their own (overlap)."""
+        self._check(self.L.lbm_batch_set_parts(self.b, int(parts)))
 
     def step(self, n: int = 1):
         self._check(self.L.lbm_batch_step(self.b, int(n)))

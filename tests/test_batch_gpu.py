@@ -172,6 +172,18 @@ def test_batch_equals_handles_stepped_alone():
         d = float(np.abs(a - b).max())
         say("member", i, "tile 6 zchunk 8: max |diff|", d)
         assert d <= 1e-6 * float(np.abs(b).max())
+    for parts in (2, 3):      # members split over streams of the batch's own
+        bt.set_parts(parts)
+        bt.step(7)
+        for i, r in enumerate(refs):
+            r.step(7)
+            a, b = sims[i].rho(), r.rho()
+            d = float(np.abs(a - b).max())
+            say("parts", parts, "member", i, "max |diff|", d)
+            assert d <= 1e-6 * float(np.abs(b).max())
+            for k in range(len(cfgs[i]["capsules"])):
+                assert np.abs(sims[i].nodes(k) - r.nodes(k)).max() <= 1e-5
+            assert sims[i].summary()["step"] == r.summary()["step"]
     bt.close()
 
 
