@@ -234,3 +234,49 @@ def test_full_batch_workload_sampled_instances():
                 1e-3 * max(np.linalg.norm(co["f_capillary"]), 1e-3)
         assert ob["summary"]["lost_reaction"] == 0
     bt.close()
+
+
+def test_checkpoint_resume_with_slabs_is_bitwise(tmp_path):
+    a = _sim(stacked_cfg())
+    a.step(40)
+    path = str(tmp_path / "slabs.bin")
+    a.save(path)
+    a.step(40)
+    b = _sim(stacked_cfg())
+    b.step(2)
+    b.load(path)
+    b.step(40)
+    assert np.array_equal(a.rho(), b.rho())
+    for k in range(2):
+        assert np.array_equal(a.nodes(k), b.nodes(k))
+    oa, ob = a.observables(meniscus=True), b.observables(meniscus=True)
+    assert np.array_equal(oa["slab_mass"], ob["slab_mass"])
+    assert np.array_equal(np.nan_to_num(oa["meniscus"], nan=-1), np.nan_to_num(ob["meniscus"], nan=-1))
+    # a handle with another slab height refuses the checkpoint
+    from paper_2007_15405_amd import LbmError
+    c = _sim(synth.workload("pf", nx=NX, ny=NY, nz=3 * LZ, slab_nz=3 * LZ, capsules=[]))
+    with pytest.raises(LbmError):
+        c.load(path)
+
+
+@pytest.mark.parametrize("storage,tol", [("f16", 1e-3), ("bf16", 8e-3)])
+def test_batch_with_16bit_storage_tracks_handles_stepped_alone(storage, tol):
+    """16-bit storage: the one-ulp FP32 differences between the batched and the single
+    kernel can flip the rounding of a stored population by one 16-bit ulp (2^-11
+    relative for FP16, 2^-8 for BF16), which then spreads; the bound is set on that
+    scale (relative L2 after 40 steps)."""
+    from paper_2007_15405_amd import Batch
+    cfgs = batch_members()[:2]
+    sims = [_sim(c, storage=storage) for c in cfgs]
+    refs = [_sim(c, storage=storage) for c in cfgs]
+    for r in refs:
+        r.set_launch(10, 4)
+    bt = Batch(sims, tile=10, zchunk=4, parts=2)
+    bt.step(40)
+    for i, r in enumerate(refs):
+        r.step(40)
+        e = rel_l2(sims[i].rho(), r.rho())
+        say(storage, "member", i, "rel-L2 vs alone", e)
+        assert max(e) <= tol
+        assert sims[i].summary()["unstable"] == 0
+    bt.close()
