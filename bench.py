@@ -32,12 +32,13 @@ WORKLOAD = "film 256x256x96, wall, 16 capsules R=10 (5120 tri), ks=0.05"
 
 TILES = {1: "32x8", 2: "64x4", 3: "32x16", 4: "64x8", 5: "16x16", 6: "pipe32x8",
          7: "pipe64x4", 8: "pipe16x16", 9: "pipe32x16", 10: "pipe64x8", 11: "rows256x2",
-         12: "rows128x4"}
+         12: "rows128x4", 13: "rows-nx"}
 
 
 def applicable(tile, nx):
-    """Whole-row tiles need nx equal to their width (the library falls back to 64x8)."""
-    return {11: nx == 256, 12: nx == 128}.get(tile, True)
+    """Whole-row tiles need nx equal to their width, or (13) 16 <= nx <= 128; the library
+    falls back to 64x8 otherwise."""
+    return {11: nx == 256, 12: nx == 128, 13: 16 <= nx <= 128}.get(tile, True)
 
 
 def tune(sim, nx, steps=10):
@@ -130,7 +131,7 @@ def run_batch(storage, steps, warmup, do_tune=True, launch=None, parts=None):
     stream = torch.cuda.current_stream()
     best = None
     fixed = launch is not None or not do_tune
-    tiles = (launch[0],) if launch is not None else ((6, 7, 8, 9, 10) if do_tune else (10,))
+    tiles = (launch[0],) if launch is not None else ((6, 7, 8, 9, 10, 13) if do_tune else (10,))
     zcs = (launch[1],) if launch is not None else ((0, 16, 24, 32, 48) if do_tune else (0,))
     for tile in tiles:
         for zc in zcs:
@@ -202,7 +203,7 @@ def run_batch(storage, steps, warmup, do_tune=True, launch=None, parts=None):
     return out
 
 
-def cpu_baseline(cfg, steps=10):
+def cpu_baseline(cfg, steps=30):
     import oracle
     cores = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
     o = oracle.Oracle(cfg, "f64", n_threads=cores)

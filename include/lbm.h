@@ -211,7 +211,8 @@ lbm_status lbm_kernel_stats(lbm_handle *h, lbm_kernel_stat *out, int32_t max, in
  * column tiles of 32x8, 64x4, 32x16, 64x8 or 16x16 sites; 6..10 its software-pipelined
  * form (tau = 1 in both components; otherwise the fused kernel of the same tile) with
  * 32x8, 64x4, 16x16, 32x16 or 64x8; 11 and 12 whole-row tiles 256x2 and 128x4 (nx = 256
- * resp. 128, otherwise 64x8); tile 0 the two-kernel variant (densities, then forces and
+ * resp. 128, otherwise 64x8); 13 whole rows of any width 16 <= nx <= 128, 512 / nx rows
+ * per tile (otherwise 64x8); tile 0 the two-kernel variant (densities, then forces and
  * collision).  zchunk is the number of z planes one workgroup marches through (0: chosen
  * from the lattice size).  Every variant performs the same arithmetic per site in the
  * same order, so results are identical.  LBM_E_INVAL for other values. */
@@ -238,8 +239,9 @@ void lbm_destroy(lbm_handle *h);
 typedef struct lbm_batch lbm_batch;
 lbm_status lbm_batch_create(lbm_handle *const *handles, int32_t n, lbm_batch **out);
 
-/* Tile of the batched fluid launch: 6..10 as in lbm_set_launch (default 10, 64x8);
- * zchunk 0 picks 48 planes, halved while the launch has fewer than 1024 workgroups. */
+/* Tile of the batched fluid launch: 6..10 or 13 as in lbm_set_launch (default 10, 64x8;
+ * 13 needs 16 <= nx <= 128 in every handle, LBM_E_INVAL otherwise); zchunk 0 picks 48
+ * planes, halved while a part's launch has fewer than 1024 workgroups. */
 lbm_status lbm_batch_set_launch(lbm_batch *b, int32_t tile, int32_t zchunk);
 
 /* Split the handles into `parts` sets of about equal fluid sites (1..4, default 1), each

@@ -580,14 +580,32 @@ static FluidArgs fluid_args(lbm_handle *h, int cur) {
 
 static const int TILE_X[13] = {0, 32, 64, 32, 64, 16, 32, 64, 16, 32, 64, 256, 128},
                  TILE_Y[13] = {0, 8, 4, 16, 8, 16, 8, 4, 16, 16, 8, 2, 4};
+constexpr int TILE_ROWS = 13;   // whole rows of the lattice's width (16 <= nx <= 128)
+
+static bool rows_fit(int nx) { return nx >= 16 && nx <= 128; }
+
+// tiles per plane of a launch shape: (tiles in x, tiles in y); the whole-row shapes fall
+// back to 64 x 8 where the width does not fit, as the launcher does
+static void tiles_of(int tile, int nx, int ny, int *tx, int *ty) {
+    if (tile == TILE_ROWS && rows_fit(nx)) {
+        const int h = rows_tile_height(nx);
+        *tx = 1;
+        *ty = (ny + h - 1) / h;
+        return;
+    }
+    if ((tile == 11 && nx != 256) || (tile == 12 && nx != 128) || tile == TILE_ROWS) tile = 10;
+    *tx = (nx + TILE_X[tile] - 1) / TILE_X[tile];
+    *ty = (ny + TILE_Y[tile] - 1) / TILE_Y[tile];
+}
 
 // z planes per workgroup: enough workgroups to fill the chip (about 1024), at least 4
 // planes so the two extra halo planes stay a small share
 static int zchunk_of(const lbm_handle *h) {
     if (h->zchunk > 0) return h->zchunk;
     if (h->tile <= 0) return h->nz;
-    const int tiles = ((h->nx + TILE_X[h->tile] - 1) / TILE_X[h->tile]) *
-                      ((h->ny + TILE_Y[h->tile] - 1) / TILE_Y[h->tile]);
+    int tx, ty;
+    tiles_of(h->tile, h->nx, h->ny, &tx, &ty);
+    const int tiles = tx * ty;
     const int chunks = (1024 + tiles - 1) / tiles;
     const int zc = (h->nz + chunks - 1) / chunks;
     return zc < 4 ? 4 : zc;
@@ -595,7 +613,7 @@ static int zchunk_of(const lbm_handle *h) {
 
 extern "C" lbm_status lbm_set_launch(lbm_handle *h, int32_t tile, int32_t zchunk) {
     if (!h) return LBM_E_INVAL;
-    if (tile < 0 || tile > 12 || zchunk < 0) return fail(h, LBM_E_INVAL, "invalid launch shape");
+    if (tile < 0 || tile > TILE_ROWS || zchunk < 0) return fail(h, LBM_E_INVAL, "invalid launch shape");
     h->tile = tile;
     h->zchunk = zchunk;
     return LBM_OK;
@@ -702,8 +720,9 @@ static int batch_zchunk(const lbm_batch *b, const BatchPart &pt, int zc) {
     long total = 0;
     for (int g : pt.idx) {
         const lbm_handle *h = b->hs[g];
-        total += (long)((h->nx + TILE_X[b->tile] - 1) / TILE_X[b->tile]) *
-                 ((h->ny + TILE_Y[b->tile] - 1) / TILE_Y[b->tile]) * ((h->nz + zc - 1) / zc);
+        int tx, ty;
+        tiles_of(b->tile, h->nx, h->ny, &tx, &ty);
+        total += (long)tx * ty * ((h->nz + zc - 1) / zc);
     }
     return (total >= 1024 || zc <= 8) ? zc : batch_zchunk(b, pt, std::max(8, zc / 2));
 }
@@ -761,8 +780,8 @@ static lbm_status batch_tables(lbm_batch *b) {
             }
             tab[j] = fluid_args(h, h->cur);
             tab[m + j] = fluid_args(h, 1 - h->cur);
-            const int tx = (h->nx + TILE_X[b->tile] - 1) / TILE_X[b->tile];
-            const int ty = (h->ny + TILE_Y[b->tile] - 1) / TILE_Y[b->tile];
+            int tx, ty;
+            tiles_of(b->tile, h->nx, h->ny, &tx, &ty);
             desc[j] = make_int4(start, tx, ty, zc);
             start += tx * ty * ((h->nz + zc - 1) / zc);
         }
@@ -830,7 +849,12 @@ extern "C" lbm_status lbm_batch_create(lbm_handle *const *handles, int32_t n, lb
 
 extern "C" lbm_status lbm_batch_set_launch(lbm_batch *b, int32_t tile, int32_t zchunk) {
     if (!b) return LBM_E_INVAL;
-    if (tile < 6 || tile > 10 || zchunk < 0) return bfail(b, LBM_E_INVAL, "batch tile must be 6..10");
+    if (!((tile >= 6 && tile <= 10) || tile == TILE_ROWS) || zchunk < 0)
+        return bfail(b, LBM_E_INVAL, "batch tile must be 6..10 or 13");
+    if (tile == TILE_ROWS)
+        for (const lbm_handle *h : b->hs)
+            if (!rows_fit(h->nx))
+                return bfail(b, LBM_E_INVAL, "tile 13 needs 16 <= nx <= 128 in every handle");
     b->tile = tile;
     b->zchunk = zchunk;
     b->dirty = true;

@@ -610,44 +610,51 @@ __device__ __forceinline__ void collide_store_eq(const FluidArgs &a, const float
 }
 
 // One workgroup's tile: logical block L of a lattice tiled tiles_x x tiles_y x (z chunks
-// of zc planes).
-template <int S, int TX, int TY, bool WX>
+// of zc planes).  RT: whole rows chosen at run time, tx = nx (16 .. 128) by
+// ty = NT / nx rows; the LDS ring is sized for TX x TY, which holds every such tile, and
+// the NT - tx * ty threads left over idle (they pull nothing and park their ring entry
+// in the unused end of the ring).
+template <int S, int TX, int TY, bool WX, bool RT = false>
 __device__ __forceinline__ void pipe_tile(const FluidArgs &a, int L, int zc, int tiles_x,
                                           int tiles_y) {
-    constexpr int NT = TX * TY, LX = TX + 2, LY = TY + 2, NL = LX * LY;
-    constexpr int NH = WX ? 2 * TX : NL - NT;
+    constexpr int NT = TX * TY, NLC = (TX + 2) * (TY + 2);
     constexpr int NW = NT / 64;
-    static_assert(NH <= NT && NT % 64 == 0, "tile shape");
-    __shared__ float s_psi[4][2][NL];
-    __shared__ uint8_t s_flag[4][NL];
+    static_assert((WX ? 2 * TX : NLC - NT) <= NT && NT % 64 == 0, "tile shape");
+    static_assert(!RT || (WX && TX == 128 && TY == 4), "run-time tiles are whole rows");
+    const int tx = RT ? a.nx : TX, ty = RT ? NT / a.nx : TY;
+    const int LX = tx + 2, NL = LX * (ty + 2);
+    const int NH = WX ? 2 * tx : NL - NT;
+    __shared__ float s_psi[4][2][NLC];
+    __shared__ uint8_t s_flag[4][NLC];
     __shared__ int s_busy[4][NW];
     __shared__ float s_drho[MAX_CAPS];
 
     const int bx = L % tiles_x, t2 = L / tiles_x, by = t2 % tiles_y, bz = t2 / tiles_y;
     const int nx = a.nx, ny = a.ny, nz = a.nz, N = a.N;
-    const int x0 = bx * TX, y0 = by * TY, z0 = bz * zc, z1 = min(z0 + zc, nz);
+    const int x0 = bx * tx, y0 = by * ty, z0 = bz * zc, z1 = min(z0 + zc, nz);
     const float sh0 = a.shift[0], sh1 = a.shift[1];
 
-    const int tid = threadIdx.x, lx = tid % TX, ly = tid / TX;
+    const int tid = threadIdx.x, lx = tid % tx, ly = tid / tx;
     const int wave = tid >> 6, lane = tid & 63;
-    const int li = (ly + 1) * LX + (lx + 1);
+    const bool act = !RT || tid < tx * ty;   // RT: threads beyond the tile idle
+    const int li = act ? (ly + 1) * LX + (lx + 1) : NL + (tid - tx * ty);
     const int ix = wrapn(x0 + lx, nx), iy = wrapn(y0 + ly, ny);
-    const bool valid = (x0 + lx < nx) && (y0 + ly < ny);
+    const bool valid = act && (x0 + lx < nx) && (y0 + ly < ny);
     int hi = -1, hx = 0, hy = 0;
     if (tid < NH) {
         int h = tid;
-        if (WX) { hx = h % TX; hy = h < TX ? -1 : TY; }
+        if (WX) { hx = h % tx; hy = h < tx ? -1 : ty; }
         else if (h < LX) { hx = h - 1; hy = -1; }
-        else if (h < 2 * LX) { hx = h - LX - 1; hy = TY; }
-        else { h -= 2 * LX; hy = h >> 1; hx = (h & 1) ? TX : -1; }
+        else if (h < 2 * LX) { hx = h - LX - 1; hy = ty; }
+        else { h -= 2 * LX; hy = h >> 1; hx = (h & 1) ? tx : -1; }
         hi = (hy + 1) * LX + (hx + 1);
         hx = wrapn(x0 + hx, nx);
         hy = wrapn(y0 + hy, ny);
     }
     // WX: ring positions that also hold this thread's value (the wrapped columns)
-    const int li_w = !WX ? -1 : (lx == TX - 1 ? li - TX : (lx == 0 ? li + TX : -1));
+    const int li_w = !WX || !act ? -1 : (lx == tx - 1 ? li - tx : (lx == 0 ? li + tx : -1));
     const int hi_w = !WX || hi < 0 ? -1
-                                   : ((hi % LX) == TX ? hi - TX : ((hi % LX) == 1 ? hi + TX : -1));
+                                   : ((hi % LX) == tx ? hi - tx : ((hi % LX) == 1 ? hi + tx : -1));
 
     for (int i = tid; i < MAX_CAPS; i += NT) s_drho[i] = a.cap_drho[i];
 
@@ -660,7 +667,7 @@ __device__ __forceinline__ void pipe_tile(const FluidArgs &a, int L, int zc, int
         ibv = make_float4(0.f, 0.f, 0.f, 0.f);
         if (!solid && (fl_me & AUX_BIT)) ibv = a.ibm[(pz * ny + iy) * nx + ix];
         float r0 = 0.f, r1 = 0.f, h0 = 0.f, h1 = 0.f;
-        if (!solid) {
+        if (!solid && act) {
 #pragma unroll
             for (int q = 0; q < Q; ++q) { r0 += fl[0][q]; r1 += fl[1][q]; }
             site_moments(fl, m);
@@ -672,7 +679,7 @@ __device__ __forceinline__ void pipe_tile(const FluidArgs &a, int L, int zc, int
 #pragma unroll
             for (int i = 0; i < 8; ++i) m[i] = 0.f;
         }
-        const uint8_t fg_me = solid ? WALL_FLAG : fl_me;
+        const uint8_t fg_me = !act ? 0 : (solid ? WALL_FLAG : fl_me);
         const float ps0 = psi_of(r0, a.inv_rho0), ps1 = psi_of(r1, a.inv_rho0);
         s_psi[slot][0][li] = ps0;
         s_psi[slot][1][li] = ps1;
@@ -709,8 +716,10 @@ __device__ __forceinline__ void pipe_tile(const FluidArgs &a, int L, int zc, int
         const bool wlo = a.wall && pr == 1, whi = a.wall && pr == lz - 1;
         g_me = g_h = 0;
         if (!(a.wall && pr == 0)) {
-            g_me = a.flag[(pz * ny + iy) * nx + ix];
-            pull_issue<S>(a.fin, N, ix, iy, pz, nx, ny, nz, wlo, whi, sh0, sh1, fl);
+            if (act) {
+                g_me = a.flag[(pz * ny + iy) * nx + ix];
+                pull_issue<S>(a.fin, N, ix, iy, pz, nx, ny, nz, wlo, whi, sh0, sh1, fl);
+            }
             if (hi >= 0) {
                 g_h = a.flag[(pz * ny + hy) * nx + hx];
                 pull_issue<S>(a.fin, N, hx, hy, pz, nx, ny, nz, wlo, whi, sh0, sh1, hf);
@@ -803,12 +812,12 @@ __device__ __forceinline__ int logical_block() {
     return (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
 }
 
-template <int S, int TX, int TY, bool WX>
+template <int S, int TX, int TY, bool WX, bool RT = false>
 __global__ void __launch_bounds__(TX * TY) k_fused_pipe(FluidArgs a, int zc, int tiles_x,
                                                         int tiles_y, int nblocks) {
     const int L = logical_block();
     if (L >= nblocks) return;
-    pipe_tile<S, TX, TY, WX>(a, L, zc, tiles_x, tiles_y);
+    pipe_tile<S, TX, TY, WX, RT>(a, L, zc, tiles_x, tiles_y);
 }
 
 // Several lattices in one launch: group g owns the logical blocks desc[g].x ..
@@ -817,7 +826,7 @@ __global__ void __launch_bounds__(TX * TY) k_fused_pipe(FluidArgs a, int zc, int
 // constant address space (scalar loads).
 typedef __attribute__((address_space(4))) const int ConstInt;
 
-template <int S, int TX, int TY>
+template <int S, int TX, int TY, bool RT = false>
 __global__ void __launch_bounds__(TX * TY) k_fused_pipe_multi(const FluidArgs *tab,
                                                               const int4 *desc, int ngroups,
                                                               int nblocks) {
@@ -832,7 +841,7 @@ __global__ void __launch_bounds__(TX * TY) k_fused_pipe_multi(const FluidArgs *t
     int *dst = reinterpret_cast<int *>(&a);
 #pragma unroll
     for (int i = 0; i < (int)(sizeof(FluidArgs) / 4); ++i) dst[i] = src[i];
-    pipe_tile<S, TX, TY, false>(a, L - cd[4 * g], cd[4 * g + 3], cd[4 * g + 1], cd[4 * g + 2]);
+    pipe_tile<S, TX, TY, RT, RT>(a, L - cd[4 * g], cd[4 * g + 3], cd[4 * g + 1], cd[4 * g + 2]);
 }
 
 template <int S>
@@ -844,8 +853,22 @@ void launch_fluid_multi(const FluidArgs *tab, const int4 *desc, int ngroups, int
         case 7: hipLaunchKernelGGL((k_fused_pipe_multi<S, 64, 4>), grid, dim3(256), 0, st, tab, desc, ngroups, nblocks); break;
         case 8: hipLaunchKernelGGL((k_fused_pipe_multi<S, 16, 16>), grid, dim3(256), 0, st, tab, desc, ngroups, nblocks); break;
         case 9: hipLaunchKernelGGL((k_fused_pipe_multi<S, 32, 16>), grid, dim3(512), 0, st, tab, desc, ngroups, nblocks); break;
+        case 13: hipLaunchKernelGGL((k_fused_pipe_multi<S, 128, 4, true>), grid, dim3(512), 0, st, tab, desc, ngroups, nblocks); break;
         default: hipLaunchKernelGGL((k_fused_pipe_multi<S, 64, 8>), grid, dim3(512), 0, st, tab, desc, ngroups, nblocks); break;
     }
+}
+
+// whole rows of run-time width nx (16 .. 128), 512 / nx rows per tile
+int rows_tile_height(int nx) { return 512 / nx; }
+
+template <int S>
+static void launch_pipe_rows(const FluidArgs &a, int zc, hipStream_t st) {
+    const int ty = rows_tile_height(a.nx);
+    const int tyn = (a.ny + ty - 1) / ty, tz = (a.nz + zc - 1) / zc;
+    const int nb = tyn * tz;
+    const int grid = (nb + 7) / 8 * 8;
+    hipLaunchKernelGGL((k_fused_pipe<S, 128, 4, true, true>), dim3(grid), dim3(512), 0, st, a, zc,
+                       1, tyn, nb);
 }
 
 template <int S, int TX, int TY, bool WX = false>
@@ -872,7 +895,7 @@ static void launch_fused_t(const FluidArgs &a, int zc, hipStream_t st) {
 
 // tile: 0 two-kernel variant; 1: 32x8; 2: 64x4; 3: 32x16; 4: 64x8; 5: 16x16; 6-10: the
 // pipelined kernel with 32x8, 64x4, 16x16, 32x16, 64x8; 11: whole rows 256x2; 12: whole
-// rows 128x4
+// rows 128x4; 13: whole rows of width nx (16 .. 128) by 512 / nx
 template <int S>
 void launch_fluid_tiled(const FluidArgs &a, int tile, int zc, hipStream_t st) {
     switch (tile) {
@@ -895,6 +918,12 @@ void launch_fluid_tiled(const FluidArgs &a, int tile, int zc, hipStream_t st) {
         case 12:
             if (a.keepf) launch_fused_t<S, 64, 8>(a, zc, st);
             else if (a.nx == 128) launch_pipe_t<S, 128, 4, true>(a, zc, st);
+            else launch_pipe_t<S, 64, 8>(a, zc, st);
+            break;
+        // whole rows of any width 16 .. 128 (512 / nx rows per tile), else 64 x 8
+        case 13:
+            if (a.keepf) launch_fused_t<S, 64, 8>(a, zc, st);
+            else if (a.nx >= 16 && a.nx <= 128) launch_pipe_rows<S>(a, zc, st);
             else launch_pipe_t<S, 64, 8>(a, zc, st);
             break;
         default: launch_fluid<S>(a, st); break;

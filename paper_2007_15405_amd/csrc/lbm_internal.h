@@ -174,7 +174,9 @@ template <int S> void launch_fluid(const FluidArgs &a, hipStream_t st);
 template <int S> void launch_fluid_tiled(const FluidArgs &a, int tile, int zc, hipStream_t st);
 // One launch of the pipelined fluid kernel over several lattices (device tables: the
 // arguments of each lattice, and per lattice {first logical block, tiles in x, tiles in
-// y, z planes per chunk}); tile 6..10 as launch_fluid_tiled.
+// y, z planes per chunk}); tile 6..10 and 13 as launch_fluid_tiled (13: every lattice
+// 16 <= nx <= 128, tiles of rows_tile_height(nx) whole rows).
+int rows_tile_height(int nx);
 template <int S> void launch_fluid_multi(const FluidArgs *tab, const int4 *desc, int ngroups,
                                          int nblocks, int tile, hipStream_t st);
 template <int S> void launch_rho(const void *f, float *rho, int nx, int ny, int nz, int wall,

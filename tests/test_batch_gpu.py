@@ -164,14 +164,15 @@ def test_batch_equals_handles_stepped_alone():
     assert max(e) <= 1e-5
     for k in range(2):
         assert np.abs(sims[1].nodes(k) - o.nodes(k)).max() <= 1e-4
-    bt.set_launch(6, 8)       # another tile and z chunk: the same result up to rounding
-    bt.step(5)
-    for i, r in enumerate(refs):
-        r.step(5)
-        a, b = sims[i].rho(), r.rho()
-        d = float(np.abs(a - b).max())
-        say("member", i, "tile 6 zchunk 8: max |diff|", d)
-        assert d <= 1e-6 * float(np.abs(b).max())
+    for tile, zc in ((6, 8), (13, 8), (13, 0)):   # other tiles and z chunks: the same
+        bt.set_launch(tile, zc)                   # result up to rounding
+        bt.step(5)
+        for i, r in enumerate(refs):
+            r.step(5)
+            a, b = sims[i].rho(), r.rho()
+            d = float(np.abs(a - b).max())
+            say("member", i, "tile", tile, "zchunk", zc, "max |diff|", d)
+            assert d <= 1e-6 * float(np.abs(b).max())
     for parts in (2, 3):      # members split over streams of the batch's own
         bt.set_parts(parts)
         bt.step(7)

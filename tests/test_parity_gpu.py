@@ -237,7 +237,7 @@ def test_fused_kernel_matches_two_kernel_variant(name):
     ref.set_launch(0)
     ref.step(steps)
     r0 = ref.rho()
-    for tile in range(1, 13):
+    for tile in range(1, 14):
         for zc in (0, 5):
             g = _sim(cfg)
             g.set_launch(tile, zc)
