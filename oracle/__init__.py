@@ -95,6 +95,10 @@ def lib(precision: str = "f64"):
                                 C.POINTER(C.c_int32), C.POINTER(C.c_double),
                                 C.POINTER(C.c_double), C.c_double, C.c_double,
                                 C.POINTER(C.c_double)]
+    L.lbmref_bending.restype = C.c_double
+    L.lbmref_bending.argtypes = [C.c_int32, C.POINTER(C.c_double), C.c_int32,
+                                 C.POINTER(C.c_int32), C.POINTER(C.c_double), C.c_double,
+                                 C.POINTER(C.c_double)]
     L.lbmref_volume.restype = C.c_double
     L.lbmref_volume.argtypes = [C.c_int32, C.POINTER(C.c_double), C.c_int32,
                                 C.POINTER(C.c_int32)]
@@ -152,6 +156,18 @@ def skalak(nodes, tris, minv, a0, ks, Cs, precision="f64"):
     E = lib(precision).lbmref_skalak(len(x), _dp(x), len(t), _ip(t),
                                      _dp(np.ascontiguousarray(minv)),
                                      _dp(np.ascontiguousarray(a0)), float(ks), float(Cs), _dp(f))
+    return E, f
+
+
+def bending(nodes, tris, ref, kb, precision="f64"):
+    """Edge-form Helfrich energy and node forces (eq. method:curvature); ``ref`` the
+    reference node positions (None: flat reference angles)."""
+    x = np.ascontiguousarray(nodes, dtype=np.float64)
+    t = np.ascontiguousarray(tris, dtype=np.int32)
+    f = np.zeros_like(x)
+    r = None if ref is None else np.ascontiguousarray(ref, dtype=np.float64)
+    E = lib(precision).lbmref_bending(len(x), _dp(x), len(t), _ip(t),
+                                      None if r is None else _dp(r), float(kb), _dp(f))
     return E, f
 
 

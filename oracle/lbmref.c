@@ -74,6 +74,9 @@ typedef struct {
     int32_t *tri;   /* [nt][3]                                               */
     double *minv;   /* [nt][4] reference inverse, row-major 2x2              */
     double *a0;     /* [nt]    reference area                                */
+    int ne;         /* edges shared by two triangles (bending, kb != 0)      */
+    int32_t *edge;  /* [ne][4] x1, x2, x3, x4: triangles (x1,x2,x3), (x2,x1,x4) */
+    double *th0;    /* [ne] reference dihedral angle                         */
     double v0, c0[3];
     double vol, cen[3];        /* at X^n, computed at the start of the step */
     double f_anchor[3];        /* sum of anchor node forces of the last step */
@@ -217,6 +220,138 @@ static double skalak_tri(const real *x1, const real *x2, const real *x3, const d
         f3[d] -= gv;
     }
     return a0 * (double)W;
+}
+
+/* Bending (Section 3.1, eq. method:curvature), in the edge form of the Helfrich energy
+ * on the triangulation: E_b = sqrt(3) kb sum_e (theta_e - theta0_e)^2, with theta_e the
+ * angle between the outward normals of the two triangles that share edge e, signed about
+ * the edge, and theta0_e its value on the stress-free reference mesh.  On an equilateral
+ * triangulation of a sphere of radius R with edge length a, theta_e = a / (sqrt(3) R); the
+ * 3 N_t / 2 edges then give sqrt(3) sum_e theta_e^2 = 8 pi, the Helfrich energy
+ * (kb / 2) oint (2H)^2 dA of the sphere, which fixes the prefactor.  The Gaussian-curvature
+ * term is a constant on a closed surface (Gauss-Bonnet) and exerts no force.  The force is
+ * -dE/dx (virtual work), with the gradient of the dihedral angle in the closed form of
+ * Blondel and Karplus (J. Comput. Chem. 17, 1132 (1996)). */
+
+typedef struct { int32_t lo, hi, from, third; } dedge_t;   /* directed edge from -> other */
+
+static int dedge_cmp(const void *a, const void *b) {
+    const dedge_t *p = (const dedge_t *)a, *q = (const dedge_t *)b;
+    if (p->lo != q->lo) return p->lo < q->lo ? -1 : 1;
+    if (p->hi != q->hi) return p->hi < q->hi ? -1 : 1;
+    return p->from < q->from ? -1 : (p->from > q->from);
+}
+
+/* Edges shared by two consistently oriented triangles: x1 -> x2 in (x1, x2, x3) and the
+ * reverse in (x2, x1, x4).  Edges of one triangle only (an open boundary) are skipped.
+ * Returns the number of shared edges, or -1 if an edge is used the same way twice or by
+ * more than two triangles. */
+static int mesh_edges(int nt, const int32_t *tri, int32_t **out) {
+    dedge_t *d = (dedge_t *)malloc(sizeof(dedge_t) * 3 * (size_t)nt);
+    for (int t = 0; t < nt; ++t)
+        for (int k = 0; k < 3; ++k) {
+            int32_t u = tri[3 * t + k], v = tri[3 * t + (k + 1) % 3], w = tri[3 * t + (k + 2) % 3];
+            dedge_t e = {u < v ? u : v, u < v ? v : u, u, w};
+            d[3 * t + k] = e;
+        }
+    qsort(d, 3 * (size_t)nt, sizeof(dedge_t), dedge_cmp);
+    int32_t *edge = (int32_t *)malloc(sizeof(int32_t) * 4 * 3 * (size_t)nt);
+    int ne = 0, bad = 0;
+    for (int i = 0; i < 3 * nt;) {
+        int j = i;
+        while (j < 3 * nt && d[j].lo == d[i].lo && d[j].hi == d[i].hi) ++j;
+        if (j - i == 2 && d[i].from != d[i + 1].from) {
+            /* d[i] runs lo -> hi: x1 = lo, x2 = hi, x3 its third node; x4 the other's */
+            edge[4 * ne] = d[i].lo;
+            edge[4 * ne + 1] = d[i].hi;
+            edge[4 * ne + 2] = d[i].third;
+            edge[4 * ne + 3] = d[i + 1].third;
+            ++ne;
+        } else if (j - i > 1) {
+            bad = 1;
+        }
+        i = j;
+    }
+    free(d);
+    if (bad) { free(edge); *out = NULL; return -1; }
+    *out = edge;
+    return ne;
+}
+
+static void sub3(const real *a, const real *b, real *o) {
+    for (int d = 0; d < 3; ++d) o[d] = a[d] - b[d];
+}
+static void cross3(const real *a, const real *b, real *o) {
+    o[0] = a[1] * b[2] - a[2] * b[1];
+    o[1] = a[2] * b[0] - a[0] * b[2];
+    o[2] = a[0] * b[1] - a[1] * b[0];
+}
+static real dot3(const real *a, const real *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+/* Dihedral angle of the edge x1 - x2 between the outward normals of (x1, x2, x3) and
+ * (x2, x1, x4), and (if g) its gradient with respect to x1 .. x4. */
+static double dihedral(const real *x1, const real *x2, const real *x3, const real *x4,
+                       real g[4][3]) {
+    real F[3], G[3], H[3], A[3], B[3], BA[3];
+    sub3(x3, x1, F);
+    sub3(x1, x2, G);
+    sub3(x4, x2, H);
+    cross3(F, G, A);   /* outward normal of (x1, x2, x3) */
+    cross3(H, G, B);   /* minus the outward normal of (x2, x1, x4) */
+    cross3(B, A, BA);
+    const real gl = sqrt(dot3(G, G)), a2 = dot3(A, A), b2 = dot3(B, B);
+    /* normals n1 = A, n2 = -B, edge direction -G / |G| */
+    const double th = atan2(-(double)dot3(BA, G) / gl, -(double)dot3(A, B));
+    if (g) {
+        const real fg = dot3(F, G) / (a2 * gl), hg = dot3(H, G) / (b2 * gl);
+        for (int d = 0; d < 3; ++d) {
+            g[2][d] = -gl / a2 * A[d];
+            g[3][d] = gl / b2 * B[d];
+            g[0][d] = gl / a2 * A[d] + fg * A[d] - hg * B[d];
+            g[1][d] = -(g[0][d] + g[2][d] + g[3][d]);
+        }
+    }
+    return th;
+}
+
+/* bending energy of one edge, and its forces added to f1 .. f4 */
+static double bending_edge(const real *x1, const real *x2, const real *x3, const real *x4,
+                           double th0, double kb, real *f1, real *f2, real *f3, real *f4) {
+    real g[4][3];
+    const double th = dihedral(x1, x2, x3, x4, g);
+    const double k = sqrt(3.0) * kb, dth = th - th0;
+    real *f[4] = {f1, f2, f3, f4};
+    for (int v = 0; v < 4; ++v)
+        for (int d = 0; d < 3; ++d) f[v][d] -= (real)(2.0 * k * dth) * g[v][d];
+    return k * dth * dth;
+}
+
+double lbmref_bending(int32_t nn, const double *x, int32_t nt, const int32_t *tri,
+                      const double *ref, double kb, double *force) {
+    int32_t *edge = NULL;
+    const int ne = mesh_edges(nt, tri, &edge);
+    if (ne < 0) return NAN;
+    real *xr = (real *)malloc(sizeof(real) * 3 * nn), *rr = (real *)malloc(sizeof(real) * 3 * nn);
+    real *fr = (real *)calloc(3 * nn, sizeof(real));
+    for (int i = 0; i < 3 * nn; ++i) {
+        xr[i] = (real)x[i];
+        rr[i] = ref ? (real)ref[i] : 0;
+    }
+    double E = 0.0;
+    for (int e = 0; e < ne; ++e) {
+        const int32_t *q = edge + 4 * e;
+        const double th0 = ref ? dihedral(rr + 3 * q[0], rr + 3 * q[1], rr + 3 * q[2],
+                                          rr + 3 * q[3], NULL) : 0.0;
+        E += bending_edge(xr + 3 * q[0], xr + 3 * q[1], xr + 3 * q[2], xr + 3 * q[3], th0, kb,
+                          fr + 3 * q[0], fr + 3 * q[1], fr + 3 * q[2], fr + 3 * q[3]);
+    }
+    if (force)
+        for (int i = 0; i < 3 * nn; ++i) force[i] = fr[i];
+    free(edge);
+    free(xr);
+    free(rr);
+    free(fr);
+    return E;
 }
 
 double lbmref_skalak(int32_t nn, const double *x, int32_t nt, const int32_t *tri,
@@ -494,7 +629,7 @@ int lbmref_add_capsule(lbmref_handle *h, const lbmref_capsule_params *cp, int32_
                        const double *xyz, int32_t nt, const int32_t *tri) {
     if (!h || !cp || nn < 4 || nt < 4 || !xyz || !tri) { set_err("invalid capsule"); return -1; }
     if (h->step > 0) { set_err("capsules must be added before the first step"); return -5; }
-    if (cp->kb != 0.0) { set_err("bending (kb != 0) is not part of this method build"); return -1; }
+    if (!(cp->kb >= 0.0)) { set_err("bending modulus must be >= 0"); return -1; }
     if (h->ncap >= 254) { set_err("too many capsules"); return -1; }
     for (int t = 0; t < 3 * nt; ++t)
         if (tri[t] < 0 || tri[t] >= nn) { set_err("triangle index out of range"); return -1; }
@@ -519,6 +654,24 @@ int lbmref_add_capsule(lbmref_handle *h, const lbmref_capsule_params *cp, int32_
         for (int d = 0; d < 3; ++d) cen[d] += xyz[3 * i + d];
     for (int d = 0; d < 3; ++d) c->c0[d] = cen[d] / nn;
     c->v0 = lbmref_volume(nn, xyz, nt, tri);
+    if (cp->kb != 0.0) {
+        /* every edge shared by two triangles; reference angles from the initial mesh */
+        c->ne = mesh_edges(nt, tri, &c->edge);
+        if (2 * c->ne != 3 * nt) {
+            set_err("bending needs a closed, consistently oriented mesh");
+            free(c->edge); free(c->x); free(c->R); free(c->F); free(c->Fh); free(c->tri);
+            free(c->minv); free(c->a0);
+            return -1;
+        }
+        c->th0 = (double *)malloc(sizeof(double) * c->ne);
+        real *xr = (real *)malloc(sizeof(real) * 3 * nn);
+        for (int i = 0; i < 3 * nn; ++i) xr[i] = (real)xyz[i];
+        for (int e = 0; e < c->ne; ++e) {
+            const int32_t *q = c->edge + 4 * e;
+            c->th0[e] = dihedral(xr + 3 * q[0], xr + 3 * q[1], xr + 3 * q[2], xr + 3 * q[3], NULL);
+        }
+        free(xr);
+    }
     h->ncap++;
     compute_labels(h);
     return h->ncap - 1;
@@ -573,6 +726,14 @@ static void membrane_forces(lbmref_handle *h) {
             skalak_tri(c->x + 3 * a, c->x + 3 * b, c->x + 3 * cc, c->minv + 4 * t, c->a0[t],
                        c->p.ks, c->p.C, c->F + 3 * a, c->F + 3 * b, c->F + 3 * cc);
         }
+        /* bending, eq. method:curvature (edge form) */
+        if (c->p.kb != 0.0)
+            for (int e = 0; e < c->ne; ++e) {
+                const int32_t *q = c->edge + 4 * e;
+                bending_edge(c->x + 3 * q[0], c->x + 3 * q[1], c->x + 3 * q[2], c->x + 3 * q[3],
+                             c->th0[e], c->p.kb, c->F + 3 * q[0], c->F + 3 * q[1],
+                             c->F + 3 * q[2], c->F + 3 * q[3]);
+            }
         /* volume penalty, eq. vol_cons */
         if (c->p.kv != 0.0)
             volume_force_add(c->nn, c->x, c->nt, c->tri, c->p.kv, c->vol, c->v0, c->cen, c->F);
@@ -959,6 +1120,7 @@ void lbmref_destroy(lbmref_handle *h) {
     for (int k = 0; k < h->ncap; ++k) {
         cap_t *c = &h->cap[k];
         free(c->x); free(c->R); free(c->F); free(c->Fh); free(c->tri); free(c->minv); free(c->a0);
+        free(c->edge); free(c->th0);
     }
     free(h->cap);
     free(h->f); free(h->fn); free(h->rho); free(h->psi); free(h->label);

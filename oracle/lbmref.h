@@ -42,7 +42,7 @@ typedef struct {
 typedef struct {
     double ks;        /* Skalak shear modulus kappa_S                     */
     double C;         /* Skalak area constant C                           */
-    double kb;        /* bending modulus: must be 0 (no bending term)     */
+    double kb;        /* bending modulus kappa_B (eq. method:curvature), >= 0 */
     double kv;        /* volume penalty kappa_V                           */
     double wet_drho;  /* wetting offset of the membrane (0: neutral)      */
     double anchor_k;  /* centroid anchor spring (0: free)                 */
@@ -89,6 +89,11 @@ void lbmref_reference_geometry(int32_t n_nodes, const double *xyz, int32_t n_tri
                                const int32_t *tri, double *minv, double *a0);
 double lbmref_skalak(int32_t n_nodes, const double *xyz, int32_t n_tri, const int32_t *tri,
                      const double *minv, const double *a0, double ks, double C, double *force);
+/* Bending energy sqrt(3) kb sum_e (theta_e - theta0_e)^2 over the edges shared by two
+ * triangles, theta0 from ref (node positions of the reference mesh) or 0 if ref is NULL;
+ * force [n_nodes][3] = -dE/dx if not NULL.  NaN for a non-manifold mesh. */
+double lbmref_bending(int32_t n_nodes, const double *xyz, int32_t n_tri, const int32_t *tri,
+                      const double *ref, double kb, double *force);
 double lbmref_volume(int32_t n_nodes, const double *xyz, int32_t n_tri, const int32_t *tri);
 void lbmref_volume_force(int32_t n_nodes, const double *xyz, int32_t n_tri, const int32_t *tri,
                          double kv, double v0, double *force);

@@ -289,3 +289,88 @@ def test_labels_sphere_count():
     Z, Y, X = np.mgrid[0:40, 0:32, 0:32]
     deep = np.sqrt((X - 16.3) ** 2 + (Y - 15.8) ** 2 + (Z - 22.45) ** 2) < R - 1.5
     assert ins[deep].all()
+
+
+# ---------------------------------------------------------------------------------------
+# Bending (Section 3.1, eq. method:curvature; edge form sqrt(3) kb sum (theta - theta0)^2)
+# ---------------------------------------------------------------------------------------
+
+
+def _hinge(theta):
+    """Two unit equilateral triangles (x1, x2, x3) and (x2, x1, x4) on the edge x1-x2 along
+    x, the second rotated about the edge so that the normals make the angle theta."""
+    s3 = math.sqrt(3.0) / 2.0
+    x1, x2 = np.array([0.0, 0.0, 0.0]), np.array([1.0, 0.0, 0.0])
+    x3 = np.array([0.5, s3, 0.0])
+    x4 = np.array([0.5, -s3 * math.cos(theta), -s3 * math.sin(theta)])
+    return np.array([x1, x2, x3, x4]), np.array([[0, 1, 2], [1, 0, 3]], dtype=np.int32)
+
+
+def test_bending_hinge_closed_form():
+    """Two triangles hinged by theta about their shared edge: E = sqrt(3) kb (theta -
+    theta0)^2, for either sign of the fold and any reference angle."""
+    for th in (0.3, -0.3, 1.1):
+        X, T = _hinge(th)
+        flat, _ = _hinge(0.0)
+        E, F = oracle.bending(X, T, flat, 0.7)
+        assert E == pytest.approx(math.sqrt(3.0) * 0.7 * th * th, rel=1e-12)
+        ref, _ = _hinge(0.5)
+        E2, _ = oracle.bending(X, T, ref, 0.7)
+        assert E2 == pytest.approx(math.sqrt(3.0) * 0.7 * (th - 0.5) ** 2, rel=1e-12, abs=1e-15)
+        assert np.allclose(F.sum(0), 0.0, atol=1e-13)
+
+
+def test_bending_reference_shape_is_stress_free():
+    X, T = synth.icosphere(3, 6.0, (16.0, 16.0, 10.0))
+    E, F = oracle.bending(X, T, X, 0.3)
+    assert E == 0.0 and np.all(F == 0.0)
+
+
+def test_bending_force_is_minus_gradient():
+    X, T = synth.icosphere(2, 3.0)
+    rng = np.random.default_rng(7)
+    Y = X + 0.08 * rng.standard_normal(X.shape)
+    E, F = oracle.bending(Y, T, X, 0.2)
+    assert E > 0.1
+    h = 1e-6
+    for i in range(0, len(Y), 5):
+        for d in range(3):
+            Yp, Ym = Y.copy(), Y.copy()
+            Yp[i, d] += h
+            Ym[i, d] -= h
+            g = (oracle.bending(Yp, T, X, 0.2)[0] - oracle.bending(Ym, T, X, 0.2)[0]) / (2 * h)
+            assert F[i, d] == pytest.approx(-g, abs=1e-7 * max(1.0, np.abs(F).max()))
+
+
+def test_bending_no_net_force_torque_and_rigid_invariance():
+    X, T = synth.icosphere(2, 4.0, (1.0, 2.0, 3.0))
+    rng = np.random.default_rng(3)
+    Y = X + 0.1 * rng.standard_normal(X.shape)
+    E, F = oracle.bending(Y, T, X, 0.5)
+    assert np.abs(F.sum(0)).max() < 1e-12
+    assert np.abs(np.cross(Y, F).sum(0)).max() < 1e-11
+    a, b = 0.7, -1.3
+    Rz = np.array([[math.cos(a), -math.sin(a), 0], [math.sin(a), math.cos(a), 0], [0, 0, 1]])
+    Rx = np.array([[1, 0, 0], [0, math.cos(b), -math.sin(b)], [0, math.sin(b), math.cos(b)]])
+    Rm, t = Rz @ Rx, np.array([5.0, -2.0, 9.0])
+    E2, F2 = oracle.bending(Y @ Rm.T + t, T, X, 0.5)     # reference may stay put
+    assert E2 == pytest.approx(E, rel=1e-10)
+    assert np.allclose(F2, F @ Rm.T, atol=1e-10)
+
+
+@pytest.mark.parametrize("level", [2, 3, 4])
+def test_bending_energy_of_a_sphere_is_helfrichs(level):
+    """Flat reference angles: the edge form of a triangulated sphere approaches the
+    Helfrich energy (kb/2) oint (2H)^2 dA = 8 pi kb of the sphere at any radius (exactly on
+    an equilateral triangulation; the icosphere's unequal triangles add 3.5 %)."""
+    E1, _ = oracle.bending(*synth.icosphere(level, 1.0), None, 1.0)
+    E10, _ = oracle.bending(*synth.icosphere(level, 10.0, (3.0, 4.0, 5.0)), None, 1.0)
+    assert E10 == pytest.approx(E1, rel=1e-9)              # scale invariant, as Helfrich's
+    assert 1.0 <= E1 / (8 * math.pi) <= 1.04
+
+
+def test_bending_needs_a_manifold_mesh():
+    X, T = synth.icosphere(1, 1.0)
+    T2 = np.vstack([T, T[:1]])                              # a triangle used twice
+    E, _ = oracle.bending(X, T2, X, 1.0)
+    assert math.isnan(E)
