@@ -229,6 +229,8 @@ def main():
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched form")
     ap.add_argument("--batch-only", action="store_true", help="only the batched form")
+    ap.add_argument("--kb", type=float, default=0.0,
+                    help="bending modulus of the film box's capsules (the workload has none)")
     ap.add_argument("--parts", type=int, default=None,
                     help="batched form: only this split over streams (default: try 1..4)")
     ap.add_argument("--tile", type=int, default=None, help="fixed launch shape (skips tuning)")
@@ -257,6 +259,8 @@ def main():
 
     import synth
     cfg = synth.workload("c3")
+    if args.kb:
+        cfg["capsules"] = [dict(c, kb=args.kb) for c in cfg["capsules"]]
     res = {}
     batched = {}
     if not args.no_batch:
@@ -293,7 +297,8 @@ def main():
         vs_baseline=None,
         dtype="f32",
         data="synthetic",
-        config=dict(workload=WORKLOAD, nx=256, ny=256, nz=96, capsules=16,
+        config=dict(workload=WORKLOAD + (f", bending kb={args.kb}" if args.kb else ""),
+                    nx=256, ny=256, nz=96, capsules=16,
                     storage=head_st, fluid_sites=head["fluid_sites"]),
         roofline=dict(bound="hbm", achieved=round(head["achieved_gbs"], 1), peak=PEAK_HBM_GBS,
                       unit="GB/s", frac=round(head["frac"], 4),

@@ -6,8 +6,8 @@
  * One time step (all on the GPU, on the handle's stream):
  *   - side labels of every lattice site from the capsule meshes (interior/exterior
  *     decoupling of the Shan-Chen force, Section 3.1);
- *   - membrane node forces: Skalak strain energy by virtual work (eq. strain), volume
- *     penalty (eq. vol_cons), Hertz particle-substrate / particle-particle repulsion
+ *   - membrane node forces: Skalak strain energy by virtual work (eq. strain), bending
+ *     (eq. method:curvature, edge form), volume penalty (eq. vol_cons), Hertz particle-substrate / particle-particle repulsion
  *     (Section 3.2, eq. interactions), a centroid anchor, and the pending reaction of
  *     the cross-membrane Shan-Chen links;
  *   - immersed-boundary spreading of the node forces (Peskin 4-point kernel);
@@ -116,7 +116,10 @@ typedef struct {
 typedef struct {
     double ks;        /* Skalak shear modulus kappa_S (eq. strain)                       */
     double C;         /* Skalak area constant C > -1/2; kappa_A = kappa_S (1 + 2C)        */
-    double kb;        /* bending modulus: must be 0 (bending is not part of this build) */
+    double kb;        /* bending modulus kappa_B >= 0 (eq. method:curvature), in the edge
+                         form sqrt(3) kb sum_e (theta_e - theta0_e)^2 over the mesh edges,
+                         theta the dihedral angle, theta0 that of the reference mesh;
+                         kb != 0 needs a closed, consistently oriented mesh            */
     double kv;        /* volume penalty kappa_V (eq. vol_cons)                           */
     double wet_drho;  /* wetting offset of the membrane (0 neutral)                      */
     double anchor_k;  /* centroid anchor spring; 0 leaves the capsule free               */

@@ -22,6 +22,8 @@ struct HostCap {
     int zbase;                 // wall layer of the capsule's slab
     std::vector<double> x0;    // [nn][3]
     std::vector<int32_t> tri;  // [nt][3]
+    std::vector<int32_t> edge; // bending (kb != 0): [ne][4] x1, x2, x3, x4 (local nodes)
+    std::vector<double> th0;   // [ne] reference dihedral angles
 };
 
 struct Timer {
@@ -77,6 +79,9 @@ struct lbm_handle {
     int nch = 1;
     float4 *d_wbuf = nullptr;
     uint8_t *d_wpar = nullptr;
+    int4 *d_edge = nullptr;
+    float *d_eth0 = nullptr;
+    int *d_eoff = nullptr, *d_elist = nullptr;
     std::vector<CapDev> h_caps;
     int tile = 1, zchunk = 0;
     Prof prof;
@@ -90,6 +95,49 @@ struct lbm_handle {
             return LBM_E_DEVICE;                                                      \
         }                                                                             \
     } while (0)
+
+// Bending edges of a closed, consistently oriented mesh: every edge x1 -> x2 of a
+// triangle (x1, x2, x3) whose reverse x2 -> x1 belongs to a triangle (x2, x1, x4), once.
+// False if some edge has no reverse or occurs twice in the same direction.
+static bool bending_edges(int nt, const int32_t *tri, std::vector<int32_t> &e4) {
+    struct Dir { int32_t a, b, w; };
+    std::vector<Dir> d;
+    d.reserve(3 * (size_t)nt);
+    for (int t = 0; t < nt; ++t)
+        for (int k = 0; k < 3; ++k)
+            d.push_back({tri[3 * t + k], tri[3 * t + (k + 1) % 3], tri[3 * t + (k + 2) % 3]});
+    auto less = [](const Dir &x, const Dir &y) { return x.a != y.a ? x.a < y.a : x.b < y.b; };
+    std::sort(d.begin(), d.end(), less);
+    for (size_t i = 1; i < d.size(); ++i)
+        if (d[i].a == d[i - 1].a && d[i].b == d[i - 1].b) return false;
+    e4.clear();
+    for (const Dir &x : d) {
+        const Dir key{x.b, x.a, 0};
+        auto it = std::lower_bound(d.begin(), d.end(), key, less);
+        if (it == d.end() || it->a != x.b || it->b != x.a) return false;
+        if (x.a < x.b) e4.insert(e4.end(), {x.a, x.b, x.w, it->w});
+    }
+    return 2 * e4.size() / 4 == 3 * (size_t)nt;
+}
+
+// signed angle between the outward normals of (p1, p2, p3) and (p2, p1, p4) about the
+// edge p1 -> p2 (FP64, for the reference mesh)
+static double dihedral_of(const double *p1, const double *p2, const double *p3, const double *p4) {
+    double e[3], u[3], v[3], n1[3], n2[3];
+    for (int d = 0; d < 3; ++d) {
+        e[d] = p2[d] - p1[d];
+        u[d] = p3[d] - p1[d];
+        v[d] = p4[d] - p2[d];
+    }
+    // n1 = e x u; n2 = (p1 - p2) x (p4 - p2) = v x e
+    n1[0] = e[1] * u[2] - e[2] * u[1]; n1[1] = e[2] * u[0] - e[0] * u[2]; n1[2] = e[0] * u[1] - e[1] * u[0];
+    n2[0] = v[1] * e[2] - v[2] * e[1]; n2[1] = v[2] * e[0] - v[0] * e[2]; n2[2] = v[0] * e[1] - v[1] * e[0];
+    const double el = std::sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
+    const double c[3] = {n1[1] * n2[2] - n1[2] * n2[1], n1[2] * n2[0] - n1[0] * n2[2],
+                         n1[0] * n2[1] - n1[1] * n2[0]};
+    return std::atan2((c[0] * e[0] + c[1] * e[1] + c[2] * e[2]) / el,
+                      n1[0] * n2[0] + n1[1] * n2[1] + n1[2] * n2[2]);
+}
 
 static lbm_status fail(lbm_handle *h, lbm_status s, const std::string &m) {
     h->err = m;
@@ -116,7 +164,8 @@ static void free_all(lbm_handle *h) {
                     h->rho_tmp, h->men_tmp, h->status, h->partial, h->d_caps, h->d_cst, h->d_X,
                     h->d_node_cap, h->d_F, h->d_Fh, h->d_R, h->d_tri, h->d_minv, h->d_a0,
                     h->d_off, h->d_list, h->d_marks, h->d_rowstart, h->d_slot, h->d_wbuf,
-                    h->d_wpar, h->d_part, h->d_xrow};
+                    h->d_wpar, h->d_part, h->d_xrow, h->d_edge, h->d_eth0, h->d_eoff,
+                    h->d_elist};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     free_prof(h->prof);
@@ -344,9 +393,8 @@ extern "C" lbm_status lbm_add_capsule(lbm_handle *h, const lbm_capsule_params *c
     if (!cp || !xyz || !tri || n_nodes < 4 || n_tri < 4 || n_nodes > MAX_CAP_NODES)
         return fail(h, LBM_E_INVAL, "invalid capsule mesh");
     if ((int)h->caps.size() >= MAX_CAPS) return fail(h, LBM_E_INVAL, "too many capsules");
-    if (cp->kb != 0.0) return fail(h, LBM_E_INVAL, "bending (kb != 0) is not supported");
     if (!(cp->ks >= 0.0) || !(cp->C > -0.5) || !(cp->kv >= 0.0) || !(cp->anchor_k >= 0.0) ||
-        !std::isfinite(cp->wet_drho))
+        !(cp->kb >= 0.0) || !std::isfinite(cp->kb) || !std::isfinite(cp->wet_drho))
         return fail(h, LBM_E_INVAL, "invalid capsule parameters");
     for (int i = 0; i < 3 * n_tri; ++i)
         if (tri[i] < 0 || tri[i] >= n_nodes) return fail(h, LBM_E_INVAL, "triangle index out of range");
@@ -394,6 +442,15 @@ extern "C" lbm_status lbm_add_capsule(lbm_handle *h, const lbm_capsule_params *c
     HostCap c;
     c.p = *cp;
     c.zbase = zbase;
+    if (cp->kb != 0.0) {
+        if (!bending_edges(n_tri, tri, c.edge))
+            return fail(h, LBM_E_INVAL, "bending needs a closed, consistently oriented mesh");
+        c.th0.resize(c.edge.size() / 4);
+        for (size_t e = 0; e < c.th0.size(); ++e) {
+            const int32_t *q = &c.edge[4 * e];
+            c.th0[e] = dihedral_of(xyz + 3 * q[0], xyz + 3 * q[1], xyz + 3 * q[2], xyz + 3 * q[3]);
+        }
+    }
     c.x0.assign(xyz, xyz + 3 * (size_t)n_nodes);
     c.tri.assign(tri, tri + 3 * (size_t)n_tri);
     h->caps.push_back(std::move(c));
@@ -446,6 +503,7 @@ static lbm_status finalize(lbm_handle *h) {
         cd.C = (float)c.p.C;
         cd.kv = (float)c.p.kv;
         cd.anchor_k = (float)c.p.anchor_k;
+        cd.kb = (float)c.p.kb;
         cd.zbase = c.zbase;
         cd.plane_z = (float)(c.zbase + 0.5 + h->p.plane_dz);
         double cen[3] = {0, 0, 0};
@@ -499,7 +557,38 @@ static lbm_status finalize(lbm_handle *h) {
         list[cur[tri[t].y]++] = 3 * t + 1;
         list[cur[tri[t].z]++] = 3 * t + 2;
     }
+    // bending edges (global node indices) and the node -> (edge, role) CSR
+    std::vector<int4> edges;
+    std::vector<float> eth0;
+    for (int k = 0; k < ncap; ++k) {
+        const HostCap &c = h->caps[k];
+        const int n0 = h->h_caps[k].node0;
+        for (size_t e = 0; e < c.th0.size(); ++e) {
+            const int32_t *q = &c.edge[4 * e];
+            edges.push_back(make_int4(n0 + q[0], n0 + q[1], n0 + q[2], n0 + q[3]));
+            eth0.push_back((float)c.th0[e]);
+        }
+    }
+    std::vector<int> eoff(h->ntot + 1, 0), elist(4 * edges.size());
+    for (const int4 &q : edges) { eoff[q.x + 1]++; eoff[q.y + 1]++; eoff[q.z + 1]++; eoff[q.w + 1]++; }
+    for (int i = 0; i < h->ntot; ++i) eoff[i + 1] += eoff[i];
+    {
+        std::vector<int> ecur(eoff.begin(), eoff.end() - 1);
+        for (size_t e = 0; e < edges.size(); ++e) {
+            const int v[4] = {edges[e].x, edges[e].y, edges[e].z, edges[e].w};
+            for (int r = 0; r < 4; ++r) elist[ecur[v[r]]++] = 4 * (int)e + r;
+        }
+    }
     const size_t nt = h->ntot, tt = h->ttot;
+    if (dalloc(&h->d_edge, edges.size()) != hipSuccess || dalloc(&h->d_eth0, eth0.size()) != hipSuccess ||
+        dalloc(&h->d_eoff, nt + 1) != hipSuccess || dalloc(&h->d_elist, elist.size()) != hipSuccess)
+        return fail(h, LBM_E_NOMEM, "device allocation failed (bending)");
+    if (!edges.empty()) {
+        HIPCHK(h, hipMemcpyAsync(h->d_edge, edges.data(), edges.size() * sizeof(int4), hipMemcpyHostToDevice, h->st));
+        HIPCHK(h, hipMemcpyAsync(h->d_eth0, eth0.data(), eth0.size() * sizeof(float), hipMemcpyHostToDevice, h->st));
+        HIPCHK(h, hipMemcpyAsync(h->d_elist, elist.data(), elist.size() * sizeof(int), hipMemcpyHostToDevice, h->st));
+    }
+    HIPCHK(h, hipMemcpyAsync(h->d_eoff, eoff.data(), (nt + 1) * sizeof(int), hipMemcpyHostToDevice, h->st));
     if (dalloc(&h->d_caps, ncap) != hipSuccess || dalloc(&h->d_cst, ncap) != hipSuccess ||
         dalloc(&h->d_X, nt) != hipSuccess || dalloc(&h->d_node_cap, nt) != hipSuccess ||
         dalloc(&h->d_F, nt) != hipSuccess || dalloc(&h->d_Fh, nt) != hipSuccess ||
@@ -543,6 +632,7 @@ static MembraneArgs membrane_args(lbm_handle *h) {
     m.X = h->d_X; m.node_cap = h->d_node_cap; m.F = h->d_F; m.Fh = h->d_Fh; m.R = h->d_R;
     m.tri = h->d_tri; m.minv = h->d_minv; m.a0 = h->d_a0;
     m.ntri_off = h->d_off; m.ntri = h->d_list;
+    m.edge = h->d_edge; m.eth0 = h->d_eth0; m.nedge_off = h->d_eoff; m.nedge = h->d_elist;
     m.marks = h->d_marks; m.rowstart = h->d_rowstart; m.xrow = h->d_xrow; m.slot = h->d_slot;
     m.part = h->d_part; m.nch = h->nch;
     m.wbuf = h->d_wbuf; m.wpar = h->d_wpar;

@@ -112,6 +112,7 @@ struct CapDev {
     int node0, nn;          // first node, node count
     int tri0, nt;           // first triangle, triangle count
     float ks, C, kv, anchor_k;
+    float kb;               // bending modulus (edge form of the Helfrich energy)
     float plane_z;          // repulsive plane of the capsule's slab
     int zbase;              // wall layer of the capsule's slab
     double v0;              // reference volume
@@ -149,6 +150,11 @@ struct MembraneArgs {
     const float *a0;        // [Ttot] reference area
     const int *ntri_off;    // [Ntot+1] node -> incident triangle CSR offsets
     const int *ntri;        // incident entries: 3 * triangle + corner
+    const int4 *edge;       // [Etot] bending edges x1, x2, x3, x4 (global node indices):
+                            // triangles (x1, x2, x3) and (x2, x1, x4)
+    const float *eth0;      // [Etot] reference dihedral angle
+    const int *nedge_off;   // [Ntot+1] node -> bending edge CSR offsets
+    const int *nedge;       // entries: 4 * edge + role (0..3 for x1..x4)
     unsigned long long *marks;  // [ncap][ROWS_MAX] crossings per window column, bit = plane
     int *rowstart;          // [ncap][ROWS_MAX + 1] node rows of each window
     double4 *xrow;          // [Ntot] node positions grouped by row (any order in a row)

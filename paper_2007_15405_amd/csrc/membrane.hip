@@ -505,6 +505,45 @@ __device__ __forceinline__ void membrane_body(const MembraneArgs &m, int blk, in
             f[2] += (float)(vcoef * (pb[0] * pc[1] - pb[1] * pc[0]) / 6.0);
         }
     }
+    if (cd.kb != 0.0f) {
+        // bending (eq. method:curvature, edge form): E = sqrt(3) kb sum_e (theta_e - theta0_e)^2
+        // with theta_e the signed angle between the outward normals of the triangles
+        // (x1, x2, x3) and (x2, x1, x4); this node's share of -dE/dx for each edge it is
+        // part of, with the closed-form dihedral gradient (Blondel and Karplus, 1996)
+        const float kk = -3.4641016f * cd.kb;   // -2 sqrt(3) kb
+        const int b1 = m.nedge_off[n + 1];
+        for (int e = m.nedge_off[n] + sl; e < b1; e += MEM_L) {
+            const int ent = m.nedge[e];
+            const int ed = ent >> 2, role = ent & 3;
+            const int4 q = m.edge[ed];
+            const double4 P1 = m.X[q.x], P2 = m.X[q.y], P3 = m.X[q.z], P4 = m.X[q.w];
+            const float3 F = make_float3((float)(P3.x - P1.x), (float)(P3.y - P1.y), (float)(P3.z - P1.z));
+            const float3 G = make_float3((float)(P1.x - P2.x), (float)(P1.y - P2.y), (float)(P1.z - P2.z));
+            const float3 H = make_float3((float)(P4.x - P2.x), (float)(P4.y - P2.y), (float)(P4.z - P2.z));
+            const float3 A = make_float3(F.y * G.z - F.z * G.y, F.z * G.x - F.x * G.z, F.x * G.y - F.y * G.x);
+            const float3 B = make_float3(H.y * G.z - H.z * G.y, H.z * G.x - H.x * G.z, H.x * G.y - H.y * G.x);
+            const float gg = G.x * G.x + G.y * G.y + G.z * G.z, gl = sqrtf(gg);
+            const float a2 = A.x * A.x + A.y * A.y + A.z * A.z, b2 = B.x * B.x + B.y * B.y + B.z * B.z;
+            const float ab = A.x * B.x + A.y * B.y + A.z * B.z;
+            // (B x A) . G
+            const float bag = (B.y * A.z - B.z * A.y) * G.x + (B.z * A.x - B.x * A.z) * G.y +
+                              (B.x * A.y - B.y * A.x) * G.z;
+            const float th = atan2f(-bag / gl, -ab);
+            const float coef = kk * (th - m.eth0[ed]);
+            const float ca = gl / a2, cb = gl / b2;
+            const float fg = (F.x * G.x + F.y * G.y + F.z * G.z) / (a2 * gl);
+            const float hg = (H.x * G.x + H.y * G.y + H.z * G.z) / (b2 * gl);
+            // d theta / d x_role = wa A + wb B
+            float wa, wb;
+            if (role == 0) { wa = ca + fg; wb = -hg; }
+            else if (role == 1) { wa = -fg; wb = hg - cb; }
+            else if (role == 2) { wa = -ca; wb = 0.f; }
+            else { wa = 0.f; wb = cb; }
+            f[0] += coef * (wa * A.x + wb * B.x);
+            f[1] += coef * (wa * A.y + wb * B.y);
+            f[2] += coef * (wa * A.z + wb * B.z);
+        }
+    }
     const float xi = m.hertz_xi, d0 = m.hertz_d0;
     if (sl == 0 && m.wall && xi > 0.f) {
         const float d = (float)(X.z - (double)cd.plane_z);

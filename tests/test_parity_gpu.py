@@ -328,3 +328,50 @@ def test_hertz_contact_between_capsules(case):
     for k in range(len(caps)):
         assert np.abs(g.nodes(k) - o.nodes(k)).max() <= 1e-4
     assert max(rel_l2(g.rho(), o.rho())) <= 1e-5
+
+
+@pytest.mark.parametrize("case", ["film", "contact"])
+def test_bending_tracks_the_oracle(case):
+    """Bending resistance (eq. method:curvature, edge form) at the paper's softness scale
+    beta = R^2 gamma / kappa_B = 25 (gamma = 0.049 for this fluid pair): a capsule deformed
+    by the film's interface, and two capsules pressed together by the Hertz contact.
+    Densities, nodes and capsule forces against the oracle; the oracle's own run without
+    bending ends visibly elsewhere, so the term is exercised."""
+    if case == "film":
+        caps = [synth.capsule((16.0, 16.0, 10.0), 6.0, 1280, 0.005, kb=0.07)]
+        cfg = synth.workload("pf", capsules=caps)
+        steps = 500
+    else:
+        caps = [synth.capsule((7.5, 12.0, 12.0), 4.0, 320, 0.02, kb=0.03),
+                synth.capsule((16.5, 12.3, 12.2), 4.0, 320, 0.02, kb=0.03)]
+        cfg = synth.workload("pf", nx=24, ny=24, nz=24, film_height=8, capsules=caps)
+        steps = 120
+    g, o = run_pair(cfg, steps)
+    e = rel_l2(g.rho(), o.rho())
+    err = max(float(np.abs(g.nodes(k) - o.nodes(k)).max()) for k in range(len(caps)))
+    flat = synth.workload("pf", **{k: cfg[k] for k in ("nx", "ny", "nz", "film_height")},
+                          capsules=[dict(c, kb=0.0) for c in caps])
+    o0 = oracle.Oracle(flat)
+    o0.step(steps)
+    shift = max(float(np.abs(o.nodes(k) - o0.nodes(k)).max()) for k in range(len(caps)))
+    say(case, "rel-L2", e, "node error", err, "effect of bending on the nodes", shift)
+    assert max(e) <= 1e-5
+    assert err <= 1e-4
+    assert shift > 1e-3 and shift > 20 * err
+    for k in range(len(caps)):
+        cg, co = g.capsule(k), o.capsule(k)
+        assert abs(cg["volume"] - co["volume"]) / co["volume"] <= 1e-5
+        for f in ("f_capillary", "f_hertz"):
+            assert np.linalg.norm(cg[f] - co[f]) <= 1e-3 * max(np.linalg.norm(co[f]), 1e-3)
+
+
+def test_bending_needs_a_closed_mesh():
+    from paper_2007_15405_amd import LbmError
+    g = _sim(synth.workload("pf", capsules=[]))
+    cap = synth.capsule((16.0, 16.0, 16.0), 4.0, 320, 0.02, kb=0.05)
+    nodes, tris = synth.capsule_mesh(cap)
+    with pytest.raises(LbmError) as ei:
+        g.add_capsule(cap, nodes, tris[:-2])          # two triangles removed: open mesh
+    assert ei.value.status == -1
+    g.add_capsule(cap, nodes, tris)
+    g.close()
