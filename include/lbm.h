@@ -266,6 +266,44 @@ lbm_status lbm_batch_kernel_stats(lbm_batch *b, lbm_kernel_stat *out, int32_t ma
 const char *lbm_batch_last_error(const lbm_batch *b);
 void lbm_batch_destroy(lbm_batch *b);
 
+/* ---- Learned surrogate ----------------------------------------------------------------
+ * A multilayer perceptron 4 -> 64 -> 64 -> 64 -> 2 with tanh hidden layers that maps a
+ * capsule pair's (separation / radius, log10 shear modulus, film height / diameter,
+ * contact angle) to (lateral capillary force, meniscus deformation), trained by Adam on
+ * data of the batched solver (mean squared error (1 / 2 sum w) sum_i w_i |y_i - t_i|^2).
+ * Every matrix product runs on the matrix cores with bfloat16 operands (rounded to
+ * nearest even) and float32 sums; parameters, Adam moments and activations are float32.
+ * Parameter vector (host float [LBM_SURROGATE_PARAMS]): W1 [4][64], b1 [64], W2 [64][64],
+ * b2, W3 [64][64], b3, W4 [64][2], b4 [2], each W [inputs][outputs] row-major, y = x W + b.
+ * Inputs and targets are passed normalised by the caller (e.g. zero mean, unit variance
+ * per column).  Host buffers are copied during the calls; every call synchronises its
+ * private stream (default priority).  Errors: LBM_E_INVAL for bad sizes or non-finite
+ * data (message in lbm_surrogate_last_error), LBM_E_STATE for training without data. */
+#define LBM_SURROGATE_PARAMS 8770
+typedef struct lbm_surrogate lbm_surrogate;
+
+/* Device state for up to max_samples samples (1 .. 2^20), parameters from theta0. */
+lbm_status lbm_surrogate_create(int32_t max_samples, const float *theta0, lbm_surrogate **out);
+
+/* Training data: x [n][4], t [n][2], w [n] sample weights >= 0 (NULL: all 1). */
+lbm_status lbm_surrogate_set_data(lbm_surrogate *s, int32_t n, const float *x, const float *t,
+                                  const float *w);
+
+/* Loss and its gradient [LBM_SURROGATE_PARAMS] at the current parameters over the data. */
+lbm_status lbm_surrogate_gradient(lbm_surrogate *s, float *loss, float *grad);
+
+/* steps Adam updates (beta1 0.9, beta2 0.999, eps 1e-8, learning rate lr) on the full data. */
+lbm_status lbm_surrogate_train(lbm_surrogate *s, int32_t steps, float lr);
+
+/* Network outputs y [n][2] for inputs x [n][4], n <= max_samples. */
+lbm_status lbm_surrogate_predict(lbm_surrogate *s, int32_t n, const float *x, float *y);
+
+/* Current parameters into theta [LBM_SURROGATE_PARAMS]. */
+lbm_status lbm_surrogate_params(lbm_surrogate *s, float *theta);
+
+const char *lbm_surrogate_last_error(const lbm_surrogate *s);
+void lbm_surrogate_destroy(lbm_surrogate *s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,0 +1,345 @@
+// surrogate.hip -- the learned form: a multilayer perceptron 4 -> 64 -> 64 -> 64 -> 2
+// (tanh hidden layers, 8770 parameters) that maps a capsule pair's separation,
+// softness, film height and contact angle to its lateral capillary force and meniscus
+// deformation, trained by Adam on data of the batched solver.
+//
+// Every matrix product runs on the matrix cores: v_mfma_f32_16x16x16_bf16, operands
+// rounded to bfloat16 (nearest, ties to even) when loaded, sums in float32.  One
+// wavefront computes one 16 x 16 tile of the product; operand and result layouts are
+// given by strides, so the same kernel serves x W, d W^T and a^T d.  Parameters, Adam
+// moments, activations and gradients are float32 in HBM (the whole state is ~0.2 MB plus
+// 1 kB per sample).
+#include "lbm.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+namespace {
+
+constexpr int NIN = 4, NH = 64, NOUT = 2, NLAYER = 4;
+constexpr int LIN[NLAYER] = {NIN, NH, NH, NH}, LOUT[NLAYER] = {NH, NH, NH, NOUT};
+// offsets of W_l ([in][out], row-major) and b_l in the parameter vector
+constexpr int woff(int l) { return l == 0 ? 0 : woff(l - 1) + LIN[l - 1] * LOUT[l - 1] + LOUT[l - 1]; }
+constexpr int boff(int l) { return woff(l) + LIN[l] * LOUT[l]; }
+constexpr int NPAR = boff(NLAYER - 1) + NOUT;
+static_assert(NPAR == LBM_SURROGATE_PARAMS, "parameter count");
+
+typedef short v4s __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ short to_bf16(float x) {
+    uint32_t u = __float_as_uint(x);
+    u += 0x7fffu + ((u >> 16) & 1u);   // round to nearest, ties to even (finite values)
+    return (short)(u >> 16);
+}
+
+enum Epi { EPI_STORE = 0, EPI_BIAS_TANH = 1, EPI_BIAS = 2, EPI_TANH_GRAD = 3 };
+
+// C[M][N] (row stride ldc) = A (M x K, element (i, k) at A[i * sar + k * sac]) times
+// B (K x N, element (k, j) at B[k * sbr + j * sbc]), then the epilogue:
+//   EPI_STORE      C = AB
+//   EPI_BIAS_TANH  C = tanh(AB + bias[j])
+//   EPI_BIAS       C = AB + bias[j]
+//   EPI_TANH_GRAD  C = AB * (1 - P[i][j]^2), P the layer's tanh output (row stride ldc)
+// One wave per 16 x 16 tile of C, four waves per block; elements outside M, N, K are 0.
+// MFMA 16x16x16 lane layout: A row = lane % 16, B column = lane % 16, both with k =
+// 4 (lane / 16) .. +3; result row = 4 (lane / 16) + i, column = lane % 16.
+__global__ void __launch_bounds__(256) k_gemm_bf16(const float *__restrict__ A, int sar, int sac,
+                                                   const float *__restrict__ B, int sbr, int sbc,
+                                                   float *__restrict__ C, int ldc, int M, int N,
+                                                   int K, int epi, const float *__restrict__ bias,
+                                                   const float *__restrict__ P) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int tiles_n = (N + 15) / 16;
+    const int tile = blockIdx.x * 4 + wave;
+    if (tile >= ((M + 15) / 16) * tiles_n) return;   // whole waves
+    const int i0 = (tile / tiles_n) * 16, j0 = (tile % tiles_n) * 16;
+    const int r = i0 + (lane & 15), c = j0 + (lane & 15), kq = 4 * (lane >> 4);
+    v4f acc = {0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < K; k0 += 16) {
+        v4s a, b;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int k = k0 + kq + j;
+            const float av = (r < M && k < K) ? A[(size_t)r * sar + (size_t)k * sac] : 0.f;
+            const float bv = (c < N && k < K) ? B[(size_t)k * sbr + (size_t)c * sbc] : 0.f;
+            a[j] = to_bf16(av);
+            b[j] = to_bf16(bv);
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+    }
+    const int col = j0 + (lane & 15);
+    if (col >= N) return;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int row = i0 + kq + i;
+        if (row >= M) continue;
+        float v = acc[i];
+        if (epi == EPI_BIAS_TANH) v = tanhf(v + bias[col]);
+        else if (epi == EPI_BIAS) v += bias[col];
+        else if (epi == EPI_TANH_GRAD) {
+            const float p = P[(size_t)row * ldc + col];
+            v *= 1.0f - p * p;
+        }
+        C[(size_t)row * ldc + col] = v;
+    }
+}
+
+// dY = w (Y - T) / sum(w); per-block partial sums of w (Y - T)^2 for the loss
+__global__ void k_loss_grad(const float *__restrict__ Y, const float *__restrict__ T,
+                            const float *__restrict__ W, float inv_n, int n,
+                            float *__restrict__ dY, float *__restrict__ part) {
+    __shared__ float s[256];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    float acc = 0.f;
+    if (i < n) {
+        for (int o = 0; o < NOUT; ++o) {
+            const float r = Y[i * NOUT + o] - T[i * NOUT + o];
+            dY[i * NOUT + o] = W[i] * r * inv_n;
+            acc += W[i] * r * r;
+        }
+    }
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) s[threadIdx.x] += s[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = s[0];
+}
+
+// db[j] = sum over the n rows of D[i][j] (one thread per column, rows in order)
+__global__ void k_colsum(const float *__restrict__ D, int n, int m, float *__restrict__ db) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= m) return;
+    float s = 0.f;
+    for (int i = 0; i < n; ++i) s += D[(size_t)i * m + j];
+    db[j] = s;
+}
+
+// Adam (Kingma & Ba): bias-corrected moments, step counted from 1
+__global__ void k_adam(float *__restrict__ th, float *__restrict__ m, float *__restrict__ v,
+                       const float *__restrict__ g, int np, float lr, float b1, float b2,
+                       float c1, float c2, float eps) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= np) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi, vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    th[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+}  // namespace
+
+struct lbm_surrogate {
+    std::string err;
+    hipStream_t st = nullptr;
+    int cap = 0, n = 0;
+    int64_t t = 0;                       // Adam steps taken
+    float *th = nullptr, *m = nullptr, *v = nullptr, *g = nullptr;
+    float *x = nullptr, *y = nullptr, *tg = nullptr, *w = nullptr, *dy = nullptr, *part = nullptr;
+    float *act[NLAYER] = {nullptr, nullptr, nullptr, nullptr};   // input, tanh of 3 layers
+    float *d[NLAYER] = {nullptr, nullptr, nullptr, nullptr};     // back-propagated dL/dz
+    double wsum = 0.0;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+lbm_status sfail(lbm_surrogate *s, lbm_status c, const std::string &m) {
+    s->err = m;
+    return c;
+}
+
+void gemm(hipStream_t st, const float *A, int sar, int sac, const float *B, int sbr, int sbc,
+          float *C, int ldc, int M, int N, int K, int epi, const float *bias, const float *P) {
+    const int tiles = ((M + 15) / 16) * ((N + 15) / 16);
+    hipLaunchKernelGGL(k_gemm_bf16, dim3((tiles + 3) / 4), dim3(256), 0, st, A, sar, sac, B, sbr,
+                       sbc, C, ldc, M, N, K, epi, bias, P);
+}
+
+// forward pass over n rows of X (activations kept for back-propagation), output into Y
+void forward(lbm_surrogate *s, const float *X, float *Y, int n) {
+    const float *h = X;
+    for (int l = 0; l < NLAYER; ++l) {
+        const int ki = LIN[l], no = LOUT[l];
+        const float *W = s->th + woff(l), *b = s->th + boff(l);
+        float *out = l < NLAYER - 1 ? s->act[l + 1] : Y;
+        gemm(s->st, h, ki, 1, W, no, 1, out, no, n, no, ki, l < NLAYER - 1 ? EPI_BIAS_TANH : EPI_BIAS,
+             b, nullptr);
+        h = out;
+    }
+}
+
+// gradient of the loss at the current parameters over the stored data, into s->g
+void backward(lbm_surrogate *s) {
+    const int n = s->n;
+    forward(s, s->act[0], s->y, n);
+    hipLaunchKernelGGL(k_loss_grad, dim3((n + 255) / 256), dim3(256), 0, s->st, s->y, s->tg, s->w,
+                       (float)(1.0 / s->wsum), n, s->dy, s->part);
+    const float *dl = s->dy;   // dL/dz of layer l
+    for (int l = NLAYER - 1; l >= 0; --l) {
+        const int ki = LIN[l], no = LOUT[l];
+        // dW_l = act_l^T dl   (ki x no, summed over the n rows)
+        gemm(s->st, s->act[l], 1, ki, dl, no, 1, s->g + woff(l), no, ki, no, n, EPI_STORE,
+             nullptr, nullptr);
+        hipLaunchKernelGGL(k_colsum, dim3((no + 63) / 64), dim3(64), 0, s->st, dl, n, no,
+                           s->g + boff(l));
+        if (l > 0) {   // dL/dz_{l-1} = (dl W_l^T) * (1 - act_l^2)
+            gemm(s->st, dl, no, 1, s->th + woff(l), 1, no, s->d[l - 1], ki, n, ki, no,
+                 EPI_TANH_GRAD, nullptr, s->act[l]);
+            dl = s->d[l - 1];
+        }
+    }
+}
+
+}  // namespace
+
+extern "C" lbm_status lbm_surrogate_create(int32_t max_samples, const float *theta0,
+                                           lbm_surrogate **out) {
+    if (!out) return LBM_E_INVAL;
+    *out = nullptr;
+    if (max_samples < 1 || max_samples > (1 << 20) || !theta0) {
+        g_err = "max_samples must be 1 .. 2^20 and theta0 given";
+        return LBM_E_INVAL;
+    }
+    lbm_surrogate *s = new (std::nothrow) lbm_surrogate();
+    if (!s) return LBM_E_NOMEM;
+    s->cap = max_samples;
+    const size_t c = (size_t)max_samples;
+    bool ok = hipStreamCreateWithFlags(&s->st, hipStreamNonBlocking) == hipSuccess;
+    float **bufs[] = {&s->th, &s->m, &s->v, &s->g};
+    for (float **b : bufs) ok = ok && hipMalloc(b, NPAR * sizeof(float)) == hipSuccess;
+    ok = ok && hipMalloc(&s->y, c * NOUT * sizeof(float)) == hipSuccess &&
+         hipMalloc(&s->tg, c * NOUT * sizeof(float)) == hipSuccess &&
+         hipMalloc(&s->dy, c * NOUT * sizeof(float)) == hipSuccess &&
+         hipMalloc(&s->w, c * sizeof(float)) == hipSuccess &&
+         hipMalloc(&s->part, ((c + 255) / 256) * sizeof(float)) == hipSuccess;
+    for (int l = 0; l < NLAYER && ok; ++l)
+        ok = hipMalloc(&s->act[l], c * LIN[l] * sizeof(float)) == hipSuccess &&
+             hipMalloc(&s->d[l], c * LOUT[l] * sizeof(float)) == hipSuccess;
+    s->x = s->act[0];
+    ok = ok && hipMemcpy(s->th, theta0, NPAR * sizeof(float), hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemset(s->m, 0, NPAR * sizeof(float)) == hipSuccess &&
+         hipMemset(s->v, 0, NPAR * sizeof(float)) == hipSuccess;
+    if (!ok) {
+        lbm_surrogate_destroy(s);
+        g_err = "device allocation failed (surrogate)";
+        return LBM_E_NOMEM;
+    }
+    *out = s;
+    return LBM_OK;
+}
+
+extern "C" lbm_status lbm_surrogate_set_data(lbm_surrogate *s, int32_t n, const float *x,
+                                             const float *t, const float *w) {
+    if (!s) return LBM_E_INVAL;
+    if (n < 1 || n > s->cap || !x || !t) return sfail(s, LBM_E_INVAL, "need 1 .. max_samples samples");
+    std::vector<float> wv(n, 1.0f);
+    if (w) wv.assign(w, w + n);
+    double ws = 0.0;
+    for (float v : wv) {
+        if (!(v >= 0.0f) || !std::isfinite(v)) return sfail(s, LBM_E_INVAL, "weights must be finite and >= 0");
+        ws += v;
+    }
+    if (!(ws > 0.0)) return sfail(s, LBM_E_INVAL, "weights sum to zero");
+    for (int i = 0; i < n * NIN; ++i)
+        if (!std::isfinite(x[i])) return sfail(s, LBM_E_INVAL, "non-finite input");
+    for (int i = 0; i < n * NOUT; ++i)
+        if (!std::isfinite(t[i])) return sfail(s, LBM_E_INVAL, "non-finite target");
+    if (hipStreamSynchronize(s->st) != hipSuccess ||
+        hipMemcpy(s->x, x, (size_t)n * NIN * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(s->tg, t, (size_t)n * NOUT * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(s->w, wv.data(), (size_t)n * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
+        return sfail(s, LBM_E_DEVICE, "data upload failed");
+    s->n = n;
+    s->wsum = ws;
+    return LBM_OK;
+}
+
+extern "C" lbm_status lbm_surrogate_gradient(lbm_surrogate *s, float *loss, float *grad) {
+    if (!s || !grad) return LBM_E_INVAL;
+    if (s->n == 0) return sfail(s, LBM_E_STATE, "no training data");
+    backward(s);
+    std::vector<float> part((s->n + 255) / 256);
+    if (hipMemcpyAsync(grad, s->g, NPAR * sizeof(float), hipMemcpyDeviceToHost, s->st) != hipSuccess ||
+        hipMemcpyAsync(part.data(), s->part, part.size() * sizeof(float), hipMemcpyDeviceToHost, s->st) != hipSuccess ||
+        hipStreamSynchronize(s->st) != hipSuccess)
+        return sfail(s, LBM_E_DEVICE, "gradient read-back failed");
+    if (loss) {
+        double a = 0.0;
+        for (float p : part) a += p;
+        *loss = (float)(0.5 * a / s->wsum);
+    }
+    return LBM_OK;
+}
+
+extern "C" lbm_status lbm_surrogate_train(lbm_surrogate *s, int32_t steps, float lr) {
+    if (!s) return LBM_E_INVAL;
+    if (s->n == 0) return sfail(s, LBM_E_STATE, "no training data");
+    if (steps < 0 || !(lr > 0.0f)) return sfail(s, LBM_E_INVAL, "steps >= 0 and lr > 0");
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    for (int i = 0; i < steps; ++i) {
+        backward(s);
+        ++s->t;
+        const float c1 = (float)(1.0 - std::pow(0.9, (double)s->t));
+        const float c2 = (float)(1.0 - std::pow(0.999, (double)s->t));
+        hipLaunchKernelGGL(k_adam, dim3((NPAR + 255) / 256), dim3(256), 0, s->st, s->th, s->m, s->v,
+                           s->g, NPAR, lr, b1, b2, c1, c2, eps);
+    }
+    if (hipStreamSynchronize(s->st) != hipSuccess || hipGetLastError() != hipSuccess)
+        return sfail(s, LBM_E_DEVICE, "training launch failed");
+    return LBM_OK;
+}
+
+extern "C" lbm_status lbm_surrogate_predict(lbm_surrogate *s, int32_t n, const float *x, float *y) {
+    if (!s) return LBM_E_INVAL;
+    if (n < 1 || n > s->cap || !x || !y) return sfail(s, LBM_E_INVAL, "need 1 .. max_samples inputs");
+    // the activations of the stored data are overwritten; the data itself is kept
+    float *xin = nullptr, *yout = nullptr;
+    bool ok = hipMalloc(&xin, (size_t)n * NIN * sizeof(float)) == hipSuccess &&
+              hipMalloc(&yout, (size_t)n * NOUT * sizeof(float)) == hipSuccess &&
+              hipStreamSynchronize(s->st) == hipSuccess &&
+              hipMemcpy(xin, x, (size_t)n * NIN * sizeof(float), hipMemcpyHostToDevice) == hipSuccess;
+    if (ok) {
+        forward(s, xin, yout, n);
+        ok = hipMemcpyAsync(y, yout, (size_t)n * NOUT * sizeof(float), hipMemcpyDeviceToHost, s->st) == hipSuccess &&
+             hipStreamSynchronize(s->st) == hipSuccess;
+    }
+    if (xin) (void)hipFree(xin);
+    if (yout) (void)hipFree(yout);
+    return ok ? LBM_OK : sfail(s, LBM_E_DEVICE, "prediction failed");
+}
+
+extern "C" lbm_status lbm_surrogate_params(lbm_surrogate *s, float *theta) {
+    if (!s || !theta) return LBM_E_INVAL;
+    if (hipStreamSynchronize(s->st) != hipSuccess ||
+        hipMemcpy(theta, s->th, NPAR * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess)
+        return sfail(s, LBM_E_DEVICE, "parameter read-back failed");
+    return LBM_OK;
+}
+
+extern "C" const char *lbm_surrogate_last_error(const lbm_surrogate *s) {
+    return s ? s->err.c_str() : g_err.c_str();
+}
+
+extern "C" void lbm_surrogate_destroy(lbm_surrogate *s) {
+    if (!s) return;
+    if (s->st) (void)hipStreamSynchronize(s->st);
+    float *bufs[] = {s->th, s->m, s->v, s->g, s->y, s->tg, s->dy, s->w, s->part};
+    for (float *b : bufs)
+        if (b) (void)hipFree(b);
+    for (int l = 0; l < NLAYER; ++l) {
+        if (s->act[l]) (void)hipFree(s->act[l]);
+        if (s->d[l]) (void)hipFree(s->d[l]);
+    }
+    if (s->st) (void)hipStreamDestroy(s->st);
+    delete s;
+}

@@ -99,6 +99,15 @@ SIGNATURES = {
     "lbm_batch_kernel_stats": (C.c_int, [H, C.POINTER(KernelStat), C.c_int32, C.POINTER(C.c_int32)]),
     "lbm_batch_last_error": (C.c_char_p, [H]),
     "lbm_batch_destroy": (None, [H]),
+    "lbm_surrogate_create": (C.c_int, [C.c_int32, C.POINTER(C.c_float), C.POINTER(C.c_void_p)]),
+    "lbm_surrogate_set_data": (C.c_int, [H, C.c_int32, C.POINTER(C.c_float), C.POINTER(C.c_float),
+                                         C.POINTER(C.c_float)]),
+    "lbm_surrogate_gradient": (C.c_int, [H, C.POINTER(C.c_float), C.POINTER(C.c_float)]),
+    "lbm_surrogate_train": (C.c_int, [H, C.c_int32, C.c_float]),
+    "lbm_surrogate_predict": (C.c_int, [H, C.c_int32, C.POINTER(C.c_float), C.POINTER(C.c_float)]),
+    "lbm_surrogate_params": (C.c_int, [H, C.POINTER(C.c_float)]),
+    "lbm_surrogate_last_error": (C.c_char_p, [H]),
+    "lbm_surrogate_destroy": (None, [H]),
 }
 
 _LIB = None
@@ -391,6 +400,77 @@ class Batch:
         if getattr(self, "b", None):
             self.L.lbm_batch_destroy(self.b)
             self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+SURROGATE_PARAMS = 8770
+
+
+def _fp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_float))
+
+
+class Surrogate:
+    """The learned surrogate network (``lbm_surrogate_*``): 4 -> 64 -> 64 -> 64 -> 2, tanh,
+    trained by Adam with the matrix products on the matrix cores (bfloat16 operands,
+    float32 sums).  Inputs and targets are passed normalised."""
+
+    def __init__(self, theta0, max_samples: int):
+        self.L = load_library()
+        th = np.ascontiguousarray(theta0, dtype=np.float32)
+        if th.shape != (SURROGATE_PARAMS,):
+            raise ValueError(f"theta0 must have {SURROGATE_PARAMS} entries")
+        s = C.c_void_p()
+        st = self.L.lbm_surrogate_create(int(max_samples), _fp(th), C.byref(s))
+        if st != LBM_OK:
+            raise LbmError(st, self.L.lbm_surrogate_last_error(None).decode())
+        self.s = s
+        self.max_samples = int(max_samples)
+
+    def _check(self, st: int):
+        if st != LBM_OK:
+            raise LbmError(st, self.L.lbm_surrogate_last_error(self.s).decode())
+
+    def set_data(self, x, t, w=None):
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        t = np.ascontiguousarray(t, dtype=np.float32)
+        wp = None
+        if w is not None:
+            w = np.ascontiguousarray(w, dtype=np.float32)
+            wp = _fp(w)
+        if x.ndim != 2 or x.shape[1] != 4 or t.shape != (len(x), 2):
+            raise ValueError("x must be [n][4] and t [n][2]")
+        self._check(self.L.lbm_surrogate_set_data(self.s, len(x), _fp(x), _fp(t), wp))
+
+    def gradient(self):
+        g = np.zeros(SURROGATE_PARAMS, np.float32)
+        loss = C.c_float()
+        self._check(self.L.lbm_surrogate_gradient(self.s, C.byref(loss), _fp(g)))
+        return float(loss.value), g
+
+    def train(self, steps: int, lr: float = 1e-3):
+        self._check(self.L.lbm_surrogate_train(self.s, int(steps), float(lr)))
+
+    def predict(self, x) -> np.ndarray:
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        y = np.zeros((len(x), 2), np.float32)
+        self._check(self.L.lbm_surrogate_predict(self.s, len(x), _fp(x), _fp(y)))
+        return y
+
+    def params(self) -> np.ndarray:
+        th = np.zeros(SURROGATE_PARAMS, np.float32)
+        self._check(self.L.lbm_surrogate_params(self.s, _fp(th)))
+        return th
+
+    def close(self):
+        if getattr(self, "s", None):
+            self.L.lbm_surrogate_destroy(self.s)
+            self.s = None
 
     def __del__(self):
         try:

@@ -1,0 +1,97 @@
+"""GPU parity of the learned surrogate's network (lbm_surrogate_*) against the CPU
+reference oracle/mlp.py in its mixed-precision mode, which rounds the same operands to
+bfloat16 but sums in float64: the kernels' float32 sums and float32 tanh differ from it
+by rounding, which can flip a bfloat16 rounding now and then; outputs agree to 1e-5
+relative, gradients to 1e-4 (relative L2), and 50 Adam steps follow the oracle's
+parameter trajectory to 1e-3 of the distance travelled.  A smooth function of four
+variables is then learned to a held-out error of a few percent."""
+import numpy as np
+import pytest
+
+from oracle import mlp
+
+pytestmark = pytest.mark.gpu
+
+
+def _theta(seed):
+    """Glorot-scaled random parameters (weights ~ N(0, 1/fan_in)), biases 0.1 N(0, 1)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(4):
+        k, n = mlp.DIMS[i], mlp.DIMS[i + 1]
+        out.append(rng.normal(0, 1 / np.sqrt(k), k * n))
+        out.append(0.1 * rng.normal(size=n))
+    return np.concatenate(out).astype(np.float32)
+
+
+def _data(n, seed):
+    rng = np.random.default_rng(seed)
+    x = rng.normal(size=(n, 4)).astype(np.float32)
+    t = np.stack([np.sin(x[:, 0]) + 0.5 * x[:, 1] ** 2 - 0.3 * x[:, 2],
+                  np.tanh(x[:, 2] - x[:, 3]) + 0.2 * x[:, 0] * x[:, 1]], 1).astype(np.float32)
+    return x, t
+
+
+def _sur(theta, n):
+    from paper_2007_15405_amd import Surrogate
+    return Surrogate(theta, n)
+
+
+def test_forward_matches_the_oracle():
+    th = _theta(1)
+    x, _ = _data(203, 2)                    # not a multiple of the 16-row tiles
+    s = _sur(th, 256)
+    y = s.predict(x)
+    yo, _ = mlp.forward(th.astype(np.float64), x, mixed=True)
+    assert np.abs(y - yo).max() <= 1e-5 * np.abs(yo).max()
+    s.close()
+
+
+def test_gradient_matches_the_oracle():
+    th = _theta(3)
+    x, t = _data(150, 4)
+    w = np.random.default_rng(5).uniform(0.1, 1.0, 150).astype(np.float32)
+    s = _sur(th, 150)
+    s.set_data(x, t, w)
+    loss, g = s.gradient()
+    lo, go = mlp.loss_and_grad(th.astype(np.float64), x, t, w, mixed=True)
+    assert loss == pytest.approx(lo, rel=1e-5)
+    assert np.linalg.norm(g - go) <= 1e-4 * np.linalg.norm(go)
+    for l, (W, b) in enumerate(mlp.unpack(np.arange(mlp.N_PARAMS))):
+        blk = np.concatenate([W.ravel(), b]).astype(int)
+        assert np.linalg.norm(g[blk] - go[blk]) <= 1e-3 * np.linalg.norm(go[blk]) + 1e-9, l
+    s.close()
+
+
+def test_adam_follows_the_oracle():
+    th = _theta(6)
+    x, t = _data(96, 7)
+    s = _sur(th, 96)
+    s.set_data(x, t)
+    s.train(50, 1e-3)
+    tg = s.params().astype(np.float64)
+    to, m, v = th.astype(np.float64), np.zeros(mlp.N_PARAMS), np.zeros(mlp.N_PARAMS)
+    for k in range(1, 51):
+        _, g = mlp.loss_and_grad(to, x, t, mixed=True)
+        to, m, v = mlp.adam(to, g, m, v, k, 1e-3)
+    travel = np.linalg.norm(to - th)
+    assert travel > 0.05
+    assert np.linalg.norm(tg - to) <= 1e-3 * travel
+    s.close()
+
+
+def test_network_learns_a_smooth_function():
+    th = _theta(8)
+    x, t = _data(1024, 9)
+    xh, th_ = _data(256, 10)
+    s = _sur(th, 1024)
+    s.set_data(x, t)
+    l0, _ = s.gradient()
+    s.train(3000, 3e-3)
+    l1, _ = s.gradient()
+    yh = s.predict(xh)
+    err = np.linalg.norm(yh - th_, axis=0) / np.linalg.norm(th_ - th_.mean(0), axis=0)
+    print("loss", l0, "->", l1, "held-out relative error per output", err, flush=True)
+    assert l1 < 0.01 * l0
+    assert np.all(err < 0.1)
+    s.close()
