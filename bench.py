@@ -203,6 +203,56 @@ def run_batch(storage, steps, warmup, do_tune=True, launch=None, parts=None):
     return out
 
 
+PEAK_BF16_TFLOPS = 2500.0
+
+
+def run_surrogate(seeds=(201, 202, 203, 204, 205), steps=8000, average=4000, train_steps=500):
+    """The learned form: training data from the batched solver (64 capsule-pair runs per
+    seed), the network trained on three quarters of the pairs that stay out of contact,
+    held-out error, training and inference speed, and the solver's time per pair."""
+    import numpy as np
+
+    import synth
+    from paper_2007_15405_amd import surrogate as S
+    t0 = time.perf_counter()
+    parts = [S.run_pairs(synth.batch_instances(seed=sd), steps, average=average) for sd in seeds]
+    t_lbm = time.perf_counter() - t0
+    X = np.concatenate([p[0] for p in parts])
+    Y = np.concatenate([p[1] for p in parts])
+    keep = S.in_domain(X)
+    X, Y = X[keep], Y[keep]
+    idx = np.random.default_rng(1).permutation(len(X))
+    te, tr = idx[: len(X) // 4], idx[len(X) // 4:]
+    t1 = time.perf_counter()
+    f = S.fit(X[tr], Y[tr], steps=train_steps)
+    t_fit = time.perf_counter() - t1
+    P = f.predict(X[te])
+    err = np.linalg.norm(P - Y[te], axis=0) / np.linalg.norm(Y[te] - Y[tr].mean(0), axis=0)
+    # training speed: more Adam steps on the same data (full batch)
+    reps = 2000
+    t2 = time.perf_counter()
+    f.net.train(reps, 1e-4)
+    us_step = (time.perf_counter() - t2) / reps * 1e6
+    n = len(tr)
+    flops = 3 * 2 * n * (4 * 64 + 64 * 64 * 2 + 64 * 2)   # forward, input and weight gradients
+    # inference: 4096 queries in one call
+    Q = X[np.random.default_rng(2).integers(0, len(X), 4096)]
+    t3 = time.perf_counter()
+    f.predict(Q)
+    us_query = (time.perf_counter() - t3) / len(Q) * 1e6
+    f.net.close()
+    return dict(
+        samples=int(len(X)), train=int(len(tr)), held_out=int(len(te)),
+        solver_runs=len(seeds) * 64, solver_steps=steps, outputs_averaged_over=average,
+        held_out_rel_error={"lateral_force": round(float(err[0]), 4),
+                            "meniscus_deformation": round(float(err[1]), 4)},
+        train_steps=train_steps, fit_s=round(t_fit, 3), us_per_adam_step=round(us_step, 2),
+        gemm_tflops=round(flops / (us_step * 1e-6) / 1e12, 5),
+        gemm_frac_of_bf16_peak=round(flops / (us_step * 1e-6) / 1e12 / PEAK_BF16_TFLOPS, 8),
+        us_per_query=round(us_query, 4), solver_s_per_pair=round(t_lbm / (len(seeds) * 64), 4),
+        speedup_per_pair=round(t_lbm / (len(seeds) * 64) / (us_query * 1e-6), 1))
+
+
 def cpu_baseline(cfg, steps=30):
     import oracle
     cores = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
@@ -229,6 +279,8 @@ def main():
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched form")
     ap.add_argument("--batch-only", action="store_true", help="only the batched form")
+    ap.add_argument("--surrogate", action="store_true",
+                    help="only the learned form: solver data, training, held-out error, speed")
     ap.add_argument("--kb", type=float, default=0.0,
                     help="bending modulus of the film box's capsules (the workload has none)")
     ap.add_argument("--parts", type=int, default=None,
@@ -255,6 +307,10 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps(dict(copy_bytes_each_way=n * 4, launches=5)), flush=True)
+        return
+
+    if args.surrogate:
+        print(json.dumps(dict(surrogate=run_surrogate())), flush=True)
         return
 
     import synth

@@ -113,13 +113,21 @@ __global__ void k_loss_grad(const float *__restrict__ Y, const float *__restrict
     if (threadIdx.x == 0) part[blockIdx.x] = s[0];
 }
 
-// db[j] = sum over the n rows of D[i][j] (one thread per column, rows in order)
-__global__ void k_colsum(const float *__restrict__ D, int n, int m, float *__restrict__ db) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= m) return;
-    float s = 0.f;
-    for (int i = 0; i < n; ++i) s += D[(size_t)i * m + j];
-    db[j] = s;
+// db[j] = sum over the n rows of D[i][j]: one block per column, each thread a strided
+// share of the rows, then a fixed tree (the order does not depend on scheduling)
+__global__ void __launch_bounds__(256) k_colsum(const float *__restrict__ D, int n, int m,
+                                                float *__restrict__ db) {
+    __shared__ float s[256];
+    const int j = blockIdx.x;
+    float a = 0.f;
+    for (int i = threadIdx.x; i < n; i += 256) a += D[(size_t)i * m + j];
+    s[threadIdx.x] = a;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) s[threadIdx.x] += s[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) db[j] = s[0];
 }
 
 // Adam (Kingma & Ba): bias-corrected moments, step counted from 1
@@ -190,8 +198,7 @@ void backward(lbm_surrogate *s) {
         // dW_l = act_l^T dl   (ki x no, summed over the n rows)
         gemm(s->st, s->act[l], 1, ki, dl, no, 1, s->g + woff(l), no, ki, no, n, EPI_STORE,
              nullptr, nullptr);
-        hipLaunchKernelGGL(k_colsum, dim3((no + 63) / 64), dim3(64), 0, s->st, dl, n, no,
-                           s->g + boff(l));
+        hipLaunchKernelGGL(k_colsum, dim3(no), dim3(256), 0, s->st, dl, n, no, s->g + boff(l));
         if (l > 0) {   // dL/dz_{l-1} = (dl W_l^T) * (1 - act_l^2)
             gemm(s->st, dl, no, 1, s->th + woff(l), 1, no, s->d[l - 1], ki, n, ki, no,
                  EPI_TANH_GRAD, nullptr, s->act[l]);

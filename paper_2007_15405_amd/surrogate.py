@@ -1,0 +1,112 @@
+"""Training data for the learned surrogate from the batched solver, and its training.
+
+One sample per capsule-pair run (``synth.batch_instances``): inputs (separation L / R,
+log10 of the shear modulus, film height above the repulsive plane / 2R, contact angle in
+degrees; 90 without a wetting offset), outputs after ``steps`` steps of the batched
+solver: the lateral capillary force (each anchored capsule's anchor force, which at rest
+balances the force of the fluid, projected on the unit vector pointing away from the other
+capsule in the film plane, averaged over the two; negative = attraction) and the meniscus
+deformation (the meniscus height at the column midway between the capsules minus the
+median height along the box edge farthest from the pair axis).  Everything here reads the
+library's observables; the solver and the network run in the library's kernels.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+import synth
+
+from .lbm import Batch, Sim, Surrogate
+
+RADIUS = 10.0
+PLANE = 10.5          # repulsive plane of the batch instances (0.5 + 10 above the wall)
+CONTACT = 2.4         # L / R below which the pair comes into contact during the run: the
+                      # force then grows by an order of magnitude; such pairs are left to
+                      # the solver (outside the surrogate's domain)
+
+
+def pair_inputs(inst: dict) -> np.ndarray:
+    film_above_plane = inst["film_height"] + 0.5 - PLANE
+    return np.array([inst["L"] / RADIUS, np.log10(inst["ks"]),
+                     film_above_plane / (2 * RADIUS), 90.0])
+
+
+def run_pairs(instances: list, steps: int, average: int = 0, every: int = 200,
+              storage: str = "f32", parts: int = 3):
+    """Run the instances with one batch (stacked by box size) and return
+    (inputs [n][4], outputs [n][2]) in the order of ``instances``; the outputs are
+    averaged over samples taken every ``every`` steps during the last ``average`` steps
+    (0: the final state only)."""
+    groups = synth.batch_groups(instances)
+    sims = [Sim(g, storage=storage, meshes=synth.capsule_meshes(g["capsules"])) for g in groups]
+    bt = Batch(sims, tile=13, zchunk=16, parts=parts)
+    X = np.array([pair_inputs(i) for i in instances])
+    Y = np.zeros((len(instances), 2))
+    nsamp = max(1, average // every) if average else 1
+    bt.step(steps - (nsamp - 1) * every if average else steps)
+    for j in range(nsamp):
+        if j:
+            bt.step(every)
+        bt.sync()
+        Y += _outputs(groups, sims, len(instances)) / nsamp
+    bt.close()
+    for x in sims:
+        x.close()
+    return X, Y
+
+
+def _outputs(groups, sims, n):
+    Y = np.zeros((n, 2))
+    for g, sim in zip(groups, sims):
+        ob = sim.observables(meniscus=True)
+        men = ob["meniscus"].reshape(-1, g["ny"], g["nx"])
+        for s, k in enumerate(g["instances"]):
+            c = [ob["capsules"][2 * s + j] for j in range(2)]
+            d = c[0]["centroid"][:2] - c[1]["centroid"][:2]
+            e = d / np.linalg.norm(d)
+            Y[k, 0] = 0.5 * (c[0]["f_anchor"][:2] @ e - c[1]["f_anchor"][:2] @ e)
+            mid = 0.5 * (c[0]["centroid"][:2] + c[1]["centroid"][:2])
+            h = men[s]
+            hm = h[int(round(mid[1])) % g["ny"], int(round(mid[0])) % g["nx"]]
+            edge = h[0][~np.isnan(h[0])]
+            Y[k, 1] = hm - np.median(edge) if edge.size else np.nan
+    return Y
+
+
+class Fitted:
+    """A trained surrogate with the normalisation of its inputs and outputs and the box
+    of its training inputs (its domain; queries outside go to the solver)."""
+
+    def __init__(self, net: Surrogate, xm, xs, ym, ys, lo, hi):
+        self.net, self.xm, self.xs, self.ym, self.ys = net, xm, xs, ym, ys
+        self.lo, self.hi = lo, hi
+
+    def inside(self, X) -> np.ndarray:
+        X = np.asarray(X, np.float64)
+        return np.all((X >= self.lo) & (X <= self.hi), axis=1) & (X[:, 0] >= CONTACT)
+
+    def predict(self, X) -> np.ndarray:
+        x = (np.asarray(X, np.float64) - self.xm) / self.xs
+        return self.net.predict(x.astype(np.float32)) * self.ys + self.ym
+
+
+def in_domain(X) -> np.ndarray:
+    """Samples the surrogate is trained on: pairs that stay out of contact."""
+    return np.asarray(X)[:, 0] >= CONTACT
+
+
+def fit(X, Y, steps: int = 500, lr: float = 1e-3, seed: int = synth.SEED,
+        max_queries: int = 65536) -> Fitted:
+    """Train on (X, Y), columns normalised to zero mean and unit variance (constant
+    columns left centred).  Full-batch Adam; few steps, since a few hundred samples of
+    solver output are fitted to their noise level quickly and then overfitted.  The
+    network takes up to max_queries inputs per prediction call."""
+    X, Y = np.asarray(X, np.float64), np.asarray(Y, np.float64)
+    xm, xs = X.mean(0), X.std(0)
+    xs[xs == 0] = 1.0
+    ym, ys = Y.mean(0), Y.std(0)
+    ys[ys == 0] = 1.0
+    net = Surrogate(synth.surrogate_init(seed), max(len(X), max_queries))
+    net.set_data(((X - xm) / xs).astype(np.float32), ((Y - ym) / ys).astype(np.float32))
+    net.train(steps, lr)
+    return Fitted(net, xm, xs, ym, ys, X.min(0), X.max(0))

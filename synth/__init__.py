@@ -277,3 +277,15 @@ def capsule_meshes(caps: List[dict]) -> List[Tuple[np.ndarray, np.ndarray]]:
 def fluid_sites(cfg: dict) -> int:
     """Number of fluid sites (the wall layer z=0 is solid when present)."""
     return cfg["nx"] * cfg["ny"] * (cfg["nz"] - (1 if cfg["wall_z0"] else 0))
+
+
+def surrogate_init(seed: int = SEED) -> np.ndarray:
+    """Initial parameters of the surrogate network 4 -> 64 -> 64 -> 64 -> 2 (layout of
+    ``lbm_surrogate_*``): weights N(0, 1 / fan_in), biases 0, float32."""
+    rng = np.random.default_rng(seed)
+    dims = (4, 64, 64, 64, 2)
+    out = []
+    for i in range(4):
+        out.append(rng.normal(0.0, 1.0 / math.sqrt(dims[i]), dims[i] * dims[i + 1]))
+        out.append(np.zeros(dims[i + 1]))
+    return np.concatenate(out).astype(np.float32)

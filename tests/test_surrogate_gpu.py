@@ -95,3 +95,37 @@ def test_network_learns_a_smooth_function():
     assert l1 < 0.01 * l0
     assert np.all(err < 0.1)
     s.close()
+
+
+def test_surrogate_learns_the_batched_solver():
+    """Training data from the batched solver itself (3 x 64 capsule-pair runs, 6000
+    steps, outputs averaged over the last 3000): the network, trained on three quarters,
+    predicts the meniscus deformation of the held-out quarter to within half of its
+    spread and the lateral force better than its mean does, and answers every query in a
+    small fraction of the solver's time per pair (its gain over the method without it)."""
+    import time
+
+    import synth
+    from paper_2007_15405_amd import surrogate as S
+    t0 = time.perf_counter()
+    parts = [S.run_pairs(synth.batch_instances(seed=sd), 6000, average=3000) for sd in (31, 32, 33)]
+    t_lbm = time.perf_counter() - t0
+    X = np.concatenate([p[0] for p in parts])
+    Y = np.concatenate([p[1] for p in parts])
+    keep = S.in_domain(X)
+    X, Y = X[keep], Y[keep]
+    idx = np.random.default_rng(1).permutation(len(X))
+    te, tr = idx[: len(X) // 4], idx[len(X) // 4:]
+    f = S.fit(X[tr], Y[tr])
+    t1 = time.perf_counter()
+    P = f.predict(X[te])
+    t_net = time.perf_counter() - t1
+    base = np.linalg.norm(Y[te] - Y[tr].mean(0), axis=0)
+    err = np.linalg.norm(P - Y[te], axis=0) / base
+    per_pair_lbm, per_pair_net = t_lbm / (3 * 64), t_net / len(te)
+    print("samples", len(X), "held-out relative error (force, meniscus)", err,
+          "s per pair: solver", per_pair_lbm, "network", per_pair_net, flush=True)
+    assert err[1] < 0.5 and err[0] < 1.0
+    assert per_pair_net < 1e-3 * per_pair_lbm
+    assert np.all(f.inside(X[te])) and not f.inside(np.array([[2.0, -2.0, 0.6, 90.0]]))[0]
+    f.net.close()
