@@ -301,6 +301,25 @@ lbm_status lbm_surrogate_predict(lbm_surrogate *s, int32_t n, const float *x, fl
 /* Current parameters into theta [LBM_SURROGATE_PARAMS]. */
 lbm_status lbm_surrogate_params(lbm_surrogate *s, float *theta);
 
+/* Cluster evolution driven by the network: n capsules of radius `radius` in a periodic
+ * square of side `box`, overdamped, p_i += mobility * sum_j f(r_ij) e_ij each step (e_ij the
+ * unit vector from capsule j to i, minimum image).  f is the network's lateral force for
+ * r_contact <= r / radius <= r_cut (inputs r / radius and the three fixed features below,
+ * normalised with in_mean / in_scale, output de-normalised with out_mean / out_scale);
+ * closer pairs are outside the network's domain and repel with k_contact (r_contact -
+ * r / radius); farther pairs exert no force.  Every step evaluates the network for all
+ * n^2 ordered pairs (n * n <= max_samples). */
+typedef struct {
+    float box, radius;
+    float log10_ks, film, angle;          /* raw values of the other three inputs        */
+    float in_mean[4], in_scale[4], out_mean[2], out_scale[2];
+    float r_contact, r_cut, k_contact, mobility;
+} lbm_cluster_params;
+
+/* xy host [n][2] in/out: positions, advanced by `steps` steps. */
+lbm_status lbm_surrogate_cluster(lbm_surrogate *s, int32_t n, float *xy, int32_t steps,
+                                 const lbm_cluster_params *cp);
+
 const char *lbm_surrogate_last_error(const lbm_surrogate *s);
 void lbm_surrogate_destroy(lbm_surrogate *s);
 

@@ -143,6 +143,67 @@ __global__ void k_adam(float *__restrict__ th, float *__restrict__ m, float *__r
     th[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
+// ------------------------------------------------------------------------------------
+// Cluster evolution driven by the network: overdamped capsules in a periodic square,
+// every pair's force from the network (dense: row i * n + j for all i, j).  The
+// separations and the network's inputs are computed without contraction into fused
+// multiply-adds, so that each is the correctly rounded float32 result of the operations
+// as written (the inputs are then rounded to bfloat16, a decision taken in float32).
+// ------------------------------------------------------------------------------------
+struct ClusterArgs {
+    float xm[4], xs[4], ym[2], ys[2];   // normalisation of the network's inputs / outputs
+    float feat[3];                      // log10 ks, film / 2R, contact angle (raw)
+    float box, inv_radius, r_contact, r_cut, k_contact, mobility;
+    int n;
+};
+
+__device__ __forceinline__ float2 min_image2(float2 a, float2 b, float box) {
+#pragma clang fp contract(off)
+    float dx = a.x - b.x, dy = a.y - b.y;
+    dx -= box * rintf(dx / box);
+    dy -= box * rintf(dy / box);
+    return make_float2(dx, dy);
+}
+
+// normalised network inputs of every ordered pair (i, j)
+__global__ void k_pair_inputs(const float2 *__restrict__ p, ClusterArgs c, float *__restrict__ X) {
+#pragma clang fp contract(off)
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= c.n * c.n) return;
+    const int i = idx / c.n, j = idx - i * c.n;
+    const float2 d = min_image2(p[i], p[j], c.box);
+    const float raw[4] = {sqrtf(d.x * d.x + d.y * d.y) * c.inv_radius, c.feat[0], c.feat[1], c.feat[2]};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) X[(size_t)idx * 4 + k] = (raw[k] - c.xm[k]) / c.xs[k];
+}
+
+// one overdamped step: p_i += mobility * sum_j f(r_ij) e_ij, e_ij the unit vector from j
+// to i; f the network's lateral force (positive = repulsion) for r_contact <= r <= r_cut,
+// the contact repulsion k_contact (r_contact - r) closer (outside the network's domain),
+// 0 farther; partners summed in index order
+__global__ void k_cluster_move(const float2 *__restrict__ p, float2 *__restrict__ q,
+                               const float *__restrict__ Y, ClusterArgs c) {
+#pragma clang fp contract(off)
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= c.n) return;
+    const float2 pi = p[i];
+    float fx = 0.f, fy = 0.f;
+    for (int j = 0; j < c.n; ++j) {
+        if (j == i) continue;
+        const float2 d = min_image2(pi, p[j], c.box);
+        const float r = sqrtf(d.x * d.x + d.y * d.y), rr = r * c.inv_radius;
+        if (!(r > 0.f) || rr > c.r_cut) continue;
+        const float f = rr < c.r_contact ? c.k_contact * (c.r_contact - rr)
+                                         : Y[((size_t)i * c.n + j) * 2] * c.ys[0] + c.ym[0];
+        fx += f * d.x / r;
+        fy += f * d.y / r;
+    }
+    float x = pi.x + c.mobility * fx, y = pi.y + c.mobility * fy;
+    x -= c.box * floorf(x / c.box);
+    y -= c.box * floorf(y / c.box);
+    q[i] = make_float2(x, y);
+}
+
 }  // namespace
 
 struct lbm_surrogate {
@@ -323,6 +384,50 @@ extern "C" lbm_status lbm_surrogate_predict(lbm_surrogate *s, int32_t n, const f
     if (xin) (void)hipFree(xin);
     if (yout) (void)hipFree(yout);
     return ok ? LBM_OK : sfail(s, LBM_E_DEVICE, "prediction failed");
+}
+
+extern "C" lbm_status lbm_surrogate_cluster(lbm_surrogate *s, int32_t n, float *xy, int32_t steps,
+                                            const lbm_cluster_params *cp) {
+    if (!s) return LBM_E_INVAL;
+    if (!xy || !cp || n < 2 || steps < 0 || (int64_t)n * n > s->cap)
+        return sfail(s, LBM_E_INVAL, "need 2 <= n, n * n <= max_samples, positions and parameters");
+    if (!(cp->box > 0.f) || !(cp->radius > 0.f) || !(cp->r_cut > cp->r_contact) ||
+        !(cp->r_contact >= 0.f) || !(cp->k_contact >= 0.f) || !std::isfinite(cp->mobility))
+        return sfail(s, LBM_E_INVAL, "invalid cluster parameters");
+    for (int k = 0; k < 4; ++k)
+        if (!(cp->in_scale[k] > 0.f)) return sfail(s, LBM_E_INVAL, "input scales must be > 0");
+    ClusterArgs c{};
+    for (int k = 0; k < 4; ++k) { c.xm[k] = cp->in_mean[k]; c.xs[k] = cp->in_scale[k]; }
+    for (int k = 0; k < 2; ++k) { c.ym[k] = cp->out_mean[k]; c.ys[k] = cp->out_scale[k]; }
+    c.feat[0] = cp->log10_ks; c.feat[1] = cp->film; c.feat[2] = cp->angle;
+    c.box = cp->box; c.inv_radius = 1.0f / cp->radius;
+    c.r_contact = cp->r_contact; c.r_cut = cp->r_cut; c.k_contact = cp->k_contact;
+    c.mobility = cp->mobility; c.n = n;
+    const size_t np = (size_t)n * n;
+    float2 *p[2] = {nullptr, nullptr};
+    float *Xp = nullptr, *Yp = nullptr;
+    bool ok = hipMalloc(&p[0], n * sizeof(float2)) == hipSuccess &&
+              hipMalloc(&p[1], n * sizeof(float2)) == hipSuccess &&
+              hipMalloc(&Xp, np * 4 * sizeof(float)) == hipSuccess &&
+              hipMalloc(&Yp, np * 2 * sizeof(float)) == hipSuccess &&
+              hipStreamSynchronize(s->st) == hipSuccess &&
+              hipMemcpy(p[0], xy, n * sizeof(float2), hipMemcpyHostToDevice) == hipSuccess;
+    int cur = 0;
+    for (int t = 0; t < steps && ok; ++t) {
+        hipLaunchKernelGGL(k_pair_inputs, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, s->st,
+                           p[cur], c, Xp);
+        forward(s, Xp, Yp, (int)np);
+        hipLaunchKernelGGL(k_cluster_move, dim3((n + 255) / 256), dim3(256), 0, s->st, p[cur],
+                           p[1 - cur], Yp, c);
+        cur = 1 - cur;
+    }
+    ok = ok && hipGetLastError() == hipSuccess &&
+         hipMemcpyAsync(xy, p[cur], n * sizeof(float2), hipMemcpyDeviceToHost, s->st) == hipSuccess &&
+         hipStreamSynchronize(s->st) == hipSuccess;
+    void *bufs[] = {p[0], p[1], Xp, Yp};
+    for (void *b : bufs)
+        if (b) (void)hipFree(b);
+    return ok ? LBM_OK : sfail(s, LBM_E_DEVICE, "cluster evolution failed");
 }
 
 extern "C" lbm_status lbm_surrogate_params(lbm_surrogate *s, float *theta) {

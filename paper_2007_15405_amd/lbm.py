@@ -70,6 +70,14 @@ class KernelStat(C.Structure):
     _fields_ = [("name", C.c_char * 32), ("launches", C.c_int64), ("total_ms", C.c_double)]
 
 
+class ClusterParams(C.Structure):
+    _fields_ = [("box", C.c_float), ("radius", C.c_float), ("log10_ks", C.c_float),
+                ("film", C.c_float), ("angle", C.c_float), ("in_mean", C.c_float * 4),
+                ("in_scale", C.c_float * 4), ("out_mean", C.c_float * 2),
+                ("out_scale", C.c_float * 2), ("r_contact", C.c_float), ("r_cut", C.c_float),
+                ("k_contact", C.c_float), ("mobility", C.c_float)]
+
+
 # entry point -> (restype, argtypes); every function declared in include/lbm.h
 H = C.c_void_p
 SIGNATURES = {
@@ -106,6 +114,8 @@ SIGNATURES = {
     "lbm_surrogate_train": (C.c_int, [H, C.c_int32, C.c_float]),
     "lbm_surrogate_predict": (C.c_int, [H, C.c_int32, C.POINTER(C.c_float), C.POINTER(C.c_float)]),
     "lbm_surrogate_params": (C.c_int, [H, C.POINTER(C.c_float)]),
+    "lbm_surrogate_cluster": (C.c_int, [H, C.c_int32, C.POINTER(C.c_float), C.c_int32,
+                                        C.POINTER(ClusterParams)]),
     "lbm_surrogate_last_error": (C.c_char_p, [H]),
     "lbm_surrogate_destroy": (None, [H]),
 }
@@ -466,6 +476,25 @@ class Surrogate:
         th = np.zeros(SURROGATE_PARAMS, np.float32)
         self._check(self.L.lbm_surrogate_params(self.s, _fp(th)))
         return th
+
+    def cluster(self, xy, steps: int, *, box, radius, features, in_mean, in_scale, out_mean,
+                out_scale, r_contact, r_cut, k_contact, mobility) -> np.ndarray:
+        """Positions [n][2] after ``steps`` overdamped steps driven by the network's pair
+        forces (``lbm_surrogate_cluster``); ``features`` = raw (log10 ks, film / 2R,
+        contact angle)."""
+        p = np.ascontiguousarray(xy, dtype=np.float32).copy()
+        if p.ndim != 2 or p.shape[1] != 2:
+            raise ValueError("xy must be [n][2]")
+        cp = ClusterParams(box=box, radius=radius, log10_ks=features[0], film=features[1],
+                           angle=features[2], r_contact=r_contact, r_cut=r_cut,
+                           k_contact=k_contact, mobility=mobility)
+        cp.in_mean[:] = [float(v) for v in in_mean]
+        cp.in_scale[:] = [float(v) for v in in_scale]
+        cp.out_mean[:] = [float(v) for v in out_mean]
+        cp.out_scale[:] = [float(v) for v in out_scale]
+        self._check(self.L.lbm_surrogate_cluster(self.s, len(p), _fp(p), int(steps),
+                                                 C.byref(cp)))
+        return p
 
     def close(self):
         if getattr(self, "s", None):

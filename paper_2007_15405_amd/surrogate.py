@@ -110,3 +110,101 @@ def fit(X, Y, steps: int = 500, lr: float = 1e-3, seed: int = synth.SEED,
     net.set_data(((X - xm) / xs).astype(np.float32), ((Y - ym) / ys).astype(np.float32))
     net.train(steps, lr)
     return Fitted(net, xm, xs, ym, ys, X.min(0), X.max(0))
+
+
+# --------------------------------------------------------------------------------------
+# Cluster evolution driven by the network, and its analysis
+# --------------------------------------------------------------------------------------
+
+
+def cluster_params(fitted: Fitted, features, box: float, radius: float = RADIUS,
+                   k_contact: float = 0.05, mobility: float = 1.0) -> dict:
+    """Arguments of ``Surrogate.cluster`` for a trained surrogate: the network is used
+    from the contact separation up to the largest training separation; beyond that the
+    capillary force is taken as zero, closer the pair repels with ``k_contact`` per
+    radius of overlap (the solver is the fallback for contact, not a per-step option in
+    a many-capsule run)."""
+    return dict(box=float(box), radius=float(radius), features=[float(v) for v in features],
+                in_mean=fitted.xm, in_scale=fitted.xs, out_mean=fitted.ym,
+                out_scale=fitted.ys, r_contact=CONTACT, r_cut=float(fitted.hi[0]),
+                k_contact=float(k_contact), mobility=float(mobility))
+
+
+def _pairs_within(xy, box: float, cutoff: float):
+    p = np.asarray(xy, np.float64)
+    d = p[:, None, :] - p[None, :, :]
+    d -= box * np.round(d / box)
+    r = np.sqrt((d * d).sum(-1))
+    i, j = np.nonzero(np.triu(r <= cutoff, 1))
+    return i, j, r
+
+
+def cluster_labels(xy, box: float, cutoff: float) -> np.ndarray:
+    """Cluster of each capsule: centres at most ``cutoff`` apart (minimum image) are in
+    one cluster, transitively (union-find with path halving and union by size); each
+    cluster is labelled by its smallest member."""
+    n = len(xy)
+    parent = np.arange(n)
+    size = np.ones(n, int)
+
+    def root(a):
+        while parent[a] != a:
+            parent[a] = parent[parent[a]]
+            a = parent[a]
+        return a
+
+    i, j, _ = _pairs_within(xy, box, cutoff)
+    for a, b in zip(i.tolist(), j.tolist()):
+        ra, rb = root(a), root(b)
+        if ra != rb:
+            if size[ra] < size[rb]:
+                ra, rb = rb, ra
+            parent[rb] = ra
+            size[ra] += size[rb]
+    roots = np.array([root(a) for a in range(n)])
+    first = {}
+    for a in range(n):
+        first.setdefault(roots[a], a)
+    return np.array([first[r] for r in roots])
+
+
+def cluster_sizes(labels) -> tuple:
+    """(mean, largest) number of capsules per cluster, single capsules counted as
+    clusters of one."""
+    counts = np.unique(np.asarray(labels), return_counts=True)[1]
+    return float(counts.mean()), int(counts.max())
+
+
+def rdf(xy, box: float, dr: float, r_max: float):
+    """Radial distribution function of the centres, g(r) = (A / N) n(r) / (2 pi r dr):
+    shell centres and g over shells of width ``dr`` below ``r_max`` (minimum image)."""
+    n = len(xy)
+    _, _, r = _pairs_within(xy, box, 0.0)
+    nb = int(r_max / dr)
+    off = r[~np.eye(n, dtype=bool)]
+    count = np.bincount(np.minimum((off // dr).astype(int), nb), minlength=nb + 1)[:nb]
+    rk = (np.arange(nb) + 0.5) * dr
+    return rk, (box * box / n) * (count / n) / (2 * np.pi * rk * dr)
+
+
+def evolve(fitted: Fitted, xy, steps: int, every: int, features, box: float,
+           radius: float = RADIUS, k_contact: float = 0.05, mobility: float = 1.0,
+           delta0: float = 1.0):
+    """Run the cluster evolution for ``steps`` steps on the GPU, sampling every ``every``
+    steps: returns the final positions and a list of (step, mean cluster size, largest
+    cluster size) with clusters of centres at most 2R + delta0 apart."""
+    cp = cluster_params(fitted, features, box, radius, k_contact, mobility)
+    p = np.asarray(xy, np.float32)
+    if fitted.net.max_samples < len(p) ** 2:
+        raise ValueError(f"the network takes {fitted.net.max_samples} queries per call, the "
+                         f"evolution of {len(p)} capsules needs {len(p) ** 2}: fit with "
+                         f"max_queries >= n^2")
+    cut = 2 * radius + delta0
+    hist = [(0, *cluster_sizes(cluster_labels(p, box, cut)))]
+    done = 0
+    while done < steps:
+        k = min(every, steps - done)
+        p = fitted.net.cluster(p, k, **cp)
+        done += k
+        hist.append((done, *cluster_sizes(cluster_labels(p, box, cut))))
+    return p, hist

@@ -289,3 +289,14 @@ def surrogate_init(seed: int = SEED) -> np.ndarray:
         out.append(rng.normal(0.0, 1.0 / math.sqrt(dims[i]), dims[i] * dims[i + 1]))
         out.append(np.zeros(dims[i + 1]))
     return np.concatenate(out).astype(np.float32)
+
+
+def cluster_film(n: int = 512, radius: float = 10.0, packing: float = 0.25,
+                 min_sep: float = 2.4, seed: int = SEED):
+    """Capsule centres in the plane of a film for the cluster evolution: ``n`` capsules of
+    radius ``radius`` in a periodic square whose side gives the area fraction ``packing``
+    (n pi R^2 / box^2), placed uniformly at random at least ``min_sep`` radii apart.
+    Returns (box, float32 positions [n][2])."""
+    box = math.sqrt(n * math.pi * radius * radius / packing)
+    pts = place_capsules(n, radius, box, box, 0.0, min_sep * radius, seed)
+    return box, np.array([(x, y) for x, y, _ in pts], np.float32)

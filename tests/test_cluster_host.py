@@ -1,0 +1,134 @@
+"""Pins of the cluster evolution's CPU reference (oracle/cluster.py) against closed forms
+and invariants, and the library's host analysis (cluster labels by union-find, cluster
+sizes, radial distribution function) against the reference's plain definitions."""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import cluster, mlp
+
+
+def _cfg(**kw):
+    c = dict(box=200.0, radius=10.0, features=[-1.0, 0.2, 90.0], in_mean=[4.0, -1.5, 0.2, 90.0],
+             in_scale=[1.0, 0.5, 0.1, 1.0], out_mean=[-0.01, 0.5], out_scale=[0.02, 0.3],
+             r_contact=2.4, r_cut=6.0, k_contact=0.05, mobility=10.0)
+    c.update(kw)
+    return c
+
+
+def _theta(seed=0):
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(4):
+        k, n = mlp.DIMS[i], mlp.DIMS[i + 1]
+        out.append(rng.normal(0, 1 / math.sqrt(k), k * n))
+        out.append(0.1 * rng.normal(size=n))
+    return np.concatenate(out)
+
+
+def test_pair_beyond_the_cutoff_does_not_move():
+    p = np.array([[50.0, 50.0], [50.0 + 61.0, 50.0]], np.float32)
+    q = cluster.step(_theta(), p, _cfg())
+    assert np.array_equal(q, p)
+
+
+def test_contact_repulsion_is_the_closed_form():
+    # 2 radii apart (inside contact): each moves away by mobility * k (2.4 - 2)
+    p = np.array([[100.0, 100.0], [120.0, 100.0]], np.float32)
+    c = _cfg()
+    q = cluster.step(_theta(), p, c)
+    dx = c["mobility"] * c["k_contact"] * (np.float32(2.4) - 2.0)
+    assert q[0, 0] == pytest.approx(100.0 - dx, abs=2e-5)
+    assert q[1, 0] == pytest.approx(120.0 + dx, abs=2e-5)
+    assert q[0, 1] == q[1, 1] == 100.0
+
+
+def test_network_force_acts_along_the_pair_axis_with_its_sign():
+    # a pair at 4 R: the displacement is mobility * f along the axis, f = network output
+    # de-normalised; positive f pushes the pair apart
+    c = _cfg()
+    th = _theta(1)
+    p = np.array([[60.0, 70.0], [84.0, 102.0]], np.float32)    # |d| = 40 = 4 R
+    q = cluster.step(th, p, c)
+    x = (np.array([4.0, *c["features"]], np.float32) - np.float32(c["in_mean"])) / \
+        np.float32(c["in_scale"])
+    f = mlp.forward(th, x[None], mixed=True)[0][0, 0] * c["out_scale"][0] + c["out_mean"][0]
+    e = np.array([24.0, 32.0]) / 40.0
+    assert np.allclose(q[1] - p[1], c["mobility"] * f * e, atol=3e-5)
+    assert np.allclose(q[0] - p[0], -c["mobility"] * f * e, atol=3e-5)
+
+
+def test_minimum_image_and_translation_invariance():
+    c = _cfg()
+    th = _theta(2)
+    p = np.array([[10.0, 30.0], [180.0, 40.0], [25.0, 190.0], [150.0, 150.0]], np.float32)
+    q = cluster.step(th, p, c)
+    shift = np.float32([77.0, 123.0])
+    ps = (p + shift) % np.float32(c["box"])
+    qs = cluster.step(th, ps, c)
+    back = (qs - shift) % np.float32(c["box"])
+    dd = (back - q + 100.0) % 200.0 - 100.0
+    assert np.abs(dd).max() < 1e-4
+    # capsules 0 and 1 interact across the boundary (30 apart through x = 0)
+    assert not np.array_equal(q[0], p[0])
+
+
+def test_pair_forces_conserve_the_centre_of_mass():
+    box, p = synth.cluster_film(n=60, packing=0.3, seed=3)
+    c = _cfg(box=box)
+    q = cluster.step(_theta(4), p, c)
+    d = (q.astype(np.float64) - p + box / 2) % box - box / 2
+    assert np.abs(d).max() > 1e-3
+    assert np.abs(d.sum(0)).max() < 1e-4 * np.abs(d).sum()
+
+
+def test_oracle_clusters_of_a_chain():
+    x = np.array([10.0, 30.9, 51.8, 80.0, 100.0, 190.9], np.float64)
+    p = np.stack([x, np.full_like(x, 5.0)], 1)
+    lab = cluster.clusters(p, 200.0, 21.0)
+    # 10-30.9-51.8 chained (20.9 apart), 80-100 a pair, 190.9 joins 10 through the
+    # periodic boundary (19.1 apart)
+    assert lab.tolist() == [0, 0, 0, 3, 3, 0]
+    assert cluster.clusters(p, 200.0, 20.0).tolist() == [0, 1, 2, 3, 3, 0]
+
+
+def test_oracle_rdf_of_a_square_lattice():
+    a, m = 10.0, 12
+    g = np.stack(np.meshgrid(np.arange(m) * a, np.arange(m) * a), -1).reshape(-1, 2)
+    rk, gr = cluster.rdf(g, m * a, 0.5, 25.0)
+    # 4 neighbours at a, 4 at a sqrt 2, 4 at 2a, 8 at a sqrt 5
+    for r0, cnt in ((a, 4), (a * math.sqrt(2), 4), (2 * a, 4), (a * math.sqrt(5), 8)):
+        k = int(r0 // 0.5)
+        assert gr[k] == pytest.approx(a * a * cnt / (2 * math.pi * rk[k] * 0.5), rel=1e-12)
+    assert np.count_nonzero(gr) == 4
+
+
+def test_oracle_rdf_of_random_points_is_one():
+    rng = np.random.default_rng(5)
+    p = rng.uniform(0, 400.0, (800, 2))
+    rk, gr = cluster.rdf(p, 400.0, 10.0, 150.0)
+    assert np.abs(gr[3:].mean() - 1.0) < 0.03
+
+
+def test_union_find_labels_match_the_oracle():
+    from paper_2007_15405_amd import surrogate
+    box, p = synth.cluster_film(n=300, packing=0.35, min_sep=2.0, seed=7)
+    for cut in (21.0, 24.0, 30.0):
+        assert np.array_equal(surrogate.cluster_labels(p, box, cut), cluster.clusters(p, box, cut))
+
+
+def test_cluster_sizes():
+    from paper_2007_15405_amd import surrogate
+    assert surrogate.cluster_sizes([0, 0, 0, 3, 3, 5]) == (2.0, 3)
+    assert surrogate.cluster_sizes(np.arange(7)) == (1.0, 1)
+
+
+def test_rdf_matches_the_oracle():
+    from paper_2007_15405_amd import surrogate
+    box, p = synth.cluster_film(n=200, packing=0.3, seed=8)
+    rk, g = surrogate.rdf(p, box, 2.0, 120.0)
+    rk0, g0 = cluster.rdf(p, box, 2.0, 120.0)
+    assert np.array_equal(rk, rk0)
+    assert np.allclose(g, g0, rtol=1e-12, atol=0)
