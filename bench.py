@@ -240,8 +240,9 @@ def run_surrogate(seeds=(201, 202, 203, 204, 205), steps=8000, average=4000, tra
     t3 = time.perf_counter()
     f.predict(Q)
     us_query = (time.perf_counter() - t3) / len(Q) * 1e6
+    cl = run_cluster(f, X[tr], Y[tr])
     f.net.close()
-    return dict(
+    return dict(cluster_evolution=cl,
         samples=int(len(X)), train=int(len(tr)), held_out=int(len(te)),
         solver_runs=len(seeds) * 64, solver_steps=steps, outputs_averaged_over=average,
         held_out_rel_error={"lateral_force": round(float(err[0]), 4),
@@ -251,6 +252,77 @@ def run_surrogate(seeds=(201, 202, 203, 204, 205), steps=8000, average=4000, tra
         gemm_frac_of_bf16_peak=round(flops / (us_step * 1e-6) / 1e12 / PEAK_BF16_TFLOPS, 8),
         us_per_query=round(us_query, 4), solver_s_per_pair=round(t_lbm / (len(seeds) * 64), 4),
         speedup_per_pair=round(t_lbm / (len(seeds) * 64) / (us_query * 1e-6), 1))
+
+
+def run_network_kernels(samples=480, adam_steps=500, capsules=512, cluster_steps=2000):
+    """The network's kernels alone on synthetic data, sized like the learned form's use:
+    full-batch Adam on ``samples`` random normalised samples (initial parameters of
+    ``synth.surrogate_init``), then the cluster evolution of ``capsules`` capsules at 25 %
+    area fraction with normalisation of unit scale.  Wall time per Adam step and per
+    cluster step."""
+    import numpy as np
+
+    import synth
+    from paper_2007_15405_amd import Surrogate
+    rng = np.random.default_rng(synth.SEED)
+    net = Surrogate(synth.surrogate_init(), samples)
+    x = rng.normal(size=(samples, 4)).astype(np.float32)
+    t = np.tanh(x[:, :2] - 0.5 * x[:, 2:]).astype(np.float32)
+    net.set_data(x, t)
+    net.train(5, 1e-3)
+    t0 = time.perf_counter()
+    net.train(adam_steps, 1e-3)
+    us_adam = (time.perf_counter() - t0) / adam_steps * 1e6
+    box, p = synth.cluster_film(n=capsules, packing=0.25)
+    cp = dict(box=box, radius=10.0, features=[-1.0, 0.2, 90.0], in_mean=[4.0, -1.0, 0.2, 90.0],
+              in_scale=[1.0, 1.0, 1.0, 1.0], out_mean=[0.0, 0.0], out_scale=[1e-3, 1.0],
+              r_contact=2.4, r_cut=6.0, k_contact=1e-3, mobility=50.0)
+    net.cluster(p, 10, **cp)
+    t0 = time.perf_counter()
+    net.cluster(p, cluster_steps, **cp)
+    us_cl = (time.perf_counter() - t0) / cluster_steps * 1e6
+    net.close()
+    pairs = capsules * (capsules - 1)
+    flop = 2 * (4 * 64 + 64 * 64 * 2 + 64 * 2) * pairs
+    return dict(adam_samples=samples, adam_steps=adam_steps, us_per_adam_step=round(us_adam, 2),
+                cluster_capsules=capsules, cluster_steps=cluster_steps,
+                us_per_cluster_step=round(us_cl, 2),
+                cluster_network_tflops=round(flop / (us_cl * 1e-6) / 1e12, 3))
+
+
+def run_cluster(f, X, Y, n=512, packing=0.25, steps=20000, every=2000, timed=2000):
+    """Cluster evolution of ``n`` capsules at area fraction ``packing`` driven by the
+    trained network (features: the medians of the training inputs; mobility such that
+    the strongest training force moves a capsule 0.5 lattice units per step): time per
+    step (one fused kernel evaluating the network for all n (n - 1) ordered pairs), the
+    network's matrix-core rate, and the cluster statistics along the run."""
+    import numpy as np
+
+    import synth
+    from paper_2007_15405_amd import surrogate as S
+    box, p0 = synth.cluster_film(n=n, packing=packing)
+    feats = np.median(X[:, 1:], axis=0)
+    mob = 0.5 / float(np.abs(Y[:, 0]).max())
+    cp = S.cluster_params(f, feats, box, mobility=mob)
+    f.net.cluster(p0, 10, **cp)                               # warm-up
+    t = time.perf_counter()
+    f.net.cluster(p0, timed, **cp)
+    us = (time.perf_counter() - t) / timed * 1e6
+    pairs = n * (n - 1)
+    flop = 2 * (4 * 64 + 64 * 64 * 2 + 64 * 2) * pairs
+    rs = np.round(np.arange(S.CONTACT, cp["r_cut"] + 1e-9, 0.4), 2)
+    curve = f.predict(np.column_stack([rs, np.tile(feats, (len(rs), 1))]))[:, 0]
+    p, hist = S.evolve(f, p0, steps, every, feats, box, mobility=mob)
+    rk, g = S.rdf(p, box, 1.0, 6 * S.RADIUS)
+    peak = float(rk[np.argmax(g)]) / (2 * S.RADIUS)
+    return dict(capsules=n, area_fraction=packing, box=round(box, 2), r_cut_radii=round(cp["r_cut"], 3),
+                us_per_step=round(us, 2), pair_evals_per_s=round(pairs / (us * 1e-6), 1),
+                network_tflops=round(flop / (us * 1e-6) / 1e12, 3),
+                frac_of_bf16_peak=round(flop / (us * 1e-6) / 1e12 / PEAK_BF16_TFLOPS, 5),
+                features=[round(float(v), 4) for v in feats], mobility=round(mob, 3),
+                learned_force_vs_L_over_R=[(float(r), float(v)) for r, v in zip(rs, np.round(curve, 6))],
+                steps=steps, mean_and_largest_cluster=[(a, round(b, 3), c) for a, b, c in hist],
+                rdf_first_peak_over_2R=round(peak, 3))
 
 
 def cpu_baseline(cfg, steps=30):
@@ -279,6 +351,10 @@ def main():
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched form")
     ap.add_argument("--batch-only", action="store_true", help="only the batched form")
+    ap.add_argument("--network-kernels", action="store_true",
+                    help="only the network's kernels on synthetic data (for kernel traces): "
+                         "500 Adam steps on 480 samples, 2000 steps of the 512-capsule cluster "
+                         "evolution")
     ap.add_argument("--surrogate", action="store_true",
                     help="only the learned form: solver data, training, held-out error, speed")
     ap.add_argument("--kb", type=float, default=0.0,
@@ -311,6 +387,9 @@ def main():
 
     if args.surrogate:
         print(json.dumps(dict(surrogate=run_surrogate())), flush=True)
+        return
+    if args.network_kernels:
+        print(json.dumps(dict(network_kernels=run_network_kernels())), flush=True)
         return
 
     import synth

@@ -307,8 +307,12 @@ lbm_status lbm_surrogate_params(lbm_surrogate *s, float *theta);
  * r_contact <= r / radius <= r_cut (inputs r / radius and the three fixed features below,
  * normalised with in_mean / in_scale, output de-normalised with out_mean / out_scale);
  * closer pairs are outside the network's domain and repel with k_contact (r_contact -
- * r / radius); farther pairs exert no force.  Every step evaluates the network for all
- * n^2 ordered pairs (n * n <= max_samples). */
+ * r / radius); farther pairs exert no force.  Each step is one kernel that evaluates the
+ * network for all n (n - 1) ordered pairs on the matrix cores (same bfloat16 operands and
+ * float32 sums as lbm_surrogate_predict) and moves every capsule; the per-capsule sum
+ * runs in a fixed order.  Uses the network's current parameters and only the first
+ * output (the force); n is not limited by max_samples.  Allocates two device buffers of
+ * n positions per call; positions are float32, wrapped into [0, box). */
 typedef struct {
     float box, radius;
     float log10_ks, film, angle;          /* raw values of the other three inputs        */

@@ -86,6 +86,17 @@ def pair_forces_abs(theta, p, c):
     return np.where(act, np.abs(f), 0.0).sum(1)
 
 
+def network_partners(p, c):
+    """Number of partners of each capsule whose force comes from the network (separation
+    in [r_contact, r_cut] radii)."""
+    p = np.asarray(p, F32)
+    _, r = _separations(p, c["box"])
+    rr = r * (F32(1) / F32(c["radius"]))
+    act = (r > 0) & (rr <= F32(c["r_cut"])) & (rr >= F32(c["r_contact"])) & \
+        ~np.eye(len(p), dtype=bool)
+    return act.sum(1)
+
+
 def clusters(p, box, cutoff):
     """Cluster index per capsule: connected components of the graph joining centres at
     most `cutoff` apart (minimum image), by breadth-first search in float64; clusters

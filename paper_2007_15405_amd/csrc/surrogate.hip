@@ -145,63 +145,168 @@ __global__ void k_adam(float *__restrict__ th, float *__restrict__ m, float *__r
 
 // ------------------------------------------------------------------------------------
 // Cluster evolution driven by the network: overdamped capsules in a periodic square,
-// every pair's force from the network (dense: row i * n + j for all i, j).  The
-// separations and the network's inputs are computed without contraction into fused
-// multiply-adds, so that each is the correctly rounded float32 result of the operations
-// as written (the inputs are then rounded to bfloat16, a decision taken in float32).
+// p_i += mobility * sum_j f(r_ij) e_ij, f the network's lateral force for separations
+// in [r_contact, r_cut] radii, a contact repulsion closer, 0 farther.
+//
+// One fused kernel per step, one block per capsule i, four waves.  Each wave takes 16
+// partners j at a time through the whole network on the matrix cores in transposed
+// form, Z^T = W^T H^T: the partners are the 16 columns, so a layer's result tile (16
+// neurons as rows, four per lane) is already, lane for lane, the next layer's B operand
+// for the same 16 neurons as k, and the activations never leave registers.  The weights
+// are A operands held in registers for the whole block (80 VGPRs); the biases sit in
+// LDS.  The separations and the network's inputs are computed without contraction into
+// fused multiply-adds, so that each is the correctly rounded float32 result of the
+// operations as written (the inputs are then rounded to bfloat16, a decision taken in
+// float32).  The partner forces are summed per lane in partner order, then over the 64
+// lanes in a fixed order: no atomics, the result does not depend on scheduling.
 // ------------------------------------------------------------------------------------
 struct ClusterArgs {
-    float xm[4], xs[4], ym[2], ys[2];   // normalisation of the network's inputs / outputs
+    float xm[4], xs[4], ym, ys;         // normalisation of the inputs / the force output
     float feat[3];                      // log10 ks, film / 2R, contact angle (raw)
     float box, inv_radius, r_contact, r_cut, k_contact, mobility;
     int n;
 };
 
-__device__ __forceinline__ float2 min_image2(float2 a, float2 b, float box) {
-#pragma clang fp contract(off)
-    float dx = a.x - b.x, dy = a.y - b.y;
-    dx -= box * rintf(dx / box);
-    dy -= box * rintf(dy / box);
-    return make_float2(dx, dy);
-}
+constexpr int CL_THREADS = 256, CL_WAVES = CL_THREADS / 64;
+// parameter offsets as constants (the recursive woff / boff are not folded for device code)
+constexpr int CW1 = woff(0), CW2 = woff(1), CW3 = woff(2), CW4 = woff(3);
+constexpr int CB1 = boff(0), CB2 = boff(1), CB3 = boff(2), CB4 = boff(3);
+static_assert(CB2 == CB1 + NH + NH * NH && CB3 == CB2 + NH + NH * NH && CB4 == CW4 + NH * NOUT,
+              "parameter layout");
 
-// normalised network inputs of every ordered pair (i, j)
-__global__ void k_pair_inputs(const float2 *__restrict__ p, ClusterArgs c, float *__restrict__ X) {
-#pragma clang fp contract(off)
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= c.n * c.n) return;
-    const int i = idx / c.n, j = idx - i * c.n;
-    const float2 d = min_image2(p[i], p[j], c.box);
-    const float raw[4] = {sqrtf(d.x * d.x + d.y * d.y) * c.inv_radius, c.feat[0], c.feat[1], c.feat[2]};
+// four float32 values to bfloat16 with the hardware conversion (nearest, ties to even)
+__device__ __forceinline__ v4s bf16x4(v4f v) {
+    v4s o;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) X[(size_t)idx * 4 + k] = (raw[k] - c.xm[k]) / c.xs[k];
+    for (int k = 0; k < 4; ++k) o[k] = __builtin_bit_cast(short, (__bf16)v[k]);
+    return o;
 }
 
-// one overdamped step: p_i += mobility * sum_j f(r_ij) e_ij, e_ij the unit vector from j
-// to i; f the network's lateral force (positive = repulsion) for r_contact <= r <= r_cut,
-// the contact repulsion k_contact (r_contact - r) closer (outside the network's domain),
-// 0 farther; partners summed in index order
-__global__ void k_cluster_move(const float2 *__restrict__ p, float2 *__restrict__ q,
-                               const float *__restrict__ Y, ClusterArgs c) {
+// tanh x = 1 - 2 / (exp(2x) + 1) with the hardware base-2 exponential and reciprocal:
+// absolute error below 1e-6, and +-1 without overflow for large |x| (exp -> inf or 0)
+__device__ __forceinline__ float tanh_hw(float x) {
+    const float e = __builtin_amdgcn_exp2f(x * 2.88539008f);   // 2 / ln 2
+    return 1.0f - 2.0f * __builtin_amdgcn_rcpf(e + 1.0f);
+}
+
+__global__ void __launch_bounds__(CL_THREADS) k_cluster_step(const float2 *__restrict__ p,
+                                                             float2 *__restrict__ q,
+                                                             const float *__restrict__ th,
+                                                             ClusterArgs c) {
 #pragma clang fp contract(off)
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= c.n) return;
+    __shared__ float sb[3 * NH + NOUT];
+    __shared__ float sf[CL_WAVES][2][16];
+    const int i = blockIdx.x, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int col = lane & 15, kq = 4 * (lane >> 4);
+    for (int t = threadIdx.x; t < 3 * NH + NOUT; t += CL_THREADS) {
+        const int l = t / NH < 3 ? t / NH : 3, o = t - NH * l;
+        sb[t] = th[(l == 0 ? CB1 : l == 1 ? CB2 : l == 2 ? CB3 : CB4) + o];
+    }
+    // A operands, A[row][k] = W[k][row]: lane holds W[16 kb + kq + j][16 ot + col]
+    v4s w1[4], w2[4][4], w3[4][4], w4[4];
+#pragma unroll
+    for (int ot = 0; ot < 4; ++ot) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            w1[ot][j] = kq == 0 ? to_bf16(th[CW1 + j * NH + 16 * ot + col]) : (short)0;
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int k = 16 * kb + kq + j;
+                w2[ot][kb][j] = to_bf16(th[CW2 + k * NH + 16 * ot + col]);
+                w3[ot][kb][j] = to_bf16(th[CW3 + k * NH + 16 * ot + col]);
+            }
+    }
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            w4[kb][j] = col < NOUT ? to_bf16(th[CW4 + (16 * kb + kq + j) * NOUT + col]) : (short)0;
+    __syncthreads();
+
+    // biases as accumulator tiles: rows 16 ot + kq + e (output row 0 only for layer 4)
+    v4f bias[3][4], b4;
+#pragma unroll
+    for (int l = 0; l < 3; ++l)
+#pragma unroll
+        for (int ot = 0; ot < 4; ++ot)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) bias[l][ot][e] = sb[l * NH + 16 * ot + kq + e];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) b4[e] = kq + e < NOUT ? sb[3 * NH + kq + e] : 0.f;
+
     const float2 pi = p[i];
     float fx = 0.f, fy = 0.f;
-    for (int j = 0; j < c.n; ++j) {
-        if (j == i) continue;
-        const float2 d = min_image2(pi, p[j], c.box);
-        const float r = sqrtf(d.x * d.x + d.y * d.y), rr = r * c.inv_radius;
-        if (!(r > 0.f) || rr > c.r_cut) continue;
-        const float f = rr < c.r_contact ? c.k_contact * (c.r_contact - rr)
-                                         : Y[((size_t)i * c.n + j) * 2] * c.ys[0] + c.ym[0];
-        fx += f * d.x / r;
-        fy += f * d.y / r;
+    for (int j0 = 16 * wave; j0 < c.n; j0 += 16 * CL_WAVES) {   // wave-uniform trip count
+        const int j = j0 + col;
+        const float2 pj = j < c.n ? p[j] : pi;
+        float dx = pi.x - pj.x, dy = pi.y - pj.y;
+        dx -= c.box * rintf(dx / c.box);
+        dy -= c.box * rintf(dy / c.box);
+        const float r = sqrtf(dx * dx + dy * dy), rr = r * c.inv_radius;
+        v4s h0 = {0, 0, 0, 0};
+        if (kq == 0) {
+            h0[0] = to_bf16((rr - c.xm[0]) / c.xs[0]);
+#pragma unroll
+            for (int k = 1; k < 4; ++k) h0[k] = to_bf16((c.feat[k - 1] - c.xm[k]) / c.xs[k]);
+        }
+        // each accumulator starts from the bias of its neuron (row), so the matrix core
+        // adds it in its float32 sum
+        v4s h1[4], h2[4], h3[4];
+#pragma unroll
+        for (int ot = 0; ot < 4; ++ot) {
+            v4f z = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w1[ot], h0, bias[0][ot], 0, 0, 0);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) z[e] = tanh_hw(z[e]);
+            h1[ot] = bf16x4(z);
+        }
+#pragma unroll
+        for (int ot = 0; ot < 4; ++ot) {
+            v4f z = bias[1][ot];
+#pragma unroll
+            for (int kb = 0; kb < 4; ++kb) z = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w2[ot][kb], h1[kb], z, 0, 0, 0);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) z[e] = tanh_hw(z[e]);
+            h2[ot] = bf16x4(z);
+        }
+#pragma unroll
+        for (int ot = 0; ot < 4; ++ot) {
+            v4f z = bias[2][ot];
+#pragma unroll
+            for (int kb = 0; kb < 4; ++kb) z = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w3[ot][kb], h2[kb], z, 0, 0, 0);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) z[e] = tanh_hw(z[e]);
+            h3[ot] = bf16x4(z);
+        }
+        v4f y = b4;
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb) y = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w4[kb], h3[kb], y, 0, 0, 0);
+        // lanes 0..15 hold output row 0 (the force) of partner j in y[0]
+        if (kq == 0 && j < c.n && j != i && r > 0.f && rr <= c.r_cut) {
+            const float f = rr < c.r_contact ? c.k_contact * (c.r_contact - rr)
+                                             : y[0] * c.ys + c.ym;
+            fx += f * dx / r;
+            fy += f * dy / r;
+        }
     }
-    float x = pi.x + c.mobility * fx, y = pi.y + c.mobility * fy;
-    x -= c.box * floorf(x / c.box);
-    y -= c.box * floorf(y / c.box);
-    q[i] = make_float2(x, y);
+    if (kq == 0) {
+        sf[wave][0][col] = fx;
+        sf[wave][1][col] = fy;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float sx = 0.f, sy = 0.f;
+        for (int w = 0; w < CL_WAVES; ++w)
+            for (int l = 0; l < 16; ++l) {
+                sx += sf[w][0][l];
+                sy += sf[w][1][l];
+            }
+        float x = pi.x + c.mobility * sx, y = pi.y + c.mobility * sy;
+        x -= c.box * floorf(x / c.box);
+        y -= c.box * floorf(y / c.box);
+        q[i] = make_float2(x, y);
+    }
 }
 
 }  // namespace
@@ -389,8 +494,8 @@ extern "C" lbm_status lbm_surrogate_predict(lbm_surrogate *s, int32_t n, const f
 extern "C" lbm_status lbm_surrogate_cluster(lbm_surrogate *s, int32_t n, float *xy, int32_t steps,
                                             const lbm_cluster_params *cp) {
     if (!s) return LBM_E_INVAL;
-    if (!xy || !cp || n < 2 || steps < 0 || (int64_t)n * n > s->cap)
-        return sfail(s, LBM_E_INVAL, "need 2 <= n, n * n <= max_samples, positions and parameters");
+    if (!xy || !cp || n < 2 || steps < 0)
+        return sfail(s, LBM_E_INVAL, "need n >= 2 capsules, positions and parameters");
     if (!(cp->box > 0.f) || !(cp->radius > 0.f) || !(cp->r_cut > cp->r_contact) ||
         !(cp->r_contact >= 0.f) || !(cp->k_contact >= 0.f) || !std::isfinite(cp->mobility))
         return sfail(s, LBM_E_INVAL, "invalid cluster parameters");
@@ -398,34 +503,27 @@ extern "C" lbm_status lbm_surrogate_cluster(lbm_surrogate *s, int32_t n, float *
         if (!(cp->in_scale[k] > 0.f)) return sfail(s, LBM_E_INVAL, "input scales must be > 0");
     ClusterArgs c{};
     for (int k = 0; k < 4; ++k) { c.xm[k] = cp->in_mean[k]; c.xs[k] = cp->in_scale[k]; }
-    for (int k = 0; k < 2; ++k) { c.ym[k] = cp->out_mean[k]; c.ys[k] = cp->out_scale[k]; }
+    c.ym = cp->out_mean[0];
+    c.ys = cp->out_scale[0];
     c.feat[0] = cp->log10_ks; c.feat[1] = cp->film; c.feat[2] = cp->angle;
     c.box = cp->box; c.inv_radius = 1.0f / cp->radius;
     c.r_contact = cp->r_contact; c.r_cut = cp->r_cut; c.k_contact = cp->k_contact;
     c.mobility = cp->mobility; c.n = n;
-    const size_t np = (size_t)n * n;
     float2 *p[2] = {nullptr, nullptr};
-    float *Xp = nullptr, *Yp = nullptr;
     bool ok = hipMalloc(&p[0], n * sizeof(float2)) == hipSuccess &&
               hipMalloc(&p[1], n * sizeof(float2)) == hipSuccess &&
-              hipMalloc(&Xp, np * 4 * sizeof(float)) == hipSuccess &&
-              hipMalloc(&Yp, np * 2 * sizeof(float)) == hipSuccess &&
               hipStreamSynchronize(s->st) == hipSuccess &&
               hipMemcpy(p[0], xy, n * sizeof(float2), hipMemcpyHostToDevice) == hipSuccess;
     int cur = 0;
     for (int t = 0; t < steps && ok; ++t) {
-        hipLaunchKernelGGL(k_pair_inputs, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, s->st,
-                           p[cur], c, Xp);
-        forward(s, Xp, Yp, (int)np);
-        hipLaunchKernelGGL(k_cluster_move, dim3((n + 255) / 256), dim3(256), 0, s->st, p[cur],
-                           p[1 - cur], Yp, c);
+        hipLaunchKernelGGL(k_cluster_step, dim3(n), dim3(CL_THREADS), 0, s->st, p[cur], p[1 - cur],
+                           s->th, c);
         cur = 1 - cur;
     }
     ok = ok && hipGetLastError() == hipSuccess &&
          hipMemcpyAsync(xy, p[cur], n * sizeof(float2), hipMemcpyDeviceToHost, s->st) == hipSuccess &&
          hipStreamSynchronize(s->st) == hipSuccess;
-    void *bufs[] = {p[0], p[1], Xp, Yp};
-    for (void *b : bufs)
+    for (float2 *b : p)
         if (b) (void)hipFree(b);
     return ok ? LBM_OK : sfail(s, LBM_E_DEVICE, "cluster evolution failed");
 }

@@ -192,14 +192,12 @@ def evolve(fitted: Fitted, xy, steps: int, every: int, features, box: float,
            delta0: float = 1.0):
     """Run the cluster evolution for ``steps`` steps on the GPU, sampling every ``every``
     steps: returns the final positions and a list of (step, mean cluster size, largest
-    cluster size) with clusters of centres at most 2R + delta0 apart."""
+    cluster size) with clusters of centres at most d + delta0 apart, d the in-plane
+    contact separation (CONTACT radii: the closest approach of two capsules in the
+    solver's pair runs, the reduced model's particle diameter in the plane)."""
     cp = cluster_params(fitted, features, box, radius, k_contact, mobility)
     p = np.asarray(xy, np.float32)
-    if fitted.net.max_samples < len(p) ** 2:
-        raise ValueError(f"the network takes {fitted.net.max_samples} queries per call, the "
-                         f"evolution of {len(p)} capsules needs {len(p) ** 2}: fit with "
-                         f"max_queries >= n^2")
-    cut = 2 * radius + delta0
+    cut = CONTACT * radius + delta0
     hist = [(0, *cluster_sizes(cluster_labels(p, box, cut)))]
     done = 0
     while done < steps:

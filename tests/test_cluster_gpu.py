@@ -1,10 +1,19 @@
 """GPU parity of the cluster evolution driven by the network (lbm_surrogate_cluster)
-against the CPU reference oracle/cluster.py.  The separations and the network's inputs
-are float32 on both sides, operation by operation, so they agree exactly; the network's
-outputs then differ by the float32 sums of the matrix cores (1e-5 relative, as for the
-plain forward pass), and the summed force by float32 accumulation: one step agrees to
-1e-4 of the sum of the pair-force magnitudes on each capsule (plus one float32 rounding
-of each coordinate), and 20 steps to 1e-3 of the distance travelled."""
+against the CPU reference oracle/cluster.py.
+
+The separations and the network's inputs are float32 on both sides, operation by
+operation, so they agree exactly.  The kernel's network (one fused kernel per step, the
+activations in registers) sums in float32 on the matrix cores and takes tanh from the
+hardware exponential and reciprocal (absolute error below 1e-6), where the reference sums
+and takes tanh in float64.  Now and then that moves a hidden activation across a bfloat16
+rounding boundary: the activation then changes by one bfloat16 step (at most 2^-8 for
+|h| < 1), which reaches the normalised output through weights of magnitude ~1/8 per layer,
+so about 1e-3 at most.  One step therefore agrees to 1e-4 of the sum of the pair-force
+magnitudes on each capsule (float32 accumulation) plus 1e-3 of the output scale per
+partner in the network's range (rounding flips) plus one float32 rounding of each
+coordinate; twenty steps agree to 1e-3 of the distance travelled plus twenty times the
+flip allowance.
+"""
 import math
 
 import numpy as np
@@ -14,6 +23,8 @@ import synth
 from oracle import cluster, mlp
 
 pytestmark = pytest.mark.gpu
+
+FLIP = 1e-3     # output change from a bfloat16 rounding flip of one hidden activation
 
 
 def _theta(seed):
@@ -49,15 +60,16 @@ def _one_step(n, packing, seed):
     th = _theta(seed)
     box, p = synth.cluster_film(n=n, packing=packing, min_sep=2.0, seed=seed)
     c = _cfg(box)
-    s = Surrogate(th, n * n)
+    s = Surrogate(th, 64)
     q = s.cluster(p, 1, **_kw(c))
     s.close()
     qo = cluster.step(th.astype(np.float64), p, c)
     d_gpu = _wrap(q.astype(np.float64) - p, box)
     d_or = _wrap(qo.astype(np.float64) - p, box)
     scale = c["mobility"] * cluster.pair_forces_abs(th.astype(np.float64), p, c)
+    flips = c["mobility"] * FLIP * c["out_scale"][0] * cluster.network_partners(p, c)
     err = np.abs(d_gpu - d_or)
-    bound = 1e-4 * scale[:, None] + 2 * _ulp(p)
+    bound = (1e-4 * scale + flips)[:, None] + 2 * _ulp(p)
     assert (scale > 0).mean() > 0.9
     assert np.abs(d_or).max() > 0.05
     assert np.all(err <= bound), (np.argmax(err / bound), (err / bound).max())
@@ -76,15 +88,16 @@ def test_twenty_steps_follow_the_oracle():
     th = _theta(13)
     box, p = synth.cluster_film(n=96, packing=0.3, min_sep=2.0, seed=13)
     c = _cfg(box)
-    s = Surrogate(th, 96 * 96)
+    s = Surrogate(th, 64)
     q = s.cluster(p, 20, **_kw(c))
     s.close()
     qo = p
     for _ in range(20):
         qo = cluster.step(th.astype(np.float64), qo, c)
     travel = np.abs(_wrap(qo.astype(np.float64) - p, box)).max()
+    flips = 20 * c["mobility"] * FLIP * c["out_scale"][0] * cluster.network_partners(p, c).max()
     assert travel > 1.0
-    assert np.abs(_wrap(q.astype(np.float64) - qo, box)).max() <= 1e-3 * travel
+    assert np.abs(_wrap(q.astype(np.float64) - qo, box)).max() <= 1e-3 * travel + flips
 
 
 def test_zero_steps_and_refusals():
@@ -92,9 +105,7 @@ def test_zero_steps_and_refusals():
     th = _theta(14)
     box, p = synth.cluster_film(n=40, packing=0.3, seed=14)
     c = _cfg(box)
-    s = Surrogate(th, 40 * 40 - 1)
-    with pytest.raises(LbmError):
-        s.cluster(p, 1, **_kw(c))                  # n^2 above the network's capacity
+    s = Surrogate(th, 16)                          # the evolution needs no sample capacity
     with pytest.raises(LbmError):
         s.cluster(p[:1], 1, **_kw(c))              # a single capsule
     bad = _cfg(box)
@@ -102,4 +113,6 @@ def test_zero_steps_and_refusals():
     with pytest.raises(LbmError):
         s.cluster(p[:30], 1, **_kw(bad))           # cutoff inside contact
     assert np.array_equal(s.cluster(p[:30], 0, **_kw(c)), p[:30])
+    one = s.cluster(p[:2], 1, **_kw(c))            # the smallest system: one pair
+    assert np.all(np.isfinite(one))
     s.close()
