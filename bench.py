@@ -206,6 +206,9 @@ def run_batch(storage, steps, warmup, do_tune=True, launch=None, parts=None):
 PEAK_BF16_TFLOPS = 2500.0
 
 
+WET_MAX = 0.08     # capsule wetting offsets sampled in [-0.08, 0.08]: contact angles ~60..120 deg
+
+
 def run_surrogate(seeds=(201, 202, 203, 204, 205), steps=8000, average=4000, train_steps=500):
     """The learned form: training data from the batched solver (64 capsule-pair runs per
     seed), the network trained on three quarters of the pairs that stay out of contact,
@@ -215,7 +218,8 @@ def run_surrogate(seeds=(201, 202, 203, 204, 205), steps=8000, average=4000, tra
     import synth
     from paper_2007_15405_amd import surrogate as S
     t0 = time.perf_counter()
-    parts = [S.run_pairs(synth.batch_instances(seed=sd), steps, average=average) for sd in seeds]
+    parts = [S.run_pairs(synth.batch_instances(seed=sd, wet_max=WET_MAX), steps, average=average)
+             for sd in seeds]
     t_lbm = time.perf_counter() - t0
     X = np.concatenate([p[0] for p in parts])
     Y = np.concatenate([p[1] for p in parts])
@@ -243,6 +247,8 @@ def run_surrogate(seeds=(201, 202, 203, 204, 205), steps=8000, average=4000, tra
     cl = run_cluster(f, X[tr], Y[tr])
     f.net.close()
     return dict(cluster_evolution=cl,
+        wetting_offsets=[-WET_MAX, WET_MAX],
+        contact_angle_range=[round(float(X[:, 3].min()), 2), round(float(X[:, 3].max()), 2)],
         samples=int(len(X)), train=int(len(tr)), held_out=int(len(te)),
         solver_runs=len(seeds) * 64, solver_steps=steps, outputs_averaged_over=average,
         held_out_rel_error={"lateral_force": round(float(err[0]), 4),

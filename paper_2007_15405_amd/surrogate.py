@@ -25,10 +25,80 @@ CONTACT = 2.4         # L / R below which the pair comes into contact during the
                       # the solver (outside the surrogate's domain)
 
 
-def pair_inputs(inst: dict) -> np.ndarray:
+def pair_inputs(inst: dict, angles=None) -> np.ndarray:
+    """(L / R, log10 ks, film above the plane / 2R, contact angle in degrees); the angle
+    of the capsules' wetting offset is interpolated in ``angles`` = (offsets, angles) of
+    ``contact_angle_table`` (90 for a neutral capsule)."""
     film_above_plane = inst["film_height"] + 0.5 - PLANE
+    w = inst.get("wet_drho", 0.0)
+    theta = 90.0 if w == 0.0 and angles is None else float(np.interp(w, *angles))
     return np.array([inst["L"] / RADIUS, np.log10(inst["ks"]),
-                     film_above_plane / (2 * RADIUS), 90.0])
+                     film_above_plane / (2 * RADIUS), theta])
+
+
+# --------------------------------------------------------------------------------------
+# Contact angle of a wetting offset: a sessile drop on the substrate, run by the library
+# --------------------------------------------------------------------------------------
+
+DROP_BOX = (80, 3, 40)      # quasi-two-dimensional: periodic in x and y, wall at z = 0
+WALL_PLANE = 0.5            # half-way bounce-back between the solid layer and z = 1
+
+
+def drop_density(radius: float) -> np.ndarray:
+    """Initial densities [2][nz][ny][nx] of a half-cylinder of component 0 (radius
+    ``radius``) resting on the wall, component 1 around it."""
+    nx, ny, nz = DROP_BOX
+    x, z = np.meshgrid(np.arange(nx), np.arange(nz))
+    inside = ((x - (nx - 1) / 2) ** 2 + (z - WALL_PLANE) ** 2 < radius * radius) & (z >= 1)
+    rho = np.empty((2, nz, ny, nx))
+    rho[0] = np.where(inside, 0.72, 0.036)[:, None, :]
+    rho[1] = np.where(inside, 0.036, 0.72)[:, None, :]
+    return rho
+
+
+def contact_angle(r0, r1, wall: float = WALL_PLANE) -> float:
+    """Contact angle (degrees, inside component 0) of a drop on the wall from density
+    planes [nz][nx]: a least-squares circle through the points where the densities are
+    equal (interpolated along rows and columns, 3 or more sites above the wall), met
+    with the wall plane."""
+    phi = np.asarray(r0, np.float64) - np.asarray(r1, np.float64)
+    nz = phi.shape[0]
+    zs = np.arange(3, nz // 2)
+    a, b = phi[zs, :-1], phi[zs, 1:]
+    zi, xi = np.nonzero(a * b < 0)
+    px = [xi + a[zi, xi] / (a[zi, xi] - b[zi, xi])]
+    pz = [zs[zi].astype(np.float64)]
+    a, b = phi[zs, :], phi[zs + 1, :]
+    zi, xi = np.nonzero(a * b < 0)
+    px.append(xi.astype(np.float64))
+    pz.append(zs[zi] + a[zi, xi] / (a[zi, xi] - b[zi, xi]))
+    x, z = np.concatenate(px), np.concatenate(pz)
+    M = np.column_stack([2 * x, 2 * z, np.ones_like(x)])
+    (xc, zc, c), *_ = np.linalg.lstsq(M, x * x + z * z, rcond=None)
+    rc = np.sqrt(c + xc * xc + zc * zc)
+    return float(np.degrees(np.arccos(np.clip((wall - zc) / rc, -1.0, 1.0))))
+
+
+def wall_contact_angle(drho: float, radius: float = 14.0, steps: int = 4000,
+                       storage: str = "f32") -> float:
+    """Contact angle of the wetting offset ``drho``: a sessile drop on a wall with that
+    offset, run ``steps`` steps on the GPU and measured with ``contact_angle``."""
+    nx, ny, nz = DROP_BOX
+    cfg = synth.workload("pf", capsules=[], wall_z0=1, nx=nx, ny=ny, nz=nz, init_mode=2,
+                         init_rho_array=drop_density(radius), wall_drho=float(drho))
+    sim = Sim(cfg, storage=storage)
+    sim.step(steps)
+    r = sim.observables(rho=True, capsules=False)["rho"][:, :, ny // 2, :]
+    sim.close()
+    return contact_angle(r[0], r[1])
+
+
+def contact_angle_table(drhos) -> tuple:
+    """(offsets, angles) for interpolation: the wall contact angle of each offset.  A
+    capsule surface takes the offset through the same substitution as the wall, so its
+    contact angle is read from this table."""
+    d = np.sort(np.asarray(drhos, np.float64))
+    return d, np.array([wall_contact_angle(v) for v in d])
 
 
 def run_pairs(instances: list, steps: int, average: int = 0, every: int = 200,
@@ -37,10 +107,12 @@ def run_pairs(instances: list, steps: int, average: int = 0, every: int = 200,
     (inputs [n][4], outputs [n][2]) in the order of ``instances``; the outputs are
     averaged over samples taken every ``every`` steps during the last ``average`` steps
     (0: the final state only)."""
+    wmax = max(abs(i.get("wet_drho", 0.0)) for i in instances)
+    angles = contact_angle_table(np.linspace(-wmax, wmax, 5)) if wmax > 0 else None
     groups = synth.batch_groups(instances)
     sims = [Sim(g, storage=storage, meshes=synth.capsule_meshes(g["capsules"])) for g in groups]
     bt = Batch(sims, tile=13, zchunk=16, parts=parts)
-    X = np.array([pair_inputs(i) for i in instances])
+    X = np.array([pair_inputs(i, angles) for i in instances])
     Y = np.zeros((len(instances), 2))
     nsamp = max(1, average // every) if average else 1
     bt.step(steps - (nsamp - 1) * every if average else steps)

@@ -202,7 +202,7 @@ def workload(name: str, **over) -> dict:
 
 
 def batch_instances(n: int = 64, seed: int = SEED, radius: float = 10.0,
-                    n_tri: int = 5120, ks_max: float = 0.2) -> List[dict]:
+                    n_tri: int = 5120, ks_max: float = 0.2, wet_max: float = 0.0) -> List[dict]:
     """Independent capsule-pair runs for the batched form: separation L uniform in
     [2.2 R, 6 R], shear modulus log-uniform in [0.002, ks_max], film height (above the
     repulsive plane) uniform in [0.4, 0.9] of the capsule diameter.  ks_max = 0.2: with
@@ -211,7 +211,10 @@ def batch_instances(n: int = 64, seed: int = SEED, radius: float = 10.0,
     library alike; the paper's stiffer capsules (up to 5) rely on its own coupling.  Box
     Lx = clamp(16 * ceil((2 L + 2 R) / 16), 64, 128), Ly = 3 Lx / 4, Lz 40 or 48; wall at
     z = 0, repulsive plane 10 lu above it, the two anchored capsules resting delta0
-    above the plane on the x axis of the box, centred in x and y."""
+    above the plane on the x axis of the box, centred in x and y.  wet_max > 0: both
+    capsules of an instance get the wetting offset wet_drho uniform in [-wet_max,
+    wet_max] (drawn after the other parameters, so wet_max = 0 leaves every other draw
+    as it was)."""
     rng = np.random.default_rng(seed)
     out = []
     z_plane, delta0 = 0.5 + 10.0, 1.5
@@ -222,10 +225,11 @@ def batch_instances(n: int = 64, seed: int = SEED, radius: float = 10.0,
         lx = int(min(max(16 * math.ceil((2.0 * L + 2.0 * radius) / 16.0), 64), 128))
         ly = 3 * lx // 4
         lz = int(rng.choice([40, 48]))
+        wet = float(rng.uniform(-wet_max, wet_max)) if wet_max > 0 else 0.0
         zc = z_plane + delta0 + radius
         caps = [capsule((lx / 2.0 + sgn * L / 2.0, ly / 2.0, zc), radius, n_tri, ks,
-                        anchor_k=1.0) for sgn in (-1.0, 1.0)]
-        out.append(dict(nx=lx, ny=ly, nz=lz, L=float(L), ks=ks,
+                        wet_drho=wet, anchor_k=1.0) for sgn in (-1.0, 1.0)]
+        out.append(dict(nx=lx, ny=ly, nz=lz, L=float(L), ks=ks, wet_drho=wet,
                         film_height=float(round(z_plane - 0.5 + film)), capsules=caps))
     return out
 
