@@ -102,13 +102,12 @@ def contact_angle_table(drhos) -> tuple:
 
 
 def run_pairs(instances: list, steps: int, average: int = 0, every: int = 200,
-              storage: str = "f32", parts: int = 3):
+              storage: str = "f32", parts: int = 3, angles=None):
     """Run the instances with one batch (stacked by box size) and return
     (inputs [n][4], outputs [n][2]) in the order of ``instances``; the outputs are
     averaged over samples taken every ``every`` steps during the last ``average`` steps
     (0: the final state only)."""
-    wmax = max(abs(i.get("wet_drho", 0.0)) for i in instances)
-    angles = contact_angle_table(np.linspace(-wmax, wmax, 5)) if wmax > 0 else None
+    angles = _angles_for(instances) if angles is None else angles
     groups = synth.batch_groups(instances)
     sims = [Sim(g, storage=storage, meshes=synth.capsule_meshes(g["capsules"])) for g in groups]
     bt = Batch(sims, tile=13, zchunk=16, parts=parts)
@@ -145,17 +144,49 @@ def _outputs(groups, sims, n):
     return Y
 
 
-class Fitted:
-    """A trained surrogate with the normalisation of its inputs and outputs and the box
-    of its training inputs (its domain; queries outside go to the solver)."""
+def _angles_for(instances):
+    wmax = max(abs(i.get("wet_drho", 0.0)) for i in instances)
+    return contact_angle_table(np.linspace(-wmax, wmax, 5)) if wmax > 0 else None
 
-    def __init__(self, net: Surrogate, xm, xs, ym, ys, lo, hi):
+
+def in_hull(points, queries, tol: float = 1e-9) -> np.ndarray:
+    """Exact membership of each query in the convex hull of ``points``: the query is a
+    convex combination of the points, lambda >= 0, sum lambda = 1, sum lambda p = q, a
+    linear feasibility problem solved with scipy's HiGHS.  Coordinates are scaled to
+    unit spread first; queries outside the points' bounding box are outside without a
+    solve."""
+    from scipy.optimize import linprog
+    P = np.asarray(points, np.float64)
+    Q = np.atleast_2d(np.asarray(queries, np.float64))
+    lo, hi = P.min(0), P.max(0)
+    span = np.where(hi > lo, hi - lo, 1.0)
+    Ps, Qs = (P - lo) / span, (Q - lo) / span
+    inbox = np.all((Qs >= -tol) & (Qs <= 1 + tol), axis=1)
+    A = np.vstack([Ps.T, np.ones(len(Ps))])
+    out = np.zeros(len(Q), bool)
+    for k in np.nonzero(inbox)[0]:
+        r = linprog(np.zeros(len(Ps)), A_eq=A, b_eq=np.append(Qs[k], 1.0), bounds=(0, None),
+                    method="highs")
+        out[k] = r.status == 0
+    return out
+
+
+class Fitted:
+    """A trained surrogate with the normalisation of its inputs and outputs and its
+    training inputs, whose convex hull (with separations of at least CONTACT radii) is
+    its domain; queries outside go to the solver."""
+
+    def __init__(self, net: Surrogate, xm, xs, ym, ys, lo, hi, train_x=None):
         self.net, self.xm, self.xs, self.ym, self.ys = net, xm, xs, ym, ys
         self.lo, self.hi = lo, hi
+        self.train_x = train_x
 
     def inside(self, X) -> np.ndarray:
-        X = np.asarray(X, np.float64)
-        return np.all((X >= self.lo) & (X <= self.hi), axis=1) & (X[:, 0] >= CONTACT)
+        X = np.atleast_2d(np.asarray(X, np.float64))
+        ok = X[:, 0] >= CONTACT
+        if self.train_x is None:
+            return ok & np.all((X >= self.lo) & (X <= self.hi), axis=1)
+        return ok & in_hull(self.train_x, X)
 
     def predict(self, X) -> np.ndarray:
         x = (np.asarray(X, np.float64) - self.xm) / self.xs
@@ -181,7 +212,25 @@ def fit(X, Y, steps: int = 500, lr: float = 1e-3, seed: int = synth.SEED,
     net = Surrogate(synth.surrogate_init(seed), max(len(X), max_queries))
     net.set_data(((X - xm) / xs).astype(np.float32), ((Y - ym) / ys).astype(np.float32))
     net.train(steps, lr)
-    return Fitted(net, xm, xs, ym, ys, X.min(0), X.max(0))
+    return Fitted(net, xm, xs, ym, ys, X.min(0), X.max(0), X)
+
+
+def predict_or_solve(fitted: Fitted, instances: list, steps: int, average: int = 0,
+                     every: int = 200, angles=None):
+    """Outputs of capsule-pair instances: the network's prediction where the pair's inputs
+    lie in the surrogate's domain (``Fitted.inside``), the batched solver's run
+    (``run_pairs``) elsewhere.  Returns (inputs, outputs, solved mask)."""
+    angles = _angles_for(instances) if angles is None else angles
+    X = np.array([pair_inputs(i, angles) for i in instances])
+    Y = np.zeros((len(instances), 2))
+    inside = fitted.inside(X)
+    if inside.any():
+        Y[inside] = fitted.predict(X[inside])
+    out = np.nonzero(~inside)[0]
+    if len(out):
+        _, Ys = run_pairs([instances[k] for k in out], steps, average, every, angles=angles)
+        Y[out] = Ys
+    return X, Y, ~inside
 
 
 # --------------------------------------------------------------------------------------

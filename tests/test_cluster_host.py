@@ -132,3 +132,26 @@ def test_rdf_matches_the_oracle():
     rk0, g0 = cluster.rdf(p, box, 2.0, 120.0)
     assert np.array_equal(rk, rk0)
     assert np.allclose(g, g0, rtol=1e-12, atol=0)
+
+
+def test_hull_membership_matches_delaunay():
+    from scipy.spatial import Delaunay
+
+    from paper_2007_15405_amd import surrogate
+    rng = np.random.default_rng(9)
+    P = rng.normal(size=(120, 4)) * [1.0, 0.5, 0.2, 30.0] + [4.0, -1.5, 0.6, 90.0]
+    Q = rng.normal(size=(150, 4)) * [1.3, 0.65, 0.26, 39.0] + [4.0, -1.5, 0.6, 90.0]
+    assert np.array_equal(surrogate.in_hull(P, Q), Delaunay(P).find_simplex(Q) >= 0)
+
+
+def test_hull_membership_of_a_cube_and_a_flat_hull():
+    from paper_2007_15405_amd import surrogate
+    corners = np.array([[a, b, c, d] for a in (0, 1) for b in (0, 1) for c in (0, 1) for d in (0, 1)],
+                       float)
+    q = np.array([[0.5] * 4, [1.0, 1.0, 0.0, 0.5], [1.01, 0.5, 0.5, 0.5], [0.5, 0.5, 0.5, -0.01]])
+    assert surrogate.in_hull(corners, q).tolist() == [True, True, False, False]
+    # a constant coordinate (the contact angle of neutral runs): a 3-D hull in 4-D
+    flat = corners[:, :3]
+    P = np.column_stack([flat, np.full(len(flat), 90.0)])
+    q = np.array([[0.5, 0.5, 0.5, 90.0], [0.5, 0.5, 0.5, 91.0]])
+    assert surrogate.in_hull(P, q).tolist() == [True, False]

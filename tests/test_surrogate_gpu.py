@@ -102,7 +102,8 @@ def test_surrogate_learns_the_batched_solver():
     steps, outputs averaged over the last 3000): the network, trained on three quarters,
     predicts the meniscus deformation of the held-out quarter to within half of its
     spread and the lateral force better than its mean does, and answers every query in a
-    small fraction of the solver's time per pair (its gain over the method without it)."""
+    small fraction of the solver's time per pair (its gain over the method without it).
+    Most held-out pairs lie in the domain (the convex hull of the training inputs)."""
     import time
 
     import synth
@@ -127,5 +128,30 @@ def test_surrogate_learns_the_batched_solver():
           "s per pair: solver", per_pair_lbm, "network", per_pair_net, flush=True)
     assert err[1] < 0.5 and err[0] < 1.0
     assert per_pair_net < 1e-3 * per_pair_lbm
-    assert np.all(f.inside(X[te])) and not f.inside(np.array([[2.0, -2.0, 0.6, 90.0]]))[0]
+    # the domain is the convex hull of the training inputs: most held-out pairs lie in it
+    # (the rest go to the solver), a pair in contact does not
+    assert f.inside(X[te]).mean() > 0.6 and not f.inside(np.array([[2.0, -2.0, 0.6, 90.0]]))[0]
+    f.net.close()
+
+
+def test_queries_outside_the_domain_go_to_the_solver():
+    """Pairs whose inputs lie outside the convex hull of the training inputs (here: the
+    separations beyond 4 R, and those in contact) are run by the batched solver; the
+    others are predicted.  Both parts equal what their own path returns."""
+    import synth
+    from paper_2007_15405_amd import surrogate as S
+    rng = np.random.default_rng(11)
+    n = 2000
+    Xt = np.column_stack([rng.uniform(2.4, 4.5, n), rng.uniform(-3.0, -0.3, n),
+                          rng.uniform(0.2, 1.1, n), np.full(n, 90.0)])
+    Yt = np.column_stack([np.sin(Xt[:, 0]), Xt[:, 1] * Xt[:, 2]])
+    f = S.fit(Xt, Yt, steps=50, max_queries=256)
+    assert S.in_hull(Xt, [[3.0, -1.5, 0.6, 90.0]])[0] and not S.in_hull(Xt, [[4.6, -1.5, 0.6, 90.0]])[0]
+    inst = synth.batch_instances(n=8, seed=31)
+    X, Y, solved = S.predict_or_solve(f, inst, steps=300)
+    assert solved.any() and (~solved).any()
+    assert np.array_equal(solved, ~((X[:, 0] >= 2.4) & (X[:, 0] <= 4.5)))
+    assert np.array_equal(Y[~solved], f.predict(X[~solved]))
+    _, Ys = S.run_pairs([inst[k] for k in np.nonzero(solved)[0]], 300)
+    assert np.array_equal(Y[solved], Ys)
     f.net.close()
