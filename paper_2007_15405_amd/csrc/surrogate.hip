@@ -153,12 +153,14 @@ __global__ void k_adam(float *__restrict__ th, float *__restrict__ m, float *__r
 // form, Z^T = W^T H^T: the partners are the 16 columns, so a layer's result tile (16
 // neurons as rows, four per lane) is already, lane for lane, the next layer's B operand
 // for the same 16 neurons as k, and the activations never leave registers.  The weights
-// are A operands held in registers for the whole block (80 VGPRs); the biases sit in
-// LDS.  The separations and the network's inputs are computed without contraction into
-// fused multiply-adds, so that each is the correctly rounded float32 result of the
-// operations as written (the inputs are then rounded to bfloat16, a decision taken in
-// float32).  The partner forces are summed per lane in partner order, then over the 64
-// lanes in a fixed order: no atomics, the result does not depend on scheduling.
+// are A operands held in registers for the whole block (80 VGPRs); the biases, staged
+// through LDS, initialise the accumulators.  tanh comes from the hardware exponential
+// and reciprocal.  The separations and the network's inputs are computed without
+// contraction into fused multiply-adds, so that each is the correctly rounded float32
+// result of the operations as written (the inputs are then rounded to bfloat16, a
+// decision taken in float32).  The partner forces are summed per lane in partner order,
+// then over the 16 lanes of each of the four waves in a fixed order: no atomics, the
+// result does not depend on scheduling.
 // ------------------------------------------------------------------------------------
 struct ClusterArgs {
     float xm[4], xs[4], ym, ys;         // normalisation of the inputs / the force output
