@@ -209,7 +209,7 @@ PEAK_BF16_TFLOPS = 2500.0
 WET_MAX = 0.08     # capsule wetting offsets sampled in [-0.08, 0.08]: contact angles ~60..120 deg
 
 
-def run_surrogate(seeds=(201, 202, 203, 204, 205), steps=8000, average=4000, train_steps=500):
+def run_surrogate(seeds=(201, 202, 203, 204, 205), steps=20000, average=10000, train_steps=500):
     """The learned form: training data from the batched solver (64 capsule-pair runs per
     seed), the network trained on three quarters of the pairs that stay out of contact,
     held-out error, training and inference speed, and the solver's time per pair."""
@@ -218,8 +218,12 @@ def run_surrogate(seeds=(201, 202, 203, 204, 205), steps=8000, average=4000, tra
     import synth
     from paper_2007_15405_amd import surrogate as S
     t0 = time.perf_counter()
-    parts = [S.run_pairs(synth.batch_instances(seed=sd, wet_max=WET_MAX), steps, average=average)
-             for sd in seeds]
+    parts = []
+    for sd in seeds:
+        parts.append(S.run_pairs(synth.batch_instances(seed=sd, wet_max=WET_MAX), steps,
+                                 average=average))
+        print(f"# surrogate data: seed {sd} done, {time.perf_counter() - t0:.1f} s",
+              file=sys.stderr, flush=True)
     t_lbm = time.perf_counter() - t0
     X = np.concatenate([p[0] for p in parts])
     Y = np.concatenate([p[1] for p in parts])
@@ -298,18 +302,22 @@ def run_network_kernels(samples=480, adam_steps=500, capsules=512, cluster_steps
 
 def run_cluster(f, X, Y, n=512, packing=0.25, steps=20000, every=2000, timed=2000):
     """Cluster evolution of ``n`` capsules at area fraction ``packing`` driven by the
-    trained network (features: the medians of the training inputs; mobility such that
-    the strongest training force moves a capsule 0.5 lattice units per step): time per
-    step (one fused kernel evaluating the network for all n (n - 1) ordered pairs), the
-    network's matrix-core rate, and the cluster statistics along the run."""
+    trained network (shear modulus and film height: the medians of the training inputs;
+    mobility such that the strongest training force F moves a capsule 0.5 lattice units
+    per step, contact stiffness 5 F per radius of overlap, so that an overlap shrinks by
+    half per step without overshoot): time per step (one fused kernel evaluating the network for all n (n - 1)
+    ordered pairs), the network's matrix-core rate, the learned force against the
+    separation, and the cluster statistics of runs at the median and at the extreme
+    contact angles of the training data."""
     import numpy as np
 
     import synth
     from paper_2007_15405_amd import surrogate as S
     box, p0 = synth.cluster_film(n=n, packing=packing)
-    feats = np.median(X[:, 1:], axis=0)
-    mob = 0.5 / float(np.abs(Y[:, 0]).max())
-    cp = S.cluster_params(f, feats, box, mobility=mob)
+    med = np.median(X[:, 1:], axis=0)
+    fmax = float(np.abs(Y[:, 0]).max())
+    mob, kc = 0.5 / fmax, 5.0 * fmax
+    cp = S.cluster_params(f, med, box, k_contact=kc, mobility=mob)
     f.net.cluster(p0, 10, **cp)                               # warm-up
     t = time.perf_counter()
     f.net.cluster(p0, timed, **cp)
@@ -317,18 +325,23 @@ def run_cluster(f, X, Y, n=512, packing=0.25, steps=20000, every=2000, timed=200
     pairs = n * (n - 1)
     flop = 2 * (4 * 64 + 64 * 64 * 2 + 64 * 2) * pairs
     rs = np.round(np.arange(S.CONTACT, cp["r_cut"] + 1e-9, 0.4), 2)
-    curve = f.predict(np.column_stack([rs, np.tile(feats, (len(rs), 1))]))[:, 0]
-    p, hist = S.evolve(f, p0, steps, every, feats, box, mobility=mob)
-    rk, g = S.rdf(p, box, 1.0, 6 * S.RADIUS)
-    peak = float(rk[np.argmax(g)]) / (2 * S.RADIUS)
+    runs = {}
+    for ang in (X[:, 3].min(), med[2], X[:, 3].max()):
+        fe = np.array([med[0], med[1], ang])
+        force = f.predict(np.column_stack([rs, np.tile(fe, (len(rs), 1))]))[:, 0]
+        p, hist = S.evolve(f, p0, steps, every, fe, box, k_contact=kc, mobility=mob)
+        rk, g = S.rdf(p, box, 1.0, 6 * S.RADIUS)
+        runs[f"{ang:.1f}"] = dict(
+            learned_force_vs_L_over_R=[(float(r), float(v)) for r, v in zip(rs, np.round(force, 6))],
+            mean_and_largest_cluster=[(a, round(b, 3), c) for a, b, c in hist],
+            rdf_first_peak_over_2R=round(float(rk[np.argmax(g)]) / (2 * S.RADIUS), 3))
     return dict(capsules=n, area_fraction=packing, box=round(box, 2), r_cut_radii=round(cp["r_cut"], 3),
                 us_per_step=round(us, 2), pair_evals_per_s=round(pairs / (us * 1e-6), 1),
                 network_tflops=round(flop / (us * 1e-6) / 1e12, 3),
                 frac_of_bf16_peak=round(flop / (us * 1e-6) / 1e12 / PEAK_BF16_TFLOPS, 5),
-                features=[round(float(v), 4) for v in feats], mobility=round(mob, 3),
-                learned_force_vs_L_over_R=[(float(r), float(v)) for r, v in zip(rs, np.round(curve, 6))],
-                steps=steps, mean_and_largest_cluster=[(a, round(b, 3), c) for a, b, c in hist],
-                rdf_first_peak_over_2R=round(peak, 3))
+                log10_ks_and_film=[round(float(v), 4) for v in med[:2]], mobility=round(mob, 3),
+                k_contact=round(kc, 4),
+                steps=steps, by_contact_angle=runs)
 
 
 def cpu_baseline(cfg, steps=30):
