@@ -301,7 +301,9 @@ lbm_status lbm_surrogate_predict(lbm_surrogate *s, int32_t n, const float *x, fl
 /* Current parameters into theta [LBM_SURROGATE_PARAMS]. */
 lbm_status lbm_surrogate_params(lbm_surrogate *s, float *theta);
 
-/* Cluster evolution driven by the network: n capsules of radius `radius` in a periodic
+/* Cluster evolution driven by the network: the many-capsule clustering of the section on
+ * clustering of soft particles in a thin film, reduced to the capsules' centres in the
+ * film plane with pair forces from the network.  n capsules of radius `radius` in a periodic
  * square of side `box`, overdamped, p_i += mobility * sum_j f(r_ij) e_ij each step (e_ij the
  * unit vector from capsule j to i, minimum image).  f is the network's lateral force for
  * r_contact <= r / radius <= r_cut (inputs r / radius and the three fixed features below,
@@ -320,7 +322,10 @@ typedef struct {
     float r_contact, r_cut, k_contact, mobility;
 } lbm_cluster_params;
 
-/* xy host [n][2] in/out: positions, advanced by `steps` steps. */
+/* xy host [n][2] in/out (caller-owned, copied to the device and back): positions, advanced
+ * by `steps` steps.  Errors: LBM_E_INVAL for n < 2, steps < 0, a non-positive box, radius or
+ * input scale, r_cut <= r_contact, a negative k_contact or a non-finite mobility;
+ * LBM_E_DEVICE if an allocation or launch fails (positions then unchanged). */
 lbm_status lbm_surrogate_cluster(lbm_surrogate *s, int32_t n, float *xy, int32_t steps,
                                  const lbm_cluster_params *cp);
 
