@@ -209,7 +209,7 @@ PEAK_BF16_TFLOPS = 2500.0
 WET_MAX = 0.08     # capsule wetting offsets sampled in [-0.08, 0.08]: contact angles ~60..120 deg
 
 
-def run_surrogate(seeds=(201, 202, 203, 204, 205), steps=20000, average=10000, train_steps=500):
+def run_surrogate(seeds=tuple(range(201, 209)), steps=20000, average=10000, train_steps=500):
     """The learned form: training data from the batched solver (64 capsule-pair runs per
     seed), the network trained on three quarters of the pairs that stay out of contact,
     held-out error, training and inference speed, and the solver's time per pair."""
