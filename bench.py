@@ -297,7 +297,34 @@ def run_network_kernels(samples=480, adam_steps=500, capsules=512, cluster_steps
     return dict(adam_samples=samples, adam_steps=adam_steps, us_per_adam_step=round(us_adam, 2),
                 cluster_capsules=capsules, cluster_steps=cluster_steps,
                 us_per_cluster_step=round(us_cl, 2),
-                cluster_network_tflops=round(flop / (us_cl * 1e-6) / 1e12, 3))
+                cluster_network_tflops=round(flop / (us_cl * 1e-6) / 1e12, 3),
+                cpu_baseline=network_cpu_baseline(x, t, p, cp))
+
+
+def network_cpu_baseline(x, t, p, cp, reps=3):
+    """The network's CPU reference (the oracle, numpy, mixed precision as the kernels)
+    timed on the same data: one Adam step (loss, gradient and update) over the samples,
+    and one cluster step of all capsules; best of ``reps``."""
+    import numpy as np
+
+    import synth
+    from oracle import cluster, mlp
+    th = synth.surrogate_init().astype(np.float64)
+    z = np.zeros_like(th)
+    best_adam = best_cl = float("inf")
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        _, g = mlp.loss_and_grad(th, x, t, mixed=True)
+        mlp.adam(th, g, z, z, 1, 1e-3)
+        best_adam = min(best_adam, time.perf_counter() - t0)
+        t0 = time.perf_counter()
+        cluster.step(th, p, cp)
+        best_cl = min(best_cl, time.perf_counter() - t0)
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+    return dict(kind="oracle", unit="us", us_per_adam_step=round(best_adam * 1e6, 1),
+                us_per_cluster_step=round(best_cl * 1e6, 1), cores=threads,
+                sample=f"best of {reps}: one Adam step on {len(x)} samples, one cluster step of "
+                       f"{len(p)} capsules (numpy, float64 with bfloat16 operands)")
 
 
 def run_cluster(f, X, Y, n=512, packing=0.25, steps=20000, every=2000, timed=2000):
