@@ -29,71 +29,80 @@ from oracle import mlp
 F32 = np.float32
 
 
-def _separations(p, box):
-    """d[i, j] = p_i - p_j (minimum image) and |d|, float32 as the operations are written."""
+def _separations(p, box, rows=None):
+    """d[i, j] = p_i - p_j (minimum image) and |d| for the capsules i of ``rows`` (all by
+    default), float32 as the operations are written."""
     p = np.asarray(p, F32)
     b = F32(box)
-    d = p[:, None, :] - p[None, :, :]
+    q = p if rows is None else p[rows]
+    d = q[:, None, :] - p[None, :, :]
     d = d - b * np.rint(d / b)
     r = np.sqrt(d[..., 0] * d[..., 0] + d[..., 1] * d[..., 1])
     return d, r
 
 
-def step(theta, p, c):
+def step(theta, p, c, rows=None):
     """One overdamped step of all capsules; c: dict with box, radius, features (raw log10
     ks, film / 2R, contact angle), in_mean, in_scale, out_mean, out_scale, r_contact,
-    r_cut, k_contact, mobility.  Returns the new float32 positions."""
+    r_cut, k_contact, mobility.  Returns the new float32 positions (of the capsules in
+    ``rows`` only, if given)."""
     p = np.asarray(p, F32)
     n = len(p)
-    d, r = _separations(p, c["box"])
+    rows = np.arange(n) if rows is None else np.asarray(rows)
+    d, r = _separations(p, c["box"], rows)
+    m = len(rows)
     rr = r * (F32(1) / F32(c["radius"]))
     xm = np.asarray(c["in_mean"], F32)
     xs = np.asarray(c["in_scale"], F32)
-    raw = np.empty((n, n, 4), F32)
+    raw = np.empty((m, n, 4), F32)
     raw[..., 0] = rr
     raw[..., 1:] = np.asarray(c["features"], F32)
     x = (raw - xm) / xs
     y, _ = mlp.forward(theta, x.reshape(-1, 4), mixed=True)
-    f_net = y[:, 0].reshape(n, n) * float(c["out_scale"][0]) + float(c["out_mean"][0])
+    f_net = y[:, 0].reshape(m, n) * float(c["out_scale"][0]) + float(c["out_mean"][0])
     rc, rcut = F32(c["r_contact"]), F32(c["r_cut"])
     f = np.where(rr < rc, float(c["k_contact"]) * (float(rc) - rr.astype(np.float64)), f_net)
-    act = (r > 0) & (rr <= rcut) & ~np.eye(n, dtype=bool)
+    act = (r > 0) & (rr <= rcut) & (rows[:, None] != np.arange(n)[None, :])
     d64, r64 = d.astype(np.float64), np.where(act, r, 1).astype(np.float64)
     w = np.where(act, f / r64, 0.0)
     force = np.einsum("ij,ijk->ik", w, d64)
-    q = p.astype(np.float64) + float(c["mobility"]) * force
+    q = p[rows].astype(np.float64) + float(c["mobility"]) * force
     box = float(F32(c["box"]))
     q = q - box * np.floor(q / box)
     return q.astype(F32)
 
 
-def pair_forces_abs(theta, p, c):
-    """sum_j |f(r_ij)| per capsule over the interacting partners: the scale of the
-    rounding error of the summed force."""
+def pair_forces_abs(theta, p, c, rows=None):
+    """sum_j |f(r_ij)| per capsule (of ``rows``) over the interacting partners: the scale
+    of the rounding error of the summed force."""
     p = np.asarray(p, F32)
     n = len(p)
-    _, r = _separations(p, c["box"])
+    rows = np.arange(n) if rows is None else np.asarray(rows)
+    _, r = _separations(p, c["box"], rows)
+    m = len(rows)
     rr = r * (F32(1) / F32(c["radius"]))
-    raw = np.empty((n, n, 4), F32)
+    raw = np.empty((m, n, 4), F32)
     raw[..., 0] = rr
     raw[..., 1:] = np.asarray(c["features"], F32)
     x = (raw - np.asarray(c["in_mean"], F32)) / np.asarray(c["in_scale"], F32)
     y, _ = mlp.forward(theta, x.reshape(-1, 4), mixed=True)
-    f_net = y[:, 0].reshape(n, n) * float(c["out_scale"][0]) + float(c["out_mean"][0])
+    f_net = y[:, 0].reshape(m, n) * float(c["out_scale"][0]) + float(c["out_mean"][0])
     f = np.where(rr < F32(c["r_contact"]), float(c["k_contact"]) *
                  (float(F32(c["r_contact"])) - rr.astype(np.float64)), f_net)
-    act = (r > 0) & (rr <= F32(c["r_cut"])) & ~np.eye(n, dtype=bool)
+    act = (r > 0) & (rr <= F32(c["r_cut"])) & (rows[:, None] != np.arange(n)[None, :])
     return np.where(act, np.abs(f), 0.0).sum(1)
 
 
-def network_partners(p, c):
-    """Number of partners of each capsule whose force comes from the network (separation
-    in [r_contact, r_cut] radii)."""
+def network_partners(p, c, rows=None):
+    """Number of partners of each capsule (of ``rows``) whose force comes from the network
+    (separation in [r_contact, r_cut] radii)."""
     p = np.asarray(p, F32)
-    _, r = _separations(p, c["box"])
+    n = len(p)
+    rows = np.arange(n) if rows is None else np.asarray(rows)
+    _, r = _separations(p, c["box"], rows)
     rr = r * (F32(1) / F32(c["radius"]))
     act = (r > 0) & (rr <= F32(c["r_cut"])) & (rr >= F32(c["r_contact"])) & \
-        ~np.eye(len(p), dtype=bool)
+        (rows[:, None] != np.arange(n)[None, :])
     return act.sum(1)
 
 
