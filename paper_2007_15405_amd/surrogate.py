@@ -31,7 +31,9 @@ def pair_inputs(inst: dict, angles=None) -> np.ndarray:
     ``contact_angle_table`` (90 for a neutral capsule)."""
     film_above_plane = inst["film_height"] + 0.5 - PLANE
     w = inst.get("wet_drho", 0.0)
-    theta = 90.0 if w == 0.0 and angles is None else float(np.interp(w, *angles))
+    if angles is None and w != 0.0:
+        raise ValueError("a wetting capsule needs the contact-angle table (contact_angle_table)")
+    theta = 90.0 if angles is None else float(np.interp(w, *angles))
     return np.array([inst["L"] / RADIUS, np.log10(inst["ks"]),
                      film_above_plane / (2 * RADIUS), theta])
 
