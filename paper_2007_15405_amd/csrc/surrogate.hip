@@ -153,8 +153,9 @@ __global__ void k_adam(float *__restrict__ th, float *__restrict__ m, float *__r
 // form, Z^T = W^T H^T: the partners are the 16 columns, so a layer's result tile (16
 // neurons as rows, four per lane) is already, lane for lane, the next layer's B operand
 // for the same 16 neurons as k, and the activations never leave registers.  The weights
-// are A operands held in registers for the whole block (80 VGPRs); the biases, staged
-// through LDS, initialise the accumulators.  tanh comes from the hardware exponential
+// are A operands held in registers for the whole block (80 VGPRs), loaded ready-made
+// from a buffer that k_pack_cluster_net writes once per call; the biases, loaded the same
+// way as accumulator tiles, initialise the accumulators.  tanh comes from the hardware exponential
 // and reciprocal.  The separations and the network's inputs are computed without
 // contraction into fused multiply-adds, so that each is the correctly rounded float32
 // result of the operations as written (the inputs are then rounded to bfloat16, a
@@ -191,52 +192,84 @@ __device__ __forceinline__ float tanh_hw(float x) {
     return 1.0f - 2.0f * __builtin_amdgcn_rcpf(e + 1.0f);
 }
 
-__global__ void __launch_bounds__(CL_THREADS) k_cluster_step(const float2 *__restrict__ p,
+// The network in the lane layout of the matrix-core operands, written once per call so
+// that each block of the step loads it with a few coalesced loads: 40 A-operand fragments
+// (bfloat16 x 4 per lane: W1 by output tile, W2 and W3 by output tile and k block, W4 by
+// k block) and 13 accumulator tiles of biases (float x 4 per lane: b1, b2, b3 by output
+// tile, then b4), each stored as [fragment][lane].  A[row][k] = W[k][row], so lane
+// (col = lane % 16, kq = 4 (lane / 16)) holds W[16 kb + kq + j][16 ot + col], j = 0..3,
+// and bias rows 16 ot + kq + e, e = 0..3.
+constexpr int CL_FRAGS = 40, CL_BTILES = 13;
+
+__global__ void __launch_bounds__(64) k_pack_cluster_net(const float *__restrict__ th,
+                                                         uint2 *__restrict__ frag,
+                                                         float4 *__restrict__ btile) {
+    const int lane = threadIdx.x, col = lane & 15, kq = 4 * (lane >> 4);
+    auto put = [&](int f, v4s v) { frag[f * 64 + lane] = __builtin_bit_cast(uint2, v); };
+    for (int ot = 0; ot < 4; ++ot) {
+        v4s w;
+        for (int j = 0; j < 4; ++j) w[j] = kq == 0 ? to_bf16(th[CW1 + j * NH + 16 * ot + col]) : (short)0;
+        put(ot, w);
+        for (int kb = 0; kb < 4; ++kb) {
+            v4s a, b;
+            for (int j = 0; j < 4; ++j) {
+                const int k = 16 * kb + kq + j;
+                a[j] = to_bf16(th[CW2 + k * NH + 16 * ot + col]);
+                b[j] = to_bf16(th[CW3 + k * NH + 16 * ot + col]);
+            }
+            put(4 + 4 * ot + kb, a);
+            put(20 + 4 * ot + kb, b);
+        }
+    }
+    for (int kb = 0; kb < 4; ++kb) {
+        v4s w;
+        for (int j = 0; j < 4; ++j)
+            w[j] = col < NOUT ? to_bf16(th[CW4 + (16 * kb + kq + j) * NOUT + col]) : (short)0;
+        put(36 + kb, w);
+    }
+    const int boffs[3] = {CB1, CB2, CB3};
+    for (int l = 0; l < 3; ++l)
+        for (int ot = 0; ot < 4; ++ot)
+            btile[(4 * l + ot) * 64 + lane] =
+                make_float4(th[boffs[l] + 16 * ot + kq], th[boffs[l] + 16 * ot + kq + 1],
+                            th[boffs[l] + 16 * ot + kq + 2], th[boffs[l] + 16 * ot + kq + 3]);
+    float b4[4];
+    for (int e = 0; e < 4; ++e) b4[e] = kq + e < NOUT ? th[CB4 + kq + e] : 0.f;
+    btile[12 * 64 + lane] = make_float4(b4[0], b4[1], b4[2], b4[3]);
+}
+
+__global__ void __launch_bounds__(CL_THREADS, 3) k_cluster_step(const float2 *__restrict__ p,
                                                              float2 *__restrict__ q,
-                                                             const float *__restrict__ th,
+                                                             const uint2 *__restrict__ frag,
+                                                             const float4 *__restrict__ btile,
                                                              ClusterArgs c) {
 #pragma clang fp contract(off)
-    __shared__ float sb[3 * NH + NOUT];
     __shared__ float sf[CL_WAVES][2][16];
     const int i = blockIdx.x, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int col = lane & 15, kq = 4 * (lane >> 4);
-    for (int t = threadIdx.x; t < 3 * NH + NOUT; t += CL_THREADS) {
-        const int l = t / NH < 3 ? t / NH : 3, o = t - NH * l;
-        sb[t] = th[(l == 0 ? CB1 : l == 1 ? CB2 : l == 2 ? CB3 : CB4) + o];
-    }
-    // A operands, A[row][k] = W[k][row]: lane holds W[16 kb + kq + j][16 ot + col]
+    auto ld = [&](int f) { return __builtin_bit_cast(v4s, frag[f * 64 + lane]); };
+    auto lb = [&](int t) {
+        const float4 b = btile[t * 64 + lane];
+        v4f v = {b.x, b.y, b.z, b.w};
+        return v;
+    };
+    // A operands (weights) and accumulator tiles (biases), see k_pack_cluster_net
     v4s w1[4], w2[4][4], w3[4][4], w4[4];
+    v4f bias[3][4];
 #pragma unroll
     for (int ot = 0; ot < 4; ++ot) {
+        w1[ot] = ld(ot);
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-            w1[ot][j] = kq == 0 ? to_bf16(th[CW1 + j * NH + 16 * ot + col]) : (short)0;
+        for (int kb = 0; kb < 4; ++kb) {
+            w2[ot][kb] = ld(4 + 4 * ot + kb);
+            w3[ot][kb] = ld(20 + 4 * ot + kb);
+        }
 #pragma unroll
-        for (int kb = 0; kb < 4; ++kb)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int k = 16 * kb + kq + j;
-                w2[ot][kb][j] = to_bf16(th[CW2 + k * NH + 16 * ot + col]);
-                w3[ot][kb][j] = to_bf16(th[CW3 + k * NH + 16 * ot + col]);
-            }
+        for (int l = 0; l < 3; ++l) bias[l][ot] = lb(4 * l + ot);
     }
 #pragma unroll
-    for (int kb = 0; kb < 4; ++kb)
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-            w4[kb][j] = col < NOUT ? to_bf16(th[CW4 + (16 * kb + kq + j) * NOUT + col]) : (short)0;
-    __syncthreads();
-
-    // biases as accumulator tiles: rows 16 ot + kq + e (output row 0 only for layer 4)
-    v4f bias[3][4], b4;
-#pragma unroll
-    for (int l = 0; l < 3; ++l)
-#pragma unroll
-        for (int ot = 0; ot < 4; ++ot)
-#pragma unroll
-            for (int e = 0; e < 4; ++e) bias[l][ot][e] = sb[l * NH + 16 * ot + kq + e];
-#pragma unroll
-    for (int e = 0; e < 4; ++e) b4[e] = kq + e < NOUT ? sb[3 * NH + kq + e] : 0.f;
+    for (int kb = 0; kb < 4; ++kb) w4[kb] = ld(36 + kb);
+    const v4f b4 = lb(12);
 
     const float2 pi = p[i];
     float fx = 0.f, fy = 0.f;
@@ -512,14 +545,20 @@ extern "C" lbm_status lbm_surrogate_cluster(lbm_surrogate *s, int32_t n, float *
     c.r_contact = cp->r_contact; c.r_cut = cp->r_cut; c.k_contact = cp->k_contact;
     c.mobility = cp->mobility; c.n = n;
     float2 *p[2] = {nullptr, nullptr};
+    uint2 *frag = nullptr;
+    float4 *btile = nullptr;
     bool ok = hipMalloc(&p[0], n * sizeof(float2)) == hipSuccess &&
               hipMalloc(&p[1], n * sizeof(float2)) == hipSuccess &&
+              hipMalloc(&frag, CL_FRAGS * 64 * sizeof(uint2)) == hipSuccess &&
+              hipMalloc(&btile, CL_BTILES * 64 * sizeof(float4)) == hipSuccess &&
               hipStreamSynchronize(s->st) == hipSuccess &&
               hipMemcpy(p[0], xy, n * sizeof(float2), hipMemcpyHostToDevice) == hipSuccess;
+    if (ok && steps > 0)
+        hipLaunchKernelGGL(k_pack_cluster_net, dim3(1), dim3(64), 0, s->st, s->th, frag, btile);
     int cur = 0;
     for (int t = 0; t < steps && ok; ++t) {
         hipLaunchKernelGGL(k_cluster_step, dim3(n), dim3(CL_THREADS), 0, s->st, p[cur], p[1 - cur],
-                           s->th, c);
+                           frag, btile, c);
         cur = 1 - cur;
     }
     ok = ok && hipGetLastError() == hipSuccess &&
@@ -527,6 +566,8 @@ extern "C" lbm_status lbm_surrogate_cluster(lbm_surrogate *s, int32_t n, float *
          hipStreamSynchronize(s->st) == hipSuccess;
     for (float2 *b : p)
         if (b) (void)hipFree(b);
+    if (frag) (void)hipFree(frag);
+    if (btile) (void)hipFree(btile);
     return ok ? LBM_OK : sfail(s, LBM_E_DEVICE, "cluster evolution failed");
 }
 
