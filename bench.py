@@ -414,7 +414,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); "
-              f"the multi-GPU halo exchange is a design, not part of this build",
+              f"the multi-GPU halo exchange is designed but not implemented",
               file=sys.stderr)
         sys.exit(2)
 
