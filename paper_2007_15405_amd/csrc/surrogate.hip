@@ -47,27 +47,31 @@ enum Epi { EPI_STORE = 0, EPI_BIAS_TANH = 1, EPI_BIAS = 2, EPI_TANH_GRAD = 3 };
 //   EPI_BIAS       C = AB + bias[j]
 //   EPI_TANH_GRAD  C = AB * (1 - P[i][j]^2), P the layer's tanh output (row stride ldc)
 // One wave per 16 x 16 tile of C, four waves per block; elements outside M, N, K are 0.
+// Split K (kz > 0, EPI_STORE only): block row y sums k in [y kz, (y + 1) kz) and writes
+// its partial product to C + y M ldc; k_sum_slices adds the slices in order.
 // MFMA 16x16x16 lane layout: A row = lane % 16, B column = lane % 16, both with k =
 // 4 (lane / 16) .. +3; result row = 4 (lane / 16) + i, column = lane % 16.
 __global__ void __launch_bounds__(256) k_gemm_bf16(const float *__restrict__ A, int sar, int sac,
                                                    const float *__restrict__ B, int sbr, int sbc,
                                                    float *__restrict__ C, int ldc, int M, int N,
                                                    int K, int epi, const float *__restrict__ bias,
-                                                   const float *__restrict__ P) {
+                                                   const float *__restrict__ P, int kz) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int tiles_n = (N + 15) / 16;
     const int tile = blockIdx.x * 4 + wave;
     if (tile >= ((M + 15) / 16) * tiles_n) return;   // whole waves
     const int i0 = (tile / tiles_n) * 16, j0 = (tile % tiles_n) * 16;
     const int r = i0 + (lane & 15), c = j0 + (lane & 15), kq = 4 * (lane >> 4);
+    const int kb = kz ? (int)blockIdx.y * kz : 0, ke = kz ? min(K, kb + kz) : K;
+    if (kz) C += (size_t)blockIdx.y * M * ldc;
     v4f acc = {0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < K; k0 += 16) {
+    for (int k0 = kb; k0 < ke; k0 += 16) {
         v4s a, b;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int k = k0 + kq + j;
-            const float av = (r < M && k < K) ? A[(size_t)r * sar + (size_t)k * sac] : 0.f;
-            const float bv = (c < N && k < K) ? B[(size_t)k * sbr + (size_t)c * sbc] : 0.f;
+            const float av = (r < M && k < ke) ? A[(size_t)r * sar + (size_t)k * sac] : 0.f;
+            const float bv = (c < N && k < ke) ? B[(size_t)k * sbr + (size_t)c * sbc] : 0.f;
             a[j] = to_bf16(av);
             b[j] = to_bf16(bv);
         }
@@ -88,6 +92,17 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(const float *__restrict__ A, 
         }
         C[(size_t)row * ldc + col] = v;
     }
+}
+
+// C[i][j] = sum over the slices y = 0 .. ns - 1, in order, of S[y][i][j] (split-K sums)
+__global__ void k_sum_slices(const float *__restrict__ S, int ns, int M, int N,
+                             float *__restrict__ C, int ldc) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= M * N) return;
+    const int i = e / N, j = e - i * N;
+    float a = 0.f;
+    for (int y = 0; y < ns; ++y) a += S[(size_t)y * M * N + e];
+    C[(size_t)i * ldc + j] = a;
 }
 
 // dY = w (Y - T) / sum(w); per-block partial sums of w (Y - T)^2 for the loss
@@ -353,6 +368,7 @@ struct lbm_surrogate {
     int64_t t = 0;                       // Adam steps taken
     float *th = nullptr, *m = nullptr, *v = nullptr, *g = nullptr;
     float *x = nullptr, *y = nullptr, *tg = nullptr, *w = nullptr, *dy = nullptr, *part = nullptr;
+    float *slices = nullptr;             // split-K partial products [KS_MAX][64][64]
     float *act[NLAYER] = {nullptr, nullptr, nullptr, nullptr};   // input, tanh of 3 layers
     float *d[NLAYER] = {nullptr, nullptr, nullptr, nullptr};     // back-propagated dL/dz
     double wsum = 0.0;
@@ -367,11 +383,27 @@ lbm_status sfail(lbm_surrogate *s, lbm_status c, const std::string &m) {
     return c;
 }
 
+// split K into at most KS_MAX slices of at least 64 (products with a long K, i.e. the
+// weight gradients summed over the samples, would otherwise run on a handful of waves)
+constexpr int KS_MAX = 32;
+
 void gemm(hipStream_t st, const float *A, int sar, int sac, const float *B, int sbr, int sbc,
-          float *C, int ldc, int M, int N, int K, int epi, const float *bias, const float *P) {
+          float *C, int ldc, int M, int N, int K, int epi, const float *bias, const float *P,
+          float *slices = nullptr) {
     const int tiles = ((M + 15) / 16) * ((N + 15) / 16);
+    if (slices && epi == EPI_STORE && K > 128 && M <= NH && N <= NH) {
+        int ns = (K + 63) / 64;
+        ns = ns < KS_MAX ? ns : KS_MAX;
+        const int kz = ((K + ns - 1) / ns + 15) / 16 * 16;
+        ns = (K + kz - 1) / kz;
+        hipLaunchKernelGGL(k_gemm_bf16, dim3((tiles + 3) / 4, ns), dim3(256), 0, st, A, sar, sac, B,
+                           sbr, sbc, slices, N, M, N, K, EPI_STORE, nullptr, nullptr, kz);
+        hipLaunchKernelGGL(k_sum_slices, dim3((M * N + 255) / 256), dim3(256), 0, st, slices, ns, M,
+                           N, C, ldc);
+        return;
+    }
     hipLaunchKernelGGL(k_gemm_bf16, dim3((tiles + 3) / 4), dim3(256), 0, st, A, sar, sac, B, sbr,
-                       sbc, C, ldc, M, N, K, epi, bias, P);
+                       sbc, C, ldc, M, N, K, epi, bias, P, 0);
 }
 
 // forward pass over n rows of X (activations kept for back-propagation), output into Y
@@ -398,7 +430,7 @@ void backward(lbm_surrogate *s) {
         const int ki = LIN[l], no = LOUT[l];
         // dW_l = act_l^T dl   (ki x no, summed over the n rows)
         gemm(s->st, s->act[l], 1, ki, dl, no, 1, s->g + woff(l), no, ki, no, n, EPI_STORE,
-             nullptr, nullptr);
+             nullptr, nullptr, s->slices);
         hipLaunchKernelGGL(k_colsum, dim3(no), dim3(256), 0, s->st, dl, n, no, s->g + boff(l));
         if (l > 0) {   // dL/dz_{l-1} = (dl W_l^T) * (1 - act_l^2)
             gemm(s->st, dl, no, 1, s->th + woff(l), 1, no, s->d[l - 1], ki, n, ki, no,
@@ -429,7 +461,8 @@ extern "C" lbm_status lbm_surrogate_create(int32_t max_samples, const float *the
          hipMalloc(&s->tg, c * NOUT * sizeof(float)) == hipSuccess &&
          hipMalloc(&s->dy, c * NOUT * sizeof(float)) == hipSuccess &&
          hipMalloc(&s->w, c * sizeof(float)) == hipSuccess &&
-         hipMalloc(&s->part, ((c + 255) / 256) * sizeof(float)) == hipSuccess;
+         hipMalloc(&s->part, ((c + 255) / 256) * sizeof(float)) == hipSuccess &&
+         hipMalloc(&s->slices, (size_t)KS_MAX * NH * NH * sizeof(float)) == hipSuccess;
     for (int l = 0; l < NLAYER && ok; ++l)
         ok = hipMalloc(&s->act[l], c * LIN[l] * sizeof(float)) == hipSuccess &&
              hipMalloc(&s->d[l], c * LOUT[l] * sizeof(float)) == hipSuccess;
@@ -586,7 +619,7 @@ extern "C" const char *lbm_surrogate_last_error(const lbm_surrogate *s) {
 extern "C" void lbm_surrogate_destroy(lbm_surrogate *s) {
     if (!s) return;
     if (s->st) (void)hipStreamSynchronize(s->st);
-    float *bufs[] = {s->th, s->m, s->v, s->g, s->y, s->tg, s->dy, s->w, s->part};
+    float *bufs[] = {s->th, s->m, s->v, s->g, s->y, s->tg, s->dy, s->w, s->part, s->slices};
     for (float *b : bufs)
         if (b) (void)hipFree(b);
     for (int l = 0; l < NLAYER; ++l) {
