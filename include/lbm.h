@@ -324,7 +324,8 @@ typedef struct {
 
 /* xy host [n][2] in/out (caller-owned, copied to the device and back): positions, advanced
  * by `steps` steps.  Errors: LBM_E_INVAL for n < 2, steps < 0, a non-positive box, radius or
- * input scale, r_cut <= r_contact, a negative k_contact or a non-finite mobility;
+ * input scale, r_cut <= r_contact, 2 r_cut radius >= box (the minimum image would miss
+ * partners), a negative k_contact or a non-finite mobility;
  * LBM_E_DEVICE if an allocation or launch fails (positions then unchanged). */
 lbm_status lbm_surrogate_cluster(lbm_surrogate *s, int32_t n, float *xy, int32_t steps,
                                  const lbm_cluster_params *cp);

@@ -569,6 +569,10 @@ extern "C" lbm_status lbm_surrogate_cluster(lbm_surrogate *s, int32_t n, float *
         return sfail(s, LBM_E_INVAL, "invalid cluster parameters");
     for (int k = 0; k < 4; ++k)
         if (!(cp->in_scale[k] > 0.f)) return sfail(s, LBM_E_INVAL, "input scales must be > 0");
+    // the minimum image finds every partner within the cutoff only if the cutoff is below
+    // half the box
+    if (!(2.0 * cp->r_cut * cp->radius < cp->box))
+        return sfail(s, LBM_E_INVAL, "box must exceed twice the cutoff distance r_cut * radius");
     ClusterArgs c{};
     for (int k = 0; k < 4; ++k) { c.xm[k] = cp->in_mean[k]; c.xs[k] = cp->in_scale[k]; }
     c.ym = cp->out_mean[0];

@@ -134,6 +134,9 @@ def test_zero_steps_and_refusals():
     bad["r_cut"] = 2.0
     with pytest.raises(LbmError):
         s.cluster(p[:30], 1, **_kw(bad))           # cutoff inside contact
+    small = _cfg(110.0)
+    with pytest.raises(LbmError):
+        s.cluster(p[:30] % 110.0, 1, **_kw(small))  # cutoff 60 above half the box
     assert np.array_equal(s.cluster(p[:30], 0, **_kw(c)), p[:30])
     one = s.cluster(p[:2], 1, **_kw(c))            # the smallest system: one pair
     assert np.all(np.isfinite(one))
