@@ -138,3 +138,20 @@ def test_batch_without_handles_is_rejected():
     assert "NULL" in L.lbm_batch_last_error(None).decode()
     assert L.lbm_batch_step(None, 1) == lbm.LBM_E_INVAL
     L.lbm_batch_destroy(None)
+
+
+def test_surrogate_entry_points_reject_bad_input_on_the_host():
+    import numpy as np
+    L = pkg.load_library()
+    out = C.c_void_p()
+    th = np.zeros(lbm.SURROGATE_PARAMS, np.float32)
+    thp = th.ctypes.data_as(C.POINTER(C.c_float))
+    assert L.lbm_surrogate_create(0, thp, C.byref(out)) == lbm.LBM_E_INVAL
+    assert L.lbm_surrogate_create((1 << 20) + 1, thp, C.byref(out)) == lbm.LBM_E_INVAL
+    assert L.lbm_surrogate_create(16, None, C.byref(out)) == lbm.LBM_E_INVAL
+    assert b"max_samples" in L.lbm_surrogate_last_error(None)
+    assert L.lbm_surrogate_create(16, thp, None) == lbm.LBM_E_INVAL
+    assert L.lbm_surrogate_train(None, 1, 1e-3) == lbm.LBM_E_INVAL
+    assert L.lbm_surrogate_predict(None, 1, None, None) == lbm.LBM_E_INVAL
+    assert L.lbm_surrogate_cluster(None, 2, None, 1, None) == lbm.LBM_E_INVAL
+    L.lbm_surrogate_destroy(None)
