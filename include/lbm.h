@@ -313,8 +313,9 @@ lbm_status lbm_surrogate_params(lbm_surrogate *s, float *theta);
  * network for all n (n - 1) ordered pairs on the matrix cores (same bfloat16 operands and
  * float32 sums as lbm_surrogate_predict) and moves every capsule; the per-capsule sum
  * runs in a fixed order.  Uses the network's current parameters and only the first
- * output (the force); n is not limited by max_samples.  Allocates two device buffers of
- * n positions per call; positions are float32, wrapped into [0, box). */
+ * output (the force); n is not limited by max_samples.  Allocates, per call, two device
+ * buffers of n positions and the network in operand layout (33 KB), freed before it
+ * returns; positions are float32, wrapped into [0, box). */
 typedef struct {
     float box, radius;
     float log10_ks, film, angle;          /* raw values of the other three inputs        */
