@@ -371,20 +371,29 @@ def run_cluster(f, X, Y, n=512, packing=0.25, steps=20000, every=2000, timed=200
                 steps=steps, by_contact_angle=runs)
 
 
-def cpu_baseline(cfg, steps=30):
+def cpu_baseline(cfg, steps=30, single_steps=3):
+    """The FP64 oracle on the same workload on the host cores: ``steps`` steps with all
+    threads (the reported value), then ``single_steps`` steps on one thread."""
     import oracle
-    cores = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
-    o = oracle.Oracle(cfg, "f64", n_threads=cores)
-    o.step(1)
-    t = time.perf_counter()
-    o.step(steps)
-    dt = time.perf_counter() - t
     import synth
+    cores = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
     sites = synth.fluid_sites(cfg)
-    o.close()
-    return dict(value=sites * steps / dt / 1e6, unit="MLUPS", cores=cores, kind="oracle",
+
+    def rate(threads, n):
+        o = oracle.Oracle(cfg, "f64", n_threads=threads)
+        o.step(1)
+        t = time.perf_counter()
+        o.step(n)
+        dt = time.perf_counter() - t
+        o.close()
+        return sites * n / dt / 1e6, dt
+
+    v, dt = rate(cores, steps)
+    v1, dt1 = rate(1, single_steps)
+    return dict(value=v, unit="MLUPS", cores=cores, kind="oracle",
                 sample=f"{steps} steps of the same workload after 1 warm-up step, FP64 oracle, "
-                       f"{dt:.1f} s")
+                       f"{dt:.1f} s",
+                single_thread=dict(value=round(v1, 3), steps=single_steps, seconds=round(dt1, 1)))
 
 
 def main():
