@@ -155,3 +155,18 @@ def test_hull_membership_of_a_cube_and_a_flat_hull():
     P = np.column_stack([flat, np.full(len(flat), 90.0)])
     q = np.array([[0.5, 0.5, 0.5, 90.0], [0.5, 0.5, 0.5, 91.0]])
     assert surrogate.in_hull(P, q).tolist() == [True, False]
+
+
+def test_pair_forces_superpose():
+    """The displacement of a capsule among several is the sum of its displacements in
+    the pair systems with each partner alone (far from the others)."""
+    c = _cfg()
+    th = _theta(6)
+    p = np.array([[100.0, 100.0], [135.0, 100.0], [100.0, 58.0], [78.0, 122.0]], np.float32)
+    q = cluster.step(th, p, c).astype(np.float64) - p[0]
+    tot = np.zeros(2)
+    for j in (1, 2, 3):
+        pair = np.stack([p[0], p[j]])
+        tot += cluster.step(th, pair, c)[0].astype(np.float64) - p[0]
+    assert np.abs(q[0] - tot).max() < 3e-5
+    assert np.abs(tot).max() > 1e-3
