@@ -10,9 +10,10 @@ to i (minimum image).  Pairs closer than r_contact radii are outside the surroga
 domain and repel with k_contact (r_contact - r / R); pairs farther than r_cut radii
 exert no force.
 
-Precision: the separations and the network's inputs are float32, each operation rounded
-as written (the inputs are then rounded to bfloat16 inside the network, so that decision
-is taken in float32 on both sides); the network is oracle/mlp.py's mixed mode; the forces
+Precision: the separations (the minimum image through the float32 reciprocal of the box)
+and the network's inputs (scaled by the float32 reciprocals of the input scales) are
+float32, each operation rounded as written (the inputs are then rounded to bfloat16 inside
+the network, so that decision is taken in float32 on both sides); the network is oracle/mlp.py's mixed mode; the forces
 and the update are float64; the positions are stored as float32 between steps.
 
 Analysis: clusters (capsules in one cluster when their centres are at most `cutoff`
@@ -36,7 +37,7 @@ def _separations(p, box, rows=None):
     b = F32(box)
     q = p if rows is None else p[rows]
     d = q[:, None, :] - p[None, :, :]
-    d = d - b * np.rint(d / b)
+    d = d - b * np.rint(d * (F32(1) / b))
     r = np.sqrt(d[..., 0] * d[..., 0] + d[..., 1] * d[..., 1])
     return d, r
 
@@ -53,11 +54,11 @@ def step(theta, p, c, rows=None):
     m = len(rows)
     rr = r * (F32(1) / F32(c["radius"]))
     xm = np.asarray(c["in_mean"], F32)
-    xs = np.asarray(c["in_scale"], F32)
+    ixs = F32(1) / np.asarray(c["in_scale"], F32)
     raw = np.empty((m, n, 4), F32)
     raw[..., 0] = rr
     raw[..., 1:] = np.asarray(c["features"], F32)
-    x = (raw - xm) / xs
+    x = (raw - xm) * ixs
     y, _ = mlp.forward(theta, x.reshape(-1, 4), mixed=True)
     f_net = y[:, 0].reshape(m, n) * float(c["out_scale"][0]) + float(c["out_mean"][0])
     rc, rcut = F32(c["r_contact"]), F32(c["r_cut"])
@@ -84,7 +85,7 @@ def pair_forces_abs(theta, p, c, rows=None):
     raw = np.empty((m, n, 4), F32)
     raw[..., 0] = rr
     raw[..., 1:] = np.asarray(c["features"], F32)
-    x = (raw - np.asarray(c["in_mean"], F32)) / np.asarray(c["in_scale"], F32)
+    x = (raw - np.asarray(c["in_mean"], F32)) * (F32(1) / np.asarray(c["in_scale"], F32))
     y, _ = mlp.forward(theta, x.reshape(-1, 4), mixed=True)
     f_net = y[:, 0].reshape(m, n) * float(c["out_scale"][0]) + float(c["out_mean"][0])
     f = np.where(rr < F32(c["r_contact"]), float(c["k_contact"]) *

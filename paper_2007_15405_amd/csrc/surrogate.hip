@@ -171,17 +171,18 @@ __global__ void k_adam(float *__restrict__ th, float *__restrict__ m, float *__r
 // are A operands held in registers for the whole block (80 VGPRs), loaded ready-made
 // from a buffer that k_pack_cluster_net writes once per call; the biases, loaded the same
 // way as accumulator tiles, initialise the accumulators.  tanh comes from the hardware exponential
-// and reciprocal.  The separations and the network's inputs are computed without
-// contraction into fused multiply-adds, so that each is the correctly rounded float32
-// result of the operations as written (the inputs are then rounded to bfloat16, a
-// decision taken in float32).  The partner forces are summed per lane in partner order,
+// and reciprocal.  The separations (minimum image through the float32 reciprocal of the
+// box) and the network's inputs (scaled by float32 reciprocals of the input scales) are
+// computed without contraction into fused multiply-adds, so that each is the correctly
+// rounded float32 result of the operations as written (the inputs are then rounded to
+// bfloat16, a decision taken in float32).  The partner forces are summed per lane in partner order,
 // then over the 16 lanes of each of the four waves in a fixed order: no atomics, the
 // result does not depend on scheduling.
 // ------------------------------------------------------------------------------------
 struct ClusterArgs {
-    float xm[4], xs[4], ym, ys;         // normalisation of the inputs / the force output
+    float xm[4], inv_xs[4], ym, ys;     // normalisation of the inputs / the force output
     float feat[3];                      // log10 ks, film / 2R, contact angle (raw)
-    float box, inv_radius, r_contact, r_cut, k_contact, mobility;
+    float box, inv_box, inv_radius, r_contact, r_cut, k_contact, mobility;
     int n;
 };
 
@@ -292,14 +293,14 @@ __global__ void __launch_bounds__(CL_THREADS, 3) k_cluster_step(const float2 *__
         const int j = j0 + col;
         const float2 pj = j < c.n ? p[j] : pi;
         float dx = pi.x - pj.x, dy = pi.y - pj.y;
-        dx -= c.box * rintf(dx / c.box);
-        dy -= c.box * rintf(dy / c.box);
+        dx -= c.box * rintf(dx * c.inv_box);
+        dy -= c.box * rintf(dy * c.inv_box);
         const float r = sqrtf(dx * dx + dy * dy), rr = r * c.inv_radius;
         v4s h0 = {0, 0, 0, 0};
         if (kq == 0) {
-            h0[0] = to_bf16((rr - c.xm[0]) / c.xs[0]);
+            h0[0] = to_bf16((rr - c.xm[0]) * c.inv_xs[0]);
 #pragma unroll
-            for (int k = 1; k < 4; ++k) h0[k] = to_bf16((c.feat[k - 1] - c.xm[k]) / c.xs[k]);
+            for (int k = 1; k < 4; ++k) h0[k] = to_bf16((c.feat[k - 1] - c.xm[k]) * c.inv_xs[k]);
         }
         // each accumulator starts from the bias of its neuron (row), so the matrix core
         // adds it in its float32 sum
@@ -336,8 +337,9 @@ __global__ void __launch_bounds__(CL_THREADS, 3) k_cluster_step(const float2 *__
         if (kq == 0 && j < c.n && j != i && r > 0.f && rr <= c.r_cut) {
             const float f = rr < c.r_contact ? c.k_contact * (c.r_contact - rr)
                                              : y[0] * c.ys + c.ym;
-            fx += f * dx / r;
-            fy += f * dy / r;
+            const float fr = f / r;
+            fx += fr * dx;
+            fy += fr * dy;
         }
     }
     if (kq == 0) {
@@ -574,11 +576,11 @@ extern "C" lbm_status lbm_surrogate_cluster(lbm_surrogate *s, int32_t n, float *
     if (!(2.0 * cp->r_cut * cp->radius < cp->box))
         return sfail(s, LBM_E_INVAL, "box must exceed twice the cutoff distance r_cut * radius");
     ClusterArgs c{};
-    for (int k = 0; k < 4; ++k) { c.xm[k] = cp->in_mean[k]; c.xs[k] = cp->in_scale[k]; }
+    for (int k = 0; k < 4; ++k) { c.xm[k] = cp->in_mean[k]; c.inv_xs[k] = 1.0f / cp->in_scale[k]; }
     c.ym = cp->out_mean[0];
     c.ys = cp->out_scale[0];
     c.feat[0] = cp->log10_ks; c.feat[1] = cp->film; c.feat[2] = cp->angle;
-    c.box = cp->box; c.inv_radius = 1.0f / cp->radius;
+    c.box = cp->box; c.inv_box = 1.0f / cp->box; c.inv_radius = 1.0f / cp->radius;
     c.r_contact = cp->r_contact; c.r_cut = cp->r_cut; c.k_contact = cp->k_contact;
     c.mobility = cp->mobility; c.n = n;
     float2 *p[2] = {nullptr, nullptr};
