@@ -175,9 +175,9 @@ __global__ void k_adam(float *__restrict__ th, float *__restrict__ m, float *__r
 // box) and the network's inputs (scaled by float32 reciprocals of the input scales) are
 // computed without contraction into fused multiply-adds, so that each is the correctly
 // rounded float32 result of the operations as written (the inputs are then rounded to
-// bfloat16, a decision taken in float32).  The partner forces are summed per lane in partner order,
-// then over the 16 lanes of each of the four waves in a fixed order: no atomics, the
-// result does not depend on scheduling.
+// bfloat16, a decision taken in float32).  The partner forces are summed per lane in
+// partner order, then over the 16 lanes of each of the four waves in a fixed order: no
+// atomics, the result does not depend on scheduling.
 // ------------------------------------------------------------------------------------
 struct ClusterArgs {
     float xm[4], inv_xs[4], ym, ys;     // normalisation of the inputs / the force output
