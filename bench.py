@@ -35,32 +35,14 @@ TILES = {1: "32x8", 2: "64x4", 3: "32x16", 4: "64x8", 5: "16x16", 6: "pipe32x8",
          12: "rows128x4", 13: "rows-nx"}
 
 
-def applicable(tile, nx):
-    """Whole-row tiles need nx equal to their width, or (13) 16 <= nx <= 128; the library
-    falls back to 64x8 otherwise."""
-    return {11: nx == 256, 12: nx == 128, 13: 16 <= nx <= 128}.get(tile, True)
-
-
-def tune(sim, nx, steps=10):
-    """Launch-shape autotuner: time the fused fluid kernel for every tile shape that
-    applies to this box and a few z-chunk depths with HIP events, keep the fastest."""
-    best = None
-    for tile in (t for t in TILES if applicable(t, nx)):
-        for zc in (0, 8, 12, 16, 24, 32, 48):
-            sim.set_launch(tile, zc)
-            sim.step(2)
-            sim.set_profiling(2)
-            sim.step(steps)
-            st = sim.kernel_stats()
-            sim.set_profiling(False)
-            n, ms = st["fluid"]
-            t = ms / n
-            print(f"#   tune tile {TILES[tile]:>15s} zchunk {zc:2d}: fluid {t * 1e3:8.1f} us",
-                  file=sys.stderr, flush=True)
-            if best is None or t < best[0]:
-                best = (t, tile, zc)
-    sim.set_launch(best[1], best[2])
-    return dict(tile=TILES[best[1]], tile_id=best[1], zchunk=best[2], fluid_ms=best[0])
+def tune(sim, steps=10):
+    """The library's launch-shape autotuner (``lbm_autotune``): every tile shape that
+    applies to this box and a few z-chunk depths, timed with HIP events, the fastest kept."""
+    t = sim.autotune(steps)
+    print(f"#   autotuner: tile {TILES[t['tile']]} zchunk {t['zchunk']}: fluid "
+          f"{t['fluid_ms'] * 1e3:.1f} us", file=sys.stderr, flush=True)
+    return dict(tile=TILES[t["tile"]], tile_id=t["tile"], zchunk=t["zchunk"],
+                fluid_ms=t["fluid_ms"])
 
 
 def run_gpu(cfg, storage, steps, warmup, do_tune=True, launch=None):
@@ -70,7 +52,8 @@ def run_gpu(cfg, storage, steps, warmup, do_tune=True, launch=None):
 
     sim = Sim(cfg, storage=storage, stream="torch")
     stream = torch.cuda.current_stream()
-    tuned = tune(sim, cfg["nx"]) if do_tune else None
+    sim.step(2)                   # capsule windows in place before the launch shapes are timed
+    tuned = tune(sim) if do_tune else None
     if launch is not None:
         sim.set_launch(*launch)
         tuned = dict(tile=TILES.get(launch[0], "two-kernel"), tile_id=launch[0], zchunk=launch[1])
@@ -129,25 +112,18 @@ def run_batch(storage, steps, warmup, do_tune=True, launch=None, parts=None):
             for g in groups]
     bt = Batch(sims)
     stream = torch.cuda.current_stream()
-    best = None
-    fixed = launch is not None or not do_tune
-    tiles = (launch[0],) if launch is not None else ((6, 7, 8, 9, 10, 13) if do_tune else (10,))
-    zcs = (launch[1],) if launch is not None else ((0, 16, 24, 32, 48) if do_tune else (0,))
-    for tile in tiles:
-        for zc in zcs:
-            bt.set_launch(tile, zc)
-            bt.step(2)
-            bt.set_profiling(2)
-            bt.step(10)
-            n, ms = bt.kernel_stats()["fluid"]
-            bt.set_profiling(0)
-            t = ms / n
-            if not fixed:
-                print(f"#   batch {storage} tune tile {TILES[tile]:>10s} zchunk {zc:2d}: fluid "
-                      f"{t * 1e3:8.1f} us", file=sys.stderr, flush=True)
-            if best is None or t < best[0]:
-                best = (t, tile, zc)
-    bt.set_launch(best[1], best[2])
+    bt.step(2)
+    if launch is not None:
+        bt.set_launch(*launch)
+        best = (None, launch[0], launch[1])
+    elif do_tune:
+        t = bt.autotune(10)
+        print(f"#   batch {storage} autotuner: tile {TILES[t['tile']]} zchunk {t['zchunk']}: "
+              f"fluid {t['fluid_ms'] * 1e3:.1f} us", file=sys.stderr, flush=True)
+        best = (t["fluid_ms"], t["tile"], t["zchunk"])
+    else:
+        best = (None, 10, 0)
+        bt.set_launch(10, 0)
 
     def timed_steps():
         torch.cuda.synchronize()
@@ -371,6 +347,18 @@ def run_cluster(f, X, Y, n=512, packing=0.25, steps=20000, every=2000, timed=200
                 steps=steps, by_contact_angle=runs)
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (first processor in /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(cfg, steps=30, single_steps=3):
     """The FP64 oracle on the same workload on the host cores: ``steps`` steps with all
     threads (the reported value), then ``single_steps`` steps on one thread."""
@@ -390,7 +378,7 @@ def cpu_baseline(cfg, steps=30, single_steps=3):
 
     v, dt = rate(cores, steps)
     v1, dt1 = rate(1, single_steps)
-    return dict(value=v, unit="MLUPS", cores=cores, kind="oracle",
+    return dict(value=v, unit="MLUPS", cores=cores, kind="oracle", cpu_model=cpu_model(),
                 sample=f"{steps} steps of the same workload after 1 warm-up step, FP64 oracle, "
                        f"{dt:.1f} s",
                 single_thread=dict(value=round(v1, 3), steps=single_steps, seconds=round(dt1, 1)))

@@ -221,6 +221,19 @@ lbm_status lbm_kernel_stats(lbm_handle *h, lbm_kernel_stat *out, int32_t max, in
  * same order, so results are identical.  LBM_E_INVAL for other values. */
 lbm_status lbm_set_launch(lbm_handle *h, int32_t tile, int32_t zchunk);
 
+/* Launch-shape autotuner of the fluid step: times reps (1..1000) launches of the fluid
+ * kernel, after two untimed ones, with HIP events on the handle's stream for every launch
+ * shape that applies to the lattice (tiles 1..13 as in lbm_set_launch, of which 1..5 with
+ * tau != 1; z-chunks 0, 8, 12, 16, 24, 32, 48 capped at nz, 0 resolved to its value) and
+ * selects the fastest as by lbm_set_launch.  The simulation is not advanced: the timed
+ * launches read the current populations and write only the buffer and the window
+ * outputs that the next step rewrites, and the status words are restored.  They run on
+ * the labels and spread forces of the last step, so call it after at least one step for a
+ * timing that includes the capsule sites.  Synchronises.  *tile, *zchunk and *fluid_ms
+ * (mean kernel time of the choice, ms) may be NULL.  LBM_E_INVAL for reps out of range. */
+lbm_status lbm_autotune(lbm_handle *h, int32_t reps, int32_t *tile, int32_t *zchunk,
+                        double *fluid_ms);
+
 /* Algorithmic HBM bytes per fluid-site update of the fused fluid kernel for the
  * handle's storage: 2 components x 19 populations x (load + store). */
 double lbm_bytes_per_site(const lbm_handle *h);
@@ -246,6 +259,14 @@ lbm_status lbm_batch_create(lbm_handle *const *handles, int32_t n, lbm_batch **o
  * 13 needs 16 <= nx <= 128 in every handle, LBM_E_INVAL otherwise); zchunk 0 picks 48
  * planes, halved while a part's launch has fewer than 1024 workgroups. */
 lbm_status lbm_batch_set_launch(lbm_batch *b, int32_t tile, int32_t zchunk);
+
+/* The autotuner of lbm_autotune for the batched fluid launch: tiles 6..10 and (when every
+ * handle has 16 <= nx <= 128) 13, z-chunks 0, 8, 12, 16, 24, 32, 48; each candidate is timed
+ * as the fluid launches of all parts back to back on the handles' stream.  Selects the
+ * fastest as by lbm_batch_set_launch; the handles are not advanced and their status words
+ * are restored.  Synchronises. */
+lbm_status lbm_batch_autotune(lbm_batch *b, int32_t reps, int32_t *tile, int32_t *zchunk,
+                              double *fluid_ms);
 
 /* Split the handles into `parts` sets of about equal fluid sites (1..4, default 1), each
  * advanced by its own chain of launches on a stream of the batch's own (default priority),

@@ -10,11 +10,13 @@ to i (minimum image).  Pairs closer than r_contact radii are outside the surroga
 domain and repel with k_contact (r_contact - r / R); pairs farther than r_cut radii
 exert no force.
 
-Precision: the separations (the minimum image through the float32 reciprocal of the box)
-and the network's inputs (scaled by the float32 reciprocals of the input scales) are
-float32, each operation rounded as written (the inputs are then rounded to bfloat16 inside
-the network, so that decision is taken in float32 on both sides); the network is oracle/mlp.py's mixed mode; the forces
-and the update are float64; the positions are stored as float32 between steps.
+Precision: the separations, the network's inputs, the forces and the update are float64,
+written as defined (minimum image d - box rint(d / box), inputs (raw - mean) / scale);
+the network is oracle/mlp.py's mixed mode, which rounds its inputs to bfloat16 as the
+kernels do; the positions are stored as float32 between steps.  A kernel that forms the
+inputs in float32 may round an input lying within a few float32 units of a bfloat16
+rounding boundary to the other neighbour: ``input_flip_allowance`` bounds what that can
+change, from the network itself.
 
 Analysis: clusters (capsules in one cluster when their centres are at most `cutoff`
 apart, transitively; the criterion of the clustering section), cluster sizes, and the
@@ -31,15 +33,41 @@ F32 = np.float32
 
 
 def _separations(p, box, rows=None):
-    """d[i, j] = p_i - p_j (minimum image) and |d| for the capsules i of ``rows`` (all by
-    default), float32 as the operations are written."""
-    p = np.asarray(p, F32)
-    b = F32(box)
+    """d[i, j] = p_i - p_j (minimum image, float64) and |d| for the capsules i of ``rows``
+    (all by default)."""
+    p = np.asarray(p, F32).astype(np.float64)
+    b = float(F32(box))
     q = p if rows is None else p[rows]
     d = q[:, None, :] - p[None, :, :]
-    d = d - b * np.rint(d * (F32(1) / b))
+    d = d - b * np.rint(d / b)
     r = np.sqrt(d[..., 0] * d[..., 0] + d[..., 1] * d[..., 1])
     return d, r
+
+
+def _inputs(r, c):
+    """Network inputs (raw - mean) / scale of every pair, float64: the separation in radii
+    and the three fixed features."""
+    raw = np.empty(r.shape + (4,))
+    raw[..., 0] = r / float(F32(c["radius"]))
+    raw[..., 1:] = np.asarray(c["features"], F32).astype(np.float64)
+    xm = np.asarray(c["in_mean"], F32).astype(np.float64)
+    xs = np.asarray(c["in_scale"], F32).astype(np.float64)
+    return raw[..., 0], (raw - xm) / xs
+
+
+def _pair_forces(theta, p, c, rows):
+    """Pair force magnitudes f [m][n], separations d [m][n][2], |d| and the mask of
+    interacting pairs for the capsules of ``rows``."""
+    n = len(p)
+    d, r = _separations(p, c["box"], rows)
+    m = len(rows)
+    rr, x = _inputs(r, c)
+    y, _ = mlp.forward(theta, x.reshape(-1, 4), mixed=True)
+    f_net = y[:, 0].reshape(m, n) * float(c["out_scale"][0]) + float(c["out_mean"][0])
+    rc, rcut = float(F32(c["r_contact"])), float(F32(c["r_cut"]))
+    f = np.where(rr < rc, float(c["k_contact"]) * (rc - rr), f_net)
+    act = (r > 0) & (rr <= rcut) & (rows[:, None] != np.arange(n)[None, :])
+    return f, d, r, act
 
 
 def step(theta, p, c, rows=None):
@@ -50,23 +78,9 @@ def step(theta, p, c, rows=None):
     p = np.asarray(p, F32)
     n = len(p)
     rows = np.arange(n) if rows is None else np.asarray(rows)
-    d, r = _separations(p, c["box"], rows)
-    m = len(rows)
-    rr = r * (F32(1) / F32(c["radius"]))
-    xm = np.asarray(c["in_mean"], F32)
-    ixs = F32(1) / np.asarray(c["in_scale"], F32)
-    raw = np.empty((m, n, 4), F32)
-    raw[..., 0] = rr
-    raw[..., 1:] = np.asarray(c["features"], F32)
-    x = (raw - xm) * ixs
-    y, _ = mlp.forward(theta, x.reshape(-1, 4), mixed=True)
-    f_net = y[:, 0].reshape(m, n) * float(c["out_scale"][0]) + float(c["out_mean"][0])
-    rc, rcut = F32(c["r_contact"]), F32(c["r_cut"])
-    f = np.where(rr < rc, float(c["k_contact"]) * (float(rc) - rr.astype(np.float64)), f_net)
-    act = (r > 0) & (rr <= rcut) & (rows[:, None] != np.arange(n)[None, :])
-    d64, r64 = d.astype(np.float64), np.where(act, r, 1).astype(np.float64)
-    w = np.where(act, f / r64, 0.0)
-    force = np.einsum("ij,ijk->ik", w, d64)
+    f, d, r, act = _pair_forces(theta, p, c, rows)
+    w = np.where(act, f / np.where(act, r, 1.0), 0.0)
+    force = np.einsum("ij,ijk->ik", w, d)
     q = p[rows].astype(np.float64) + float(c["mobility"]) * force
     box = float(F32(c["box"]))
     q = q - box * np.floor(q / box)
@@ -77,21 +91,53 @@ def pair_forces_abs(theta, p, c, rows=None):
     """sum_j |f(r_ij)| per capsule (of ``rows``) over the interacting partners: the scale
     of the rounding error of the summed force."""
     p = np.asarray(p, F32)
+    rows = np.arange(len(p)) if rows is None else np.asarray(rows)
+    f, _, _, act = _pair_forces(theta, p, c, rows)
+    return np.where(act, np.abs(f), 0.0).sum(1)
+
+
+def input_flip_allowance(theta, p, c, rows=None, ulps=32):
+    """Per capsule (of ``rows``): the largest change of its summed pair force that rounding
+    the separation input to the other bfloat16 neighbour can make.  A pair qualifies when
+    its float64 input lies within ``ulps`` float32 units (of the larger of |rr| and
+    |mean|, divided by |scale|) of a point where the float32-then-bfloat16 rounding changes
+    value; its allowance is |f(x - t) - f(x + t)| of the network at the two ends, t that
+    distance.  The fixed features must not lie that close to a rounding point (checked:
+    ValueError), unless they equal their mean, which gives exactly 0 in any precision."""
+    p = np.asarray(p, F32)
     n = len(p)
     rows = np.arange(n) if rows is None else np.asarray(rows)
     _, r = _separations(p, c["box"], rows)
-    m = len(rows)
-    rr = r * (F32(1) / F32(c["radius"]))
-    raw = np.empty((m, n, 4), F32)
-    raw[..., 0] = rr
-    raw[..., 1:] = np.asarray(c["features"], F32)
-    x = (raw - np.asarray(c["in_mean"], F32)) * (F32(1) / np.asarray(c["in_scale"], F32))
-    y, _ = mlp.forward(theta, x.reshape(-1, 4), mixed=True)
-    f_net = y[:, 0].reshape(m, n) * float(c["out_scale"][0]) + float(c["out_mean"][0])
-    f = np.where(rr < F32(c["r_contact"]), float(c["k_contact"]) *
-                 (float(F32(c["r_contact"])) - rr.astype(np.float64)), f_net)
-    act = (r > 0) & (rr <= F32(c["r_cut"])) & (rows[:, None] != np.arange(n)[None, :])
-    return np.where(act, np.abs(f), 0.0).sum(1)
+    rr, x = _inputs(r, c)
+    xm = np.asarray(c["in_mean"], F32).astype(np.float64)
+    xs = np.abs(np.asarray(c["in_scale"], F32).astype(np.float64))
+    raw_abs = np.concatenate([[0.0], np.abs(np.asarray(c["features"], F32))])
+    feats = np.asarray(c["features"], F32).astype(np.float64)
+    for k in range(1, 4):
+        if feats[k - 1] == xm[k]:
+            continue                    # (raw - mean) is exactly 0 in any precision
+        t = ulps * 2.0 ** -24 * max(raw_abs[k], abs(xm[k])) / xs[k]
+        v = x[0, 0, k] if x.size else 0.0
+        if mlp.bf16(v - t) != mlp.bf16(v + t):
+            raise ValueError(f"fixed input {k} lies within float32 rounding of a bfloat16 boundary")
+    rc, rcut = float(F32(c["r_contact"])), float(F32(c["r_cut"]))
+    net = (r > 0) & (rr >= rc) & (rr <= rcut) & (rows[:, None] != np.arange(n)[None, :])
+    t0 = ulps * 2.0 ** -24 * np.maximum(rr, abs(xm[0])) / xs[0]
+    x0 = x[..., 0]
+    near = net & (mlp.bf16(x0 - t0) != mlp.bf16(x0 + t0))
+    out = np.zeros(len(rows))
+    if not near.any():
+        return out
+    xa = x[near].copy()
+    xb = x[near].copy()
+    xa[:, 0] -= t0[near]
+    xb[:, 0] += t0[near]
+    ya, _ = mlp.forward(theta, xa, mixed=True)
+    yb, _ = mlp.forward(theta, xb, mixed=True)
+    dy = np.abs(ya[:, 0] - yb[:, 0]) * abs(float(c["out_scale"][0]))
+    ii = np.nonzero(near)[0]
+    np.add.at(out, ii, dy)
+    return out
 
 
 def network_partners(p, c, rows=None):
@@ -101,8 +147,8 @@ def network_partners(p, c, rows=None):
     n = len(p)
     rows = np.arange(n) if rows is None else np.asarray(rows)
     _, r = _separations(p, c["box"], rows)
-    rr = r * (F32(1) / F32(c["radius"]))
-    act = (r > 0) & (rr <= F32(c["r_cut"])) & (rr >= F32(c["r_contact"])) & \
+    rr = r / float(F32(c["radius"]))
+    act = (r > 0) & (rr <= float(F32(c["r_cut"]))) & (rr >= float(F32(c["r_contact"]))) & \
         (rows[:, None] != np.arange(n)[None, :])
     return act.sum(1)
 

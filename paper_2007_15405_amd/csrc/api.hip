@@ -690,16 +690,18 @@ static void tiles_of(int tile, int nx, int ny, int *tx, int *ty) {
 
 // z planes per workgroup: enough workgroups to fill the chip (about 1024), at least 4
 // planes so the two extra halo planes stay a small share
-static int zchunk_of(const lbm_handle *h) {
-    if (h->zchunk > 0) return h->zchunk;
-    if (h->tile <= 0) return h->nz;
+static int zchunk_for(const lbm_handle *h, int tile, int zchunk) {
+    if (zchunk > 0) return zchunk;
+    if (tile <= 0) return h->nz;
     int tx, ty;
-    tiles_of(h->tile, h->nx, h->ny, &tx, &ty);
+    tiles_of(tile, h->nx, h->ny, &tx, &ty);
     const int tiles = tx * ty;
     const int chunks = (1024 + tiles - 1) / tiles;
     const int zc = (h->nz + chunks - 1) / chunks;
     return zc < 4 ? 4 : zc;
 }
+
+static int zchunk_of(const lbm_handle *h) { return zchunk_for(h, h->tile, h->zchunk); }
 
 extern "C" lbm_status lbm_set_launch(lbm_handle *h, int32_t tile, int32_t zchunk) {
     if (!h) return LBM_E_INVAL;
@@ -744,6 +746,106 @@ extern "C" lbm_status lbm_step(lbm_handle *h, int64_t n) {
         h->step++;
     }
     HIPCHK(h, hipGetLastError());
+    return LBM_OK;
+}
+
+// ------------------------------------------------------------------------------------
+// Launch-shape autotuner
+// ------------------------------------------------------------------------------------
+static void enqueue_fluid(const lbm_handle *h, const FluidArgs &a, int tile, int zc, hipStream_t st) {
+    switch (h->storage) {
+        case 0: launch_fluid_tiled<0>(a, tile, zc, st); break;
+        case 1: launch_fluid_tiled<1>(a, tile, zc, st); break;
+        default: launch_fluid_tiled<2>(a, tile, zc, st); break;
+    }
+}
+
+// z-chunk depths the tuners try (0: the default from the lattice size)
+static const int TUNE_ZC[] = {0, 8, 12, 16, 24, 32, 48};
+
+// tiles the tuner tries on a lattice of width nx: every fused shape that applies.  With
+// tau != 1 the pipelined and whole-row numbers run the fused kernel of 1..5 or 64 x 8, so
+// only 1..5 are distinct there.
+static bool tile_applies(int tile, int nx, bool keepf) {
+    if (tile < 1 || tile > TILE_ROWS || (keepf && tile >= 6)) return false;
+    if (tile == 11) return nx == 256;
+    if (tile == 12) return nx == 128;
+    if (tile == TILE_ROWS) return rows_fit(nx);
+    return true;
+}
+
+// mean duration of `reps` calls of `launch` on stream st (events e0, e1), after two untimed
+template <typename F>
+static hipError_t time_launches(hipStream_t st, int reps, hipEvent_t e0, hipEvent_t e1,
+                                F &&launch, double *ms) {
+    launch();
+    launch();
+    hipError_t e = hipEventRecord(e0, st);
+    for (int r = 0; r < reps && e == hipSuccess; ++r) launch();
+    if (e == hipSuccess) e = hipEventRecord(e1, st);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float t = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+    if (e == hipSuccess) e = hipGetLastError();
+    *ms = (double)t / reps;
+    return e;
+}
+
+struct EventPair {
+    hipEvent_t a = nullptr, b = nullptr;
+    hipError_t make() {
+        hipError_t e = hipEventCreate(&a);
+        return e == hipSuccess ? hipEventCreate(&b) : e;
+    }
+    ~EventPair() {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+};
+
+extern "C" lbm_status lbm_autotune(lbm_handle *h, int32_t reps, int32_t *tile, int32_t *zchunk,
+                                   double *fluid_ms) {
+    if (!h) return LBM_E_INVAL;
+    if (reps < 1 || reps > 1000) return fail(h, LBM_E_INVAL, "reps must be 1..1000");
+    if (!h->finalized) {
+        lbm_status s = finalize(h);
+        if (s != LBM_OK) return s;
+    }
+    HIPCHK(h, hipSetDevice(h->p.device));
+    int saved[ST_WORDS];
+    HIPCHK(h, hipMemcpyAsync(saved, h->status, sizeof saved, hipMemcpyDeviceToHost, h->st));
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    EventPair ev;
+    HIPCHK(h, ev.make());
+    const FluidArgs a = fluid_args(h, h->cur);
+    double best = INFINITY;
+    int bt = h->tile, bz = h->zchunk;
+    for (int t = 1; t <= TILE_ROWS; ++t) {
+        if (!tile_applies(t, h->nx, a.keepf)) continue;
+        int seen[sizeof TUNE_ZC / sizeof TUNE_ZC[0]], ns = 0;
+        for (int z : TUNE_ZC) {
+            const int zc = std::min(zchunk_for(h, t, z), h->nz);
+            if (std::find(seen, seen + ns, zc) != seen + ns) continue;
+            seen[ns++] = zc;
+            double ms = 0.0;
+            HIPCHK(h, time_launches(h->st, reps, ev.a, ev.b,
+                                    [&] { enqueue_fluid(h, a, t, zc, h->st); }, &ms));
+            if (ms < best) {
+                best = ms;
+                bt = t;
+                bz = zc;
+            }
+        }
+    }
+    // the timed launches wrote only the buffer the next step overwrites and the window
+    // outputs it recomputes; the status words (lost-reaction count) are put back
+    HIPCHK(h, hipMemcpyAsync(h->status, saved, sizeof saved, hipMemcpyHostToDevice, h->st));
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    h->tile = bt;
+    h->zchunk = bz;
+    if (tile) *tile = bt;
+    if (zchunk) *zchunk = bz;
+    if (fluid_ms) *fluid_ms = best;
     return LBM_OK;
 }
 
@@ -1025,6 +1127,71 @@ extern "C" lbm_status lbm_batch_step(lbm_batch *b, int64_t n) {
         }
     if (e == hipSuccess) e = hipGetLastError();
     if (e != hipSuccess) return bfail(b, LBM_E_DEVICE, std::string("batch step: ") + hipGetErrorString(e));
+    return LBM_OK;
+}
+
+extern "C" lbm_status lbm_batch_autotune(lbm_batch *b, int32_t reps, int32_t *tile,
+                                         int32_t *zchunk, double *fluid_ms) {
+    if (!b) return LBM_E_INVAL;
+    if (reps < 1 || reps > 1000) return bfail(b, LBM_E_INVAL, "reps must be 1..1000");
+    const int ng = (int)b->hs.size();
+    for (lbm_handle *h : b->hs)
+        if (!h->finalized) {
+            lbm_status s = finalize(h);
+            if (s != LBM_OK) return bfail(b, s, h->err);
+        }
+    auto dev = [&](hipError_t e) { return e == hipSuccess; };
+    std::vector<int> saved((size_t)ng * ST_WORDS);
+    if (!dev(hipStreamSynchronize(b->st))) return bfail(b, LBM_E_DEVICE, "stream synchronisation failed");
+    for (BatchPart &pt : b->parts)
+        if (!dev(hipStreamSynchronize(pt.st))) return bfail(b, LBM_E_DEVICE, "stream synchronisation failed");
+    for (int g = 0; g < ng; ++g)
+        if (!dev(hipMemcpy(&saved[(size_t)g * ST_WORDS], b->hs[g]->status, ST_WORDS * sizeof(int),
+                           hipMemcpyDeviceToHost)))
+            return bfail(b, LBM_E_DEVICE, "status copy failed");
+    EventPair ev;
+    if (!dev(ev.make())) return bfail(b, LBM_E_DEVICE, "event creation failed");
+    bool rows = true;
+    for (const lbm_handle *h : b->hs) rows = rows && rows_fit(h->nx);
+    const int tiles[] = {6, 7, 8, 9, 10, TILE_ROWS};
+    double best = INFINITY;
+    int bt = b->tile, bz = b->zchunk;
+    for (int t : tiles) {
+        if (t == TILE_ROWS && !rows) continue;
+        for (int z : TUNE_ZC) {
+            b->tile = t;
+            b->zchunk = z;
+            lbm_status s = batch_tables(b);   // per-part z-chunk and block tables of this shape
+            if (s != LBM_OK) return s;
+            double ms = 0.0;
+            hipError_t e = time_launches(b->st, reps, ev.a, ev.b, [&] {
+                for (BatchPart &pt : b->parts) {
+                    const int m = (int)pt.idx.size();
+                    switch (b->storage) {
+                        case 0: launch_fluid_multi<0>(pt.d_tab, pt.d_desc, m, pt.nblocks, t, b->st); break;
+                        case 1: launch_fluid_multi<1>(pt.d_tab, pt.d_desc, m, pt.nblocks, t, b->st); break;
+                        default: launch_fluid_multi<2>(pt.d_tab, pt.d_desc, m, pt.nblocks, t, b->st); break;
+                    }
+                }
+            }, &ms);
+            if (e != hipSuccess) return bfail(b, LBM_E_DEVICE, std::string("batch autotune: ") + hipGetErrorString(e));
+            if (ms < best) {
+                best = ms;
+                bt = t;
+                bz = z;
+            }
+        }
+    }
+    for (int g = 0; g < ng; ++g)
+        if (!dev(hipMemcpy(b->hs[g]->status, &saved[(size_t)g * ST_WORDS], ST_WORDS * sizeof(int),
+                           hipMemcpyHostToDevice)))
+            return bfail(b, LBM_E_DEVICE, "status copy failed");
+    b->tile = bt;
+    b->zchunk = bz;
+    b->dirty = true;
+    if (tile) *tile = bt;
+    if (zchunk) *zchunk = bz;
+    if (fluid_ms) *fluid_ms = best;
     return LBM_OK;
 }
 

@@ -95,6 +95,8 @@ SIGNATURES = {
     "lbm_set_profiling": (C.c_int, [H, C.c_int32]),
     "lbm_kernel_stats": (C.c_int, [H, C.POINTER(KernelStat), C.c_int32, C.POINTER(C.c_int32)]),
     "lbm_set_launch": (C.c_int, [H, C.c_int32, C.c_int32]),
+    "lbm_autotune": (C.c_int, [H, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                               C.POINTER(C.c_double)]),
     "lbm_bytes_per_site": (C.c_double, [H]),
     "lbm_fluid_sites": (C.c_int64, [H]),
     "lbm_last_error": (C.c_char_p, [H]),
@@ -102,6 +104,8 @@ SIGNATURES = {
     "lbm_batch_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(C.c_void_p)]),
     "lbm_batch_set_launch": (C.c_int, [H, C.c_int32, C.c_int32]),
     "lbm_batch_set_parts": (C.c_int, [H, C.c_int32]),
+    "lbm_batch_autotune": (C.c_int, [H, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                     C.POINTER(C.c_double)]),
     "lbm_batch_step": (C.c_int, [H, C.c_int64]),
     "lbm_batch_set_profiling": (C.c_int, [H, C.c_int32]),
     "lbm_batch_kernel_stats": (C.c_int, [H, C.POINTER(KernelStat), C.c_int32, C.POINTER(C.c_int32)]),
@@ -334,6 +338,13 @@ class Sim:
         """Fluid-step launch shape (tile 0: two-kernel variant; 1..5: fused kernel)."""
         self._check(self.L.lbm_set_launch(self.h, int(tile), int(zchunk)))
 
+    def autotune(self, reps: int = 10) -> dict:
+        """Time the fluid kernel in every applicable launch shape on the current state and
+        keep the fastest (``lbm_autotune``; the simulation is not advanced)."""
+        t, z, ms = C.c_int32(), C.c_int32(), C.c_double()
+        self._check(self.L.lbm_autotune(self.h, int(reps), C.byref(t), C.byref(z), C.byref(ms)))
+        return dict(tile=t.value, zchunk=z.value, fluid_ms=ms.value)
+
     @property
     def bytes_per_site(self) -> float:
         return self.L.lbm_bytes_per_site(self.h)
@@ -384,6 +395,13 @@ class Batch:
 
     def step(self, n: int = 1):
         self._check(self.L.lbm_batch_step(self.b, int(n)))
+
+    def autotune(self, reps: int = 10) -> dict:
+        """``lbm_batch_autotune``: the fastest batched fluid launch shape (not advancing)."""
+        t, z, ms = C.c_int32(), C.c_int32(), C.c_double()
+        self._check(self.L.lbm_batch_autotune(self.b, int(reps), C.byref(t), C.byref(z),
+                                              C.byref(ms)))
+        return dict(tile=t.value, zchunk=z.value, fluid_ms=ms.value)
 
     def sync(self):
         for s in self.sims:

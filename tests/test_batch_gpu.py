@@ -13,24 +13,14 @@ several lattices advanced by one fluid launch (lbm_batch_*).
   few multiply-adds differently in it (about one ulp): densities agree to 1e-6 relative,
   as between the launch shapes of the fluid kernel, and nodes to 1e-5.
 """
-import sys
-
 import numpy as np
 import pytest
 
 import oracle
 import synth
+from parity_tools import rel_l2, say, site_check
 
 pytestmark = pytest.mark.gpu
-
-
-def say(*a):
-    print(*a, flush=True)
-    sys.stdout.flush()
-
-
-def rel_l2(a, b):
-    return [float(np.linalg.norm(a[c] - b[c]) / np.linalg.norm(b[c])) for c in range(2)]
 
 
 def _sim(cfg, **kw):
@@ -81,9 +71,11 @@ def test_stacked_slabs_match_the_oracle_box_by_box(tile):
         cfg = box_cfg(s)
         o = oracle.Oracle(cfg)
         o.step(steps)
-        e = rel_l2(rho[:, s], o.rho())
+        ro = o.rho()
+        e = rel_l2(rho[:, s], ro)
         say("slab", s, "rel-L2 vs oracle", e)
         assert max(e) <= 1e-5
+        site_check(rho[:, s], ro, 1e-5, f"slab {s} tile {tile}")
         so = o.summary()
         assert np.all(np.abs(ob["slab_mass"][s] - so["mass"]) / so["mass"] < 1e-5)
         mo, mg = o.meniscus(), ob["meniscus"][s]
@@ -235,6 +227,76 @@ def test_full_batch_workload_sampled_instances():
                 1e-3 * max(np.linalg.norm(co["f_capillary"]), 1e-3)
         assert ob["summary"]["lost_reaction"] == 0
     bt.close()
+
+
+BENCH_STEPS = 200
+
+
+@pytest.fixture(scope="module")
+def batch_reference():
+    """The oracle running the first and the last instance of the batched workload as boxes
+    of their own for BENCH_STEPS steps."""
+    inst = synth.batch_instances()
+    ref = {}
+    for k in (0, len(inst) - 1):
+        i = inst[k]
+        cfg = synth.workload("c2", nx=i["nx"], ny=i["ny"], nz=i["nz"],
+                             film_height=i["film_height"], capsules=i["capsules"])
+        say("oracle: batch instance", k, (i["nx"], i["ny"], i["nz"]), BENCH_STEPS, "steps")
+        o = oracle.Oracle(cfg)
+        o.step(BENCH_STEPS)
+        ref[k] = dict(rho=o.rho(), meniscus=o.meniscus(), caps=[o.capsule(j) for j in range(2)],
+                      mass=o.summary()["mass"])
+        o.close()
+    return inst, ref
+
+
+@pytest.mark.parametrize("launch", [(13, 16, 3), "tuned"])
+def test_batch_instances_in_benchmark_launch_match_the_oracle(batch_reference, launch):
+    """The batched workload in the launch shape behind the batched figures and the
+    surrogate's training data (whole rows of the box width, z-chunks of 16 planes, three
+    parts), and in the shape the library's autotuner picks: 200 steps, then the first and
+    the last instance against the oracle, every site checked."""
+    from paper_2007_15405_amd import Batch
+    inst, ref = batch_reference
+    groups = synth.batch_groups(inst)
+    sims = [_sim(g, meshes=synth.capsule_meshes(g["capsules"])) for g in groups]
+    if launch == "tuned":
+        bt = Batch(sims, parts=1)
+        bt.step(1)
+        t = bt.autotune(3)
+        say("batch autotuner choice:", t)
+        bt.step(BENCH_STEPS - 1)
+    else:
+        bt = Batch(sims, tile=launch[0], zchunk=launch[1], parts=launch[2])
+        bt.step(BENCH_STEPS)
+    bt.sync()
+    for k, r in ref.items():
+        gi = next(j for j, g in enumerate(groups) if k in g["instances"])
+        g, sim = groups[gi], sims[gi]
+        s = g["instances"].index(k)
+        lz = g["slab_nz"]
+        ob = sim.observables(rho=True, meniscus=True)
+        rho = ob["rho"].reshape(2, -1, lz, g["ny"], g["nx"])[:, s]
+        lab = sim.labels().reshape(-1, lz, g["ny"], g["nx"])[s]
+        e = rel_l2(rho, r["rho"])
+        say("instance", k, "launch", launch, "rel-L2", e)
+        assert max(e) <= 1e-5
+        site_check(rho, r["rho"], 1e-5, f"batch instance {k} launch {launch}", lab)
+        assert np.all(np.abs(ob["slab_mass"][s] - r["mass"]) / r["mass"] < 1e-5)
+        men = ob["meniscus"].reshape(-1, g["ny"], g["nx"])[s]
+        assert np.array_equal(np.isnan(men), np.isnan(r["meniscus"]))
+        ok = ~np.isnan(men)
+        assert np.abs(men[ok] - r["meniscus"][ok]).max() <= 1e-3
+        for j in range(2):
+            cg, co = ob["capsules"][2 * s + j], r["caps"][j]
+            assert np.abs(cg["centroid"] - np.array([0, 0, s * lz]) - co["centroid"]).max() <= 1e-4
+            for f in ("f_capillary", "f_anchor"):
+                assert np.linalg.norm(cg[f] - co[f]) <= 1e-3 * max(np.linalg.norm(co[f]), 1e-3)
+        assert ob["summary"]["lost_reaction"] == 0
+    bt.close()
+    for x in sims:
+        x.close()
 
 
 def test_checkpoint_resume_with_slabs_is_bitwise(tmp_path):
