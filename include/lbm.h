@@ -352,6 +352,22 @@ typedef struct {
 lbm_status lbm_surrogate_cluster(lbm_surrogate *s, int32_t n, float *xy, int32_t steps,
                                  const lbm_cluster_params *cp);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): lbm_surrogate_cluster without any
+ * allocation.  xy_device is a caller-owned DEVICE buffer [n][2] float of positions, in/out
+ * (advanced in place by `steps` steps, wrapped into [0, box)).  Everything else it needs
+ * (the second position buffer of the step's ping-pong and the network in operand layout,
+ * about 161 kB) lives in a file-scope device array of the library, one per GPU, held until
+ * the process ends and shared by every call on that GPU: calls that overlap on one GPU
+ * race, and each call rewrites what it reads of it.  The arithmetic is that of
+ * lbm_surrogate_cluster (same kernels), so the results are identical.  Runs on the
+ * surrogate's stream and synchronises it.  Errors: as lbm_surrogate_cluster, and
+ * LBM_E_INVAL for n > LBM_CLUSTER_NOALLOC_MAX or a NULL buffer; LBM_E_DEVICE if a launch or
+ * the look-up of the array's device address fails (positions then undefined). */
+#define LBM_CLUSTER_NOALLOC_MAX 16384
+lbm_status lbm_surrogate_cluster_noalloc(lbm_surrogate *s, int32_t n, float *xy_device,
+                                         int32_t steps, const lbm_cluster_params *cp);
+
 const char *lbm_surrogate_last_error(const lbm_surrogate *s);
 void lbm_surrogate_destroy(lbm_surrogate *s);
 

@@ -15,6 +15,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -366,6 +367,7 @@ __global__ void __launch_bounds__(CL_THREADS, 3) k_cluster_step(const float2 *__
 struct lbm_surrogate {
     std::string err;
     hipStream_t st = nullptr;
+    int dev = 0;                         // device of the stream and the buffers
     int cap = 0, n = 0;
     int64_t t = 0;                       // Adam steps taken
     float *th = nullptr, *m = nullptr, *v = nullptr, *g = nullptr;
@@ -456,7 +458,8 @@ extern "C" lbm_status lbm_surrogate_create(int32_t max_samples, const float *the
     if (!s) return LBM_E_NOMEM;
     s->cap = max_samples;
     const size_t c = (size_t)max_samples;
-    bool ok = hipStreamCreateWithFlags(&s->st, hipStreamNonBlocking) == hipSuccess;
+    bool ok = hipGetDevice(&s->dev) == hipSuccess &&
+              hipStreamCreateWithFlags(&s->st, hipStreamNonBlocking) == hipSuccess;
     float **bufs[] = {&s->th, &s->m, &s->v, &s->g};
     for (float **b : bufs) ok = ok && hipMalloc(b, NPAR * sizeof(float)) == hipSuccess;
     ok = ok && hipMalloc(&s->y, c * NOUT * sizeof(float)) == hipSuccess &&
@@ -607,6 +610,94 @@ extern "C" lbm_status lbm_surrogate_cluster(lbm_surrogate *s, int32_t n, float *
         if (b) (void)hipFree(b);
     if (frag) (void)hipFree(frag);
     if (btile) (void)hipFree(btile);
+    return ok ? LBM_OK : sfail(s, LBM_E_DEVICE, "cluster evolution failed");
+}
+
+// ------------------------------------------------------------------------------------
+// Cluster evolution without allocation
+// ------------------------------------------------------------------------------------
+// File-scope scratch of the allocation-free entry point, one copy per device: the second
+// position buffer of the step's ping-pong (LBM_CLUSTER_NOALLOC_MAX float2) and the network
+// in operand layout (bfloat16 fragments and bias tiles), each part 256-byte aligned.
+constexpr size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+constexpr size_t SCR_POS = 0;
+constexpr size_t SCR_FRAG = align256(SCR_POS + (size_t)LBM_CLUSTER_NOALLOC_MAX * sizeof(float2));
+constexpr size_t SCR_BTILE = align256(SCR_FRAG + (size_t)CL_FRAGS * 64 * sizeof(uint2));
+constexpr size_t SCR_BYTES = align256(SCR_BTILE + (size_t)CL_BTILES * 64 * sizeof(float4));
+
+static __device__ __align__(256) unsigned char scratch[SCR_BYTES];
+
+// device address of `scratch` on each device, taken once per device with that device
+// current (the host-side name of the array is not a device address)
+constexpr int SCR_MAX_DEVICES = 64;
+static std::mutex g_scr_mutex;
+static void *g_scr_ptr[SCR_MAX_DEVICES] = {};
+
+static hipError_t scratch_of(int dev, unsigned char **out) {
+    if (dev < 0 || dev >= SCR_MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scr_mutex);
+    if (!g_scr_ptr[dev]) {
+        void *ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scr_ptr[dev] = ptr;
+    }
+    *out = static_cast<unsigned char *>(g_scr_ptr[dev]);
+    return hipSuccess;
+}
+
+extern "C" lbm_status lbm_surrogate_cluster_noalloc(lbm_surrogate *s, int32_t n, float *xy_device,
+                                                    int32_t steps, const lbm_cluster_params *cp) {
+    if (!s) return LBM_E_INVAL;
+    if (!xy_device || !cp || n < 2 || steps < 0)
+        return sfail(s, LBM_E_INVAL, "need n >= 2 capsules, device positions and parameters");
+    if (n > LBM_CLUSTER_NOALLOC_MAX)
+        return sfail(s, LBM_E_INVAL, "n exceeds LBM_CLUSTER_NOALLOC_MAX (the scratch holds "
+                                     "that many positions)");
+    if (!(cp->box > 0.f) || !(cp->radius > 0.f) || !(cp->r_cut > cp->r_contact) ||
+        !(cp->r_contact >= 0.f) || !(cp->k_contact >= 0.f) || !std::isfinite(cp->mobility))
+        return sfail(s, LBM_E_INVAL, "invalid cluster parameters");
+    for (int k = 0; k < 4; ++k)
+        if (!(cp->in_scale[k] > 0.f)) return sfail(s, LBM_E_INVAL, "input scales must be > 0");
+    if (!(2.0 * cp->r_cut * cp->radius < cp->box))
+        return sfail(s, LBM_E_INVAL, "box must exceed twice the cutoff distance r_cut * radius");
+    // the scratch address is taken, and the kernels run, with the surrogate's device current;
+    // the caller's current device is restored on return
+    int prev = 0;
+    if (hipGetDevice(&prev) != hipSuccess || hipSetDevice(s->dev) != hipSuccess)
+        return sfail(s, LBM_E_DEVICE, "hipSetDevice failed");
+    struct Restore {
+        int d;
+        ~Restore() { (void)hipSetDevice(d); }
+    } restore{prev};
+    unsigned char *scr = nullptr;
+    if (scratch_of(s->dev, &scr) != hipSuccess)
+        return sfail(s, LBM_E_DEVICE, "hipGetSymbolAddress of the scratch array failed");
+    ClusterArgs c{};
+    for (int k = 0; k < 4; ++k) { c.xm[k] = cp->in_mean[k]; c.inv_xs[k] = 1.0f / cp->in_scale[k]; }
+    c.ym = cp->out_mean[0];
+    c.ys = cp->out_scale[0];
+    c.feat[0] = cp->log10_ks; c.feat[1] = cp->film; c.feat[2] = cp->angle;
+    c.box = cp->box; c.inv_box = 1.0f / cp->box; c.inv_radius = 1.0f / cp->radius;
+    c.r_contact = cp->r_contact; c.r_cut = cp->r_cut; c.k_contact = cp->k_contact;
+    c.mobility = cp->mobility; c.n = n;
+    float2 *p[2] = {reinterpret_cast<float2 *>(xy_device), reinterpret_cast<float2 *>(scr + SCR_POS)};
+    uint2 *frag = reinterpret_cast<uint2 *>(scr + SCR_FRAG);
+    float4 *btile = reinterpret_cast<float4 *>(scr + SCR_BTILE);
+    // the positions and the network fragments in the scratch are written before they are
+    // read in every call, so nothing of an earlier call's contents is used
+    if (steps > 0)
+        hipLaunchKernelGGL(k_pack_cluster_net, dim3(1), dim3(64), 0, s->st, s->th, frag, btile);
+    int cur = 0;
+    for (int t = 0; t < steps; ++t) {
+        hipLaunchKernelGGL(k_cluster_step, dim3(n), dim3(CL_THREADS), 0, s->st, p[cur], p[1 - cur],
+                           frag, btile, c);
+        cur = 1 - cur;
+    }
+    bool ok = hipGetLastError() == hipSuccess;
+    if (ok && cur == 1)         // an odd step count leaves the result in the scratch
+        ok = hipMemcpyAsync(p[0], p[1], n * sizeof(float2), hipMemcpyDeviceToDevice, s->st) == hipSuccess;
+    ok = ok && hipStreamSynchronize(s->st) == hipSuccess;
     return ok ? LBM_OK : sfail(s, LBM_E_DEVICE, "cluster evolution failed");
 }
 

@@ -120,6 +120,8 @@ SIGNATURES = {
     "lbm_surrogate_params": (C.c_int, [H, C.POINTER(C.c_float)]),
     "lbm_surrogate_cluster": (C.c_int, [H, C.c_int32, C.POINTER(C.c_float), C.c_int32,
                                         C.POINTER(ClusterParams)]),
+    "lbm_surrogate_cluster_noalloc": (C.c_int, [H, C.c_int32, C.c_void_p, C.c_int32,
+                                                C.POINTER(ClusterParams)]),
     "lbm_surrogate_last_error": (C.c_char_p, [H]),
     "lbm_surrogate_destroy": (None, [H]),
 }
@@ -437,6 +439,7 @@ class Batch:
 
 
 SURROGATE_PARAMS = 8770
+CLUSTER_NOALLOC_MAX = 16384      # LBM_CLUSTER_NOALLOC_MAX
 
 
 def _fp(a):
@@ -513,6 +516,27 @@ class Surrogate:
         self._check(self.L.lbm_surrogate_cluster(self.s, len(p), _fp(p), int(steps),
                                                  C.byref(cp)))
         return p
+
+    def cluster_noalloc(self, xy_device, steps: int, *, box, radius, features, in_mean,
+                        in_scale, out_mean, out_scale, r_contact, r_cut, k_contact,
+                        mobility):
+        """``lbm_surrogate_cluster_noalloc``: advance a device tensor of positions [n][2]
+        (float32, contiguous, on the GPU) in place, with no device allocation."""
+        import torch
+        if xy_device.dtype != torch.float32 or xy_device.dim() != 2 or xy_device.shape[1] != 2 \
+                or not xy_device.is_contiguous() or not xy_device.is_cuda:
+            raise ValueError("xy_device must be a contiguous float32 [n][2] GPU tensor")
+        cp = ClusterParams(box=box, radius=radius, log10_ks=features[0], film=features[1],
+                           angle=features[2], r_contact=r_contact, r_cut=r_cut,
+                           k_contact=k_contact, mobility=mobility)
+        cp.in_mean[:] = [float(v) for v in in_mean]
+        cp.in_scale[:] = [float(v) for v in in_scale]
+        cp.out_mean[:] = [float(v) for v in out_mean]
+        cp.out_scale[:] = [float(v) for v in out_scale]
+        self._check(self.L.lbm_surrogate_cluster_noalloc(
+            self.s, int(xy_device.shape[0]), C.c_void_p(xy_device.data_ptr()), int(steps),
+            C.byref(cp)))
+        return xy_device
 
     def close(self):
         if getattr(self, "s", None):
