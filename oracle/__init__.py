@@ -26,6 +26,7 @@ class Params(C.Structure):
         ("film_height", C.c_double), ("rho_maj", C.c_double), ("rho_min", C.c_double),
         ("rho_iface", C.c_double), ("init_rho_array", C.POINTER(C.c_double)),
         ("hertz_xi", C.c_double), ("hertz_delta0", C.c_double), ("plane_dz", C.c_double),
+        ("coupling", C.c_int32), ("node_mass", C.c_double),
     ]
 
 
@@ -37,14 +38,15 @@ class CapsuleParams(C.Structure):
 class CapsuleObs(C.Structure):
     _fields_ = [("centroid", C.c_double * 3), ("volume", C.c_double),
                 ("f_anchor", C.c_double * 3), ("f_capillary", C.c_double * 3),
-                ("f_hertz", C.c_double * 3)]
+                ("f_hertz", C.c_double * 3), ("f_fluid", C.c_double * 3)]
 
 
 class Summary(C.Structure):
     _fields_ = [("mass", C.c_double * 2), ("momentum", C.c_double * 3),
                 ("pending", C.c_double * 3), ("step", C.c_int64),
                 ("lost_reaction", C.c_int64), ("n_capsules", C.c_int32),
-                ("unstable", C.c_int32)]
+                ("unstable", C.c_int32), ("node_momentum", C.c_double * 3),
+                ("lost_links", C.c_int64), ("links", C.c_int64)]
 
 
 _LIBS = {}
@@ -105,6 +107,8 @@ def lib(precision: str = "f64"):
     L.lbmref_volume_force.argtypes = [C.c_int32, C.POINTER(C.c_double), C.c_int32,
                                       C.POINTER(C.c_int32), C.c_double, C.c_double,
                                       C.POINTER(C.c_double)]
+    L.lbmref_miss_distance.restype = C.c_double
+    L.lbmref_miss_distance.argtypes = [C.POINTER(C.c_double)] * 5
     L.lbmref_hertz.restype = C.c_double
     L.lbmref_hertz.argtypes = [C.c_double, C.c_double, C.c_double]
     L.lbmref_column_labels.argtypes = [C.c_int32, C.POINTER(C.c_double), C.c_int32,
@@ -187,6 +191,12 @@ def hertz(d, xi=1.5, delta0=1.5):
     return lib().lbmref_hertz(float(d), float(xi), float(delta0))
 
 
+def miss_distance(p0, p1, a, b, c):
+    """Miss distance of the segment p0 -> p1 from triangle (a, b, c) (0: they meet)."""
+    v = [np.ascontiguousarray(x, dtype=np.float64) for x in (p0, p1, a, b, c)]
+    return lib().lbmref_miss_distance(*[_dp(x) for x in v])
+
+
 def column_labels(nodes, tris, origin, dims):
     x = np.ascontiguousarray(nodes, dtype=np.float64); t = np.ascontiguousarray(tris, np.int32)
     out = np.zeros(int(np.prod(dims)), np.uint8)
@@ -221,6 +231,8 @@ def make_params(cfg: dict, n_threads: int = 0):
         assert keep.shape == (2, cfg["nz"], cfg["ny"], cfg["nx"])
         p.init_rho_array = _dp(keep)
     p.hertz_xi, p.hertz_delta0, p.plane_dz = cfg["hertz_xi"], cfg["hertz_delta0"], cfg["plane_dz"]
+    p.coupling = int(cfg.get("coupling", 0))
+    p.node_mass = float(cfg.get("node_mass", 25.0))
     return p, keep
 
 
@@ -289,14 +301,16 @@ class Oracle:
             raise IndexError(k)
         return dict(centroid=np.array(o.centroid), volume=o.volume,
                     f_anchor=np.array(o.f_anchor), f_capillary=np.array(o.f_capillary),
-                    f_hertz=np.array(o.f_hertz))
+                    f_hertz=np.array(o.f_hertz), f_fluid=np.array(o.f_fluid))
 
     def summary(self) -> dict:
         s = Summary()
         self.L.lbmref_get_summary(self.h, C.byref(s))
         return dict(mass=np.array(s.mass), momentum=np.array(s.momentum),
                     pending=np.array(s.pending), step=s.step, lost_reaction=s.lost_reaction,
-                    n_capsules=s.n_capsules, unstable=s.unstable)
+                    n_capsules=s.n_capsules, unstable=s.unstable,
+                    node_momentum=np.array(s.node_momentum), lost_links=s.lost_links,
+                    links=s.links)
 
     def close(self):
         if getattr(self, "h", None):

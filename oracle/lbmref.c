@@ -1,6 +1,7 @@
 /*
  * lbmref.c -- CPU oracle: two-component Shan-Chen D3Q19 lattice Boltzmann fluid with
- * triangulated Skalak capsules coupled by an immersed boundary.
+ * triangulated Skalak capsules coupled by an immersed boundary, or by half-way
+ * bounce-back on the membrane with momentum exchange (the coupling of Section 3.1).
  *
  * TEST INFRASTRUCTURE ONLY: used by the tests, the smoke check and the CPU baseline of
  * the benchmark.  It is deliberately plain and slow: one loop per step of the method,
@@ -22,6 +23,17 @@
  *      Shan-Chen shifted velocity
  *   7. interpolation of the physical velocity to the nodes, node advection, and
  *      gathering of the reaction onto the nodes (applied in the next step)
+ *
+ * With the bounce-back coupling of Section 3.1 (coupling = 1) steps 3 and 7 become:
+ *   3'. every lattice link between a site inside capsule k and a site outside it finds
+ *      the membrane triangle it crosses; half-way bounce-back on that moving triangle
+ *      (Ladd's moving-wall term with the mean velocity of its three nodes) is applied
+ *      to the post-collision populations, and the exchanged momentum goes a third to
+ *      each of the triangle's nodes (the homogeneous element-to-node weighting)
+ *   7'. the Shan-Chen force across each link is returned to its triangle the same way;
+ *      the nodes (mass node_mass, 25 rho0 in Section 3.2) take the membrane forces, the
+ *      exchanged momentum spread over this and the next step (against staggered
+ *      momenta) and the reaction: v += F / m, x += v
  *
  * Build: gcc -O2 -fopenmp -ffp-contract=off -fPIC -shared lbmref.c -lm
  *        (-DLBMREF_REAL=float for the FP32 diagnostic build).
@@ -80,7 +92,20 @@ typedef struct {
     double v0, c0[3];
     double vol, cen[3];        /* at X^n, computed at the start of the step */
     double f_anchor[3];        /* sum of anchor node forces of the last step */
+    /* bounce-back coupling */
+    real *V;        /* [nn][3] node velocities                               */
+    real *Pex;      /* [nn][3] momentum exchanged with the fluid this step   */
+    real *Pprev;    /* [nn][3] momentum exchanged in the previous step       */
+    real *Rsc;      /* [nn][3] Shan-Chen reaction of this step's links       */
+    double f_fluid[3];         /* fluid force on the membrane of the last step */
 } cap_t;
+
+/* a bounce-back link: site a inside capsule k, direction q, b = a + e_q outside it;
+ * tri: the membrane triangle it crosses (-1: none found) */
+typedef struct {
+    long a, b;
+    int q, k, tri;
+} link_t;
 
 struct lbmref_handle {
     lbmref_params p;
@@ -96,6 +121,9 @@ struct lbmref_handle {
     cap_t *cap;
     int64_t step, lost;
     int unstable;
+    link_t *links;     /* bounce-back links of the current step */
+    long nlinks, links_cap;
+    int64_t lost_links;
 };
 
 static inline int wrapi(int a, int n) { a %= n; return a < 0 ? a + n : a; }
@@ -573,6 +601,8 @@ lbmref_handle *lbmref_create(const lbmref_params *p) {
     if (!(p->rho0 > 0)) { set_err("rho0 must be positive"); return NULL; }
     if (p->init_mode < 0 || p->init_mode > 2) { set_err("invalid init_mode"); return NULL; }
     if (p->init_mode == 2 && !p->init_rho_array) { set_err("init_rho_array missing"); return NULL; }
+    if (p->coupling < 0 || p->coupling > 1) { set_err("invalid coupling"); return NULL; }
+    if (p->coupling == 1 && !(p->node_mass > 0)) { set_err("node_mass must be positive"); return NULL; }
     lbmref_handle *h = (lbmref_handle *)calloc(1, sizeof *h);
     h->p = *p;
     h->p.init_rho_array = NULL;
@@ -642,6 +672,10 @@ int lbmref_add_capsule(lbmref_handle *h, const lbmref_capsule_params *cp, int32_
     c->R = (real *)calloc(3 * nn, sizeof(real));
     c->F = (real *)calloc(3 * nn, sizeof(real));
     c->Fh = (real *)calloc(3 * nn, sizeof(real));
+    c->V = (real *)calloc(3 * nn, sizeof(real));
+    c->Pex = (real *)calloc(3 * nn, sizeof(real));
+    c->Pprev = (real *)calloc(3 * nn, sizeof(real));
+    c->Rsc = (real *)calloc(3 * nn, sizeof(real));
     c->tri = (int32_t *)malloc(sizeof(int32_t) * 3 * nt);
     c->minv = (double *)malloc(sizeof(double) * 4 * nt);
     c->a0 = (double *)malloc(sizeof(double) * nt);
@@ -981,7 +1015,9 @@ static void fluid_step(lbmref_handle *h) {
                         rt > 0 ? (jm[0][d] + jm[1][d] + (F[0][d] + F[1][d]) / 2) / rt : 0;
                     h->react[d * N + s] = rx[d];
                 }
-                if ((rx[0] != 0 || rx[1] != 0 || rx[2] != 0) && !(h->fibm[3 * N + s] > 0)) lost++;
+                if (h->p.coupling == 0 && (rx[0] != 0 || rx[1] != 0 || rx[2] != 0) &&
+                    !(h->fibm[3 * N + s] > 0))
+                    lost++;
             }
     }
     real *t = h->f; h->f = h->fn; h->fn = t;
@@ -989,14 +1025,227 @@ static void fluid_step(lbmref_handle *h) {
     if (bad) h->unstable = 1;
 }
 
+/* ----------------------------------------------------------------------------------- */
+/* Half-way bounce-back on the membrane with Ladd's momentum exchange (Section 3.1)     */
+/* ----------------------------------------------------------------------------------- */
+
+/* six times the signed volume of the tetrahedron (a, b, c, d) */
+static double orient3(const double *a, const double *b, const double *c, const double *d) {
+    double ab[3], ac[3], ad[3];
+    for (int k = 0; k < 3; ++k) {
+        ab[k] = b[k] - a[k];
+        ac[k] = c[k] - a[k];
+        ad[k] = d[k] - a[k];
+    }
+    return ab[0] * (ac[1] * ad[2] - ac[2] * ad[1]) + ab[1] * (ac[2] * ad[0] - ac[0] * ad[2]) +
+           ab[2] * (ac[0] * ad[1] - ac[1] * ad[0]);
+}
+
+double lbmref_miss_distance(const double p0[3], const double p1[3], const double a[3],
+                            const double b[3], const double c[3]) {
+    /* the line crosses the triangle's plane at parameter t (signed distances of the ends) */
+    double s0 = orient3(a, b, c, p0), s1 = orient3(a, b, c, p1);
+    double den = s0 - s1;
+    if (den == 0.0) return INFINITY;
+    double t = s0 / den;
+    /* barycentric coordinates of that crossing: the line's orientation against each edge */
+    double wa = orient3(p0, p1, b, c), wb = orient3(p0, p1, c, a), wc = orient3(p0, p1, a, b);
+    double sum = wa + wb + wc;
+    if (sum == 0.0) return INFINITY;
+    double u = wa / sum, v = wb / sum, w = wc / sum;
+    double d = 0.0;
+    if (-u > d) d = -u;
+    if (-v > d) d = -v;
+    if (-w > d) d = -w;
+    if (-t > d) d = -t;
+    if (t - 1.0 > d) d = t - 1.0;
+    return d;
+}
+
+/* nearest periodic image of lattice coordinate i to the unwrapped position x */
+static int image_of(int i, double x, int n, int periodic) {
+    return periodic ? i + n * (int)floor((x - i) / n + 0.5) : i;
+}
+
+/* The triangle of capsule c crossed by the segment p0 -> p1 (capsule frame): among the
+ * triangles whose bounding box (FP32-rounded nodes) meets the segment's closed bounding
+ * box, the one of least miss distance, the lowest index on ties; -1 if none qualifies. */
+static int link_triangle(const cap_t *c, const double p0[3], const double p1[3]) {
+    double lo[3], hi[3];
+    for (int d = 0; d < 3; ++d) {
+        lo[d] = p0[d] < p1[d] ? p0[d] : p1[d];
+        hi[d] = p0[d] < p1[d] ? p1[d] : p0[d];
+    }
+    int best = -1;
+    double bd = INFINITY;
+    for (int t = 0; t < c->nt; ++t) {
+        double v[3][3];
+        int ok = 1;
+        for (int m = 0; m < 3; ++m)
+            for (int d = 0; d < 3; ++d) v[m][d] = (double)(float)c->x[3 * c->tri[3 * t + m] + d];
+        for (int d = 0; d < 3 && ok; ++d) {
+            double tl = v[0][d], th = v[0][d];
+            for (int m = 1; m < 3; ++m) {
+                if (v[m][d] < tl) tl = v[m][d];
+                if (v[m][d] > th) th = v[m][d];
+            }
+            if (tl > hi[d] || th < lo[d]) ok = 0;
+        }
+        if (!ok) continue;
+        double md = lbmref_miss_distance(p0, p1, v[0], v[1], v[2]);
+        if (md < bd) { bd = md; best = t; }
+    }
+    return best;
+}
+
+/* Find this step's links: every site a inside capsule k (label k+1) and direction q whose
+ * neighbour b = a + e_q is fluid of another side (exterior, or a capsule of higher
+ * index: the lower index owns a link between two capsules). */
+static void find_links(lbmref_handle *h) {
+    h->nlinks = 0;
+    for (int k = 0; k < h->ncap; ++k) {
+        cap_t *c = &h->cap[k];
+        double cen[3];
+        centroid_of(c->nn, c->x, cen);
+        for (int kk = 0; kk < h->nz; ++kk)
+            for (int jj = 0; jj < h->ny; ++jj)
+                for (int ii = 0; ii < h->nx; ++ii) {
+                    long a = sidx(h, ii, jj, kk);
+                    if (h->label[a] != k + 1) continue;
+                    for (int q = 1; q < 19; ++q) {
+                        int bi = wrapi(ii + EV[q][0], h->nx), bj = wrapi(jj + EV[q][1], h->ny),
+                            bk = wrapi(kk + EV[q][2], h->nz);
+                        long b = sidx(h, bi, bj, bk);
+                        int lb = h->label[b];
+                        if (lb == k + 1 || lb == LABEL_SOLID || (lb != 0 && lb < k + 1)) continue;
+                        double p0[3] = {image_of(ii, cen[0], h->nx, 1),
+                                        image_of(jj, cen[1], h->ny, 1),
+                                        image_of(kk, cen[2], h->nz, !h->p.wall_z0)};
+                        double p1[3] = {p0[0] + EV[q][0], p0[1] + EV[q][1], p0[2] + EV[q][2]};
+                        if (h->nlinks == h->links_cap) {
+                            h->links_cap = h->links_cap ? 2 * h->links_cap : 4096;
+                            h->links = (link_t *)realloc(h->links, sizeof(link_t) * h->links_cap);
+                        }
+                        link_t *L = &h->links[h->nlinks++];
+                        L->a = a; L->b = b; L->q = q; L->k = k;
+                        L->tri = link_triangle(c, p0, p1);
+                    }
+                }
+    }
+}
+
+/* Bounce-back of every link on the post-collision populations, before streaming: the
+ * population of a towards b is replaced by b's population towards a reflected by the
+ * membrane, and vice versa, each with the moving-wall term delta = 2 w_q rho u_b.e_q / c_s^2
+ * (rho: the mean density of the component over the link's two sites, u_b: the mean velocity
+ * of the crossed triangle's nodes), so that plain pull streaming delivers
+ * f_q(b) = f*_qbar(b) + delta and f_qbar(a) = f*_q(a) - delta.  The momentum given to the
+ * membrane, (2 f*_q(a) - 2 f*_qbar(b) - 2 delta) e_q summed over the components, goes to the
+ * crossed triangle, a third to each of its nodes. */
+static void bounce_back(lbmref_handle *h) {
+    long N = h->N;
+    for (int k = 0; k < h->ncap; ++k) memset(h->cap[k].Pex, 0, sizeof(real) * 3 * h->cap[k].nn);
+    /* densities of the populations before any link is changed */
+    real *rho = (real *)malloc(sizeof(real) * 2 * N);
+    for (int c = 0; c < 2; ++c)
+        for (long s = 0; s < N; ++s) {
+            real r = 0;
+            for (int q = 0; q < 19; ++q) r += h->f[((long)c * 19 + q) * N + s];
+            rho[c * N + s] = r;
+        }
+    for (long l = 0; l < h->nlinks; ++l) {
+        const link_t *L = &h->links[l];
+        cap_t *cp = &h->cap[L->k];
+        int q = L->q, qb = OPPQ[q];
+        real ub[3] = {0, 0, 0};
+        if (L->tri >= 0)
+            for (int m = 0; m < 3; ++m)
+                for (int d = 0; d < 3; ++d) ub[d] += cp->V[3 * cp->tri[3 * L->tri + m] + d] / 3;
+        real eu = ub[0] * EV[q][0] + ub[1] * EV[q][1] + ub[2] * EV[q][2];
+        real dp = 0;
+        for (int c = 0; c < 2; ++c) {
+            real *fa = &h->f[((long)c * 19 + q) * N + L->a];
+            real *fb = &h->f[((long)c * 19 + qb) * N + L->b];
+            real rb = (rho[c * N + L->a] + rho[c * N + L->b]) / 2;
+            real delta = 2 * (real)OMEGA[q] * rb * eu * 3;
+            real va = *fa, vb = *fb;
+            *fa = vb + delta;
+            *fb = va - delta;
+            dp += 2 * va - 2 * vb - 2 * delta;
+        }
+        if (L->tri < 0) { h->lost_links++; continue; }
+        for (int m = 0; m < 3; ++m)
+            for (int d = 0; d < 3; ++d)
+                cp->Pex[3 * cp->tri[3 * L->tri + m] + d] += dp * EV[q][d] / 3;
+    }
+    free(rho);
+}
+
+/* Shan-Chen reaction of every link after the fluid step: the cross-membrane parts of the
+ * force on a (from b) and on b (from a), with the same substitution as the fluid step,
+ * returned to the crossed triangle, a third to each of its nodes. */
+static void link_reaction(lbmref_handle *h) {
+    long N = h->N;
+    const double G = h->p.G;
+    for (int k = 0; k < h->ncap; ++k) memset(h->cap[k].Rsc, 0, sizeof(real) * 3 * h->cap[k].nn);
+    for (long l = 0; l < h->nlinks; ++l) {
+        const link_t *L = &h->links[l];
+        if (L->tri < 0) continue;
+        cap_t *cp = &h->cap[L->k];
+        int q = L->q, la = h->label[L->a], lb = h->label[L->b];
+        real wq = (real)(h->p.sc_norm * OMEGA[q]);
+        double dra = boundary_drho(h, la, lb), drb = boundary_drho(h, lb, la);
+        real r = 0;
+        for (int c = 0; c < 2; ++c) {
+            int cq = 1 - c;
+            real sg = (real)(cq == 0 ? 1.0 : -1.0);
+            real ra = h->rho[cq * N + L->a] + sg * (real)dra;
+            real rbv = h->rho[cq * N + L->b] + sg * (real)drb;
+            if (ra < 0) ra = 0;
+            if (rbv < 0) rbv = 0;
+            r += (real)G * wq * (h->psi[c * N + L->a] * psi_of(h, ra) -
+                                 h->psi[c * N + L->b] * psi_of(h, rbv));
+        }
+        for (int m = 0; m < 3; ++m)
+            for (int d = 0; d < 3; ++d) cp->Rsc[3 * cp->tri[3 * L->tri + m] + d] += r * EV[q][d] / 3;
+    }
+}
+
+/* Newtonian nodes of mass m (Section 3.2): the exchanged momentum spread over this and the
+ * next step, v += (F_membrane + (P_ex(n) + P_ex(n-1)) / 2 + R_sc) / m, x += v. */
+static void update_nodes_bb(lbmref_handle *h) {
+    real im = (real)(1.0 / h->p.node_mass);
+    for (int k = 0; k < h->ncap; ++k) {
+        cap_t *c = &h->cap[k];
+        for (int d = 0; d < 3; ++d) c->f_fluid[d] = 0.0;
+        for (int n = 0; n < c->nn; ++n)
+            for (int d = 0; d < 3; ++d) {
+                int i = 3 * n + d;
+                real ff = (c->Pex[i] + c->Pprev[i]) / 2 + c->Rsc[i];
+                c->f_fluid[d] += ff;
+                c->V[i] += (c->F[i] + ff) * im;
+                c->x[i] += c->V[i];
+                c->Pprev[i] = c->Pex[i];
+            }
+    }
+}
+
 int lbmref_step(lbmref_handle *h, int64_t n) {
     if (!h || n < 0) { set_err("invalid step call"); return -1; }
     for (int64_t s = 0; s < n; ++s) {
         compute_labels(h);
         membrane_forces(h);
-        spread(h);
-        fluid_step(h);
-        update_nodes(h);
+        if (h->p.coupling == 1) {
+            find_links(h);
+            bounce_back(h);
+            fluid_step(h);
+            link_reaction(h);
+            update_nodes_bb(h);
+        } else {
+            spread(h);
+            fluid_step(h);
+            update_nodes(h);
+        }
         h->step++;
     }
     return h->unstable ? -4 : 0;
@@ -1071,9 +1320,13 @@ int lbmref_capsule_observe(lbmref_handle *h, int32_t k, lbmref_capsule_obs *o) {
         o->centroid[d] = cen[d];
         o->f_anchor[d] = -c->f_anchor[d];
         double sr = 0, sh = 0;
-        for (int i = 0; i < c->nn; ++i) { sr += c->R[3 * i + d]; sh += c->Fh[3 * i + d]; }
+        for (int i = 0; i < c->nn; ++i) {
+            sr += h->p.coupling == 1 ? c->Rsc[3 * i + d] : c->R[3 * i + d];
+            sh += c->Fh[3 * i + d];
+        }
         o->f_capillary[d] = sr;
         o->f_hertz[d] = sh;
+        o->f_fluid[d] = h->p.coupling == 1 ? c->f_fluid[d] : sr;
     }
     o->volume = volume_of(c->nn, c->x, c->nt, c->tri, cen);
     return 0;
@@ -1107,7 +1360,14 @@ int lbmref_get_summary(lbmref_handle *h, lbmref_summary *o) {
     }
     for (int k = 0; k < h->ncap; ++k)
         for (int i = 0; i < h->cap[k].nn; ++i)
-            for (int d = 0; d < 3; ++d) o->pending[d] += h->cap[k].R[3 * i + d];
+            for (int d = 0; d < 3; ++d) {
+                const cap_t *c = &h->cap[k];
+                /* bounce-back: half of the last exchange is still to be applied */
+                o->pending[d] += h->p.coupling == 1 ? c->Pprev[3 * i + d] / 2 : c->R[3 * i + d];
+                o->node_momentum[d] += h->p.coupling == 1 ? h->p.node_mass * c->V[3 * i + d] : 0.0;
+            }
+    o->lost_links = h->lost_links;
+    o->links = h->nlinks;
     o->step = h->step;
     o->lost_reaction = h->lost;
     o->n_capsules = h->ncap;
@@ -1121,9 +1381,11 @@ void lbmref_destroy(lbmref_handle *h) {
         cap_t *c = &h->cap[k];
         free(c->x); free(c->R); free(c->F); free(c->Fh); free(c->tri); free(c->minv); free(c->a0);
         free(c->edge); free(c->th0);
+        free(c->V); free(c->Pex); free(c->Pprev); free(c->Rsc);
     }
     free(h->cap);
     free(h->f); free(h->fn); free(h->rho); free(h->psi); free(h->label);
     free(h->fibm); free(h->uphys); free(h->react);
+    free(h->links);
     free(h);
 }

@@ -1,6 +1,7 @@
 /*
  * lbmref.h -- CPU oracle for the two-component Shan-Chen D3Q19 lattice Boltzmann fluid
- * coupled to triangulated Skalak capsule membranes by an immersed boundary.
+ * coupled to triangulated Skalak capsule membranes by an immersed boundary or by
+ * half-way bounce-back with momentum exchange (Section 3.1).
  *
  * TEST INFRASTRUCTURE ONLY.  Nothing in the product library includes, links or
  * calls this code; only the tests, the smoke check and the CPU-baseline leg of the
@@ -37,6 +38,9 @@ typedef struct {
     const double *init_rho_array;          /* mode 2: [2][nz][ny][nx], copied              */
     double hertz_xi, hertz_delta0;         /* Hertz repulsion strength and range           */
     double plane_dz;           /* repulsive plane at z = 0.5 + plane_dz (wall only)          */
+    int32_t coupling;          /* 0: immersed boundary; 1: half-way bounce-back on the
+                                  membrane with momentum exchange (Section 3.1)              */
+    double node_mass;          /* bounce-back coupling: mass of every membrane node          */
 } lbmref_params;
 
 typedef struct {
@@ -54,6 +58,9 @@ typedef struct {
     double f_anchor[3];     /* force of the fluid on the anchored capsule (= -sum of anchor forces) */
     double f_capillary[3];  /* sum of the pending membrane reaction R_n          */
     double f_hertz[3];      /* sum of Hertz forces on the capsule nodes          */
+    double f_fluid[3];      /* force of the fluid on the membrane in the last step (bounce-
+                               back: smoothed momentum exchange plus the Shan-Chen reaction;
+                               immersed boundary: the Shan-Chen reaction)              */
 } lbmref_capsule_obs;
 
 typedef struct {
@@ -64,6 +71,9 @@ typedef struct {
     int64_t lost_reaction;  /* sites with cross-membrane links and zero coverage  */
     int32_t n_capsules;
     int32_t unstable;       /* 1 if a non-finite or negative density was seen     */
+    double node_momentum[3];/* bounce-back coupling: sum of node mass x velocity  */
+    int64_t lost_links;     /* bounce-back links that found no triangle           */
+    int64_t links;          /* bounce-back links of the last step                 */
 } lbmref_summary;
 
 const char *lbmref_error(void);
@@ -98,6 +108,12 @@ double lbmref_volume(int32_t n_nodes, const double *xyz, int32_t n_tri, const in
 void lbmref_volume_force(int32_t n_nodes, const double *xyz, int32_t n_tri, const int32_t *tri,
                          double kv, double v0, double *force);
 double lbmref_hertz(double d, double xi, double delta0);
+/* Miss distance of the segment p0 -> p1 from triangle (a, b, c): 0 when the closed
+ * segment meets the closed triangle, else max(-u, -v, -w, -t, t - 1) with (u, v, w) the
+ * barycentric coordinates of the segment's line in the triangle's plane and t the segment
+ * parameter there; +inf when the line is parallel to the plane.  Evaluated in double. */
+double lbmref_miss_distance(const double p0[3], const double p1[3], const double a[3],
+                            const double b[3], const double c[3]);
 int lbmref_column_labels(int32_t n_nodes, const double *xyz, int32_t n_tri, const int32_t *tri,
                          int32_t x0, int32_t y0, int32_t z0, int32_t dx, int32_t dy, int32_t dz,
                          uint8_t *inside);

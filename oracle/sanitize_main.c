@@ -4,6 +4,7 @@
  *
  * Usage: lbmref_sanitize <case file>.  The case file is text:
  *   nx ny nz wall_z0 init_mode film_height steps n_caps body_force_x wall_drho tau0 tau1
+ *   coupling node_mass
  *   per capsule: n_nodes n_tri ks C kb kv wet_drho anchor_k, then n_nodes lines "x y z"
  *   and n_tri lines "a b c".
  * It builds the simulation, steps it, and prints the summary, the capsule observables and
@@ -20,11 +21,13 @@
 #include "lbmref.h"
 
 static int read_case(FILE *fp, lbmref_params *p, int *steps, int *ncaps) {
-    int wall, mode;
-    double film, gx, drho, t0, t1;
-    if (fscanf(fp, "%d %d %d %d %d %lf %d %d %lf %lf %lf %lf", &p->nx, &p->ny, &p->nz, &wall,
-               &mode, &film, steps, ncaps, &gx, &drho, &t0, &t1) != 12)
+    int wall, mode, coupling;
+    double film, gx, drho, t0, t1, mass;
+    if (fscanf(fp, "%d %d %d %d %d %lf %d %d %lf %lf %lf %lf %d %lf", &p->nx, &p->ny, &p->nz,
+               &wall, &mode, &film, steps, ncaps, &gx, &drho, &t0, &t1, &coupling, &mass) != 14)
         return -1;
+    p->coupling = coupling;
+    p->node_mass = mass;
     p->wall_z0 = wall;
     p->init_mode = mode;
     p->film_height = film;
@@ -58,6 +61,7 @@ int main(int argc, char **argv) {
     double *x0 = NULL;
     int32_t *t0 = NULL, nn0 = 0, nt0 = 0;
     lbmref_capsule_params cp0;
+    memset(&cp0, 0, sizeof cp0);
     for (int k = 0; k < ncaps; ++k) {
         int nn, nt;
         lbmref_capsule_params cp;
@@ -87,14 +91,16 @@ int main(int argc, char **argv) {
     lbmref_get_summary(h, &s);
     printf("status %d\nmass0 %.17g\nmass1 %.17g\n", st, s.mass[0], s.mass[1]);
     for (int d = 0; d < 3; ++d) printf("momentum%d %.17g\npending%d %.17g\n", d, s.momentum[d], d, s.pending[d]);
-    printf("step %lld\nlost %lld\nunstable %d\n", (long long)s.step, (long long)s.lost_reaction, s.unstable);
+    printf("step %lld\nlost %lld\nunstable %d\nlinks %lld\n", (long long)s.step,
+           (long long)s.lost_reaction, s.unstable, (long long)s.links);
+    for (int d = 0; d < 3; ++d) printf("node_momentum%d %.17g\n", d, s.node_momentum[d]);
     for (int k = 0; k < ncaps; ++k) {
         lbmref_capsule_obs o;
         lbmref_capsule_observe(h, k, &o);
         for (int d = 0; d < 3; ++d)
             printf("cap%d_centroid%d %.17g\ncap%d_f_anchor%d %.17g\ncap%d_f_capillary%d %.17g\n"
-                   "cap%d_f_hertz%d %.17g\n", k, d, o.centroid[d], k, d, o.f_anchor[d], k, d,
-                   o.f_capillary[d], k, d, o.f_hertz[d]);
+                   "cap%d_f_hertz%d %.17g\ncap%d_f_fluid%d %.17g\n", k, d, o.centroid[d], k, d,
+                   o.f_anchor[d], k, d, o.f_capillary[d], k, d, o.f_hertz[d], k, d, o.f_fluid[d]);
         printf("cap%d_volume %.17g\n", k, o.volume);
     }
     double *men = (double *)malloc(sizeof(double) * (size_t)p.nx * p.ny);
@@ -129,13 +135,15 @@ int main(int argc, char **argv) {
         lbmref_reference_geometry(nn0, x0, nt0, t0, minv, a0);
         double es = lbmref_skalak(nn0, x0, nt0, t0, minv, a0, cp0.ks, cp0.C, f);
         double eb = lbmref_bending(nn0, x0, nt0, t0, NULL, 0.1, f);
+        double p0[3] = {x0[0] - 0.3, x0[1] - 0.2, x0[2] - 0.4}, p1[3] = {x0[0] + 0.5, x0[1] + 0.4, x0[2] + 0.3};
+        double md = lbmref_miss_distance(p0, p1, x0 + 3 * t0[0], x0 + 3 * t0[1], x0 + 3 * t0[2]);
         double v = lbmref_volume(nn0, x0, nt0, t0);
         lbmref_volume_force(nn0, x0, nt0, t0, 0.3, 0.9 * v, f);
         uint8_t inside[8 * 8 * 8];
         lbmref_column_labels(nn0, x0, nt0, t0, 0, 0, 0, 8, 8, 8, inside);
         printf("helper_feq0 %.17g\nhelper_phi4 %.17g\nhelper_hertz %.17g\nhelper_skalak %.17g\n"
-               "helper_bending %.17g\nhelper_volume %.17g\n", fe[0], lbmref_phi4(0.3),
-               lbmref_hertz(0.5, 1.5, 1.5), es, eb, v);
+               "helper_bending %.17g\nhelper_volume %.17g\nhelper_miss %.17g\n", fe[0],
+               lbmref_phi4(0.3), lbmref_hertz(0.5, 1.5, 1.5), es, eb, v, md);
         free(minv); free(a0); free(f);
         free(x0); free(t0);
     }

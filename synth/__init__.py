@@ -158,6 +158,7 @@ _BASE = dict(
     init_rho_array=None,
     hertz_xi=1.5, hertz_delta0=1.5, plane_dz=0.0,
     slab_nz=0, slab_film_height=None,
+    coupling=0, node_mass=25.0,
     capsules=[], steps=1,
 )
 

@@ -1,14 +1,20 @@
 """FP64 oracle reference for the storage-precision study.
 
-Workload: the film-drying box of two anchored capsules (128 x 128 x 64 lattice, wall at
-z = 0, film 12 layers high, repulsive plane 10 lattice units above the wall, capsules
-R = 10 of 5120 triangles at separation 3R, ks = 0.05, anchor spring 1).  The oracle is
-stepped to each checkpoint and its meniscus height field, capsule observables and
-component masses are written to ``c2_precision_reference.npz`` next to this script.
+Workloads:
+* ``c2``: the film-drying box of two anchored capsules (128 x 128 x 64 lattice, wall at
+  z = 0, film 12 layers high, repulsive plane 10 lattice units above the wall, capsules
+  R = 10 of 5120 triangles at separation 3R, ks = 0.05, anchor spring 1), checkpoints
+  1000 and 5000 steps;
+* ``c3``: the precision form's box (256 x 256 x 96, the same film and plane, 16 anchored
+  capsules R = 10 at seeded random positions, ks = 0.05), checkpoints 1000, 5000 and
+  10000 steps.
+The oracle is stepped to each checkpoint and its meniscus height field, capsule
+observables and component masses are written to ``<workload>_precision_reference.npz``
+next to this script.
 
 Only the oracle and the seeded input generators are used.  Run from the repository root:
 
-    python tests/golden/make_precision_reference.py [--threads N]
+    python tests/golden/make_precision_reference.py [--workload c2|c3] [--threads N]
 """
 import argparse
 import os
@@ -23,22 +29,23 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 import oracle  # noqa: E402
 import synth  # noqa: E402
 
-CHECKPOINTS = (1000, 5000)
-OUT = os.path.join(HERE, "c2_precision_reference.npz")
+CHECKPOINTS = {"c2": (1000, 5000), "c3": (1000, 5000, 10000)}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--threads", type=int, default=0)
+    ap.add_argument("--workload", default="c2", choices=sorted(CHECKPOINTS))
     args = ap.parse_args()
-    cfg = synth.workload("c2", ks=0.05)
+    cfg = synth.workload("c2", ks=0.05) if args.workload == "c2" else synth.workload("c3")
+    out = os.path.join(HERE, f"{args.workload}_precision_reference.npz")
     o = oracle.Oracle(cfg, "f64", n_threads=args.threads)
     ncap = len(cfg["capsules"])
     mass0 = o.summary()["mass"].copy()
-    rec = dict(checkpoints=np.array(CHECKPOINTS), mass0=mass0)
+    rec = dict(checkpoints=np.array(CHECKPOINTS[args.workload]), mass0=mass0)
     done = 0
     t0 = time.time()
-    for cp in CHECKPOINTS:
+    for cp in CHECKPOINTS[args.workload]:
         st = o.step(cp - done)
         if st != 0:
             raise SystemExit(f"oracle step failed with status {st}")
@@ -51,8 +58,8 @@ def main():
         rec[f"volume_{cp}"] = np.array([c["volume"] for c in caps])
         print(f"step {cp}: {time.time() - t0:.0f} s", flush=True)
     o.close()
-    np.savez_compressed(OUT, **rec)
-    print("wrote", OUT)
+    np.savez_compressed(out, **rec)
+    print("wrote", out)
 
 
 if __name__ == "__main__":
