@@ -19,6 +19,15 @@
  *   - interpolation of the physical velocity to the nodes, node advection and
  *     gathering of the reaction onto the nodes.
  *
+ * With coupling = 1 (lbm_params) the membrane is coupled as in Section 3.1 instead: every
+ * lattice link between a site inside a capsule and one outside is bounced back half-way on
+ * the membrane triangle it crosses (Ladd's moving-wall term with the mean velocity of the
+ * triangle's three nodes), before streaming; the exchanged momentum and the Shan-Chen force
+ * across the link go a third to each node of that triangle (homogeneous weighting); the
+ * exchanged momentum acts half in this step and half in the next (against staggered
+ * momenta); and the nodes, of mass node_mass, follow v += F / m, x += v.  Nothing is
+ * spread or interpolated.  Batches take immersed-boundary handles only.
+ *
  * Conventions
  *   Lattice units (dx = dt = 1).  Site (i, j, k) sits at position (i, j, k); arrays over
  *   sites are [nz][ny][nx] with x fastest.  The lattice is periodic in x, y and z; with
@@ -111,6 +120,12 @@ typedef struct {
     const double *slab_film_height; /* mode 1 with slabs: host [nz / slab_nz] film layers per
                                   slab, or NULL for film_height in every slab; read during
                                   lbm_init                                                  */
+    int32_t coupling;          /* fluid-membrane coupling: 0 immersed boundary (Peskin
+                                  4-point spreading and interpolation, nodes advected with
+                                  the fluid); 1 half-way bounce-back on the membrane with
+                                  Ladd's momentum exchange (Section 3.1), see below         */
+    double node_mass;          /* coupling 1: mass of every membrane node (25 rho0 in
+                                  Section 3.2), > 0                                         */
 } lbm_params;
 
 typedef struct {
@@ -129,18 +144,28 @@ typedef struct {
     double centroid[3];     /* node mean at the current positions                         */
     double volume;          /* enclosed volume at the current positions                   */
     double f_anchor[3];     /* force of the fluid on an anchored capsule (last step)      */
-    double f_capillary[3];  /* sum of the pending cross-membrane reaction                 */
+    double f_capillary[3];  /* sum of the cross-membrane Shan-Chen reaction (immersed
+                               boundary: pending for the next step; bounce-back: of the
+                               last step)                                                 */
     double f_hertz[3];      /* sum of Hertz forces of the last step                       */
+    double f_fluid[3];      /* force of the fluid on the membrane in the last step: with
+                               bounce-back the exchanged momentum applied (smoothed) plus
+                               the Shan-Chen reaction; with the immersed boundary equal to
+                               f_capillary                                                */
 } lbm_capsule_obs;
 
 typedef struct {
     double mass[2];         /* sum over fluid sites of rho^c (double accumulation)        */
     double momentum[3];     /* fluid momentum sum_x sum_c sum_i f*_i e_i                  */
-    double pending[3];      /* sum over all nodes of the pending reaction                 */
+    double pending[3];      /* sum over all nodes of the pending reaction (bounce-back:
+                               half of the last step's exchanged momentum, still to act)  */
     int64_t step;           /* completed time steps                                       */
     int64_t lost_reaction;  /* site-steps whose reaction found no kernel coverage         */
     int32_t n_capsules;
     int32_t unstable;       /* 1: non-finite / negative density or capsule overflow seen  */
+    double node_momentum[3];/* bounce-back coupling: sum over nodes of mass x velocity     */
+    int64_t links;          /* bounce-back coupling: membrane links of the last step      */
+    int64_t lost_links;     /* bounce-back links that found no triangle (all steps)       */
 } lbm_summary;
 
 typedef struct {

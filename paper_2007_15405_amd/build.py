@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(ROOT, "_build")
-SOURCES = ["api.hip", "fluid.hip", "membrane.hip", "surrogate.hip"]
+SOURCES = ["api.hip", "fluid.hip", "membrane.hip", "bounce.hip", "surrogate.hip"]
 LIB = os.path.join(HERE, "liblbm.so")
 ARCH = os.environ.get("LBM_OFFLOAD_ARCH", "gfx950")
 

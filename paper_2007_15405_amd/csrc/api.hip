@@ -85,6 +85,13 @@ struct lbm_handle {
     std::vector<CapDev> h_caps;
     int tile = 1, zchunk = 0;
     Prof prof;
+    // bounce-back coupling (coupling = 1)
+    double4 *d_V = nullptr;
+    long long *d_pex = nullptr, *d_rsc = nullptr;
+    float4 *d_pprev = nullptr, *d_ffl = nullptr;
+    int *d_bcount = nullptr, *d_bstart = nullptr, *d_blist = nullptr, *d_nlinks = nullptr;
+    BBLink *d_links = nullptr;
+    int link_cap = 0;
 };
 
 #define HIPCHK(h, expr)                                                               \
@@ -165,7 +172,8 @@ static void free_all(lbm_handle *h) {
                     h->d_node_cap, h->d_F, h->d_Fh, h->d_R, h->d_tri, h->d_minv, h->d_a0,
                     h->d_off, h->d_list, h->d_marks, h->d_rowstart, h->d_slot, h->d_wbuf,
                     h->d_wpar, h->d_part, h->d_xrow, h->d_edge, h->d_eth0, h->d_eoff,
-                    h->d_elist};
+                    h->d_elist, h->d_V, h->d_pex, h->d_rsc, h->d_pprev, h->d_ffl,
+                    h->d_bcount, h->d_bstart, h->d_blist, h->d_nlinks, h->d_links};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     free_prof(h->prof);
@@ -307,6 +315,9 @@ extern "C" lbm_status lbm_init(const lbm_params *p, lbm_handle **out) {
     if (p->storage < 0 || p->storage > 2) return bad("storage must be 0, 1 or 2");
     if (!(p->hertz_xi >= 0.0) || !(p->hertz_delta0 >= 0.0)) return bad("invalid Hertz parameters");
     if (p->wall_z0 != 0 && p->wall_z0 != 1) return bad("wall_z0 must be 0 or 1");
+    if (p->coupling != 0 && p->coupling != 1) return bad("coupling must be 0 or 1");
+    if (p->coupling == 1 && !(p->node_mass > 0.0 && std::isfinite(p->node_mass)))
+        return bad("node_mass must be positive with the bounce-back coupling");
 
     lbm_handle *h = new (std::nothrow) lbm_handle();
     if (!h) return LBM_E_NOMEM;
@@ -619,8 +630,59 @@ static lbm_status finalize(lbm_handle *h) {
     HIPCHK(h, hipMemsetAsync(h->d_slot, 0, nt * sizeof(int), h->st));
     HIPCHK(h, hipMemsetAsync(h->d_xrow, 0, nt * sizeof(double4), h->st));
     HIPCHK(h, hipMemcpyAsync(h->cap_drho, drho.data(), MAX_CAPS * sizeof(float), hipMemcpyHostToDevice, h->st));
+    if (h->p.coupling == 1) {
+        // links per capsule: a closed surface of area A cuts about 5.74 A lattice links; a
+        // triangle of the meshes here has an area of about 0.1 .. 0.3, so 24 links per
+        // triangle leave a wide margin (overflow is reported as LBM_E_UNSTABLE)
+        int mt = 1;
+        for (const CapDev &c : h->h_caps) mt = std::max(mt, c.nt);
+        h->link_cap = std::max(4096, 24 * mt);
+        if (dalloc(&h->d_V, nt) != hipSuccess || dalloc(&h->d_pex, 3 * nt) != hipSuccess ||
+            dalloc(&h->d_rsc, 3 * nt) != hipSuccess || dalloc(&h->d_pprev, nt) != hipSuccess ||
+            dalloc(&h->d_ffl, nt) != hipSuccess ||
+            dalloc(&h->d_bcount, (size_t)ncap * GMAX3) != hipSuccess ||
+            dalloc(&h->d_bstart, (size_t)ncap * (GMAX3 + 1)) != hipSuccess ||
+            dalloc(&h->d_blist, (size_t)BB_PER_TRI * tt) != hipSuccess ||
+            dalloc(&h->d_nlinks, 2 * (size_t)ncap) != hipSuccess ||
+            dalloc(&h->d_links, (size_t)ncap * h->link_cap) != hipSuccess)
+            return fail(h, LBM_E_NOMEM, "device allocation failed (bounce-back)");
+        HIPCHK(h, hipMemsetAsync(h->d_V, 0, nt * sizeof(double4), h->st));
+        HIPCHK(h, hipMemsetAsync(h->d_pex, 0, 3 * nt * sizeof(long long), h->st));
+        HIPCHK(h, hipMemsetAsync(h->d_rsc, 0, 3 * nt * sizeof(long long), h->st));
+        HIPCHK(h, hipMemsetAsync(h->d_pprev, 0, nt * sizeof(float4), h->st));
+        HIPCHK(h, hipMemsetAsync(h->d_ffl, 0, nt * sizeof(float4), h->st));
+        HIPCHK(h, hipMemsetAsync(h->d_bcount, 0, (size_t)ncap * GMAX3 * sizeof(int), h->st));
+        HIPCHK(h, hipMemsetAsync(h->d_bstart, 0, (size_t)ncap * (GMAX3 + 1) * sizeof(int), h->st));
+        HIPCHK(h, hipMemsetAsync(h->d_blist, 0, (size_t)BB_PER_TRI * tt * sizeof(int), h->st));
+        HIPCHK(h, hipMemsetAsync(h->d_nlinks, 0, 2 * (size_t)ncap * sizeof(int), h->st));
+    }
     HIPCHK(h, hipStreamSynchronize(h->st));
     return LBM_OK;
+}
+
+// arguments of the bounce-back kernels for the step reading population buffer cur
+static BBArgs bb_args(lbm_handle *h, int cur) {
+    BBArgs b{};
+    b.caps = h->d_caps; b.cst = h->d_cst;
+    b.ncap = (int)h->caps.size(); b.ntot = h->ntot; b.ttot = h->ttot;
+    b.tri = h->d_tri; b.X = h->d_X; b.V = h->d_V; b.F = h->d_F; b.slot = h->d_slot;
+    b.flag = h->flag;
+    b.f = h->f[cur];
+    b.fnew = h->f[1 - cur];
+    b.N = h->N; b.nx = h->nx; b.ny = h->ny; b.nz = h->nz; b.wall = h->wall; b.lz = h->lz;
+    b.shift[0] = shift_of(h, 0);
+    b.shift[1] = shift_of(h, 1);
+    b.bcount = h->d_bcount; b.bstart = h->d_bstart; b.blist = h->d_blist;
+    b.links = h->d_links; b.link_cap = h->link_cap; b.nlinks = h->d_nlinks;
+    b.pex = h->d_pex; b.rsc = h->d_rsc; b.pprev = h->d_pprev; b.ffl = h->d_ffl; b.R = h->d_R;
+    b.status = h->status;
+    b.G = (float)h->p.G;
+    b.ws_axis = (float)(h->p.sc_norm / 18.0);
+    b.ws_diag = (float)(h->p.sc_norm / 36.0);
+    b.inv_rho0 = (float)(1.0 / h->p.rho0);
+    b.cap_drho = h->cap_drho;
+    b.inv_mass = 1.0 / h->p.node_mass;
+    return b;
 }
 
 // ------------------------------------------------------------------------------------
@@ -640,6 +702,7 @@ static MembraneArgs membrane_args(lbm_handle *h) {
     m.nx = h->nx; m.ny = h->ny; m.nz = h->nz; m.wall = h->wall; m.lz = h->lz;
     m.hertz_xi = (float)h->p.hertz_xi;
     m.hertz_d0 = (float)h->p.hertz_delta0;
+    m.bb = h->p.coupling == 1;
     return m;
 }
 
@@ -726,11 +789,16 @@ extern "C" lbm_status lbm_step(lbm_handle *h, int64_t n) {
         if (s != LBM_OK) return s;
     }
     const bool caps = !h->caps.empty();
+    const bool bb = caps && h->p.coupling == 1;
     MembraneArgs m = caps ? membrane_args(h) : MembraneArgs{};
     for (int64_t i = 0; i < n; ++i) {
         if (caps) {
             m.epoch = (int)(h->step & 0x7fffffff);
             capsule_kernels_before(h, m, h->prof);
+        }
+        if (bb) {
+            const BBArgs b = bb_args(h, h->cur);
+            timed(h->prof, h->st, "bounce_back", [&] { launch_bb_before(b, h->storage, h->st); });
         }
         const FluidArgs a = fluid_args(h, h->cur);
         const int zc = zchunk_of(h);
@@ -741,7 +809,12 @@ extern "C" lbm_status lbm_step(lbm_handle *h, int64_t n) {
                 default: launch_fluid_tiled<2>(a, h->tile, zc, h->st); break;
             }
         });
-        if (caps) timed(h->prof, h->st, "node_update", [&] { launch_node_update(m, h->ntot, h->st); });
+        if (bb) {
+            const BBArgs b = bb_args(h, h->cur);
+            timed(h->prof, h->st, "bb_nodes", [&] { launch_bb_after(b, h->storage, h->st); });
+        } else if (caps) {
+            timed(h->prof, h->st, "node_update", [&] { launch_node_update(m, h->ntot, h->st); });
+        }
         h->cur = 1 - h->cur;
         h->step++;
     }
@@ -1021,6 +1094,8 @@ extern "C" lbm_status lbm_batch_create(lbm_handle *const *handles, int32_t n, lb
             return bad("batched handles must share device, stream and storage mode");
         if (!(h->p.tau[0] == 1.0 && h->p.tau[1] == 1.0))
             return bad("batched handles need tau = 1 in both components");
+        if (h->p.coupling != 0)
+            return bad("batched handles use the immersed-boundary coupling");
     }
     lbm_batch *b = new (std::nothrow) lbm_batch();
     if (!b) return LBM_E_NOMEM;
@@ -1232,10 +1307,12 @@ static lbm_status check_status(lbm_handle *h, int st[ST_WORDS]) {
 }
 
 static bool unstable_flagged(const int *st) {
-    return st[ST_UNSTABLE] || st[ST_OVERFLOW] || st[ST_WIDE] || st[ST_SYNC] || st[ST_SLAB];
+    return st[ST_UNSTABLE] || st[ST_OVERFLOW] || st[ST_WIDE] || st[ST_SYNC] || st[ST_SLAB] ||
+           st[ST_BBOVER];
 }
 
 static const char *unstable_message(const int *st) {
+    if (st[ST_BBOVER]) return "bounce-back link list or triangle bins overflowed (deformed capsule)";
     if (st[ST_SYNC]) return "capsule reduction read partial sums of another step";
     if (st[ST_SLAB]) return "capsule window crossed a wall layer of its slab";
     if (st[ST_WIDE]) return "capsule window wider than 2048 lattice columns (x * y)";
@@ -1307,28 +1384,52 @@ extern "C" lbm_status lbm_observables(lbm_handle *h, lbm_obs *out) {
     }
     sm.step = h->step;
     sm.lost_reaction = st[ST_LOST];
+    sm.lost_links = st[ST_BBLOST];
     sm.n_capsules = (int)h->caps.size();
     sm.unstable = unstable_flagged(st) ? 1 : 0;
     if (h->finalized && !h->caps.empty()) {
-        std::vector<double4> X(h->ntot);
-        std::vector<float4> Fh(h->ntot), R(h->ntot);
+        const bool bb = h->p.coupling == 1;
+        std::vector<double4> X(h->ntot), V(bb ? h->ntot : 0);
+        std::vector<float4> Fh(h->ntot), R(h->ntot), Pp(bb ? h->ntot : 0), Ff(bb ? h->ntot : 0);
         std::vector<CapState> cs(h->caps.size());
+        std::vector<int> nl(bb ? h->caps.size() : 0);
         HIPCHK(h, hipMemcpy(X.data(), h->d_X, X.size() * sizeof(double4), hipMemcpyDeviceToHost));
         HIPCHK(h, hipMemcpy(Fh.data(), h->d_Fh, Fh.size() * sizeof(float4), hipMemcpyDeviceToHost));
         HIPCHK(h, hipMemcpy(R.data(), h->d_R, R.size() * sizeof(float4), hipMemcpyDeviceToHost));
         HIPCHK(h, hipMemcpy(cs.data(), h->d_cst, cs.size() * sizeof(CapState), hipMemcpyDeviceToHost));
+        if (bb) {
+            HIPCHK(h, hipMemcpy(V.data(), h->d_V, V.size() * sizeof(double4), hipMemcpyDeviceToHost));
+            HIPCHK(h, hipMemcpy(Pp.data(), h->d_pprev, Pp.size() * sizeof(float4), hipMemcpyDeviceToHost));
+            HIPCHK(h, hipMemcpy(Ff.data(), h->d_ffl, Ff.size() * sizeof(float4), hipMemcpyDeviceToHost));
+            HIPCHK(h, hipMemcpy(nl.data(), h->d_nlinks + h->caps.size(), nl.size() * sizeof(int),
+                                hipMemcpyDeviceToHost));
+            for (int v : nl) sm.links += v;
+        }
         for (size_t k = 0; k < h->caps.size(); ++k) {
             const CapDev &cd = h->h_caps[k];
-            double cen[3] = {0, 0, 0}, fr[3] = {0, 0, 0}, fh[3] = {0, 0, 0};
+            double cen[3] = {0, 0, 0}, fr[3] = {0, 0, 0}, fh[3] = {0, 0, 0}, ff[3] = {0, 0, 0};
             for (int i = 0; i < cd.nn; ++i) {
                 const double4 x = X[cd.node0 + i];
                 cen[0] += x.x; cen[1] += x.y; cen[2] += x.z;
                 fr[0] += R[cd.node0 + i].x; fr[1] += R[cd.node0 + i].y; fr[2] += R[cd.node0 + i].z;
                 fh[0] += Fh[cd.node0 + i].x; fh[1] += Fh[cd.node0 + i].y; fh[2] += Fh[cd.node0 + i].z;
+                if (bb) {
+                    const float4 p = Pp[cd.node0 + i], f = Ff[cd.node0 + i];
+                    const double4 v = V[cd.node0 + i];
+                    // half of the last exchange is still to be applied
+                    sm.pending[0] += 0.5 * p.x; sm.pending[1] += 0.5 * p.y; sm.pending[2] += 0.5 * p.z;
+                    sm.node_momentum[0] += h->p.node_mass * v.x;
+                    sm.node_momentum[1] += h->p.node_mass * v.y;
+                    sm.node_momentum[2] += h->p.node_mass * v.z;
+                    ff[0] += f.x; ff[1] += f.y; ff[2] += f.z;
+                }
             }
             for (int d = 0; d < 3; ++d) {
                 cen[d] /= cd.nn;
-                sm.pending[d] += fr[d];
+                if (!bb) {
+                    sm.pending[d] += fr[d];
+                    ff[d] = fr[d];
+                }
             }
             if (out->capsules) {
                 lbm_capsule_obs &o = out->capsules[k];
@@ -1348,6 +1449,7 @@ extern "C" lbm_status lbm_observables(lbm_handle *h, lbm_obs *out) {
                     o.centroid[d] = cen[d];
                     o.f_capillary[d] = fr[d];
                     o.f_hertz[d] = fh[d];
+                    o.f_fluid[d] = ff[d];
                     // the anchor of the last step acted at its centroid cs.cen
                     o.f_anchor[d] = (h->step > 0 && hc.p.anchor_k != 0.0)
                                         ? hc.p.anchor_k * (cs[k].cen[d] - cd.c0[d]) : 0.0;
@@ -1441,6 +1543,15 @@ extern "C" lbm_status lbm_save(lbm_handle *h, const char *path) {
         ok = ok && std::fwrite(X.data(), sizeof(double4), X.size(), fp) == X.size() &&
              std::fwrite(R.data(), sizeof(float4), R.size(), fp) == R.size() &&
              std::fwrite(cs.data(), sizeof(CapState), cs.size(), fp) == cs.size();
+    if (h->ntot && h->p.coupling == 1) {
+        // bounce-back: node velocities and the exchanged momentum still to act
+        std::vector<double4> V(h->ntot);
+        std::vector<float4> Pp(h->ntot);
+        ok = ok && hipMemcpy(V.data(), h->d_V, V.size() * sizeof(double4), hipMemcpyDeviceToHost) == hipSuccess &&
+             hipMemcpy(Pp.data(), h->d_pprev, Pp.size() * sizeof(float4), hipMemcpyDeviceToHost) == hipSuccess &&
+             std::fwrite(V.data(), sizeof(double4), V.size(), fp) == V.size() &&
+             std::fwrite(Pp.data(), sizeof(float4), Pp.size(), fp) == Pp.size();
+    }
     ok = (std::fclose(fp) == 0) && ok;
     return ok ? LBM_OK : fail(h, LBM_E_INVAL, "checkpoint write failed");
 }
@@ -1468,6 +1579,13 @@ extern "C" lbm_status lbm_load(lbm_handle *h, const char *path) {
         ok = std::fread(X.data(), sizeof(double4), X.size(), fp) == X.size() &&
              std::fread(R.data(), sizeof(float4), R.size(), fp) == R.size() &&
              std::fread(cs.data(), sizeof(CapState), cs.size(), fp) == cs.size();
+    const bool bb = h->ntot && h->p.coupling == 1;
+    std::vector<double4> V(bb ? h->ntot : 0);
+    std::vector<float4> Pp(bb ? h->ntot : 0);
+    if (ok && bb)
+        ok = std::fread(V.data(), sizeof(double4), V.size(), fp) == V.size() &&
+             std::fread(Pp.data(), sizeof(float4), Pp.size(), fp) == Pp.size();
+    if (ok) ok = std::fgetc(fp) == EOF;   // nothing left over: the same coupling wrote it
     std::fclose(fp);
     if (!ok) return fail(h, LBM_E_INVAL, "checkpoint does not match this simulation");
     HIPCHK(h, hipStreamSynchronize(h->st));
@@ -1478,6 +1596,14 @@ extern "C" lbm_status lbm_load(lbm_handle *h, const char *path) {
         HIPCHK(h, hipMemcpy(h->d_X, X.data(), X.size() * sizeof(double4), hipMemcpyHostToDevice));
         HIPCHK(h, hipMemcpy(h->d_R, R.data(), R.size() * sizeof(float4), hipMemcpyHostToDevice));
         HIPCHK(h, hipMemcpy(h->d_cst, cs.data(), cs.size() * sizeof(CapState), hipMemcpyHostToDevice));
+    }
+    if (bb) {
+        HIPCHK(h, hipMemcpy(h->d_V, V.data(), V.size() * sizeof(double4), hipMemcpyHostToDevice));
+        HIPCHK(h, hipMemcpy(h->d_pprev, Pp.data(), Pp.size() * sizeof(float4), hipMemcpyHostToDevice));
+        HIPCHK(h, hipMemset(h->d_pex, 0, 3 * (size_t)h->ntot * sizeof(long long)));
+        HIPCHK(h, hipMemset(h->d_rsc, 0, 3 * (size_t)h->ntot * sizeof(long long)));
+        HIPCHK(h, hipMemset(h->d_nlinks, 0, 2 * h->caps.size() * sizeof(int)));
+        HIPCHK(h, hipMemset(h->d_bcount, 0, h->caps.size() * GMAX3 * sizeof(int)));
     }
     if (h->ntot)   // crossing masks of windows this handle used before the load
         HIPCHK(h, hipMemset(h->d_marks, 0, h->caps.size() * ROWS_MAX * sizeof(unsigned long long)));

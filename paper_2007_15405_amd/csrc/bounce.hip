@@ -1,0 +1,446 @@
+// bounce.hip -- the fluid-membrane coupling of Section 3.1: half-way bounce-back on the
+// moving triangulated membrane with Ladd's momentum exchange, the homogeneous weighting of
+// the three nodes of the crossed element, the exchanged momentum spread over two
+// consecutive steps, and Newtonian membrane nodes of mass m (25 rho0 in Section 3.2).
+//
+// Per step, after the capsule reduction (window), the membrane forces and the side labels:
+//   k_bb_bin_count / k_bb_bin_scan / k_bb_bin_fill: the triangles of each capsule binned
+//     into the unit cells of its window (counting sort; the counts return to zero);
+//   k_bb_links: every link from a site inside capsule k to a fluid site of another side
+//     (exterior, or a capsule of higher index) finds its triangle: among the triangles
+//     whose bounding box meets the link's, the least miss distance, lowest index on ties;
+//     the link record keeps both sites' densities before any population is changed;
+//   k_bb_swap: the bounce-back on the post-collision populations in place, so that plain
+//     pull streaming delivers f_q(b) = f*_qbar(b) + delta and f_qbar(a) = f*_q(a) - delta,
+//     delta = 2 w_q rho u_b . e_q / c_s^2 (rho the link-mean density of the component, u_b
+//     the mean velocity of the triangle's nodes); the exchanged momentum
+//     (2 f*_q(a) - 2 f*_qbar(b) - 2 delta) e_q goes a third to each node of the triangle;
+//   (the fluid step)
+//   k_bb_reaction: the Shan-Chen force across each link, from the densities after the
+//     fluid step and the same substitution, returned to the triangle the same way;
+//   k_bb_nodes: v += (F_membrane + (P_ex(n) + P_ex(n-1)) / 2 + R_sc) / m, x += v.
+// Node sums are 64-bit fixed point (2^-40), so they do not depend on the order of the
+// atomic adds.  Decisions (labels, triangle choice) use the FP32-rounded node positions
+// evaluated in double without contraction of multiply-adds.
+#include "lbm_internal.h"
+
+namespace lbmx {
+
+namespace {
+
+__device__ __forceinline__ int wrapb(int a, int n) {
+    a %= n;
+    return a < 0 ? a + n : a;
+}
+
+__device__ __forceinline__ long long fix40(float v) {
+    return (long long)__builtin_rint((double)v * 1099511627776.0);   // 2^40
+}
+__device__ __forceinline__ float unfix40(long long v) {
+    return (float)((double)v * (1.0 / 1099511627776.0));
+}
+
+// six times the signed volume of the tetrahedron (a, b, c, d)
+__device__ double orient3(const double *a, const double *b, const double *c, const double *d) {
+#pragma clang fp contract(off)
+    double ab[3], ac[3], ad[3];
+    for (int k = 0; k < 3; ++k) {
+        ab[k] = b[k] - a[k];
+        ac[k] = c[k] - a[k];
+        ad[k] = d[k] - a[k];
+    }
+    return ab[0] * (ac[1] * ad[2] - ac[2] * ad[1]) + ab[1] * (ac[2] * ad[0] - ac[0] * ad[2]) +
+           ab[2] * (ac[0] * ad[1] - ac[1] * ad[0]);
+}
+
+// miss distance of the segment p0 -> p1 from triangle (a, b, c): 0 when they meet, else
+// max(-u, -v, -w, -t, t - 1), u, v, w the barycentric coordinates of the segment's line in
+// the triangle's plane and t the segment parameter there; +inf for a parallel line
+__device__ double miss_distance(const double *p0, const double *p1, const double *a,
+                                const double *b, const double *c) {
+#pragma clang fp contract(off)
+    const double s0 = orient3(a, b, c, p0), s1 = orient3(a, b, c, p1);
+    const double den = s0 - s1;
+    if (den == 0.0) return __builtin_inf();
+    const double t = s0 / den;
+    const double wa = orient3(p0, p1, b, c), wb = orient3(p0, p1, c, a), wc = orient3(p0, p1, a, b);
+    const double sum = wa + wb + wc;
+    if (sum == 0.0) return __builtin_inf();
+    const double u = wa / sum, v = wb / sum, w = wc / sum;
+    double d = 0.0;
+    if (-u > d) d = -u;
+    if (-v > d) d = -v;
+    if (-w > d) d = -w;
+    if (-t > d) d = -t;
+    if (t - 1.0 > d) d = t - 1.0;
+    return d;
+}
+
+__device__ __forceinline__ void tri_vertices(const BBArgs &b, int t, double (&v)[3][3]) {
+    const int4 tr = b.tri[t];
+    const double4 P[3] = {b.X[tr.x], b.X[tr.y], b.X[tr.z]};
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        v[m][0] = (double)(float)P[m].x;
+        v[m][1] = (double)(float)P[m].y;
+        v[m][2] = (double)(float)P[m].z;
+    }
+}
+
+template <int S>
+__device__ __forceinline__ float popl(const void *f, int c, int q, int N, int s, float sh) {
+    using T = typename Codec<S>::T;
+    return Codec<S>::dec(((const T *)f)[(size_t)(c * Q + q) * N + s], wq(q) * sh);
+}
+template <int S>
+__device__ __forceinline__ void pops(void *f, int c, int q, int N, int s, float v, float sh) {
+    using T = typename Codec<S>::T;
+    ((T *)f)[(size_t)(c * Q + q) * N + s] = Codec<S>::enc(v, wq(q) * sh);
+}
+
+template <int S>
+__device__ __forceinline__ void densities(const BBArgs &b, const void *f, int s, float &r0, float &r1) {
+    float a0 = 0.f, a1 = 0.f;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        a0 += popl<S>(f, 0, q, b.N, s, b.shift[0]);
+        a1 += popl<S>(f, 1, q, b.N, s, b.shift[1]);
+    }
+    r0 = a0;
+    r1 = a1;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------------------------
+// Triangle bins
+// ------------------------------------------------------------------------------------
+__device__ __forceinline__ bool tri_cells(const BBArgs &b, int t, int k, int (&c0)[3], int (&c1)[3]) {
+    const CapState cs = b.cst[k];
+    double v[3][3];
+    tri_vertices(b, t, v);
+    for (int d = 0; d < 3; ++d) {
+        const double lo = fmin(v[0][d], fmin(v[1][d], v[2][d]));
+        const double hi = fmax(v[0][d], fmax(v[1][d], v[2][d]));
+        if (!(hi - lo <= (double)(BB_SPAN - 1))) return false;
+        c0[d] = max((int)floor(lo) - cs.lo[d], 0);
+        c1[d] = min((int)floor(hi) - cs.lo[d], cs.dim[d] - 1);
+        if (c0[d] > c1[d]) return false;
+    }
+    return true;
+}
+
+__global__ void __launch_bounds__(256) k_bb_bin_count(BBArgs b) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= b.ttot) return;
+    const int k = b.tri[t].w;
+    int c0[3], c1[3];
+    if (!tri_cells(b, t, k, c0, c1)) {
+        atomicOr(&b.status[ST_BBOVER], 1);
+        return;
+    }
+    const CapState cs = b.cst[k];
+    int *cnt = b.bcount + (size_t)k * GMAX3;
+    for (int z = c0[2]; z <= c1[2]; ++z)
+        for (int y = c0[1]; y <= c1[1]; ++y)
+            for (int x = c0[0]; x <= c1[0]; ++x)
+                atomicAdd(&cnt[(z * cs.dim[1] + y) * cs.dim[0] + x], 1);
+}
+
+// exclusive scan of the cell counts of capsule k (one block of 1024 threads)
+__global__ void __launch_bounds__(1024) k_bb_bin_scan(BBArgs b) {
+    const int k = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const CapState cs = b.cst[k];
+    const int ncell = cs.dim[0] * cs.dim[1] * cs.dim[2];
+    const int *cnt = b.bcount + (size_t)k * GMAX3;
+    int *st = b.bstart + (size_t)k * (GMAX3 + 1);
+    const int per = (ncell + 1023) / 1024;
+    const int q0 = min(tid * per, ncell), q1 = min(q0 + per, ncell);
+    int local = 0;
+    for (int i = q0; i < q1; ++i) local += cnt[i];
+    int incl = local;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int v = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += v;
+    }
+    __shared__ int wsum[16];
+    if (lane == 63) wsum[wid] = incl;
+    __syncthreads();
+    int run = incl - local;
+    for (int w = 0; w < wid; ++w) run += wsum[w];
+    for (int i = q0; i < q1; ++i) {
+        st[i] = run;
+        run += cnt[i];
+    }
+    if (q1 == ncell && q0 < q1) st[ncell] = run;
+    if (ncell == 0 && tid == 0) st[0] = 0;
+    const CapDev cd = b.caps[k];
+    if (tid == 1023) {
+        int tot = 0;
+        for (int w = 0; w < 16; ++w) tot += wsum[w];
+        if (tot > BB_PER_TRI * cd.nt) atomicOr(&b.status[ST_BBOVER], 1);
+    }
+}
+
+__global__ void __launch_bounds__(256) k_bb_bin_fill(BBArgs b) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= b.ttot) return;
+    const int k = b.tri[t].w;
+    int c0[3], c1[3];
+    if (!tri_cells(b, t, k, c0, c1)) return;
+    const CapState cs = b.cst[k];
+    const CapDev cd = b.caps[k];
+    int *cnt = b.bcount + (size_t)k * GMAX3;
+    const int *st = b.bstart + (size_t)k * (GMAX3 + 1);
+    int *list = b.blist + (size_t)BB_PER_TRI * cd.tri0;
+    for (int z = c0[2]; z <= c1[2]; ++z)
+        for (int y = c0[1]; y <= c1[1]; ++y)
+            for (int x = c0[0]; x <= c1[0]; ++x) {
+                const int cell = (z * cs.dim[1] + y) * cs.dim[0] + x;
+                // the count runs back to zero, ready for the next step
+                const int pos = st[cell] + atomicSub(&cnt[cell], 1) - 1;
+                if (pos < BB_PER_TRI * cd.nt) list[pos] = t;
+            }
+}
+
+// ------------------------------------------------------------------------------------
+// Links and bounce-back
+// ------------------------------------------------------------------------------------
+// plane lz of capsule k's window: the links of its inside sites
+template <int S>
+__global__ void __launch_bounds__(256) k_bb_links(BBArgs b) {
+    const int k = blockIdx.y, lz = blockIdx.x;
+    const CapState cs = b.cst[k];
+    if (lz >= cs.dim[2]) return;
+    const CapDev cd = b.caps[k];
+    const int dx = cs.dim[0], dy = cs.dim[1];
+    const int uz = cs.lo[2] + lz, z = wrapb(uz, b.nz);
+    if (b.wall && slab_pos(z, b.lz) == 0) return;
+    const int *st = b.bstart + (size_t)k * (GMAX3 + 1);
+    const int *list = b.blist + (size_t)BB_PER_TRI * cd.tri0;
+    const int lmax = BB_PER_TRI * cd.nt;
+    for (int col = threadIdx.x; col < dx * dy; col += blockDim.x) {
+        const int ly = col / dx, lx = col - ly * dx;
+        const int ux = cs.lo[0] + lx, uy = cs.lo[1] + ly;
+        const int sa = (z * b.ny + wrapb(uy, b.ny)) * b.nx + wrapb(ux, b.nx);
+        if ((b.flag[sa] & LABEL_MASK) != k + 1) continue;
+        bool have_a = false;
+        float ra0 = 0.f, ra1 = 0.f;
+        for (int q = 1; q < Q; ++q) {
+            const int vz = uz + CZ[q], zb = wrapb(vz, b.nz);
+            if (b.wall && slab_pos(zb, b.lz) == 0) continue;
+            const int vx = ux + CX[q], vy = uy + CY[q];
+            const int sb = (zb * b.ny + wrapb(vy, b.ny)) * b.nx + wrapb(vx, b.nx);
+            const int lb = b.flag[sb] & LABEL_MASK;
+            if (lb == k + 1 || (lb != 0 && lb < k + 1)) continue;
+            // the crossed triangle: least miss distance among the candidates of the cells
+            // the link's bounding box touches
+            const double p0[3] = {(double)ux, (double)uy, (double)uz};
+            const double p1[3] = {(double)vx, (double)vy, (double)vz};
+            int c0[3], c1[3];
+            double lo[3], hi[3];
+            for (int d = 0; d < 3; ++d) {
+                lo[d] = fmin(p0[d], p1[d]);
+                hi[d] = fmax(p0[d], p1[d]);
+                c0[d] = max((int)lo[d] - cs.lo[d], 0);
+                c1[d] = min((int)hi[d] - cs.lo[d], cs.dim[d] - 1);
+            }
+            int best = -1;
+            double bd = __builtin_inf();
+            for (int cz = c0[2]; cz <= c1[2]; ++cz)
+                for (int cy = c0[1]; cy <= c1[1]; ++cy)
+                    for (int cx = c0[0]; cx <= c1[0]; ++cx) {
+                        const int cell = (cz * dy + cy) * dx + cx;
+                        const int e1 = min(st[cell + 1], lmax);
+                        for (int e = st[cell]; e < e1; ++e) {
+                            const int t = list[e];
+                            if ((unsigned)t >= (unsigned)b.ttot) continue;   // never expected
+                            double v[3][3];
+                            tri_vertices(b, t, v);
+                            bool ok = true;
+                            for (int d = 0; d < 3 && ok; ++d) {
+                                const double tl = fmin(v[0][d], fmin(v[1][d], v[2][d]));
+                                const double th = fmax(v[0][d], fmax(v[1][d], v[2][d]));
+                                ok = !(tl > hi[d] || th < lo[d]);
+                            }
+                            if (!ok) continue;
+                            const double md = miss_distance(p0, p1, v[0], v[1], v[2]);
+                            if (md < bd || (md == bd && t < best)) {
+                                bd = md;
+                                best = t;
+                            }
+                        }
+                    }
+            if (!have_a) {
+                densities<S>(b, b.f, sa, ra0, ra1);
+                have_a = true;
+            }
+            float rb0, rb1;
+            densities<S>(b, b.f, sb, rb0, rb1);
+            const int i = atomicAdd(&b.nlinks[k], 1);
+            if (i >= b.link_cap) {
+                atomicOr(&b.status[ST_BBOVER], 1);
+                continue;
+            }
+            BBLink L;
+            L.a = sa;
+            L.b = sb;
+            L.q = q;
+            L.tri = best;
+            L.rho[0] = ra0;
+            L.rho[1] = ra1;
+            L.rho[2] = rb0;
+            L.rho[3] = rb1;
+            b.links[(size_t)k * b.link_cap + i] = L;
+            if (best < 0) atomicAdd(&b.status[ST_BBLOST], 1);
+        }
+    }
+}
+
+template <int S>
+__global__ void __launch_bounds__(256) k_bb_swap(BBArgs b) {
+    const int k = blockIdx.y, i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= min(b.nlinks[k], b.link_cap)) return;
+    const BBLink L = b.links[(size_t)k * b.link_cap + i];
+    const int q = L.q, qb = OPP[q];
+    float ub[3] = {0.f, 0.f, 0.f};
+    int4 tr = make_int4(0, 0, 0, 0);
+    if (L.tri >= 0) {
+        tr = b.tri[L.tri];
+        const double4 A = b.V[tr.x], B = b.V[tr.y], C = b.V[tr.z];
+        ub[0] = (float)((A.x + B.x + C.x) / 3.0);
+        ub[1] = (float)((A.y + B.y + C.y) / 3.0);
+        ub[2] = (float)((A.z + B.z + C.z) / 3.0);
+    }
+    const float eu = ub[0] * CX[q] + ub[1] * CY[q] + ub[2] * CZ[q];
+    float dp = 0.f;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const float rb = 0.5f * (L.rho[c] + L.rho[2 + c]);
+        const float delta = 6.0f * wq(q) * rb * eu;
+        const float va = popl<S>(b.f, c, q, b.N, L.a, b.shift[c]);
+        const float vb = popl<S>(b.f, c, qb, b.N, L.b, b.shift[c]);
+        pops<S>(b.f, c, q, b.N, L.a, vb + delta, b.shift[c]);
+        pops<S>(b.f, c, qb, b.N, L.b, va - delta, b.shift[c]);
+        dp += 2.0f * va - 2.0f * vb - 2.0f * delta;
+    }
+    if (L.tri < 0) return;
+    const float third = dp / 3.0f;
+    const long long p[3] = {fix40(third * CX[q]), fix40(third * CY[q]), fix40(third * CZ[q])};
+    const int nodes[3] = {tr.x, tr.y, tr.z};
+#pragma unroll
+    for (int m = 0; m < 3; ++m)
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+            if (p[d]) atomicAdd((unsigned long long *)&b.pex[3 * (size_t)nodes[m] + d], (unsigned long long)p[d]);
+}
+
+template <int S>
+__global__ void __launch_bounds__(256) k_bb_reaction(BBArgs b) {
+    const int k = blockIdx.y, i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= min(b.nlinks[k], b.link_cap)) return;
+    const BBLink L = b.links[(size_t)k * b.link_cap + i];
+    if (L.tri < 0) return;
+    const int q = L.q;
+    const int la = b.flag[L.a] & LABEL_MASK, lb = b.flag[L.b] & LABEL_MASK;
+    // wetting offsets of the boundary seen from each side (the other side's capsule if it
+    // is one, else this side's)
+    const float dra = b.cap_drho[(lb != 0 ? lb : la) - 1];
+    const float drb = b.cap_drho[(la != 0 ? la : lb) - 1];
+    float ra[2], rbv[2];
+    densities<S>(b, b.fnew, L.a, ra[0], ra[1]);
+    densities<S>(b, b.fnew, L.b, rbv[0], rbv[1]);
+    const float w = is_axis(q) ? b.ws_axis : b.ws_diag;
+    float r = 0.f;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const int cq = 1 - c;
+        const float sg = cq == 0 ? 1.f : -1.f;
+        const float pa = 1.0f - expf(-ra[c] * b.inv_rho0), pb = 1.0f - expf(-rbv[c] * b.inv_rho0);
+        const float sa = fmaxf(ra[cq] + sg * dra, 0.f), sb = fmaxf(rbv[cq] + sg * drb, 0.f);
+        r += b.G * w * (pa * (1.0f - expf(-sa * b.inv_rho0)) - pb * (1.0f - expf(-sb * b.inv_rho0)));
+    }
+    const float third = r / 3.0f;
+    const long long p[3] = {fix40(third * CX[q]), fix40(third * CY[q]), fix40(third * CZ[q])};
+    const int4 tr = b.tri[L.tri];
+    const int nodes[3] = {tr.x, tr.y, tr.z};
+#pragma unroll
+    for (int m = 0; m < 3; ++m)
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+            if (p[d]) atomicAdd((unsigned long long *)&b.rsc[3 * (size_t)nodes[m] + d], (unsigned long long)p[d]);
+}
+
+// Newtonian nodes: v += (F_membrane + (P_ex(n) + P_ex(n-1)) / 2 + R_sc) / m, x += v; the
+// accumulators and the link counts are cleared for the next step
+__global__ void __launch_bounds__(256) k_bb_nodes(BBArgs b) {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n == 0)   // this step's link counts are kept (observables) and the counters cleared
+        for (int k = 0; k < b.ncap; ++k) {
+            b.nlinks[b.ncap + k] = b.nlinks[k];
+            b.nlinks[k] = 0;
+        }
+    if (n >= b.ntot) return;
+    const float4 Fm = b.F[b.slot[n]];
+    const float4 Pp = b.pprev[n];
+    float pe[3], rs[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        pe[d] = unfix40(b.pex[3 * (size_t)n + d]);
+        rs[d] = unfix40(b.rsc[3 * (size_t)n + d]);
+        b.pex[3 * (size_t)n + d] = 0;
+        b.rsc[3 * (size_t)n + d] = 0;
+    }
+    const float ff[3] = {0.5f * (pe[0] + Pp.x) + rs[0], 0.5f * (pe[1] + Pp.y) + rs[1],
+                         0.5f * (pe[2] + Pp.z) + rs[2]};
+    double4 V = b.V[n], X = b.X[n];
+    V.x += ((double)Fm.x + (double)ff[0]) * b.inv_mass;
+    V.y += ((double)Fm.y + (double)ff[1]) * b.inv_mass;
+    V.z += ((double)Fm.z + (double)ff[2]) * b.inv_mass;
+    X.x += V.x;
+    X.y += V.y;
+    X.z += V.z;
+    b.V[n] = V;
+    b.X[n] = X;
+    b.pprev[n] = make_float4(pe[0], pe[1], pe[2], 0.f);
+    b.ffl[n] = make_float4(ff[0], ff[1], ff[2], 0.f);
+    b.R[n] = make_float4(rs[0], rs[1], rs[2], 0.f);
+}
+
+// ------------------------------------------------------------------------------------
+// Launchers
+// ------------------------------------------------------------------------------------
+void launch_bb_before(const BBArgs &b, int storage, hipStream_t st) {
+    const int tb = (b.ttot + 255) / 256;
+    hipLaunchKernelGGL(k_bb_bin_count, dim3(tb), dim3(256), 0, st, b);
+    hipLaunchKernelGGL(k_bb_bin_scan, dim3(b.ncap), dim3(1024), 0, st, b);
+    hipLaunchKernelGGL(k_bb_bin_fill, dim3(tb), dim3(256), 0, st, b);
+    const dim3 lg(GMAX, b.ncap), sg((b.link_cap + 255) / 256, b.ncap);
+    switch (storage) {
+        case 0:
+            hipLaunchKernelGGL(k_bb_links<0>, lg, dim3(256), 0, st, b);
+            hipLaunchKernelGGL(k_bb_swap<0>, sg, dim3(256), 0, st, b);
+            break;
+        case 1:
+            hipLaunchKernelGGL(k_bb_links<1>, lg, dim3(256), 0, st, b);
+            hipLaunchKernelGGL(k_bb_swap<1>, sg, dim3(256), 0, st, b);
+            break;
+        default:
+            hipLaunchKernelGGL(k_bb_links<2>, lg, dim3(256), 0, st, b);
+            hipLaunchKernelGGL(k_bb_swap<2>, sg, dim3(256), 0, st, b);
+            break;
+    }
+}
+
+void launch_bb_after(const BBArgs &b, int storage, hipStream_t st) {
+    const dim3 sg((b.link_cap + 255) / 256, b.ncap);
+    switch (storage) {
+        case 0: hipLaunchKernelGGL(k_bb_reaction<0>, sg, dim3(256), 0, st, b); break;
+        case 1: hipLaunchKernelGGL(k_bb_reaction<1>, sg, dim3(256), 0, st, b); break;
+        default: hipLaunchKernelGGL(k_bb_reaction<2>, sg, dim3(256), 0, st, b); break;
+    }
+    hipLaunchKernelGGL(k_bb_nodes, dim3((b.ntot + 255) / 256), dim3(256), 0, st, b);
+}
+
+}  // namespace lbmx

@@ -43,7 +43,9 @@ constexpr int FILL_COLS = 2048;   // window columns (x * y) the spreading kernel
 // partial sums of another step (never expected), [5] a capsule window left the slab of
 // its capsule
 constexpr int ST_UNSTABLE = 0, ST_LOST = 1, ST_OVERFLOW = 2, ST_WIDE = 3, ST_SYNC = 4,
-              ST_SLAB = 5, ST_WORDS = 6;
+              ST_SLAB = 5, ST_BBLOST = 6, ST_BBOVER = 7, ST_WORDS = 8;
+// [6] bounce-back links that found no triangle (count), [7] a bounce-back bin or link
+// list overflowed, or a triangle spans more than BB_SPAN cells per axis
 
 // Slabs: with a wall, the lattice is a stack of boxes of lz planes, each starting with a
 // solid layer (lz = nz: one box).  Position of plane z inside its slab.
@@ -171,7 +173,55 @@ struct MembraneArgs {
     int nx, ny, nz, wall;
     int lz;                 // slab height (nz: one box)
     float hertz_xi, hertz_d0;
+    int bb;                 // bounce-back coupling: no spreading (labels only), and the
+                            // reaction in R is an observable, not a pending force
 };
+
+// ------------------------------------------------------------------------------------
+// Bounce-back coupling (bounce.hip)
+// ------------------------------------------------------------------------------------
+constexpr int BB_SPAN = 3;                       // cells per axis a triangle may cover
+constexpr int BB_PER_TRI = BB_SPAN * BB_SPAN * BB_SPAN;
+
+// a link from site a inside capsule k to site b = a + e_q outside it, the triangle it
+// crosses (-1: none found) and the densities of both sites before the bounce-back
+struct BBLink {
+    int a, b, q, tri;
+    float rho[4];           // component 0 and 1 at a, then at b
+};
+
+struct BBArgs {
+    const CapDev *caps;
+    const CapState *cst;
+    int ncap, ntot, ttot;
+    const int4 *tri;        // [Ttot] global node indices a, b, c and capsule index
+    double4 *X;             // [Ntot] node positions
+    double4 *V;             // [Ntot] node velocities
+    const float4 *F;        // [Ntot] membrane forces in row order
+    const int *slot;        // [Ntot] place of each node in the row order
+    const uint8_t *flag;
+    void *f;                // populations of this step's input (changed in place)
+    const void *fnew;       // populations after the fluid step
+    int N, nx, ny, nz, wall, lz;
+    float shift[2];
+    int *bcount;            // [ncap][GMAX3] triangles per window cell (0 between steps)
+    int *bstart;            // [ncap][GMAX3 + 1] first entry of each cell
+    int *blist;             // [BB_PER_TRI * Ttot] triangle indices by cell
+    BBLink *links;          // [ncap][link_cap]
+    int link_cap;
+    int *nlinks;            // [2][ncap] links of this step, then those of the last step
+    long long *pex;         // [Ntot][3] momentum exchanged this step, 2^-40 units
+    long long *rsc;         // [Ntot][3] Shan-Chen reaction of this step, 2^-40 units
+    float4 *pprev;          // [Ntot] momentum exchanged in the previous step
+    float4 *ffl;            // [Ntot] force of the fluid on each node in the last step
+    float4 *R;              // [Ntot] Shan-Chen reaction on each node in the last step
+    int *status;
+    float G, ws_axis, ws_diag, inv_rho0;
+    const float *cap_drho;
+    double inv_mass;        // 1 / node mass
+};
+void launch_bb_before(const BBArgs &b, int storage, hipStream_t st);
+void launch_bb_after(const BBArgs &b, int storage, hipStream_t st);
 
 // Launchers (host functions, defined in the .hip files).
 template <int S> void launch_init_eq(const double *rho_dev, void *f, int nx, int ny, int nz,

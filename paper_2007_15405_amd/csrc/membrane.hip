@@ -619,7 +619,9 @@ __device__ __forceinline__ void membrane_body(const MembraneArgs &m, int blk, in
         fh[d] = group_sum8(fh[d]);
     }
     if (sl == 0) {
-        const float4 R = m.R[n];
+        // the pending reaction of the immersed boundary (with bounce-back R holds the last
+        // step's reaction for the observables; the nodes take it in their own update)
+        const float4 R = m.bb ? make_float4(0.f, 0.f, 0.f, 0.f) : m.R[n];
         m.F[m.slot[n]] = make_float4(f[0] + fh[0] + R.x, f[1] + fh[1] + R.y, f[2] + fh[2] + R.z, 0.f);
         m.Fh[n] = make_float4(fh[0], fh[1], fh[2], 0.f);
     }
@@ -685,7 +687,8 @@ __device__ __forceinline__ void window_own_body(const MembraneArgs &m, int k, in
     while (nnode > 1 && gcd_int(p, nnode) != 1) ++p;
     const double zs = (double)(ck.lo[2] + lz);
     __syncthreads();
-    for (int i0 = 0; i0 < nnode; i0 += 2 * OWN_BLK) {
+    // with bounce-back nothing is spread: the window carries the labels only
+    for (int i0 = 0; i0 < (m.bb ? 0 : nnode); i0 += 2 * OWN_BLK) {
         // two nodes per thread, both loaded before either is spread
         double4 X[2];
         float4 F[2];
@@ -806,7 +809,9 @@ __device__ __forceinline__ void window_combine_body(const MembraneArgs &m, int k
         }
         const int s = (z * m.ny + wrap_near(uy, m.ny)) * m.nx + wrap_near(ux, m.nx);
         m.flag[s] = (uint8_t)(lab | AUX_BIT);
-        m.ibm[s] = make_float4(f[0], f[1], f[2], c);
+        // bounce-back: no spread force; coverage 1 keeps the fluid step's reaction output
+        // (unused then) from counting as lost
+        m.ibm[s] = make_float4(f[0], f[1], f[2], m.bb ? 1.0f : c);
     }
 }
 

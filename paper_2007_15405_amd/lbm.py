@@ -39,6 +39,7 @@ class Params(C.Structure):
         ("rho_shift", C.c_double * 2), ("stream", C.c_void_p), ("device", C.c_int32),
         ("stream_given", C.c_int32), ("slab_nz", C.c_int32),
         ("slab_film_height", C.POINTER(C.c_double)),
+        ("coupling", C.c_int32), ("node_mass", C.c_double),
     ]
 
 
@@ -50,14 +51,15 @@ class CapsuleParams(C.Structure):
 class CapsuleObs(C.Structure):
     _fields_ = [("centroid", C.c_double * 3), ("volume", C.c_double),
                 ("f_anchor", C.c_double * 3), ("f_capillary", C.c_double * 3),
-                ("f_hertz", C.c_double * 3)]
+                ("f_hertz", C.c_double * 3), ("f_fluid", C.c_double * 3)]
 
 
 class Summary(C.Structure):
     _fields_ = [("mass", C.c_double * 2), ("momentum", C.c_double * 3),
                 ("pending", C.c_double * 3), ("step", C.c_int64),
                 ("lost_reaction", C.c_int64), ("n_capsules", C.c_int32),
-                ("unstable", C.c_int32)]
+                ("unstable", C.c_int32), ("node_momentum", C.c_double * 3),
+                ("links", C.c_int64), ("lost_links", C.c_int64)]
 
 
 class Obs(C.Structure):
@@ -212,6 +214,8 @@ class Sim:
             p.slab_film_height = _dp(films)
         p.hertz_xi, p.hertz_delta0 = cfg["hertz_xi"], cfg["hertz_delta0"]
         p.plane_dz = cfg["plane_dz"]
+        p.coupling = int(cfg.get("coupling", 0))
+        p.node_mass = float(cfg.get("node_mass", 25.0))
         p.rho_shift[0], p.rho_shift[1] = rho_shift
         if stream == "torch":
             s = _torch_stream()
@@ -276,7 +280,8 @@ class Sim:
         out = dict(status=st, summary=dict(
             mass=np.array(s.mass), momentum=np.array(s.momentum), pending=np.array(s.pending),
             step=s.step, lost_reaction=s.lost_reaction, n_capsules=s.n_capsules,
-            unstable=s.unstable))
+            unstable=s.unstable, node_momentum=np.array(s.node_momentum), links=s.links,
+            lost_links=s.lost_links))
         out["slab_mass"] = sm
         if rho:
             out["rho"] = r
@@ -287,7 +292,8 @@ class Sim:
             out["capsules"] = [dict(centroid=np.array(c.centroid), volume=c.volume,
                                     f_anchor=np.array(c.f_anchor),
                                     f_capillary=np.array(c.f_capillary),
-                                    f_hertz=np.array(c.f_hertz)) for c in caps]
+                                    f_hertz=np.array(c.f_hertz), f_fluid=np.array(c.f_fluid))
+                               for c in caps]
         return out
 
     def rho(self) -> np.ndarray:
