@@ -393,6 +393,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched form")
+    ap.add_argument("--no-bounce-back", action="store_true",
+                    help="skip the bounce-back coupling leg")
     ap.add_argument("--batch-only", action="store_true", help="only the batched form")
     ap.add_argument("--network-kernels", action="store_true",
                     help="only the network's kernels on synthetic data (for kernel traces): "
@@ -460,6 +462,17 @@ def main():
         print(f"# {st}: {res[st]['mlups']:.1f} MLUPS, {res[st]['ms_per_step']:.4f} ms/step, "
               f"fluid {res[st]['fluid_ms']:.4f} ms = {res[st]['achieved_gbs']:.0f} GB/s",
               file=sys.stderr, flush=True)
+    # the paper's own coupling (half-way bounce-back on the membrane, momentum exchange,
+    # Newtonian nodes) on the same box, FP32 storage
+    coupling = {}
+    if not args.no_bounce_back:
+        bcfg = dict(cfg, coupling=1)
+        fixed = (args.tile, args.zchunk) if args.tile is not None else None
+        coupling["bounce_back"] = run_gpu(bcfg, "f32", min(args.steps, 100), args.warmup,
+                                          not args.no_tune and fixed is None, fixed)
+        b = coupling["bounce_back"]
+        print(f"# bounce-back f32: {b['mlups']:.1f} MLUPS, {b['ms_per_step']:.4f} ms/step",
+              file=sys.stderr, flush=True)
     head = res["f32"] if "f32" in res else next(iter(res.values()))
     head_st = "f32" if "f32" in res else next(iter(res))
     line = dict(
@@ -495,6 +508,10 @@ def main():
                                   launch=v["launch"])
                           for k, v in res.items()},
         batched=batched or None,
+        couplings={k: dict(mlups=round(v["mlups"], 2), ms_per_step=round(v["ms_per_step"], 5),
+                           fluid_ms=round(v["fluid_ms"], 5), kernels_ms=v["kernels"],
+                           launch=v["launch"])
+                   for k, v in coupling.items()} or None,
     )
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(cfg)

@@ -91,6 +91,7 @@ struct lbm_handle {
     float4 *d_pprev = nullptr, *d_ffl = nullptr;
     int *d_bcount = nullptr, *d_bstart = nullptr, *d_blist = nullptr, *d_nlinks = nullptr;
     BBLink *d_links = nullptr;
+    float4 *d_tpos = nullptr;
     int link_cap = 0;
 };
 
@@ -173,7 +174,7 @@ static void free_all(lbm_handle *h) {
                     h->d_off, h->d_list, h->d_marks, h->d_rowstart, h->d_slot, h->d_wbuf,
                     h->d_wpar, h->d_part, h->d_xrow, h->d_edge, h->d_eth0, h->d_eoff,
                     h->d_elist, h->d_V, h->d_pex, h->d_rsc, h->d_pprev, h->d_ffl,
-                    h->d_bcount, h->d_bstart, h->d_blist, h->d_nlinks, h->d_links};
+                    h->d_bcount, h->d_bstart, h->d_blist, h->d_nlinks, h->d_links, h->d_tpos};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     free_prof(h->prof);
@@ -644,7 +645,8 @@ static lbm_status finalize(lbm_handle *h) {
             dalloc(&h->d_bstart, (size_t)ncap * (GMAX3 + 1)) != hipSuccess ||
             dalloc(&h->d_blist, (size_t)BB_PER_TRI * tt) != hipSuccess ||
             dalloc(&h->d_nlinks, 2 * (size_t)ncap) != hipSuccess ||
-            dalloc(&h->d_links, (size_t)ncap * h->link_cap) != hipSuccess)
+            dalloc(&h->d_links, (size_t)ncap * h->link_cap) != hipSuccess ||
+            dalloc(&h->d_tpos, 3 * tt) != hipSuccess)
             return fail(h, LBM_E_NOMEM, "device allocation failed (bounce-back)");
         HIPCHK(h, hipMemsetAsync(h->d_V, 0, nt * sizeof(double4), h->st));
         HIPCHK(h, hipMemsetAsync(h->d_pex, 0, 3 * nt * sizeof(long long), h->st));
@@ -668,7 +670,8 @@ static BBArgs bb_args(lbm_handle *h, int cur) {
     b.tri = h->d_tri; b.X = h->d_X; b.V = h->d_V; b.F = h->d_F; b.slot = h->d_slot;
     b.flag = h->flag;
     b.f = h->f[cur];
-    b.fnew = h->f[1 - cur];
+    b.dens = h->ro;
+    b.tpos = h->d_tpos;
     b.N = h->N; b.nx = h->nx; b.ny = h->ny; b.nz = h->nz; b.wall = h->wall; b.lz = h->lz;
     b.shift[0] = shift_of(h, 0);
     b.shift[1] = shift_of(h, 1);
@@ -726,6 +729,7 @@ static FluidArgs fluid_args(lbm_handle *h, int cur) {
     for (int d = 0; d < 3; ++d) a.g[d] = (float)h->p.body_force[d];
     a.wall_drho = (float)h->p.wall_drho;
     a.keepf = !(h->p.tau[0] == 1.0 && h->p.tau[1] == 1.0);
+    a.bb = !h->caps.empty() && h->p.coupling == 1;
     a.zero_drho = h->p.wall_drho == 0.0;
     for (const HostCap &c : h->caps) a.zero_drho = a.zero_drho && c.p.wet_drho == 0.0;
     return a;

@@ -6,18 +6,20 @@
 // Per step, after the capsule reduction (window), the membrane forces and the side labels:
 //   k_bb_bin_count / k_bb_bin_scan / k_bb_bin_fill: the triangles of each capsule binned
 //     into the unit cells of its window (counting sort; the counts return to zero);
-//   k_bb_links: every link from a site inside capsule k to a fluid site of another side
-//     (exterior, or a capsule of higher index) finds its triangle: among the triangles
-//     whose bounding box meets the link's, the least miss distance, lowest index on ties;
-//     the link record keeps both sites' densities before any population is changed;
+//   k_bb_find: every link from a site inside capsule k to a fluid site of another side
+//     (exterior, or a capsule of higher index) is appended to the capsule's link list;
+//   k_bb_resolve: 16 lanes per link find its triangle (among the triangles whose bounding
+//     box meets the link's, the least miss distance, lowest index on ties) and the
+//     densities of both sites before any population is changed;
 //   k_bb_swap: the bounce-back on the post-collision populations in place, so that plain
 //     pull streaming delivers f_q(b) = f*_qbar(b) + delta and f_qbar(a) = f*_q(a) - delta,
 //     delta = 2 w_q rho u_b . e_q / c_s^2 (rho the link-mean density of the component, u_b
 //     the mean velocity of the triangle's nodes); the exchanged momentum
 //     (2 f*_q(a) - 2 f*_qbar(b) - 2 delta) e_q goes a third to each node of the triangle;
 //   (the fluid step)
-//   k_bb_reaction: the Shan-Chen force across each link, from the densities after the
-//     fluid step and the same substitution, returned to the triangle the same way;
+//   k_bb_reaction: the Shan-Chen force across each link, from the densities and psi the
+//     fluid step used (stored on window sites) with the same substitution, returned to
+//     the triangle the same way;
 //   k_bb_nodes: v += (F_membrane + (P_ex(n) + P_ex(n-1)) / 2 + R_sc) / m, x += v.
 // Node sums are 64-bit fixed point (2^-40), so they do not depend on the order of the
 // atomic adds.  Decisions (labels, triangle choice) use the FP32-rounded node positions
@@ -98,18 +100,6 @@ __device__ __forceinline__ void pops(void *f, int c, int q, int N, int s, float 
     ((T *)f)[(size_t)(c * Q + q) * N + s] = Codec<S>::enc(v, wq(q) * sh);
 }
 
-template <int S>
-__device__ __forceinline__ void densities(const BBArgs &b, const void *f, int s, float &r0, float &r1) {
-    float a0 = 0.f, a1 = 0.f;
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-        a0 += popl<S>(f, 0, q, b.N, s, b.shift[0]);
-        a1 += popl<S>(f, 1, q, b.N, s, b.shift[1]);
-    }
-    r0 = a0;
-    r1 = a1;
-}
-
 }  // namespace
 
 // ------------------------------------------------------------------------------------
@@ -134,6 +124,14 @@ __global__ void __launch_bounds__(256) k_bb_bin_count(BBArgs b) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= b.ttot) return;
     const int k = b.tri[t].w;
+    {
+        // the FP32-rounded vertices, compact for the link search
+        double v[3][3];
+        tri_vertices(b, t, v);
+#pragma unroll
+        for (int m = 0; m < 3; ++m)
+            b.tpos[3 * (size_t)t + m] = make_float4((float)v[m][0], (float)v[m][1], (float)v[m][2], 0.f);
+    }
     int c0[3], c1[3];
     if (!tri_cells(b, t, k, c0, c1)) {
         atomicOr(&b.status[ST_BBOVER], 1);
@@ -207,101 +205,157 @@ __global__ void __launch_bounds__(256) k_bb_bin_fill(BBArgs b) {
 // ------------------------------------------------------------------------------------
 // Links and bounce-back
 // ------------------------------------------------------------------------------------
-// plane lz of capsule k's window: the links of its inside sites
-template <int S>
-__global__ void __launch_bounds__(256) k_bb_links(BBArgs b) {
+// plane lz of capsule k's window: the links of its inside sites, appended as (a, b, q)
+__global__ void __launch_bounds__(256) k_bb_find(BBArgs b) {
     const int k = blockIdx.y, lz = blockIdx.x;
     const CapState cs = b.cst[k];
     if (lz >= cs.dim[2]) return;
-    const CapDev cd = b.caps[k];
     const int dx = cs.dim[0], dy = cs.dim[1];
     const int uz = cs.lo[2] + lz, z = wrapb(uz, b.nz);
     if (b.wall && slab_pos(z, b.lz) == 0) return;
-    const int *st = b.bstart + (size_t)k * (GMAX3 + 1);
-    const int *list = b.blist + (size_t)BB_PER_TRI * cd.tri0;
-    const int lmax = BB_PER_TRI * cd.nt;
     for (int col = threadIdx.x; col < dx * dy; col += blockDim.x) {
         const int ly = col / dx, lx = col - ly * dx;
         const int ux = cs.lo[0] + lx, uy = cs.lo[1] + ly;
         const int sa = (z * b.ny + wrapb(uy, b.ny)) * b.nx + wrapb(ux, b.nx);
         if ((b.flag[sa] & LABEL_MASK) != k + 1) continue;
-        bool have_a = false;
-        float ra0 = 0.f, ra1 = 0.f;
+        int sb[Q - 1];
+        unsigned mask = 0u;
         for (int q = 1; q < Q; ++q) {
-            const int vz = uz + CZ[q], zb = wrapb(vz, b.nz);
+            const int zb = wrapb(uz + CZ[q], b.nz);
+            sb[q - 1] = (zb * b.ny + wrapb(uy + CY[q], b.ny)) * b.nx + wrapb(ux + CX[q], b.nx);
             if (b.wall && slab_pos(zb, b.lz) == 0) continue;
-            const int vx = ux + CX[q], vy = uy + CY[q];
-            const int sb = (zb * b.ny + wrapb(vy, b.ny)) * b.nx + wrapb(vx, b.nx);
-            const int lb = b.flag[sb] & LABEL_MASK;
+            const int lb = b.flag[sb[q - 1]] & LABEL_MASK;
             if (lb == k + 1 || (lb != 0 && lb < k + 1)) continue;
-            // the crossed triangle: least miss distance among the candidates of the cells
-            // the link's bounding box touches
-            const double p0[3] = {(double)ux, (double)uy, (double)uz};
-            const double p1[3] = {(double)vx, (double)vy, (double)vz};
-            int c0[3], c1[3];
-            double lo[3], hi[3];
-            for (int d = 0; d < 3; ++d) {
-                lo[d] = fmin(p0[d], p1[d]);
-                hi[d] = fmax(p0[d], p1[d]);
-                c0[d] = max((int)lo[d] - cs.lo[d], 0);
-                c1[d] = min((int)hi[d] - cs.lo[d], cs.dim[d] - 1);
-            }
-            int best = -1;
-            double bd = __builtin_inf();
-            for (int cz = c0[2]; cz <= c1[2]; ++cz)
-                for (int cy = c0[1]; cy <= c1[1]; ++cy)
-                    for (int cx = c0[0]; cx <= c1[0]; ++cx) {
-                        const int cell = (cz * dy + cy) * dx + cx;
-                        const int e1 = min(st[cell + 1], lmax);
-                        for (int e = st[cell]; e < e1; ++e) {
-                            const int t = list[e];
-                            if ((unsigned)t >= (unsigned)b.ttot) continue;   // never expected
-                            double v[3][3];
-                            tri_vertices(b, t, v);
-                            bool ok = true;
-                            for (int d = 0; d < 3 && ok; ++d) {
-                                const double tl = fmin(v[0][d], fmin(v[1][d], v[2][d]));
-                                const double th = fmax(v[0][d], fmax(v[1][d], v[2][d]));
-                                ok = !(tl > hi[d] || th < lo[d]);
-                            }
-                            if (!ok) continue;
-                            const double md = miss_distance(p0, p1, v[0], v[1], v[2]);
-                            if (md < bd || (md == bd && t < best)) {
-                                bd = md;
-                                best = t;
-                            }
-                        }
-                    }
-            if (!have_a) {
-                densities<S>(b, b.f, sa, ra0, ra1);
-                have_a = true;
-            }
-            float rb0, rb1;
-            densities<S>(b, b.f, sb, rb0, rb1);
-            const int i = atomicAdd(&b.nlinks[k], 1);
+            mask |= 1u << q;
+        }
+        if (!mask) continue;
+        int i = atomicAdd(&b.nlinks[k], __popc(mask));
+        for (int q = 1; q < Q; ++q) {
+            if (!(mask & (1u << q))) continue;
             if (i >= b.link_cap) {
                 atomicOr(&b.status[ST_BBOVER], 1);
-                continue;
+                break;
             }
             BBLink L;
             L.a = sa;
-            L.b = sb;
+            L.b = sb[q - 1];
             L.q = q;
-            L.tri = best;
+            L.tri = -1;
+            L.rho[0] = L.rho[1] = L.rho[2] = L.rho[3] = 0.f;
+            b.links[(size_t)k * b.link_cap + i] = L;
+            ++i;
+        }
+    }
+}
+
+// BB_RL lanes per link: the crossed triangle (least miss distance among the candidates of
+// the cells the link's bounding box touches, lowest index on ties; the lanes split the
+// candidates and reduce), and both sites' densities before any population changes
+constexpr int BB_RL = 16;
+
+template <int S>
+__global__ void __launch_bounds__(256) k_bb_resolve(BBArgs b) {
+    const int k = blockIdx.y, sl = threadIdx.x % BB_RL;
+    const int nl = min(b.nlinks[k], b.link_cap);
+    const CapState cs = b.cst[k];
+    const CapDev cd = b.caps[k];
+    const int dx = cs.dim[0], dy = cs.dim[1];
+    const int *st = b.bstart + (size_t)k * (GMAX3 + 1);
+    const int *list = b.blist + (size_t)BB_PER_TRI * cd.tri0;
+    const int lmax = BB_PER_TRI * cd.nt;
+    // groups of BB_RL lanes take links in a grid-stride loop (uniform inside a group)
+    const int g0 = blockIdx.x * (blockDim.x / BB_RL) + threadIdx.x / BB_RL;
+    const int gstride = gridDim.x * (blockDim.x / BB_RL);
+    for (int i = g0; i < nl; i += gstride) {
+        BBLink &L = b.links[(size_t)k * b.link_cap + i];
+        const int sa = L.a, sbi = L.b, q = L.q;
+        // unwrapped coordinates of a in the window's frame, from its lattice index
+        const int ax = sa % b.nx, ay = (sa / b.nx) % b.ny, az = sa / (b.nx * b.ny);
+        const int ux = cs.lo[0] + wrapb(ax - cs.lo[0], b.nx);
+        const int uy = cs.lo[1] + wrapb(ay - cs.lo[1], b.ny);
+        const int uz = cs.lo[2] + wrapb(az - cs.lo[2], b.nz);
+        const double p0[3] = {(double)ux, (double)uy, (double)uz};
+        const double p1[3] = {(double)(ux + CX[q]), (double)(uy + CY[q]), (double)(uz + CZ[q])};
+        double lo[3], hi[3];
+        int c0[3], c1[3];
+        for (int d = 0; d < 3; ++d) {
+            lo[d] = fmin(p0[d], p1[d]);
+            hi[d] = fmax(p0[d], p1[d]);
+            c0[d] = max((int)lo[d] - cs.lo[d], 0);
+            c1[d] = min((int)hi[d] - cs.lo[d], cs.dim[d] - 1);
+        }
+        // candidate entries of the (at most 2 x 2 x 2) cells, concatenated
+        int beg[8], cnt[8], nc = 0, tot = 0;
+        for (int cz = c0[2]; cz <= c1[2]; ++cz)
+            for (int cy = c0[1]; cy <= c1[1]; ++cy)
+                for (int cx = c0[0]; cx <= c1[0]; ++cx) {
+                    const int cell = (cz * dy + cy) * dx + cx;
+                    const int e0 = st[cell], e1 = min(st[cell + 1], lmax);
+                    beg[nc] = e0;
+                    cnt[nc] = max(e1 - e0, 0);
+                    tot += cnt[nc];
+                    ++nc;
+                }
+        double bd = __builtin_inf();
+        int best = 0x7fffffff;
+        for (int e = sl; e < tot; e += BB_RL) {
+            int r = e, n = 0;
+            while (r >= cnt[n]) r -= cnt[n++];
+            const int t = list[beg[n] + r];
+            if ((unsigned)t >= (unsigned)b.ttot) continue;   // never expected
+            const float4 A = b.tpos[3 * (size_t)t], B = b.tpos[3 * (size_t)t + 1],
+                         C = b.tpos[3 * (size_t)t + 2];
+            const double v[3][3] = {{A.x, A.y, A.z}, {B.x, B.y, B.z}, {C.x, C.y, C.z}};
+            bool ok = true;
+            for (int d = 0; d < 3 && ok; ++d) {
+                const double tl = fmin(v[0][d], fmin(v[1][d], v[2][d]));
+                const double th = fmax(v[0][d], fmax(v[1][d], v[2][d]));
+                ok = !(tl > hi[d] || th < lo[d]);
+            }
+            if (!ok) continue;
+            const double md = miss_distance(p0, p1, v[0], v[1], v[2]);
+            if (md < bd || (md == bd && t < best)) {
+                bd = md;
+                best = t;
+            }
+        }
+        // densities of both sites, populations split over the lanes
+        float ra0 = 0.f, ra1 = 0.f, rb0 = 0.f, rb1 = 0.f;
+        for (int qq = sl; qq < Q; qq += BB_RL) {
+            ra0 += popl<S>(b.f, 0, qq, b.N, sa, b.shift[0]);
+            ra1 += popl<S>(b.f, 1, qq, b.N, sa, b.shift[1]);
+            rb0 += popl<S>(b.f, 0, qq, b.N, sbi, b.shift[0]);
+            rb1 += popl<S>(b.f, 1, qq, b.N, sbi, b.shift[1]);
+        }
+        // fixed butterfly over the group: the lexicographic minimum of (distance, index)
+        // and the density sums
+#pragma unroll
+        for (int o = BB_RL / 2; o > 0; o >>= 1) {
+            const double od = __shfl_xor(bd, o, BB_RL);
+            const int ot = __shfl_xor(best, o, BB_RL);
+            if (od < bd || (od == bd && ot < best)) {
+                bd = od;
+                best = ot;
+            }
+            ra0 += __shfl_xor(ra0, o, BB_RL);
+            ra1 += __shfl_xor(ra1, o, BB_RL);
+            rb0 += __shfl_xor(rb0, o, BB_RL);
+            rb1 += __shfl_xor(rb1, o, BB_RL);
+        }
+        if (sl == 0) {
+            const bool found = best != 0x7fffffff;
+            L.tri = found ? best : -1;
             L.rho[0] = ra0;
             L.rho[1] = ra1;
             L.rho[2] = rb0;
             L.rho[3] = rb1;
-            b.links[(size_t)k * b.link_cap + i] = L;
-            if (best < 0) atomicAdd(&b.status[ST_BBLOST], 1);
+            if (!found) atomicAdd(&b.status[ST_BBLOST], 1);
         }
     }
 }
 
 template <int S>
-__global__ void __launch_bounds__(256) k_bb_swap(BBArgs b) {
-    const int k = blockIdx.y, i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= min(b.nlinks[k], b.link_cap)) return;
+__device__ __forceinline__ void bb_swap_one(const BBArgs &b, int k, int i) {
     const BBLink L = b.links[(size_t)k * b.link_cap + i];
     const int q = L.q, qb = OPP[q];
     float ub[3] = {0.f, 0.f, 0.f};
@@ -337,9 +391,18 @@ __global__ void __launch_bounds__(256) k_bb_swap(BBArgs b) {
 }
 
 template <int S>
-__global__ void __launch_bounds__(256) k_bb_reaction(BBArgs b) {
-    const int k = blockIdx.y, i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= min(b.nlinks[k], b.link_cap)) return;
+__global__ void __launch_bounds__(256) k_bb_swap(BBArgs b) {
+    const int k = blockIdx.y, nl = min(b.nlinks[k], b.link_cap);
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nl; i += gridDim.x * blockDim.x)
+        bb_swap_one<S>(b, k, i);
+}
+
+// psi = 1 - exp(-rho / rho0) as the fluid kernel evaluates it
+__device__ __forceinline__ float bb_psi(float rho, float inv_rho0) {
+    return 1.0f - __expf(-rho * inv_rho0);
+}
+
+__device__ __forceinline__ void bb_reaction_one(const BBArgs &b, int k, int i) {
     const BBLink L = b.links[(size_t)k * b.link_cap + i];
     if (L.tri < 0) return;
     const int q = L.q;
@@ -348,18 +411,21 @@ __global__ void __launch_bounds__(256) k_bb_reaction(BBArgs b) {
     // is one, else this side's)
     const float dra = b.cap_drho[(lb != 0 ? lb : la) - 1];
     const float drb = b.cap_drho[(la != 0 ? la : lb) - 1];
-    float ra[2], rbv[2];
-    densities<S>(b, b.fnew, L.a, ra[0], ra[1]);
-    densities<S>(b, b.fnew, L.b, rbv[0], rbv[1]);
+    // densities and psi of both sites as the fluid step used them (written there on the
+    // window sites)
+    const float4 A = b.dens[L.a], B = b.dens[L.b];
+    const float ra[2] = {A.x, A.y}, pa[2] = {A.z, A.w};
+    const float rbv[2] = {B.x, B.y}, pb[2] = {B.z, B.w};
     const float w = is_axis(q) ? b.ws_axis : b.ws_diag;
     float r = 0.f;
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
         const int cq = 1 - c;
         const float sg = cq == 0 ? 1.f : -1.f;
-        const float pa = 1.0f - expf(-ra[c] * b.inv_rho0), pb = 1.0f - expf(-rbv[c] * b.inv_rho0);
-        const float sa = fmaxf(ra[cq] + sg * dra, 0.f), sb = fmaxf(rbv[cq] + sg * drb, 0.f);
-        r += b.G * w * (pa * (1.0f - expf(-sa * b.inv_rho0)) - pb * (1.0f - expf(-sb * b.inv_rho0)));
+        // with a zero offset the substituted psi is the site's own psi of the partner
+        const float qa = dra == 0.f ? pa[cq] : bb_psi(fmaxf(ra[cq] + sg * dra, 0.f), b.inv_rho0);
+        const float qb = drb == 0.f ? pb[cq] : bb_psi(fmaxf(rbv[cq] + sg * drb, 0.f), b.inv_rho0);
+        r += b.G * w * (pa[c] * qa - pb[c] * qb);
     }
     const float third = r / 3.0f;
     const long long p[3] = {fix40(third * CX[q]), fix40(third * CY[q]), fix40(third * CZ[q])};
@@ -370,6 +436,12 @@ __global__ void __launch_bounds__(256) k_bb_reaction(BBArgs b) {
 #pragma unroll
         for (int d = 0; d < 3; ++d)
             if (p[d]) atomicAdd((unsigned long long *)&b.rsc[3 * (size_t)nodes[m] + d], (unsigned long long)p[d]);
+}
+
+__global__ void __launch_bounds__(256) k_bb_reaction(BBArgs b) {
+    const int k = blockIdx.y, nl = min(b.nlinks[k], b.link_cap);
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nl; i += gridDim.x * blockDim.x)
+        bb_reaction_one(b, k, i);
 }
 
 // Newtonian nodes: v += (F_membrane + (P_ex(n) + P_ex(n-1)) / 2 + R_sc) / m, x += v; the
@@ -411,35 +483,39 @@ __global__ void __launch_bounds__(256) k_bb_nodes(BBArgs b) {
 // ------------------------------------------------------------------------------------
 // Launchers
 // ------------------------------------------------------------------------------------
+// link-kernel grid per capsule: enough blocks for the links of an R = 10 capsule in one
+// pass, a grid-stride loop beyond
+static int link_blocks(const BBArgs &b, int per_block) {
+    const int nb = (b.link_cap + per_block - 1) / per_block;
+    return nb < 64 ? nb : 64;
+}
+
 void launch_bb_before(const BBArgs &b, int storage, hipStream_t st) {
     const int tb = (b.ttot + 255) / 256;
     hipLaunchKernelGGL(k_bb_bin_count, dim3(tb), dim3(256), 0, st, b);
     hipLaunchKernelGGL(k_bb_bin_scan, dim3(b.ncap), dim3(1024), 0, st, b);
     hipLaunchKernelGGL(k_bb_bin_fill, dim3(tb), dim3(256), 0, st, b);
-    const dim3 lg(GMAX, b.ncap), sg((b.link_cap + 255) / 256, b.ncap);
+    hipLaunchKernelGGL(k_bb_find, dim3(GMAX, b.ncap), dim3(256), 0, st, b);
+    const dim3 rg(4 * link_blocks(b, 256 / BB_RL), b.ncap), sg(link_blocks(b, 256), b.ncap);
     switch (storage) {
         case 0:
-            hipLaunchKernelGGL(k_bb_links<0>, lg, dim3(256), 0, st, b);
+            hipLaunchKernelGGL(k_bb_resolve<0>, rg, dim3(256), 0, st, b);
             hipLaunchKernelGGL(k_bb_swap<0>, sg, dim3(256), 0, st, b);
             break;
         case 1:
-            hipLaunchKernelGGL(k_bb_links<1>, lg, dim3(256), 0, st, b);
+            hipLaunchKernelGGL(k_bb_resolve<1>, rg, dim3(256), 0, st, b);
             hipLaunchKernelGGL(k_bb_swap<1>, sg, dim3(256), 0, st, b);
             break;
         default:
-            hipLaunchKernelGGL(k_bb_links<2>, lg, dim3(256), 0, st, b);
+            hipLaunchKernelGGL(k_bb_resolve<2>, rg, dim3(256), 0, st, b);
             hipLaunchKernelGGL(k_bb_swap<2>, sg, dim3(256), 0, st, b);
             break;
     }
 }
 
 void launch_bb_after(const BBArgs &b, int storage, hipStream_t st) {
-    const dim3 sg((b.link_cap + 255) / 256, b.ncap);
-    switch (storage) {
-        case 0: hipLaunchKernelGGL(k_bb_reaction<0>, sg, dim3(256), 0, st, b); break;
-        case 1: hipLaunchKernelGGL(k_bb_reaction<1>, sg, dim3(256), 0, st, b); break;
-        default: hipLaunchKernelGGL(k_bb_reaction<2>, sg, dim3(256), 0, st, b); break;
-    }
+    (void)storage;
+    hipLaunchKernelGGL(k_bb_reaction, dim3(link_blocks(b, 256), b.ncap), dim3(256), 0, st, b);
     hipLaunchKernelGGL(k_bb_nodes, dim3((b.ntot + 255) / 256), dim3(256), 0, st, b);
 }
 

@@ -244,7 +244,8 @@ __device__ __forceinline__ void collide_store(const FluidArgs &a, const float (&
                               (jy[0] + jy[1] + 0.5f * (F0[1] + F1[1])) * irt,
                               (jz[0] + jz[1] + 0.5f * (F0[2] + F1[2])) * irt, fb[3]);
         const float ic = fb[3] > 0.f ? 1.0f / fb[3] : 0.f;
-        a.ro[s] = make_float4(rx[0] * ic, rx[1] * ic, rx[2] * ic, 0.f);
+        a.ro[s] = a.bb ? make_float4(rho[0], rho[1], psi0, psi1)
+                       : make_float4(rx[0] * ic, rx[1] * ic, rx[2] * ic, 0.f);
     }
     if ((rx[0] != 0.f || rx[1] != 0.f || rx[2] != 0.f) && !(aux && fb[3] > 0.f))
         atomicAdd(&a.status[ST_LOST], 1);
@@ -603,7 +604,8 @@ __device__ __forceinline__ void collide_store_eq(const FluidArgs &a, const float
                               (jy[0] + jy[1] + 0.5f * (F0[1] + F1[1])) * irt,
                               (jz[0] + jz[1] + 0.5f * (F0[2] + F1[2])) * irt, fb[3]);
         const float ic = fb[3] > 0.f ? 1.0f / fb[3] : 0.f;
-        a.ro[s] = make_float4(rx[0] * ic, rx[1] * ic, rx[2] * ic, 0.f);
+        a.ro[s] = a.bb ? make_float4(rho[0], rho[1], psi0, psi1)
+                       : make_float4(rx[0] * ic, rx[1] * ic, rx[2] * ic, 0.f);
     }
     if ((rx[0] != 0.f || rx[1] != 0.f || rx[2] != 0.f) && !(aux && fb[3] > 0.f))
         atomicAdd(&a.status[ST_LOST], 1);

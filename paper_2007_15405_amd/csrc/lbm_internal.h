@@ -106,6 +106,8 @@ struct FluidArgs {
     float wall_drho;
     float shift[2];         // storage shift rho_s per component (16-bit modes)
     int keepf;              // 0: tau = 1 for both components, so f* = f^eq (moments suffice)
+    int bb;                 // bounce-back coupling: window sites store (rho0, rho1, psi0,
+                            // psi1) in ro instead of the reaction
     int zero_drho;          // 1: the wall and every capsule have a zero wetting offset
 };
 
@@ -201,7 +203,9 @@ struct BBArgs {
     const int *slot;        // [Ntot] place of each node in the row order
     const uint8_t *flag;
     void *f;                // populations of this step's input (changed in place)
-    const void *fnew;       // populations after the fluid step
+    const float4 *dens;     // [N] densities and psi of both components, written by the
+                            // fluid step on window sites (rho0, rho1, psi0, psi1)
+    float4 *tpos;           // [Ttot][3] FP32-rounded triangle vertices of this step
     int N, nx, ny, nz, wall, lz;
     float shift[2];
     int *bcount;            // [ncap][GMAX3] triangles per window cell (0 between steps)
