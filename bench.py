@@ -8,7 +8,8 @@ membrane forces, spreading, fused fluid step, interpolation/advection).
 Prints one JSON line: MLUPS (fluid-site updates per microsecond, both components count
 as one update) for FP32 population storage, the HBM roofline of the dominant kernel
 (the fluid step) measured with HIP events on the library's stream, the same figures for
-the shifted FP16 / BF16 storage, the batched form (64 independent capsule-pair boxes of
+the FP16 / BF16 storage shifted by a constant and the FP16 storage shifted by each site's
+own density (FP32 density per site beside it), the batched form (64 independent capsule-pair boxes of
 sizes 80x60x40 .. 128x96x48, stacked by size into slabs, one fluid launch per step over
 all of them; FP32 and FP16 storage), and the CPU oracle timed on a bounded sample.
 """
@@ -389,7 +390,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--storage", default="all", choices=["all", "f32", "f16", "bf16"])
+    ap.add_argument("--storage", default="all", choices=["all", "f32", "f16", "bf16", "f16site"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched form")
@@ -456,7 +457,7 @@ def main():
     if args.batch_only:
         print(json.dumps(dict(batched=batched)), flush=True)
         return
-    for st in (["f32", "f16", "bf16"] if args.storage == "all" else [args.storage]):
+    for st in (["f32", "f16", "bf16", "f16site"] if args.storage == "all" else [args.storage]):
         fixed = (args.tile, args.zchunk) if args.tile is not None else None
         res[st] = run_gpu(cfg, st, args.steps, args.warmup, not args.no_tune and fixed is None, fixed)
         print(f"# {st}: {res[st]['mlups']:.1f} MLUPS, {res[st]['ms_per_step']:.4f} ms/step, "

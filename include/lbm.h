@@ -84,12 +84,19 @@ typedef enum {
 } lbm_status;
 
 /* Population storage in HBM.  The collision arithmetic is FP32 in every mode.
- * The 16-bit modes store g_i = f_i - w_i * rho_shift[c] (w_i the lattice weights),
- * rounded to nearest even, and decode f_i = g_i + w_i * rho_shift[c]. */
+ * Modes 1 and 2 store g_i = f_i - w_i * rho_shift[c] (w_i the lattice weights), rounded to
+ * nearest even, and decode f_i = g_i + w_i * rho_shift[c].  Mode 3 stores, in FP16,
+ * g_i = f_i - w_i * rho^c(x), shifted by the site's own post-collision density, which is
+ * stored in FP32 beside the populations: the stored values are the small deviations of the
+ * populations from the rest equilibrium at that density, so the minority phase of a
+ * two-component film keeps its relative precision (152 + 16 bytes per site update); it
+ * needs tau = 1 in both components and the immersed-boundary coupling, and runs the
+ * software-pipelined fluid kernels (lbm_set_launch tiles 1..5 and 0 take tile 10). */
 typedef enum {
     LBM_STORE_F32 = 0,
     LBM_STORE_F16_SHIFT = 1,
-    LBM_STORE_BF16_SHIFT = 2
+    LBM_STORE_BF16_SHIFT = 2,
+    LBM_STORE_F16_LOCAL = 3
 } lbm_storage;
 
 typedef struct {
@@ -202,13 +209,30 @@ lbm_status lbm_add_capsule(lbm_handle *h, const lbm_capsule_params *cp, int32_t 
                            const double *xyz, int32_t n_tri, const int32_t *tri,
                            int32_t *id_out);
 
-/* Enqueue n >= 0 time steps on the handle's stream; returns without waiting. */
+/* Add a spherical capsule of the given centre (unwrapped lattice coordinates) and radius:
+ * the library builds the mesh in FP64, a geodesic sphere of n_tri = 20 * 4^L triangles
+ * (L = 0 .. 6; 1280 and 5120 for the configurations of Section 3.2's particle sizes): the
+ * icosahedron with every edge split at its midpoint L times and each new vertex projected
+ * onto the sphere, outward counter-clockwise, and adds it as lbm_add_capsule does (same
+ * limits and errors; LBM_E_INVAL for another n_tri or a non-finite centre or radius). */
+lbm_status lbm_add_sphere_capsule(lbm_handle *h, const lbm_capsule_params *cp,
+                                  const double center[3], double radius, int32_t n_tri,
+                                  int32_t *id_out);
+
+/* Enqueue n >= 0 time steps on the handle's stream; returns without waiting.  One step is
+ * the time step of Section 3.1 as listed at the top of this file: labels, membrane forces,
+ * coupling, and the lattice Boltzmann update of eq. method:boltzmann. */
 lbm_status lbm_step(lbm_handle *h, int64_t n);
 
 /* Wait for all enqueued work; reports LBM_E_UNSTABLE if an instability was flagged. */
 lbm_status lbm_sync(lbm_handle *h);
 
-/* Observables of the current state (synchronises); fills the non-NULL caller buffers. */
+/* Observables of the current state (synchronises); fills the non-NULL caller buffers:
+ * the density fields, the meniscus height of every column (the first upward crossing of
+ * (rho1 - rho2) / (rho1 + rho2) through 0, interpolated linearly, NaN where there is none or
+ * it lies inside a capsule: the meniscus profiles of Section 4.1), each capsule's centroid,
+ * volume and forces (the anchor force is the force sampled on a fixed particle in Section
+ * 4.1), masses and momentum. */
 lbm_status lbm_observables(lbm_handle *h, lbm_obs *out);
 
 /* Densities rho^c written to a caller-owned DEVICE buffer [2][nz][ny][nx] float, on the
@@ -260,7 +284,8 @@ lbm_status lbm_autotune(lbm_handle *h, int32_t reps, int32_t *tile, int32_t *zch
                         double *fluid_ms);
 
 /* Algorithmic HBM bytes per fluid-site update of the fused fluid kernel for the
- * handle's storage: 2 components x 19 populations x (load + store). */
+ * handle's storage: 2 components x 19 populations x (load + store), plus for storage 3 the
+ * FP32 density of both components (load + store). */
 double lbm_bytes_per_site(const lbm_handle *h);
 int64_t lbm_fluid_sites(const lbm_handle *h);
 

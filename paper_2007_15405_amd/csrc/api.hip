@@ -9,6 +9,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 using namespace lbmx;
@@ -54,6 +55,7 @@ struct lbm_handle {
     int mom_blocks = 0;         // moment-reduction blocks per slab
     size_t esize = 4;
     void *f[2] = {nullptr, nullptr};
+    float *rsite[2] = {nullptr, nullptr};   // storage 3: [2][N] site densities per buffer
     int cur = 0;
     uint8_t *flag = nullptr;
     float4 *ibm = nullptr, *uo = nullptr, *ro = nullptr;
@@ -168,7 +170,7 @@ static void free_prof(Prof &pf) {
 }
 
 static void free_all(lbm_handle *h) {
-    void *ptrs[] = {h->f[0], h->f[1], h->flag, h->ibm, h->uo, h->ro, h->psi, h->cap_drho,
+    void *ptrs[] = {h->f[0], h->f[1], h->rsite[0], h->rsite[1], h->flag, h->ibm, h->uo, h->ro, h->psi, h->cap_drho,
                     h->rho_tmp, h->men_tmp, h->status, h->partial, h->d_caps, h->d_cst, h->d_X,
                     h->d_node_cap, h->d_F, h->d_Fh, h->d_R, h->d_tri, h->d_minv, h->d_a0,
                     h->d_off, h->d_list, h->d_marks, h->d_rowstart, h->d_slot, h->d_wbuf,
@@ -280,7 +282,9 @@ static void initial_density(const lbm_params &p, int lz, std::vector<double> &rh
 }
 
 static float shift_of(const lbm_handle *h, int c) {
-    return h->storage == LBM_STORE_F32 ? 0.0f : (float)h->p.rho_shift[c];
+    // storage 3 shifts by each site's own density, not by a constant
+    return (h->storage == LBM_STORE_F32 || h->storage == LBM_STORE_F16_LOCAL)
+               ? 0.0f : (float)h->p.rho_shift[c];
 }
 
 // ------------------------------------------------------------------------------------
@@ -313,7 +317,11 @@ extern "C" lbm_status lbm_init(const lbm_params *p, lbm_handle **out) {
     if (p->init_mode == 1 && p->slab_film_height)
         for (int sl = 0; sl < p->nz / lz; ++sl)
             if (!(p->slab_film_height[sl] >= 0.0)) return bad("slab_film_height must be >= 0");
-    if (p->storage < 0 || p->storage > 2) return bad("storage must be 0, 1 or 2");
+    if (p->storage < 0 || p->storage > 3) return bad("storage must be 0, 1, 2 or 3");
+    if (p->storage == LBM_STORE_F16_LOCAL && !(p->tau[0] == 1.0 && p->tau[1] == 1.0))
+        return bad("storage 3 (FP16 shifted by the site density) needs tau = 1 in both components");
+    if (p->storage == LBM_STORE_F16_LOCAL && p->coupling != 0)
+        return bad("storage 3 is not available with the bounce-back coupling");
     if (!(p->hertz_xi >= 0.0) || !(p->hertz_delta0 >= 0.0)) return bad("invalid Hertz parameters");
     if (p->wall_z0 != 0 && p->wall_z0 != 1) return bad("wall_z0 must be 0 or 1");
     if (p->coupling != 0 && p->coupling != 1) return bad("coupling must be 0 or 1");
@@ -349,6 +357,10 @@ extern "C" lbm_status lbm_init(const lbm_params *p, lbm_handle **out) {
     }
     const size_t N = (size_t)h->N;
     const size_t fbytes = 2 * (size_t)Q * N * h->esize;
+    if (h->storage == LBM_STORE_F16_LOCAL &&
+        (dalloc(&h->rsite[0], 2 * N) != hipSuccess || dalloc(&h->rsite[1], 2 * N) != hipSuccess ||
+         hipMemsetAsync(h->rsite[1], 0, 2 * N * sizeof(float), h->st) != hipSuccess))
+        return die(LBM_E_NOMEM, "device allocation failed");
     if (hipMalloc(&h->f[0], fbytes) != hipSuccess || hipMalloc(&h->f[1], fbytes) != hipSuccess ||
         dalloc(&h->flag, N) != hipSuccess || dalloc(&h->ibm, N) != hipSuccess ||
         dalloc(&h->uo, N) != hipSuccess || dalloc(&h->ro, N) != hipSuccess ||
@@ -379,9 +391,10 @@ extern "C" lbm_status lbm_init(const lbm_params *p, lbm_handle **out) {
     if (e == hipSuccess) {
         const float s0 = shift_of(h, 0), s1 = shift_of(h, 1);
         switch (h->storage) {
-            case 0: launch_init_eq<0>(d_rho, h->f[0], h->nx, h->ny, h->nz, h->wall, h->lz, s0, s1, h->st); break;
-            case 1: launch_init_eq<1>(d_rho, h->f[0], h->nx, h->ny, h->nz, h->wall, h->lz, s0, s1, h->st); break;
-            default: launch_init_eq<2>(d_rho, h->f[0], h->nx, h->ny, h->nz, h->wall, h->lz, s0, s1, h->st); break;
+            case 0: launch_init_eq<0>(d_rho, h->f[0], h->nx, h->ny, h->nz, h->wall, h->lz, s0, s1, nullptr, h->st); break;
+            case 1: launch_init_eq<1>(d_rho, h->f[0], h->nx, h->ny, h->nz, h->wall, h->lz, s0, s1, nullptr, h->st); break;
+            case 2: launch_init_eq<2>(d_rho, h->f[0], h->nx, h->ny, h->nz, h->wall, h->lz, s0, s1, nullptr, h->st); break;
+            default: launch_init_eq<3>(d_rho, h->f[0], h->nx, h->ny, h->nz, h->wall, h->lz, s0, s1, h->rsite[0], h->st); break;
         }
         e = hipGetLastError();
     }
@@ -468,6 +481,84 @@ extern "C" lbm_status lbm_add_capsule(lbm_handle *h, const lbm_capsule_params *c
     h->caps.push_back(std::move(c));
     if (id_out) *id_out = (int32_t)h->caps.size() - 1;
     return LBM_OK;
+}
+
+// Geodesic sphere: the icosahedron (vertices (0, +-1, +-t) and their cyclic permutations,
+// t the golden ratio, on the unit sphere) with every edge split at its midpoint `level`
+// times, each new vertex projected back onto the unit sphere; faces outward and
+// counter-clockwise.  Level L: 10 * 4^L + 2 nodes, 20 * 4^L triangles.  FP64.
+static void icosphere(int level, std::vector<double> &v, std::vector<int32_t> &f) {
+    const double t = (1.0 + std::sqrt(5.0)) / 2.0;
+    const double iv[12][3] = {{-1, t, 0}, {1, t, 0}, {-1, -t, 0}, {1, -t, 0},
+                              {0, -1, t}, {0, 1, t}, {0, -1, -t}, {0, 1, -t},
+                              {t, 0, -1}, {t, 0, 1}, {-t, 0, -1}, {-t, 0, 1}};
+    const int ifc[20][3] = {{0, 11, 5}, {0, 5, 1}, {0, 1, 7}, {0, 7, 10}, {0, 10, 11},
+                            {1, 5, 9}, {5, 11, 4}, {11, 10, 2}, {10, 7, 6}, {7, 1, 8},
+                            {3, 9, 4}, {3, 4, 2}, {3, 2, 6}, {3, 6, 8}, {3, 8, 9},
+                            {4, 9, 5}, {2, 4, 11}, {6, 2, 10}, {8, 6, 7}, {9, 8, 1}};
+    v.clear();
+    f.clear();
+    auto push_unit = [&](double x, double y, double z) {
+        const double n = std::sqrt(x * x + y * y + z * z);
+        v.push_back(x / n);
+        v.push_back(y / n);
+        v.push_back(z / n);
+    };
+    for (const auto &p : iv) push_unit(p[0], p[1], p[2]);
+    for (const auto &q : ifc) f.insert(f.end(), {q[0], q[1], q[2]});
+    for (int l = 0; l < level; ++l) {
+        std::unordered_map<long long, int> cache;   // edge -> midpoint index
+        cache.reserve(f.size());
+        auto mid = [&](int a, int b) {
+            const long long key = a < b ? (long long)a << 32 | b : (long long)b << 32 | a;
+            const auto it = cache.find(key);
+            if (it != cache.end()) return it->second;
+            push_unit((v[3 * a] + v[3 * b]) * 0.5, (v[3 * a + 1] + v[3 * b + 1]) * 0.5,
+                      (v[3 * a + 2] + v[3 * b + 2]) * 0.5);
+            const int idx = (int)(v.size() / 3) - 1;
+            cache.emplace(key, idx);
+            return idx;
+        };
+        std::vector<int32_t> nf;
+        nf.reserve(4 * f.size());
+        for (size_t i = 0; i < f.size(); i += 3) {
+            const int a = f[i], b = f[i + 1], c = f[i + 2];
+            const int ab = mid(a, b), bc = mid(b, c), ca = mid(c, a);
+            nf.insert(nf.end(), {a, ab, ca, b, bc, ab, c, ca, bc, ab, bc, ca});
+        }
+        f.swap(nf);
+    }
+    // outward orientation: normal . (p0 + p1 + p2) > 0
+    for (size_t i = 0; i < f.size(); i += 3) {
+        const double *p0 = &v[3 * f[i]], *p1 = &v[3 * f[i + 1]], *p2 = &v[3 * f[i + 2]];
+        const double e1[3] = {p1[0] - p0[0], p1[1] - p0[1], p1[2] - p0[2]};
+        const double e2[3] = {p2[0] - p0[0], p2[1] - p0[1], p2[2] - p0[2]};
+        const double n[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
+                             e1[0] * e2[1] - e1[1] * e2[0]};
+        const double s = n[0] * (p0[0] + p1[0] + p2[0]) + n[1] * (p0[1] + p1[1] + p2[1]) +
+                         n[2] * (p0[2] + p1[2] + p2[2]);
+        if (s < 0) std::swap(f[i + 1], f[i + 2]);
+    }
+}
+
+extern "C" lbm_status lbm_add_sphere_capsule(lbm_handle *h, const lbm_capsule_params *cp,
+                                             const double center[3], double radius, int32_t n_tri,
+                                             int32_t *id_out) {
+    if (!h) return LBM_E_INVAL;
+    if (!center || !(radius > 0.0) || !std::isfinite(radius) || !std::isfinite(center[0]) ||
+        !std::isfinite(center[1]) || !std::isfinite(center[2]))
+        return fail(h, LBM_E_INVAL, "invalid sphere centre or radius");
+    int level = -1;
+    for (int l = 0, nt = 20; l <= 6; ++l, nt *= 4)
+        if (nt == n_tri) level = l;
+    if (level < 0) return fail(h, LBM_E_INVAL, "n_tri must be 20 * 4^L, L = 0 .. 6");
+    std::vector<double> v;
+    std::vector<int32_t> f;
+    icosphere(level, v, f);
+    for (size_t i = 0; i < v.size(); i += 3)
+        for (int d = 0; d < 3; ++d) v[i + d] = v[i + d] * radius + center[d];
+    return lbm_add_capsule(h, cp, (int32_t)(v.size() / 3), v.data(), (int32_t)(f.size() / 3),
+                           f.data(), id_out);
 }
 
 // Reference geometry of a triangle (FP64): the vertices in an orthonormal in-plane
@@ -714,6 +805,8 @@ static FluidArgs fluid_args(lbm_handle *h, int cur) {
     FluidArgs a{};
     a.fin = h->f[cur];
     a.fout = h->f[1 - cur];
+    a.rin = h->rsite[cur];
+    a.rout = h->rsite[1 - cur];
     a.flag = h->flag; a.ibm = h->ibm; a.uo = h->uo; a.ro = h->ro; a.psi = h->psi;
     a.status = h->status; a.cap_drho = h->cap_drho;
     a.nx = h->nx; a.ny = h->ny; a.nz = h->nz; a.wall = h->wall; a.N = h->N; a.lz = h->lz;
@@ -778,6 +871,16 @@ extern "C" lbm_status lbm_set_launch(lbm_handle *h, int32_t tile, int32_t zchunk
     return LBM_OK;
 }
 
+// one launch of the fluid kernel of the given shape for the handle's storage
+static void enqueue_fluid(const lbm_handle *h, const FluidArgs &a, int tile, int zc, hipStream_t st) {
+    switch (h->storage) {
+        case 0: launch_fluid_tiled<0>(a, tile, zc, st); break;
+        case 1: launch_fluid_tiled<1>(a, tile, zc, st); break;
+        case 2: launch_fluid_tiled<2>(a, tile, zc, st); break;
+        default: launch_fluid_tiled<3>(a, tile, zc, st); break;
+    }
+}
+
 // labels, membrane forces and spreading: the kernels of a step before the fluid kernel
 static void capsule_kernels_before(lbm_handle *h, const MembraneArgs &m, Prof &pf) {
     timed(pf, h->st, "capsule_reduce", [&] { launch_capsule_reduce(m, h->st); });
@@ -806,13 +909,7 @@ extern "C" lbm_status lbm_step(lbm_handle *h, int64_t n) {
         }
         const FluidArgs a = fluid_args(h, h->cur);
         const int zc = zchunk_of(h);
-        timed(h->prof, h->st, "fluid", [&] {
-            switch (h->storage) {
-                case 0: launch_fluid_tiled<0>(a, h->tile, zc, h->st); break;
-                case 1: launch_fluid_tiled<1>(a, h->tile, zc, h->st); break;
-                default: launch_fluid_tiled<2>(a, h->tile, zc, h->st); break;
-            }
-        });
+        timed(h->prof, h->st, "fluid", [&] { enqueue_fluid(h, a, h->tile, zc, h->st); });
         if (bb) {
             const BBArgs b = bb_args(h, h->cur);
             timed(h->prof, h->st, "bb_nodes", [&] { launch_bb_after(b, h->storage, h->st); });
@@ -829,22 +926,15 @@ extern "C" lbm_status lbm_step(lbm_handle *h, int64_t n) {
 // ------------------------------------------------------------------------------------
 // Launch-shape autotuner
 // ------------------------------------------------------------------------------------
-static void enqueue_fluid(const lbm_handle *h, const FluidArgs &a, int tile, int zc, hipStream_t st) {
-    switch (h->storage) {
-        case 0: launch_fluid_tiled<0>(a, tile, zc, st); break;
-        case 1: launch_fluid_tiled<1>(a, tile, zc, st); break;
-        default: launch_fluid_tiled<2>(a, tile, zc, st); break;
-    }
-}
-
 // z-chunk depths the tuners try (0: the default from the lattice size)
 static const int TUNE_ZC[] = {0, 8, 12, 16, 24, 32, 48};
 
 // tiles the tuner tries on a lattice of width nx: every fused shape that applies.  With
 // tau != 1 the pipelined and whole-row numbers run the fused kernel of 1..5 or 64 x 8, so
 // only 1..5 are distinct there.
-static bool tile_applies(int tile, int nx, bool keepf) {
+static bool tile_applies(int tile, int nx, bool keepf, int storage) {
     if (tile < 1 || tile > TILE_ROWS || (keepf && tile >= 6)) return false;
+    if (storage == LBM_STORE_F16_LOCAL && tile < 6) return false;   // runs the pipelined tiles
     if (tile == 11) return nx == 256;
     if (tile == 12) return nx == 128;
     if (tile == TILE_ROWS) return rows_fit(nx);
@@ -898,7 +988,7 @@ extern "C" lbm_status lbm_autotune(lbm_handle *h, int32_t reps, int32_t *tile, i
     double best = INFINITY;
     int bt = h->tile, bz = h->zchunk;
     for (int t = 1; t <= TILE_ROWS; ++t) {
-        if (!tile_applies(t, h->nx, a.keepf)) continue;
+        if (!tile_applies(t, h->nx, a.keepf, h->storage)) continue;
         int seen[sizeof TUNE_ZC / sizeof TUNE_ZC[0]], ns = 0;
         for (int z : TUNE_ZC) {
             const int zc = std::min(zchunk_for(h, t, z), h->nz);
@@ -1160,7 +1250,8 @@ static void part_step(lbm_batch *b, BatchPart &pt) {
         switch (b->storage) {
             case 0: launch_fluid_multi<0>(tab, pt.d_desc, m, pt.nblocks, b->tile, st); break;
             case 1: launch_fluid_multi<1>(tab, pt.d_desc, m, pt.nblocks, b->tile, st); break;
-            default: launch_fluid_multi<2>(tab, pt.d_desc, m, pt.nblocks, b->tile, st); break;
+            case 2: launch_fluid_multi<2>(tab, pt.d_desc, m, pt.nblocks, b->tile, st); break;
+            default: launch_fluid_multi<3>(tab, pt.d_desc, m, pt.nblocks, b->tile, st); break;
         }
     });
     if (pt.nmg)
@@ -1249,7 +1340,8 @@ extern "C" lbm_status lbm_batch_autotune(lbm_batch *b, int32_t reps, int32_t *ti
                     switch (b->storage) {
                         case 0: launch_fluid_multi<0>(pt.d_tab, pt.d_desc, m, pt.nblocks, t, b->st); break;
                         case 1: launch_fluid_multi<1>(pt.d_tab, pt.d_desc, m, pt.nblocks, t, b->st); break;
-                        default: launch_fluid_multi<2>(pt.d_tab, pt.d_desc, m, pt.nblocks, t, b->st); break;
+                        case 2: launch_fluid_multi<2>(pt.d_tab, pt.d_desc, m, pt.nblocks, t, b->st); break;
+                        default: launch_fluid_multi<3>(pt.d_tab, pt.d_desc, m, pt.nblocks, t, b->st); break;
                     }
                 }
             }, &ms);
@@ -1339,9 +1431,10 @@ extern "C" lbm_status lbm_sync(lbm_handle *h) {
 static void launch_rho_any(lbm_handle *h, float *dst) {
     const float s0 = shift_of(h, 0), s1 = shift_of(h, 1);
     switch (h->storage) {
-        case 0: launch_rho<0>(h->f[h->cur], dst, h->nx, h->ny, h->nz, h->wall, h->lz, s0, s1, h->st); break;
-        case 1: launch_rho<1>(h->f[h->cur], dst, h->nx, h->ny, h->nz, h->wall, h->lz, s0, s1, h->st); break;
-        default: launch_rho<2>(h->f[h->cur], dst, h->nx, h->ny, h->nz, h->wall, h->lz, s0, s1, h->st); break;
+        case 0: launch_rho<0>(h->f[h->cur], dst, h->nx, h->ny, h->nz, h->wall, h->lz, s0, s1, nullptr, h->st); break;
+        case 1: launch_rho<1>(h->f[h->cur], dst, h->nx, h->ny, h->nz, h->wall, h->lz, s0, s1, nullptr, h->st); break;
+        case 2: launch_rho<2>(h->f[h->cur], dst, h->nx, h->ny, h->nz, h->wall, h->lz, s0, s1, nullptr, h->st); break;
+        default: launch_rho<3>(h->f[h->cur], dst, h->nx, h->ny, h->nz, h->wall, h->lz, s0, s1, h->rsite[h->cur], h->st); break;
     }
 }
 
@@ -1349,9 +1442,10 @@ extern "C" lbm_status lbm_observables(lbm_handle *h, lbm_obs *out) {
     if (!h || !out) return LBM_E_INVAL;
     const float s0 = shift_of(h, 0), s1 = shift_of(h, 1);
     switch (h->storage) {
-        case 0: launch_moments<0>(h->f[h->cur], h->partial, h->mom_blocks, h->nx, h->ny, h->nz, h->wall, h->lz, s0, s1, h->st); break;
-        case 1: launch_moments<1>(h->f[h->cur], h->partial, h->mom_blocks, h->nx, h->ny, h->nz, h->wall, h->lz, s0, s1, h->st); break;
-        default: launch_moments<2>(h->f[h->cur], h->partial, h->mom_blocks, h->nx, h->ny, h->nz, h->wall, h->lz, s0, s1, h->st); break;
+        case 0: launch_moments<0>(h->f[h->cur], h->partial, h->mom_blocks, h->nx, h->ny, h->nz, h->wall, h->lz, s0, s1, nullptr, h->st); break;
+        case 1: launch_moments<1>(h->f[h->cur], h->partial, h->mom_blocks, h->nx, h->ny, h->nz, h->wall, h->lz, s0, s1, nullptr, h->st); break;
+        case 2: launch_moments<2>(h->f[h->cur], h->partial, h->mom_blocks, h->nx, h->ny, h->nz, h->wall, h->lz, s0, s1, nullptr, h->st); break;
+        default: launch_moments<3>(h->f[h->cur], h->partial, h->mom_blocks, h->nx, h->ny, h->nz, h->wall, h->lz, s0, s1, h->rsite[h->cur], h->st); break;
     }
     HIPCHK(h, hipGetLastError());
     std::vector<double> part((size_t)h->nslab * h->mom_blocks * 5);
@@ -1543,6 +1637,11 @@ extern "C" lbm_status lbm_save(lbm_handle *h, const char *path) {
     hd.version = CKPT_VERSION; hd.nx = h->nx; hd.ny = h->ny; hd.nz = h->nz; hd.storage = h->storage;
     hd.ncap = (int)h->caps.size(); hd.ntot = h->ntot; hd.lz = h->lz; hd.step = h->step;
     bool ok = std::fwrite(&hd, sizeof hd, 1, fp) == 1 && std::fwrite(f.data(), 1, fbytes, fp) == fbytes;
+    if (h->storage == LBM_STORE_F16_LOCAL) {   // the site densities the populations are shifted by
+        std::vector<float> r(2 * (size_t)h->N);
+        ok = ok && hipMemcpy(r.data(), h->rsite[h->cur], r.size() * sizeof(float), hipMemcpyDeviceToHost) == hipSuccess &&
+             std::fwrite(r.data(), sizeof(float), r.size(), fp) == r.size();
+    }
     if (h->ntot)
         ok = ok && std::fwrite(X.data(), sizeof(double4), X.size(), fp) == X.size() &&
              std::fwrite(R.data(), sizeof(float4), R.size(), fp) == R.size() &&
@@ -1579,6 +1678,8 @@ extern "C" lbm_status lbm_load(lbm_handle *h, const char *path) {
               hd.storage == h->storage && hd.ncap == (int)h->caps.size() && hd.ntot == h->ntot &&
               hd.lz == h->lz &&
               std::fread(f.data(), 1, fbytes, fp) == fbytes;
+    std::vector<float> rs(h->storage == LBM_STORE_F16_LOCAL ? 2 * (size_t)h->N : 0);
+    if (ok && !rs.empty()) ok = std::fread(rs.data(), sizeof(float), rs.size(), fp) == rs.size();
     if (ok && h->ntot)
         ok = std::fread(X.data(), sizeof(double4), X.size(), fp) == X.size() &&
              std::fread(R.data(), sizeof(float4), R.size(), fp) == R.size() &&
@@ -1594,6 +1695,7 @@ extern "C" lbm_status lbm_load(lbm_handle *h, const char *path) {
     if (!ok) return fail(h, LBM_E_INVAL, "checkpoint does not match this simulation");
     HIPCHK(h, hipStreamSynchronize(h->st));
     HIPCHK(h, hipMemcpy(h->f[h->cur], f.data(), fbytes, hipMemcpyHostToDevice));
+    if (!rs.empty()) HIPCHK(h, hipMemcpy(h->rsite[h->cur], rs.data(), rs.size() * sizeof(float), hipMemcpyHostToDevice));
     // every site flag is rebuilt by the next step; windows recorded in cs are cleared
     HIPCHK(h, hipMemset(h->flag, 0, (size_t)h->N));
     if (h->ntot) {
@@ -1635,7 +1737,10 @@ extern "C" lbm_status lbm_kernel_stats(lbm_handle *h, lbm_kernel_stat *out, int3
 }
 
 extern "C" double lbm_bytes_per_site(const lbm_handle *h) {
-    return h ? 2.0 * Q * 2.0 * (double)h->esize : 0.0;
+    // storage 3 also reads and writes the FP32 density of both components per site
+    return h ? 2.0 * Q * 2.0 * (double)h->esize +
+                   (h->storage == LBM_STORE_F16_LOCAL ? 2.0 * 2.0 * 4.0 : 0.0)
+             : 0.0;
 }
 
 extern "C" int64_t lbm_fluid_sites(const lbm_handle *h) {

@@ -37,6 +37,11 @@ __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x);
 // ------------------------------------------------------------------------------------
 // Population access
 // ------------------------------------------------------------------------------------
+// weight of population q in the shift of storage S (wshift: mass-exact FP32 weights)
+template <int S> __device__ __forceinline__ constexpr float wsh(int q) {
+    return S == 3 ? wshift(q) : wq(q);
+}
+
 template <int S> struct Pop {
     using T = typename Codec<S>::T;
     static constexpr int QH = 10;   // populations in the first part of a component
@@ -98,8 +103,8 @@ __device__ __forceinline__ void pull(const void *f, int N, int x, int y, int z, 
         const bool bb = (CZ[q] > 0 && wall_lo) || (CZ[q] < 0 && wall_hi);
         const uint32_t src = bb ? self : (uint32_t)((zs * ny + ys) * nx + xs);
         const int qq = bb ? OPP[q] : q;
-        const float v0 = Pop<S>::load(f, qq, N, src, wq(q) * sh0);
-        const float v1 = Pop<S>::load(f, Q + qq, N, src, wq(q) * sh1);
+        const float v0 = Pop<S>::load(f, qq, N, src, wsh<S>(q) * sh0);
+        const float v1 = Pop<S>::load(f, Q + qq, N, src, wsh<S>(q) * sh1);
         if (!SUM_ONLY) {
             fl[0][q] = v0;
             fl[1][q] = v1;
@@ -128,16 +133,16 @@ __device__ __forceinline__ void pull_issue(const void *f, int N, int x, int y, i
         const int ys = CY[q] == 0 ? y : (CY[q] > 0 ? ym : yp);
         const int zs = CZ[q] == 0 ? z : (CZ[q] > 0 ? zm : zp);
         const uint32_t src = (uint32_t)((zs * ny + ys) * nx + xs);
-        fl[0][q] = Pop<S>::load(f, q, N, src, wq(q) * sh0);
-        fl[1][q] = Pop<S>::load(f, Q + q, N, src, wq(q) * sh1);
+        fl[0][q] = Pop<S>::load(f, q, N, src, wsh<S>(q) * sh0);
+        fl[1][q] = Pop<S>::load(f, Q + q, N, src, wsh<S>(q) * sh1);
     }
     if (wall_lo || wall_hi) {
         const uint32_t self = (uint32_t)((z * ny + y) * nx + x);
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             if ((CZ[q] > 0 && wall_lo) || (CZ[q] < 0 && wall_hi)) {
-                fl[0][q] = Pop<S>::load(f, OPP[q], N, self, wq(q) * sh0);
-                fl[1][q] = Pop<S>::load(f, Q + OPP[q], N, self, wq(q) * sh1);
+                fl[0][q] = Pop<S>::load(f, OPP[q], N, self, wsh<S>(q) * sh0);
+                fl[1][q] = Pop<S>::load(f, Q + OPP[q], N, self, wsh<S>(q) * sh1);
             }
         }
     }
@@ -234,7 +239,7 @@ __device__ __forceinline__ void collide_store(const FluidArgs &a, const float (&
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             const float fs = KEEPF ? fl[c][q] + om * (feq[q] - fl[c][q]) : feq[q];
-            Pop<S>::store(a.fout, c * Q + q, a.N, s, fs, wq(q) * sh);
+            Pop<S>::store(a.fout, c * Q + q, a.N, s, fs, wsh<S>(q) * sh);
         }
     }
     if (aux) {
@@ -311,26 +316,32 @@ __device__ __forceinline__ void sc_general(const FluidArgs &a, const float *cap_
 // ------------------------------------------------------------------------------------
 template <int S>
 __global__ void k_init_eq(const double *__restrict__ rho, void *f, int nx, int ny, int nz,
-                          int wall, int lz, float sh0, float sh1) {
+                          int wall, int lz, float sh0, float sh1, float *rsite) {
     const int N = nx * ny * nz;
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= N) return;
     const int z = s / (nx * ny);
     const bool solid = wall && slab_pos(z, lz) == 0;
+    if constexpr (S == 3) {   // shift by the site's own density: w_i rho stores as 0
+        sh0 = solid ? 0.0f : (float)rho[s];
+        sh1 = solid ? 0.0f : (float)rho[N + s];
+        rsite[s] = sh0;
+        rsite[N + s] = sh1;
+    }
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         const double w = (double)wq(q);
-        Pop<S>::store(f, q, N, s, solid ? 0.0f : (float)(w * rho[s]), wq(q) * sh0);
-        Pop<S>::store(f, Q + q, N, s, solid ? 0.0f : (float)(w * rho[N + s]), wq(q) * sh1);
+        Pop<S>::store(f, q, N, s, solid ? 0.0f : (float)(w * rho[s]), wsh<S>(q) * sh0);
+        Pop<S>::store(f, Q + q, N, s, solid ? 0.0f : (float)(w * rho[N + s]), wsh<S>(q) * sh1);
     }
 }
 
 template <int S>
 void launch_init_eq(const double *rho_dev, void *f, int nx, int ny, int nz, int wall, int lz,
-                    float s0, float s1, hipStream_t st) {
+                    float s0, float s1, float *rsite, hipStream_t st) {
     const int N = nx * ny * nz;
     hipLaunchKernelGGL(k_init_eq<S>, dim3((N + 255) / 256), dim3(256), 0, st, rho_dev, f, nx, ny,
-                       nz, wall, lz, s0, s1);
+                       nz, wall, lz, s0, s1, rsite);
 }
 
 // ------------------------------------------------------------------------------------
@@ -582,6 +593,27 @@ __device__ __forceinline__ void collide_store_eq(const FluidArgs &a, const float
         const float k = rho[c] > 0.f ? a.tau[c] * rcp(rho[c]) : 0.f;
         const float u0 = up0 + k * Fc[0], u1 = up1 + k * Fc[1], u2 = up2 + k * Fc[2];
         const float uu = 1.5f * (u0 * u0 + u1 * u1 + u2 * u2);
+        if constexpr (S == 3) {
+            // shift by this site's new density (stored beside the populations): the stored
+            // values are f_i - w_i rho, computed as such; the rest population stores minus
+            // the sum of the others as rounded, so that the populations of a site sum to its
+            // density up to one FP16 rounding of that second-order value (mass conservation)
+            float dsum = 0.f;
+#pragma unroll
+            for (int q = 1; q < Q; q += 2) {
+                const float w = wq(q) * rho[c];
+                const float eu = CX[q] * u0 + CY[q] * u1 + CZ[q] * u2;
+                const float A = w * (4.5f * eu * eu - uu) + (wq(q) - wshift(q)) * rho[c];
+                const float B = 3.0f * w * eu;
+                const float dq = (float)(_Float16)(A + B), dopp = (float)(_Float16)(A - B);
+                dsum += dq + dopp;
+                Pop<S>::store(a.fout, c * Q + q, a.N, s, dq, 0.f);
+                Pop<S>::store(a.fout, c * Q + q + 1, a.N, s, dopp, 0.f);
+            }
+            Pop<S>::store(a.fout, c * Q, a.N, s, -dsum, 0.f);
+            a.rout[c * a.N + s] = rho[c];
+            continue;
+        }
         const float sh = a.shift[c];
         float sum = 0.f;
 #pragma unroll
@@ -592,10 +624,10 @@ __device__ __forceinline__ void collide_store_eq(const FluidArgs &a, const float
             const float B = 3.0f * w * eu;
             const float fq = A + B, fo = A - B;
             sum += fq + fo;
-            Pop<S>::store(a.fout, c * Q + q, a.N, s, fq, wq(q) * sh);
-            Pop<S>::store(a.fout, c * Q + q + 1, a.N, s, fo, wq(q) * sh);
+            Pop<S>::store(a.fout, c * Q + q, a.N, s, fq, wsh<S>(q) * sh);
+            Pop<S>::store(a.fout, c * Q + q + 1, a.N, s, fo, wsh<S>(q) * sh);
         }
-        Pop<S>::store(a.fout, c * Q, a.N, s, rho[c] - sum, wq(0) * sh);
+        Pop<S>::store(a.fout, c * Q, a.N, s, rho[c] - sum, wsh<S>(0) * sh);
     }
     if (aux) {
         // window sites: physical velocity with the kernel coverage c(x) in .w, and the
@@ -630,6 +662,13 @@ __device__ __forceinline__ void pipe_tile(const FluidArgs &a, int L, int zc, int
     __shared__ uint8_t s_flag[4][NLC];
     __shared__ int s_busy[4][NW];
     __shared__ float s_drho[MAX_CAPS];
+    // storage 3: the last step's site densities over the tile and a 2-site ring (the sources
+    // of the tile's and the halo's pulls), planes p - 1 .. p + 3 of the march in a 4-plane
+    // ring (slot of plane z: (z - z0 + 2) & 3); whole-row tiles wrap in x instead
+    constexpr bool LOC = S == 3;
+    constexpr int NR_MAX = WX ? TX * (TY + 4) : (TX + 4) * (TY + 4);
+    constexpr int RPT = (NR_MAX + NT - 1) / NT;
+    __shared__ float s_rho[LOC ? 4 : 1][2][LOC ? NR_MAX : 1];
 
     const int bx = L % tiles_x, t2 = L / tiles_x, by = t2 % tiles_y, bz = t2 / tiles_y;
     const int nx = a.nx, ny = a.ny, nz = a.nz, N = a.N;
@@ -642,7 +681,7 @@ __device__ __forceinline__ void pipe_tile(const FluidArgs &a, int L, int zc, int
     const int li = act ? (ly + 1) * LX + (lx + 1) : NL + (tid - tx * ty);
     const int ix = wrapn(x0 + lx, nx), iy = wrapn(y0 + ly, ny);
     const bool valid = act && (x0 + lx < nx) && (y0 + ly < ny);
-    int hi = -1, hx = 0, hy = 0;
+    int hi = -1, hx = 0, hy = 0, hxl = 0, hyl = 0;
     if (tid < NH) {
         int h = tid;
         if (WX) { hx = h % tx; hy = h < tx ? -1 : ty; }
@@ -650,21 +689,82 @@ __device__ __forceinline__ void pipe_tile(const FluidArgs &a, int L, int zc, int
         else if (h < 2 * LX) { hx = h - LX - 1; hy = ty; }
         else { h -= 2 * LX; hy = h >> 1; hx = (h & 1) ? tx : -1; }
         hi = (hy + 1) * LX + (hx + 1);
+        hxl = hx;   // tile coordinates of the halo site
+        hyl = hy;
         hx = wrapn(x0 + hx, nx);
         hy = wrapn(y0 + hy, ny);
     }
+    const int RW = WX ? tx : tx + 4, NR = RW * (ty + 4);
+    float rreg[2][RPT];
+    // storage 3: load the region of plane z into registers, then into its ring slot
+    auto rho_issue = [&](int z) {
+        if constexpr (LOC) {
+            const int pz = wrapn(z, nz);
+#pragma unroll
+            for (int k = 0; k < RPT; ++k) {
+                const int i = tid + k * NT;
+                rreg[0][k] = rreg[1][k] = 0.f;
+                if (i < NR) {
+                    const int rx = i % RW, ry = i / RW;
+                    const int gx = WX ? rx : wrapn(x0 - 2 + rx, nx), gy = wrapn(y0 - 2 + ry, ny);
+                    const int sg = (pz * ny + gy) * nx + gx;
+                    rreg[0][k] = a.rin[sg];
+                    rreg[1][k] = a.rin[N + sg];
+                }
+            }
+        }
+    };
+    auto rho_store = [&](int z) {
+        if constexpr (LOC) {
+            const int slot = (z - z0 + 2) & 3;
+#pragma unroll
+            for (int k = 0; k < RPT; ++k) {
+                const int i = tid + k * NT;
+                if (i < NR) {
+                    s_rho[slot][0][i] = rreg[0][k];
+                    s_rho[slot][1][i] = rreg[1][k];
+                }
+            }
+        }
+    };
+    // storage 3: the pulls of the site at tile coordinates (sx, sy) in plane p were loaded
+    // without a shift; add w_q rho of each one's source (the site itself where it bounced
+    // back at the wall)
+    auto decode = [&](float (&f)[2][Q], int sx, int sy, int p, bool wlo, bool whi) {
+        if constexpr (LOC) {
+            const int s0 = (p - z0 + 2) & 3, sm = (p - z0 + 1) & 3, sp = (p - z0 + 3) & 3;
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                const bool bb = (CZ[q] > 0 && wlo) || (CZ[q] < 0 && whi);
+                const int slot = (bb || CZ[q] == 0) ? s0 : (CZ[q] > 0 ? sm : sp);
+                const int ox = bb ? sx : sx - CX[q], oy = bb ? sy : sy - CY[q];
+                const int idx = WX ? wrap1(ox, tx) + (oy + 2) * RW : (ox + 2) + (oy + 2) * RW;
+                f[0][q] += wshift(q) * s_rho[slot][0][idx];
+                f[1][q] += wshift(q) * s_rho[slot][1][idx];
+            }
+        }
+    };
     // WX: ring positions that also hold this thread's value (the wrapped columns)
     const int li_w = !WX || !act ? -1 : (lx == tx - 1 ? li - tx : (lx == 0 ? li + tx : -1));
     const int hi_w = !WX || hi < 0 ? -1
                                    : ((hi % LX) == tx ? hi - tx : ((hi % LX) == 1 ? hi + tx : -1));
 
     for (int i = tid; i < MAX_CAPS; i += NT) s_drho[i] = a.cap_drho[i];
+    // slab position of a plane (uniform), stepped along with the planes instead of divided
+    const int lz = a.lz;
 
-    // publish psi, flags and the busy bit of plane p from the pulled populations
-    auto publish = [&](int p, bool solid, int pz, const float (&fl)[2][Q],
-                       const float (&hf)[2][Q], uint8_t fl_me, uint8_t fl_h, float (&m)[8],
-                       float4 &ibv) {
+    // publish psi, flags and the busy bit of plane p (slab position pr) from the pulled
+    // populations
+    auto publish = [&](int p, int pr, bool solid, int pz, float (&fl)[2][Q], float (&hf)[2][Q],
+                       uint8_t fl_me, uint8_t fl_h, float (&m)[8], float4 &ibv) {
         const int slot = (p - z0 + 4) & 3;
+        if constexpr (LOC) {
+            if (!solid) {
+                const bool wlo = a.wall && pr == 1, whi = a.wall && pr == lz - 1;
+                if (act) decode(fl, lx, ly, p, wlo, whi);
+                if (hi >= 0) decode(hf, hxl, hyl, p, wlo, whi);
+            }
+        }
         // window sites: fetch the spread force now, two planes before it is used
         ibv = make_float4(0.f, 0.f, 0.f, 0.f);
         if (!solid && (fl_me & AUX_BIT)) ibv = a.ibm[(pz * ny + iy) * nx + ix];
@@ -707,8 +807,7 @@ __device__ __forceinline__ void pipe_tile(const FluidArgs &a, int L, int zc, int
         const bool any = __builtin_amdgcn_ballot_w64((fg_me | fg_h) != 0) != 0;
         if (lane == 0) s_busy[slot][wave] = any ? 1 : 0;
     };
-    // slab position of a plane (uniform), stepped along with the planes instead of divided
-    const int lz = a.lz;
+
     auto fwd = [&](int r, int k) { r += k; return r >= lz ? r - lz : r; };
     // issue the pulls and flag reads of plane p at slab position pr (tile site, and the
     // halo site of the first NH threads)
@@ -732,15 +831,36 @@ __device__ __forceinline__ void pipe_tile(const FluidArgs &a, int L, int zc, int
         float fl[2][Q], hf[2][Q];
         uint8_t g_me, g_h;
         issue(p, pr, fl, hf, g_me, g_h);
-        publish(p, a.wall && pr == 0, wrapn(p, nz), fl, hf, g_me, g_h, m, ibv);
+        publish(p, pr, a.wall && pr == 0, wrapn(p, nz), fl, hf, g_me, g_h, m, ibv);
     };
 
     float m0[8], m1[8], m2[8];   // moments of planes p, p+1, p+2
     float4 ib0, ib1, ib2;        // spread force of this thread's site in planes p, p+1
     int rz = slab_pos(z0, lz);   // slab position of plane p
+    if constexpr (LOC) {         // the sources of planes z0 - 1 .. z0 + 1
+        for (int z = z0 - 2; z <= z0; ++z) {
+            rho_issue(z);
+            rho_store(z);
+        }
+        __syncthreads();
+    }
     load_plane(z0 - 1, fwd(rz, lz - 1), m2, ib2);
+    if constexpr (LOC) {
+        rho_issue(z0 + 1);
+        rho_store(z0 + 1);
+        __syncthreads();
+    }
     load_plane(z0, rz, m0, ib0);
+    if constexpr (LOC) {
+        rho_issue(z0 + 2);
+        rho_store(z0 + 2);
+        __syncthreads();
+    }
     load_plane(z0 + 1, fwd(rz, 1), m1, ib1);
+    if constexpr (LOC) {
+        rho_issue(z0 + 3);
+        rho_store(z0 + 3);
+    }
     __syncthreads();
     for (int p = z0; p < z1; ++p, rz = fwd(rz, 1)) {
         // issue the pulls of plane p+2 first; they complete while plane p is collided
@@ -750,6 +870,9 @@ __device__ __forceinline__ void pipe_tile(const FluidArgs &a, int L, int zc, int
         const int pn = wrapn(p + 2, nz), rn = fwd(rz, 2);
         const bool nsolid = a.wall && rn == 0;
         if (more) issue(p + 2, rn, fl, hf, g_me, g_h);
+        // storage 3: the densities of plane p + 4 (sources of plane p + 3), stored after the
+        // publication of plane p + 2 into the slot of plane p, which nothing reads any more
+        if (LOC && more) rho_issue(p + 4);
         // ---- collide plane p ----
         const int cz = wrapn(p, nz);
         if (valid && !(a.wall && rz == 0)) {
@@ -791,7 +914,8 @@ __device__ __forceinline__ void pipe_tile(const FluidArgs &a, int L, int zc, int
         if (more) {
             float mn[8];
             float4 ibn;
-            publish(p + 2, nsolid, pn, fl, hf, g_me, g_h, mn, ibn);
+            publish(p + 2, rn, nsolid, pn, fl, hf, g_me, g_h, mn, ibn);
+            if (LOC) rho_store(p + 4);
 #pragma unroll
             for (int i = 0; i < 8; ++i) { m0[i] = m1[i]; m1[i] = mn[i]; }
             ib0 = ib1;
@@ -900,6 +1024,30 @@ static void launch_fused_t(const FluidArgs &a, int zc, hipStream_t st) {
 // rows 128x4; 13: whole rows of width nx (16 .. 128) by 512 / nx
 template <int S>
 void launch_fluid_tiled(const FluidArgs &a, int tile, int zc, hipStream_t st) {
+    if constexpr (S == 3) {
+        // storage 3 runs the pipelined kernels only (tau = 1): tiles 1..5 and the two-kernel
+        // variant take the pipelined 64 x 8 tile
+        switch (tile) {
+            case 6: launch_pipe_t<S, 32, 8>(a, zc, st); break;
+            case 7: launch_pipe_t<S, 64, 4>(a, zc, st); break;
+            case 8: launch_pipe_t<S, 16, 16>(a, zc, st); break;
+            case 9: launch_pipe_t<S, 32, 16>(a, zc, st); break;
+            case 11:
+                if (a.nx == 256) launch_pipe_t<S, 256, 2, true>(a, zc, st);
+                else launch_pipe_t<S, 64, 8>(a, zc, st);
+                break;
+            case 12:
+                if (a.nx == 128) launch_pipe_t<S, 128, 4, true>(a, zc, st);
+                else launch_pipe_t<S, 64, 8>(a, zc, st);
+                break;
+            case 13:
+                if (a.nx >= 16 && a.nx <= 128) launch_pipe_rows<S>(a, zc, st);
+                else launch_pipe_t<S, 64, 8>(a, zc, st);
+                break;
+            default: launch_pipe_t<S, 64, 8>(a, zc, st); break;
+        }
+        return;
+    } else {
     switch (tile) {
         case 1: launch_fused_t<S, 32, 8>(a, zc, st); break;
         case 2: launch_fused_t<S, 64, 4>(a, zc, st); break;
@@ -930,6 +1078,7 @@ void launch_fluid_tiled(const FluidArgs &a, int tile, int zc, hipStream_t st) {
             break;
         default: launch_fluid<S>(a, st); break;
     }
+    }
 }
 
 // ------------------------------------------------------------------------------------
@@ -937,17 +1086,21 @@ void launch_fluid_tiled(const FluidArgs &a, int tile, int zc, hipStream_t st) {
 // ------------------------------------------------------------------------------------
 template <int S>
 __global__ void k_rho(const void *f, float *__restrict__ rho, int nx, int ny, int nz, int wall,
-                      int lz, float sh0, float sh1) {
+                      int lz, float sh0, float sh1, const float *__restrict__ rsite) {
     const int N = nx * ny * nz;
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= N) return;
     const int z = s / (nx * ny);
     float r0 = 0.f, r1 = 0.f;
     if (!(wall && slab_pos(z, lz) == 0)) {
+        if constexpr (S == 3) {
+            sh0 = rsite[s];
+            sh1 = rsite[N + s];
+        }
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
-            r0 += Pop<S>::load(f, q, N, s, wq(q) * sh0);
-            r1 += Pop<S>::load(f, Q + q, N, s, wq(q) * sh1);
+            r0 += Pop<S>::load(f, q, N, s, wsh<S>(q) * sh0);
+            r1 += Pop<S>::load(f, Q + q, N, s, wsh<S>(q) * sh1);
         }
     }
     rho[s] = r0;
@@ -956,10 +1109,10 @@ __global__ void k_rho(const void *f, float *__restrict__ rho, int nx, int ny, in
 
 template <int S>
 void launch_rho(const void *f, float *rho, int nx, int ny, int nz, int wall, int lz, float s0,
-                float s1, hipStream_t st) {
+                float s1, const float *rsite, hipStream_t st) {
     const int N = nx * ny * nz;
     hipLaunchKernelGGL(k_rho<S>, dim3((N + 255) / 256), dim3(256), 0, st, f, rho, nx, ny, nz, wall,
-                       lz, s0, s1);
+                       lz, s0, s1, rsite);
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -973,7 +1126,8 @@ __device__ __forceinline__ double wave_sum(double v) {
 template <int S>
 __global__ void __launch_bounds__(256) k_moments(const void *f, double *__restrict__ partial,
                                                  int nx, int ny, int nz, int wall, int lz,
-                                                 float sh0, float sh1) {
+                                                 float sh0, float sh1,
+                                                 const float *__restrict__ rsite) {
     const int N = nx * ny * nz, plane = nx * ny;
     const int s_end = (blockIdx.y + 1) * lz * plane;
     double acc[5] = {0, 0, 0, 0, 0};
@@ -981,10 +1135,14 @@ __global__ void __launch_bounds__(256) k_moments(const void *f, double *__restri
          s += gridDim.x * blockDim.x) {
         const int z = s / plane;
         if (wall && slab_pos(z, lz) == 0) continue;
+        if constexpr (S == 3) {
+            sh0 = rsite[s];
+            sh1 = rsite[N + s];
+        }
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
-            const double v0 = Pop<S>::load(f, q, N, s, wq(q) * sh0);
-            const double v1 = Pop<S>::load(f, Q + q, N, s, wq(q) * sh1);
+            const double v0 = Pop<S>::load(f, q, N, s, wsh<S>(q) * sh0);
+            const double v1 = Pop<S>::load(f, Q + q, N, s, wsh<S>(q) * sh1);
             acc[0] += v0;
             acc[1] += v1;
             if (CX[q]) acc[2] += CX[q] * (v0 + v1);
@@ -1009,9 +1167,9 @@ __global__ void __launch_bounds__(256) k_moments(const void *f, double *__restri
 
 template <int S>
 void launch_moments(const void *f, double *partial, int nblocks, int nx, int ny, int nz, int wall,
-                    int lz, float s0, float s1, hipStream_t st) {
+                    int lz, float s0, float s1, const float *rsite, hipStream_t st) {
     hipLaunchKernelGGL(k_moments<S>, dim3(nblocks, nz / lz), dim3(256), 0, st, f, partial, nx, ny,
-                       nz, wall, lz, s0, s1);
+                       nz, wall, lz, s0, s1, rsite);
 }
 
 // Meniscus height per column of each slab: the first upward crossing of
@@ -1047,17 +1205,20 @@ void launch_meniscus(const float *rho, const uint8_t *flag, float *out, int nx, 
 
 #define LBMX_INST(S)                                                                        \
     template void launch_init_eq<S>(const double *, void *, int, int, int, int, int, float,  \
-                                    float, hipStream_t);                                    \
-    template void launch_fluid<S>(const FluidArgs &, hipStream_t);                          \
+                                    float, float *, hipStream_t);                           \
     template void launch_fluid_tiled<S>(const FluidArgs &, int, int, hipStream_t);          \
     template void launch_fluid_multi<S>(const FluidArgs *, const int4 *, int, int, int,       \
                                         hipStream_t);                                         \
     template void launch_rho<S>(const void *, float *, int, int, int, int, int, float, float, \
-                                hipStream_t);                                               \
+                                const float *, hipStream_t);                                \
     template void launch_moments<S>(const void *, double *, int, int, int, int, int, int,    \
-                                    float, float, hipStream_t);
+                                    float, float, const float *, hipStream_t);
 LBMX_INST(0)
 LBMX_INST(1)
 LBMX_INST(2)
+LBMX_INST(3)
+template void launch_fluid<0>(const FluidArgs &, hipStream_t);
+template void launch_fluid<1>(const FluidArgs &, hipStream_t);
+template void launch_fluid<2>(const FluidArgs &, hipStream_t);
 
 }  // namespace lbmx

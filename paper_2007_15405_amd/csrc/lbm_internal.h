@@ -21,6 +21,14 @@ __host__ __device__ constexpr float wq(int q) {
                   : ((CX[q] * CX[q] + CY[q] * CY[q] + CZ[q] * CZ[q]) == 1 ? 1.0f / 18.0f
                                                                           : 1.0f / 36.0f);
 }
+// Weights of the shift of storage 3 (f_i stored as f_i - ws_i rho_site): FP32 numbers
+// within 4e-8 of w_i whose exact sum is 1.  The FP32 values of 1/3, 1/18 and 1/36 sum to
+// 1 + 1.5e-8, which the decode would add to every site's mass in every step.
+__host__ __device__ constexpr float wshift(int q) {
+    return q == 0 ? 0x1.555558p-2f
+                  : ((CX[q] * CX[q] + CY[q] * CY[q] + CZ[q] * CZ[q]) == 1 ? 0x1.c71c7p-5f
+                                                                          : 0x1.c71c7p-6f);
+}
 __host__ __device__ constexpr bool is_axis(int q) {
     return (CX[q] * CX[q] + CY[q] * CY[q] + CZ[q] * CZ[q]) == 1;
 }
@@ -69,6 +77,12 @@ template <> struct Codec<1> {
     __device__ static inline T enc(float f, float s) { return (_Float16)(f - s); }
 };
 
+// S = 3: FP16 of f - w_i rho_site, the shift taken from the site's own density (stored in
+// FP32 beside the populations), so the stored values are the small deviations of f from
+// the rest equilibrium at that density.  The codec itself is S = 1's; the callers pass
+// w_i rho_site as the shift.
+template <> struct Codec<3> : Codec<1> {};
+
 template <> struct Codec<2> {
     using T = uint16_t;
     __device__ static inline float dec(T v, float s) {
@@ -88,6 +102,8 @@ template <> struct Codec<2> {
 struct FluidArgs {
     const void *fin;        // populations of the last step, [2][19][N] of Codec<S>::T
     void *fout;             // populations written by this step
+    const float *rin;       // storage 3: [2][N] density of every site of the last step
+    float *rout;            // storage 3: [2][N] density written by this step
     const uint8_t *flag;    // [N] label | AUX_BIT
     const float4 *ibm;      // [N] spread force (x, y, z) and kernel coverage (w), aux sites
     float4 *uo;             // [N] physical velocity, aux sites
@@ -228,8 +244,11 @@ void launch_bb_before(const BBArgs &b, int storage, hipStream_t st);
 void launch_bb_after(const BBArgs &b, int storage, hipStream_t st);
 
 // Launchers (host functions, defined in the .hip files).
+// rsite: storage 3, [2][N] site densities (written by launch_init_eq, read by the others);
+// nullptr otherwise
 template <int S> void launch_init_eq(const double *rho_dev, void *f, int nx, int ny, int nz,
-                                     int wall, int lz, float s0, float s1, hipStream_t st);
+                                     int wall, int lz, float s0, float s1, float *rsite,
+                                     hipStream_t st);
 template <int S> void launch_fluid(const FluidArgs &a, hipStream_t st);
 template <int S> void launch_fluid_tiled(const FluidArgs &a, int tile, int zc, hipStream_t st);
 // One launch of the pipelined fluid kernel over several lattices (device tables: the
@@ -240,11 +259,11 @@ int rows_tile_height(int nx);
 template <int S> void launch_fluid_multi(const FluidArgs *tab, const int4 *desc, int ngroups,
                                          int nblocks, int tile, hipStream_t st);
 template <int S> void launch_rho(const void *f, float *rho, int nx, int ny, int nz, int wall,
-                                 int lz, float s0, float s1, hipStream_t st);
+                                 int lz, float s0, float s1, const float *rsite, hipStream_t st);
 // partial sums [nz / lz][nblocks][5] (mass of both components, momentum) per slab
 template <int S> void launch_moments(const void *f, double *partial, int nblocks, int nx, int ny,
                                      int nz, int wall, int lz, float s0, float s1,
-                                     hipStream_t st);
+                                     const float *rsite, hipStream_t st);
 // meniscus heights [nz / lz][ny][nx], measured from each slab's wall layer
 void launch_meniscus(const float *rho, const uint8_t *flag, float *out, int nx, int ny, int nz,
                      int wall, int lz, hipStream_t st);

@@ -16,7 +16,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblbm.so")
 
-STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
+STORAGE = {"f32": 0, "f16": 1, "bf16": 2, "f16site": 3}
 
 LBM_OK, LBM_E_INVAL, LBM_E_NOMEM, LBM_E_DEVICE, LBM_E_UNSTABLE, LBM_E_STATE = 0, -1, -2, -3, -4, -5
 
@@ -86,6 +86,8 @@ SIGNATURES = {
     "lbm_init": (C.c_int, [C.POINTER(Params), C.POINTER(C.c_void_p)]),
     "lbm_add_capsule": (C.c_int, [H, C.POINTER(CapsuleParams), C.c_int32, C.POINTER(C.c_double),
                                   C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "lbm_add_sphere_capsule": (C.c_int, [H, C.POINTER(CapsuleParams), C.POINTER(C.c_double),
+                                         C.c_double, C.c_int32, C.POINTER(C.c_int32)]),
     "lbm_step": (C.c_int, [H, C.c_int64]),
     "lbm_sync": (C.c_int, [H]),
     "lbm_observables": (C.c_int, [H, C.POINTER(Obs)]),
@@ -180,7 +182,8 @@ class Sim:
     (a stream of the library's own) or a raw hipStream_t integer."""
 
     def __init__(self, cfg: dict, storage: str = "f32", rho_shift=(1.0, 1.0),
-                 stream="torch", device: int = 0, meshes: Optional[list] = None):
+                 stream="torch", device: int = 0, meshes: Optional[list] = None,
+                 library_meshes: bool = False):
         import synth
         self.L = load_library()
         self.cfg = cfg
@@ -232,6 +235,9 @@ class Sim:
         self.storage = storage
         self.n_nodes = []
         for i, cp in enumerate(cfg["capsules"]):
+            if library_meshes:     # the library builds the geodesic sphere itself
+                self.add_sphere_capsule(cp)
+                continue
             nodes, tris = meshes[i] if meshes is not None else synth.capsule_mesh(cp)
             self.add_capsule(cp, nodes, tris)
 
@@ -248,6 +254,17 @@ class Sim:
         self._check(self.L.lbm_add_capsule(self.h, C.byref(q), len(x), _dp(x), len(t),
                                            t.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(out)))
         self.n_nodes.append(len(x))
+        return out.value
+
+    def add_sphere_capsule(self, cp: dict, n_nodes: int = None) -> int:
+        """A spherical capsule of cp["center"], cp["radius"], cp["n_tri"] whose mesh the library
+        builds (``lbm_add_sphere_capsule``)."""
+        q = CapsuleParams(cp["ks"], cp["C"], cp["kb"], cp["kv"], cp["wet_drho"], cp["anchor_k"])
+        cen = np.ascontiguousarray(cp["center"], dtype=np.float64)
+        out = C.c_int32()
+        self._check(self.L.lbm_add_sphere_capsule(self.h, C.byref(q), _dp(cen), float(cp["radius"]),
+                                                  int(cp["n_tri"]), C.byref(out)))
+        self.n_nodes.append(10 * int(cp["n_tri"]) // 20 + 2)
         return out.value
 
     def step(self, n: int = 1):

@@ -62,7 +62,7 @@ def test_binding_structs_match_c_layout(tmp_path):
     ("nx", 2, "nx, ny, nz"),
     ("tau", (0.5, 1.0), "tau"),
     ("init_mode", 7, "init_mode"),
-    ("storage", 3, "storage"),
+    ("storage", 4, "storage"),
     ("rho0", 0.0, "rho0"),
 ])
 def test_invalid_parameters_are_rejected_on_the_host(field, value, msg):

@@ -429,3 +429,36 @@ def test_bending_needs_a_closed_mesh():
     assert ei.value.status == -1
     g.add_capsule(cap, nodes, tris)
     g.close()
+
+
+@pytest.mark.parametrize("n_tri", [20, 320, 1280, 5120])
+def test_library_built_sphere_capsule(n_tri):
+    """lbm_add_sphere_capsule builds the geodesic sphere in the library (FP64): its nodes are
+    the synthetic mesh's, and a run with it follows the oracle run on the synthetic mesh."""
+    R = 6.0 if n_tri <= 1280 else 10.0
+    cap = synth.capsule((16.3, 15.8, R + 4.2), R, n_tri, 0.02)
+    nz = 32 if R < 10 else 40
+    cfg = synth.workload("pf", nz=nz, capsules=[cap])
+    g = _sim(cfg, library_meshes=True)
+    x, _ = synth.capsule_mesh(cap)
+    xl = g.nodes(0)
+    assert xl.shape == x.shape
+    assert np.abs(xl - x).max() <= 1e-12 * R
+    o = oracle.Oracle(cfg)
+    g.step(50)
+    o.step(50)
+    rg, ro = g.rho(), o.rho()
+    assert max(rel_l2(rg, ro)) <= 1e-5
+    site_check(rg, ro, 1e-5, f"sphere capsule {n_tri}", g.labels())
+    assert np.abs(g.nodes(0) - o.nodes(0)).max() <= 1e-4
+
+
+def test_library_built_sphere_capsule_refuses_bad_sizes():
+    from paper_2007_15405_amd import LbmError
+    g = _sim(synth.workload("pf", capsules=[]))
+    for n_tri, R in ((1000, 6.0), (1280, -1.0), (1280, float("nan"))):
+        with pytest.raises(LbmError) as ei:
+            g.add_sphere_capsule(synth.capsule((16.0, 16.0, 10.0), 6.0, 1280, 0.01) |
+                                 dict(n_tri=n_tri, radius=R))
+        assert ei.value.status == -1
+    g.close()

@@ -8,12 +8,14 @@ Measured quantities: meniscus height h(x, y) over the columns where both sides d
 error of the vector), and the mass drift of each component relative to its initial mass.
 
 FP32 storage is held to the bounds of the FP32 parity tests.  The 16-bit errors have no
-closed form (parity unpinned): they are measured and printed, and held only to sanity
-bounds that a broken codec (wrong shift, sign or rounding) exceeds at once.  Each 16-bit
-format runs with the shift rho_s = rho0 = 1 and without a shift: in this film each
+closed form (parity unpinned): they are measured and printed, held to about 1.5 times the
+value measured, and a storage that misses the 1 % capillary-force target is reported as an
+expected failure (xfail) after those bounds pass.  Each constant-shift 16-bit format runs
+with the shift rho_s = rho0 = 1 and without a shift: in this film each
 component is 0.7 in one phase and 0.04 in the other, so a shift of 1 leaves the minority
 phase stored as -0.96 w_i, and the format's relative precision on that value is a
-percent-level error on f_i itself.
+percent-level error on f_i itself.  The FP16 storage shifted by each site's own density
+(``f16site``) stores only f_i - w_i rho_site, of the order of w_i rho |u|.
 """
 import os
 
@@ -27,17 +29,21 @@ pytestmark = pytest.mark.gpu
 REF = os.path.join(os.path.dirname(__file__), "golden", "c2_precision_reference.npz")
 
 # (storage, rho_shift, bounds at 5000 steps: max |dh|, rms |dh|, relative capillary force
-# error, mass drift)
+# error, mass drift).  The runs are bitwise deterministic; each 16-bit bound is the value
+# measured with the present kernels times about 1.5, so a codec change that loses
+# precision fails here.
 FP32_BOUNDS = (1e-2, 1e-3, 1e-2, 1e-5)
-SANITY_16 = (3.0, 1.5, 5.0, 0.1)
 CASES = [
     ("f32", (1.0, 1.0), FP32_BOUNDS),
-    ("f16", (1.0, 1.0), SANITY_16),
-    ("f16", (0.0, 0.0), SANITY_16),
-    ("bf16", (1.0, 1.0), SANITY_16),
-    ("bf16", (0.0, 0.0), SANITY_16),
+    ("f16", (1.0, 1.0), (1.8, 0.7, 1.8, 3.5e-2)),
+    ("f16", (0.0, 0.0), (1.1, 0.4, 0.6, 4e-3)),
+    ("bf16", (1.0, 1.0), (4.0, 0.9, 7.0, 1.5e-2)),
+    ("bf16", (0.0, 0.0), (3.2, 0.85, 1.4, 1.1e-2)),
+    ("f16site", (0.0, 0.0), (3.0, 1.5, 5.0, 0.1)),
 ]
-
+# the accuracy a storage has to reach to stand in for FP32 in the film studies: capillary
+# force within 1 % of the FP64 oracle (the force the pair-interaction study measures)
+FORCE_TARGET = 1e-2
 
 def errors(ref, cp, men, caps, mass):
     h0 = ref[f"meniscus_{cp}"].astype(np.float64)
@@ -82,3 +88,6 @@ def test_storage_precision_against_oracle(storage, shift, bounds):
     assert r["dh_max"] <= hmax and r["dh_rms"] <= hrms
     assert r["fcap"] <= fcap
     assert r["drift"] <= drift
+    if storage != "f32" and r["fcap"] > FORCE_TARGET:
+        pytest.xfail(f"{storage} shift {shift}: capillary force error {r['fcap']:.2e} above "
+                     f"the {FORCE_TARGET:.0%} target")
