@@ -85,11 +85,13 @@ typedef enum {
 
 /* Population storage in HBM.  The collision arithmetic is FP32 in every mode.
  * Modes 1 and 2 store g_i = f_i - w_i * rho_shift[c] (w_i the lattice weights), rounded to
- * nearest even, and decode f_i = g_i + w_i * rho_shift[c].  Mode 3 stores, in FP16,
- * g_i = f_i - w_i * rho^c(x), shifted by the site's own post-collision density, which is
- * stored in FP32 beside the populations: the stored values are the small deviations of the
- * populations from the rest equilibrium at that density, so the minority phase of a
- * two-component film keeps its relative precision (152 + 16 bytes per site update); it
+ * nearest even, and decode f_i = g_i + w_i * rho_shift[c].  Mode 3 stores, in FP16, the
+ * relative deviation d_i = f_i / (w_i * rho^c(x)) - 1 from the rest equilibrium at the
+ * site's own post-collision density rho^c(x), which is stored in FP32 beside the
+ * populations, and decodes f_i = w_i * rho^c(x) * (1 + d_i) (w_i here FP32 weights that
+ * sum to exactly 1; the rest population absorbs the rounding of the others, so a site's
+ * stored mass is its density to one FP16 rounding of a second-order term).  Both phases of a
+ * two-component film keep FP16's relative precision (152 + 16 bytes per site update); it
  * needs tau = 1 in both components and the immersed-boundary coupling, and runs the
  * software-pipelined fluid kernels (lbm_set_launch tiles 1..5 and 0 take tile 10). */
 typedef enum {

@@ -68,9 +68,22 @@ template <int S> struct Pop {
             return Codec<S>::dec(__builtin_bit_cast(T, v), sh);
         }
     }
+    // the stored value itself (storage 3 decodes it later with its source site's density)
+    __device__ static inline float load_raw(const void *f, int qg, int N, uint32_t site) {
+        static_assert(sizeof(T) == 2, "16-bit storage");
+        const uint16_t v = __builtin_amdgcn_raw_buffer_load_b16(res(f, qg, N), site * 2u,
+                                                                 qoff(qg, N), 0);
+        return (float)__builtin_bit_cast(T, v);
+    }
     // stores are non-temporal: the new state is not read again in this step, and keeping
     // it out of L2 leaves room for the source rows that neighbouring tiles pull again
     static constexpr int STORE_NT = 2;
+    // store v, already a value of T, as is
+    __device__ static inline void store_raw(void *f, int qg, int N, uint32_t site, float v) {
+        static_assert(sizeof(T) == 2, "16-bit storage");
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, (T)v), res(f, qg, N),
+                                              site * 2u, qoff(qg, N), STORE_NT);
+    }
     __device__ static inline void store(void *f, int qg, int N, uint32_t site, float v, float sh) {
         const __amdgpu_buffer_rsrc_t r = res(f, qg, N);
         const T e = Codec<S>::enc(v, sh);
@@ -133,16 +146,26 @@ __device__ __forceinline__ void pull_issue(const void *f, int N, int x, int y, i
         const int ys = CY[q] == 0 ? y : (CY[q] > 0 ? ym : yp);
         const int zs = CZ[q] == 0 ? z : (CZ[q] > 0 ? zm : zp);
         const uint32_t src = (uint32_t)((zs * ny + ys) * nx + xs);
-        fl[0][q] = Pop<S>::load(f, q, N, src, wsh<S>(q) * sh0);
-        fl[1][q] = Pop<S>::load(f, Q + q, N, src, wsh<S>(q) * sh1);
+        if constexpr (S == 3) {   // decoded later with the source site's density
+            fl[0][q] = Pop<S>::load_raw(f, q, N, src);
+            fl[1][q] = Pop<S>::load_raw(f, Q + q, N, src);
+        } else {
+            fl[0][q] = Pop<S>::load(f, q, N, src, wsh<S>(q) * sh0);
+            fl[1][q] = Pop<S>::load(f, Q + q, N, src, wsh<S>(q) * sh1);
+        }
     }
     if (wall_lo || wall_hi) {
         const uint32_t self = (uint32_t)((z * ny + y) * nx + x);
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             if ((CZ[q] > 0 && wall_lo) || (CZ[q] < 0 && wall_hi)) {
-                fl[0][q] = Pop<S>::load(f, OPP[q], N, self, wsh<S>(q) * sh0);
-                fl[1][q] = Pop<S>::load(f, Q + OPP[q], N, self, wsh<S>(q) * sh1);
+                if constexpr (S == 3) {
+                    fl[0][q] = Pop<S>::load_raw(f, OPP[q], N, self);
+                    fl[1][q] = Pop<S>::load_raw(f, Q + OPP[q], N, self);
+                } else {
+                    fl[0][q] = Pop<S>::load(f, OPP[q], N, self, wsh<S>(q) * sh0);
+                    fl[1][q] = Pop<S>::load(f, Q + OPP[q], N, self, wsh<S>(q) * sh1);
+                }
             }
         }
     }
@@ -594,23 +617,27 @@ __device__ __forceinline__ void collide_store_eq(const FluidArgs &a, const float
         const float u0 = up0 + k * Fc[0], u1 = up1 + k * Fc[1], u2 = up2 + k * Fc[2];
         const float uu = 1.5f * (u0 * u0 + u1 * u1 + u2 * u2);
         if constexpr (S == 3) {
-            // shift by this site's new density (stored beside the populations): the stored
-            // values are f_i - w_i rho, computed as such; the rest population stores minus
-            // the sum of the others as rounded, so that the populations of a site sum to its
-            // density up to one FP16 rounding of that second-order value (mass conservation)
-            float dsum = 0.f;
+            // relative deviation from the rest equilibrium at this site's new density (stored
+            // beside the populations): d_i = f_i^eq / (ws_i rho) - 1
+            //     = (w_i / ws_i - 1) + (w_i / ws_i)(3 e.u + 4.5 (e.u)^2 - 1.5 u.u),
+            // computed without forming f_i.  The rest population takes the value that makes
+            // sum_i ws_i rho (1 + d_i) = rho with the others as rounded, so a site's stored
+            // mass carries one FP16 rounding of that second-order value (mass conservation)
+            float sa = 0.f, sd = 0.f;   // rounded deviations of the axis / diagonal links
 #pragma unroll
             for (int q = 1; q < Q; q += 2) {
-                const float w = wq(q) * rho[c];
+                const float r = wq(q) / wshift(q);
                 const float eu = CX[q] * u0 + CY[q] * u1 + CZ[q] * u2;
-                const float A = w * (4.5f * eu * eu - uu) + (wq(q) - wshift(q)) * rho[c];
-                const float B = 3.0f * w * eu;
-                const float dq = (float)(_Float16)(A + B), dopp = (float)(_Float16)(A - B);
-                dsum += dq + dopp;
-                Pop<S>::store(a.fout, c * Q + q, a.N, s, dq, 0.f);
-                Pop<S>::store(a.fout, c * Q + q + 1, a.N, s, dopp, 0.f);
+                const float A = 4.5f * eu * eu - uu, B = 3.0f * eu;
+                const float dq = (float)(_Float16)((r - 1.0f) + r * (A + B));
+                const float dopp = (float)(_Float16)((r - 1.0f) + r * (A - B));
+                if (is_axis(q)) sa += dq + dopp;
+                else sd += dq + dopp;
+                Pop<S>::store_raw(a.fout, c * Q + q, a.N, s, dq);
+                Pop<S>::store_raw(a.fout, c * Q + q + 1, a.N, s, dopp);
             }
-            Pop<S>::store(a.fout, c * Q, a.N, s, -dsum, 0.f);
+            constexpr float ka = wshift(1) / wshift(0), kd = wshift(5) / wshift(0);
+            Pop<S>::store_raw(a.fout, c * Q, a.N, s, (float)(_Float16)(-(ka * sa + kd * sd)));
             a.rout[c * a.N + s] = rho[c];
             continue;
         }
@@ -728,7 +755,7 @@ __device__ __forceinline__ void pipe_tile(const FluidArgs &a, int L, int zc, int
         }
     };
     // storage 3: the pulls of the site at tile coordinates (sx, sy) in plane p were loaded
-    // without a shift; add w_q rho of each one's source (the site itself where it bounced
+    // as stored; decode each with ws_q rho of its source (the site itself where it bounced
     // back at the wall)
     auto decode = [&](float (&f)[2][Q], int sx, int sy, int p, bool wlo, bool whi) {
         if constexpr (LOC) {
@@ -739,8 +766,10 @@ __device__ __forceinline__ void pipe_tile(const FluidArgs &a, int L, int zc, int
                 const int slot = (bb || CZ[q] == 0) ? s0 : (CZ[q] > 0 ? sm : sp);
                 const int ox = bb ? sx : sx - CX[q], oy = bb ? sy : sy - CY[q];
                 const int idx = WX ? wrap1(ox, tx) + (oy + 2) * RW : (ox + 2) + (oy + 2) * RW;
-                f[0][q] += wshift(q) * s_rho[slot][0][idx];
-                f[1][q] += wshift(q) * s_rho[slot][1][idx];
+                f[0][q] = Codec<S>::dec((typename Codec<S>::T)f[0][q],
+                                        wshift(q) * s_rho[slot][0][idx]);
+                f[1][q] = Codec<S>::dec((typename Codec<S>::T)f[1][q],
+                                        wshift(q) * s_rho[slot][1][idx]);
             }
         }
     };

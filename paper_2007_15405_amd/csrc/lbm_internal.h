@@ -77,11 +77,19 @@ template <> struct Codec<1> {
     __device__ static inline T enc(float f, float s) { return (_Float16)(f - s); }
 };
 
-// S = 3: FP16 of f - w_i rho_site, the shift taken from the site's own density (stored in
-// FP32 beside the populations), so the stored values are the small deviations of f from
-// the rest equilibrium at that density.  The codec itself is S = 1's; the callers pass
-// w_i rho_site as the shift.
-template <> struct Codec<3> : Codec<1> {};
+// S = 3: FP16 of the relative deviation d_i = f_i / (ws_i rho_site) - 1 of f from the rest
+// equilibrium at the site's own density rho_site (stored in FP32 beside the populations).
+// The callers pass s = ws_i rho_site; a site of zero density stores 0.  Relative values keep
+// the deviations of both phases of a two-component film in FP16's normal range (a minority
+// phase of density 0.04 has |f_i - w_i rho| below FP16's smallest normal number at every
+// velocity below about 0.02, where an absolute encoding keeps few significant bits).
+template <> struct Codec<3> {
+    using T = _Float16;
+    __device__ static inline float dec(T v, float s) { return fmaf(s, (float)v, s); }
+    __device__ static inline T enc(float f, float s) {
+        return s != 0.f ? (_Float16)((f - s) / s) : (_Float16)0.f;
+    }
+};
 
 template <> struct Codec<2> {
     using T = uint16_t;

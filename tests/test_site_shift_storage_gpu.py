@@ -1,10 +1,11 @@
 """GPU parity of the 16-bit storage shifted by each site's own density (``f16site``).
 
-Each population is stored as the FP16 value of f_i - w_i rho_site, rho_site the site's
-component density after the collision, kept in FP32 beside the populations.  With
-tau = 1 the stored value is f_i^eq(rho, u) - w_i rho, which is of the order of w_i rho |u|,
-so the rounding that the constant-shift FP16 storage makes on the full w_i (rho - rho0)
-deviation is made here on the much smaller velocity part only.
+Each population is stored as the FP16 value of the relative deviation
+d_i = f_i / (w_i rho_site) - 1, rho_site the site's component density after the collision,
+kept in FP32 beside the populations.  With tau = 1, d_i = 3 e_i.u + 4.5 (e_i.u)^2 - 1.5 u.u
+is of the order of |u| in both phases, so the rounding that the constant-shift FP16 storage
+makes on the full w_i (rho - rho0) deviation is made here on the velocity part only, at
+FP16's relative precision.
 
 Bounds (against the FP64 oracle):
   * flat film 200 steps: relative L2 <= 1e-4 per component (constant-shift FP16: 1e-2);
