@@ -78,15 +78,12 @@ template <int S> struct Pop {
     // stores are non-temporal: the new state is not read again in this step, and keeping
     // it out of L2 leaves room for the source rows that neighbouring tiles pull again
     static constexpr int STORE_NT = 2;
-    // store v, already a value of T, as is
-    __device__ static inline void store_raw(void *f, int qg, int N, uint32_t site, float v) {
-        static_assert(sizeof(T) == 2, "16-bit storage");
-        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, (T)v), res(f, qg, N),
-                                              site * 2u, qoff(qg, N), STORE_NT);
-    }
     __device__ static inline void store(void *f, int qg, int N, uint32_t site, float v, float sh) {
+        store_enc(f, qg, N, site, Codec<S>::enc(v, sh));
+    }
+    // store an encoded value
+    __device__ static inline void store_enc(void *f, int qg, int N, uint32_t site, T e) {
         const __amdgpu_buffer_rsrc_t r = res(f, qg, N);
-        const T e = Codec<S>::enc(v, sh);
         if constexpr (sizeof(T) == 4)
             __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, e), r, site * 4u,
                                                   qoff(qg, N), STORE_NT);
@@ -582,11 +579,14 @@ __global__ void __launch_bounds__(TX * TY) k_fused(FluidArgs a, int zc, int tile
 // plane a run of TX * 4 contiguous bytes per population, which the memory system
 // serves better than shorter runs.
 // ------------------------------------------------------------------------------------
-template <int S>
-__device__ __forceinline__ void collide_store_eq(const FluidArgs &a, const float (&m)[8],
-                                                 uint32_t s, uint8_t fg, const float4 &ibv,
-                                                 float psi0, float psi1, const float (&S0)[3],
-                                                 const float (&S1)[3], const float (&rx)[3]) {
+// Forces and the equilibrium velocity of both components at one site (tau = 1), and the
+// outputs of window sites.  m: rho, j of both components; S0/S1: stencil sums over the
+// partner component of 0 and 1; ue[c]: u^eq of component c.
+__device__ __forceinline__ void eq_velocity(const FluidArgs &a, const float (&m)[8], uint32_t s,
+                                            uint8_t fg, const float4 &ibv, float psi0,
+                                            float psi1, const float (&S0)[3],
+                                            const float (&S1)[3], const float (&rx)[3],
+                                            float (&ue)[2][3]) {
     const float rho[2] = {m[0], m[4]};
     const float jx[2] = {m[1], m[5]}, jy[2] = {m[2], m[6]}, jz[2] = {m[3], m[7]};
     if (!(rho[0] >= 0.f) || !(rho[1] >= 0.f) || !(rho[0] + rho[1] < 3.0e38f))
@@ -614,47 +614,9 @@ __device__ __forceinline__ void collide_store_eq(const FluidArgs &a, const float
     for (int c = 0; c < 2; ++c) {
         const float *Fc = c == 0 ? F0 : F1;
         const float k = rho[c] > 0.f ? a.tau[c] * rcp(rho[c]) : 0.f;
-        const float u0 = up0 + k * Fc[0], u1 = up1 + k * Fc[1], u2 = up2 + k * Fc[2];
-        const float uu = 1.5f * (u0 * u0 + u1 * u1 + u2 * u2);
-        if constexpr (S == 3) {
-            // relative deviation from the rest equilibrium at this site's new density (stored
-            // beside the populations): d_i = f_i^eq / (ws_i rho) - 1
-            //     = (w_i / ws_i - 1) + (w_i / ws_i)(3 e.u + 4.5 (e.u)^2 - 1.5 u.u),
-            // computed without forming f_i.  The rest population takes the value that makes
-            // sum_i ws_i rho (1 + d_i) = rho with the others as rounded, so a site's stored
-            // mass carries one FP16 rounding of that second-order value (mass conservation)
-            float sa = 0.f, sd = 0.f;   // rounded deviations of the axis / diagonal links
-#pragma unroll
-            for (int q = 1; q < Q; q += 2) {
-                const float r = wq(q) / wshift(q);
-                const float eu = CX[q] * u0 + CY[q] * u1 + CZ[q] * u2;
-                const float A = 4.5f * eu * eu - uu, B = 3.0f * eu;
-                const float dq = (float)(_Float16)((r - 1.0f) + r * (A + B));
-                const float dopp = (float)(_Float16)((r - 1.0f) + r * (A - B));
-                if (is_axis(q)) sa += dq + dopp;
-                else sd += dq + dopp;
-                Pop<S>::store_raw(a.fout, c * Q + q, a.N, s, dq);
-                Pop<S>::store_raw(a.fout, c * Q + q + 1, a.N, s, dopp);
-            }
-            constexpr float ka = wshift(1) / wshift(0), kd = wshift(5) / wshift(0);
-            Pop<S>::store_raw(a.fout, c * Q, a.N, s, (float)(_Float16)(-(ka * sa + kd * sd)));
-            a.rout[c * a.N + s] = rho[c];
-            continue;
-        }
-        const float sh = a.shift[c];
-        float sum = 0.f;
-#pragma unroll
-        for (int q = 1; q < Q; q += 2) {
-            const float w = wq(q) * rho[c];
-            const float eu = CX[q] * u0 + CY[q] * u1 + CZ[q] * u2;
-            const float A = w * (1.0f + 4.5f * eu * eu - uu);
-            const float B = 3.0f * w * eu;
-            const float fq = A + B, fo = A - B;
-            sum += fq + fo;
-            Pop<S>::store(a.fout, c * Q + q, a.N, s, fq, wsh<S>(q) * sh);
-            Pop<S>::store(a.fout, c * Q + q + 1, a.N, s, fo, wsh<S>(q) * sh);
-        }
-        Pop<S>::store(a.fout, c * Q, a.N, s, rho[c] - sum, wsh<S>(0) * sh);
+        ue[c][0] = up0 + k * Fc[0];
+        ue[c][1] = up1 + k * Fc[1];
+        ue[c][2] = up2 + k * Fc[2];
     }
     if (aux) {
         // window sites: physical velocity with the kernel coverage c(x) in .w, and the
@@ -668,6 +630,91 @@ __device__ __forceinline__ void collide_store_eq(const FluidArgs &a, const float
     }
     if ((rx[0] != 0.f || rx[1] != 0.f || rx[2] != 0.f) && !(aux && fb[3] > 0.f))
         atomicAdd(&a.status[ST_LOST], 1);
+}
+
+// The stored values (Codec<S>::T) of f^eq (eq. lbm:equilibrium) of one component at a site
+// of density rho and equilibrium velocity u.  Opposite links q, q + 1 (q odd) are
+// evaluated as a symmetric part A and an antisymmetric part B (eq_link, q ascending); the
+// rest population (eq_rest) takes rho minus the others so the rounded weights add no mass.
+// acc carries the running sums between them.
+struct EqAcc {
+    float a = 0.f, b = 0.f;
+};
+
+template <int S>
+__device__ __forceinline__ void eq_link(int q, float rho, float u0, float u1, float u2, float uu,
+                                        float sh, EqAcc &acc, typename Codec<S>::T &eq,
+                                        typename Codec<S>::T &eo) {
+    using T = typename Codec<S>::T;
+    const float eu = CX[q] * u0 + CY[q] * u1 + CZ[q] * u2;
+    if constexpr (S == 3) {
+        // relative deviation from the rest equilibrium at this site's new density (stored
+        // beside the populations): d_i = f_i^eq / (ws_i rho) - 1
+        //     = (w_i / ws_i - 1) + (w_i / ws_i)(3 e.u + 4.5 (e.u)^2 - 1.5 u.u),
+        // computed without forming f_i; acc sums the rounded values of axis (a) and diagonal
+        // (b) links
+        const float r = wq(q) / wshift(q);
+        const float A = 4.5f * eu * eu - uu, B = 3.0f * eu;
+        eq = (T)((r - 1.0f) + r * (A + B));
+        eo = (T)((r - 1.0f) + r * (A - B));
+        if (is_axis(q)) acc.a += (float)eq + (float)eo;
+        else acc.b += (float)eq + (float)eo;
+    } else {
+        const float w = wq(q) * rho;
+        const float A = w * (1.0f + 4.5f * eu * eu - uu);
+        const float B = 3.0f * w * eu;
+        const float fq = A + B, fo = A - B;
+        acc.a += fq + fo;
+        eq = Codec<S>::enc(fq, wsh<S>(q) * sh);
+        eo = Codec<S>::enc(fo, wsh<S>(q) * sh);
+    }
+}
+
+template <int S>
+__device__ __forceinline__ typename Codec<S>::T eq_rest(float rho, float sh, const EqAcc &acc) {
+    if constexpr (S == 3) {
+        // the rest deviation that makes sum_i ws_i rho (1 + d_i) = rho with the others as
+        // rounded, so a site's stored mass carries one FP16 rounding of that second-order
+        // value (mass conservation)
+        constexpr float ka = wshift(1) / wshift(0), kd = wshift(5) / wshift(0);
+        return (typename Codec<S>::T)(-(ka * acc.a + kd * acc.b));
+    } else {
+        return Codec<S>::enc(rho - acc.a, wsh<S>(0) * sh);
+    }
+}
+
+__device__ __forceinline__ float eq_uu(const float (&u)[3]) {
+    return 1.5f * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+}
+
+template <int S>
+__device__ __forceinline__ void eq_encode(const FluidArgs &a, int c, float rho,
+                                          const float (&u)[3],
+                                          typename Codec<S>::T (&e)[Q]) {
+    const float uu = eq_uu(u);
+    const float sh = S == 3 ? 0.f : a.shift[c];
+    EqAcc acc;
+#pragma unroll
+    for (int q = 1; q < Q; q += 2) eq_link<S>(q, rho, u[0], u[1], u[2], uu, sh, acc, e[q], e[q + 1]);
+    e[0] = eq_rest<S>(rho, sh, acc);
+}
+
+// Forces, BGK collision with tau = 1 (f* = f^eq) and store of one site.
+template <int S>
+__device__ __forceinline__ void collide_store_eq(const FluidArgs &a, const float (&m)[8],
+                                                 uint32_t s, uint8_t fg, const float4 &ibv,
+                                                 float psi0, float psi1, const float (&S0)[3],
+                                                 const float (&S1)[3], const float (&rx)[3]) {
+    float ue[2][3];
+    eq_velocity(a, m, s, fg, ibv, psi0, psi1, S0, S1, rx, ue);
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        typename Codec<S>::T e[Q];
+        eq_encode<S>(a, c, m[4 * c], ue[c], e);
+#pragma unroll
+        for (int q = 0; q < Q; ++q) Pop<S>::store_enc(a.fout, c * Q + q, a.N, s, e[q]);
+        if constexpr (S == 3) a.rout[c * a.N + s] = m[4 * c];
+    }
 }
 
 // One workgroup's tile: logical block L of a lattice tiled tiles_x x tiles_y x (z chunks
