@@ -332,6 +332,16 @@ lbm_status lbm_batch_set_parts(lbm_batch *b, int32_t parts);
  * returns, which is without waiting. */
 lbm_status lbm_batch_step(lbm_batch *b, int64_t n);
 
+/* Step replay from a HIP graph: with on = 1, lbm_batch_step runs pairs of steps by
+ * launching a graph that holds two whole steps of every part (their kernels and the
+ * cross-stream dependencies, recorded once per buffer parity on a stream of the batch's own,
+ * at the first step that needs it) on the handles' stream; an odd last step, and every step
+ * while event timing is on, is enqueued as usual.  The graphs are dropped and recorded again
+ * when the batch's tables change (launch shape, parts, a member stepped alone).  Results are
+ * the same bits as without.  on = 0 (the default) enqueues every step.  LBM_E_INVAL for other
+ * values. */
+lbm_status lbm_batch_set_graph(lbm_batch *b, int32_t on);
+
 /* Event timing of the batch's kernels, as lbm_set_profiling / lbm_kernel_stats. */
 lbm_status lbm_batch_set_profiling(lbm_batch *b, int32_t on);
 lbm_status lbm_batch_kernel_stats(lbm_batch *b, lbm_kernel_stat *out, int32_t max, int32_t *n);

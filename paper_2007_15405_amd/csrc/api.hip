@@ -1035,6 +1035,7 @@ struct BatchPart {
     MGroupTotals mtot{};
     int nmg = 0;                   // handles with capsules
     int nblocks = 0;
+    int *d_step = nullptr;         // steps of the part since the tables were written (device)
 };
 
 struct lbm_batch {
@@ -1049,6 +1050,10 @@ struct lbm_batch {
     int64_t since = 0;             // batch steps since then
     bool dirty = true;
     Prof prof;
+    bool use_graph = false;        // replay pairs of steps from a captured graph
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};   // two steps from buffer parity 0 / 1
+    hipStream_t gst = nullptr;     // stream the graphs are captured on (the handles' stream
+                                   // may be the null stream, which cannot be captured)
 };
 
 extern "C" void lbm_batch_destroy(lbm_batch *b);
@@ -1058,14 +1063,23 @@ static lbm_status bfail(lbm_batch *b, lbm_status s, const std::string &m) {
     return s;
 }
 
+static void free_graphs(lbm_batch *b) {
+    for (hipGraphExec_t &g : b->gexec)
+        if (g) {
+            (void)hipGraphExecDestroy(g);
+            g = nullptr;
+        }
+}
+
 static void free_parts(lbm_batch *b) {
+    free_graphs(b);   // they hold the parts' tables and streams
     for (BatchPart &pt : b->parts) {
         if (pt.st && pt.own_stream) {
             (void)hipStreamSynchronize(pt.st);
             (void)hipStreamDestroy(pt.st);
         }
         if (pt.done) (void)hipEventDestroy(pt.done);
-        void *ptrs[] = {pt.d_tab, pt.d_desc, pt.d_mtab, pt.d_mgrp};
+        void *ptrs[] = {pt.d_tab, pt.d_desc, pt.d_mtab, pt.d_mgrp, pt.d_step};
         for (void *q : ptrs)
             if (q) (void)hipFree(q);
     }
@@ -1152,6 +1166,7 @@ static lbm_status batch_tables(lbm_batch *b) {
                   dalloc(&pt.d_desc, desc.size()) == hipSuccess &&
                   dalloc(&pt.d_mtab, mtab.size()) == hipSuccess &&
                   dalloc(&pt.d_mgrp, mgrp.size()) == hipSuccess &&
+                  dalloc(&pt.d_step, 1) == hipSuccess &&
                   hipEventCreateWithFlags(&pt.done, hipEventDisableTiming) == hipSuccess;
         if (ok && np > 1) {
             ok = hipStreamCreateWithFlags(&pt.st, hipStreamNonBlocking) == hipSuccess;
@@ -1160,7 +1175,9 @@ static lbm_status batch_tables(lbm_batch *b) {
             pt.st = b->st;
         }
         if (!ok) return bfail(b, LBM_E_NOMEM, "device allocation failed (batch)");
-        if (hipMemcpy(pt.d_tab, tab.data(), tab.size() * sizeof(FluidArgs), hipMemcpyHostToDevice) != hipSuccess ||
+        const int zero = 0;
+        if (hipMemcpy(pt.d_step, &zero, sizeof zero, hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(pt.d_tab, tab.data(), tab.size() * sizeof(FluidArgs), hipMemcpyHostToDevice) != hipSuccess ||
             hipMemcpy(pt.d_desc, desc.data(), desc.size() * sizeof(int4), hipMemcpyHostToDevice) != hipSuccess ||
             (pt.nmg && (hipMemcpy(pt.d_mtab, mtab.data(), mtab.size() * sizeof(MembraneArgs), hipMemcpyHostToDevice) != hipSuccess ||
                         hipMemcpy(pt.d_mgrp, mgrp.data(), mgrp.size() * sizeof(MGroup), hipMemcpyHostToDevice) != hipSuccess)))
@@ -1230,14 +1247,20 @@ extern "C" lbm_status lbm_batch_set_parts(lbm_batch *b, int32_t parts) {
     return LBM_OK;
 }
 
+extern "C" lbm_status lbm_batch_set_graph(lbm_batch *b, int32_t on) {
+    if (!b) return LBM_E_INVAL;
+    if (on != 0 && on != 1) return bfail(b, LBM_E_INVAL, "graph must be 0 or 1");
+    b->use_graph = on != 0;
+    return LBM_OK;
+}
+
 // one step of a part on its stream: labels / forces / spreading, fluid, node update
 static void part_step(lbm_batch *b, BatchPart &pt) {
     const hipStream_t st = pt.st;
     const MGroupTotals &mt = pt.mtot;
-    const int de = (int)(b->since & 0x7fffffff);
     if (pt.nmg) {
         timed(b->prof, st, "capsule_reduce", [&] {
-            launch_capsule_reduce_multi(pt.d_mtab, pt.d_mgrp, pt.nmg, mt, de, st);
+            launch_capsule_reduce_multi(pt.d_mtab, pt.d_mgrp, pt.nmg, mt, pt.d_step, st);
         });
         timed(b->prof, st, "membrane", [&] { launch_membrane_multi(pt.d_mtab, pt.d_mgrp, pt.nmg, mt, st); });
         timed(b->prof, st, "window_fill", [&] {
@@ -1255,7 +1278,73 @@ static void part_step(lbm_batch *b, BatchPart &pt) {
         }
     });
     if (pt.nmg)
-        timed(b->prof, st, "node_update", [&] { launch_node_update_multi(pt.d_mtab, pt.d_mgrp, pt.nmg, mt, st); });
+        timed(b->prof, st, "node_update", [&] {
+            launch_node_update_multi(pt.d_mtab, pt.d_mgrp, pt.nmg, mt, pt.d_step, st);
+        });
+}
+
+// enqueue n steps of every part (on the parts' streams, forked from and joined back to the
+// stream ost) and advance the handles' buffer parity and step counts
+static hipError_t enqueue_batch_steps(lbm_batch *b, int64_t n, hipStream_t ost) {
+    hipError_t e = hipSuccess;
+    bool forked = false;
+    for (const BatchPart &pt : b->parts) forked = forked || pt.st != ost;
+    if (forked) {   // the parts' streams start after the work already on ost
+        e = hipEventRecord(b->start, ost);
+        for (BatchPart &pt : b->parts)
+            if (e == hipSuccess && pt.st != ost) e = hipStreamWaitEvent(pt.st, b->start, 0);
+    }
+    for (int64_t i = 0; i < n && e == hipSuccess; ++i) {
+        for (BatchPart &pt : b->parts) part_step(b, pt);
+        for (lbm_handle *h : b->hs) {
+            h->cur = 1 - h->cur;
+            h->step++;
+        }
+        b->since++;
+    }
+    if (forked)     // and ost continues after all of them
+        for (BatchPart &pt : b->parts) {
+            if (e == hipSuccess && pt.st != ost) e = hipEventRecord(pt.done, pt.st);
+            if (e == hipSuccess && pt.st != ost) e = hipStreamWaitEvent(ost, pt.done, 0);
+        }
+    return e;
+}
+
+// capture two steps starting from buffer parity par (the current one) into gexec[par]; the
+// capture only records, so the bookkeeping that enqueue_batch_steps advanced is put back
+static hipError_t capture_batch_graph(lbm_batch *b, int par) {
+    const int64_t since = b->since;
+    std::vector<int> cur;
+    std::vector<int64_t> step;
+    for (const lbm_handle *h : b->hs) {
+        cur.push_back(h->cur);
+        step.push_back(h->step);
+    }
+    hipError_t e = b->gst ? hipSuccess : hipStreamCreateWithFlags(&b->gst, hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+    // a part that runs on the handles' stream is recorded on the capture stream instead
+    std::vector<bool> moved;
+    for (BatchPart &pt : b->parts) {
+        moved.push_back(pt.st == b->st);
+        if (pt.st == b->st) pt.st = b->gst;
+    }
+    e = hipStreamBeginCapture(b->gst, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        const hipError_t eq = enqueue_batch_steps(b, 2, b->gst);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(b->gst, &g);
+        if (e == hipSuccess) e = eq;
+        if (e == hipSuccess) e = hipGraphInstantiate(&b->gexec[par], g, nullptr, nullptr, 0);
+        if (g) (void)hipGraphDestroy(g);
+    }
+    for (size_t i = 0; i < b->parts.size(); ++i)
+        if (moved[i]) b->parts[i].st = b->st;
+    b->since = since;
+    for (size_t i = 0; i < b->hs.size(); ++i) {
+        b->hs[i]->cur = cur[i];
+        b->hs[i]->step = step[i];
+    }
+    return e;
 }
 
 extern "C" lbm_status lbm_batch_step(lbm_batch *b, int64_t n) {
@@ -1276,25 +1365,19 @@ extern "C" lbm_status lbm_batch_step(lbm_batch *b, int64_t n) {
         if (s != LBM_OK) return s;
     }
     hipError_t e = hipSuccess;
-    const bool forked = b->parts.size() > 1;
-    if (forked) {   // the parts' streams start after the work already on the handles' stream
-        e = hipEventRecord(b->start, b->st);
-        for (BatchPart &pt : b->parts)
-            if (e == hipSuccess) e = hipStreamWaitEvent(pt.st, b->start, 0);
-    }
-    for (int64_t i = 0; i < n && e == hipSuccess; ++i) {
-        for (BatchPart &pt : b->parts) part_step(b, pt);
-        for (lbm_handle *h : b->hs) {
-            h->cur = 1 - h->cur;
-            h->step++;
+    int64_t left = n;
+    if (b->use_graph && b->prof.mode == 0) {
+        // pairs of steps replayed from the graph of the current buffer parity
+        for (; left >= 2 && e == hipSuccess; left -= 2) {
+            const int par = (int)(b->since & 1);
+            if (!b->gexec[par]) e = capture_batch_graph(b, par);
+            if (e == hipSuccess) e = hipGraphLaunch(b->gexec[par], b->st);
+            if (e != hipSuccess) break;
+            for (lbm_handle *h : b->hs) h->step += 2;   // two steps: parity unchanged
+            b->since += 2;
         }
-        b->since++;
     }
-    if (forked)     // and the handles' stream continues after all of them
-        for (BatchPart &pt : b->parts) {
-            if (e == hipSuccess) e = hipEventRecord(pt.done, pt.st);
-            if (e == hipSuccess) e = hipStreamWaitEvent(b->st, pt.done, 0);
-        }
+    if (e == hipSuccess && left > 0) e = enqueue_batch_steps(b, left, b->st);
     if (e == hipSuccess) e = hipGetLastError();
     if (e != hipSuccess) return bfail(b, LBM_E_DEVICE, std::string("batch step: ") + hipGetErrorString(e));
     return LBM_OK;
@@ -1391,6 +1474,10 @@ extern "C" void lbm_batch_destroy(lbm_batch *b) {
     if (!b) return;
     if (b->st) (void)hipStreamSynchronize(b->st);
     free_parts(b);
+    if (b->gst) {
+        (void)hipStreamSynchronize(b->gst);
+        (void)hipStreamDestroy(b->gst);
+    }
     if (b->start) (void)hipEventDestroy(b->start);
     free_prof(b->prof);
     delete b;

@@ -288,15 +288,16 @@ struct MGroupTotals {
 };
 int membrane_blocks(int ntot, int ttot, int *nb_forces);
 int node_update_blocks(int ntot);
-// de: steps since the tables were written (added to each group's epoch0)
+// *d_de: steps since the tables were written (added to each group's epoch0), kept on the
+// device and advanced by launch_node_update_multi, so a captured step graph replays as is
 void launch_capsule_reduce_multi(const MembraneArgs *tab, const MGroup *grp, int ng,
-                                 const MGroupTotals &t, int de, hipStream_t st);
+                                 const MGroupTotals &t, const int *d_de, hipStream_t st);
 void launch_membrane_multi(const MembraneArgs *tab, const MGroup *grp, int ng,
                            const MGroupTotals &t, hipStream_t st);
 void launch_window_fill_multi(const MembraneArgs *tab, const MGroup *grp, int ng,
                               const MGroupTotals &t, hipStream_t st);
 void launch_node_update_multi(const MembraneArgs *tab, const MGroup *grp, int ng,
-                              const MGroupTotals &t, hipStream_t st);
+                              const MGroupTotals &t, int *d_step, hipStream_t st);
 
 int reduce_chunks(int max_work);
 void launch_capsule_reduce(const MembraneArgs &m, hipStream_t st);

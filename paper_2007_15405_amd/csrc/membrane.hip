@@ -931,7 +931,8 @@ enum { MG_CAP0 = 0, MG_MEM0 = 1, MG_UPD0 = 2, MG_NTOT = 3, MG_TTOT = 4, MG_NBF =
 
 __global__ void __launch_bounds__(RED_BLK) k_capsule_partial_multi(const MembraneArgs *tab,
                                                                    const MGroup *grp, int ng,
-                                                                   int de) {
+                                                                   const int *d_de) {
+    const int de = *d_de;
     const int K = blockIdx.y, g = find_group(grp, ng, MG_CAP0, K);
     MembraneArgs m;
     load_margs(tab, g, m);
@@ -942,7 +943,8 @@ __global__ void __launch_bounds__(RED_BLK) k_capsule_partial_multi(const Membran
 
 __global__ void __launch_bounds__(RED_BLK) k_capsule_window_multi(const MembraneArgs *tab,
                                                                   const MGroup *grp, int ng,
-                                                                  int de) {
+                                                                  const int *d_de) {
+    const int de = *d_de;
     const int K = blockIdx.x, g = find_group(grp, ng, MG_CAP0, K);
     MembraneArgs m;
     load_margs(tab, g, m);
@@ -976,8 +978,12 @@ __global__ void __launch_bounds__(256) k_window_combine_multi(const MembraneArgs
 }
 
 __global__ void __launch_bounds__(UPD_BLK) k_node_update_multi(const MembraneArgs *tab,
-                                                               const MGroup *grp, int ng) {
+                                                               const MGroup *grp, int ng,
+                                                               int *d_step) {
     const int B = blockIdx.x, g = find_group(grp, ng, MG_UPD0, B);
+    // the step count the next reduction stamps its records with (no kernel of this step
+    // reads it any more)
+    if (B == 0 && threadIdx.x == 0) *d_step += 1;
     MembraneArgs m;
     load_margs(tab, g, m);
     node_update_body(m, B - grp_field(grp, g, MG_UPD0), grp_field(grp, g, MG_NBU),
@@ -985,11 +991,11 @@ __global__ void __launch_bounds__(UPD_BLK) k_node_update_multi(const MembraneArg
 }
 
 void launch_capsule_reduce_multi(const MembraneArgs *tab, const MGroup *grp, int ng,
-                                 const MGroupTotals &t, int de, hipStream_t st) {
+                                 const MGroupTotals &t, const int *d_de, hipStream_t st) {
     hipLaunchKernelGGL(k_capsule_partial_multi, dim3(t.nch_max, t.ncap), dim3(RED_BLK), 0, st,
-                       tab, grp, ng, de);
+                       tab, grp, ng, d_de);
     hipLaunchKernelGGL(k_capsule_window_multi, dim3(t.ncap), dim3(RED_BLK), 0, st, tab, grp, ng,
-                       de);
+                       d_de);
 }
 
 void launch_membrane_multi(const MembraneArgs *tab, const MGroup *grp, int ng,
@@ -1004,9 +1010,9 @@ void launch_window_fill_multi(const MembraneArgs *tab, const MGroup *grp, int ng
 }
 
 void launch_node_update_multi(const MembraneArgs *tab, const MGroup *grp, int ng,
-                              const MGroupTotals &t, hipStream_t st) {
+                              const MGroupTotals &t, int *d_step, hipStream_t st) {
     hipLaunchKernelGGL(k_node_update_multi, dim3(t.upd_blocks), dim3(UPD_BLK), 0, st, tab, grp,
-                       ng);
+                       ng, d_step);
 }
 
 }  // namespace lbmx

@@ -112,6 +112,7 @@ SIGNATURES = {
                                      C.POINTER(C.c_double)]),
     "lbm_batch_step": (C.c_int, [H, C.c_int64]),
     "lbm_batch_set_profiling": (C.c_int, [H, C.c_int32]),
+    "lbm_batch_set_graph": (C.c_int, [H, C.c_int32]),
     "lbm_batch_kernel_stats": (C.c_int, [H, C.POINTER(KernelStat), C.c_int32, C.POINTER(C.c_int32)]),
     "lbm_batch_last_error": (C.c_char_p, [H]),
     "lbm_batch_destroy": (None, [H]),
@@ -434,6 +435,10 @@ class Batch:
 
     def set_profiling(self, on=True):
         self._check(self.L.lbm_batch_set_profiling(self.b, int(on)))
+
+    def set_graph(self, on=True):
+        """``lbm_batch_set_graph``: replay pairs of steps from a captured HIP graph."""
+        self._check(self.L.lbm_batch_set_graph(self.b, int(bool(on))))
 
     def kernel_stats(self) -> dict:
         arr = (KernelStat * 32)()

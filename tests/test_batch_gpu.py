@@ -343,3 +343,53 @@ def test_batch_with_16bit_storage_tracks_handles_stepped_alone(storage, tol):
         assert max(e) <= tol
         assert sims[i].summary()["unstable"] == 0
     bt.close()
+
+
+@pytest.mark.parametrize("parts", [1, 2])
+def test_graph_replay_equals_enqueued_steps(parts):
+    """lbm_batch_set_graph: pairs of steps replayed from a captured graph give the same bits
+    as the same steps enqueued one by one.  Replays are checked one at a time, with the
+    program's own work (observables, synchronisation) between them; an odd step count, a
+    member stepped alone (the graphs are recorded again) and event timing (steps enqueued
+    as usual) are covered."""
+    from paper_2007_15405_amd import Batch
+    cfgs = batch_members()
+    sims = [_sim(c) for c in cfgs]
+    refs = [_sim(c) for c in cfgs]
+    for x in sims + refs:
+        x.set_launch(10, 4)
+    bg = Batch(sims, tile=10, zchunk=4, parts=parts)
+    br = Batch(refs, tile=10, zchunk=4, parts=parts)
+    bg.set_graph(True)
+
+    def same(tag):
+        for i, (s, r) in enumerate(zip(sims, refs)):
+            assert np.array_equal(s.rho(), r.rho()), f"{tag}: member {i} densities"
+            for k in range(len(cfgs[i]["capsules"])):
+                assert np.array_equal(s.nodes(k), r.nodes(k)), f"{tag}: member {i} nodes"
+            ss = s.summary()
+            assert ss["step"] == r.summary()["step"] and ss["unstable"] == 0, tag
+
+    for rep in range(4):          # one graph launch per call, checked after each
+        bg.step(2)
+        br.step(2)
+        same(f"replay {rep}")
+    bg.step(5)                    # two replays and an enqueued step: the other parity next
+    br.step(5)
+    same("odd count")
+    bg.step(4)
+    br.step(4)
+    same("replays from parity 1")
+    sims[1].step(1)               # tables rewritten: graphs recorded again
+    refs[1].step(1)
+    bg.step(6)
+    br.step(6)
+    same("after a member stepped alone")
+    bg.set_profiling(1)           # timed steps are enqueued
+    bg.step(2)
+    br.step(2)
+    bg.set_profiling(0)
+    same("timed")
+    say("graph replay, parts", parts, ": bit-identical after", sims[0].summary()["step"], "steps")
+    bg.close()
+    br.close()
