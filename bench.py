@@ -166,6 +166,23 @@ def run_batch(storage, steps, warmup, do_tune=True, launch=None, parts=None):
     bt.set_graph(False)
     graph = ms_graph < ms
     ms = min(ms, ms_graph)
+    # the fluid launch as a resident grid taking tiles from a device work queue: its kernel
+    # time with one part (as fluid_ms), then the step time with the fastest split
+    bt.set_schedule(True)
+    bt.set_parts(1)
+    bt.step(warmup)
+    bt.sync()
+    bt.kernel_stats()
+    bt.set_profiling(2)
+    bt.step(min(steps, 20))
+    nq, fq = bt.kernel_stats()["fluid"]
+    bt.set_profiling(0)
+    bt.set_parts(best_parts)
+    bt.step(warmup)
+    ms_queue = timed_steps()
+    bt.set_schedule(False)
+    schedule = "queue" if ms_queue < ms else "static"
+    ms = min(ms, ms_queue)
     sites, bps = bt.fluid_sites, bt.bytes_per_site
     fl_avg = fms / n
     achieved = bps * sites / (fl_avg * 1e-3) / 1e9
@@ -179,6 +196,8 @@ def run_batch(storage, steps, warmup, do_tune=True, launch=None, parts=None):
         parts=best_parts,
         ms_per_step_by_parts={k: round(v / steps, 5) for k, v in per_parts.items()},
         ms_per_step_graph=round(ms_graph / steps, 5), graph=graph,
+        ms_per_step_queue=round(ms_queue / steps, 5), fluid_ms_queue=round(fq / nq, 5),
+        schedule=schedule,
         fluid_ms=round(fl_avg, 5), bytes_per_site=bps, achieved_gbs=round(achieved, 1),
         frac=round(achieved / PEAK_HBM_GBS, 4),
         launch=dict(tile=TILES[best[1]], tile_id=best[1], zchunk=best[2]),

@@ -332,6 +332,14 @@ lbm_status lbm_batch_set_parts(lbm_batch *b, int32_t parts);
  * returns, which is without waiting. */
 lbm_status lbm_batch_step(lbm_batch *b, int64_t n);
 
+/* Block schedule of the batched fluid launch.  queue = 0 (the default): one workgroup per
+ * tile, numbered so that each XCD runs a contiguous run of tiles.  queue = 1: a resident
+ * grid of one 512-thread workgroup (two of 256) per compute unit takes the tiles from a
+ * work queue on the device, each XCD its own run first, then those of the others.  The
+ * per-tile arithmetic is the same, so results are the same bits.  LBM_E_INVAL for other
+ * values. */
+lbm_status lbm_batch_set_schedule(lbm_batch *b, int32_t queue);
+
 /* Step replay from a HIP graph: with on = 1, lbm_batch_step runs pairs of steps by
  * launching a graph that holds two whole steps of every part (their kernels and the
  * cross-stream dependencies, recorded once per buffer parity on a stream of the batch's own,

@@ -1036,6 +1036,7 @@ struct BatchPart {
     int nmg = 0;                   // handles with capsules
     int nblocks = 0;
     int *d_step = nullptr;         // steps of the part since the tables were written (device)
+    int *d_queue = nullptr;        // work queue of the persistent fluid launch (9 ints)
 };
 
 struct lbm_batch {
@@ -1050,6 +1051,8 @@ struct lbm_batch {
     int64_t since = 0;             // batch steps since then
     bool dirty = true;
     Prof prof;
+    bool queue = false;            // fluid launch: resident grid with a work queue
+    int ncu = 0;                   // compute units of the device
     bool use_graph = false;        // replay pairs of steps from a captured graph
     hipGraphExec_t gexec[2] = {nullptr, nullptr};   // two steps from buffer parity 0 / 1
     hipStream_t gst = nullptr;     // stream the graphs are captured on (the handles' stream
@@ -1079,7 +1082,7 @@ static void free_parts(lbm_batch *b) {
             (void)hipStreamDestroy(pt.st);
         }
         if (pt.done) (void)hipEventDestroy(pt.done);
-        void *ptrs[] = {pt.d_tab, pt.d_desc, pt.d_mtab, pt.d_mgrp, pt.d_step};
+        void *ptrs[] = {pt.d_tab, pt.d_desc, pt.d_mtab, pt.d_mgrp, pt.d_step, pt.d_queue};
         for (void *q : ptrs)
             if (q) (void)hipFree(q);
     }
@@ -1166,7 +1169,7 @@ static lbm_status batch_tables(lbm_batch *b) {
                   dalloc(&pt.d_desc, desc.size()) == hipSuccess &&
                   dalloc(&pt.d_mtab, mtab.size()) == hipSuccess &&
                   dalloc(&pt.d_mgrp, mgrp.size()) == hipSuccess &&
-                  dalloc(&pt.d_step, 1) == hipSuccess &&
+                  dalloc(&pt.d_step, 1) == hipSuccess && dalloc(&pt.d_queue, 9) == hipSuccess &&
                   hipEventCreateWithFlags(&pt.done, hipEventDisableTiming) == hipSuccess;
         if (ok && np > 1) {
             ok = hipStreamCreateWithFlags(&pt.st, hipStreamNonBlocking) == hipSuccess;
@@ -1175,8 +1178,9 @@ static lbm_status batch_tables(lbm_batch *b) {
             pt.st = b->st;
         }
         if (!ok) return bfail(b, LBM_E_NOMEM, "device allocation failed (batch)");
-        const int zero = 0;
-        if (hipMemcpy(pt.d_step, &zero, sizeof zero, hipMemcpyHostToDevice) != hipSuccess ||
+        const int zero[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+        if (hipMemcpy(pt.d_step, zero, sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(pt.d_queue, zero, sizeof zero, hipMemcpyHostToDevice) != hipSuccess ||
             hipMemcpy(pt.d_tab, tab.data(), tab.size() * sizeof(FluidArgs), hipMemcpyHostToDevice) != hipSuccess ||
             hipMemcpy(pt.d_desc, desc.data(), desc.size() * sizeof(int4), hipMemcpyHostToDevice) != hipSuccess ||
             (pt.nmg && (hipMemcpy(pt.d_mtab, mtab.data(), mtab.size() * sizeof(MembraneArgs), hipMemcpyHostToDevice) != hipSuccess ||
@@ -1216,7 +1220,9 @@ extern "C" lbm_status lbm_batch_create(lbm_handle *const *handles, int32_t n, lb
     b->device = handles[0]->p.device;
     b->step0.assign(n, 0);
     if (hipSetDevice(b->device) != hipSuccess ||
-        hipEventCreateWithFlags(&b->start, hipEventDisableTiming) != hipSuccess) {
+        hipEventCreateWithFlags(&b->start, hipEventDisableTiming) != hipSuccess ||
+        hipDeviceGetAttribute(&b->ncu, hipDeviceAttributeMultiprocessorCount, b->device) !=
+            hipSuccess) {
         lbm_batch_destroy(b);
         g_init_error = "device call failed (batch)";
         return LBM_E_DEVICE;
@@ -1247,6 +1253,14 @@ extern "C" lbm_status lbm_batch_set_parts(lbm_batch *b, int32_t parts) {
     return LBM_OK;
 }
 
+extern "C" lbm_status lbm_batch_set_schedule(lbm_batch *b, int32_t queue) {
+    if (!b) return LBM_E_INVAL;
+    if (queue != 0 && queue != 1) return bfail(b, LBM_E_INVAL, "schedule must be 0 or 1");
+    b->queue = queue != 0;
+    free_graphs(b);   // the recorded fluid launches follow the schedule
+    return LBM_OK;
+}
+
 extern "C" lbm_status lbm_batch_set_graph(lbm_batch *b, int32_t on) {
     if (!b) return LBM_E_INVAL;
     if (on != 0 && on != 1) return bfail(b, LBM_E_INVAL, "graph must be 0 or 1");
@@ -1269,12 +1283,13 @@ static void part_step(lbm_batch *b, BatchPart &pt) {
     }
     const int m = (int)pt.idx.size();
     const FluidArgs *tab = pt.d_tab + (size_t)(b->since & 1) * m;
+    int *q = b->queue ? pt.d_queue : nullptr;
     timed(b->prof, st, "fluid", [&] {
         switch (b->storage) {
-            case 0: launch_fluid_multi<0>(tab, pt.d_desc, m, pt.nblocks, b->tile, st); break;
-            case 1: launch_fluid_multi<1>(tab, pt.d_desc, m, pt.nblocks, b->tile, st); break;
-            case 2: launch_fluid_multi<2>(tab, pt.d_desc, m, pt.nblocks, b->tile, st); break;
-            default: launch_fluid_multi<3>(tab, pt.d_desc, m, pt.nblocks, b->tile, st); break;
+            case 0: launch_fluid_multi<0>(tab, pt.d_desc, m, pt.nblocks, b->tile, q, b->ncu, st); break;
+            case 1: launch_fluid_multi<1>(tab, pt.d_desc, m, pt.nblocks, b->tile, q, b->ncu, st); break;
+            case 2: launch_fluid_multi<2>(tab, pt.d_desc, m, pt.nblocks, b->tile, q, b->ncu, st); break;
+            default: launch_fluid_multi<3>(tab, pt.d_desc, m, pt.nblocks, b->tile, q, b->ncu, st); break;
         }
     });
     if (pt.nmg)
@@ -1420,11 +1435,12 @@ extern "C" lbm_status lbm_batch_autotune(lbm_batch *b, int32_t reps, int32_t *ti
             hipError_t e = time_launches(b->st, reps, ev.a, ev.b, [&] {
                 for (BatchPart &pt : b->parts) {
                     const int m = (int)pt.idx.size();
+                    int *q = b->queue ? pt.d_queue : nullptr;
                     switch (b->storage) {
-                        case 0: launch_fluid_multi<0>(pt.d_tab, pt.d_desc, m, pt.nblocks, t, b->st); break;
-                        case 1: launch_fluid_multi<1>(pt.d_tab, pt.d_desc, m, pt.nblocks, t, b->st); break;
-                        case 2: launch_fluid_multi<2>(pt.d_tab, pt.d_desc, m, pt.nblocks, t, b->st); break;
-                        default: launch_fluid_multi<3>(pt.d_tab, pt.d_desc, m, pt.nblocks, t, b->st); break;
+                        case 0: launch_fluid_multi<0>(pt.d_tab, pt.d_desc, m, pt.nblocks, t, q, b->ncu, b->st); break;
+                        case 1: launch_fluid_multi<1>(pt.d_tab, pt.d_desc, m, pt.nblocks, t, q, b->ncu, b->st); break;
+                        case 2: launch_fluid_multi<2>(pt.d_tab, pt.d_desc, m, pt.nblocks, t, q, b->ncu, b->st); break;
+                        default: launch_fluid_multi<3>(pt.d_tab, pt.d_desc, m, pt.nblocks, t, q, b->ncu, b->st); break;
                     }
                 }
             }, &ms);

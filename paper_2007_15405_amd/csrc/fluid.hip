@@ -12,6 +12,8 @@
 // instead of one per population, which the compiler would otherwise keep live across
 // the z march).  Out-of-range offsets read 0 and drop stores instead of faulting.  The
 // byte size of 10 populations of one component must fit 32 bits.
+#include <algorithm>
+
 #include "lbm_internal.h"
 
 namespace lbmx {
@@ -862,10 +864,12 @@ __device__ __forceinline__ void pipe_tile(const FluidArgs &a, int L, int zc, int
         s_psi[slot][0][li] = ps0;
         s_psi[slot][1][li] = ps1;
         s_flag[slot][li] = fg_me;
-        if (WX && li_w >= 0) {
-            s_psi[slot][0][li_w] = ps0;
-            s_psi[slot][1][li_w] = ps1;
-            s_flag[slot][li_w] = fg_me;
+        if constexpr (WX) {
+            if (li_w >= 0) {
+                s_psi[slot][0][li_w] = ps0;
+                s_psi[slot][1][li_w] = ps1;
+                s_flag[slot][li_w] = fg_me;
+            }
         }
         uint8_t fg_h = 0;
         if (hi >= 0) {
@@ -874,10 +878,12 @@ __device__ __forceinline__ void pipe_tile(const FluidArgs &a, int L, int zc, int
             s_psi[slot][0][hi] = hp0;
             s_psi[slot][1][hi] = hp1;
             s_flag[slot][hi] = fg_h;
-            if (WX && hi_w >= 0) {
-                s_psi[slot][0][hi_w] = hp0;
-                s_psi[slot][1][hi_w] = hp1;
-                s_flag[slot][hi_w] = fg_h;
+            if constexpr (WX) {
+                if (hi_w >= 0) {
+                    s_psi[slot][0][hi_w] = hp0;
+                    s_psi[slot][1][hi_w] = hp1;
+                    s_flag[slot][hi_w] = fg_h;
+                }
             }
         }
         const bool any = __builtin_amdgcn_ballot_w64((fg_me | fg_h) != 0) != 0;
@@ -1028,13 +1034,11 @@ __global__ void __launch_bounds__(TX * TY) k_fused_pipe(FluidArgs a, int zc, int
 // constant address space (scalar loads).
 typedef __attribute__((address_space(4))) const int ConstInt;
 
-template <int S, int TX, int TY, bool RT = false>
-__global__ void __launch_bounds__(TX * TY) k_fused_pipe_multi(const FluidArgs *tab,
-                                                              const int4 *desc, int ngroups,
-                                                              int nblocks) {
+// logical block L of a multi-lattice launch: find its lattice, run its tile
+template <int S, int TX, int TY, bool RT>
+__device__ __forceinline__ void pipe_multi_tile(const FluidArgs *tab, const int4 *desc,
+                                                int ngroups, int L) {
     static_assert(sizeof(FluidArgs) % 4 == 0, "word copy");
-    const int L = logical_block();
-    if (L >= nblocks) return;
     ConstInt *cd = (ConstInt *)desc;   // int4 rows
     int g = 0;
     while (g + 1 < ngroups && L >= cd[4 * (g + 1)]) ++g;
@@ -1046,9 +1050,67 @@ __global__ void __launch_bounds__(TX * TY) k_fused_pipe_multi(const FluidArgs *t
     pipe_tile<S, TX, TY, RT, RT>(a, L - cd[4 * g], cd[4 * g + 3], cd[4 * g + 1], cd[4 * g + 2]);
 }
 
+template <int S, int TX, int TY, bool RT = false>
+__global__ void __launch_bounds__(TX * TY) k_fused_pipe_multi(const FluidArgs *tab,
+                                                              const int4 *desc, int ngroups,
+                                                              int nblocks) {
+    const int L = logical_block();
+    if (L >= nblocks) return;
+    pipe_multi_tile<S, TX, TY, RT>(tab, desc, ngroups, L);
+}
+
+// Work-queue form: a resident grid whose blocks take logical tiles from a queue until none
+// is left.  queue[x] counts the tickets of XCD x (hardware block b runs on XCD b % 8), which
+// owns the run of tiles [x * per, (x + 1) * per) as in the static order; a block whose XCD's
+// run is used up takes tickets of the next XCDs.  queue[8] counts the blocks that are done;
+// the last one clears the queue, which must be zero when the kernel starts.
+template <int S, int TX, int TY, bool RT = false>
+__global__ void __launch_bounds__(TX * TY) k_fused_pipe_multi_q(const FluidArgs *tab,
+                                                                const int4 *desc, int ngroups,
+                                                                int nblocks, int *queue) {
+    __shared__ int s_L;
+    const int per = (nblocks + 7) / 8;
+    int x = (int)(blockIdx.x % 8), tried = 0;   // used by thread 0 only
+    for (;;) {
+        if (threadIdx.x == 0) {
+            int L = -1;
+            while (tried < 8) {
+                const int t = atomicAdd(&queue[x], 1);
+                if (t < per && x * per + t < nblocks) {
+                    L = x * per + t;
+                    break;
+                }
+                x = (x + 1) % 8;
+                ++tried;
+            }
+            s_L = L;
+        }
+        __syncthreads();
+        const int L = s_L;
+        __syncthreads();   // s_L is written again only after every thread has read it
+        if (L < 0) break;
+        pipe_multi_tile<S, TX, TY, RT>(tab, desc, ngroups, L);
+    }
+    if (threadIdx.x == 0 && atomicAdd(&queue[8], 1) == (int)gridDim.x - 1)
+        for (int i = 0; i <= 8; ++i) atomicExch(&queue[i], 0);
+}
+
 template <int S>
 void launch_fluid_multi(const FluidArgs *tab, const int4 *desc, int ngroups, int nblocks,
-                        int tile, hipStream_t st) {
+                        int tile, int *queue, int ncu, hipStream_t st) {
+    if (queue) {   // one resident block of 512 threads (two of 256) per compute unit
+        const int nt = (tile >= 6 && tile <= 8) ? 256 : 512;
+        const dim3 grid(std::max(8, std::min(ncu * (512 / nt), nblocks)));
+        switch (tile) {
+            case 6: hipLaunchKernelGGL((k_fused_pipe_multi_q<S, 32, 8>), grid, dim3(256), 0, st, tab, desc, ngroups, nblocks, queue); break;
+            case 7: hipLaunchKernelGGL((k_fused_pipe_multi_q<S, 64, 4>), grid, dim3(256), 0, st, tab, desc, ngroups, nblocks, queue); break;
+            case 8: hipLaunchKernelGGL((k_fused_pipe_multi_q<S, 16, 16>), grid, dim3(256), 0, st, tab, desc, ngroups, nblocks, queue); break;
+            case 9: hipLaunchKernelGGL((k_fused_pipe_multi_q<S, 32, 16>), grid, dim3(512), 0, st, tab, desc, ngroups, nblocks, queue); break;
+            case 13: hipLaunchKernelGGL((k_fused_pipe_multi_q<S, 128, 4, true>), grid, dim3(512), 0, st, tab, desc, ngroups, nblocks, queue); break;
+            default: hipLaunchKernelGGL((k_fused_pipe_multi_q<S, 64, 8>), grid, dim3(512), 0, st, tab, desc, ngroups, nblocks, queue); break;
+        }
+        return;
+    }
     const dim3 grid((nblocks + 7) / 8 * 8);
     switch (tile) {
         case 6: hipLaunchKernelGGL((k_fused_pipe_multi<S, 32, 8>), grid, dim3(256), 0, st, tab, desc, ngroups, nblocks); break;
@@ -1283,8 +1345,8 @@ void launch_meniscus(const float *rho, const uint8_t *flag, float *out, int nx, 
     template void launch_init_eq<S>(const double *, void *, int, int, int, int, int, float,  \
                                     float, float *, hipStream_t);                           \
     template void launch_fluid_tiled<S>(const FluidArgs &, int, int, hipStream_t);          \
-    template void launch_fluid_multi<S>(const FluidArgs *, const int4 *, int, int, int,       \
-                                        hipStream_t);                                         \
+    template void launch_fluid_multi<S>(const FluidArgs *, const int4 *, int, int, int, int *, \
+                                        int, hipStream_t);                                    \
     template void launch_rho<S>(const void *, float *, int, int, int, int, int, float, float, \
                                 const float *, hipStream_t);                                \
     template void launch_moments<S>(const void *, double *, int, int, int, int, int, int,    \

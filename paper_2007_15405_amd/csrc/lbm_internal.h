@@ -264,8 +264,11 @@ template <int S> void launch_fluid_tiled(const FluidArgs &a, int tile, int zc, h
 // y, z planes per chunk}); tile 6..10 and 13 as launch_fluid_tiled (13: every lattice
 // 16 <= nx <= 128, tiles of rows_tile_height(nx) whole rows).
 int rows_tile_height(int nx);
+// queue: nullptr for the static block order; else 9 zeroed device ints of a work queue,
+// and the launch is a resident grid of ncu (compute units) blocks of 512 threads
 template <int S> void launch_fluid_multi(const FluidArgs *tab, const int4 *desc, int ngroups,
-                                         int nblocks, int tile, hipStream_t st);
+                                         int nblocks, int tile, int *queue, int ncu,
+                                         hipStream_t st);
 template <int S> void launch_rho(const void *f, float *rho, int nx, int ny, int nz, int wall,
                                  int lz, float s0, float s1, const float *rsite, hipStream_t st);
 // partial sums [nz / lz][nblocks][5] (mass of both components, momentum) per slab

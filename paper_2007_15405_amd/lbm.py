@@ -113,6 +113,7 @@ SIGNATURES = {
     "lbm_batch_step": (C.c_int, [H, C.c_int64]),
     "lbm_batch_set_profiling": (C.c_int, [H, C.c_int32]),
     "lbm_batch_set_graph": (C.c_int, [H, C.c_int32]),
+    "lbm_batch_set_schedule": (C.c_int, [H, C.c_int32]),
     "lbm_batch_kernel_stats": (C.c_int, [H, C.POINTER(KernelStat), C.c_int32, C.POINTER(C.c_int32)]),
     "lbm_batch_last_error": (C.c_char_p, [H]),
     "lbm_batch_destroy": (None, [H]),
@@ -435,6 +436,11 @@ class Batch:
 
     def set_profiling(self, on=True):
         self._check(self.L.lbm_batch_set_profiling(self.b, int(on)))
+
+    def set_schedule(self, queue=True):
+        """``lbm_batch_set_schedule``: the fluid launch as a resident grid with a work queue
+        (True) or one workgroup per tile in the static order (False)."""
+        self._check(self.L.lbm_batch_set_schedule(self.b, int(bool(queue))))
 
     def set_graph(self, on=True):
         """``lbm_batch_set_graph``: replay pairs of steps from a captured HIP graph."""

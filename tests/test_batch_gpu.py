@@ -393,3 +393,29 @@ def test_graph_replay_equals_enqueued_steps(parts):
     say("graph replay, parts", parts, ": bit-identical after", sims[0].summary()["step"], "steps")
     bg.close()
     br.close()
+
+
+@pytest.mark.parametrize("tile", [10, 13])
+def test_work_queue_schedule_gives_the_same_bits(tile):
+    """lbm_batch_set_schedule(1): the fluid launch as a resident grid taking tiles from a
+    device work queue (the queue clears itself at the end of each launch, also inside a
+    replayed graph) gives the same bits as one workgroup per tile."""
+    from paper_2007_15405_amd import Batch
+    cfgs = batch_members()
+    sims = [_sim(c) for c in cfgs]
+    refs = [_sim(c) for c in cfgs]
+    bq = Batch(sims, tile=tile, zchunk=4, parts=2)
+    br = Batch(refs, tile=tile, zchunk=4, parts=2)
+    bq.set_schedule(True)
+    bq.step(9)
+    br.step(9)
+    bq.set_graph(True)
+    bq.step(6)
+    br.step(6)
+    for i, (s, r) in enumerate(zip(sims, refs)):
+        assert np.array_equal(s.rho(), r.rho()), f"member {i}"
+        for k in range(len(cfgs[i]["capsules"])):
+            assert np.array_equal(s.nodes(k), r.nodes(k))
+    say("work queue, tile", tile, ": bit-identical after 15 steps")
+    bq.close()
+    br.close()

@@ -138,6 +138,7 @@ def test_batch_without_handles_is_rejected():
     assert "NULL" in L.lbm_batch_last_error(None).decode()
     assert L.lbm_batch_step(None, 1) == lbm.LBM_E_INVAL
     assert L.lbm_batch_set_graph(None, 1) == lbm.LBM_E_INVAL
+    assert L.lbm_batch_set_schedule(None, 1) == lbm.LBM_E_INVAL
     L.lbm_batch_destroy(None)
 
 
