@@ -70,12 +70,13 @@ template <int S> struct Pop {
             return Codec<S>::dec(__builtin_bit_cast(T, v), sh);
         }
     }
-    // the stored value itself (storage 3 decodes it later with its source site's density)
+    // the stored value itself, not shifted back (the pipelined kernels add the shifts of a
+    // site's populations once; storage 3 decodes with its source site's density later)
     __device__ static inline float load_raw(const void *f, int qg, int N, uint32_t site) {
         static_assert(sizeof(T) == 2, "16-bit storage");
         const uint16_t v = __builtin_amdgcn_raw_buffer_load_b16(res(f, qg, N), site * 2u,
                                                                  qoff(qg, N), 0);
-        return (float)__builtin_bit_cast(T, v);
+        return Codec<S>::val(__builtin_bit_cast(T, v));
     }
     // stores are non-temporal: the new state is not read again in this step, and keeping
     // it out of L2 leaves room for the source rows that neighbouring tiles pull again
@@ -129,7 +130,10 @@ __device__ __forceinline__ void pull(const void *f, int N, int x, int y, int z, 
 }
 
 // Issue the 38 pulls of site (x, y, z) into registers without consuming them, so the
-// loads stay in flight while other work runs.  Links that cross the wall first read the
+// loads stay in flight while other work runs.  16-bit storages pull the stored values:
+// with a constant shift the shifts of a site's populations add rho_s sum_i w_i to its
+// density and nothing to its momentum (sum_i w_i e_i = 0), which the caller adds once;
+// storage 3 decodes each value with its source site's density.  Links that cross the wall first read the
 // (unused) wall site; a wave-uniform fix-up then replaces them by the bounced
 // population f*_{opp(i)}(x), keeping the load stream free of per-link branches.
 template <int S>
@@ -145,7 +149,7 @@ __device__ __forceinline__ void pull_issue(const void *f, int N, int x, int y, i
         const int ys = CY[q] == 0 ? y : (CY[q] > 0 ? ym : yp);
         const int zs = CZ[q] == 0 ? z : (CZ[q] > 0 ? zm : zp);
         const uint32_t src = (uint32_t)((zs * ny + ys) * nx + xs);
-        if constexpr (S == 3) {   // decoded later with the source site's density
+        if constexpr (S != 0) {   // stored values; the shifts are applied later
             fl[0][q] = Pop<S>::load_raw(f, q, N, src);
             fl[1][q] = Pop<S>::load_raw(f, Q + q, N, src);
         } else {
@@ -158,7 +162,7 @@ __device__ __forceinline__ void pull_issue(const void *f, int N, int x, int y, i
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             if ((CZ[q] > 0 && wall_lo) || (CZ[q] < 0 && wall_hi)) {
-                if constexpr (S == 3) {
+                if constexpr (S != 0) {
                     fl[0][q] = Pop<S>::load_raw(f, OPP[q], N, self);
                     fl[1][q] = Pop<S>::load_raw(f, Q + OPP[q], N, self);
                 } else {
@@ -750,6 +754,17 @@ __device__ __forceinline__ void pipe_tile(const FluidArgs &a, int L, int zc, int
     const int nx = a.nx, ny = a.ny, nz = a.nz, N = a.N;
     const int x0 = bx * tx, y0 = by * ty, z0 = bz * zc, z1 = min(z0 + zc, nz);
     const float sh0 = a.shift[0], sh1 = a.shift[1];
+    // storages 1 and 2: the pulls are the stored values f_i - w_i rho_s; a site's density
+    // takes the sum of its populations' shifts, as encoded (FP32 products w_i rho_s)
+    constexpr bool CONST_SHIFT = S == 1 || S == 2;
+    float ssum0 = 0.f, ssum1 = 0.f;
+    if constexpr (CONST_SHIFT) {
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            ssum0 += wsh<S>(q) * sh0;
+            ssum1 += wsh<S>(q) * sh1;
+        }
+    }
 
     const int tid = threadIdx.x, lx = tid % tx, ly = tid / tx;
     const int wave = tid >> 6, lane = tid & 63;
@@ -854,6 +869,14 @@ __device__ __forceinline__ void pipe_tile(const FluidArgs &a, int L, int zc, int
             if (hi >= 0) {
 #pragma unroll
                 for (int q = 0; q < Q; ++q) { h0 += hf[0][q]; h1 += hf[1][q]; }
+            }
+            if constexpr (CONST_SHIFT) {   // the populations' shifts, once per site
+                r0 += ssum0;
+                r1 += ssum1;
+                h0 += ssum0;
+                h1 += ssum1;
+                m[0] = r0;
+                m[4] = r1;
             }
         } else {
 #pragma unroll

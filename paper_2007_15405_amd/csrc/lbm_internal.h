@@ -73,7 +73,8 @@ template <> struct Codec<0> {
 
 template <> struct Codec<1> {
     using T = _Float16;
-    __device__ static inline float dec(T v, float s) { return (float)v + s; }
+    __device__ static inline float val(T v) { return (float)v; }   // the stored value
+    __device__ static inline float dec(T v, float s) { return val(v) + s; }
     __device__ static inline T enc(float f, float s) { return (_Float16)(f - s); }
 };
 
@@ -85,7 +86,8 @@ template <> struct Codec<1> {
 // velocity below about 0.02, where an absolute encoding keeps few significant bits).
 template <> struct Codec<3> {
     using T = _Float16;
-    __device__ static inline float dec(T v, float s) { return fmaf(s, (float)v, s); }
+    __device__ static inline float val(T v) { return (float)v; }
+    __device__ static inline float dec(T v, float s) { return fmaf(s, val(v), s); }
     __device__ static inline T enc(float f, float s) {
         return s != 0.f ? (_Float16)((f - s) / s) : (_Float16)0.f;
     }
@@ -93,9 +95,8 @@ template <> struct Codec<3> {
 
 template <> struct Codec<2> {
     using T = uint16_t;
-    __device__ static inline float dec(T v, float s) {
-        return __uint_as_float((uint32_t)v << 16) + s;
-    }
+    __device__ static inline float val(T v) { return __uint_as_float((uint32_t)v << 16); }
+    __device__ static inline float dec(T v, float s) { return val(v) + s; }
     __device__ static inline T enc(float f, float s) {
         uint32_t u = __float_as_uint(f - s);
         if ((u & 0x7fffffffu) > 0x7f800000u) return (T)((u >> 16) | 0x40u);  // quiet NaN
