@@ -77,8 +77,6 @@ struct lbm_handle {
     int *d_off = nullptr, *d_list = nullptr, *d_rowstart = nullptr, *d_slot = nullptr;
     double4 *d_xrow = nullptr;
     unsigned long long *d_marks = nullptr;
-    CapPartial *d_part = nullptr;
-    int nch = 1;
     float4 *d_wbuf = nullptr;
     uint8_t *d_wpar = nullptr;
     int4 *d_edge = nullptr;
@@ -174,7 +172,7 @@ static void free_all(lbm_handle *h) {
                     h->rho_tmp, h->men_tmp, h->status, h->partial, h->d_caps, h->d_cst, h->d_X,
                     h->d_node_cap, h->d_F, h->d_Fh, h->d_R, h->d_tri, h->d_minv, h->d_a0,
                     h->d_off, h->d_list, h->d_marks, h->d_rowstart, h->d_slot, h->d_wbuf,
-                    h->d_wpar, h->d_part, h->d_xrow, h->d_edge, h->d_eth0, h->d_eoff,
+                    h->d_wpar, h->d_xrow, h->d_edge, h->d_eth0, h->d_eoff,
                     h->d_elist, h->d_V, h->d_pex, h->d_rsc, h->d_pprev, h->d_ffl,
                     h->d_bcount, h->d_bstart, h->d_blist, h->d_nlinks, h->d_links, h->d_tpos};
     for (void *p : ptrs)
@@ -643,11 +641,6 @@ static lbm_status finalize(lbm_handle *h) {
         h->h_caps.push_back(cd);
     }
     h->ntot = (int)X.size();
-    {
-        int mw = 1;
-        for (const CapDev &c : h->h_caps) mw = std::max(mw, std::max(c.nn, c.nt));
-        h->nch = reduce_chunks(mw);
-    }
     h->ttot = (int)tri.size();
     // node -> incident triangle CSR (entries 3 * triangle + corner, triangle order)
     off.assign(h->ntot + 1, 0);
@@ -699,7 +692,6 @@ static lbm_status finalize(lbm_handle *h) {
         dalloc(&h->d_minv, tt) != hipSuccess || dalloc(&h->d_a0, tt) != hipSuccess ||
         dalloc(&h->d_off, nt + 1) != hipSuccess || dalloc(&h->d_list, list.size()) != hipSuccess ||
         dalloc(&h->d_marks, (size_t)ncap * ROWS_MAX) != hipSuccess ||
-        dalloc(&h->d_part, (size_t)ncap * h->nch) != hipSuccess ||
         dalloc(&h->d_rowstart, (size_t)ncap * (ROWS_MAX + 1)) != hipSuccess ||
         dalloc(&h->d_slot, nt) != hipSuccess || dalloc(&h->d_xrow, nt) != hipSuccess ||
         dalloc(&h->d_wbuf, (size_t)ncap * GMAX3) != hipSuccess ||
@@ -790,7 +782,7 @@ static MembraneArgs membrane_args(lbm_handle *h) {
     m.ntri_off = h->d_off; m.ntri = h->d_list;
     m.edge = h->d_edge; m.eth0 = h->d_eth0; m.nedge_off = h->d_eoff; m.nedge = h->d_elist;
     m.marks = h->d_marks; m.rowstart = h->d_rowstart; m.xrow = h->d_xrow; m.slot = h->d_slot;
-    m.part = h->d_part; m.nch = h->nch;
+
     m.wbuf = h->d_wbuf; m.wpar = h->d_wpar;
     m.flag = h->flag; m.ibm = h->ibm; m.uo = h->uo; m.ro = h->ro; m.status = h->status;
     m.nx = h->nx; m.ny = h->ny; m.nz = h->nz; m.wall = h->wall; m.lz = h->lz;
@@ -899,10 +891,7 @@ extern "C" lbm_status lbm_step(lbm_handle *h, int64_t n) {
     const bool bb = caps && h->p.coupling == 1;
     MembraneArgs m = caps ? membrane_args(h) : MembraneArgs{};
     for (int64_t i = 0; i < n; ++i) {
-        if (caps) {
-            m.epoch = (int)(h->step & 0x7fffffff);
-            capsule_kernels_before(h, m, h->prof);
-        }
+        if (caps) capsule_kernels_before(h, m, h->prof);
         if (bb) {
             const BBArgs b = bb_args(h, h->cur);
             timed(h->prof, h->st, "bounce_back", [&] { launch_bb_before(b, h->storage, h->st); });
@@ -1035,7 +1024,6 @@ struct BatchPart {
     MGroupTotals mtot{};
     int nmg = 0;                   // handles with capsules
     int nblocks = 0;
-    int *d_step = nullptr;         // steps of the part since the tables were written (device)
     int *d_queue = nullptr;        // work queue of the persistent fluid launch (9 ints)
 };
 
@@ -1082,7 +1070,7 @@ static void free_parts(lbm_batch *b) {
             (void)hipStreamDestroy(pt.st);
         }
         if (pt.done) (void)hipEventDestroy(pt.done);
-        void *ptrs[] = {pt.d_tab, pt.d_desc, pt.d_mtab, pt.d_mgrp, pt.d_step, pt.d_queue};
+        void *ptrs[] = {pt.d_tab, pt.d_desc, pt.d_mtab, pt.d_mgrp, pt.d_queue};
         for (void *q : ptrs)
             if (q) (void)hipFree(q);
     }
@@ -1146,11 +1134,9 @@ static lbm_status batch_tables(lbm_batch *b) {
                 mg.ntot = h->ntot;
                 mg.ttot = h->ttot;
                 mg.nbu = node_update_blocks(h->ntot);
-                mg.epoch0 = (int)(h->step & 0x7fffffff);
                 t.ncap += (int)h->caps.size();
                 t.mem_blocks += membrane_blocks(h->ntot, h->ttot, &mg.nbf);
                 t.upd_blocks += mg.nbu;
-                t.nch_max = std::max(t.nch_max, h->nch);
                 mtab.push_back(membrane_args(h));
                 mgrp.push_back(mg);
             }
@@ -1169,7 +1155,7 @@ static lbm_status batch_tables(lbm_batch *b) {
                   dalloc(&pt.d_desc, desc.size()) == hipSuccess &&
                   dalloc(&pt.d_mtab, mtab.size()) == hipSuccess &&
                   dalloc(&pt.d_mgrp, mgrp.size()) == hipSuccess &&
-                  dalloc(&pt.d_step, 1) == hipSuccess && dalloc(&pt.d_queue, 9) == hipSuccess &&
+                  dalloc(&pt.d_queue, 9) == hipSuccess &&
                   hipEventCreateWithFlags(&pt.done, hipEventDisableTiming) == hipSuccess;
         if (ok && np > 1) {
             ok = hipStreamCreateWithFlags(&pt.st, hipStreamNonBlocking) == hipSuccess;
@@ -1179,8 +1165,7 @@ static lbm_status batch_tables(lbm_batch *b) {
         }
         if (!ok) return bfail(b, LBM_E_NOMEM, "device allocation failed (batch)");
         const int zero[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-        if (hipMemcpy(pt.d_step, zero, sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
-            hipMemcpy(pt.d_queue, zero, sizeof zero, hipMemcpyHostToDevice) != hipSuccess ||
+        if (hipMemcpy(pt.d_queue, zero, sizeof zero, hipMemcpyHostToDevice) != hipSuccess ||
             hipMemcpy(pt.d_tab, tab.data(), tab.size() * sizeof(FluidArgs), hipMemcpyHostToDevice) != hipSuccess ||
             hipMemcpy(pt.d_desc, desc.data(), desc.size() * sizeof(int4), hipMemcpyHostToDevice) != hipSuccess ||
             (pt.nmg && (hipMemcpy(pt.d_mtab, mtab.data(), mtab.size() * sizeof(MembraneArgs), hipMemcpyHostToDevice) != hipSuccess ||
@@ -1274,7 +1259,7 @@ static void part_step(lbm_batch *b, BatchPart &pt) {
     const MGroupTotals &mt = pt.mtot;
     if (pt.nmg) {
         timed(b->prof, st, "capsule_reduce", [&] {
-            launch_capsule_reduce_multi(pt.d_mtab, pt.d_mgrp, pt.nmg, mt, pt.d_step, st);
+            launch_capsule_reduce_multi(pt.d_mtab, pt.d_mgrp, pt.nmg, mt, st);
         });
         timed(b->prof, st, "membrane", [&] { launch_membrane_multi(pt.d_mtab, pt.d_mgrp, pt.nmg, mt, st); });
         timed(b->prof, st, "window_fill", [&] {
@@ -1294,7 +1279,7 @@ static void part_step(lbm_batch *b, BatchPart &pt) {
     });
     if (pt.nmg)
         timed(b->prof, st, "node_update", [&] {
-            launch_node_update_multi(pt.d_mtab, pt.d_mgrp, pt.nmg, mt, pt.d_step, st);
+            launch_node_update_multi(pt.d_mtab, pt.d_mgrp, pt.nmg, mt, st);
         });
 }
 
@@ -1506,13 +1491,12 @@ static lbm_status check_status(lbm_handle *h, int st[ST_WORDS]) {
 }
 
 static bool unstable_flagged(const int *st) {
-    return st[ST_UNSTABLE] || st[ST_OVERFLOW] || st[ST_WIDE] || st[ST_SYNC] || st[ST_SLAB] ||
+    return st[ST_UNSTABLE] || st[ST_OVERFLOW] || st[ST_WIDE] || st[ST_SLAB] ||
            st[ST_BBOVER];
 }
 
 static const char *unstable_message(const int *st) {
     if (st[ST_BBOVER]) return "bounce-back link list or triangle bins overflowed (deformed capsule)";
-    if (st[ST_SYNC]) return "capsule reduction read partial sums of another step";
     if (st[ST_SLAB]) return "capsule window crossed a wall layer of its slab";
     if (st[ST_WIDE]) return "capsule window wider than 2048 lattice columns (x * y)";
     if (st[ST_OVERFLOW]) return "capsule outgrew its window";

@@ -47,11 +47,10 @@ constexpr int ROWS_MAX = GMAX * GMAX;
 constexpr int FILL_COLS = 2048;   // window columns (x * y) the spreading kernel holds in LDS
 
 // status words (device): [0] unstable flag, [1] lost reaction count, [2] window overflow,
-// [3] window wider than the spreading plane buffer, [4] the capsule reduction read
-// partial sums of another step (never expected), [5] a capsule window left the slab of
-// its capsule
-constexpr int ST_UNSTABLE = 0, ST_LOST = 1, ST_OVERFLOW = 2, ST_WIDE = 3, ST_SYNC = 4,
-              ST_SLAB = 5, ST_BBLOST = 6, ST_BBOVER = 7, ST_WORDS = 8;
+// [3] window wider than the spreading plane buffer, [4] unused, [5] a capsule window left
+// the slab of its capsule
+constexpr int ST_UNSTABLE = 0, ST_LOST = 1, ST_OVERFLOW = 2, ST_WIDE = 3, ST_SLAB = 5,
+              ST_BBLOST = 6, ST_BBOVER = 7, ST_WORDS = 8;
 // [6] bounce-back links that found no triangle (count), [7] a bounce-back bin or link
 // list overflowed, or a triangle spans more than BB_SPAN cells per axis
 
@@ -156,15 +155,6 @@ struct CapState {
     int lo[3], dim[3];      // window: sites lo .. lo + dim - 1 (unwrapped)
 };
 
-// Partial sums of one block of the capsule reduction.
-struct CapPartial {
-    double s[3];            // sum of X - X_ref over the block's nodes (X_ref: first node)
-    double vol;             // sum of signed tetrahedron volumes, apex X_ref
-    float mn[3], mx[3];     // bounding box of the FP32-rounded positions
-    int epoch;              // step that wrote it
-    int pad;
-};
-
 struct MembraneArgs {
     const CapDev *caps;
     CapState *cst;
@@ -188,9 +178,6 @@ struct MembraneArgs {
     int *rowstart;          // [ncap][ROWS_MAX + 1] node rows of each window
     double4 *xrow;          // [Ntot] node positions grouped by row (any order in a row)
     int *slot;              // [Ntot] place of node n in the row order (global index)
-    CapPartial *part;       // [ncap][nch] partial sums of the capsule reduction
-    int nch;                // reduction blocks per capsule
-    int epoch;              // step index (low 32 bits)
     float4 *wbuf;           // [ncap][GMAX3] own spread force and coverage per window site
     uint8_t *wpar;          // [ncap][GMAX3] own crossing parity per window site
     uint8_t *flag;
@@ -282,28 +269,25 @@ void launch_meniscus(const float *rho, const uint8_t *flag, float *out, int nx, 
 
 // Capsule kernels of several simulations in one launch each (see membrane.hip): per
 // group (simulation with capsules) its first capsule, membrane block and node-update
-// block in the launches, node and triangle counts, force-block count, node-update block
-// count and the step stamp of its reductions when the tables were written.
+// block in the launches, node and triangle counts, force-block count and node-update
+// block count.
 struct MGroup {
-    int cap0, mem0, upd0, ntot, ttot, nbf, nbu, epoch0;
+    int cap0, mem0, upd0, ntot, ttot, nbf, nbu;
 };
 struct MGroupTotals {
-    int ncap, nch_max, mem_blocks, upd_blocks;
+    int ncap, mem_blocks, upd_blocks;
 };
 int membrane_blocks(int ntot, int ttot, int *nb_forces);
 int node_update_blocks(int ntot);
-// *d_de: steps since the tables were written (added to each group's epoch0), kept on the
-// device and advanced by launch_node_update_multi, so a captured step graph replays as is
 void launch_capsule_reduce_multi(const MembraneArgs *tab, const MGroup *grp, int ng,
-                                 const MGroupTotals &t, const int *d_de, hipStream_t st);
+                                 const MGroupTotals &t, hipStream_t st);
 void launch_membrane_multi(const MembraneArgs *tab, const MGroup *grp, int ng,
                            const MGroupTotals &t, hipStream_t st);
 void launch_window_fill_multi(const MembraneArgs *tab, const MGroup *grp, int ng,
                               const MGroupTotals &t, hipStream_t st);
 void launch_node_update_multi(const MembraneArgs *tab, const MGroup *grp, int ng,
-                              const MGroupTotals &t, int *d_step, hipStream_t st);
+                              const MGroupTotals &t, hipStream_t st);
 
-int reduce_chunks(int max_work);
 void launch_capsule_reduce(const MembraneArgs &m, hipStream_t st);
 void launch_membrane(const MembraneArgs &m, int ntot, int ttot, hipStream_t st);
 void launch_window_fill(const MembraneArgs &m, hipStream_t st);

@@ -97,60 +97,63 @@ __device__ __forceinline__ int wrap_near(int a, int n) {
 }
 
 // ------------------------------------------------------------------------------------
-// Capsule reduction, in two kernels.  Partials, grid (nch, ncap): each block first clears
-// its share of the flags and crossing masks of capsule k's previous window, then reduces
-// its share of the nodes (sum of X - X_ref, FP32 bounding box) and triangles (signed
-// tetrahedron volumes with apex X_ref, the first node; the volume of a closed mesh does
-// not depend on the apex) into a partial record.  Window, one block per capsule: sums the
-// records in block order, so the result does not depend on scheduling, then derives the
-// centroid, volume (only for capsules with a volume penalty; else 0), bounding box and
-// site window, and bins the nodes by the (y, z) lattice row of floor(X) inside the
-// window: positions in row order (any order inside a row), and each node's place in that
-// order.  (Counting finished blocks instead, and letting the last one go on, needs a
-// device-scope release fence in every block, which writes back the L2 of its XCD: for
-// many capsules that cost more than the second launch.)
+// Capsule reduction, one block per capsule: first clear the flags and crossing masks of
+// capsule k's previous window, then reduce the nodes (sum of X - X_ref, FP32 bounding box)
+// and, for capsules with a volume penalty, the triangles (signed tetrahedron volumes with
+// apex X_ref, the first node; the volume of a closed mesh does not depend on the apex),
+// each thread a strided share, then the waves in a fixed order, so the result does not
+// depend on scheduling.  From the totals: centroid, volume, bounding box and site window;
+// then the nodes are binned by the (y, z) lattice row of floor(X) inside the window:
+// positions in row order (any order inside a row), and each node's place in that order.
+// (A capsule has at most LBM_MAX_CAPSULE_NODES nodes, 16 per thread.  Earlier forms
+// spread the sums over several blocks per capsule, with a second launch or a last-block
+// counter to combine them; one block is one launch and no partial records.)
 // ------------------------------------------------------------------------------------
-constexpr int RED_BLK = 256, RED_W = RED_BLK / 64;
+constexpr int RED_BLK = 512, RED_W = RED_BLK / 64, RED_GRP = 8;
 
-int reduce_chunks(int max_work) {
-    const int c = (max_work + RED_BLK - 1) / RED_BLK;
-    return c < 1 ? 1 : (c > RED_BLK ? RED_BLK : c);
-}
-
-// block c of capsule k
-__device__ __forceinline__ void capsule_partial_body(const MembraneArgs &m, int k, int c) {
-    const int nch = m.nch;
+__device__ __forceinline__ void capsule_reduce_body(const MembraneArgs &m, int k) {
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    const int gstride = nch * RED_BLK, g0 = c * RED_BLK + tid;
     const CapDev cd = m.caps[k];
     {
-        // flags and crossing masks of the previous window (rewritten by the window kernel,
-        // which runs after this one)
+        // flags and crossing masks of the previous window (the window kernels of this step
+        // write the new ones)
         const CapState old = m.cst[k];
-        const int dx = old.dim[0], dy = old.dim[1], pv = dx * dy * old.dim[2];
-        for (int i = g0; i < pv; i += gstride) {
-            const int lx = i % dx, t = i / dx, ly = t % dy, lz = t / dy;
-            const int x = wrapm(old.lo[0] + lx, m.nx), y = wrapm(old.lo[1] + ly, m.ny),
-                      z = wrapm(old.lo[2] + lz, m.nz);
-            m.flag[(z * m.ny + y) * m.nx + x] = 0;
+        const int dx = old.dim[0], dy = old.dim[1], dz = old.dim[2];
+        // a wave per (y, z) row of the window, a lane per x (dx <= GMAX = 64)
+        static_assert(GMAX <= 64, "a window row fits one wave");
+        const int x = wrapm(old.lo[0] + lane, m.nx);
+        for (int lz = 0; lz < dz; ++lz) {
+            const int z = wrapm(old.lo[2] + lz, m.nz);
+            for (int ly = wid; ly < dy; ly += RED_W) {
+                const int y = wrapm(old.lo[1] + ly, m.ny);
+                if (lane < dx) m.flag[(z * m.ny + y) * m.nx + x] = 0;
+            }
         }
-        for (int i = g0; i < dx * dy; i += gstride) m.marks[(size_t)k * ROWS_MAX + i] = 0ull;
+        for (int i = tid; i < dx * dy; i += RED_BLK) m.marks[(size_t)k * ROWS_MAX + i] = 0ull;
     }
     const double4 Xr = m.X[cd.node0];
     double s[3] = {0.0, 0.0, 0.0}, vol = 0.0;
     float mn[3] = {3e38f, 3e38f, 3e38f}, mx[3] = {-3e38f, -3e38f, -3e38f};
-    for (int n = g0; n < cd.nn; n += gstride) {
-        const double4 X = m.X[cd.node0 + n];
-        const double p[3] = {X.x, X.y, X.z}, r[3] = {Xr.x, Xr.y, Xr.z};
+    // RED_GRP nodes per thread with every (clamped) load in flight at once
+    for (int n0 = 0; n0 < cd.nn; n0 += RED_GRP * RED_BLK) {   // uniform over the block
+        double4 Xg[RED_GRP];
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            s[d] += p[d] - r[d];
-            mn[d] = fminf(mn[d], (float)p[d]);
-            mx[d] = fmaxf(mx[d], (float)p[d]);
+        for (int i = 0; i < RED_GRP; ++i)
+            Xg[i] = m.X[cd.node0 + min(n0 + tid + i * RED_BLK, cd.nn - 1)];
+#pragma unroll
+        for (int i = 0; i < RED_GRP; ++i) {
+            if (n0 + tid + i * RED_BLK >= cd.nn) continue;
+            const double p[3] = {Xg[i].x, Xg[i].y, Xg[i].z}, r[3] = {Xr.x, Xr.y, Xr.z};
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                s[d] += p[d] - r[d];
+                mn[d] = fminf(mn[d], (float)p[d]);
+                mx[d] = fmaxf(mx[d], (float)p[d]);
+            }
         }
     }
     // the enclosed volume is needed on the device only for the volume penalty
-    for (int t = g0; cd.kv != 0.0f && t < cd.nt; t += gstride) {
+    for (int t = tid; cd.kv != 0.0f && t < cd.nt; t += RED_BLK) {
         const int4 tr = m.tri[cd.tri0 + t];
         const double4 A = m.X[tr.x], B = m.X[tr.y], C = m.X[tr.z];
         const double a[3] = {A.x - Xr.x, A.y - Xr.y, A.z - Xr.z};
@@ -161,6 +164,8 @@ __device__ __forceinline__ void capsule_partial_body(const MembraneArgs &m, int 
     }
     __shared__ double sd[RED_W][4];
     __shared__ float smn[RED_W][3], smx[RED_W][3];
+    __shared__ int s_lo[3], s_dim[3];
+    __shared__ int cnt[ROWS_MAX];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         const double v = wave_sum_d(s[d]);
@@ -171,61 +176,26 @@ __device__ __forceinline__ void capsule_partial_body(const MembraneArgs &m, int 
     if (lane == 0) sd[wid][3] = vol;
     __syncthreads();
     if (tid == 0) {
-        CapPartial P;
+        double tot[4];
+        float bmin[3], bmax[3];
         for (int d = 0; d < 4; ++d) {
             double v = sd[0][d];
             for (int w = 1; w < RED_W; ++w) v += sd[w][d];
-            if (d < 3) P.s[d] = v; else P.vol = v;
+            tot[d] = v;
         }
         for (int d = 0; d < 3; ++d) {
             float a = smn[0][d], b = smx[0][d];
             for (int w = 1; w < RED_W; ++w) { a = fminf(a, smn[w][d]); b = fmaxf(b, smx[w][d]); }
-            P.mn[d] = a;
-            P.mx[d] = b;
+            bmin[d] = a;
+            bmax[d] = b;
         }
-        P.epoch = m.epoch;
-        P.pad = 0;
-        m.part[(size_t)k * nch + c] = P;
-    }
-}
-
-// capsule k: totals in block order, window, node rows
-__device__ __forceinline__ void capsule_window_body(const MembraneArgs &m, int k) {
-    const int nch = m.nch;
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    const CapDev cd = m.caps[k];
-    const double4 Xr = m.X[cd.node0];
-    __shared__ CapPartial s_part[RED_BLK];
-    __shared__ double s_tot[10];
-    __shared__ int s_lo[3], s_dim[3];
-    __shared__ int cnt[ROWS_MAX];
-    for (int i = tid; i < nch; i += RED_BLK) s_part[i] = m.part[(size_t)k * nch + i];
-    __syncthreads();
-    if (tid < 10) {
-        // one component per thread, summed over the records in block order
-        double v = tid < 3 ? 0.0 : (tid == 3 ? 0.0 : (tid < 7 ? 3e38 : -3e38));
-        for (int i = 0; i < nch; ++i) {
-            const CapPartial &P = s_part[i];
-            if (tid < 3) v += P.s[tid];
-            else if (tid == 3) v += P.vol;
-            else if (tid < 7) v = fmin(v, (double)P.mn[tid - 4]);
-            else v = fmax(v, (double)P.mx[tid - 7]);
-        }
-        s_tot[tid] = v;
-    } else if (tid == 10) {
-        bool stale = false;
-        for (int i = 0; i < nch; ++i) stale = stale || s_part[i].epoch != m.epoch;
-        if (stale) atomicOr(&m.status[ST_SYNC], 1);
-    }
-    __syncthreads();
-    if (tid == 0) {
         CapState cs;
         const double r[3] = {Xr.x, Xr.y, Xr.z};
         const int nd[3] = {m.nx, m.ny, m.nz};
-        cs.vol = s_tot[3];
+        cs.vol = tot[3];
         for (int d = 0; d < 3; ++d) {
-            const float a = (float)s_tot[4 + d], b = (float)s_tot[7 + d];
-            cs.cen[d] = r[d] + s_tot[d] / cd.nn;
+            const float a = bmin[d], b = bmax[d];
+            cs.cen[d] = r[d] + tot[d] / cd.nn;
             cs.bmin[d] = a;
             cs.bmax[d] = b;
             int fa = 0, dim = min(GMAX, nd[d]);
@@ -326,17 +296,12 @@ __device__ __forceinline__ void capsule_window_body(const MembraneArgs &m, int k
     }
 }
 
-__global__ void __launch_bounds__(RED_BLK) k_capsule_partial(MembraneArgs m) {
-    capsule_partial_body(m, blockIdx.y, blockIdx.x);
-}
-
-__global__ void __launch_bounds__(RED_BLK) k_capsule_window(MembraneArgs m) {
-    capsule_window_body(m, blockIdx.x);
+__global__ void __launch_bounds__(RED_BLK) k_capsule_reduce(MembraneArgs m) {
+    capsule_reduce_body(m, blockIdx.x);
 }
 
 void launch_capsule_reduce(const MembraneArgs &m, hipStream_t st) {
-    hipLaunchKernelGGL(k_capsule_partial, dim3(m.nch, m.ncap), dim3(RED_BLK), 0, st, m);
-    hipLaunchKernelGGL(k_capsule_window, dim3(m.ncap), dim3(RED_BLK), 0, st, m);
+    hipLaunchKernelGGL(k_capsule_reduce, dim3(m.ncap), dim3(RED_BLK), 0, st, m);
 }
 
 // ------------------------------------------------------------------------------------
@@ -907,16 +872,16 @@ void launch_node_update(const MembraneArgs &m, int ntot, hipStream_t st) {
 typedef __attribute__((address_space(4))) const int ConstIntM;
 
 __device__ __forceinline__ void load_margs(const MembraneArgs *tab, int g, MembraneArgs &m) {
-    static_assert(sizeof(MembraneArgs) % 4 == 0 && sizeof(MGroup) == 32, "word copies");
+    static_assert(sizeof(MembraneArgs) % 4 == 0 && sizeof(MGroup) == 28, "word copies");
     ConstIntM *src = (ConstIntM *)(tab + g);
     int *dst = reinterpret_cast<int *>(&m);
 #pragma unroll
     for (int i = 0; i < (int)(sizeof(MembraneArgs) / 4); ++i) dst[i] = src[i];
 }
 
-// field f of group g (MGroup as 8 ints)
+// field f of group g (MGroup as 7 ints)
 __device__ __forceinline__ int grp_field(const MGroup *grp, int g, int f) {
-    return ((ConstIntM *)grp)[8 * g + f];
+    return ((ConstIntM *)grp)[7 * g + f];
 }
 
 // the last group whose field f (a start index, increasing with g) is <= v
@@ -926,30 +891,14 @@ __device__ __forceinline__ int find_group(const MGroup *grp, int ng, int f, int 
     return g;
 }
 
-enum { MG_CAP0 = 0, MG_MEM0 = 1, MG_UPD0 = 2, MG_NTOT = 3, MG_TTOT = 4, MG_NBF = 5, MG_NBU = 6,
-       MG_EPOCH0 = 7 };
+enum { MG_CAP0 = 0, MG_MEM0 = 1, MG_UPD0 = 2, MG_NTOT = 3, MG_TTOT = 4, MG_NBF = 5, MG_NBU = 6 };
 
-__global__ void __launch_bounds__(RED_BLK) k_capsule_partial_multi(const MembraneArgs *tab,
-                                                                   const MGroup *grp, int ng,
-                                                                   const int *d_de) {
-    const int de = *d_de;
-    const int K = blockIdx.y, g = find_group(grp, ng, MG_CAP0, K);
-    MembraneArgs m;
-    load_margs(tab, g, m);
-    if ((int)blockIdx.x >= m.nch) return;
-    m.epoch = (grp_field(grp, g, MG_EPOCH0) + de) & 0x7fffffff;
-    capsule_partial_body(m, K - grp_field(grp, g, MG_CAP0), blockIdx.x);
-}
-
-__global__ void __launch_bounds__(RED_BLK) k_capsule_window_multi(const MembraneArgs *tab,
-                                                                  const MGroup *grp, int ng,
-                                                                  const int *d_de) {
-    const int de = *d_de;
+__global__ void __launch_bounds__(RED_BLK) k_capsule_reduce_multi(const MembraneArgs *tab,
+                                                                  const MGroup *grp, int ng) {
     const int K = blockIdx.x, g = find_group(grp, ng, MG_CAP0, K);
     MembraneArgs m;
     load_margs(tab, g, m);
-    m.epoch = (grp_field(grp, g, MG_EPOCH0) + de) & 0x7fffffff;
-    capsule_window_body(m, K - grp_field(grp, g, MG_CAP0));
+    capsule_reduce_body(m, K - grp_field(grp, g, MG_CAP0));
 }
 
 __global__ void __launch_bounds__(MEM_BLK) k_membrane_multi(const MembraneArgs *tab,
@@ -978,12 +927,8 @@ __global__ void __launch_bounds__(256) k_window_combine_multi(const MembraneArgs
 }
 
 __global__ void __launch_bounds__(UPD_BLK) k_node_update_multi(const MembraneArgs *tab,
-                                                               const MGroup *grp, int ng,
-                                                               int *d_step) {
+                                                               const MGroup *grp, int ng) {
     const int B = blockIdx.x, g = find_group(grp, ng, MG_UPD0, B);
-    // the step count the next reduction stamps its records with (no kernel of this step
-    // reads it any more)
-    if (B == 0 && threadIdx.x == 0) *d_step += 1;
     MembraneArgs m;
     load_margs(tab, g, m);
     node_update_body(m, B - grp_field(grp, g, MG_UPD0), grp_field(grp, g, MG_NBU),
@@ -991,11 +936,8 @@ __global__ void __launch_bounds__(UPD_BLK) k_node_update_multi(const MembraneArg
 }
 
 void launch_capsule_reduce_multi(const MembraneArgs *tab, const MGroup *grp, int ng,
-                                 const MGroupTotals &t, const int *d_de, hipStream_t st) {
-    hipLaunchKernelGGL(k_capsule_partial_multi, dim3(t.nch_max, t.ncap), dim3(RED_BLK), 0, st,
-                       tab, grp, ng, d_de);
-    hipLaunchKernelGGL(k_capsule_window_multi, dim3(t.ncap), dim3(RED_BLK), 0, st, tab, grp, ng,
-                       d_de);
+                                 const MGroupTotals &t, hipStream_t st) {
+    hipLaunchKernelGGL(k_capsule_reduce_multi, dim3(t.ncap), dim3(RED_BLK), 0, st, tab, grp, ng);
 }
 
 void launch_membrane_multi(const MembraneArgs *tab, const MGroup *grp, int ng,
@@ -1010,9 +952,9 @@ void launch_window_fill_multi(const MembraneArgs *tab, const MGroup *grp, int ng
 }
 
 void launch_node_update_multi(const MembraneArgs *tab, const MGroup *grp, int ng,
-                              const MGroupTotals &t, int *d_step, hipStream_t st) {
+                              const MGroupTotals &t, hipStream_t st) {
     hipLaunchKernelGGL(k_node_update_multi, dim3(t.upd_blocks), dim3(UPD_BLK), 0, st, tab, grp,
-                       ng, d_step);
+                       ng);
 }
 
 }  // namespace lbmx
