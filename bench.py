@@ -450,14 +450,24 @@ def main():
     if args.copy_calib:
         # plain copy kernel of known size: rocprofv3's FETCH_SIZE / WRITE_SIZE of this run
         # give the counter scale (bytes counted per byte moved) used for the traffic figure
+        # the same copies timed with HIP events give the device's practical read + write rate
         import torch
         n = args.copy_calib * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record()
         for _ in range(5):
             dst.copy_(src)
+        t1.record()
         torch.cuda.synchronize()
-        print(json.dumps(dict(copy_bytes_each_way=n * 4, launches=5)), flush=True)
+        ms = t0.elapsed_time(t1) / 5
+        print(json.dumps(dict(copy_bytes_each_way=n * 4, launches=6, ms_per_copy=round(ms, 4),
+                              read_plus_write_gbs=round(2 * n * 4 / (ms * 1e-3) / 1e9, 1))),
+              flush=True)
         return
 
     if args.surrogate:
