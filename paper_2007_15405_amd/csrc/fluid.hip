@@ -287,14 +287,19 @@ __device__ __forceinline__ void collide_store(const FluidArgs &a, const float (&
 // density at x itself plus the wetting offset (+ for component 0, - for component 1).
 // With zero offsets that value is psi at x itself (psi0, psi1), so no exponential is
 // evaluated; the result is the same to the bit.
-// Returns the stencil sums and the reaction G sum_c psi^c (cross-membrane part).
+// Returns the stencil sums and the reaction G sum_c psi^c (cross-membrane part).  Where
+// every membrane-crossing link of a site substitutes the site's own psi (always without
+// wetting offsets), the reaction G sum over those links of w_i e_i (psi0 psi1 + psi1 psi0)
+// is 2 G psi0 psi1 times the stencil of the crossing links' indicator; that form is taken
+// whenever it holds, so a site gets the same bits whether or not other capsules of the run
+// carry offsets.
 __device__ __forceinline__ void sc_general(const FluidArgs &a, const float *cap_drho,
                                            const float (&p0n)[Q - 1], const float (&p1n)[Q - 1],
                                            const int (&nlab)[Q - 1], int lab, float rho0,
                                            float rho1, float psi0, float psi1, float (&S0)[3],
                                            float (&S1)[3], float (&rx)[3]) {
     float e0[Q - 1], e1[Q - 1];
-    bool anycross = false;
+    bool anycross = false, own = true;
     if (a.zero_drho) {
         // zero offsets everywhere: the substituted value is the site's own psi
 #pragma unroll
@@ -315,13 +320,24 @@ __device__ __forceinline__ void sc_general(const FluidArgs &a, const float *cap_
                 e0[q - 1] = psi_of(fmaxf(rho0 + dr, 0.f), a.inv_rho0);
                 e1[q - 1] = psi_of(fmaxf(rho1 - dr, 0.f), a.inv_rho0);
                 anycross = anycross || nl != LABEL_WALL;
+                own = own && (nl == LABEL_WALL || dr == 0.f);
             }
         }
     }
     stencil(e1, a.ws_axis, a.ws_diag, S0[0], S0[1], S0[2]);
     stencil(e0, a.ws_axis, a.ws_diag, S1[0], S1[1], S1[2]);
     rx[0] = rx[1] = rx[2] = 0.f;
-    if (anycross) {
+    if (anycross && own) {
+        float c[Q - 1];
+#pragma unroll
+        for (int q = 1; q < Q; ++q)
+            c[q - 1] = nlab[q - 1] != lab && nlab[q - 1] != LABEL_WALL ? 1.f : 0.f;
+        float K[3];
+        stencil(c, a.ws_axis, a.ws_diag, K[0], K[1], K[2]);
+        const float g2 = 2.0f * a.G * psi0 * psi1;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) rx[d] = g2 * K[d];
+    } else if (anycross) {
         float c1[Q - 1], c0[Q - 1];
 #pragma unroll
         for (int q = 1; q < Q; ++q) {
@@ -848,8 +864,8 @@ __device__ __forceinline__ void pipe_tile(const FluidArgs &a, int L, int zc, int
 
     // publish psi, flags and the busy bit of plane p (slab position pr) from the pulled
     // populations
-    auto publish = [&](int p, int pr, bool solid, int pz, float (&fl)[2][Q], float (&hf)[2][Q],
-                       uint8_t fl_me, uint8_t fl_h, float (&m)[8], float4 &ibv) {
+    auto publish = [&](int p, int pr, bool solid, float (&fl)[2][Q], float (&hf)[2][Q],
+                       uint8_t fl_me, uint8_t fl_h, float (&m)[8], uint8_t &fg_out) {
         const int slot = (p - z0 + 4) & 3;
         if constexpr (LOC) {
             if (!solid) {
@@ -858,9 +874,6 @@ __device__ __forceinline__ void pipe_tile(const FluidArgs &a, int L, int zc, int
                 if (hi >= 0) decode(hf, hxl, hyl, p, wlo, whi);
             }
         }
-        // window sites: fetch the spread force now, two planes before it is used
-        ibv = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (!solid && (fl_me & AUX_BIT)) ibv = a.ibm[(pz * ny + iy) * nx + ix];
         float r0 = 0.f, r1 = 0.f, h0 = 0.f, h1 = 0.f;
         if (!solid && act) {
 #pragma unroll
@@ -883,6 +896,7 @@ __device__ __forceinline__ void pipe_tile(const FluidArgs &a, int L, int zc, int
             for (int i = 0; i < 8; ++i) m[i] = 0.f;
         }
         const uint8_t fg_me = !act ? 0 : (solid ? WALL_FLAG : fl_me);
+        fg_out = fg_me;
         const float ps0 = psi_of(r0, a.inv_rho0), ps1 = psi_of(r1, a.inv_rho0);
         s_psi[slot][0][li] = ps0;
         s_psi[slot][1][li] = ps1;
@@ -932,15 +946,21 @@ __device__ __forceinline__ void pipe_tile(const FluidArgs &a, int L, int zc, int
             }
         }
     };
-    auto load_plane = [&](int p, int pr, float (&m)[8], float4 &ibv) {
+    auto load_plane = [&](int p, int pr, float (&m)[8], uint8_t &fg_out) {
         float fl[2][Q], hf[2][Q];
         uint8_t g_me, g_h;
         issue(p, pr, fl, hf, g_me, g_h);
-        publish(p, pr, a.wall && pr == 0, wrapn(p, nz), fl, hf, g_me, g_h, m, ibv);
+        publish(p, pr, a.wall && pr == 0, fl, hf, g_me, g_h, m, fg_out);
     };
 
     float m0[8], m1[8], m2[8];   // moments of planes p, p+1, p+2
-    float4 ib0, ib1, ib2;        // spread force of this thread's site in planes p, p+1
+    uint8_t fgx, fg0, fg1;       // this thread's flag in planes z0 - 1, z0 and p + 1
+    // the spread force of a window site in a plane, or zeros elsewhere
+    auto ibm_load = [&](int p, uint8_t fg) {
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (fg & AUX_BIT) v = a.ibm[(wrapn(p, nz) * ny + iy) * nx + ix];
+        return v;
+    };
     int rz = slab_pos(z0, lz);   // slab position of plane p
     if constexpr (LOC) {         // the sources of planes z0 - 1 .. z0 + 1
         for (int z = z0 - 2; z <= z0; ++z) {
@@ -949,30 +969,35 @@ __device__ __forceinline__ void pipe_tile(const FluidArgs &a, int L, int zc, int
         }
         __syncthreads();
     }
-    load_plane(z0 - 1, fwd(rz, lz - 1), m2, ib2);
+    load_plane(z0 - 1, fwd(rz, lz - 1), m2, fgx);
     if constexpr (LOC) {
         rho_issue(z0 + 1);
         rho_store(z0 + 1);
         __syncthreads();
     }
-    load_plane(z0, rz, m0, ib0);
+    load_plane(z0, rz, m0, fg0);
     if constexpr (LOC) {
         rho_issue(z0 + 2);
         rho_store(z0 + 2);
         __syncthreads();
     }
-    load_plane(z0 + 1, fwd(rz, 1), m1, ib1);
+    load_plane(z0 + 1, fwd(rz, 1), m1, fg1);
     if constexpr (LOC) {
         rho_issue(z0 + 3);
         rho_store(z0 + 3);
     }
+    float4 ib0 = ibm_load(z0, fg0);   // the spread force of this thread's site in plane p
     __syncthreads();
     for (int p = z0; p < z1; ++p, rz = fwd(rz, 1)) {
+        // the spread force of plane p + 1 is loaded before the pulls of plane p + 2: the
+        // wait for those pulls (publication of p + 2) then covers it, and a window site
+        // costs no wait of its own
+        const float4 ibn = p + 1 < z1 ? ibm_load(p + 1, fg1) : make_float4(0.f, 0.f, 0.f, 0.f);
         // issue the pulls of plane p+2 first; they complete while plane p is collided
         const bool more = p + 2 <= z1;
         float fl[2][Q], hf[2][Q];
         uint8_t g_me = 0, g_h = 0;
-        const int pn = wrapn(p + 2, nz), rn = fwd(rz, 2);
+        const int rn = fwd(rz, 2);
         const bool nsolid = a.wall && rn == 0;
         if (more) issue(p + 2, rn, fl, hf, g_me, g_h);
         // storage 3: the densities of plane p + 4 (sources of plane p + 3), stored after the
@@ -1018,22 +1043,21 @@ __device__ __forceinline__ void pipe_tile(const FluidArgs &a, int L, int zc, int
         // ---- fold plane p+2 into the ring ----
         if (more) {
             float mn[8];
-            float4 ibn;
-            publish(p + 2, rn, nsolid, pn, fl, hf, g_me, g_h, mn, ibn);
+            uint8_t fgn;
+            publish(p + 2, rn, nsolid, fl, hf, g_me, g_h, mn, fgn);
             if (LOC) rho_store(p + 4);
 #pragma unroll
             for (int i = 0; i < 8; ++i) { m0[i] = m1[i]; m1[i] = mn[i]; }
-            ib0 = ib1;
-            ib1 = ibn;
+            fg1 = fgn;
         } else {
 #pragma unroll
             for (int i = 0; i < 8; ++i) m0[i] = m1[i];
-            ib0 = ib1;
         }
+        ib0 = ibn;
         __syncthreads();
     }
     (void)m2;
-    (void)ib2;
+    (void)fgx;
 }
 
 // XCD-aware renumbering: hardware block b runs on XCD b % 8; each XCD gets a contiguous
