@@ -1690,8 +1690,8 @@ extern "C" lbm_status lbm_labels(lbm_handle *h, uint8_t *out) {
 // Checkpoints
 // ------------------------------------------------------------------------------------
 namespace {
-// version 3: slab height in the header
-constexpr int32_t CKPT_VERSION = 3;
+// version 3: slab height in the header; version 4: previous window in the capsule state
+constexpr int32_t CKPT_VERSION = 4;
 struct CkptHeader {
     char magic[8];
     int32_t version, nx, ny, nz, storage, ncap, ntot, lz;

@@ -153,6 +153,7 @@ struct CapState {
     double vol;             // enclosed volume at X^n (capsules with kv != 0; else 0)
     float bmin[3], bmax[3]; // node bounding box (FP32 positions)
     int lo[3], dim[3];      // window: sites lo .. lo + dim - 1 (unwrapped)
+    int plo[3], pdim[3];    // the previous step's window, whose flags the window kernel clears
 };
 
 struct MembraneArgs {

@@ -97,8 +97,9 @@ __device__ __forceinline__ int wrap_near(int a, int n) {
 }
 
 // ------------------------------------------------------------------------------------
-// Capsule reduction, one block per capsule: first clear the flags and crossing masks of
-// capsule k's previous window, then reduce the nodes (sum of X - X_ref, FP32 bounding box)
+// Capsule reduction, one block per capsule: first clear the crossing masks of capsule k's
+// previous window (and keep that window for the window kernel, which clears its flags),
+// then reduce the nodes (sum of X - X_ref, FP32 bounding box)
 // and, for capsules with a volume penalty, the triangles (signed tetrahedron volumes with
 // apex X_ref, the first node; the volume of a closed mesh does not depend on the apex),
 // each thread a strided share, then the waves in a fixed order, so the result does not
@@ -114,23 +115,11 @@ constexpr int RED_BLK = 512, RED_W = RED_BLK / 64, RED_GRP = 8;
 __device__ __forceinline__ void capsule_reduce_body(const MembraneArgs &m, int k) {
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const CapDev cd = m.caps[k];
-    {
-        // flags and crossing masks of the previous window (the window kernels of this step
-        // write the new ones)
-        const CapState old = m.cst[k];
-        const int dx = old.dim[0], dy = old.dim[1], dz = old.dim[2];
-        // a wave per (y, z) row of the window, a lane per x (dx <= GMAX = 64)
-        static_assert(GMAX <= 64, "a window row fits one wave");
-        const int x = wrapm(old.lo[0] + lane, m.nx);
-        for (int lz = 0; lz < dz; ++lz) {
-            const int z = wrapm(old.lo[2] + lz, m.nz);
-            for (int ly = wid; ly < dy; ly += RED_W) {
-                const int y = wrapm(old.lo[1] + ly, m.ny);
-                if (lane < dx) m.flag[(z * m.ny + y) * m.nx + x] = 0;
-            }
-        }
-        for (int i = tid; i < dx * dy; i += RED_BLK) m.marks[(size_t)k * ROWS_MAX + i] = 0ull;
-    }
+    // the previous window: its crossing masks are cleared here (the membrane kernel marks
+    // the new ones); its flags are cleared by the window kernel, spread over its planes
+    const CapState old = m.cst[k];
+    for (int i = tid; i < old.dim[0] * old.dim[1]; i += RED_BLK)
+        m.marks[(size_t)k * ROWS_MAX + i] = 0ull;
     const double4 Xr = m.X[cd.node0];
     double s[3] = {0.0, 0.0, 0.0}, vol = 0.0;
     float mn[3] = {3e38f, 3e38f, 3e38f}, mx[3] = {-3e38f, -3e38f, -3e38f};
@@ -190,6 +179,10 @@ __device__ __forceinline__ void capsule_reduce_body(const MembraneArgs &m, int k
             bmax[d] = b;
         }
         CapState cs;
+        for (int d = 0; d < 3; ++d) {
+            cs.plo[d] = old.lo[d];
+            cs.pdim[d] = old.dim[d];
+        }
         const double r[3] = {Xr.x, Xr.y, Xr.z};
         const int nd[3] = {m.nx, m.ny, m.nz};
         cs.vol = tot[3];
@@ -605,7 +598,8 @@ void launch_membrane(const MembraneArgs &m, int ntot, int ttot, hipStream_t st) 
 // ------------------------------------------------------------------------------------
 // Window fill, in two kernels.
 //
-// k_window_own: one block per (capsule k, plane of its window).  Every node whose kernel
+// k_window_own: one block per (capsule k, plane of its window); the same block first clears
+// the flags of plane lz of capsule k's previous window.  Every node whose kernel
 // support reaches the plane (node planes lz - 2 .. lz + 1, a contiguous run of the row
 // order) adds its 4 x 4 sites of the plane, F_n phi(x - X_n) and phi(x - X_n), into an
 // LDS plane buffer.  The sums are 64-bit fixed point (2^-40 units), so the atomic adds
@@ -631,6 +625,16 @@ __device__ __forceinline__ int gcd_int(int a, int b) {
 __device__ __forceinline__ void window_own_body(const MembraneArgs &m, int k, int lz) {
     const int tid = threadIdx.x;
     const CapState ck = m.cst[k];
+    if (lz < ck.pdim[2]) {
+        // plane lz of the previous step's window: clear its flags (the combine kernel then
+        // writes those of the new windows)
+        const int pdx = ck.pdim[0], ncol = pdx * ck.pdim[1];
+        const int zrow = wrap_near(ck.plo[2] + lz, m.nz) * m.ny;
+        for (int i = tid; i < ncol; i += OWN_BLK) {
+            const int ly = i / pdx, lx = i - ly * pdx;
+            m.flag[(zrow + wrap_near(ck.plo[1] + ly, m.ny)) * m.nx + wrap_near(ck.plo[0] + lx, m.nx)] = 0;
+        }
+    }
     if (lz >= ck.dim[2]) return;
     const int dx = ck.dim[0], dy = ck.dim[1], ncol = dx * dy;
     __shared__ unsigned long long s_acc[4][FILL_COLS];
@@ -796,30 +800,35 @@ void launch_window_fill(const MembraneArgs &m, hipStream_t st) {
 // ------------------------------------------------------------------------------------
 // Node update: U_n = sum_x u(x) phi(x - X_n) (wall sites contribute nothing),
 // R_n = sum_x r(x) phi(x - X_n) / c(x) over covered sites (the fluid step stores r / c),
-// X_n += U_n.  UPD_L = 16 lanes per node, one (y, z) row of 4 sites each; the 16 row sums
-// are combined by a fixed butterfly.
+// X_n += U_n.  UPD_L = 16 lanes per node, one (x, y) column of 4 sites each, x fastest
+// across the lanes, so one load instruction reads 4 contiguous sites of each of 16 rows;
+// the 16 column sums are combined by a fixed butterfly.
 // ------------------------------------------------------------------------------------
 constexpr int UPD_BLK = 256, UPD_L = 16, UPD_NPB = UPD_BLK / UPD_L, UPD_GRID = 1 << 20;
 
 __device__ __forceinline__ void node_update_one(const MembraneArgs &m, int n, int sl) {
     double4 X = m.X[n];
-    const int oy = sl & 3, oz = sl >> 2;
+    const int ox = sl & 3, oy = sl >> 2;
     const int bx = (int)floor(X.x) - 1, by = (int)floor(X.y) - 1, bz = (int)floor(X.z) - 1;
     float U[3] = {0.f, 0.f, 0.f}, Rr[3] = {0.f, 0.f, 0.f};
-    const int z = wrap_near(bz + oz, m.nz);
-    if (!(m.wall && slab_pos(z, m.lz) == 0)) {
-        const float wyz = phi4((float)(X.y - (double)(by + oy))) *
-                          phi4((float)(X.z - (double)(bz + oz)));
-        const int row = (z * m.ny + wrap_near(by + oy, m.ny)) * m.nx;
+    const float wxy = phi4((float)(X.x - (double)(bx + ox))) *
+                      phi4((float)(X.y - (double)(by + oy)));
+    const int col = wrap_near(by + oy, m.ny) * m.nx + wrap_near(bx + ox, m.nx);
+    // planes bz .. bz + 3, with their slab positions stepped alongside (nz is a multiple
+    // of lz, so both wrap together); wall sites contribute nothing
+    int z = wrap_near(bz, m.nz), zr = m.wall ? slab_pos(z, m.lz) : 1;
 #pragma unroll
-        for (int ox = 0; ox < 4; ++ox) {
-            const int s = row + wrap_near(bx + ox, m.nx);
-            const float w = phi4((float)(X.x - (double)(bx + ox))) * wyz;
+    for (int oz = 0; oz < 4; ++oz) {
+        if (!(m.wall && zr == 0)) {
+            const int s = z * m.ny * m.nx + col;
+            const float w = wxy * phi4((float)(X.z - (double)(bz + oz)));
             const float4 u = m.uo[s];
             const float4 r = m.ro[s];   // reaction / coverage, 0 where uncovered
             U[0] += w * u.x; U[1] += w * u.y; U[2] += w * u.z;
             Rr[0] += w * r.x; Rr[1] += w * r.y; Rr[2] += w * r.z;
         }
+        if (++z == m.nz) z = 0;
+        if (++zr == m.lz) zr = 0;
     }
     static_assert(UPD_L == 16, "group sums are over 16 lanes");
 #pragma unroll
