@@ -62,11 +62,18 @@ __device__ __forceinline__ float group_sum16(float v) {
 }
 
 // Fixed-point accumulation (2^-40 units) for sums whose terms arrive in no fixed order.
+// v 2^40 rounded to the nearest integer, ties to even: adding 1.5 * 2^52 in FP64 (one fused
+// multiply-add) leaves that integer in the low bits of the significand, exact for
+// |v| < 2^11; v is clamped to that range.  (The hardware has no FP-to-int64 conversion.)
+__device__ __forceinline__ long long fix_of(double x) {
+    const double t = fma(x, 1099511627776.0, 6755399441055744.0);
+    return __double_as_longlong(t) - 0x4338000000000000ll;
+}
 __device__ __forceinline__ long long to_fix(float v) {
-    return __float2ll_rn(v * 1099511627776.0f);
+    return fix_of((double)fminf(fmaxf(v, -2047.0f), 2047.0f));
 }
 __device__ __forceinline__ long long to_fix_d(double v) {
-    return __double2ll_rn(v * 1099511627776.0);
+    return fix_of(fmin(fmax(v, -2047.0), 2047.0));
 }
 __device__ __forceinline__ float from_fix(long long v) {
     return (float)((double)v * (1.0 / 1099511627776.0));
