@@ -390,19 +390,21 @@ __device__ void label_marks(const MembraneArgs &m, int t) {
         }
 }
 
-// One launch, two kinds of block: the first nb_forces blocks compute node forces, MEM_L
-// lanes per node (incident triangles and the candidates of each partner capsule split
-// over the lanes, summed by a fixed butterfly); the remaining blocks toggle the crossing
-// masks, one thread per triangle.
+// One launch, two kinds of block: the first blocks toggle the crossing masks, one thread
+// per triangle; the remaining blocks compute node forces, MEM_L lanes per node (incident
+// triangles and the candidates of each partner capsule split over the lanes, summed by a
+// fixed butterfly).  The short mask blocks come first, so the long force blocks are not
+// the ones left waiting for room when the launch exceeds the resident blocks.
 constexpr int MEM_BLK = 256, MEM_L = 8, MEM_NPB = MEM_BLK / MEM_L;
 
-__device__ __forceinline__ void membrane_body(const MembraneArgs &m, int blk, int ntot, int ttot,
-                                              int nb_forces) {
-    if (blk >= nb_forces) {
-        const int t = (blk - nb_forces) * MEM_BLK + threadIdx.x;
+__device__ __forceinline__ void membrane_body(const MembraneArgs &m, int blk, int ntot, int ttot) {
+    const int nb_marks = (ttot + MEM_BLK - 1) / MEM_BLK;
+    if (blk < nb_marks) {
+        const int t = blk * MEM_BLK + threadIdx.x;
         if (t < ttot) label_marks(m, t);
         return;
     }
+    blk -= nb_marks;
     __shared__ CapState s_cst[MAX_CAPS];
     __shared__ uint8_t s_nearf[2][MAX_CAPS];
     __shared__ int s_near[2][MAX_CAPS], s_nnear[2];
@@ -592,14 +594,13 @@ __device__ __forceinline__ void membrane_body(const MembraneArgs &m, int blk, in
     }
 }
 
-__global__ void __launch_bounds__(MEM_BLK) k_membrane(MembraneArgs m, int ntot, int ttot,
-                                                      int nb_forces) {
-    membrane_body(m, blockIdx.x, ntot, ttot, nb_forces);
+__global__ void __launch_bounds__(MEM_BLK) k_membrane(MembraneArgs m, int ntot, int ttot) {
+    membrane_body(m, blockIdx.x, ntot, ttot);
 }
 
 void launch_membrane(const MembraneArgs &m, int ntot, int ttot, hipStream_t st) {
     const int nbf = (ntot + MEM_NPB - 1) / MEM_NPB, nbm = (ttot + MEM_BLK - 1) / MEM_BLK;
-    hipLaunchKernelGGL(k_membrane, dim3(nbf + nbm), dim3(MEM_BLK), 0, st, m, ntot, ttot, nbf);
+    hipLaunchKernelGGL(k_membrane, dim3(nbf + nbm), dim3(MEM_BLK), 0, st, m, ntot, ttot);
 }
 
 // ------------------------------------------------------------------------------------
@@ -923,7 +924,7 @@ __global__ void __launch_bounds__(MEM_BLK) k_membrane_multi(const MembraneArgs *
     MembraneArgs m;
     load_margs(tab, g, m);
     membrane_body(m, B - grp_field(grp, g, MG_MEM0), grp_field(grp, g, MG_NTOT),
-                  grp_field(grp, g, MG_TTOT), grp_field(grp, g, MG_NBF));
+                  grp_field(grp, g, MG_TTOT));
 }
 
 __global__ void __launch_bounds__(OWN_BLK) k_window_own_multi(const MembraneArgs *tab,
