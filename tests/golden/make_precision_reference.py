@@ -12,9 +12,15 @@ The oracle is stepped to each checkpoint and its meniscus height field, capsule
 observables and component masses are written to ``<workload>_precision_reference.npz``
 next to this script.
 
+``--precision f32 --until N`` runs the oracle's FP32 build instead, to the checkpoints up
+to N, and writes ``<workload>_precision_oracle_f32.npz``: the same quantities from an
+independent FP32 computation, which bound how far FP32 arithmetic alone moves them from
+the FP64 reference.
+
 Only the oracle and the seeded input generators are used.  Run from the repository root:
 
     python tests/golden/make_precision_reference.py [--workload c2|c3] [--threads N]
+        [--precision f64|f32] [--until STEPS]
 """
 import argparse
 import os
@@ -36,16 +42,20 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--threads", type=int, default=0)
     ap.add_argument("--workload", default="c2", choices=sorted(CHECKPOINTS))
+    ap.add_argument("--precision", default="f64", choices=["f64", "f32"])
+    ap.add_argument("--until", type=int, default=0)
     args = ap.parse_args()
     cfg = synth.workload("c2", ks=0.05) if args.workload == "c2" else synth.workload("c3")
-    out = os.path.join(HERE, f"{args.workload}_precision_reference.npz")
-    o = oracle.Oracle(cfg, "f64", n_threads=args.threads)
+    name = "reference" if args.precision == "f64" else "oracle_f32"
+    out = os.path.join(HERE, f"{args.workload}_precision_{name}.npz")
+    cps = [c for c in CHECKPOINTS[args.workload] if args.until <= 0 or c <= args.until]
+    o = oracle.Oracle(cfg, args.precision, n_threads=args.threads)
     ncap = len(cfg["capsules"])
     mass0 = o.summary()["mass"].copy()
-    rec = dict(checkpoints=np.array(CHECKPOINTS[args.workload]), mass0=mass0)
+    rec = dict(checkpoints=np.array(cps), mass0=mass0)
     done = 0
     t0 = time.time()
-    for cp in CHECKPOINTS[args.workload]:
+    for cp in cps:
         st = o.step(cp - done)
         if st != 0:
             raise SystemExit(f"oracle step failed with status {st}")
