@@ -62,18 +62,16 @@ __device__ __forceinline__ float group_sum16(float v) {
 }
 
 // Fixed-point accumulation (2^-40 units) for sums whose terms arrive in no fixed order.
-// v 2^40 rounded to the nearest integer, ties to even: adding 1.5 * 2^52 in FP64 (one fused
-// multiply-add) leaves that integer in the low bits of the significand, exact for
-// |v| < 2^11; v is clamped to that range.  (The hardware has no FP-to-int64 conversion.)
-__device__ __forceinline__ long long fix_of(double x) {
-    const double t = fma(x, 1099511627776.0, 6755399441055744.0);
-    return __double_as_longlong(t) - 0x4338000000000000ll;
-}
-__device__ __forceinline__ long long to_fix(float v) {
-    return fix_of((double)fminf(fmaxf(v, -2047.0f), 2047.0f));
+// fix_mul(w, s) is w s rounded to the nearest integer, ties to even, for |w s| < 2^51: one
+// FP64 fused multiply-add adds 1.5 * 2^52, which leaves that integer in the low bits of the
+// significand.  (The hardware has no FP-to-int64 conversion.)  Values are clamped to
+// |v| < 2^11 before they are scaled by 2^40.
+constexpr double FIX_ONE = 1099511627776.0;   // 2^40
+__device__ __forceinline__ long long fix_mul(double w, double s) {
+    return __double_as_longlong(fma(w, s, 6755399441055744.0)) - 0x4338000000000000ll;
 }
 __device__ __forceinline__ long long to_fix_d(double v) {
-    return fix_of(fmin(fmax(v, -2047.0), 2047.0));
+    return fix_mul(fmin(fmax(v, -2047.0), 2047.0), FIX_ONE);
 }
 __device__ __forceinline__ float from_fix(long long v) {
     return (float)((double)v * (1.0 / 1099511627776.0));
@@ -685,6 +683,11 @@ __device__ __forceinline__ void window_own_body(const MembraneArgs &m, int k, in
             const float wz = phi4((float)(X[u].z - zs));
             const float rx = (float)(X[u].x - fx), ry = (float)(X[u].y - fy);
             const int bx = (int)fx - 1 - ck.lo[0], by = (int)fy - 1 - ck.lo[1];
+            // the force in fixed-point units, once per node (clamped so that its product with
+            // a kernel weight, at most 1, stays below 2^51 units)
+            const double fs[3] = {(double)fminf(fmaxf(F[u].x, -2047.f), 2047.f) * FIX_ONE,
+                                  (double)fminf(fmaxf(F[u].y, -2047.f), 2047.f) * FIX_ONE,
+                                  (double)fminf(fmaxf(F[u].z, -2047.f), 2047.f) * FIX_ONE};
             float wx[4];
 #pragma unroll
             for (int o = 0; o < 4; ++o) wx[o] = phi4(rx + (float)(1 - o));
@@ -697,12 +700,12 @@ __device__ __forceinline__ void window_own_body(const MembraneArgs &m, int k, in
                 for (int ox = 0; ox < 4; ++ox) {
                     const int lx = bx + ox;
                     if (lx < 0 || lx >= dx) continue;
-                    const float wgt = wx[ox] * wyz;
+                    const double wgt = (double)(wx[ox] * wyz);
                     const int col = ly * dx + lx;
-                    atomicAdd(&acc[col], (unsigned long long)to_fix(wgt * F[u].x));
-                    atomicAdd(&acc[stride + col], (unsigned long long)to_fix(wgt * F[u].y));
-                    atomicAdd(&acc[2 * stride + col], (unsigned long long)to_fix(wgt * F[u].z));
-                    atomicAdd(&acc[3 * stride + col], (unsigned long long)to_fix(wgt));
+                    atomicAdd(&acc[col], (unsigned long long)fix_mul(wgt, fs[0]));
+                    atomicAdd(&acc[stride + col], (unsigned long long)fix_mul(wgt, fs[1]));
+                    atomicAdd(&acc[2 * stride + col], (unsigned long long)fix_mul(wgt, fs[2]));
+                    atomicAdd(&acc[3 * stride + col], (unsigned long long)fix_mul(wgt, FIX_ONE));
                 }
             }
         }
