@@ -78,6 +78,11 @@ template <int S> struct Pop {
                                                                  qoff(qg, N), 0);
         return Codec<S>::val(__builtin_bit_cast(T, v));
     }
+    // the stored bits, zero-extended (FP16: pairs of them feed the packed dot products)
+    __device__ static inline uint32_t load_bits(const void *f, int qg, int N, uint32_t site) {
+        static_assert(sizeof(T) == 2, "16-bit storage");
+        return __builtin_amdgcn_raw_buffer_load_b16(res(f, qg, N), site * 2u, qoff(qg, N), 0);
+    }
     // stores are non-temporal: the new state is not read again in this step, and keeping
     // it out of L2 leaves room for the source rows that neighbouring tiles pull again
     static constexpr int STORE_NT = 2;
@@ -149,7 +154,10 @@ __device__ __forceinline__ void pull_issue(const void *f, int N, int x, int y, i
         const int ys = CY[q] == 0 ? y : (CY[q] > 0 ? ym : yp);
         const int zs = CZ[q] == 0 ? z : (CZ[q] > 0 ? zm : zp);
         const uint32_t src = (uint32_t)((zs * ny + ys) * nx + xs);
-        if constexpr (S != 0) {   // stored values; the shifts are applied later
+        if constexpr (S == 1) {   // FP16 bits, summed later by packed dot products
+            fl[0][q] = __uint_as_float(Pop<S>::load_bits(f, q, N, src));
+            fl[1][q] = __uint_as_float(Pop<S>::load_bits(f, Q + q, N, src));
+        } else if constexpr (S != 0) {   // stored values; the shifts are applied later
             fl[0][q] = Pop<S>::load_raw(f, q, N, src);
             fl[1][q] = Pop<S>::load_raw(f, Q + q, N, src);
         } else {
@@ -162,7 +170,10 @@ __device__ __forceinline__ void pull_issue(const void *f, int N, int x, int y, i
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             if ((CZ[q] > 0 && wall_lo) || (CZ[q] < 0 && wall_hi)) {
-                if constexpr (S != 0) {
+                if constexpr (S == 1) {
+                    fl[0][q] = __uint_as_float(Pop<S>::load_bits(f, OPP[q], N, self));
+                    fl[1][q] = __uint_as_float(Pop<S>::load_bits(f, Q + OPP[q], N, self));
+                } else if constexpr (S != 0) {
                     fl[0][q] = Pop<S>::load_raw(f, OPP[q], N, self);
                     fl[1][q] = Pop<S>::load_raw(f, Q + OPP[q], N, self);
                 } else {
@@ -179,6 +190,50 @@ __device__ __forceinline__ void moments(const float (&f)[Q], float &jx, float &j
     jx = ((f[1] - f[2]) + (f[5] - f[6])) + ((f[7] - f[8]) + (f[11] - f[12])) + (f[13] - f[14]);
     jy = ((f[3] - f[4]) + (f[5] - f[6])) + ((f[8] - f[7]) + (f[15] - f[16])) + (f[17] - f[18]);
     jz = ((f[9] - f[10]) + (f[11] - f[12])) + ((f[14] - f[13]) + (f[15] - f[16])) + (f[18] - f[17]);
+}
+
+// FP16 storage: density and momentum of one component from the stored bits of its 19
+// populations (zero-extended FP16 in each float's bits).  Opposite links (q, q + 1) share
+// one register as a half pair, and each sum takes a packed dot product with FP32
+// accumulation: (1, 1) for the density, (1, -1) or (-1, 1) for a momentum component, the
+// same differences of opposite links as moments().  Products of FP16 values with +-1 are
+// exact; only the accumulation rounds.
+typedef _Float16 half2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ half2v half_pair(const float (&f)[Q], int q) {
+    return __builtin_bit_cast(half2v, __float_as_uint(f[q]) | (__float_as_uint(f[q + 1]) << 16));
+}
+__device__ __forceinline__ float half_rest(const float (&f)[Q]) {
+    return (float)__builtin_bit_cast(_Float16, (uint16_t)__float_as_uint(f[0]));
+}
+__device__ __forceinline__ float half_density(const float (&f)[Q]) {
+    const half2v one = {(_Float16)1.0f, (_Float16)1.0f};
+    float r = half_rest(f);
+#pragma unroll
+    for (int q = 1; q < Q; q += 2) r = __builtin_amdgcn_fdot2(half_pair(f, q), one, r, false);
+    return r;
+}
+__device__ __forceinline__ void half_moments(const float (&f)[Q], float &r, float &jx, float &jy,
+                                             float &jz) {
+    const half2v pl = {(_Float16)1.0f, (_Float16)-1.0f}, mi = {(_Float16)-1.0f, (_Float16)1.0f};
+    r = half_density(f);
+    const half2v p1 = half_pair(f, 1), p3 = half_pair(f, 3), p5 = half_pair(f, 5);
+    const half2v p7 = half_pair(f, 7), p9 = half_pair(f, 9), p11 = half_pair(f, 11);
+    const half2v p13 = half_pair(f, 13), p15 = half_pair(f, 15), p17 = half_pair(f, 17);
+    jx = __builtin_amdgcn_fdot2(p1, pl, 0.f, false);
+    jx = __builtin_amdgcn_fdot2(p5, pl, jx, false);
+    jx = __builtin_amdgcn_fdot2(p7, pl, jx, false);
+    jx = __builtin_amdgcn_fdot2(p11, pl, jx, false);
+    jx = __builtin_amdgcn_fdot2(p13, pl, jx, false);
+    jy = __builtin_amdgcn_fdot2(p3, pl, 0.f, false);
+    jy = __builtin_amdgcn_fdot2(p5, pl, jy, false);
+    jy = __builtin_amdgcn_fdot2(p7, mi, jy, false);
+    jy = __builtin_amdgcn_fdot2(p15, pl, jy, false);
+    jy = __builtin_amdgcn_fdot2(p17, pl, jy, false);
+    jz = __builtin_amdgcn_fdot2(p9, pl, 0.f, false);
+    jz = __builtin_amdgcn_fdot2(p11, pl, jz, false);
+    jz = __builtin_amdgcn_fdot2(p13, mi, jz, false);
+    jz = __builtin_amdgcn_fdot2(p15, pl, jz, false);
+    jz = __builtin_amdgcn_fdot2(p17, mi, jz, false);
 }
 
 // Stencil sum sum_i w_i psi_i e_i of eq. shanchen from the 18 neighbour values
@@ -876,12 +931,23 @@ __device__ __forceinline__ void pipe_tile(const FluidArgs &a, int L, int zc, int
         }
         float r0 = 0.f, r1 = 0.f, h0 = 0.f, h1 = 0.f;
         if (!solid && act) {
+            if constexpr (S == 1) {
+                half_moments(fl[0], m[0], m[1], m[2], m[3]);
+                half_moments(fl[1], m[4], m[5], m[6], m[7]);
+                r0 = m[0];
+                r1 = m[4];
+                if (hi >= 0) {
+                    h0 = half_density(hf[0]);
+                    h1 = half_density(hf[1]);
+                }
+            } else {
 #pragma unroll
-            for (int q = 0; q < Q; ++q) { r0 += fl[0][q]; r1 += fl[1][q]; }
-            site_moments(fl, m);
-            if (hi >= 0) {
+                for (int q = 0; q < Q; ++q) { r0 += fl[0][q]; r1 += fl[1][q]; }
+                site_moments(fl, m);
+                if (hi >= 0) {
 #pragma unroll
-                for (int q = 0; q < Q; ++q) { h0 += hf[0][q]; h1 += hf[1][q]; }
+                    for (int q = 0; q < Q; ++q) { h0 += hf[0][q]; h1 += hf[1][q]; }
+                }
             }
             if constexpr (CONST_SHIFT) {   // the populations' shifts, once per site
                 r0 += ssum0;
