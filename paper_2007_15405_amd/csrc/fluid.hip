@@ -154,7 +154,7 @@ __device__ __forceinline__ void pull_issue(const void *f, int N, int x, int y, i
         const int ys = CY[q] == 0 ? y : (CY[q] > 0 ? ym : yp);
         const int zs = CZ[q] == 0 ? z : (CZ[q] > 0 ? zm : zp);
         const uint32_t src = (uint32_t)((zs * ny + ys) * nx + xs);
-        if constexpr (S == 1) {   // FP16 bits, summed later by packed dot products
+        if constexpr (S == 1 || S == 2) {   // stored bits, summed later by packed dot products
             fl[0][q] = __uint_as_float(Pop<S>::load_bits(f, q, N, src));
             fl[1][q] = __uint_as_float(Pop<S>::load_bits(f, Q + q, N, src));
         } else if constexpr (S != 0) {   // stored values; the shifts are applied later
@@ -170,7 +170,7 @@ __device__ __forceinline__ void pull_issue(const void *f, int N, int x, int y, i
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             if ((CZ[q] > 0 && wall_lo) || (CZ[q] < 0 && wall_hi)) {
-                if constexpr (S == 1) {
+                if constexpr (S == 1 || S == 2) {
                     fl[0][q] = __uint_as_float(Pop<S>::load_bits(f, OPP[q], N, self));
                     fl[1][q] = __uint_as_float(Pop<S>::load_bits(f, Q + OPP[q], N, self));
                 } else if constexpr (S != 0) {
@@ -192,48 +192,70 @@ __device__ __forceinline__ void moments(const float (&f)[Q], float &jx, float &j
     jz = ((f[9] - f[10]) + (f[11] - f[12])) + ((f[14] - f[13]) + (f[15] - f[16])) + (f[18] - f[17]);
 }
 
-// FP16 storage: density and momentum of one component from the stored bits of its 19
-// populations (zero-extended FP16 in each float's bits).  Opposite links (q, q + 1) share
-// one register as a half pair, and each sum takes a packed dot product with FP32
+// 16-bit storages (FP16, BF16): density and momentum of one component from the stored bits
+// of its 19 populations (zero-extended in each float's bits).  Opposite links (q, q + 1)
+// share one register as a 16-bit pair, and each sum takes a packed dot product with FP32
 // accumulation: (1, 1) for the density, (1, -1) or (-1, 1) for a momentum component, the
-// same differences of opposite links as moments().  Products of FP16 values with +-1 are
+// same differences of opposite links as moments().  Products of stored values with +-1 are
 // exact; only the accumulation rounds.
 typedef _Float16 half2v __attribute__((ext_vector_type(2)));
-__device__ __forceinline__ half2v half_pair(const float (&f)[Q], int q) {
-    return __builtin_bit_cast(half2v, __float_as_uint(f[q]) | (__float_as_uint(f[q + 1]) << 16));
+typedef __bf16 bf162v __attribute__((ext_vector_type(2)));
+template <int S> struct PairDot;
+template <> struct PairDot<1> {
+    using V = half2v;
+    __device__ static inline V vec(float a, float b) { return V{(_Float16)a, (_Float16)b}; }
+    __device__ static inline float dot(V p, V c, float acc) {
+        return __builtin_amdgcn_fdot2(p, c, acc, false);
+    }
+    __device__ static inline float rest(uint32_t bits) {
+        return (float)__builtin_bit_cast(_Float16, (uint16_t)bits);
+    }
+};
+template <> struct PairDot<2> {
+    using V = bf162v;
+    __device__ static inline V vec(float a, float b) { return V{(__bf16)a, (__bf16)b}; }
+    __device__ static inline float dot(V p, V c, float acc) {
+        return __builtin_amdgcn_fdot2_f32_bf16(p, c, acc, false);
+    }
+    __device__ static inline float rest(uint32_t bits) { return __uint_as_float(bits << 16); }
+};
+template <int S> __device__ __forceinline__ typename PairDot<S>::V pair_of(const float (&f)[Q], int q) {
+    return __builtin_bit_cast(typename PairDot<S>::V,
+                              __float_as_uint(f[q]) | (__float_as_uint(f[q + 1]) << 16));
 }
-__device__ __forceinline__ float half_rest(const float (&f)[Q]) {
-    return (float)__builtin_bit_cast(_Float16, (uint16_t)__float_as_uint(f[0]));
-}
-__device__ __forceinline__ float half_density(const float (&f)[Q]) {
-    const half2v one = {(_Float16)1.0f, (_Float16)1.0f};
-    float r = half_rest(f);
+template <int S> __device__ __forceinline__ float pair_density(const float (&f)[Q]) {
+    using D = PairDot<S>;
+    const typename D::V one = D::vec(1.0f, 1.0f);
+    float r = D::rest(__float_as_uint(f[0]));
 #pragma unroll
-    for (int q = 1; q < Q; q += 2) r = __builtin_amdgcn_fdot2(half_pair(f, q), one, r, false);
+    for (int q = 1; q < Q; q += 2) r = D::dot(pair_of<S>(f, q), one, r);
     return r;
 }
-__device__ __forceinline__ void half_moments(const float (&f)[Q], float &r, float &jx, float &jy,
+template <int S>
+__device__ __forceinline__ void pair_moments(const float (&f)[Q], float &r, float &jx, float &jy,
                                              float &jz) {
-    const half2v pl = {(_Float16)1.0f, (_Float16)-1.0f}, mi = {(_Float16)-1.0f, (_Float16)1.0f};
-    r = half_density(f);
-    const half2v p1 = half_pair(f, 1), p3 = half_pair(f, 3), p5 = half_pair(f, 5);
-    const half2v p7 = half_pair(f, 7), p9 = half_pair(f, 9), p11 = half_pair(f, 11);
-    const half2v p13 = half_pair(f, 13), p15 = half_pair(f, 15), p17 = half_pair(f, 17);
-    jx = __builtin_amdgcn_fdot2(p1, pl, 0.f, false);
-    jx = __builtin_amdgcn_fdot2(p5, pl, jx, false);
-    jx = __builtin_amdgcn_fdot2(p7, pl, jx, false);
-    jx = __builtin_amdgcn_fdot2(p11, pl, jx, false);
-    jx = __builtin_amdgcn_fdot2(p13, pl, jx, false);
-    jy = __builtin_amdgcn_fdot2(p3, pl, 0.f, false);
-    jy = __builtin_amdgcn_fdot2(p5, pl, jy, false);
-    jy = __builtin_amdgcn_fdot2(p7, mi, jy, false);
-    jy = __builtin_amdgcn_fdot2(p15, pl, jy, false);
-    jy = __builtin_amdgcn_fdot2(p17, pl, jy, false);
-    jz = __builtin_amdgcn_fdot2(p9, pl, 0.f, false);
-    jz = __builtin_amdgcn_fdot2(p11, pl, jz, false);
-    jz = __builtin_amdgcn_fdot2(p13, mi, jz, false);
-    jz = __builtin_amdgcn_fdot2(p15, pl, jz, false);
-    jz = __builtin_amdgcn_fdot2(p17, mi, jz, false);
+    using D = PairDot<S>;
+    using V = typename D::V;
+    const V pl = D::vec(1.0f, -1.0f), mi = D::vec(-1.0f, 1.0f);
+    r = pair_density<S>(f);
+    const V p1 = pair_of<S>(f, 1), p3 = pair_of<S>(f, 3), p5 = pair_of<S>(f, 5);
+    const V p7 = pair_of<S>(f, 7), p9 = pair_of<S>(f, 9), p11 = pair_of<S>(f, 11);
+    const V p13 = pair_of<S>(f, 13), p15 = pair_of<S>(f, 15), p17 = pair_of<S>(f, 17);
+    jx = D::dot(p1, pl, 0.f);
+    jx = D::dot(p5, pl, jx);
+    jx = D::dot(p7, pl, jx);
+    jx = D::dot(p11, pl, jx);
+    jx = D::dot(p13, pl, jx);
+    jy = D::dot(p3, pl, 0.f);
+    jy = D::dot(p5, pl, jy);
+    jy = D::dot(p7, mi, jy);
+    jy = D::dot(p15, pl, jy);
+    jy = D::dot(p17, pl, jy);
+    jz = D::dot(p9, pl, 0.f);
+    jz = D::dot(p11, pl, jz);
+    jz = D::dot(p13, mi, jz);
+    jz = D::dot(p15, pl, jz);
+    jz = D::dot(p17, mi, jz);
 }
 
 // Stencil sum sum_i w_i psi_i e_i of eq. shanchen from the 18 neighbour values
@@ -931,14 +953,14 @@ __device__ __forceinline__ void pipe_tile(const FluidArgs &a, int L, int zc, int
         }
         float r0 = 0.f, r1 = 0.f, h0 = 0.f, h1 = 0.f;
         if (!solid && act) {
-            if constexpr (S == 1) {
-                half_moments(fl[0], m[0], m[1], m[2], m[3]);
-                half_moments(fl[1], m[4], m[5], m[6], m[7]);
+            if constexpr (S == 1 || S == 2) {
+                pair_moments<S>(fl[0], m[0], m[1], m[2], m[3]);
+                pair_moments<S>(fl[1], m[4], m[5], m[6], m[7]);
                 r0 = m[0];
                 r1 = m[4];
                 if (hi >= 0) {
-                    h0 = half_density(hf[0]);
-                    h1 = half_density(hf[1]);
+                    h0 = pair_density<S>(hf[0]);
+                    h1 = pair_density<S>(hf[1]);
                 }
             } else {
 #pragma unroll
