@@ -394,6 +394,7 @@ __device__ void label_marks(const MembraneArgs &m, int t) {
 // fixed butterfly).  The short mask blocks come first, so the long force blocks are not
 // the ones left waiting for room when the launch exceeds the resident blocks.
 constexpr int MEM_BLK = 256, MEM_L = 8, MEM_NPB = MEM_BLK / MEM_L;
+static_assert(MEM_BLK >= 128, "two waves list the Hertz partners");
 
 __device__ __forceinline__ void membrane_body(const MembraneArgs &m, int blk, int ntot, int ttot) {
     const int nb_marks = (ttot + MEM_BLK - 1) / MEM_BLK;
@@ -404,9 +405,12 @@ __device__ __forceinline__ void membrane_body(const MembraneArgs &m, int blk, in
     }
     blk -= nb_marks;
     __shared__ CapState s_cst[MAX_CAPS];
-    __shared__ uint8_t s_nearf[2][MAX_CAPS];
+    __shared__ int s_zb[MAX_CAPS];
     __shared__ int s_near[2][MAX_CAPS], s_nnear[2];
-    for (int j = threadIdx.x; j < m.ncap; j += MEM_BLK) s_cst[j] = m.cst[j];
+    for (int j = threadIdx.x; j < m.ncap; j += MEM_BLK) {
+        s_cst[j] = m.cst[j];
+        s_zb[j] = m.caps[j].zbase;
+    }
     // the capsules of this block's first and last node (node ranges are contiguous)
     const int nb0 = blk * MEM_NPB, nb1 = min(nb0 + MEM_NPB, ntot) - 1;
     const int kb[2] = {m.node_cap[nb0], m.node_cap[nb1]};
@@ -418,27 +422,32 @@ __device__ __forceinline__ void membrane_body(const MembraneArgs &m, int blk, in
         const bool per[3] = {true, true, !m.wall};
         const int nd[3] = {m.nx, m.ny, m.nz};
         const float d0 = m.hertz_d0, slack = 1e-3f;
-        for (int i = threadIdx.x; i < 2 * m.ncap; i += MEM_BLK) {
-            const int w = i / m.ncap, j = i - w * m.ncap;
-            const CapState &A = s_cst[kb[w]], &B = s_cst[j];
-            bool near = j != kb[w] && m.caps[j].zbase == m.caps[kb[w]].zbase;
-            for (int d = 0; d < 3 && near; ++d) {
-                const float ha = 0.5f * (A.bmax[d] - A.bmin[d]), hb = 0.5f * (B.bmax[d] - B.bmin[d]);
-                float dc = 0.5f * (A.bmin[d] + A.bmax[d]) - 0.5f * (B.bmin[d] + B.bmax[d]);
-                if (per[d]) {
-                    if (2.f * (ha + hb + d0 + 1.f) >= (float)nd[d]) continue;   // box-sized: keep
-                    dc -= nd[d] * floorf(dc / nd[d] + 0.5f);
-                }
-                near = fabsf(dc) - ha - hb <= d0 + slack;
-            }
-            s_nearf[w][j] = near ? 1 : 0;
-        }
-        __syncthreads();
-        if (threadIdx.x < 2) {
+        // wave w (0, 1) lists the partners of capsule kb[w] in ascending order: a lane per
+        // candidate, compacted by ballot
+        const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        if (w < 2) {
             int c = 0;
-            for (int j = 0; j < m.ncap; ++j)
-                if (s_nearf[threadIdx.x][j]) s_near[threadIdx.x][c++] = j;
-            s_nnear[threadIdx.x] = c;
+            for (int j0 = 0; j0 < m.ncap; j0 += 64) {   // uniform over the wave
+                const int j = j0 + lane;
+                bool near = j < m.ncap && j != kb[w] && s_zb[j] == s_zb[kb[w]];
+                if (near) {
+                    const CapState &A = s_cst[kb[w]], &B = s_cst[j];
+                    for (int d = 0; d < 3 && near; ++d) {
+                        const float ha = 0.5f * (A.bmax[d] - A.bmin[d]),
+                                    hb = 0.5f * (B.bmax[d] - B.bmin[d]);
+                        float dc = 0.5f * (A.bmin[d] + A.bmax[d]) - 0.5f * (B.bmin[d] + B.bmax[d]);
+                        if (per[d]) {
+                            if (2.f * (ha + hb + d0 + 1.f) >= (float)nd[d]) continue;   // box-sized: keep
+                            dc -= nd[d] * floorf(dc / nd[d] + 0.5f);
+                        }
+                        near = fabsf(dc) - ha - hb <= d0 + slack;
+                    }
+                }
+                const unsigned long long b = __ballot(near);
+                if (near) s_near[w][c + __popcll(b & ((1ull << lane) - 1ull))] = j;
+                c += __popcll(b);
+            }
+            if (lane == 0) s_nnear[w] = c;
         }
         __syncthreads();
     }
@@ -531,7 +540,7 @@ __device__ __forceinline__ void membrane_body(const MembraneArgs &m, int blk, in
         const int w = k == kb[0] ? 0 : 1, nj = listed ? s_nnear[w] : m.ncap;
         for (int jj = 0; jj < nj; ++jj) {
             const int j = listed ? s_near[w][jj] : jj;
-            if (j == k || (!listed && m.caps[j].zbase != cd.zbase)) continue;
+            if (j == k || (!listed && s_zb[j] != cd.zbase)) continue;
             const CapState &cj = s_cst[j];
             double pl[3];   // this node in the periodic image closest to window j
             bool far = false, small = true;
