@@ -631,13 +631,20 @@ void launch_membrane(const MembraneArgs &m, int ntot, int ttot, hipStream_t st) 
 // ------------------------------------------------------------------------------------
 constexpr int OWN_BLK = 256;
 
+// Columns the spreading kernel's LDS buffer holds (4 x 8 bytes each, dynamic shared memory):
+// 2048 (64 KB, two blocks per CU) for launches of at most OWN_FEW capsules, whose few active
+// blocks then spread over the CUs; 1024 (32 KB, four blocks per CU) for more capsules, where
+// the launch has many times more blocks than the CUs.  Wider windows take passes.
+constexpr int OWN_FEW = 24;
+static int own_cap(int ncap) { return ncap <= OWN_FEW ? 2048 : 1024; }
+
 __device__ __forceinline__ int gcd_int(int a, int b) {
     while (b) { const int t = a % b; a = b; b = t; }
     return a;
 }
 
 // plane lz of capsule k's window
-__device__ __forceinline__ void window_own_body(const MembraneArgs &m, int k, int lz) {
+__device__ __forceinline__ void window_own_body(const MembraneArgs &m, int k, int lz, int cap) {
     const int tid = threadIdx.x;
     const CapState ck = m.cst[k];
     if (lz < ck.pdim[2]) {
@@ -652,15 +659,14 @@ __device__ __forceinline__ void window_own_body(const MembraneArgs &m, int k, in
     }
     if (lz >= ck.dim[2]) return;
     const int dx = ck.dim[0], dy = ck.dim[1], ncol = dx * dy;
-    __shared__ unsigned long long s_acc[4][FILL_COLS];
+    // the LDS buffer holds cap columns; a wider window is spread in passes over column ranges
+    extern __shared__ unsigned long long s_acc[];   // [4][cap]
     if (ncol > FILL_COLS) {   // uniform over the block
         if (tid == 0) atomicOr(&m.status[ST_WIDE], 1);
         return;
     }
-    unsigned long long *acc = &s_acc[0][0];
-    constexpr int stride = FILL_COLS;
-    for (int i = tid; i < ncol; i += OWN_BLK)
-        for (int d = 0; d < 4; ++d) acc[d * stride + i] = 0ull;
+    unsigned long long *acc = s_acc;
+    const int stride = cap;
     // nodes with floor(Z) - lo_z in [lz - 2, lz + 1] reach this plane
     const int r0 = max(lz - 2, 0), r1 = min(lz + 1, ck.dim[2] - 1);
     const int *rs = m.rowstart + (size_t)k * (ROWS_MAX + 1);
@@ -670,65 +676,73 @@ __device__ __forceinline__ void window_own_body(const MembraneArgs &m, int k, in
     int p = nnode / 64 + 1;
     while (nnode > 1 && gcd_int(p, nnode) != 1) ++p;
     const double zs = (double)(ck.lo[2] + lz);
-    __syncthreads();
-    // with bounce-back nothing is spread: the window carries the labels only
-    for (int i0 = 0; i0 < (m.bb ? 0 : nnode); i0 += 2 * OWN_BLK) {
-        // two nodes per thread, both loaded before either is spread
-        double4 X[2];
-        float4 F[2];
-        bool ok[2];
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            const int i = i0 + tid + u * OWN_BLK;
-            ok[u] = i < nnode;
-            const int e = ok[u] ? (int)(((long long)i * p) % nnode) : 0;
-            X[u] = m.xrow[node0 + e];
-            F[u] = m.F[node0 + e];
-        }
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            if (!ok[u]) continue;
-            const double fx = floor(X[u].x), fy = floor(X[u].y);
-            const float wz = phi4((float)(X[u].z - zs));
-            const float rx = (float)(X[u].x - fx), ry = (float)(X[u].y - fy);
-            const int bx = (int)fx - 1 - ck.lo[0], by = (int)fy - 1 - ck.lo[1];
-            // the force in fixed-point units, once per node (clamped so that its product with
-            // a kernel weight, at most 1, stays below 2^51 units)
-            const double fs[3] = {(double)fminf(fmaxf(F[u].x, -2047.f), 2047.f) * FIX_ONE,
-                                  (double)fminf(fmaxf(F[u].y, -2047.f), 2047.f) * FIX_ONE,
-                                  (double)fminf(fmaxf(F[u].z, -2047.f), 2047.f) * FIX_ONE};
-            float wx[4];
-#pragma unroll
-            for (int o = 0; o < 4; ++o) wx[o] = phi4(rx + (float)(1 - o));
-#pragma unroll
-            for (int oy = 0; oy < 4; ++oy) {
-                const int ly = by + oy;
-                if (ly < 0 || ly >= dy) continue;
-                const float wyz = phi4(ry + (float)(1 - oy)) * wz;
-#pragma unroll
-                for (int ox = 0; ox < 4; ++ox) {
-                    const int lx = bx + ox;
-                    if (lx < 0 || lx >= dx) continue;
-                    const double wgt = (double)(wx[ox] * wyz);
-                    const int col = ly * dx + lx;
-                    atomicAdd(&acc[col], (unsigned long long)fix_mul(wgt, fs[0]));
-                    atomicAdd(&acc[stride + col], (unsigned long long)fix_mul(wgt, fs[1]));
-                    atomicAdd(&acc[2 * stride + col], (unsigned long long)fix_mul(wgt, fs[2]));
-                    atomicAdd(&acc[3 * stride + col], (unsigned long long)fix_mul(wgt, FIX_ONE));
-                }
-            }
-        }
-    }
-    __syncthreads();
     float4 *wb = m.wbuf + (size_t)k * GMAX3 + (size_t)lz * ncol;
     uint8_t *wp = m.wpar + (size_t)k * GMAX3 + (size_t)lz * ncol;
     const unsigned long long *mk = m.marks + (size_t)k * ROWS_MAX;
     const unsigned long long below = (2ull << lz) - 1ull;   // planes 0 .. lz (lz <= 63)
-    for (int col = tid; col < ncol; col += OWN_BLK) {
-        wb[col] = make_float4(from_fix((long long)acc[col]), from_fix((long long)acc[stride + col]),
-                              from_fix((long long)acc[2 * stride + col]),
-                              from_fix((long long)acc[3 * stride + col]));
-        wp[col] = (uint8_t)(__popcll(mk[col] & below) & 1);
+    for (int c0 = 0; c0 < ncol; c0 += cap) {   // uniform over the block
+        const int c1 = min(c0 + cap, ncol);
+        for (int i = tid; i < c1 - c0; i += OWN_BLK)
+            for (int d = 0; d < 4; ++d) acc[d * stride + i] = 0ull;
+        __syncthreads();
+        // with bounce-back nothing is spread: the window carries the labels only
+        for (int i0 = 0; i0 < (m.bb ? 0 : nnode); i0 += 2 * OWN_BLK) {
+            // two nodes per thread, both loaded before either is spread
+            double4 X[2];
+            float4 F[2];
+            bool ok[2];
+    #pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int i = i0 + tid + u * OWN_BLK;
+                ok[u] = i < nnode;
+                const int e = ok[u] ? (int)(((long long)i * p) % nnode) : 0;
+                X[u] = m.xrow[node0 + e];
+                F[u] = m.F[node0 + e];
+            }
+    #pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                if (!ok[u]) continue;
+                const double fx = floor(X[u].x), fy = floor(X[u].y);
+                const float wz = phi4((float)(X[u].z - zs));
+                const float rx = (float)(X[u].x - fx), ry = (float)(X[u].y - fy);
+                const int bx = (int)fx - 1 - ck.lo[0], by = (int)fy - 1 - ck.lo[1];
+                // the force in fixed-point units, once per node (clamped so that its product with
+                // a kernel weight, at most 1, stays below 2^51 units)
+                const double fs[3] = {(double)fminf(fmaxf(F[u].x, -2047.f), 2047.f) * FIX_ONE,
+                                      (double)fminf(fmaxf(F[u].y, -2047.f), 2047.f) * FIX_ONE,
+                                      (double)fminf(fmaxf(F[u].z, -2047.f), 2047.f) * FIX_ONE};
+                float wx[4];
+    #pragma unroll
+                for (int o = 0; o < 4; ++o) wx[o] = phi4(rx + (float)(1 - o));
+    #pragma unroll
+                for (int oy = 0; oy < 4; ++oy) {
+                    const int ly = by + oy;
+                    if (ly < 0 || ly >= dy) continue;
+                    const float wyz = phi4(ry + (float)(1 - oy)) * wz;
+    #pragma unroll
+                    for (int ox = 0; ox < 4; ++ox) {
+                        const int lx = bx + ox;
+                        if (lx < 0 || lx >= dx) continue;
+                        const double wgt = (double)(wx[ox] * wyz);
+                        const int col = ly * dx + lx - c0;
+                        if (col < 0 || col >= c1 - c0) continue;
+                        atomicAdd(&acc[col], (unsigned long long)fix_mul(wgt, fs[0]));
+                        atomicAdd(&acc[stride + col], (unsigned long long)fix_mul(wgt, fs[1]));
+                        atomicAdd(&acc[2 * stride + col], (unsigned long long)fix_mul(wgt, fs[2]));
+                        atomicAdd(&acc[3 * stride + col], (unsigned long long)fix_mul(wgt, FIX_ONE));
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        for (int i = tid; i < c1 - c0; i += OWN_BLK) {
+            const int col = c0 + i;
+            wb[col] = make_float4(from_fix((long long)acc[i]), from_fix((long long)acc[stride + i]),
+                                  from_fix((long long)acc[2 * stride + i]),
+                                  from_fix((long long)acc[3 * stride + i]));
+            wp[col] = (uint8_t)(__popcll(mk[col] & below) & 1);
+        }
+        __syncthreads();   // the next pass clears the buffer
     }
 }
 
@@ -804,8 +818,8 @@ __device__ __forceinline__ void window_combine_body(const MembraneArgs &m, int k
     }
 }
 
-__global__ void __launch_bounds__(OWN_BLK) k_window_own(MembraneArgs m) {
-    window_own_body(m, blockIdx.y, blockIdx.x);
+__global__ void __launch_bounds__(OWN_BLK) k_window_own(MembraneArgs m, int cap) {
+    window_own_body(m, blockIdx.y, blockIdx.x, cap);
 }
 
 __global__ void __launch_bounds__(256) k_window_combine(MembraneArgs m) {
@@ -813,7 +827,9 @@ __global__ void __launch_bounds__(256) k_window_combine(MembraneArgs m) {
 }
 
 void launch_window_fill(const MembraneArgs &m, hipStream_t st) {
-    hipLaunchKernelGGL(k_window_own, dim3(GMAX, m.ncap), dim3(256), 0, st, m);
+    const int cap = own_cap(m.ncap);
+    hipLaunchKernelGGL(k_window_own, dim3(GMAX, m.ncap), dim3(OWN_BLK), 4 * cap * sizeof(unsigned long long),
+                       st, m, cap);
     hipLaunchKernelGGL(k_window_combine, dim3(GMAX, m.ncap), dim3(256), 0, st, m);
 }
 
@@ -940,11 +956,11 @@ __global__ void __launch_bounds__(MEM_BLK) k_membrane_multi(const MembraneArgs *
 }
 
 __global__ void __launch_bounds__(OWN_BLK) k_window_own_multi(const MembraneArgs *tab,
-                                                              const MGroup *grp, int ng) {
+                                                              const MGroup *grp, int ng, int cap) {
     const int K = blockIdx.y, g = find_group(grp, ng, MG_CAP0, K);
     MembraneArgs m;
     load_margs(tab, g, m);
-    window_own_body(m, K - grp_field(grp, g, MG_CAP0), blockIdx.x);
+    window_own_body(m, K - grp_field(grp, g, MG_CAP0), blockIdx.x, cap);
 }
 
 __global__ void __launch_bounds__(256) k_window_combine_multi(const MembraneArgs *tab,
@@ -976,7 +992,9 @@ void launch_membrane_multi(const MembraneArgs *tab, const MGroup *grp, int ng,
 
 void launch_window_fill_multi(const MembraneArgs *tab, const MGroup *grp, int ng,
                               const MGroupTotals &t, hipStream_t st) {
-    hipLaunchKernelGGL(k_window_own_multi, dim3(GMAX, t.ncap), dim3(OWN_BLK), 0, st, tab, grp, ng);
+    const int cap = own_cap(t.ncap);
+    hipLaunchKernelGGL(k_window_own_multi, dim3(GMAX, t.ncap), dim3(OWN_BLK),
+                       4 * cap * sizeof(unsigned long long), st, tab, grp, ng, cap);
     hipLaunchKernelGGL(k_window_combine_multi, dim3(GMAX, t.ncap), dim3(256), 0, st, tab, grp, ng);
 }
 

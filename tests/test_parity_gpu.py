@@ -85,6 +85,26 @@ def test_film_with_capsule_1000_steps():
     assert (g.labels() != o.labels()).sum() <= 4
 
 
+def test_wide_window_is_spread_in_column_passes():
+    """With more than 24 capsules the spreading kernel's LDS buffer holds 1024 columns
+    (x * y), and a wider window is spread in two passes over column ranges; it follows the
+    oracle like the narrow windows do (the sums are fixed point, so one pass or two give
+    the same bits).  One capsule of R = 16 (a window of about 37 x 37 columns) in the film,
+    25 capsules of R = 4 above it."""
+    caps = [synth.capsule((31.6, 32.3, 20.2), 16.0, 1280, 0.02)]
+    caps += [synth.capsule((8.3 + 12.0 * i, 8.1 + 12.0 * j, 41.4), 4.0, 320, 0.02)
+             for i in range(5) for j in range(5)]
+    cfg = synth.workload("pf", nx=64, ny=64, nz=48, film_height=12.0, capsules=caps)
+    g, o = run_pair(cfg, 40)
+    rg, ro = g.rho(), o.rho()
+    e = rel_l2(rg, ro)
+    say("wide window rel-L2", e)
+    assert max(e) <= 1e-5
+    site_check(rg, ro, 1e-5, "wide window 40 steps", g.labels())
+    assert np.abs(g.nodes(0) - o.nodes(0)).max() <= 1e-4
+    assert g.summary()["lost_reaction"] == 0 and o.summary()["lost_reaction"] == 0
+
+
 def test_noisy_mixture_with_capsule():
     cfg = synth.workload("c1")
     g = _sim(cfg)
