@@ -115,7 +115,7 @@ __device__ __forceinline__ int wrap_near(int a, int n) {
 // spread the sums over several blocks per capsule, with a second launch or a last-block
 // counter to combine them; one block is one launch and no partial records.)
 // ------------------------------------------------------------------------------------
-constexpr int RED_BLK = 512, RED_W = RED_BLK / 64, RED_GRP = 8;
+constexpr int RED_BLK = 512, RED_W = RED_BLK / 64;
 
 __device__ __forceinline__ void capsule_reduce_body(const MembraneArgs &m, int k) {
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -128,22 +128,24 @@ __device__ __forceinline__ void capsule_reduce_body(const MembraneArgs &m, int k
     const double4 Xr = m.X[cd.node0];
     double s[3] = {0.0, 0.0, 0.0}, vol = 0.0;
     float mn[3] = {3e38f, 3e38f, 3e38f}, mx[3] = {-3e38f, -3e38f, -3e38f};
-    // RED_GRP nodes per thread with every (clamped) load in flight at once
-    for (int n0 = 0; n0 < cd.nn; n0 += RED_GRP * RED_BLK) {   // uniform over the block
-        double4 Xg[RED_GRP];
+    // every node is loaded once, into registers (thread tid holds nodes tid + i RED_BLK),
+    // with all of a thread's (clamped) loads in flight at once; the sums, the row count and
+    // the scatter below all read these registers
+    constexpr int PER = MAX_CAP_NODES / RED_BLK;
+    double4 Xn[PER];
 #pragma unroll
-        for (int i = 0; i < RED_GRP; ++i)
-            Xg[i] = m.X[cd.node0 + min(n0 + tid + i * RED_BLK, cd.nn - 1)];
+    for (int i = 0; i < PER; ++i)
+        Xn[i] = i * RED_BLK < cd.nn ? m.X[cd.node0 + min(tid + i * RED_BLK, cd.nn - 1)]   // uniform
+                                    : make_double4(0.0, 0.0, 0.0, 0.0);
 #pragma unroll
-        for (int i = 0; i < RED_GRP; ++i) {
-            if (n0 + tid + i * RED_BLK >= cd.nn) continue;
-            const double p[3] = {Xg[i].x, Xg[i].y, Xg[i].z}, r[3] = {Xr.x, Xr.y, Xr.z};
+    for (int i = 0; i < PER; ++i) {
+        if (tid + i * RED_BLK >= cd.nn) continue;
+        const double p[3] = {Xn[i].x, Xn[i].y, Xn[i].z}, r[3] = {Xr.x, Xr.y, Xr.z};
 #pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                s[d] += p[d] - r[d];
-                mn[d] = fminf(mn[d], (float)p[d]);
-                mx[d] = fmaxf(mx[d], (float)p[d]);
-            }
+        for (int d = 0; d < 3; ++d) {
+            s[d] += p[d] - r[d];
+            mn[d] = fminf(mn[d], (float)p[d]);
+            mx[d] = fmaxf(mx[d], (float)p[d]);
         }
     }
     // the enclosed volume is needed on the device only for the volume penalty
@@ -224,29 +226,14 @@ __device__ __forceinline__ void capsule_reduce_body(const MembraneArgs &m, int k
     const int rows = dim1 * dim2;
     for (int r = tid; r < rows; r += RED_BLK) cnt[r] = 0;
     __syncthreads();
-    // nodes in groups of GRP per thread; inside a group every (clamped) load is valid, so
-    // all of them can be in flight at once
-    constexpr int PER = MAX_CAP_NODES / RED_BLK, GRP = 8;
     auto row_of = [&](double y, double z) {
         const int ry = min(max((int)floor(y) - lo1, 0), dim1 - 1);
         const int rz = min(max((int)floor(z) - lo2, 0), dim2 - 1);
         return rz * dim1 + ry;
     };
 #pragma unroll
-    for (int g = 0; g < PER / GRP; ++g) {
-        if (g * GRP * RED_BLK < cd.nn) {   // uniform over the block
-            double y[GRP], z[GRP];
-#pragma unroll
-            for (int i = 0; i < GRP; ++i) {
-                const int nc = min(tid + (g * GRP + i) * RED_BLK, cd.nn - 1);
-                y[i] = m.X[cd.node0 + nc].y;
-                z[i] = m.X[cd.node0 + nc].z;
-            }
-#pragma unroll
-            for (int i = 0; i < GRP; ++i)
-                if (tid + (g * GRP + i) * RED_BLK < cd.nn) atomicAdd(&cnt[row_of(y[i], z[i])], 1);
-        }
-    }
+    for (int i = 0; i < PER; ++i)
+        if (tid + i * RED_BLK < cd.nn) atomicAdd(&cnt[row_of(Xn[i].y, Xn[i].z)], 1);
     __syncthreads();
     // exclusive scan: each thread owns a contiguous run of rows
     __shared__ int wsum[RED_W];
@@ -275,21 +262,12 @@ __device__ __forceinline__ void capsule_reduce_body(const MembraneArgs &m, int k
     if (tid == 0) rs[rows] = cd.nn;
     __syncthreads();
 #pragma unroll
-    for (int g = 0; g < PER / GRP; ++g) {
-        if (g * GRP * RED_BLK < cd.nn) {   // uniform over the block
-            double4 Xg[GRP];
-#pragma unroll
-            for (int i = 0; i < GRP; ++i)
-                Xg[i] = m.X[cd.node0 + min(tid + (g * GRP + i) * RED_BLK, cd.nn - 1)];
-#pragma unroll
-            for (int i = 0; i < GRP; ++i) {
-                const int n = tid + (g * GRP + i) * RED_BLK;
-                if (n < cd.nn) {
-                    const int e = cd.node0 + atomicAdd(&cnt[row_of(Xg[i].y, Xg[i].z)], 1);
-                    m.xrow[e] = Xg[i];
-                    m.slot[cd.node0 + n] = e;
-                }
-            }
+    for (int i = 0; i < PER; ++i) {
+        const int n = tid + i * RED_BLK;
+        if (n < cd.nn) {
+            const int e = cd.node0 + atomicAdd(&cnt[row_of(Xn[i].y, Xn[i].z)], 1);
+            m.xrow[e] = Xn[i];
+            m.slot[cd.node0 + n] = e;
         }
     }
 }
