@@ -18,6 +18,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 namespace {
@@ -153,6 +154,239 @@ __global__ void k_adam(float *__restrict__ th, float *__restrict__ m, float *__r
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= np) return;
     const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi, vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    th[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// ------------------------------------------------------------------------------------
+// Training in two launches per Adam step.
+//
+// k_train_chunk: the samples are taken in chunks of 64 rows, chunk c by workgroup
+// c mod TC_BLOCKS (8 waves).  Per chunk: forward through the four layers, the loss
+// gradient and back-propagation, each product on the matrix cores with the operands
+// rounded to bfloat16 as they are read (as k_gemm_bf16 does).  A 64 x 64 product is 16
+// tiles, two per wave.  The weight gradients stay in accumulator registers across a
+// workgroup's chunks: each of their 40 tiles (dW3 16, dW2 16, dW4 4, dW1 4) has one owning
+// wave; the bias gradients are float32 column sums of dL/dz (not rounded, as k_colsum),
+// one column per lane of an owning wave.  The weights (row stride 65 for the 64-wide
+// layers, so that reading W^T does not hit one LDS bank 16 times), the chunk's inputs,
+// targets, weights, activations and dL/dz are in LDS.  Rows of a chunk past the last
+// sample carry zero inputs and zero loss gradient.  Each workgroup writes its gradient,
+// in the parameter layout, to row blockIdx.x of G.
+//
+// k_train_update: per parameter, the rows of G summed in workgroup order, then Adam.
+// Every sum runs in a fixed order, so the result does not depend on scheduling.
+// ------------------------------------------------------------------------------------
+constexpr int TC_THREADS = 512, TC_ROWS = 64, TC_LD = NH + 1, TC_BLOCKS = 128;
+constexpr int TW1 = woff(0), TW2 = woff(1), TW3 = woff(2), TW4 = woff(3);
+constexpr int TB1 = boff(0), TB2 = boff(1), TB3 = boff(2), TB4 = boff(3);
+
+struct TrainArgs {
+    const float *th, *x, *t, *w;
+    float *G;                          // [gridDim.x][NPAR] gradients of the workgroups
+    int n;
+    float inv_wsum;
+};
+
+__global__ void __launch_bounds__(TC_THREADS) k_train_chunk(TrainArgs a) {
+    // parameters: W1 [4][64], W2, W3 [64][65], W4 [64][2], biases
+    __shared__ float sW1[NIN * NH], sW2[NH * TC_LD], sW3[NH * TC_LD], sW4[NH * NOUT];
+    __shared__ float sb1[NH], sb2[NH], sb3[NH], sb4[NOUT];
+    // the chunk's activations (the three tanh layers), dL/dz of two layers, its data
+    __shared__ float sA[3][TC_ROWS * TC_LD], sD[2][TC_ROWS * TC_LD];
+    __shared__ float sDy[TC_ROWS * NOUT], sX[TC_ROWS * NIN], sT[TC_ROWS * NOUT], sWt[TC_ROWS];
+
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int lc = lane & 15, kq = 4 * (lane >> 4);
+    for (int p = tid; p < NPAR; p += TC_THREADS) {
+        const float v = a.th[p];
+        if (p < TB1) sW1[p] = v;
+        else if (p < TW2) sb1[p - TB1] = v;
+        else if (p < TB2) { const int q = p - TW2; sW2[(q / NH) * TC_LD + q % NH] = v; }
+        else if (p < TW3) sb2[p - TB2] = v;
+        else if (p < TB3) { const int q = p - TW3; sW3[(q / NH) * TC_LD + q % NH] = v; }
+        else if (p < TW4) sb3[p - TB3] = v;
+        else if (p < TB4) sW4[p - TW4] = v;
+        else sb4[p - TB4] = v;
+    }
+
+    // one 16 x 16 tile of a product: acc += A B over k < KN (A(i, k), B(k, j) given as
+    // functions returning 0 outside the operands); row i0 + lc of A and column j0 + lc of
+    // B per lane, k = k0 + kq + 0..3
+    auto tile = [&](v4f acc, int i0, int j0, auto kn, auto fa, auto fb) {
+        constexpr int KN = decltype(kn)::value;
+#pragma unroll
+        for (int k0 = 0; k0 < KN; k0 += 16) {
+            v4s av, bv;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {   // hardware conversion, nearest even
+                const int k = k0 + kq + j;
+                av[j] = __builtin_bit_cast(short, (__bf16)fa(i0 + lc, k));
+                bv[j] = __builtin_bit_cast(short, (__bf16)fb(k, j0 + lc));
+            }
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
+        }
+        return acc;
+    };
+    using K16 = std::integral_constant<int, 16>;
+    using K64 = std::integral_constant<int, 64>;
+    const v4f zero = {0.f, 0.f, 0.f, 0.f};
+    // this wave's two tiles of a 64 x 64 product: tiles wave and wave + 8
+    const int ti[2] = {16 * (wave >> 2), 16 * ((wave + 8) >> 2)}, tj = 16 * (wave & 3);
+
+    v4f gW3[2] = {zero, zero}, gW2[2] = {zero, zero};   // owned weight-gradient tiles
+    v4f gW4 = zero, gW1 = zero;   // waves 0..3: dW4 row tile; waves 4..7: dW1 column tile
+    float gB = 0.f;               // waves 4..7: a column of db4, db3, db2, db1
+    // column `lane` of the chunk's rows of D (row stride ld), summed in row order
+    auto colsum = [&](const float *D, int ld) {
+        float acc = 0.f;
+#pragma unroll 8
+        for (int r = 0; r < TC_ROWS; ++r) acc += D[r * ld + lane];
+        gB += acc;
+    };
+    for (int r0 = blockIdx.x * TC_ROWS; r0 < a.n; r0 += gridDim.x * TC_ROWS) {   // uniform
+        const int nr = min(TC_ROWS, a.n - r0);
+        __syncthreads();   // the previous chunk is done with the data and activations
+        for (int e = tid; e < TC_ROWS * NIN; e += TC_THREADS)
+            sX[e] = e < nr * NIN ? a.x[r0 * NIN + e] : 0.f;
+        for (int e = tid; e < TC_ROWS * NOUT; e += TC_THREADS)
+            sT[e] = e < nr * NOUT ? a.t[r0 * NOUT + e] : 0.f;
+        for (int e = tid; e < TC_ROWS; e += TC_THREADS) sWt[e] = e < nr ? a.w[r0 + e] : 0.f;
+        __syncthreads();
+        // ---- forward: a1 = tanh(x W1 + b1), a2, a3, then the output layer ----
+        {
+            v4f c[2];
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+                c[u] = tile(zero, ti[u], tj, K16{}, [&](int i, int k) { return k < NIN ? sX[i * NIN + k] : 0.f; },
+                            [&](int k, int j) { return k < NIN ? sW1[k * NH + j] : 0.f; });
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    sA[0][(ti[u] + kq + e) * TC_LD + tj + lc] = tanhf(c[u][e] + sb1[tj + lc]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int l = 1; l < 3; ++l) {
+            const float *Ap = sA[l - 1], *W = l == 1 ? sW2 : sW3, *b = l == 1 ? sb2 : sb3;
+            v4f c[2];
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+                c[u] = tile(zero, ti[u], tj, K64{}, [&](int i, int k) { return Ap[i * TC_LD + k]; },
+                            [&](int k, int j) { return W[k * TC_LD + j]; });
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    sA[l][(ti[u] + kq + e) * TC_LD + tj + lc] = tanhf(c[u][e] + b[tj + lc]);
+            __syncthreads();
+        }
+        if (wave < 4) {   // y = a3 W4 + b4, then dL/dy = w (y - t) / sum w (0 past n)
+            v4f c = tile(zero, 16 * wave, 0, K64{}, [&](int i, int k) { return sA[2][i * TC_LD + k]; },
+                         [&](int k, int j) { return j < NOUT ? sW4[k * NOUT + j] : 0.f; });
+            if (lc < NOUT) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int i = 16 * wave + kq + e;
+                    const float y = c[e] + sb4[lc];
+                    sDy[i * NOUT + lc] = i < nr ? sWt[i] * (y - sT[i * NOUT + lc]) * a.inv_wsum : 0.f;
+                }
+            }
+        }
+        __syncthreads();
+        // ---- back-propagation ----
+        // d3 = (dy W4^T) (1 - a3^2); dW4 += a3^T dy (waves 0..3); db4 (wave 4)
+        {
+            v4f c[2];
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+                c[u] = tile(zero, ti[u], tj, K16{}, [&](int i, int k) { return k < NOUT ? sDy[i * NOUT + k] : 0.f; },
+                            [&](int k, int j) { return k < NOUT ? sW4[j * NOUT + k] : 0.f; });
+            if (wave < 4)
+                gW4 = tile(gW4, 16 * wave, 0, K64{}, [&](int i, int k) { return sA[2][k * TC_LD + i]; },
+                           [&](int k, int j) { return j < NOUT ? sDy[k * NOUT + j] : 0.f; });
+            else if (wave == 4 && lane < NOUT)
+                colsum(sDy, NOUT);
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int o = (ti[u] + kq + e) * TC_LD + tj + lc;
+                    const float p = sA[2][o];
+                    sD[0][o] = c[u][e] * (1.0f - p * p);
+                }
+        }
+        __syncthreads();
+        // d2 = (d3 W3^T) (1 - a2^2); dW3 += a2^T d3; db3 (wave 5)
+        // d1 = (d2 W2^T) (1 - a1^2); dW2 += a1^T d2; db2 (wave 6)
+#pragma unroll
+        for (int l = 2; l >= 1; --l) {
+            const float *Dn = sD[(2 - l) & 1], *Ap = sA[l - 1], *W = l == 2 ? sW3 : sW2;
+            float *Dp = sD[(3 - l) & 1];
+            v4f (&gW)[2] = l == 2 ? gW3 : gW2;
+            v4f c[2];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                c[u] = tile(zero, ti[u], tj, K64{}, [&](int i, int k) { return Dn[i * TC_LD + k]; },
+                            [&](int k, int j) { return W[j * TC_LD + k]; });
+                gW[u] = tile(gW[u], ti[u], tj, K64{}, [&](int i, int k) { return Ap[k * TC_LD + i]; },
+                             [&](int k, int j) { return Dn[k * TC_LD + j]; });
+            }
+            if (wave == (l == 2 ? 5 : 6)) colsum(Dn, TC_LD);
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int o = (ti[u] + kq + e) * TC_LD + tj + lc;
+                    const float p = Ap[o];
+                    Dp[o] = c[u][e] * (1.0f - p * p);
+                }
+            __syncthreads();
+        }
+        // dW1 += x^T d1 (waves 4..7); db1 (wave 7)
+        if (wave >= 4) {
+            const float *D1 = sD[0];
+            gW1 = tile(gW1, 0, 16 * (wave - 4), K64{}, [&](int i, int k) { return i < NIN ? sX[k * NIN + i] : 0.f; },
+                       [&](int k, int j) { return D1[k * TC_LD + j]; });
+            if (wave == 7) colsum(D1, TC_LD);
+        }
+    }
+    // ---- the workgroup's gradient, in the parameter layout, into its row of G ----
+    float *G = a.G + (size_t)blockIdx.x * NPAR;
+    auto put = [&](const v4f &g, int base, int i0, int j0, int rows, int cols, int ld) {
+        if (j0 + lc >= cols) return;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int i = i0 + kq + e;
+            if (i < rows) G[base + i * ld + j0 + lc] = g[e];
+        }
+    };
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        put(gW3[u], TW3, ti[u], tj, NH, NH, NH);
+        put(gW2[u], TW2, ti[u], tj, NH, NH, NH);
+    }
+    if (wave < 4) {
+        put(gW4, TW4, 16 * wave, 0, NH, NOUT, NOUT);
+    } else {
+        put(gW1, TW1, 0, 16 * (wave - 4), NIN, NH, NH);
+        const int bo[4] = {TB4, TB3, TB2, TB1};
+        if (wave > 4 || lane < NOUT) G[bo[wave - 4] + lane] = gB;
+    }
+}
+
+// per parameter: the workgroups' gradients summed in order, then Adam (bias-corrected
+// moments, step counted from 1)
+__global__ void k_train_update(float *__restrict__ th, float *__restrict__ m, float *__restrict__ v,
+                               const float *__restrict__ G, int nb, float lr, float b1, float b2,
+                               float c1, float c2, float eps) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= NPAR) return;
+    float gi = 0.f;
+    for (int b = 0; b < nb; ++b) gi += G[(size_t)b * NPAR + i];
     const float mi = b1 * m[i] + (1.f - b1) * gi, vi = b2 * v[i] + (1.f - b2) * gi * gi;
     m[i] = mi;
     v[i] = vi;
@@ -373,6 +607,7 @@ struct lbm_surrogate {
     float *th = nullptr, *m = nullptr, *v = nullptr, *g = nullptr;
     float *x = nullptr, *y = nullptr, *tg = nullptr, *w = nullptr, *dy = nullptr, *part = nullptr;
     float *slices = nullptr;             // split-K partial products [KS_MAX][64][64]
+    float *gtrain = nullptr;             // the training workgroups' gradients [TC_BLOCKS][NPAR]
     float *act[NLAYER] = {nullptr, nullptr, nullptr, nullptr};   // input, tanh of 3 layers
     float *d[NLAYER] = {nullptr, nullptr, nullptr, nullptr};     // back-propagated dL/dz
     double wsum = 0.0;
@@ -467,7 +702,8 @@ extern "C" lbm_status lbm_surrogate_create(int32_t max_samples, const float *the
          hipMalloc(&s->dy, c * NOUT * sizeof(float)) == hipSuccess &&
          hipMalloc(&s->w, c * sizeof(float)) == hipSuccess &&
          hipMalloc(&s->part, ((c + 255) / 256) * sizeof(float)) == hipSuccess &&
-         hipMalloc(&s->slices, (size_t)KS_MAX * NH * NH * sizeof(float)) == hipSuccess;
+         hipMalloc(&s->slices, (size_t)KS_MAX * NH * NH * sizeof(float)) == hipSuccess &&
+         hipMalloc(&s->gtrain, (size_t)TC_BLOCKS * NPAR * sizeof(float)) == hipSuccess;
     for (int l = 0; l < NLAYER && ok; ++l)
         ok = hipMalloc(&s->act[l], c * LIN[l] * sizeof(float)) == hipSuccess &&
              hipMalloc(&s->d[l], c * LOUT[l] * sizeof(float)) == hipSuccess;
@@ -532,13 +768,18 @@ extern "C" lbm_status lbm_surrogate_train(lbm_surrogate *s, int32_t steps, float
     if (s->n == 0) return sfail(s, LBM_E_STATE, "no training data");
     if (steps < 0 || !(lr > 0.0f)) return sfail(s, LBM_E_INVAL, "steps >= 0 and lr > 0");
     const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    // one launch computes the gradient (64-sample chunks over up to TC_BLOCKS workgroups),
+    // a second sums the workgroups' gradients and takes the Adam step
+    const int chunks = (s->n + TC_ROWS - 1) / TC_ROWS;
+    const int nb = chunks < TC_BLOCKS ? chunks : TC_BLOCKS;
+    TrainArgs ta{s->th, s->x, s->tg, s->w, s->gtrain, s->n, (float)(1.0 / s->wsum)};
     for (int i = 0; i < steps; ++i) {
-        backward(s);
+        hipLaunchKernelGGL(k_train_chunk, dim3(nb), dim3(TC_THREADS), 0, s->st, ta);
         ++s->t;
         const float c1 = (float)(1.0 - std::pow(0.9, (double)s->t));
         const float c2 = (float)(1.0 - std::pow(0.999, (double)s->t));
-        hipLaunchKernelGGL(k_adam, dim3((NPAR + 255) / 256), dim3(256), 0, s->st, s->th, s->m, s->v,
-                           s->g, NPAR, lr, b1, b2, c1, c2, eps);
+        hipLaunchKernelGGL(k_train_update, dim3((NPAR + 255) / 256), dim3(256), 0, s->st, s->th,
+                           s->m, s->v, s->gtrain, nb, lr, b1, b2, c1, c2, eps);
     }
     if (hipStreamSynchronize(s->st) != hipSuccess || hipGetLastError() != hipSuccess)
         return sfail(s, LBM_E_DEVICE, "training launch failed");
@@ -716,7 +957,8 @@ extern "C" const char *lbm_surrogate_last_error(const lbm_surrogate *s) {
 extern "C" void lbm_surrogate_destroy(lbm_surrogate *s) {
     if (!s) return;
     if (s->st) (void)hipStreamSynchronize(s->st);
-    float *bufs[] = {s->th, s->m, s->v, s->g, s->y, s->tg, s->dy, s->w, s->part, s->slices};
+    float *bufs[] = {s->th, s->m, s->v, s->g, s->y, s->tg, s->dy, s->w, s->part, s->slices,
+                     s->gtrain};
     for (float *b : bufs)
         if (b) (void)hipFree(b);
     for (int l = 0; l < NLAYER; ++l) {
