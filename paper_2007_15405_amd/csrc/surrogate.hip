@@ -163,11 +163,12 @@ __global__ void k_adam(float *__restrict__ th, float *__restrict__ m, float *__r
 // ------------------------------------------------------------------------------------
 // Training in two launches per Adam step.
 //
-// k_train_chunk: the samples are taken in chunks of 64 rows, chunk c by workgroup
-// c mod TC_BLOCKS (8 waves).  Per chunk: forward through the four layers, the loss
-// gradient and back-propagation, each product on the matrix cores with the operands
-// rounded to bfloat16 as they are read (as k_gemm_bf16 does).  A 64 x 64 product is 16
-// tiles, two per wave.  The weight gradients stay in accumulator registers across a
+// k_train_chunk: the samples are taken in chunks of TC_ROWS = 32 rows, chunk c by
+// workgroup c mod TC_BLOCKS (8 waves).  Per chunk: forward through the four layers, the
+// loss gradient and back-propagation, each product on the matrix cores with the operands
+// rounded to bfloat16 as they are read (as k_gemm_bf16 does).  A chunk's 32 x 64 product
+// is 8 tiles, one per wave (row tile tr); a 64 x 64 weight gradient is 16 tiles, two per
+// wave (ti, tj).  The weight gradients stay in accumulator registers across a
 // workgroup's chunks: each of their 40 tiles (dW3 16, dW2 16, dW4 4, dW1 4) has one owning
 // wave; the bias gradients are float32 column sums of dL/dz (not rounded, as k_colsum),
 // one column per lane of an owning wave.  The weights (row stride 65 for the 64-wide
@@ -179,7 +180,8 @@ __global__ void k_adam(float *__restrict__ th, float *__restrict__ m, float *__r
 // k_train_update: per parameter, the rows of G summed in workgroup order, then Adam.
 // Every sum runs in a fixed order, so the result does not depend on scheduling.
 // ------------------------------------------------------------------------------------
-constexpr int TC_THREADS = 512, TC_ROWS = 64, TC_LD = NH + 1, TC_BLOCKS = 128;
+constexpr int TC_THREADS = 512, TC_ROWS = 32, TC_LD = NH + 1, TC_BLOCKS = 128;
+static_assert(TC_ROWS == 32, "one 16 x 16 tile of a chunk product per wave");
 constexpr int TW1 = woff(0), TW2 = woff(1), TW3 = woff(2), TW4 = woff(3);
 constexpr int TB1 = boff(0), TB2 = boff(1), TB3 = boff(2), TB4 = boff(3);
 
@@ -231,10 +233,13 @@ __global__ void __launch_bounds__(TC_THREADS) k_train_chunk(TrainArgs a) {
         return acc;
     };
     using K16 = std::integral_constant<int, 16>;
+    using KR = std::integral_constant<int, TC_ROWS>;
     using K64 = std::integral_constant<int, 64>;
     const v4f zero = {0.f, 0.f, 0.f, 0.f};
-    // this wave's two tiles of a 64 x 64 product: tiles wave and wave + 8
-    const int ti[2] = {16 * (wave >> 2), 16 * ((wave + 8) >> 2)}, tj = 16 * (wave & 3);
+    // this wave's tile of a chunk product (rows tr, columns tj) and its two tiles of a
+    // 64 x 64 weight gradient: tiles wave and wave + 8
+    const int tr = 16 * (wave >> 2), tj = 16 * (wave & 3);
+    const int ti[2] = {16 * (wave >> 2), 16 * ((wave + 8) >> 2)};
 
     v4f gW3[2] = {zero, zero}, gW2[2] = {zero, zero};   // owned weight-gradient tiles
     v4f gW4 = zero, gW1 = zero;   // waves 0..3: dW4 row tile; waves 4..7: dW1 column tile
@@ -257,34 +262,24 @@ __global__ void __launch_bounds__(TC_THREADS) k_train_chunk(TrainArgs a) {
         __syncthreads();
         // ---- forward: a1 = tanh(x W1 + b1), a2, a3, then the output layer ----
         {
-            v4f c[2];
+            const v4f c = tile(zero, tr, tj, K16{}, [&](int i, int k) { return k < NIN ? sX[i * NIN + k] : 0.f; },
+                               [&](int k, int j) { return k < NIN ? sW1[k * NH + j] : 0.f; });
 #pragma unroll
-            for (int u = 0; u < 2; ++u)
-                c[u] = tile(zero, ti[u], tj, K16{}, [&](int i, int k) { return k < NIN ? sX[i * NIN + k] : 0.f; },
-                            [&](int k, int j) { return k < NIN ? sW1[k * NH + j] : 0.f; });
-#pragma unroll
-            for (int u = 0; u < 2; ++u)
-#pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    sA[0][(ti[u] + kq + e) * TC_LD + tj + lc] = tanhf(c[u][e] + sb1[tj + lc]);
+            for (int e = 0; e < 4; ++e)
+                sA[0][(tr + kq + e) * TC_LD + tj + lc] = tanhf(c[e] + sb1[tj + lc]);
         }
         __syncthreads();
 #pragma unroll
         for (int l = 1; l < 3; ++l) {
             const float *Ap = sA[l - 1], *W = l == 1 ? sW2 : sW3, *b = l == 1 ? sb2 : sb3;
-            v4f c[2];
+            const v4f c = tile(zero, tr, tj, K64{}, [&](int i, int k) { return Ap[i * TC_LD + k]; },
+                               [&](int k, int j) { return W[k * TC_LD + j]; });
 #pragma unroll
-            for (int u = 0; u < 2; ++u)
-                c[u] = tile(zero, ti[u], tj, K64{}, [&](int i, int k) { return Ap[i * TC_LD + k]; },
-                            [&](int k, int j) { return W[k * TC_LD + j]; });
-#pragma unroll
-            for (int u = 0; u < 2; ++u)
-#pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    sA[l][(ti[u] + kq + e) * TC_LD + tj + lc] = tanhf(c[u][e] + b[tj + lc]);
+            for (int e = 0; e < 4; ++e)
+                sA[l][(tr + kq + e) * TC_LD + tj + lc] = tanhf(c[e] + b[tj + lc]);
             __syncthreads();
         }
-        if (wave < 4) {   // y = a3 W4 + b4, then dL/dy = w (y - t) / sum w (0 past n)
+        if (wave < TC_ROWS / 16) {   // y = a3 W4 + b4, then dL/dy = w (y - t) / sum w (0 past n)
             v4f c = tile(zero, 16 * wave, 0, K64{}, [&](int i, int k) { return sA[2][i * TC_LD + k]; },
                          [&](int k, int j) { return j < NOUT ? sW4[k * NOUT + j] : 0.f; });
             if (lc < NOUT) {
@@ -300,24 +295,19 @@ __global__ void __launch_bounds__(TC_THREADS) k_train_chunk(TrainArgs a) {
         // ---- back-propagation ----
         // d3 = (dy W4^T) (1 - a3^2); dW4 += a3^T dy (waves 0..3); db4 (wave 4)
         {
-            v4f c[2];
-#pragma unroll
-            for (int u = 0; u < 2; ++u)
-                c[u] = tile(zero, ti[u], tj, K16{}, [&](int i, int k) { return k < NOUT ? sDy[i * NOUT + k] : 0.f; },
-                            [&](int k, int j) { return k < NOUT ? sW4[j * NOUT + k] : 0.f; });
+            const v4f c = tile(zero, tr, tj, K16{}, [&](int i, int k) { return k < NOUT ? sDy[i * NOUT + k] : 0.f; },
+                               [&](int k, int j) { return k < NOUT ? sW4[j * NOUT + k] : 0.f; });
             if (wave < 4)
-                gW4 = tile(gW4, 16 * wave, 0, K64{}, [&](int i, int k) { return sA[2][k * TC_LD + i]; },
+                gW4 = tile(gW4, 16 * wave, 0, KR{}, [&](int i, int k) { return sA[2][k * TC_LD + i]; },
                            [&](int k, int j) { return j < NOUT ? sDy[k * NOUT + j] : 0.f; });
             else if (wave == 4 && lane < NOUT)
                 colsum(sDy, NOUT);
 #pragma unroll
-            for (int u = 0; u < 2; ++u)
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int o = (ti[u] + kq + e) * TC_LD + tj + lc;
-                    const float p = sA[2][o];
-                    sD[0][o] = c[u][e] * (1.0f - p * p);
-                }
+            for (int e = 0; e < 4; ++e) {
+                const int o = (tr + kq + e) * TC_LD + tj + lc;
+                const float p = sA[2][o];
+                sD[0][o] = c[e] * (1.0f - p * p);
+            }
         }
         __syncthreads();
         // d2 = (d3 W3^T) (1 - a2^2); dW3 += a2^T d3; db3 (wave 5)
@@ -327,29 +317,25 @@ __global__ void __launch_bounds__(TC_THREADS) k_train_chunk(TrainArgs a) {
             const float *Dn = sD[(2 - l) & 1], *Ap = sA[l - 1], *W = l == 2 ? sW3 : sW2;
             float *Dp = sD[(3 - l) & 1];
             v4f (&gW)[2] = l == 2 ? gW3 : gW2;
-            v4f c[2];
-#pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                c[u] = tile(zero, ti[u], tj, K64{}, [&](int i, int k) { return Dn[i * TC_LD + k]; },
-                            [&](int k, int j) { return W[j * TC_LD + k]; });
-                gW[u] = tile(gW[u], ti[u], tj, K64{}, [&](int i, int k) { return Ap[k * TC_LD + i]; },
-                             [&](int k, int j) { return Dn[k * TC_LD + j]; });
-            }
-            if (wave == (l == 2 ? 5 : 6)) colsum(Dn, TC_LD);
+            const v4f c = tile(zero, tr, tj, K64{}, [&](int i, int k) { return Dn[i * TC_LD + k]; },
+                               [&](int k, int j) { return W[j * TC_LD + k]; });
 #pragma unroll
             for (int u = 0; u < 2; ++u)
+                gW[u] = tile(gW[u], ti[u], tj, KR{}, [&](int i, int k) { return Ap[k * TC_LD + i]; },
+                             [&](int k, int j) { return Dn[k * TC_LD + j]; });
+            if (wave == (l == 2 ? 5 : 6)) colsum(Dn, TC_LD);
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int o = (ti[u] + kq + e) * TC_LD + tj + lc;
-                    const float p = Ap[o];
-                    Dp[o] = c[u][e] * (1.0f - p * p);
-                }
+            for (int e = 0; e < 4; ++e) {
+                const int o = (tr + kq + e) * TC_LD + tj + lc;
+                const float p = Ap[o];
+                Dp[o] = c[e] * (1.0f - p * p);
+            }
             __syncthreads();
         }
         // dW1 += x^T d1 (waves 4..7); db1 (wave 7)
         if (wave >= 4) {
             const float *D1 = sD[0];
-            gW1 = tile(gW1, 0, 16 * (wave - 4), K64{}, [&](int i, int k) { return i < NIN ? sX[k * NIN + i] : 0.f; },
+            gW1 = tile(gW1, 0, 16 * (wave - 4), KR{}, [&](int i, int k) { return i < NIN ? sX[k * NIN + i] : 0.f; },
                        [&](int k, int j) { return D1[k * TC_LD + j]; });
             if (wave == 7) colsum(D1, TC_LD);
         }
@@ -386,7 +372,15 @@ __global__ void k_train_update(float *__restrict__ th, float *__restrict__ m, fl
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= NPAR) return;
     float gi = 0.f;
-    for (int b = 0; b < nb; ++b) gi += G[(size_t)b * NPAR + i];
+    // rows in groups of 16 with every load of a group in flight, summed in row order
+    for (int b0 = 0; b0 < nb; b0 += 16) {
+        float r[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) r[k] = b0 + k < nb ? G[(size_t)(b0 + k) * NPAR + i] : 0.f;
+#pragma unroll
+        for (int k = 0; k < 16; ++k)
+            if (b0 + k < nb) gi += r[k];
+    }
     const float mi = b1 * m[i] + (1.f - b1) * gi, vi = b2 * v[i] + (1.f - b2) * gi * gi;
     m[i] = mi;
     v[i] = vi;
