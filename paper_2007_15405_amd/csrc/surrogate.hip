@@ -762,7 +762,7 @@ extern "C" lbm_status lbm_surrogate_train(lbm_surrogate *s, int32_t steps, float
     if (s->n == 0) return sfail(s, LBM_E_STATE, "no training data");
     if (steps < 0 || !(lr > 0.0f)) return sfail(s, LBM_E_INVAL, "steps >= 0 and lr > 0");
     const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
-    // one launch computes the gradient (64-sample chunks over up to TC_BLOCKS workgroups),
+    // one launch computes the gradient (chunks of TC_ROWS samples over up to TC_BLOCKS workgroups),
     // a second sums the workgroups' gradients and takes the Adam step
     const int chunks = (s->n + TC_ROWS - 1) / TC_ROWS;
     const int nb = chunks < TC_BLOCKS ? chunks : TC_BLOCKS;
