@@ -89,9 +89,10 @@ struct lbm_handle {
     double4 *d_V = nullptr;
     long long *d_pex = nullptr, *d_rsc = nullptr;
     float4 *d_pprev = nullptr, *d_ffl = nullptr;
-    int *d_bcount = nullptr, *d_bstart = nullptr, *d_blist = nullptr, *d_nlinks = nullptr;
+    int *d_bstart = nullptr, *d_blist = nullptr, *d_nlinks = nullptr;
     BBLink *d_links = nullptr;
     float4 *d_tpos = nullptr;
+    int *d_tcell = nullptr;
     int link_cap = 0;
 };
 
@@ -174,7 +175,7 @@ static void free_all(lbm_handle *h) {
                     h->d_off, h->d_list, h->d_marks, h->d_rowstart, h->d_slot, h->d_wbuf,
                     h->d_wpar, h->d_xrow, h->d_edge, h->d_eth0, h->d_eoff,
                     h->d_elist, h->d_V, h->d_pex, h->d_rsc, h->d_pprev, h->d_ffl,
-                    h->d_bcount, h->d_bstart, h->d_blist, h->d_nlinks, h->d_links, h->d_tpos};
+                    h->d_bstart, h->d_blist, h->d_nlinks, h->d_links, h->d_tpos, h->d_tcell};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     free_prof(h->prof);
@@ -721,22 +722,20 @@ static lbm_status finalize(lbm_handle *h) {
         int mt = 1;
         for (const CapDev &c : h->h_caps) mt = std::max(mt, c.nt);
         h->link_cap = std::max(4096, 24 * mt);
-        if (dalloc(&h->d_V, nt) != hipSuccess || dalloc(&h->d_pex, 3 * nt) != hipSuccess ||
-            dalloc(&h->d_rsc, 3 * nt) != hipSuccess || dalloc(&h->d_pprev, nt) != hipSuccess ||
+        if (dalloc(&h->d_V, nt) != hipSuccess || dalloc(&h->d_pex, 3 * tt) != hipSuccess ||
+            dalloc(&h->d_rsc, 3 * tt) != hipSuccess || dalloc(&h->d_pprev, nt) != hipSuccess ||
             dalloc(&h->d_ffl, nt) != hipSuccess ||
-            dalloc(&h->d_bcount, (size_t)ncap * GMAX3) != hipSuccess ||
             dalloc(&h->d_bstart, (size_t)ncap * (GMAX3 + 1)) != hipSuccess ||
             dalloc(&h->d_blist, (size_t)BB_PER_TRI * tt) != hipSuccess ||
             dalloc(&h->d_nlinks, 2 * (size_t)ncap) != hipSuccess ||
             dalloc(&h->d_links, (size_t)ncap * h->link_cap) != hipSuccess ||
-            dalloc(&h->d_tpos, 3 * tt) != hipSuccess)
+            dalloc(&h->d_tpos, 3 * tt) != hipSuccess || dalloc(&h->d_tcell, tt) != hipSuccess)
             return fail(h, LBM_E_NOMEM, "device allocation failed (bounce-back)");
         HIPCHK(h, hipMemsetAsync(h->d_V, 0, nt * sizeof(double4), h->st));
-        HIPCHK(h, hipMemsetAsync(h->d_pex, 0, 3 * nt * sizeof(long long), h->st));
-        HIPCHK(h, hipMemsetAsync(h->d_rsc, 0, 3 * nt * sizeof(long long), h->st));
+        HIPCHK(h, hipMemsetAsync(h->d_pex, 0, 3 * tt * sizeof(long long), h->st));
+        HIPCHK(h, hipMemsetAsync(h->d_rsc, 0, 3 * tt * sizeof(long long), h->st));
         HIPCHK(h, hipMemsetAsync(h->d_pprev, 0, nt * sizeof(float4), h->st));
         HIPCHK(h, hipMemsetAsync(h->d_ffl, 0, nt * sizeof(float4), h->st));
-        HIPCHK(h, hipMemsetAsync(h->d_bcount, 0, (size_t)ncap * GMAX3 * sizeof(int), h->st));
         HIPCHK(h, hipMemsetAsync(h->d_bstart, 0, (size_t)ncap * (GMAX3 + 1) * sizeof(int), h->st));
         HIPCHK(h, hipMemsetAsync(h->d_blist, 0, (size_t)BB_PER_TRI * tt * sizeof(int), h->st));
         HIPCHK(h, hipMemsetAsync(h->d_nlinks, 0, 2 * (size_t)ncap * sizeof(int), h->st));
@@ -755,12 +754,13 @@ static BBArgs bb_args(lbm_handle *h, int cur) {
     b.f = h->f[cur];
     b.dens = h->ro;
     b.tpos = h->d_tpos;
+    b.tcell = h->d_tcell;
     b.N = h->N; b.nx = h->nx; b.ny = h->ny; b.nz = h->nz; b.wall = h->wall; b.lz = h->lz;
     b.shift[0] = shift_of(h, 0);
     b.shift[1] = shift_of(h, 1);
-    b.bcount = h->d_bcount; b.bstart = h->d_bstart; b.blist = h->d_blist;
+    b.bstart = h->d_bstart; b.blist = h->d_blist;
     b.links = h->d_links; b.link_cap = h->link_cap; b.nlinks = h->d_nlinks;
-    b.pex = h->d_pex; b.rsc = h->d_rsc; b.pprev = h->d_pprev; b.ffl = h->d_ffl; b.R = h->d_R;
+    b.pex = h->d_pex; b.rsc = h->d_rsc; b.ntri_off = h->d_off; b.ntri = h->d_list; b.pprev = h->d_pprev; b.ffl = h->d_ffl; b.R = h->d_R;
     b.status = h->status;
     b.G = (float)h->p.G;
     b.ws_axis = (float)(h->p.sc_norm / 18.0);
@@ -1793,10 +1793,9 @@ extern "C" lbm_status lbm_load(lbm_handle *h, const char *path) {
     if (bb) {
         HIPCHK(h, hipMemcpy(h->d_V, V.data(), V.size() * sizeof(double4), hipMemcpyHostToDevice));
         HIPCHK(h, hipMemcpy(h->d_pprev, Pp.data(), Pp.size() * sizeof(float4), hipMemcpyHostToDevice));
-        HIPCHK(h, hipMemset(h->d_pex, 0, 3 * (size_t)h->ntot * sizeof(long long)));
-        HIPCHK(h, hipMemset(h->d_rsc, 0, 3 * (size_t)h->ntot * sizeof(long long)));
+        HIPCHK(h, hipMemset(h->d_pex, 0, 3 * (size_t)h->ttot * sizeof(long long)));
+        HIPCHK(h, hipMemset(h->d_rsc, 0, 3 * (size_t)h->ttot * sizeof(long long)));
         HIPCHK(h, hipMemset(h->d_nlinks, 0, 2 * h->caps.size() * sizeof(int)));
-        HIPCHK(h, hipMemset(h->d_bcount, 0, h->caps.size() * GMAX3 * sizeof(int)));
     }
     if (h->ntot)   // crossing masks of windows this handle used before the load
         HIPCHK(h, hipMemset(h->d_marks, 0, h->caps.size() * ROWS_MAX * sizeof(unsigned long long)));

@@ -4,11 +4,12 @@
 // consecutive steps, and Newtonian membrane nodes of mass m (25 rho0 in Section 3.2).
 //
 // Per step, after the capsule reduction (window), the membrane forces and the side labels:
-//   k_bb_bin_count / k_bb_bin_scan / k_bb_bin_fill: the triangles of each capsule binned
-//     into the unit cells of its window (counting sort; the counts return to zero);
+//   k_bb_tri / k_bb_bins: the triangles of each capsule binned into the unit cells of its
+//     window (their cell ranges per triangle, then a counting sort in LDS, one workgroup
+//     per capsule);
 //   k_bb_find: every link from a site inside capsule k to a fluid site of another side
 //     (exterior, or a capsule of higher index) is appended to the capsule's link list;
-//   k_bb_resolve: 16 lanes per link find its triangle (among the triangles whose bounding
+//   k_bb_resolve: 8 lanes per link find its triangle (among the triangles whose bounding
 //     box meets the link's, the least miss distance, lowest index on ties) and the
 //     densities of both sites before any population is changed;
 //   k_bb_swap: the bounce-back on the post-collision populations in place, so that plain
@@ -105,10 +106,11 @@ __device__ __forceinline__ void pops(void *f, int c, int q, int N, int s, float 
 // ------------------------------------------------------------------------------------
 // Triangle bins
 // ------------------------------------------------------------------------------------
-__device__ __forceinline__ bool tri_cells(const BBArgs &b, int t, int k, int (&c0)[3], int (&c1)[3]) {
+// the window cells (first and last per axis) that the box of a triangle with vertices v
+// covers; false for a triangle wider than BB_SPAN cells or outside the window
+__device__ __forceinline__ bool tri_cells(const BBArgs &b, const double (&v)[3][3], int k, int (&c0)[3],
+                                          int (&c1)[3]) {
     const CapState cs = b.cst[k];
-    double v[3][3];
-    tri_vertices(b, t, v);
     for (int d = 0; d < 3; ++d) {
         const double lo = fmin(v[0][d], fmin(v[1][d], v[2][d]));
         const double hi = fmax(v[0][d], fmax(v[1][d], v[2][d]));
@@ -120,125 +122,215 @@ __device__ __forceinline__ bool tri_cells(const BBArgs &b, int t, int k, int (&c
     return true;
 }
 
-__global__ void __launch_bounds__(256) k_bb_bin_count(BBArgs b) {
+// one thread per triangle: its FP32-rounded vertices, compact for the link search, and the
+// window cells its box covers, packed into one word for the sort
+static_assert(GMAX <= 64 && BB_SPAN <= 4, "cell ranges are packed into 6 + 2 bits per axis");
+__global__ void __launch_bounds__(256) k_bb_tri(BBArgs b) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= b.ttot) return;
-    const int k = b.tri[t].w;
-    {
-        // the FP32-rounded vertices, compact for the link search
-        double v[3][3];
-        tri_vertices(b, t, v);
+    double v[3][3];
+    tri_vertices(b, t, v);
 #pragma unroll
-        for (int m = 0; m < 3; ++m)
-            b.tpos[3 * (size_t)t + m] = make_float4((float)v[m][0], (float)v[m][1], (float)v[m][2], 0.f);
-    }
+    for (int m = 0; m < 3; ++m)
+        b.tpos[3 * (size_t)t + m] = make_float4((float)v[m][0], (float)v[m][1], (float)v[m][2], 0.f);
     int c0[3], c1[3];
-    if (!tri_cells(b, t, k, c0, c1)) {
+    int packed = -1;
+    if (tri_cells(b, v, b.tri[t].w, c0, c1))
+        packed = c0[0] | c0[1] << 6 | c0[2] << 12 | (c1[0] - c0[0]) << 18 | (c1[1] - c0[1]) << 20 |
+                 (c1[2] - c0[2]) << 22;
+    else
         atomicOr(&b.status[ST_BBOVER], 1);
-        return;
+    b.tcell[t] = packed;
+    // this step's momentum exchange and reaction through the triangle start from zero
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        b.pex[3 * (size_t)t + d] = 0;
+        b.rsc[3 * (size_t)t + d] = 0;
     }
-    const CapState cs = b.cst[k];
-    int *cnt = b.bcount + (size_t)k * GMAX3;
-    for (int z = c0[2]; z <= c1[2]; ++z)
-        for (int y = c0[1]; y <= c1[1]; ++y)
-            for (int x = c0[0]; x <= c1[0]; ++x)
-                atomicAdd(&cnt[(z * cs.dim[1] + y) * cs.dim[0] + x], 1);
 }
 
-// exclusive scan of the cell counts of capsule k (one block of 1024 threads)
-__global__ void __launch_bounds__(1024) k_bb_bin_scan(BBArgs b) {
+// one workgroup per capsule: a counting sort of the capsule's triangles into the unit
+// cells of its window.  The cell counters are in LDS; a window of more than BB_LDS_CELLS
+// cells is sorted in passes over cell ranges, each pass counting, scanning and filling its
+// range.  The entries of one cell come in no fixed order: the link search takes the least
+// (distance, index) over them, which does not depend on it.
+constexpr int BB_BIN_BLK = 1024;
+constexpr int BB_LDS_CELLS = 16384;   // 64 KB of counters
+constexpr int BB_BIN_TB = 8;          // triangles per thread whose ranges are loaded together
+
+// the cells of triangle range word w that fall in [p0, p0 + n), in window order, relative to p0
+template <typename Fn>
+__device__ __forceinline__ void for_cells(int w, int dx, int dy, int p0, int n, Fn &&fn) {
+    const int x0 = w & 63, y0 = (w >> 6) & 63, z0 = (w >> 12) & 63;
+    const int ex = (w >> 18) & 3, ey = (w >> 20) & 3, ez = (w >> 22) & 3;
+    for (int z = z0; z <= z0 + ez; ++z)
+        for (int y = y0; y <= y0 + ey; ++y)
+            for (int x = x0; x <= x0 + ex; ++x) {
+                const int cell = (z * dy + y) * dx + x - p0;
+                if (cell >= 0 && cell < n) fn(cell);
+            }
+}
+
+__global__ void __launch_bounds__(BB_BIN_BLK) k_bb_bins(BBArgs b) {
     const int k = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const CapState cs = b.cst[k];
-    const int ncell = cs.dim[0] * cs.dim[1] * cs.dim[2];
-    const int *cnt = b.bcount + (size_t)k * GMAX3;
+    const CapDev cd = b.caps[k];
+    const int dx = cs.dim[0], dy = cs.dim[1], ncell = dx * dy * cs.dim[2];
+    const int lmax = BB_PER_TRI * cd.nt;
     int *st = b.bstart + (size_t)k * (GMAX3 + 1);
-    const int per = (ncell + 1023) / 1024;
-    const int q0 = min(tid * per, ncell), q1 = min(q0 + per, ncell);
-    int local = 0;
-    for (int i = q0; i < q1; ++i) local += cnt[i];
-    int incl = local;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const int v = __shfl_up(incl, o, 64);
-        if (lane >= o) incl += v;
-    }
-    __shared__ int wsum[16];
-    if (lane == 63) wsum[wid] = incl;
-    __syncthreads();
-    int run = incl - local;
-    for (int w = 0; w < wid; ++w) run += wsum[w];
-    for (int i = q0; i < q1; ++i) {
-        st[i] = run;
-        run += cnt[i];
-    }
-    if (q1 == ncell && q0 < q1) st[ncell] = run;
-    if (ncell == 0 && tid == 0) st[0] = 0;
-    const CapDev cd = b.caps[k];
-    if (tid == 1023) {
-        int tot = 0;
-        for (int w = 0; w < 16; ++w) tot += wsum[w];
-        if (tot > BB_PER_TRI * cd.nt) atomicOr(&b.status[ST_BBOVER], 1);
-    }
-}
-
-__global__ void __launch_bounds__(256) k_bb_bin_fill(BBArgs b) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= b.ttot) return;
-    const int k = b.tri[t].w;
-    int c0[3], c1[3];
-    if (!tri_cells(b, t, k, c0, c1)) return;
-    const CapState cs = b.cst[k];
-    const CapDev cd = b.caps[k];
-    int *cnt = b.bcount + (size_t)k * GMAX3;
-    const int *st = b.bstart + (size_t)k * (GMAX3 + 1);
     int *list = b.blist + (size_t)BB_PER_TRI * cd.tri0;
-    for (int z = c0[2]; z <= c1[2]; ++z)
-        for (int y = c0[1]; y <= c1[1]; ++y)
-            for (int x = c0[0]; x <= c1[0]; ++x) {
-                const int cell = (z * cs.dim[1] + y) * cs.dim[0] + x;
-                // the count runs back to zero, ready for the next step
-                const int pos = st[cell] + atomicSub(&cnt[cell], 1) - 1;
-                if (pos < BB_PER_TRI * cd.nt) list[pos] = t;
+    const int *tc = b.tcell + cd.tri0;
+    __shared__ int s_cnt[BB_LDS_CELLS];
+    __shared__ int s_wsum[BB_BIN_BLK / 64];
+    int base = 0;   // entries of the cells before this pass
+    for (int p0 = 0; p0 < ncell; p0 += BB_LDS_CELLS) {   // uniform over the block
+        const int n = min(BB_LDS_CELLS, ncell - p0);
+        for (int i = tid; i < n; i += BB_BIN_BLK) s_cnt[i] = 0;
+        __syncthreads();
+        for (int t0 = 0; t0 < cd.nt; t0 += BB_BIN_TB * BB_BIN_BLK) {
+            int w[BB_BIN_TB];
+#pragma unroll
+            for (int u = 0; u < BB_BIN_TB; ++u) {
+                const int t = t0 + tid + u * BB_BIN_BLK;
+                w[u] = t < cd.nt ? tc[t] : -1;
             }
+#pragma unroll
+            for (int u = 0; u < BB_BIN_TB; ++u)
+                if (w[u] >= 0) for_cells(w[u], dx, dy, p0, n, [&](int c) { atomicAdd(&s_cnt[c], 1); });
+        }
+        __syncthreads();
+        // exclusive scan of the pass's counts: each thread sums a contiguous run, the run
+        // sums are scanned over the lanes and then over the waves
+        const int per = (n + BB_BIN_BLK - 1) / BB_BIN_BLK;
+        const int q0 = min(tid * per, n), q1 = min(q0 + per, n);
+        int local = 0;
+        for (int i = q0; i < q1; ++i) local += s_cnt[i];
+        int incl = local;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int v = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += v;
+        }
+        if (lane == 63) s_wsum[wid] = incl;
+        __syncthreads();
+        int run = base + incl - local, total = 0;
+        for (int w = 0; w < BB_BIN_BLK / 64; ++w) {
+            if (w < wid) run += s_wsum[w];
+            total += s_wsum[w];
+        }
+        for (int i = q0; i < q1; ++i) {
+            const int c = s_cnt[i];
+            s_cnt[i] = run;
+            run += c;
+        }
+        __syncthreads();
+        for (int i = tid; i < n; i += BB_BIN_BLK) st[p0 + i] = s_cnt[i];
+        __syncthreads();   // the starts are read before the fill moves the cursors
+        for (int t0 = 0; t0 < cd.nt; t0 += BB_BIN_TB * BB_BIN_BLK) {
+            int w[BB_BIN_TB];
+#pragma unroll
+            for (int u = 0; u < BB_BIN_TB; ++u) {
+                const int t = t0 + tid + u * BB_BIN_BLK;
+                w[u] = t < cd.nt ? tc[t] : -1;
+            }
+#pragma unroll
+            for (int u = 0; u < BB_BIN_TB; ++u) {
+                const int t = cd.tri0 + t0 + tid + u * BB_BIN_BLK;
+                if (w[u] >= 0)
+                    for_cells(w[u], dx, dy, p0, n, [&](int c) {
+                        const int pos = atomicAdd(&s_cnt[c], 1);
+                        if (pos < lmax) list[pos] = t;
+                    });
+            }
+        }
+        base += total;
+        __syncthreads();   // the next pass clears the counters and rewrites the wave sums
+    }
+    if (tid == 0) {
+        st[ncell] = base;
+        if (base > lmax) atomicOr(&b.status[ST_BBOVER], 1);
+    }
 }
 
 // ------------------------------------------------------------------------------------
 // Links and bounce-back
 // ------------------------------------------------------------------------------------
-// plane lz of capsule k's window: the links of its inside sites, appended as (a, b, q)
-__global__ void __launch_bounds__(256) k_bb_find(BBArgs b) {
-    const int k = blockIdx.y, lz = blockIdx.x;
+// plane lz of capsule k's window: the links of its inside sites, appended as (a, b, q).
+// Each wave reserves the places of all its lanes' links with one atomic add (the lanes'
+// counts scanned over the wave), so the capsule's counter sees one add per wave, not one
+// per site; the order of the list does not enter any result.
+constexpr int BB_FIND_BLK = 1024;   // one pass over a window plane of up to 1024 columns
+
+__global__ void __launch_bounds__(BB_FIND_BLK) k_bb_find(BBArgs b) {
+    const int k = blockIdx.y, lz = blockIdx.x, lane = threadIdx.x & 63;
     const CapState cs = b.cst[k];
     if (lz >= cs.dim[2]) return;
-    const int dx = cs.dim[0], dy = cs.dim[1];
+    const int dx = cs.dim[0], dy = cs.dim[1], ncol = dx * dy;
     const int uz = cs.lo[2] + lz, z = wrapb(uz, b.nz);
     if (b.wall && slab_pos(z, b.lz) == 0) return;
-    for (int col = threadIdx.x; col < dx * dy; col += blockDim.x) {
-        const int ly = col / dx, lx = col - ly * dx;
-        const int ux = cs.lo[0] + lx, uy = cs.lo[1] + ly;
-        const int sa = (z * b.ny + wrapb(uy, b.ny)) * b.nx + wrapb(ux, b.nx);
-        if ((b.flag[sa] & LABEL_MASK) != k + 1) continue;
-        int sb[Q - 1];
+    // the planes below and above, and whether they are wall planes (uniform over the block)
+    const int zm = z == 0 ? b.nz - 1 : z - 1, zp = z == b.nz - 1 ? 0 : z + 1;
+    const bool wm = b.wall && slab_pos(zm, b.lz) == 0, wp = b.wall && slab_pos(zp, b.lz) == 0;
+    for (int c0 = 0; c0 < ncol; c0 += blockDim.x) {   // uniform over the block
+        const int col = c0 + threadIdx.x;
+        int sa = 0, x = 0, y = 0, xm = 0, xp = 0, ym = 0, yp = 0;
         unsigned mask = 0u;
-        for (int q = 1; q < Q; ++q) {
-            const int zb = wrapb(uz + CZ[q], b.nz);
-            sb[q - 1] = (zb * b.ny + wrapb(uy + CY[q], b.ny)) * b.nx + wrapb(ux + CX[q], b.nx);
-            if (b.wall && slab_pos(zb, b.lz) == 0) continue;
-            const int lb = b.flag[sb[q - 1]] & LABEL_MASK;
-            if (lb == k + 1 || (lb != 0 && lb < k + 1)) continue;
-            mask |= 1u << q;
+        if (col < ncol) {
+            const int ly = col / dx, lx = col - ly * dx;
+            x = wrapb(cs.lo[0] + lx, b.nx);
+            y = wrapb(cs.lo[1] + ly, b.ny);
+            sa = (z * b.ny + y) * b.nx + x;
+            // neighbour coordinates wrap by one step at most
+            xm = x == 0 ? b.nx - 1 : x - 1;
+            xp = x == b.nx - 1 ? 0 : x + 1;
+            ym = y == 0 ? b.ny - 1 : y - 1;
+            yp = y == b.ny - 1 ? 0 : y + 1;
+            if ((b.flag[sa] & LABEL_MASK) == k + 1) {
+                // every neighbour is a lattice site: its flag is loaded unconditionally, all 18
+                // loads issued before the first is tested
+                uint8_t fb[Q - 1];
+#pragma unroll
+                for (int q = 1; q < Q; ++q) {
+                    const int xb = CX[q] < 0 ? xm : (CX[q] > 0 ? xp : x);
+                    const int yb = CY[q] < 0 ? ym : (CY[q] > 0 ? yp : y);
+                    const int zb = CZ[q] < 0 ? zm : (CZ[q] > 0 ? zp : z);
+                    fb[q - 1] = b.flag[(zb * b.ny + yb) * b.nx + xb];
+                }
+#pragma unroll
+                for (int q = 1; q < Q; ++q) {
+                    if (CZ[q] < 0 ? wm : (CZ[q] > 0 ? wp : false)) continue;
+                    const int lb = fb[q - 1] & LABEL_MASK;
+                    if (lb == k + 1 || (lb != 0 && lb < k + 1)) continue;
+                    mask |= 1u << q;
+                }
+            }
         }
+        const int cnt = __popc(mask);
+        int incl = cnt;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int v = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += v;
+        }
+        const int wtot = __shfl(incl, 63, 64);
+        if (wtot == 0) continue;   // uniform over the wave
+        int i = 0;
+        if (lane == 63) i = atomicAdd(&b.nlinks[k], wtot);
+        i = __shfl(i, 63, 64) + incl - cnt;
         if (!mask) continue;
-        int i = atomicAdd(&b.nlinks[k], __popc(mask));
+#pragma unroll
         for (int q = 1; q < Q; ++q) {
             if (!(mask & (1u << q))) continue;
             if (i >= b.link_cap) {
                 atomicOr(&b.status[ST_BBOVER], 1);
                 break;
             }
+            const int xb = CX[q] < 0 ? xm : (CX[q] > 0 ? xp : x);
+            const int yb = CY[q] < 0 ? ym : (CY[q] > 0 ? yp : y);
+            const int zb = CZ[q] < 0 ? zm : (CZ[q] > 0 ? zp : z);
             BBLink L;
             L.a = sa;
-            L.b = sb[q - 1];
+            L.b = (zb * b.ny + yb) * b.nx + xb;
             L.q = q;
             L.tri = -1;
             L.rho[0] = L.rho[1] = L.rho[2] = L.rho[3] = 0.f;
@@ -251,10 +343,11 @@ __global__ void __launch_bounds__(256) k_bb_find(BBArgs b) {
 // BB_RL lanes per link: the crossed triangle (least miss distance among the candidates of
 // the cells the link's bounding box touches, lowest index on ties; the lanes split the
 // candidates and reduce), and both sites' densities before any population changes
-constexpr int BB_RL = 16;
+constexpr int BB_RL = 8;
+static_assert(BB_RL == 8, "the density sums take two of sixteen partial sums per lane");
 
 template <int S>
-__global__ void __launch_bounds__(256) k_bb_resolve(BBArgs b) {
+__global__ void __launch_bounds__(256, 3) k_bb_resolve(BBArgs b) {
     const int k = blockIdx.y, sl = threadIdx.x % BB_RL;
     const int nl = min(b.nlinks[k], b.link_cap);
     const CapState cs = b.cst[k];
@@ -269,6 +362,24 @@ __global__ void __launch_bounds__(256) k_bb_resolve(BBArgs b) {
     for (int i = g0; i < nl; i += gstride) {
         BBLink &L = b.links[(size_t)k * b.link_cap + i];
         const int sa = L.a, sbi = L.b, q = L.q;
+        // densities of both sites (issued first, so that their loads are in flight during
+        // the candidate search), summed in the order of a 16-wide butterfly whatever the
+        // group's width: partial sum j < 16 holds the populations j and j + 16, lane sl holds
+        // the partial sums sl and sl + 8 and adds them as that butterfly's first level does
+        float ra0 = 0.f, ra1 = 0.f, rb0 = 0.f, rb1 = 0.f;
+        float xa0 = 0.f, xa1 = 0.f, xb0 = 0.f, xb1 = 0.f;
+        for (int qq = sl; qq < Q; qq += 16) {
+            ra0 += popl<S>(b.f, 0, qq, b.N, sa, b.shift[0]);
+            ra1 += popl<S>(b.f, 1, qq, b.N, sa, b.shift[1]);
+            rb0 += popl<S>(b.f, 0, qq, b.N, sbi, b.shift[0]);
+            rb1 += popl<S>(b.f, 1, qq, b.N, sbi, b.shift[1]);
+        }
+        for (int qq = sl + 8; qq < Q; qq += 16) {
+            xa0 += popl<S>(b.f, 0, qq, b.N, sa, b.shift[0]);
+            xa1 += popl<S>(b.f, 1, qq, b.N, sa, b.shift[1]);
+            xb0 += popl<S>(b.f, 0, qq, b.N, sbi, b.shift[0]);
+            xb1 += popl<S>(b.f, 1, qq, b.N, sbi, b.shift[1]);
+        }
         // unwrapped coordinates of a in the window's frame, from its lattice index
         const int ax = sa % b.nx, ay = (sa / b.nx) % b.ny, az = sa / (b.nx * b.ny);
         const int ux = cs.lo[0] + wrapb(ax - cs.lo[0], b.nx);
@@ -277,55 +388,87 @@ __global__ void __launch_bounds__(256) k_bb_resolve(BBArgs b) {
         const double p0[3] = {(double)ux, (double)uy, (double)uz};
         const double p1[3] = {(double)(ux + CX[q]), (double)(uy + CY[q]), (double)(uz + CZ[q])};
         double lo[3], hi[3];
-        int c0[3], c1[3];
+        int c0[3], nc3[3];
         for (int d = 0; d < 3; ++d) {
             lo[d] = fmin(p0[d], p1[d]);
             hi[d] = fmax(p0[d], p1[d]);
             c0[d] = max((int)lo[d] - cs.lo[d], 0);
-            c1[d] = min((int)hi[d] - cs.lo[d], cs.dim[d] - 1);
+            // one or two cells per axis (a link moves at most one site per axis)
+            nc3[d] = max(min((int)hi[d] - cs.lo[d], cs.dim[d] - 1) - c0[d] + 1, 0);
         }
-        // candidate entries of the (at most 2 x 2 x 2) cells, concatenated
-        int beg[8], cnt[8], nc = 0, tot = 0;
-        for (int cz = c0[2]; cz <= c1[2]; ++cz)
-            for (int cy = c0[1]; cy <= c1[1]; ++cy)
-                for (int cx = c0[0]; cx <= c1[0]; ++cx) {
-                    const int cell = (cz * dy + cy) * dx + cx;
-                    const int e0 = st[cell], e1 = min(st[cell + 1], lmax);
-                    beg[nc] = e0;
-                    cnt[nc] = max(e1 - e0, 0);
-                    tot += cnt[nc];
-                    ++nc;
-                }
+        // the (at most 2 x 2 x 2) cells, x fastest: lane j of the group reads the start and
+        // the end of cell j, and the group shares them
+        int my_beg = 0, my_cnt = 0;
+        if (sl < nc3[0] * nc3[1] * nc3[2]) {
+            const int ix = nc3[0] == 2 ? (sl & 1) : 0, r1 = nc3[0] == 2 ? sl >> 1 : sl;
+            const int iy = nc3[1] == 2 ? (r1 & 1) : 0, iz = nc3[1] == 2 ? r1 >> 1 : r1;
+            const int cell = ((c0[2] + iz) * dy + c0[1] + iy) * dx + c0[0] + ix;
+            my_beg = st[cell];
+            my_cnt = max(min(st[cell + 1], lmax) - my_beg, 0);
+        }
+        // the first level of the density butterfly (the cell starts' wait covers the loads)
+        ra0 += xa0;
+        ra1 += xa1;
+        rb0 += xb0;
+        rb1 += xb1;
+        int beg[8], cnt[8], tot = 0;
+#pragma unroll
+        for (int n = 0; n < 8; ++n) {
+            beg[n] = __shfl(my_beg, n, BB_RL);
+            cnt[n] = __shfl(my_cnt, n, BB_RL);
+            tot += cnt[n];
+        }
         double bd = __builtin_inf();
         int best = 0x7fffffff;
-        for (int e = sl; e < tot; e += BB_RL) {
-            int r = e, n = 0;
-            while (r >= cnt[n]) r -= cnt[n++];
-            const int t = list[beg[n] + r];
-            if ((unsigned)t >= (unsigned)b.ttot) continue;   // never expected
-            const float4 A = b.tpos[3 * (size_t)t], B = b.tpos[3 * (size_t)t + 1],
-                         C = b.tpos[3 * (size_t)t + 2];
-            const double v[3][3] = {{A.x, A.y, A.z}, {B.x, B.y, B.z}, {C.x, C.y, C.z}};
-            bool ok = true;
-            for (int d = 0; d < 3 && ok; ++d) {
-                const double tl = fmin(v[0][d], fmin(v[1][d], v[2][d]));
-                const double th = fmax(v[0][d], fmax(v[1][d], v[2][d]));
-                ok = !(tl > hi[d] || th < lo[d]);
+        // the candidates split over the lanes, BB_RB per lane at a time: the list entries
+        // are loaded together, then the vertices together
+        constexpr int BB_RB = 4;
+        for (int e0 = 0; e0 < tot; e0 += BB_RB * BB_RL) {   // uniform inside a group
+            int tt[BB_RB];
+#pragma unroll
+            for (int u = 0; u < BB_RB; ++u) {
+                int r = e0 + sl + u * BB_RL, at = -1;
+                if (r < tot) {
+#pragma unroll
+                    for (int n = 0; n < 8; ++n) {
+                        if (at < 0) {
+                            if (r < cnt[n]) at = beg[n] + r;
+                            else r -= cnt[n];
+                        }
+                    }
+                }
+                tt[u] = at >= 0 ? list[at] : -1;
             }
-            if (!ok) continue;
-            const double md = miss_distance(p0, p1, v[0], v[1], v[2]);
-            if (md < bd || (md == bd && t < best)) {
-                bd = md;
-                best = t;
+            float4 A[BB_RB], B[BB_RB], C[BB_RB];
+#pragma unroll
+            for (int u = 0; u < BB_RB; ++u) {
+                if ((unsigned)tt[u] >= (unsigned)b.ttot) tt[u] = -1;   // out of range: never expected
+                const size_t o = 3 * (size_t)(tt[u] < 0 ? 0 : tt[u]);
+                if (tt[u] >= 0) {
+                    A[u] = b.tpos[o];
+                    B[u] = b.tpos[o + 1];
+                    C[u] = b.tpos[o + 2];
+                }
             }
-        }
-        // densities of both sites, populations split over the lanes
-        float ra0 = 0.f, ra1 = 0.f, rb0 = 0.f, rb1 = 0.f;
-        for (int qq = sl; qq < Q; qq += BB_RL) {
-            ra0 += popl<S>(b.f, 0, qq, b.N, sa, b.shift[0]);
-            ra1 += popl<S>(b.f, 1, qq, b.N, sa, b.shift[1]);
-            rb0 += popl<S>(b.f, 0, qq, b.N, sbi, b.shift[0]);
-            rb1 += popl<S>(b.f, 1, qq, b.N, sbi, b.shift[1]);
+#pragma unroll
+            for (int u = 0; u < BB_RB; ++u) {
+                const int t = tt[u];
+                if (t < 0) continue;
+                const double v[3][3] = {{A[u].x, A[u].y, A[u].z}, {B[u].x, B[u].y, B[u].z},
+                                        {C[u].x, C[u].y, C[u].z}};
+                bool ok = true;
+                for (int d = 0; d < 3 && ok; ++d) {
+                    const double tl = fmin(v[0][d], fmin(v[1][d], v[2][d]));
+                    const double th = fmax(v[0][d], fmax(v[1][d], v[2][d]));
+                    ok = !(tl > hi[d] || th < lo[d]);
+                }
+                if (!ok) continue;
+                const double md = miss_distance(p0, p1, v[0], v[1], v[2]);
+                if (md < bd || (md == bd && t < best)) {
+                    bd = md;
+                    best = t;
+                }
+            }
         }
         // fixed butterfly over the group: the lexicographic minimum of (distance, index)
         // and the density sums
@@ -380,14 +523,12 @@ __device__ __forceinline__ void bb_swap_one(const BBArgs &b, int k, int i) {
         dp += 2.0f * va - 2.0f * vb - 2.0f * delta;
     }
     if (L.tri < 0) return;
+    // a third to each node of the triangle: summed per triangle here, per node in k_bb_nodes
     const float third = dp / 3.0f;
     const long long p[3] = {fix40(third * CX[q]), fix40(third * CY[q]), fix40(third * CZ[q])};
-    const int nodes[3] = {tr.x, tr.y, tr.z};
 #pragma unroll
-    for (int m = 0; m < 3; ++m)
-#pragma unroll
-        for (int d = 0; d < 3; ++d)
-            if (p[d]) atomicAdd((unsigned long long *)&b.pex[3 * (size_t)nodes[m] + d], (unsigned long long)p[d]);
+    for (int d = 0; d < 3; ++d)
+        if (p[d]) atomicAdd((unsigned long long *)&b.pex[3 * (size_t)L.tri + d], (unsigned long long)p[d]);
 }
 
 template <int S>
@@ -429,13 +570,9 @@ __device__ __forceinline__ void bb_reaction_one(const BBArgs &b, int k, int i) {
     }
     const float third = r / 3.0f;
     const long long p[3] = {fix40(third * CX[q]), fix40(third * CY[q]), fix40(third * CZ[q])};
-    const int4 tr = b.tri[L.tri];
-    const int nodes[3] = {tr.x, tr.y, tr.z};
 #pragma unroll
-    for (int m = 0; m < 3; ++m)
-#pragma unroll
-        for (int d = 0; d < 3; ++d)
-            if (p[d]) atomicAdd((unsigned long long *)&b.rsc[3 * (size_t)nodes[m] + d], (unsigned long long)p[d]);
+    for (int d = 0; d < 3; ++d)
+        if (p[d]) atomicAdd((unsigned long long *)&b.rsc[3 * (size_t)L.tri + d], (unsigned long long)p[d]);
 }
 
 __global__ void __launch_bounds__(256) k_bb_reaction(BBArgs b) {
@@ -445,7 +582,7 @@ __global__ void __launch_bounds__(256) k_bb_reaction(BBArgs b) {
 }
 
 // Newtonian nodes: v += (F_membrane + (P_ex(n) + P_ex(n-1)) / 2 + R_sc) / m, x += v; the
-// accumulators and the link counts are cleared for the next step
+// link counts are cleared for the next step
 __global__ void __launch_bounds__(256) k_bb_nodes(BBArgs b) {
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n == 0)   // this step's link counts are kept (observables) and the counters cleared
@@ -456,13 +593,22 @@ __global__ void __launch_bounds__(256) k_bb_nodes(BBArgs b) {
     if (n >= b.ntot) return;
     const float4 Fm = b.F[b.slot[n]];
     const float4 Pp = b.pprev[n];
+    // the node's third of every incident triangle's sums (integers: the order of the
+    // additions does not matter)
+    long long ps[3] = {0, 0, 0}, qs[3] = {0, 0, 0};
+    for (int e = b.ntri_off[n]; e < b.ntri_off[n + 1]; ++e) {
+        const size_t t = (size_t)(b.ntri[e] / 3);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            ps[d] += b.pex[3 * t + d];
+            qs[d] += b.rsc[3 * t + d];
+        }
+    }
     float pe[3], rs[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        pe[d] = unfix40(b.pex[3 * (size_t)n + d]);
-        rs[d] = unfix40(b.rsc[3 * (size_t)n + d]);
-        b.pex[3 * (size_t)n + d] = 0;
-        b.rsc[3 * (size_t)n + d] = 0;
+        pe[d] = unfix40(ps[d]);
+        rs[d] = unfix40(qs[d]);
     }
     const float ff[3] = {0.5f * (pe[0] + Pp.x) + rs[0], 0.5f * (pe[1] + Pp.y) + rs[1],
                          0.5f * (pe[2] + Pp.z) + rs[2]};
@@ -491,11 +637,9 @@ static int link_blocks(const BBArgs &b, int per_block) {
 }
 
 void launch_bb_before(const BBArgs &b, int storage, hipStream_t st) {
-    const int tb = (b.ttot + 255) / 256;
-    hipLaunchKernelGGL(k_bb_bin_count, dim3(tb), dim3(256), 0, st, b);
-    hipLaunchKernelGGL(k_bb_bin_scan, dim3(b.ncap), dim3(1024), 0, st, b);
-    hipLaunchKernelGGL(k_bb_bin_fill, dim3(tb), dim3(256), 0, st, b);
-    hipLaunchKernelGGL(k_bb_find, dim3(GMAX, b.ncap), dim3(256), 0, st, b);
+    hipLaunchKernelGGL(k_bb_tri, dim3((b.ttot + 255) / 256), dim3(256), 0, st, b);
+    hipLaunchKernelGGL(k_bb_bins, dim3(b.ncap), dim3(BB_BIN_BLK), 0, st, b);
+    hipLaunchKernelGGL(k_bb_find, dim3(GMAX, b.ncap), dim3(BB_FIND_BLK), 0, st, b);
     const dim3 rg(4 * link_blocks(b, 256 / BB_RL), b.ncap), sg(link_blocks(b, 256), b.ncap);
     switch (storage) {
         case 0:

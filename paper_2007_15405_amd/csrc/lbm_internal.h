@@ -219,16 +219,21 @@ struct BBArgs {
     const float4 *dens;     // [N] densities and psi of both components, written by the
                             // fluid step on window sites (rho0, rho1, psi0, psi1)
     float4 *tpos;           // [Ttot][3] FP32-rounded triangle vertices of this step
+    int *tcell;             // [Ttot] window cells each triangle's box covers, packed
+                            // (first cell x, y, z: 6 bits each; extent - 1: 2 bits each),
+                            // -1 for a triangle the bins cannot hold
     int N, nx, ny, nz, wall, lz;
     float shift[2];
-    int *bcount;            // [ncap][GMAX3] triangles per window cell (0 between steps)
     int *bstart;            // [ncap][GMAX3 + 1] first entry of each cell
     int *blist;             // [BB_PER_TRI * Ttot] triangle indices by cell
     BBLink *links;          // [ncap][link_cap]
     int link_cap;
     int *nlinks;            // [2][ncap] links of this step, then those of the last step
-    long long *pex;         // [Ntot][3] momentum exchanged this step, 2^-40 units
-    long long *rsc;         // [Ntot][3] Shan-Chen reaction of this step, 2^-40 units
+    long long *pex;         // [Ttot][3] momentum exchanged this step through each triangle's
+                            // links, 2^-40 units (cleared at the next step's start)
+    long long *rsc;         // [Ttot][3] Shan-Chen reaction of this step, likewise
+    const int *ntri_off;    // [Ntot+1] node -> incident triangle CSR offsets
+    const int *ntri;        // incident entries: 3 * triangle + corner
     float4 *pprev;          // [Ntot] momentum exchanged in the previous step
     float4 *ffl;            // [Ntot] force of the fluid on each node in the last step
     float4 *R;              // [Ntot] Shan-Chen reaction on each node in the last step
