@@ -256,16 +256,19 @@ __global__ void __launch_bounds__(BB_BIN_BLK) k_bb_bins(BBArgs b) {
 // Links and bounce-back
 // ------------------------------------------------------------------------------------
 // plane lz of capsule k's window: the links of its inside sites, appended as (a, b, q).
-// Each wave reserves the places of all its lanes' links with one atomic add (the lanes'
-// counts scanned over the wave), so the capsule's counter sees one add per wave, not one
-// per site; the order of the list does not enter any result.
+// Each block reserves the places of all its links with one atomic add (the lanes' counts
+// scanned over the wave, the waves' totals over the block): the capsules' counters share a
+// cache line, and one add per site or per wave queued thousands of atomics on it.  The
+// order of the list does not enter any result.
 constexpr int BB_FIND_BLK = 1024;   // one pass over a window plane of up to 1024 columns
 
 __global__ void __launch_bounds__(BB_FIND_BLK) k_bb_find(BBArgs b) {
-    const int k = blockIdx.y, lz = blockIdx.x, lane = threadIdx.x & 63;
+    const int k = blockIdx.y, lz = blockIdx.x, lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const CapState cs = b.cst[k];
     if (lz >= cs.dim[2]) return;
     const int dx = cs.dim[0], dy = cs.dim[1], ncol = dx * dy;
+    __shared__ int s_w[BB_FIND_BLK / 64];
+    __shared__ int s_base;
     const int uz = cs.lo[2] + lz, z = wrapb(uz, b.nz);
     if (b.wall && slab_pos(z, b.lz) == 0) return;
     // the planes below and above, and whether they are wall planes (uniform over the block)
@@ -312,11 +315,23 @@ __global__ void __launch_bounds__(BB_FIND_BLK) k_bb_find(BBArgs b) {
             const int v = __shfl_up(incl, o, 64);
             if (lane >= o) incl += v;
         }
+        // the waves' totals scanned in LDS, one atomic add per block for all of them (the
+        // shuffle runs on every lane: it reads lane 63)
         const int wtot = __shfl(incl, 63, 64);
-        if (wtot == 0) continue;   // uniform over the wave
-        int i = 0;
-        if (lane == 63) i = atomicAdd(&b.nlinks[k], wtot);
-        i = __shfl(i, 63, 64) + incl - cnt;
+        if (lane == 0) s_w[wid] = wtot;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int tot = 0;
+            for (int w = 0; w < BB_FIND_BLK / 64; ++w) {
+                const int v = s_w[w];
+                s_w[w] = tot;
+                tot += v;
+            }
+            s_base = tot ? atomicAdd(&b.nlinks[k], tot) : 0;
+        }
+        __syncthreads();
+        int i = s_base + s_w[wid] + incl - cnt;
+        __syncthreads();   // s_w and s_base are rewritten by the next pass
         if (!mask) continue;
 #pragma unroll
         for (int q = 1; q < Q; ++q) {

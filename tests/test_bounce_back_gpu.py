@@ -96,6 +96,29 @@ def test_film_with_capsule(ks, steps):
     assert np.abs(mg[ok] - mo[ok]).max() <= 1e-3
 
 
+def test_wide_window_sorts_its_triangles_in_passes():
+    """An R = 13 capsule of 5120 triangles on a 48 x 48 x 40 film: its window (floor of the
+    node extent + 4 sites per axis, about 29^3) holds more cells than the 16384 counters the
+    triangle sort keeps in LDS, so the bins are built in two passes over cell ranges.  Labels,
+    link counts, densities and nodes against the oracle after 20 steps."""
+    cfg = synth.workload("pf", nx=48, ny=48, nz=40, coupling=1,
+                         capsules=[synth.capsule((24.23, 23.81, 14.17), 13.0, 5120, 0.05)])
+    g, o = run_pair(cfg, 20)
+    n = o.nodes(0)
+    cells = int(np.prod(np.floor(n.max(0)) - np.floor(n.min(0)) + 4))
+    say("window cells", cells)
+    assert cells > 16384
+    rg, ro = g.rho(), o.rho()
+    assert max(rel_l2(rg, ro)) <= 1e-5
+    site_check(rg, ro, 1e-5, "bounce-back wide window 20 steps", g.labels())
+    check_capsules(g, o, 1)
+    assert np.array_equal(g.labels(), o.labels())
+    sg, so = g.summary(), o.summary()
+    say("links gpu", sg["links"], "oracle", so["links"])
+    assert sg["links"] == so["links"] > 10000
+    assert sg["lost_links"] == 0 and sg["unstable"] == 0
+
+
 def test_wetting_capsules_in_contact_on_a_ragged_periodic_box():
     """Two wetting capsules with a volume penalty pressed into Hertz contact, on a box
     whose sizes are no tile multiples, one capsule across the periodic boundary."""
