@@ -829,20 +829,26 @@ __device__ __forceinline__ void node_update_one(const MembraneArgs &m, int n, in
                       phi4((float)(X.y - (double)(by + oy)));
     const int col = wrap_near(by + oy, m.ny) * m.nx + wrap_near(bx + ox, m.nx);
     // planes bz .. bz + 3, with their slab positions stepped alongside (nz is a multiple
-    // of lz, so both wrap together); wall sites contribute nothing
+    // of lz, so both wrap together); wall sites contribute nothing.  Every plane's site is
+    // a lattice site, so the eight loads are issued before any is used.
     int z = wrap_near(bz, m.nz), zr = m.wall ? slab_pos(z, m.lz) : 1;
+    float4 u[4], r[4];
+    bool fluid[4];
 #pragma unroll
     for (int oz = 0; oz < 4; ++oz) {
-        if (!(m.wall && zr == 0)) {
-            const int s = z * m.ny * m.nx + col;
-            const float w = wxy * phi4((float)(X.z - (double)(bz + oz)));
-            const float4 u = m.uo[s];
-            const float4 r = m.ro[s];   // reaction / coverage, 0 where uncovered
-            U[0] += w * u.x; U[1] += w * u.y; U[2] += w * u.z;
-            Rr[0] += w * r.x; Rr[1] += w * r.y; Rr[2] += w * r.z;
-        }
+        const int s = z * m.ny * m.nx + col;
+        u[oz] = m.uo[s];
+        r[oz] = m.ro[s];   // reaction / coverage, 0 where uncovered
+        fluid[oz] = !(m.wall && zr == 0);
         if (++z == m.nz) z = 0;
         if (++zr == m.lz) zr = 0;
+    }
+#pragma unroll
+    for (int oz = 0; oz < 4; ++oz) {
+        if (!fluid[oz]) continue;
+        const float w = wxy * phi4((float)(X.z - (double)(bz + oz)));
+        U[0] += w * u[oz].x; U[1] += w * u[oz].y; U[2] += w * u[oz].z;
+        Rr[0] += w * r[oz].x; Rr[1] += w * r[oz].y; Rr[2] += w * r[oz].z;
     }
     static_assert(UPD_L == 16, "group sums are over 16 lanes");
 #pragma unroll
