@@ -359,7 +359,9 @@ __global__ void __launch_bounds__(BB_FIND_BLK) k_bb_find(BBArgs b) {
 // the cells the link's bounding box touches, lowest index on ties; the lanes split the
 // candidates and reduce), and both sites' densities before any population changes
 constexpr int BB_RL = 8;
-static_assert(BB_RL == 8, "the density sums take two of sixteen partial sums per lane");
+static_assert(BB_RL == 4 || BB_RL == 8 || BB_RL == 16, "lanes per link divide 16");
+constexpr int BB_RH = 16 / BB_RL;                   // partial density sums per lane
+constexpr int BB_RC = BB_RL >= 8 ? 1 : 8 / BB_RL;   // cells per lane
 
 template <int S>
 __global__ void __launch_bounds__(256, 3) k_bb_resolve(BBArgs b) {
@@ -379,21 +381,19 @@ __global__ void __launch_bounds__(256, 3) k_bb_resolve(BBArgs b) {
         const int sa = L.a, sbi = L.b, q = L.q;
         // densities of both sites (issued first, so that their loads are in flight during
         // the candidate search), summed in the order of a 16-wide butterfly whatever the
-        // group's width: partial sum j < 16 holds the populations j and j + 16, lane sl holds
-        // the partial sums sl and sl + 8 and adds them as that butterfly's first level does
-        float ra0 = 0.f, ra1 = 0.f, rb0 = 0.f, rb1 = 0.f;
-        float xa0 = 0.f, xa1 = 0.f, xb0 = 0.f, xb1 = 0.f;
-        for (int qq = sl; qq < Q; qq += 16) {
-            ra0 += popl<S>(b.f, 0, qq, b.N, sa, b.shift[0]);
-            ra1 += popl<S>(b.f, 1, qq, b.N, sa, b.shift[1]);
-            rb0 += popl<S>(b.f, 0, qq, b.N, sbi, b.shift[0]);
-            rb1 += popl<S>(b.f, 1, qq, b.N, sbi, b.shift[1]);
-        }
-        for (int qq = sl + 8; qq < Q; qq += 16) {
-            xa0 += popl<S>(b.f, 0, qq, b.N, sa, b.shift[0]);
-            xa1 += popl<S>(b.f, 1, qq, b.N, sa, b.shift[1]);
-            xb0 += popl<S>(b.f, 0, qq, b.N, sbi, b.shift[0]);
-            xb1 += popl<S>(b.f, 1, qq, b.N, sbi, b.shift[1]);
+        // group's width: partial sum j < 16 holds the populations j and j + 16, lane sl
+        // holds the partial sums sl + h BB_RL and combines them as that butterfly's first
+        // levels do
+        float pr[BB_RH][4];
+#pragma unroll
+        for (int h = 0; h < BB_RH; ++h) {
+            pr[h][0] = pr[h][1] = pr[h][2] = pr[h][3] = 0.f;
+            for (int qq = sl + h * BB_RL; qq < Q; qq += 16) {
+                pr[h][0] += popl<S>(b.f, 0, qq, b.N, sa, b.shift[0]);
+                pr[h][1] += popl<S>(b.f, 1, qq, b.N, sa, b.shift[1]);
+                pr[h][2] += popl<S>(b.f, 0, qq, b.N, sbi, b.shift[0]);
+                pr[h][3] += popl<S>(b.f, 1, qq, b.N, sbi, b.shift[1]);
+            }
         }
         // unwrapped coordinates of a in the window's frame, from its lattice index
         const int ax = sa % b.nx, ay = (sa / b.nx) % b.ny, az = sa / (b.nx * b.ny);
@@ -411,26 +411,35 @@ __global__ void __launch_bounds__(256, 3) k_bb_resolve(BBArgs b) {
             // one or two cells per axis (a link moves at most one site per axis)
             nc3[d] = max(min((int)hi[d] - cs.lo[d], cs.dim[d] - 1) - c0[d] + 1, 0);
         }
-        // the (at most 2 x 2 x 2) cells, x fastest: lane j of the group reads the start and
-        // the end of cell j, and the group shares them
-        int my_beg = 0, my_cnt = 0;
-        if (sl < nc3[0] * nc3[1] * nc3[2]) {
-            const int ix = nc3[0] == 2 ? (sl & 1) : 0, r1 = nc3[0] == 2 ? sl >> 1 : sl;
-            const int iy = nc3[1] == 2 ? (r1 & 1) : 0, iz = nc3[1] == 2 ? r1 >> 1 : r1;
-            const int cell = ((c0[2] + iz) * dy + c0[1] + iy) * dx + c0[0] + ix;
-            my_beg = st[cell];
-            my_cnt = max(min(st[cell + 1], lmax) - my_beg, 0);
+        // the (at most 2 x 2 x 2) cells, x fastest: cell j's start and end are read by lane
+        // j mod BB_RL, and the group shares them
+        int my_beg[BB_RC], my_cnt[BB_RC];
+#pragma unroll
+        for (int h = 0; h < BB_RC; ++h) {
+            const int j = sl + h * BB_RL;
+            my_beg[h] = my_cnt[h] = 0;
+            if (j < 8 && j < nc3[0] * nc3[1] * nc3[2]) {
+                const int ix = nc3[0] == 2 ? (j & 1) : 0, r1 = nc3[0] == 2 ? j >> 1 : j;
+                const int iy = nc3[1] == 2 ? (r1 & 1) : 0, iz = nc3[1] == 2 ? r1 >> 1 : r1;
+                const int cell = ((c0[2] + iz) * dy + c0[1] + iy) * dx + c0[0] + ix;
+                my_beg[h] = st[cell];
+                my_cnt[h] = max(min(st[cell + 1], lmax) - my_beg[h], 0);
+            }
         }
-        // the first level of the density butterfly (the cell starts' wait covers the loads)
-        ra0 += xa0;
-        ra1 += xa1;
-        rb0 += xb0;
-        rb1 += xb1;
+        // the first levels of the density butterfly, inside the lane (the cell starts' wait
+        // covers the loads): level o pairs partial sum j with j + o
+#pragma unroll
+        for (int o = 8; o >= BB_RL; o >>= 1)
+#pragma unroll
+            for (int h = 0; h < o / BB_RL; ++h)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) pr[h][c] += pr[h + o / BB_RL][c];
+        float ra0 = pr[0][0], ra1 = pr[0][1], rb0 = pr[0][2], rb1 = pr[0][3];
         int beg[8], cnt[8], tot = 0;
 #pragma unroll
         for (int n = 0; n < 8; ++n) {
-            beg[n] = __shfl(my_beg, n, BB_RL);
-            cnt[n] = __shfl(my_cnt, n, BB_RL);
+            beg[n] = __shfl(my_beg[n / BB_RL < BB_RC ? n / BB_RL : 0], n % BB_RL, BB_RL);
+            cnt[n] = __shfl(my_cnt[n / BB_RL < BB_RC ? n / BB_RL : 0], n % BB_RL, BB_RL);
             tot += cnt[n];
         }
         double bd = __builtin_inf();
