@@ -147,19 +147,6 @@ __global__ void __launch_bounds__(256) k_colsum(const float *__restrict__ D, int
     if (threadIdx.x == 0) db[j] = s[0];
 }
 
-// Adam (Kingma & Ba): bias-corrected moments, step counted from 1
-__global__ void k_adam(float *__restrict__ th, float *__restrict__ m, float *__restrict__ v,
-                       const float *__restrict__ g, int np, float lr, float b1, float b2,
-                       float c1, float c2, float eps) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= np) return;
-    const float gi = g[i];
-    const float mi = b1 * m[i] + (1.f - b1) * gi, vi = b2 * v[i] + (1.f - b2) * gi * gi;
-    m[i] = mi;
-    v[i] = vi;
-    th[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
-}
-
 // ------------------------------------------------------------------------------------
 // Training in two launches per Adam step.
 //
@@ -177,7 +164,8 @@ __global__ void k_adam(float *__restrict__ th, float *__restrict__ m, float *__r
 // sample carry zero inputs and zero loss gradient.  Each workgroup writes its gradient,
 // in the parameter layout, to row blockIdx.x of G.
 //
-// k_train_update: per parameter, the rows of G summed in workgroup order, then Adam.
+// k_train_update: per parameter, the rows of G summed in workgroup order, then Adam
+// (Kingma & Ba: bias-corrected moments, step counted from 1).
 // Every sum runs in a fixed order, so the result does not depend on scheduling.
 // ------------------------------------------------------------------------------------
 constexpr int TC_THREADS = 512, TC_ROWS = 32, TC_LD = NH + 1, TC_BLOCKS = 128;
