@@ -617,8 +617,8 @@ __global__ void __launch_bounds__(256) k_bb_nodes(BBArgs b) {
     if (n >= b.ntot) return;
     const float4 Fm = b.F[b.slot[n]];
     const float4 Pp = b.pprev[n];
-    // the node's third of every incident triangle's sums (integers: the order of the
-    // additions does not matter)
+    // the sums of every incident triangle, each already the third of its links' momentum
+    // that goes to each of its nodes (integers: the order of the additions does not matter)
     long long ps[3] = {0, 0, 0}, qs[3] = {0, 0, 0};
     for (int e = b.ntri_off[n]; e < b.ntri_off[n + 1]; ++e) {
         const size_t t = (size_t)(b.ntri[e] / 3);
