@@ -26,8 +26,9 @@ PEAK_HBM_GBS = 8000.0
 
 # HBM bytes per launch of the fused fluid kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE,
 # scaled by the same counters on a plain 1 GiB copy (profiles/fluid_c3_f32_hbm_traffic.md),
-# keyed by (storage, tile, zchunk).  Reported only for the launch shape it was taken on.
-MEASURED_TRAFFIC_BYTES = {("f32", 11, 48): 2.0404e9}
+# keyed by (storage, tile, zchunk, first-chunk offset).  Reported only for the launch shape
+# it was taken on.
+MEASURED_TRAFFIC_BYTES = {}
 WORKLOAD = "film 256x256x96, wall, 16 capsules R=10 (5120 tri), ks=0.05"
 
 
@@ -40,9 +41,10 @@ def tune(sim, steps=10):
     """The library's launch-shape autotuner (``lbm_autotune``): every tile shape that
     applies to this box and a few z-chunk depths, timed with HIP events, the fastest kept."""
     t = sim.autotune(steps)
-    print(f"#   autotuner: tile {TILES[t['tile']]} zchunk {t['zchunk']}: fluid "
-          f"{t['fluid_ms'] * 1e3:.1f} us", file=sys.stderr, flush=True)
-    return dict(tile=TILES[t["tile"]], tile_id=t["tile"], zchunk=t["zchunk"],
+    print(f"#   autotuner: tile {TILES[t['tile']]} zchunk {t['zchunk']} first chunk "
+          f"{t['zoff']} planes shorter: fluid {t['fluid_ms'] * 1e3:.1f} us", file=sys.stderr,
+          flush=True)
+    return dict(tile=TILES[t["tile"]], tile_id=t["tile"], zchunk=t["zchunk"], zoff=t["zoff"],
                 fluid_ms=t["fluid_ms"])
 
 
@@ -56,8 +58,11 @@ def run_gpu(cfg, storage, steps, warmup, do_tune=True, launch=None):
     sim.step(2)                   # capsule windows in place before the launch shapes are timed
     tuned = tune(sim) if do_tune else None
     if launch is not None:
-        sim.set_launch(*launch)
-        tuned = dict(tile=TILES.get(launch[0], "two-kernel"), tile_id=launch[0], zchunk=launch[1])
+        sim.set_launch(launch[0], launch[1])
+        zoff = launch[2] if len(launch) > 2 else 0
+        sim.set_zoffset(zoff)
+        tuned = dict(tile=TILES.get(launch[0], "two-kernel"), tile_id=launch[0], zchunk=launch[1],
+                     zoff=zoff)
     sim.step(warmup)
     sim.sync()
     sim.kernel_stats()            # discard
@@ -440,6 +445,8 @@ def main():
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MB",
                     help="only run a plain device copy of MB megabytes (counter calibration)")
     ap.add_argument("--zchunk", type=int, default=0)
+    ap.add_argument("--zoff", type=int, default=0,
+                    help="with --tile: planes the first z-chunk is shortened by")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); "
@@ -497,7 +504,7 @@ def main():
         print(json.dumps(dict(batched=batched)), flush=True)
         return
     for st in (["f32", "f16", "bf16", "f16site"] if args.storage == "all" else [args.storage]):
-        fixed = (args.tile, args.zchunk) if args.tile is not None else None
+        fixed = (args.tile, args.zchunk, args.zoff) if args.tile is not None else None
         res[st] = run_gpu(cfg, st, args.steps, args.warmup, not args.no_tune and fixed is None, fixed)
         print(f"# {st}: {res[st]['mlups']:.1f} MLUPS, {res[st]['ms_per_step']:.4f} ms/step, "
               f"fluid {res[st]['fluid_ms']:.4f} ms = {res[st]['achieved_gbs']:.0f} GB/s",
@@ -507,7 +514,7 @@ def main():
     coupling = {}
     if not args.no_bounce_back:
         bcfg = dict(cfg, coupling=1)
-        fixed = (args.tile, args.zchunk) if args.tile is not None else None
+        fixed = (args.tile, args.zchunk, args.zoff) if args.tile is not None else None
         coupling["bounce_back"] = run_gpu(bcfg, "f32", min(args.steps, 100), args.warmup,
                                           not args.no_tune and fixed is None, fixed)
         b = coupling["bounce_back"]
@@ -534,8 +541,8 @@ def main():
         roofline=dict(bound="hbm", achieved=round(head["achieved_gbs"], 1), peak=PEAK_HBM_GBS,
                       unit="GB/s", frac=round(head["frac"], 4),
                       traffic=MEASURED_TRAFFIC_BYTES.get(
-                          (head_st, head["launch"]["tile_id"], head["launch"]["zchunk"])
-                          if head.get("launch") else None),
+                          (head_st, head["launch"]["tile_id"], head["launch"]["zchunk"],
+                           head["launch"].get("zoff", 0)) if head.get("launch") else None),
                       traffic_unit="bytes per launch",
                       algorithmic_bytes=head["bytes_per_site"] * head["fluid_sites"],
                       bytes_per_site=head["bytes_per_site"], kernel="fluid",

@@ -272,11 +272,24 @@ lbm_status lbm_kernel_stats(lbm_handle *h, lbm_kernel_stat *out, int32_t max, in
  * same order, so results are identical.  LBM_E_INVAL for other values. */
 lbm_status lbm_set_launch(lbm_handle *h, int32_t tile, int32_t zchunk);
 
+/* Shortens the first z-chunk of the fluid launch by `planes` planes; the last chunk takes
+ * them, so the number of workgroups is unchanged.  Each workgroup marches its chunk, and the
+ * launch lasts as long as its slowest one: where the capsule windows lie in the lower chunk
+ * (a film on a wall), its workgroups carry the extra window work, and a shorter lower chunk
+ * balances them.  0 <= planes < the launch's z-chunk, and 0 when the launch has one chunk
+ * (LBM_E_INVAL otherwise).  Results are identical for every offset.  lbm_set_launch resets
+ * it to 0; lbm_autotune chooses it. */
+lbm_status lbm_set_zoffset(lbm_handle *h, int32_t planes);
+/* The current offset of the first z-chunk (0 for a NULL handle). */
+int32_t lbm_zoffset(const lbm_handle *h);
+
 /* Launch-shape autotuner of the fluid step: times reps (1..1000) launches of the fluid
  * kernel, after two untimed ones, with HIP events on the handle's stream for every launch
  * shape that applies to the lattice (tiles 1..13 as in lbm_set_launch, of which 1..5 with
  * tau != 1; z-chunks 0, 8, 12, 16, 24, 32, 48 capped at nz, 0 resolved to its value) and
- * selects the fastest as by lbm_set_launch.  The simulation is not advanced: the timed
+ * selects the fastest as by lbm_set_launch; then times that shape with its first z-chunk
+ * shortened by 1 .. 4 planes (lbm_set_zoffset) and keeps the fastest offset, 0 included.
+ * The simulation is not advanced: the timed
  * launches read the current populations and write only the buffer and the window
  * outputs that the next step rewrites, and the status words are restored.  They run on
  * the labels and spread forces of the last step, so call it after at least one step for a

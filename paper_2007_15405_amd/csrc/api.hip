@@ -84,6 +84,7 @@ struct lbm_handle {
     int *d_eoff = nullptr, *d_elist = nullptr;
     std::vector<CapDev> h_caps;
     int tile = 1, zchunk = 0;
+    int zoff = 0;                  // planes the first z-chunk is shortened by
     Prof prof;
     // bounce-back coupling (coupling = 1)
     double4 *d_V = nullptr;
@@ -860,11 +861,27 @@ extern "C" lbm_status lbm_set_launch(lbm_handle *h, int32_t tile, int32_t zchunk
     if (tile < 0 || tile > TILE_ROWS || zchunk < 0) return fail(h, LBM_E_INVAL, "invalid launch shape");
     h->tile = tile;
     h->zchunk = zchunk;
+    h->zoff = 0;
     return LBM_OK;
 }
 
-// one launch of the fluid kernel of the given shape for the handle's storage
-static void enqueue_fluid(const lbm_handle *h, const FluidArgs &a, int tile, int zc, hipStream_t st) {
+extern "C" lbm_status lbm_set_zoffset(lbm_handle *h, int32_t planes) {
+    if (!h) return LBM_E_INVAL;
+    const int zc = zchunk_of(h);
+    if (planes < 0 || (planes > 0 && (zc >= h->nz || planes >= zc)))
+        return fail(h, LBM_E_INVAL, "z offset must be 0 .. z-chunk - 1, and 0 for one chunk");
+    h->zoff = planes;
+    return LBM_OK;
+}
+
+extern "C" int32_t lbm_zoffset(const lbm_handle *h) { return h ? h->zoff : 0; }
+
+// one launch of the fluid kernel of the given shape for the handle's storage, the first
+// z-chunk shortened by zoff planes
+static void enqueue_fluid(const lbm_handle *h, const FluidArgs &a0, int tile, int zc, int zoff,
+                          hipStream_t st) {
+    FluidArgs a = a0;
+    a.zoff = zoff < zc ? zoff : 0;
     switch (h->storage) {
         case 0: launch_fluid_tiled<0>(a, tile, zc, st); break;
         case 1: launch_fluid_tiled<1>(a, tile, zc, st); break;
@@ -898,7 +915,7 @@ extern "C" lbm_status lbm_step(lbm_handle *h, int64_t n) {
         }
         const FluidArgs a = fluid_args(h, h->cur);
         const int zc = zchunk_of(h);
-        timed(h->prof, h->st, "fluid", [&] { enqueue_fluid(h, a, h->tile, zc, h->st); });
+        timed(h->prof, h->st, "fluid", [&] { enqueue_fluid(h, a, h->tile, zc, h->zoff, h->st); });
         if (bb) {
             const BBArgs b = bb_args(h, h->cur);
             timed(h->prof, h->st, "bb_nodes", [&] { launch_bb_after(b, h->storage, h->st); });
@@ -985,12 +1002,24 @@ extern "C" lbm_status lbm_autotune(lbm_handle *h, int32_t reps, int32_t *tile, i
             seen[ns++] = zc;
             double ms = 0.0;
             HIPCHK(h, time_launches(h->st, reps, ev.a, ev.b,
-                                    [&] { enqueue_fluid(h, a, t, zc, h->st); }, &ms));
+                                    [&] { enqueue_fluid(h, a, t, zc, 0, h->st); }, &ms));
             if (ms < best) {
                 best = ms;
                 bt = t;
                 bz = zc;
             }
+        }
+    }
+    // the chosen shape with its first z-chunk shortened by 1 .. 4 planes: a launch whose
+    // lower chunk holds the capsule sites balances its blocks that way
+    int bo = 0;
+    for (int d = 1; d <= 4 && bz < h->nz && d < bz; ++d) {
+        double ms = 0.0;
+        HIPCHK(h, time_launches(h->st, reps, ev.a, ev.b,
+                                [&] { enqueue_fluid(h, a, bt, bz, d, h->st); }, &ms));
+        if (ms < best) {
+            best = ms;
+            bo = d;
         }
     }
     // the timed launches wrote only the buffer the next step overwrites and the window
@@ -999,6 +1028,7 @@ extern "C" lbm_status lbm_autotune(lbm_handle *h, int32_t reps, int32_t *tile, i
     HIPCHK(h, hipStreamSynchronize(h->st));
     h->tile = bt;
     h->zchunk = bz;
+    h->zoff = bo;
     if (tile) *tile = bt;
     if (zchunk) *zchunk = bz;
     if (fluid_ms) *fluid_ms = best;

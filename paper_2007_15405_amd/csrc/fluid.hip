@@ -551,7 +551,9 @@ __global__ void __launch_bounds__(TX * TY) k_fused(FluidArgs a, int zc, int tile
     if (L >= nblocks) return;
     const int bx = L % tiles_x, t2 = L / tiles_x, by = t2 % tiles_y, bz = t2 / tiles_y;
     const int nx = a.nx, ny = a.ny, nz = a.nz, N = a.N;
-    const int x0 = bx * TX, y0 = by * TY, z0 = bz * zc, z1 = min(z0 + zc, nz);
+    const int x0 = bx * TX, y0 = by * TY;
+    int z0, z1;
+    zchunk_range(bz, zc, a.zoff, nz, z0, z1);
     const float sh0 = a.shift[0], sh1 = a.shift[1];
 
     const int tid = threadIdx.x, lx = tid % TX, ly = tid / TX;
@@ -845,7 +847,9 @@ __device__ __forceinline__ void pipe_tile(const FluidArgs &a, int L, int zc, int
 
     const int bx = L % tiles_x, t2 = L / tiles_x, by = t2 % tiles_y, bz = t2 / tiles_y;
     const int nx = a.nx, ny = a.ny, nz = a.nz, N = a.N;
-    const int x0 = bx * tx, y0 = by * ty, z0 = bz * zc, z1 = min(z0 + zc, nz);
+    const int x0 = bx * tx, y0 = by * ty;
+    int z0, z1;
+    zchunk_range(bz, zc, a.zoff, nz, z0, z1);
     const float sh0 = a.shift[0], sh1 = a.shift[1];
     // storages 1 and 2: the pulls are the stored values f_i - w_i rho_s; a site's density
     // takes the sum of its populations' shifts, as encoded (FP32 products w_i rho_s)

@@ -133,7 +133,17 @@ struct FluidArgs {
     int bb;                 // bounce-back coupling: window sites store (rho0, rho1, psi0,
                             // psi1) in ro instead of the reaction
     int zero_drho;          // 1: the wall and every capsule have a zero wetting offset
+    int zoff;               // planes the first z-chunk of the launch is shortened by (the
+                            // last takes them; 0 <= zoff < the chunk)
 };
+
+// planes [z0, z1) of z-chunk bz of a launch with chunks of zc planes, the first shortened by
+// zoff planes and the last taking them, so that the chunk count stays ceil(nz / zc)
+__host__ __device__ inline void zchunk_range(int bz, int zc, int zoff, int nz, int &z0, int &z1) {
+    const int tz = (nz + zc - 1) / zc;
+    z0 = bz == 0 ? 0 : bz * zc - zoff;
+    z1 = bz == tz - 1 ? nz : (bz + 1) * zc - zoff;
+}
 
 // Device description of one capsule.
 struct CapDev {

@@ -99,6 +99,8 @@ SIGNATURES = {
     "lbm_set_profiling": (C.c_int, [H, C.c_int32]),
     "lbm_kernel_stats": (C.c_int, [H, C.POINTER(KernelStat), C.c_int32, C.POINTER(C.c_int32)]),
     "lbm_set_launch": (C.c_int, [H, C.c_int32, C.c_int32]),
+    "lbm_set_zoffset": (C.c_int, [H, C.c_int32]),
+    "lbm_zoffset": (C.c_int32, [H]),
     "lbm_autotune": (C.c_int, [H, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                C.POINTER(C.c_double)]),
     "lbm_bytes_per_site": (C.c_double, [H]),
@@ -370,7 +372,15 @@ class Sim:
         keep the fastest (``lbm_autotune``; the simulation is not advanced)."""
         t, z, ms = C.c_int32(), C.c_int32(), C.c_double()
         self._check(self.L.lbm_autotune(self.h, int(reps), C.byref(t), C.byref(z), C.byref(ms)))
-        return dict(tile=t.value, zchunk=z.value, fluid_ms=ms.value)
+        return dict(tile=t.value, zchunk=z.value, zoff=self.zoffset, fluid_ms=ms.value)
+
+    def set_zoffset(self, planes: int = 0):
+        """Shorten the fluid launch's first z-chunk by ``planes`` planes (``lbm_set_zoffset``)."""
+        self._check(self.L.lbm_set_zoffset(self.h, int(planes)))
+
+    @property
+    def zoffset(self) -> int:
+        return int(self.L.lbm_zoffset(self.h))
 
     @property
     def bytes_per_site(self) -> float:

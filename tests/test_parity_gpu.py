@@ -219,11 +219,13 @@ def c3_reference():
 
 
 # (storage, launch, per-site bound): the launch shape the benchmark times on this machine
-# (whole rows 256 x 2, z-chunks of 48 planes) in every storage, and the autotuner's choice.
+# (whole rows 256 x 2, z-chunks of 48 planes, with and without the first chunk shortened by
+# two planes) in every storage, and the autotuner's choice (tile, chunk and offset).
 # 16-bit storage differs from the FP64 oracle by the rounding of the stored populations
 # (FP16 ulp 2^-15 .. 2^-14 at the shifted values of the minority phase, BF16 8x more).
-C3_CASES = [("f32", (11, 48), 1e-5), ("f32", "tuned", 1e-5), ("f16", (11, 48), 2e-3),
-            ("bf16", (11, 48), 1.5e-2), ("f16", "tuned", 2e-3)]
+C3_CASES = [("f32", (11, 48), 1e-5), ("f32", (11, 48, 2), 1e-5), ("f32", "tuned", 1e-5),
+            ("f16", (11, 48), 2e-3), ("f16", (11, 48, 2), 2e-3), ("bf16", (11, 48), 1.5e-2),
+            ("f16", "tuned", 2e-3)]
 
 
 @pytest.mark.parametrize("storage,launch,bound", C3_CASES)
@@ -234,7 +236,10 @@ def test_full_size_film_box_in_benchmark_launch(c3_reference, storage, launch, b
     cfg = ref["cfg"]
     g = _sim(cfg, storage=storage)
     if launch != "tuned":
-        g.set_launch(*launch)
+        g.set_launch(*launch[:2])
+        if len(launch) > 2:
+            g.set_zoffset(launch[2])
+            assert g.zoffset == launch[2]
     g.step(1)
     if launch == "tuned":
         t = g.autotune(3)
@@ -258,6 +263,26 @@ def test_full_size_film_box_in_benchmark_launch(c3_reference, storage, launch, b
         assert np.abs(mg[ok] - mo[ok]).max() <= 1e-4
     assert g.summary()["lost_reaction"] == 0
     assert g.summary()["unstable"] == 0
+    g.close()
+
+
+def test_z_offset_is_validated():
+    """The first z-chunk may be shortened by 0 .. chunk - 1 planes, and not at all when the
+    launch has one chunk; lbm_set_launch resets the offset."""
+    from paper_2007_15405_amd import LbmError
+    g = _sim(synth.workload("pf"))      # 32^3
+    g.set_launch(10, 8)
+    g.set_zoffset(7)
+    assert g.zoffset == 7
+    for bad in (-1, 8):
+        with pytest.raises(LbmError) as ei:
+            g.set_zoffset(bad)
+        assert ei.value.status == -1   # LBM_E_INVAL
+    g.set_launch(10, 48)                 # one chunk of all 32 planes
+    assert g.zoffset == 0
+    g.set_zoffset(0)
+    with pytest.raises(LbmError):
+        g.set_zoffset(1)
     g.close()
 
 
@@ -302,13 +327,15 @@ def test_fused_kernel_matches_two_kernel_variant(name):
     ref.step(steps)
     r0 = ref.rho()
     for tile in range(1, 14):
-        for zc in (0, 5, 48):
+        # z-chunks of 5 planes also with the first one 3 planes shorter (the last longer)
+        for zc, zo in ((0, 0), (5, 0), (5, 3), (48, 0)):
             g = _sim(cfg)
             g.set_launch(tile, zc)
+            g.set_zoffset(zo)
             g.step(steps)
             r = g.rho()
             d = float(np.abs(r - r0).max())
-            say("tile", tile, "zchunk", zc, "max |diff|", d)
+            say("tile", tile, "zchunk", zc, "offset", zo, "max |diff|", d)
             assert d <= 1e-6 * float(np.abs(r0).max())
             g.close()
 
