@@ -28,7 +28,7 @@ PEAK_HBM_GBS = 8000.0
 # scaled by the same counters on a plain 1 GiB copy (profiles/fluid_c3_f32_hbm_traffic.md),
 # keyed by (storage, tile, zchunk, first-chunk offset).  Reported only for the launch shape
 # it was taken on.
-MEASURED_TRAFFIC_BYTES = {}
+MEASURED_TRAFFIC_BYTES = {("f32", 11, 48, 2): 2.0277e9}
 WORKLOAD = "film 256x256x96, wall, 16 capsules R=10 (5120 tri), ks=0.05"
 
 
