@@ -877,7 +877,8 @@ extern "C" lbm_status lbm_set_zoffset(lbm_handle *h, int32_t planes) {
 extern "C" int32_t lbm_zoffset(const lbm_handle *h) { return h ? h->zoff : 0; }
 
 // one launch of the fluid kernel of the given shape for the handle's storage, the first
-// z-chunk shortened by zoff planes
+// z-chunk shortened by zoff planes (an offset not below the chunk, which lbm_set_zoffset
+// never stores, launches equal chunks)
 static void enqueue_fluid(const lbm_handle *h, const FluidArgs &a0, int tile, int zc, int zoff,
                           hipStream_t st) {
     FluidArgs a = a0;
